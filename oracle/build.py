@@ -1,0 +1,27 @@
+"""Build the FP64 CPU oracle (test infrastructure) as a shared library.
+
+Plain g++, -O2, one thread; no BLAS.  Called by the repository's build
+entry point and, when the library is missing, by the test suite.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "bilu_oracle.cpp")
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
+        return LIB
+    tmp = LIB + ".tmp"
+    cmd = ["g++", "-O2", "-march=native", "-std=c++17", "-fPIC", "-shared",
+           "-o", tmp, SRC]
+    subprocess.check_call(cmd, cwd=HERE)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(force="--force" in sys.argv or True))

@@ -1,0 +1,583 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+Every test here runs on the CPU.  None of them re-types the oracle's own
+formulas: each checks a closed form, an invariant, a textbook special case
+or an independent brute-force computation (dense NumPy).
+"""
+import numpy as np
+import pytest
+
+from oracle import Oracle, OracleOptions, cosine_groups, ilu1t_blocks, perturb_invert, \
+    fgmres_plain
+from paper_1908_10169_amd import matgen as mg
+
+NO_BLOCKING = dict(use_cosine=False, use_ilu1t=False, use_aggregation=False)
+
+
+# ---------------------------------------------------------------------------
+# helpers: dense assembly of the oracle's factors (independent of its code)
+# ---------------------------------------------------------------------------
+def assemble(o: Oracle):
+    """Dense L (unit), S (block diag, S_K = D_K^{-1}), U (unit) and perm."""
+    f = o.factors()
+    n = o.n
+    L = np.eye(n)
+    U = np.eye(n)
+    S = np.zeros((n, n))
+    for k in range(len(f.starts) - 1):
+        a, b = f.starts[k], f.starts[k + 1]
+        S[a:b, a:b] = np.linalg.inv(f.D[k])
+        if len(f.R[k]):
+            L[np.ix_(f.R[k], np.arange(a, b))] = f.L[k]
+        if len(f.C[k]):
+            U[np.ix_(np.arange(a, b), f.C[k])] = f.D[k] @ f.W[k]
+    return L, S, U, f
+
+
+def permuted_dense(a, perm):
+    A = a.to_dense()
+    return A[np.ix_(perm, perm)]
+
+
+def scalar_crout_ilu(A, mask, tau):
+    """Alg. 1 of the paper (Crout ILU), dense arrays with a pattern mask.
+
+    Column k of L and row k of U are formed from the already computed parts;
+    l_ik is dropped when |l_ik| <= tau |l_kk|, u_ki when |u_ki| <= tau |u_kk|.
+    Returns unit L, upper U (with pivots) and their kept masks."""
+    n = A.shape[0]
+    L = np.zeros((n, n)); Lm = np.zeros((n, n), bool)
+    U = np.zeros((n, n)); Um = np.zeros((n, n), bool)
+    for k in range(n):
+        col = {i: A[i, k] for i in range(k, n) if mask[i, k]}
+        for j in range(k):
+            if Um[j, k]:
+                for i in range(k, n):
+                    if Lm[i, j]:
+                        col[i] = col.get(i, 0.0) - L[i, j] * U[j, k]
+        lkk = col.get(k, 0.0)
+        for i, v in col.items():
+            if i > k and abs(v) > tau * abs(lkk):
+                L[i, k] = v / lkk
+                Lm[i, k] = True
+        L[k, k] = 1.0
+        Lm[k, k] = True
+        row = {i: A[k, i] for i in range(k, n) if mask[k, i]}
+        for j in range(k):
+            if Lm[k, j]:
+                for i in range(k, n):
+                    if Um[j, i]:
+                        row[i] = row.get(i, 0.0) - L[k, j] * U[j, i]
+        ukk = row.get(k, 0.0)
+        U[k, k] = ukk
+        Um[k, k] = True
+        for i, v in row.items():
+            if i > k and abs(v) > tau * abs(ukk):
+                U[k, i] = v
+                Um[k, i] = True
+    return L, Lm, U, Um
+
+
+def tridiag(n, seed, diag=4.0):
+    rng = np.random.default_rng(seed)
+    A = np.diag(diag + rng.uniform(0, 1, n))
+    A += np.diag(rng.choice([-1.0, 1.0], n - 1) * rng.uniform(0.5, 1, n - 1), 1)
+    A += np.diag(rng.choice([-1.0, 1.0], n - 1) * rng.uniform(0.5, 1, n - 1), -1)
+    return A
+
+
+# ---------------------------------------------------------------------------
+# P1: tau = 0 keeps every nonzero: the factorization is exact LU
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("blocking", [NO_BLOCKING, {}])
+def test_p1_tau0_is_exact_lu(blocking):
+    a = mg.random_sparse(200, 0.03, seed=3, diag_shift=8.0)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=0.0, **blocking)) == 0
+    A = a.to_dense()
+    b = A @ np.ones(a.n) + np.arange(a.n) / a.n
+    y = o.apply(b)
+    x_ref = np.linalg.solve(A, b)
+    assert np.linalg.norm(y - x_ref) <= 1e-12 * np.linalg.norm(x_ref)
+    L, S, U, f = assemble(o)
+    P = permuted_dense(a, f.perm)
+    assert np.linalg.norm(L @ S @ U - P) <= 1e-14 * np.linalg.norm(P) * 10
+    _, info = o.fgmres(A @ np.ones(a.n), restart=30, rtol=1e-8)
+    assert info["converged"] and info["iterations"] == 1
+
+
+# ---------------------------------------------------------------------------
+# P2: with scalar blocks and no blocking strategy BILU is the scalar Crout ILU
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("tau", [1e-1, 1e-2, 1e-3])
+@pytest.mark.parametrize("seed", [11, 12])
+def test_p2_scalar_blocks_equal_alg1(tau, seed):
+    a = mg.random_sparse(90, 0.06, seed=seed, diag_shift=3.0)
+    A = a.to_dense()
+    mask = np.zeros_like(A, bool)
+    rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
+    mask[rows, a.colind] = True
+    Lr, Lm, Ur, Um = scalar_crout_ilu(A, mask, tau)
+    o = Oracle()
+    assert o.run_partition(a, np.arange(a.n + 1), OracleOptions(tau=tau, **NO_BLOCKING)) == 0
+    f = o.factors()
+    for k in range(a.n):
+        ref_rows = np.flatnonzero(Lm[k + 1:, k]) + k + 1
+        assert np.array_equal(f.R[k], ref_rows)
+        assert np.allclose(f.L[k][:, 0], Lr[ref_rows, k], rtol=1e-13, atol=1e-15)
+        ref_cols = np.flatnonzero(Um[k, k + 1:]) + k + 1
+        assert np.array_equal(f.C[k], ref_cols)
+        assert np.allclose(f.W[k][0], Ur[k, ref_cols], rtol=1e-13, atol=1e-15)
+        assert abs(f.D[k][0, 0] * Ur[k, k] - 1.0) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# P3: banded input with nothing dropped: BILU equals (block) LU
+# ---------------------------------------------------------------------------
+def test_p3_tridiagonal_equals_lu():
+    A = tridiag(120, seed=5)
+    a = mg.dense_to_csr(A)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=1e-3)) == 0
+    log = o.droplog()
+    assert log["kept"][np.flatnonzero(log["norm"] > 0)].all()
+    b = np.sin(np.arange(a.n))
+    assert np.linalg.norm(o.apply(b) - np.linalg.solve(A, b)) <= 1e-13 * np.linalg.norm(b)
+
+
+def test_p3_block_tridiagonal_equals_block_lu():
+    rng = np.random.default_rng(9)
+    nb, bs = 40, 3
+    n = nb * bs
+    A = np.zeros((n, n))
+    for k in range(nb):
+        s = slice(k * bs, (k + 1) * bs)
+        A[s, s] = rng.uniform(-1, 1, (bs, bs)) + 6 * np.eye(bs)
+        if k + 1 < nb:
+            t = slice((k + 1) * bs, (k + 2) * bs)
+            A[s, t] = rng.uniform(-1, 1, (bs, bs))
+            A[t, s] = rng.uniform(-1, 1, (bs, bs))
+    a = mg.dense_to_csr(A)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=1e-4)) == 0
+    b = np.cos(np.arange(n))
+    assert np.linalg.norm(o.apply(b) - np.linalg.solve(A, b)) <= 1e-13 * np.linalg.norm(b)
+
+
+# ---------------------------------------------------------------------------
+# P4: fill stays inside the structural recurrence and the symbolic LU
+# ---------------------------------------------------------------------------
+def symbolic_block_lu(P, starts):
+    """Boolean block LU of the pattern of P: kept patterns with no dropping."""
+    n = P.shape[0]
+    F = P != 0
+    nb = len(starts) - 1
+    for k in range(nb):
+        a, b = starts[k], starts[k + 1]
+        rows = np.flatnonzero(F[b:, a:b].any(axis=1)) + b
+        cols = np.flatnonzero(F[a:b, b:].any(axis=0)) + b
+        F[np.ix_(rows, cols)] = True
+    return F
+
+
+@pytest.mark.parametrize("tau", [1e-1, 1e-2])
+def test_p4_fill_bound(tau):
+    a = mg.grid3d_convdiff(b=2, dims=(5, 5, 4), seed=4)
+    perm = mg.node_perm_to_scalar(mg.grid_nd_node_order((5, 5, 4)), 2)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=tau, use_aggregation=False), pre_perm=perm) == 0
+    f = o.factors()
+    P = permuted_dense(a, f.perm)
+    F = symbolic_block_lu(P, f.starts)
+    for k in range(len(f.starts) - 1):
+        s, e = f.starts[k], f.starts[k + 1]
+        assert F[np.ix_(f.R[k], np.arange(s, e))].any(axis=1).all()
+        assert F[np.ix_(np.arange(s, e), f.C[k])].any(axis=0).all()
+        # local recurrence: rows of A(:,K) below K plus rows of the J that update K
+        allowed = set(np.flatnonzero((P[e:, s:e] != 0).any(axis=1)) + e)
+        for j in range(k):
+            if np.any((f.C[j] >= s) & (f.C[j] < e)):
+                allowed |= set(int(i) for i in f.R[j] if i >= e)
+        assert set(int(i) for i in f.R[k]) <= allowed
+
+
+# ---------------------------------------------------------------------------
+# P5: (L S U)_Omega = A_Omega on the computed pattern, for any tau
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("tau", [3e-1, 1e-2, 1e-4])
+@pytest.mark.parametrize("agg", [False, True])
+def test_p5_kept_pattern_identity(tau, agg):
+    a = mg.grid2d_random_blocks(12, 3, 4.5, seed=1)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=tau, use_aggregation=agg)) == 0
+    assert o.kept_residual() <= 1e-13
+
+
+# ---------------------------------------------------------------------------
+# P6: every dropped row/column is at or below tau, every kept one above,
+# recomputed densely from the factors (Schur complement of the leading part)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("tau", [2e-1, 3e-2])
+def test_p6_drop_rule(tau):
+    a = mg.grid2d_random_blocks(8, 2, 3.0, seed=2)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=tau, use_aggregation=False)) == 0
+    L, S, U, f = assemble(o)
+    P = permuted_dense(a, f.perm)
+    W = S @ U
+    n = a.n
+    checked = 0
+    for k in range(len(f.starts) - 1):
+        s, e = f.starts[k], f.starts[k + 1]
+        D = f.D[k]
+        Cpan = P[e:, s:e] - L[e:, :s] @ W[:s, s:e]
+        Lc = Cpan @ D
+        nr = np.abs(Lc).max(axis=1)
+        kept = np.zeros(n - e, bool)
+        kept[f.R[k] - e] = True
+        margin = 1e-12 * max(1.0, np.abs(Lc).max(initial=0))
+        assert np.all(nr[kept] > tau - margin)
+        assert np.all(nr[~kept] <= tau + margin)
+        assert np.allclose(f.L[k], Lc[kept], rtol=1e-11, atol=1e-13)
+        Rpan = P[s:e, e:] - L[s:e, :s] @ W[:s, e:]
+        Uc = D @ Rpan
+        nc = np.abs(Uc).max(axis=0)
+        keptc = np.zeros(n - e, bool)
+        keptc[f.C[k] - e] = True
+        assert np.all(nc[keptc] > tau - margin)
+        assert np.all(nc[~keptc] <= tau + margin)
+        assert np.allclose(f.W[k], Rpan[:, keptc], rtol=1e-11, atol=1e-13)
+        checked += (~kept).sum() + (~keptc).sum()
+    assert checked > 0
+
+
+# ---------------------------------------------------------------------------
+# P7: cosine blocking recovers the node partition of node-blocked stencils
+# ---------------------------------------------------------------------------
+def _stencil_pattern(dims, offs, b, numbering, seed=0):
+    dims = np.asarray(dims)
+    N = int(np.prod(dims))
+    coords = np.stack(np.unravel_index(np.arange(N), tuple(dims[::-1])), axis=1)[:, ::-1]
+    rng = np.random.default_rng(seed)
+    node_label = np.arange(N) if numbering != "random" else rng.permutation(N)
+    idx = {tuple(c): i for i, c in enumerate(coords)}
+    n = N * b
+
+    def sid(v, c):
+        lv = node_label[v]
+        return c * N + lv if numbering == "component" else b * lv + c
+
+    M = np.zeros((n, n), bool)
+    for v, c in enumerate(coords):
+        for o in offs:
+            w = idx.get(tuple(c + o))
+            if w is None:
+                continue
+            for c1 in range(b):
+                for c2 in range(b):
+                    M[sid(v, c1), sid(w, c2)] = True
+    nodes = [frozenset(sid(v, c) for c in range(b)) for v in range(N)]
+    return M, set(nodes)
+
+
+TRI = [(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1), (1, -1), (-1, 1)]
+
+
+@pytest.mark.parametrize("kind,dims", [("star", (6, 5)), ("star", (4, 4, 3)), ("box", (5, 5, 5)),
+                                       ("tri", (6, 6))])
+@pytest.mark.parametrize("b", [1, 2, 3, 4])
+@pytest.mark.parametrize("numbering", ["node", "component", "random"])
+def test_p7_cosine_node_partition(kind, dims, b, numbering):
+    if kind == "tri":
+        offs = np.array(TRI)
+    else:
+        offs = mg._offsets(len(dims), kind)
+    M, nodes = _stencil_pattern(dims, offs, b, numbering)
+    a = mg.dense_to_csr(M.astype(float), M)
+    perm, gs, nig = cosine_groups(a)
+    assert nig == 0
+    groups = {frozenset(int(x) for x in perm[gs[g]:gs[g + 1]]) for g in range(len(gs) - 1)}
+    if b == 1:
+        # scalar stencils: a group may only join rows with identical or near patterns;
+        # no two grid points of a star/box/tri stencil satisfy the test
+        assert all(len(g) == 1 for g in groups)
+    else:
+        assert groups == nodes
+
+
+def test_p7_cosine_filter_ignores_dense_rows():
+    # an arrow matrix: the dense row/column exceed mu + 2 sigma and stay alone
+    n = 40
+    M = np.eye(n, dtype=bool)
+    M[0, :] = True
+    M[:, 0] = True
+    for i in range(1, n - 1, 2):
+        M[i, i + 1] = M[i + 1, i] = True
+    a = mg.dense_to_csr(M.astype(float), M)
+    perm, gs, nig = cosine_groups(a)
+    assert nig == 1
+    g0 = [list(perm[gs[g]:gs[g + 1]]) for g in range(len(gs) - 1) if 0 in perm[gs[g]:gs[g + 1]]]
+    assert g0 == [[0]]
+
+
+# ---------------------------------------------------------------------------
+# P8: ILU(1,tau) growth closed forms
+# ---------------------------------------------------------------------------
+def test_p8_diagonal_blocks_of_five():
+    # diagonal: r = s = 0, c = l, f = l^2: grow iff l' <= 5
+    a = mg.dense_to_csr(np.diag(np.arange(1.0, 24.0)))
+    bs = ilu1t_blocks(a, np.arange(a.n + 1), 1e-2)
+    assert list(np.diff(bs)) == [5, 5, 5, 5, 3]
+
+
+def test_p8_tridiagonal_blocks_of_five():
+    # large off-diagonals: r = s = 1, c = 3l, f = (l+2) l: grow iff l' <= 5
+    n = 23
+    A = 4 * np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1)
+    bs = ilu1t_blocks(mg.dense_to_csr(A), np.arange(n + 1), 1e-2)
+    assert list(np.diff(bs)) == [5, 5, 5, 5, 3]
+
+
+@pytest.mark.parametrize("n,bmax", [(40, 128), (40, 16)])
+def test_p8_dense_single_block(n, bmax):
+    # dense with all entries above tau|a_kk|: f = c, always grows (up to the cap)
+    A = np.ones((n, n)) + n * np.eye(n)
+    bs = ilu1t_blocks(mg.dense_to_csr(A), np.arange(n + 1), 1e-2, max_block=bmax)
+    expect = [bmax] * (n // bmax) + ([n % bmax] if n % bmax else [])
+    assert list(np.diff(bs)) == expect
+
+
+# ---------------------------------------------------------------------------
+# P9: progressive aggregation closed forms: nu - mu = 2p <= 2(p+q)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind", ["diag", "tri"])
+def test_p9_aggregation_to_cap(kind):
+    n, bmax = 30, 8
+    A = 4 * np.eye(n)
+    if kind == "tri":
+        A += np.eye(n, k=1) + np.eye(n, k=-1)
+    o = Oracle()
+    opts = OracleOptions(tau=1e-2, use_cosine=False, use_ilu1t=False, use_aggregation=True,
+                         max_block=bmax)
+    assert o.run(mg.dense_to_csr(A), opts) == 0
+    assert list(np.diff(o.starts())) == [8, 8, 8, 6]
+    rec = o.mergelog()
+    # every test with a width-1 block K: mu, nu as the closed form says
+    for k, p, q, mu, nu, merged in rec:
+        assert q == 1
+        if kind == "diag":
+            assert (mu, nu) == (p * p + 1, (p + 1) ** 2)
+        else:
+            lastblk = k == n - 1
+            if not lastblk:
+                assert (mu, nu) == (p * p + 2 * p + 3, (p + 1) * (p + 3))
+        assert merged == (p + q <= bmax)
+
+
+# ---------------------------------------------------------------------------
+# P10: merging preserves L S U and keeps D^ = S^{-1}
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("tau", [1e-1, 1e-2])
+def test_p10_merge_preserves_product(tau):
+    a = mg.grid2d_random_blocks(10, 2, 3.5, seed=6)
+    o0, o1 = Oracle(), Oracle()
+    opts0 = OracleOptions(tau=tau, use_aggregation=False, use_ilu1t=False)
+    opts1 = OracleOptions(tau=tau, use_aggregation=True, use_ilu1t=False)
+    assert o0.run(a, opts0) == 0 and o1.run(a, opts1) == 0
+    assert o1.stats()["merges"] > 0
+    assert np.array_equal(o0.perm(), o1.perm())
+    L0, S0, U0, _ = assemble(o0)
+    L1, S1, U1, _ = assemble(o1)
+    M0 = L0 @ S0 @ U0
+    M1 = L1 @ S1 @ U1
+    assert np.linalg.norm(M1 - M0) <= 1e-14 * np.linalg.norm(M0) * 10
+    # apply (uses D) inverts the product (uses S) on random vectors
+    rng = np.random.default_rng(0)
+    perm = o1.perm()
+    for _ in range(3):
+        x = rng.standard_normal(a.n)
+        xp = np.empty_like(x)
+        xp[perm] = o1.lsu_matvec(x[perm])
+        assert np.linalg.norm(o1.apply(xp) - x) <= 1e-12 * np.linalg.norm(x)
+
+
+# ---------------------------------------------------------------------------
+# P11: perturbation of singular pivot blocks
+# ---------------------------------------------------------------------------
+def test_p11_zero_column():
+    s = np.array([[2.0, 0.0, 1.0], [1.0, 0.0, 3.0], [0.5, 0.0, 1.0]])
+    r, su, di = perturb_invert(s, alpha=7.0)
+    assert r >= 1
+    assert su[1, 1] == pytest.approx(1e-2 * 7.0, rel=0, abs=1e-15)
+    assert np.allclose(su @ di, np.eye(3), atol=1e-12)
+
+
+def test_p11_all_ones_2x2():
+    s = np.ones((2, 2))
+    r, su, di = perturb_invert(s, alpha=1.0)
+    assert r == 1
+    # columns: 1*1.1+0.01 = 1.11 on both diagonals; rows: 1.11*1.111+0.01
+    assert np.allclose(su, [[1.24321, 1.0], [1.0, 1.24321]], rtol=0, atol=1e-14)
+    assert np.allclose(su @ di, np.eye(2), atol=1e-13)
+
+
+def test_p11_beta_one_reading():
+    s = np.ones((2, 2))
+    r, su, _ = perturb_invert(s, alpha=1.0, opts=OracleOptions(beta_one=True))
+    # beta = 1: columns 1*1.1+0.01 = 1.11; rows 1.11*1.1+0.01 = 1.231
+    assert np.allclose(su, [[1.231, 1.0], [1.0, 1.231]], rtol=0, atol=1e-14)
+
+
+def test_p11_regular_block_untouched():
+    s = np.array([[4.0, 1.0], [2.0, 3.0]])
+    r, su, di = perturb_invert(s, alpha=4.0)
+    assert r == 0 and np.array_equal(su, s)
+    assert np.allclose(di, np.linalg.inv(s), rtol=1e-15, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# P12: apply = dense solve with the assembled preconditioner
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("agg", [False, True])
+def test_p12_apply_dense(agg):
+    a = mg.grid2d_random_blocks(9, 3, 4.5, seed=8)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=5e-2, use_aggregation=agg)) == 0
+    L, S, U, f = assemble(o)
+    M = L @ S @ U
+    Pm = np.eye(a.n)[:, f.perm]     # (Pm x)[perm[i]] = x[i]
+    Morig = Pm @ M @ Pm.T
+    x = np.random.default_rng(1).standard_normal(a.n)
+    y = o.apply(x)
+    assert np.linalg.norm(y - np.linalg.solve(Morig, x)) <= 1e-12 * np.linalg.norm(y)
+
+
+# ---------------------------------------------------------------------------
+# P13: FGMRES with M = I minimises the residual over the Krylov space
+# ---------------------------------------------------------------------------
+def test_p13_fgmres_minimal_residual():
+    a = mg.random_sparse(60, 0.1, seed=21, diag_shift=1.5)
+    A = a.to_dense()
+    b = np.random.default_rng(2).standard_normal(a.n)
+    m = 10
+    _, info, hist = fgmres_plain(a, b, restart=m, rtol=1e-14, maxit=m)
+    assert len(hist) == m
+    K = np.zeros((a.n, m))
+    v = b / np.linalg.norm(b)
+    for j in range(m):          # orthonormal Krylov basis by repeated QR
+        K[:, j] = v
+        Q, _ = np.linalg.qr(K[:, :j + 1])
+        v = A @ Q[:, j]
+    for j in range(1, m + 1):
+        Q, _ = np.linalg.qr(K[:, :j])
+        AQ = A @ Q
+        y, *_ = np.linalg.lstsq(AQ, b, rcond=None)
+        rmin = np.linalg.norm(b - AQ @ y)
+        assert hist[j - 1] == pytest.approx(rmin, rel=1e-8)
+    assert np.all(np.diff(hist) <= 1e-12 * hist[0])
+
+
+# ---------------------------------------------------------------------------
+# P14: determinism
+# ---------------------------------------------------------------------------
+def test_p14_deterministic():
+    a = mg.grid2d_random_blocks()
+    outs = []
+    for _ in range(2):
+        o = Oracle()
+        assert o.run(a, OracleOptions()) == 0
+        f = o.factors()
+        outs.append((f.starts.tobytes(), b"".join(x.tobytes() for x in f.L),
+                     b"".join(x.tobytes() for x in f.W), b"".join(x.tobytes() for x in f.D)))
+    assert outs[0] == outs[1]
+
+
+# ---------------------------------------------------------------------------
+# The small workload converges (checked before any GPU work)
+# ---------------------------------------------------------------------------
+def test_cd2d_workload_converges():
+    a = mg.grid2d_random_blocks(32, 3, 4.5, seed=0)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=1e-2)) == 0
+    b = a.matvec(np.ones(a.n))
+    x, info = o.fgmres(b, restart=30, rtol=1e-8)
+    assert info["converged"] and info["rel_residual"] <= 1e-8
+    assert np.abs(x - 1).max() < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# P8 (sets): at tau = 0 the ILU(1,tau) estimate is the textbook ILU(1)
+# pattern: original entries plus fill created by two original entries
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1])
+def test_p8_sets_tau0_are_ilu1_pattern(seed):
+    from oracle import ilu1t_sets
+    a = mg.random_sparse(70, 0.05, seed=seed, diag_shift=2.0)
+    Pm = a.to_dense() != 0
+    n = a.n
+    lower = np.tril(Pm, -1).astype(int)
+    upper = np.triu(Pm, 1).astype(int)
+    lev1 = Pm | ((lower @ upper) > 0)   # fill (i,k) via some j < min(i,k)
+    for k in range(n):
+        I, J = ilu1t_sets(a, k, 0.0)
+        assert np.array_equal(I, np.flatnonzero(lev1[k + 1:, k]) + k + 1)
+        assert np.array_equal(J, np.flatnonzero(lev1[k, k + 1:]) + k + 1)
+
+
+@pytest.mark.parametrize("tau,expect_fill,expect_orig", [(0.05, True, True), (0.07, False, True),
+                                                        (0.3, False, False)])
+def test_p8_sets_5point_thresholds(tau, expect_fill, expect_orig):
+    # 5-point Laplacian (4, -1) on a 6x6 grid, natural order: the level-1 fill
+    # at (k+nx-1, k) has size |(-1)(-1)/4| = 1/4, compared with tau*4;
+    # original neighbours have size 1, compared with tau*4.
+    from oracle import ilu1t_sets
+    nx = 6
+    n = nx * nx
+    A = 4 * np.eye(n)
+    for i in range(n):
+        x, y = i % nx, i // nx
+        if x + 1 < nx:
+            A[i, i + 1] = A[i + 1, i] = -1
+        if y + 1 < nx:
+            A[i, i + nx] = A[i + nx, i] = -1
+    a = mg.dense_to_csr(A)
+    k = 2 * nx + 2                   # interior point
+    I, J = ilu1t_sets(a, k, tau)
+    exp = set()
+    if expect_orig:
+        exp |= {k + 1, k + nx}
+    if expect_fill:
+        exp |= {k + nx - 1}
+    assert set(I.tolist()) == exp
+    assert set(J.tolist()) == exp      # symmetric matrix: J~ mirrors I~
+
+
+def test_p11_negative_block_sign():
+    s = -np.ones((2, 2))
+    r, su, _ = perturb_invert(s, alpha=1.0)
+    assert r == 1
+    assert np.allclose(su, [[-1.24321, -1.0], [-1.0, -1.24321]], rtol=0, atol=1e-14)
+
+
+def test_p8_sets_use_the_pivot_diagonal():
+    # The fill a_ki a_ij (i < k) is measured against |a_ii a_kk|: raising the
+    # diagonal of the intermediate index i = k-1 to 8 makes the fill 1/(8*4)
+    # of the product, below tau = 0.05 (it would pass against a_jj = 4).
+    from oracle import ilu1t_sets
+    nx = 6
+    n = nx * nx
+    A = 4 * np.eye(n)
+    for i in range(n):
+        x, y = i % nx, i // nx
+        if x + 1 < nx:
+            A[i, i + 1] = A[i + 1, i] = -1
+        if y + 1 < nx:
+            A[i, i + nx] = A[i + nx, i] = -1
+    k = 2 * nx + 2
+    A[k - 1, k - 1] = 8.0
+    I, J = ilu1t_sets(mg.dense_to_csr(A), k, 0.05)
+    assert set(I.tolist()) == {k + 1, k + nx}
+    assert set(J.tolist()) == {k + 1, k + nx}
+    I, J = ilu1t_sets(mg.dense_to_csr(A), k, 0.03)
+    assert set(I.tolist()) == {k + 1, k + nx, k + nx - 1}
+    assert set(J.tolist()) == {k + 1, k + nx, k + nx - 1}
