@@ -1,0 +1,185 @@
+/*
+ * bilu.h -- block incomplete LU (BILU) on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Bollhoefer, Schenk and Verbosio, "High Performance Block
+ * Incomplete LU Factorization" (arXiv 1908.10169).  The library computes the
+ * Crout-type block ILU of Sec. 2.2 on a permuted matrix
+ *
+ *      P^T A P  ~  L S U,   L, U^T unit block lower triangular,
+ *                           S block diagonal, D_K = S_K^{-1} stored,
+ *
+ * with the initial blocking of Sec. 3.2 (cosine) and Sec. 3.4 (ILU(1,tau)),
+ * the symmetric reordering of Sec. 3.3, the perturbation of Sec. 3.6 and the
+ * progressive aggregation of Sec. 3.5, and uses it as the preconditioner
+ * M = P L S U P^T of Sec. 3.7 (no scaling/matching: D_l = D_r = Pi = I)
+ * inside flexible GMRES.
+ *
+ * Conventions
+ *  - 0-based CSR: rowptr int64[n+1], colind int32[nnz] strictly increasing
+ *    within each row, val double[nnz] finite.
+ *  - Host arrays are borrowed for the duration of a call and copied.
+ *  - Device arrays are plain HIP device pointers owned by the caller;
+ *    work is enqueued on the handle's stream (the stream given at create;
+ *    NULL = the default stream) and calls that return results to the host
+ *    synchronize that stream.
+ *  - Every entry point returns a bilu_status; no C++ exception, abort or
+ *    exit crosses this boundary.  bilu_last_error() gives a message.
+ *  - A handle is not thread-safe.
+ */
+#ifndef BILU_H
+#define BILU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BILU_OK = 0,
+  BILU_WARN_PERTURBED = 1,      /* factor succeeded, some pivot blocks perturbed */
+  BILU_WARN_NOT_CONVERGED = 2,  /* solver stopped at maxit above rtol           */
+  BILU_ERR_INVALID = -1,        /* bad argument or malformed CSR                 */
+  BILU_ERR_NO_MEMORY = -2,      /* device or host allocation, or a capacity cap  */
+  BILU_ERR_STATE = -3,          /* call order: analyze before factor before apply */
+  BILU_ERR_SINGULAR = -4,       /* a pivot block stayed singular after perturbing */
+  BILU_ERR_DEVICE = -5,         /* HIP runtime error or kernel-reported fault     */
+  BILU_ERR_INTERNAL = -6
+} bilu_status;
+
+typedef enum { BILU_ORDER_ND = 0, BILU_ORDER_NATURAL = 1 } bilu_ordering;
+typedef enum { BILU_PREC_F64 = 0, BILU_PREC_F32 = 1, BILU_PREC_BF16 = 2 } bilu_precision;
+typedef enum { BILU_NORM_INF = 0, BILU_NORM_TWO = 1 } bilu_drop_norm;
+
+typedef struct {
+  int use_cosine;        /* Sec. 3.2 initial blocking (default 1)                     */
+  int use_ilu1t;         /* Sec. 3.4 ILU(1,tau) block growth (default 1)              */
+  int use_aggregation;   /* Sec. 3.5 progressive aggregation (default 1)              */
+  int max_block;         /* cap on block widths, 1..128 (default 128)                 */
+  double cos_eps;        /* cosine threshold (default 0.8)                            */
+  int ordering;          /* bilu_ordering of the compressed graph (default ND)        */
+  const int64_t* pre_perm; /* optional host permutation new->old applied to A before  */
+                         /* the cosine step (NULL = identity); read during analyze    */
+  int drop_norm;         /* bilu_drop_norm of the scaled block rows/columns (INF)     */
+  double perturb_tau;    /* Sec. 3.6 absolute tolerance (default 1e-2)                */
+  double perturb_rho;    /* Sec. 3.6 relative tolerance (default 1e-1)                */
+  double pivot_eps;      /* pivot |u_jj| <= pivot_eps*max|S| triggers perturbation    */
+  int beta_one;          /* 0: beta_j = max|column j| (default); 1: beta_j = 1        */
+  int update_precision;  /* bilu_precision of the Schur-complement products (F64)    */
+  size_t heap_bytes;     /* factor heap size; 0 = sized from nnz(A)                  */
+} bilu_options;
+
+typedef struct bilu_handle bilu_handle;
+
+typedef struct {
+  int64_t iterations;    /* Arnoldi steps taken                                       */
+  int64_t restarts;      /* restart cycles started                                    */
+  double rel_residual;   /* true ||b - A x||_2 / ||b||_2 at exit                      */
+  double seconds;        /* wall time of the call                                     */
+  int converged;
+} bilu_solve_info;
+
+typedef struct {
+  int64_t n, nnz_a;
+  int64_t ngroups;            /* cosine groups                                        */
+  int64_t nblocks_initial;    /* blocks after ILU(1,tau), before aggregation         */
+  int64_t nblocks;            /* final blocks                                         */
+  int64_t max_width;
+  double avg_width, std_width;
+  int64_t nnz_l, nnz_w, nnz_d;/* stored factor entries                               */
+  int64_t merges, perturbed_blocks;
+  int64_t factor_levels;      /* dependency levels of the factorization schedule     */
+  int64_t apply_levels_fwd, apply_levels_bwd;
+  double flops_update;        /* counted Schur-update flops (2 m p q per product)    */
+  double bytes_apply;         /* algorithmic bytes of one preconditioner apply        */
+  double t_analyze, t_ilu1t, t_factor_device, t_aggregate, t_factor;  /* seconds   */
+} bilu_stats;
+
+/* Library-allocated host copy of the factors (for checking), final blocks. */
+typedef struct {
+  int64_t n, nblocks, nblocks_initial;
+  int64_t* perm;           /* [n] new -> old                                         */
+  int64_t* starts;         /* [nblocks+1]                                            */
+  int64_t* starts_initial; /* [nblocks_initial+1]                                    */
+  int64_t* group_starts;   /* [ngroups+1] cosine groups in the permuted numbering    */
+  int64_t ngroups;
+  int64_t* r_ptr;          /* [nblocks+1] offsets into r_idx                         */
+  int32_t* r_idx;          /* rows of L per block, ascending                         */
+  int64_t* c_ptr;          /* [nblocks+1]                                            */
+  int32_t* c_idx;          /* columns of U per block, ascending                      */
+  double* l_val;           /* per block |R_K| x q row-major, blocks concatenated     */
+  double* w_val;           /* per block q x |C_K| column-major                       */
+  double* d_val;           /* per block q x q row-major                              */
+} bilu_factors_host;
+
+/* Defaults: the paper's constants (Sec. 3.2, 3.4-3.6). */
+void bilu_default_options(bilu_options* opt);
+
+/* Create a handle.  opt may be NULL (defaults).  hip_stream is a hipStream_t
+ * (NULL = default stream).  Returns BILU_ERR_INVALID on bad options. */
+bilu_status bilu_create(bilu_handle** h, const bilu_options* opt, void* hip_stream);
+
+/* Sec. 3.2-3.3 (preprocessing steps 2-3 of Sec. 3.7): validate the CSR,
+ * cosine-group the rows, compress, order the compressed graph, expand the
+ * permutation, and upload the permuted matrix.  Host arrays.  Synchronous.
+ * Errors: BILU_ERR_INVALID (n <= 0, unsorted/duplicate/out-of-range column,
+ * non-finite value, bad pre_perm), BILU_ERR_NO_MEMORY. */
+bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr,
+                         const int32_t* colind, const double* val);
+
+/* Sec. 3.4-3.6 and Sec. 2.2: guess the initial blocks with ILU(1,tau), run
+ * the block Crout sweep on the GPU with drop tolerance tau >= 0 (tau = 0
+ * drops only exactly-zero rows/columns), perturb singular pivot blocks, and
+ * aggregate blocks progressively.  May be called again with another tau.
+ * Returns BILU_OK, BILU_WARN_PERTURBED, BILU_ERR_SINGULAR, BILU_ERR_STATE
+ * (no analyze), BILU_ERR_NO_MEMORY, BILU_ERR_DEVICE.  Synchronous. */
+bilu_status bilu_factor(bilu_handle* h, double tau);
+
+/* Sec. 3.7: y = M^{-1} x = P (L S U)^{-1} P^T x, multiplying by D_K
+ * (Sec. 2.2).  x, y: device arrays of n doubles in the original numbering,
+ * x != y.  Asynchronous on the handle's stream.  BILU_ERR_STATE before a
+ * successful factor. */
+bilu_status bilu_apply(bilu_handle* h, const double* x, double* y);
+
+/* y = A x with the analyzed matrix (original numbering), device arrays. */
+bilu_status bilu_spmv(bilu_handle* h, const double* x, double* y);
+
+/* Right-preconditioned restarted flexible GMRES(restart) for A x = b with M
+ * from bilu_factor.  b, x: device arrays (original numbering); x holds the
+ * initial guess on entry and the solution on exit.  Stops when the
+ * residual estimate reaches rtol*||b|| and the true residual confirms it,
+ * or after maxit Arnoldi steps.  info (host, may be NULL) receives counts
+ * and the true relative residual.  Returns BILU_OK or
+ * BILU_WARN_NOT_CONVERGED.  Synchronous. */
+bilu_status bilu_fgmres_solve(bilu_handle* h, const double* b, double* x, int restart,
+                              double rtol, int maxit, bilu_solve_info* info);
+
+/* Host-only structural preprocessing (no GPU is touched): the cosine
+ * groups (Sec. 3.2), the ordering of the compressed graph (Sec. 3.3) and the
+ * ILU(1,tau) initial partition (Sec. 3.4) that bilu_analyze + bilu_factor
+ * would use.  perm (n entries, new -> old), group_starts (n+1 entries) and
+ * block_starts (n+1 entries) are caller-allocated host arrays; *ngroups and
+ * *nblocks receive the counts.  Same errors as bilu_analyze. */
+bilu_status bilu_preprocess(const bilu_options* opt, int64_t n, const int64_t* rowptr,
+                            const int32_t* colind, const double* val, double tau,
+                            int64_t* perm, int64_t* group_starts, int64_t* ngroups,
+                            int64_t* block_starts, int64_t* nblocks);
+
+/* Statistics of the last analyze/factor (block sizes as in the paper's
+ * tables of Sec. 3.2-3.5: number, max, average, standard deviation). */
+bilu_status bilu_get_stats(const bilu_handle* h, bilu_stats* st);
+
+/* Host copies of permutation, partition and factors; free with
+ * bilu_free_factors. */
+bilu_status bilu_export_factors(const bilu_handle* h, bilu_factors_host* out);
+void bilu_free_factors(bilu_factors_host* f);
+
+void bilu_destroy(bilu_handle* h);
+const char* bilu_status_string(bilu_status s);
+const char* bilu_last_error(const bilu_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BILU_H */

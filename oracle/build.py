@@ -16,7 +16,7 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB
     tmp = LIB + ".tmp"
-    cmd = ["g++", "-O2", "-march=native", "-std=c++17", "-fPIC", "-shared",
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared",
            "-o", tmp, SRC]
     subprocess.check_call(cmd, cwd=HERE)
     os.replace(tmp, LIB)

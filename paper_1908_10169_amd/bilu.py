@@ -1,0 +1,284 @@
+"""Thin ctypes binding of libbilu.so (include/bilu.h).
+
+Argument marshalling only: every step of analyze/factor/apply/solve runs in
+the library.  PyTorch provides device buffers and the current HIP stream.
+Importing this module never falls back to anything: a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbilu.so")
+
+BILU_OK = 0
+BILU_WARN_PERTURBED = 1
+BILU_WARN_NOT_CONVERGED = 2
+BILU_ERR_INVALID = -1
+BILU_ERR_NO_MEMORY = -2
+BILU_ERR_STATE = -3
+BILU_ERR_SINGULAR = -4
+BILU_ERR_DEVICE = -5
+BILU_ERR_INTERNAL = -6
+
+ORDER_ND, ORDER_NATURAL = 0, 1
+PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("use_cosine", C.c_int), ("use_ilu1t", C.c_int), ("use_aggregation", C.c_int),
+        ("max_block", C.c_int), ("cos_eps", C.c_double), ("ordering", C.c_int),
+        ("pre_perm", C.c_void_p), ("drop_norm", C.c_int), ("perturb_tau", C.c_double),
+        ("perturb_rho", C.c_double), ("pivot_eps", C.c_double), ("beta_one", C.c_int),
+        ("update_precision", C.c_int), ("heap_bytes", C.c_size_t),
+    ]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("restarts", C.c_int64),
+                ("rel_residual", C.c_double), ("seconds", C.c_double), ("converged", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("nnz_a", C.c_int64), ("ngroups", C.c_int64),
+        ("nblocks_initial", C.c_int64), ("nblocks", C.c_int64), ("max_width", C.c_int64),
+        ("avg_width", C.c_double), ("std_width", C.c_double),
+        ("nnz_l", C.c_int64), ("nnz_w", C.c_int64), ("nnz_d", C.c_int64),
+        ("merges", C.c_int64), ("perturbed_blocks", C.c_int64), ("factor_levels", C.c_int64),
+        ("apply_levels_fwd", C.c_int64), ("apply_levels_bwd", C.c_int64),
+        ("flops_update", C.c_double), ("bytes_apply", C.c_double),
+        ("t_analyze", C.c_double), ("t_ilu1t", C.c_double), ("t_factor_device", C.c_double),
+        ("t_aggregate", C.c_double), ("t_factor", C.c_double),
+    ]
+
+
+class FactorsHost(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("nblocks", C.c_int64), ("nblocks_initial", C.c_int64),
+        ("perm", C.POINTER(C.c_int64)), ("starts", C.POINTER(C.c_int64)),
+        ("starts_initial", C.POINTER(C.c_int64)), ("group_starts", C.POINTER(C.c_int64)),
+        ("ngroups", C.c_int64),
+        ("r_ptr", C.POINTER(C.c_int64)), ("r_idx", C.POINTER(C.c_int32)),
+        ("c_ptr", C.POINTER(C.c_int64)), ("c_idx", C.POINTER(C.c_int32)),
+        ("l_val", C.POINTER(C.c_double)), ("w_val", C.POINTER(C.c_double)),
+        ("d_val", C.POINTER(C.c_double)),
+    ]
+
+
+EXPORTED = [
+    "bilu_default_options", "bilu_create", "bilu_analyze", "bilu_factor", "bilu_apply",
+    "bilu_spmv", "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors",
+    "bilu_free_factors", "bilu_destroy", "bilu_status_string", "bilu_last_error",
+    "bilu_preprocess",
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libbilu.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1908_10169_amd/build.py")
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    lib.bilu_default_options.argtypes = [C.POINTER(Options)]
+    lib.bilu_create.argtypes = [C.POINTER(vp), C.POINTER(Options), vp]
+    lib.bilu_analyze.argtypes = [vp, C.c_int64, vp, vp, vp]
+    lib.bilu_factor.argtypes = [vp, C.c_double]
+    lib.bilu_apply.argtypes = [vp, vp, vp]
+    lib.bilu_spmv.argtypes = [vp, vp, vp]
+    lib.bilu_fgmres_solve.argtypes = [vp, vp, vp, C.c_int, C.c_double, C.c_int,
+                                      C.POINTER(SolveInfo)]
+    lib.bilu_get_stats.argtypes = [vp, C.POINTER(Stats)]
+    lib.bilu_export_factors.argtypes = [vp, C.POINTER(FactorsHost)]
+    lib.bilu_free_factors.argtypes = [C.POINTER(FactorsHost)]
+    lib.bilu_destroy.argtypes = [vp]
+    lib.bilu_destroy.restype = None
+    lib.bilu_status_string.argtypes = [C.c_int]
+    lib.bilu_status_string.restype = C.c_char_p
+    lib.bilu_last_error.argtypes = [vp]
+    lib.bilu_last_error.restype = C.c_char_p
+    lib.bilu_preprocess.argtypes = [C.POINTER(Options), C.c_int64, vp, vp, vp, C.c_double,
+                                    vp, vp, C.POINTER(C.c_int64), vp, C.POINTER(C.c_int64)]
+    for f in ("bilu_create", "bilu_analyze", "bilu_factor", "bilu_apply", "bilu_spmv",
+              "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors", "bilu_preprocess"):
+        getattr(lib, f).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+class BiluError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{load().bilu_status_string(status).decode()}: {msg}")
+        self.status = status
+
+
+def default_options(**kw) -> Options:
+    o = Options()
+    load().bilu_default_options(C.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, int(v) if isinstance(v, bool) else v)
+    return o
+
+
+@dataclass
+class Factors:
+    perm: np.ndarray
+    starts: np.ndarray
+    starts_initial: np.ndarray
+    group_starts: np.ndarray
+    R: list
+    L: list
+    C: list
+    W: list
+    D: list
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return stream
+
+
+def preprocess(a, tau: float, pre_perm=None, **kw):
+    """Host-only structural preprocessing: (perm, group_starts, block_starts)."""
+    lib = load()
+    opts = default_options(**kw)
+    pp = None
+    if pre_perm is not None:
+        pp = np.ascontiguousarray(pre_perm, dtype=np.int64)
+        opts.pre_perm = pp.ctypes.data
+    rp = np.ascontiguousarray(a.rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(a.colind, dtype=np.int32)
+    v = np.ascontiguousarray(a.val, dtype=np.float64)
+    perm = np.empty(a.n, dtype=np.int64)
+    gs = np.empty(a.n + 1, dtype=np.int64)
+    bs = np.empty(a.n + 1, dtype=np.int64)
+    ng, nb = C.c_int64(), C.c_int64()
+    st = lib.bilu_preprocess(C.byref(opts), a.n, rp.ctypes.data, ci.ctypes.data, v.ctypes.data,
+                             tau, perm.ctypes.data, gs.ctypes.data, C.byref(ng), bs.ctypes.data,
+                             C.byref(nb))
+    if st != BILU_OK:
+        raise BiluError(st, "bilu_preprocess")
+    return perm, gs[:ng.value + 1].copy(), bs[:nb.value + 1].copy()
+
+
+class Bilu:
+    """One BILU preconditioner handle (one matrix)."""
+
+    def __init__(self, options: Options | None = None, stream=None, **kw):
+        self._lib = load()
+        self._h = C.c_void_p()
+        opts = options if options is not None else default_options(**kw)
+        self._pre = None
+        if kw.get("pre_perm") is not None:
+            raise ValueError("pass pre_perm to analyze()")
+        self._opts = opts
+        st = self._lib.bilu_create(C.byref(self._h), C.byref(opts), C.c_void_p(_stream_ptr(stream)))
+        if st != BILU_OK:
+            raise BiluError(st, "bilu_create")
+
+    def _check(self, st, what, ok=(BILU_OK,)):
+        if st not in ok:
+            raise BiluError(st, f"{what}: {self._lib.bilu_last_error(self._h).decode()}")
+        return st
+
+    def close(self):
+        if self._h:
+            self._lib.bilu_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ API
+    def analyze(self, a, pre_perm=None):
+        rp = np.ascontiguousarray(a.rowptr, dtype=np.int64)
+        ci = np.ascontiguousarray(a.colind, dtype=np.int32)
+        v = np.ascontiguousarray(a.val, dtype=np.float64)
+        if pre_perm is not None:
+            self._pre = np.ascontiguousarray(pre_perm, dtype=np.int64)
+            self._opts.pre_perm = self._pre.ctypes.data
+        else:
+            self._opts.pre_perm = None
+        # options are copied at create: rebuild the handle with the permutation
+        self.close()
+        st = self._lib.bilu_create(C.byref(self._h), C.byref(self._opts),
+                                   C.c_void_p(_stream_ptr(None)))
+        if st != BILU_OK:
+            raise BiluError(st, "bilu_create")
+        self.n = a.n
+        return self._check(self._lib.bilu_analyze(self._h, a.n, rp.ctypes.data, ci.ctypes.data,
+                                                  v.ctypes.data), "bilu_analyze")
+
+    def factor(self, tau: float):
+        return self._check(self._lib.bilu_factor(self._h, tau), "bilu_factor",
+                           ok=(BILU_OK, BILU_WARN_PERTURBED))
+
+    def apply(self, x, y):
+        """y = M^{-1} x; x, y: torch float64 CUDA tensors of length n."""
+        return self._check(self._lib.bilu_apply(self._h, x.data_ptr(), y.data_ptr()), "bilu_apply")
+
+    def spmv(self, x, y):
+        return self._check(self._lib.bilu_spmv(self._h, x.data_ptr(), y.data_ptr()), "bilu_spmv")
+
+    def fgmres(self, b, x, restart=30, rtol=1e-8, maxit=2000):
+        info = SolveInfo()
+        st = self._lib.bilu_fgmres_solve(self._h, b.data_ptr(), x.data_ptr(), restart, rtol,
+                                         maxit, C.byref(info))
+        self._check(st, "bilu_fgmres_solve", ok=(BILU_OK, BILU_WARN_NOT_CONVERGED))
+        return dict(iterations=info.iterations, restarts=info.restarts,
+                    rel_residual=info.rel_residual, seconds=info.seconds,
+                    converged=bool(info.converged))
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self._lib.bilu_get_stats(self._h, C.byref(s)), "bilu_get_stats")
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def export(self) -> Factors:
+        fh = FactorsHost()
+        self._check(self._lib.bilu_export_factors(self._h, C.byref(fh)), "bilu_export_factors")
+        try:
+            n, nb = fh.n, fh.nblocks
+            arr = lambda p, m, dt: np.ctypeslib.as_array(p, shape=(m,)).astype(dt, copy=True)  # noqa
+            starts = arr(fh.starts, nb + 1, np.int64)
+            rp = arr(fh.r_ptr, nb + 1, np.int64)
+            cp = arr(fh.c_ptr, nb + 1, np.int64)
+            q = np.diff(starts)
+            tr, tc = int(rp[-1]), int(cp[-1])
+            ridx = arr(fh.r_idx, max(tr, 1), np.int64)[:tr]
+            cidx = arr(fh.c_idx, max(tc, 1), np.int64)[:tc]
+            lv = arr(fh.l_val, max(int((np.diff(rp) * q).sum()), 1), np.float64)
+            wv = arr(fh.w_val, max(int((np.diff(cp) * q).sum()), 1), np.float64)
+            dv = arr(fh.d_val, max(int((q * q).sum()), 1), np.float64)
+            f = Factors(arr(fh.perm, n, np.int64), starts,
+                        arr(fh.starts_initial, fh.nblocks_initial + 1, np.int64),
+                        arr(fh.group_starts, fh.ngroups + 1, np.int64), [], [], [], [], [])
+            lo = wo = do = 0
+            for k in range(nb):
+                qk = int(q[k])
+                mr, mc = int(rp[k + 1] - rp[k]), int(cp[k + 1] - cp[k])
+                f.R.append(ridx[rp[k]:rp[k + 1]])
+                f.C.append(cidx[cp[k]:cp[k + 1]])
+                f.L.append(lv[lo:lo + mr * qk].reshape(mr, qk)); lo += mr * qk
+                f.W.append(wv[wo:wo + mc * qk].reshape(mc, qk).T); wo += mc * qk
+                f.D.append(dv[do:do + qk * qk].reshape(qk, qk)); do += qk * qk
+            return f
+        finally:
+            self._lib.bilu_free_factors(C.byref(fh))

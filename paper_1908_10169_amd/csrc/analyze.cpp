@@ -1,0 +1,674 @@
+// Host-side structural preprocessing of the BILU library:
+//   - CSR validation,
+//   - cosine-based grouping of rows with similar patterns (Sec. 3.2),
+//   - compression to the group graph, ordering, expansion (Sec. 3.3),
+//   - the simplified ILU(1,tau) guess of the initial blocks (Sec. 3.4),
+//   - the block elimination tree that schedules the numeric sweep.
+// Integer and comparison work only; all numeric factorization runs on the GPU.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <numeric>
+#include <thread>
+
+#include "internal.h"
+
+namespace bilu {
+namespace {
+
+// Run body(lo, hi) over [0, n) on the host's cores.
+template <class F>
+void parallel_for(int64_t n, F body) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 4096 || nt == 1) {
+    body(int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  int64_t chunk = (n + nt - 1) / nt;
+  for (unsigned t = 0; t < nt; ++t) {
+    int64_t lo = t * chunk, hi = std::min<int64_t>(n, lo + chunk);
+    if (lo >= hi) break;
+    th.emplace_back([=] { body(lo, hi); });
+  }
+  for (auto& x : th) x.join();
+}
+
+struct Csr {
+  int64_t n = 0;
+  std::vector<int64_t> rp;
+  std::vector<int32_t> ci;
+  std::vector<double> v;
+};
+
+// Transpose (CSR -> CSC), rows of each column ascending.
+Csr transpose(const Csr& a) {
+  Csr t;
+  t.n = a.n;
+  t.rp.assign(a.n + 1, 0);
+  for (int32_t c : a.ci) t.rp[c + 1]++;
+  std::partial_sum(t.rp.begin(), t.rp.end(), t.rp.begin());
+  t.ci.resize(a.ci.size());
+  t.v.resize(a.v.size());
+  std::vector<int64_t> fill(t.rp.begin(), t.rp.end() - 1);
+  for (int64_t i = 0; i < a.n; ++i)
+    for (int64_t k = a.rp[i]; k < a.rp[i + 1]; ++k) {
+      int64_t d = fill[a.ci[k]]++;
+      t.ci[d] = (int32_t)i;
+      t.v[d] = a.v[k];
+    }
+  return t;
+}
+
+// B = A(perm, perm) with perm new -> old; columns re-sorted per row.
+Csr permute(const Csr& a, const std::vector<int64_t>& perm) {
+  const int64_t n = a.n;
+  std::vector<int32_t> inv(n);
+  for (int64_t i = 0; i < n; ++i) inv[perm[i]] = (int32_t)i;
+  Csr b;
+  b.n = n;
+  b.rp.assign(n + 1, 0);
+  for (int64_t i = 0; i < n; ++i) b.rp[i + 1] = a.rp[perm[i] + 1] - a.rp[perm[i]];
+  std::partial_sum(b.rp.begin(), b.rp.end(), b.rp.begin());
+  b.ci.resize(a.ci.size());
+  b.v.resize(a.v.size());
+  parallel_for(n, [&](int64_t lo, int64_t hi) {
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t i = lo; i < hi; ++i) {
+      int64_t o = perm[i];
+      row.clear();
+      for (int64_t k = a.rp[o]; k < a.rp[o + 1]; ++k) row.emplace_back(inv[a.ci[k]], a.v[k]);
+      std::sort(row.begin(), row.end(),
+                [](const auto& x, const auto& y) { return x.first < y.first; });
+      int64_t d = b.rp[i];
+      for (auto& e : row) {
+        b.ci[d] = e.first;
+        b.v[d++] = e.second;
+      }
+    }
+  });
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 3.2 cosine grouping.  Row j > i joins the group seeded by row i when
+// |pat(i) & pat(j)|^2 >= eps |pat(i)| |pat(j)| and neither row nor column
+// of j (or i) has more than mu + 2 sigma entries.  The test involves only
+// the pair, so candidates are found for every seed in parallel and the
+// greedy seed order (ascending i, members ascending j, at most max_block
+// members) is replayed afterwards.
+// ---------------------------------------------------------------------------
+void cosine(const Csr& a, const Csr& at, double eps, int max_block, std::vector<int64_t>& q,
+            std::vector<int64_t>& gstart) {
+  const int64_t n = a.n;
+  std::vector<int64_t> rc(n), cc(n);
+  for (int64_t i = 0; i < n; ++i) {
+    rc[i] = a.rp[i + 1] - a.rp[i];
+    cc[i] = at.rp[i + 1] - at.rp[i];
+  }
+  const double mean = double(a.rp[n]) / double(n);
+  double vr = 0.0, vc = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    vr += (rc[i] - mean) * (rc[i] - mean);
+    vc += (cc[i] - mean) * (cc[i] - mean);
+  }
+  const double lim_r = mean + 2.0 * std::sqrt(vr / n), lim_c = mean + 2.0 * std::sqrt(vc / n);
+  std::vector<char> skip(n);
+  for (int64_t i = 0; i < n; ++i) skip[i] = rc[i] > lim_r || cc[i] > lim_c;
+
+  // candidates per seed, found in parallel
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  int64_t chunk = (n + nt - 1) / nt;
+  std::vector<std::vector<int64_t>> cptr(nt), clist(nt);
+  std::vector<std::thread> th;
+  const bool int_test = (eps == 0.8);
+  for (unsigned t = 0; t < nt; ++t) {
+    th.emplace_back([&, t] {
+      int64_t lo = std::min<int64_t>(n, t * chunk), hi = std::min<int64_t>(n, lo + chunk);
+      std::vector<int32_t> hits(n, 0);
+      std::vector<int64_t> seen;
+      auto& P = cptr[t];
+      auto& Lst = clist[t];
+      P.push_back(0);
+      for (int64_t i = lo; i < hi; ++i) {
+        if (!skip[i]) {
+          seen.clear();
+          for (int64_t k = a.rp[i]; k < a.rp[i + 1]; ++k) {
+            const int32_t c = a.ci[k];
+            for (int64_t m = at.rp[c + 1] - 1; m >= at.rp[c]; --m) {
+              const int64_t j = at.ci[m];
+              if (j <= i) break;
+              if (skip[j]) continue;
+              if (hits[j]++ == 0) seen.push_back(j);
+            }
+          }
+          std::sort(seen.begin(), seen.end());
+          for (int64_t j : seen) {
+            const int64_t ov = hits[j];
+            hits[j] = 0;
+            bool ok = int_test ? (5 * ov * ov >= 4 * rc[i] * rc[j])
+                               : (double(ov) * ov >= eps * double(rc[i]) * double(rc[j]));
+            if (ok) Lst.push_back(j);
+          }
+        }
+        P.push_back((int64_t)Lst.size());
+      }
+    });
+  }
+  for (auto& x : th) x.join();
+  std::vector<char> taken(n, 0);
+  q.clear();
+  q.reserve(n);
+  gstart.assign(1, 0);
+  for (unsigned t = 0; t < nt; ++t) {
+    int64_t lo = std::min<int64_t>(n, t * chunk);
+    for (int64_t i = lo; i < lo + (int64_t)cptr[t].size() - 1; ++i) {
+      if (taken[i]) continue;
+      taken[i] = 1;
+      q.push_back(i);
+      int members = 1;
+      for (int64_t k = cptr[t][i - lo]; k < cptr[t][i - lo + 1] && members < max_block; ++k) {
+        int64_t j = clist[t][k];
+        if (taken[j]) continue;
+        taken[j] = 1;
+        q.push_back(j);
+        ++members;
+      }
+      gstart.push_back((int64_t)q.size());
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 3.3 ordering of the compressed (group) graph: nested dissection by
+// recursive level-structure bisection.  A pseudo-peripheral vertex of each
+// connected part is found by repeated breadth-first search; the middle
+// level (the first level holding half of the part) is the separator,
+// reduced to the vertices that touch the far side; both sides are ordered
+// first and the separator last.  Parts of at most 8 vertices keep their
+// input order.
+// ---------------------------------------------------------------------------
+struct Graph {
+  int64_t n = 0;
+  std::vector<int64_t> xadj;
+  std::vector<int32_t> adj;
+};
+
+void nd_order(const Graph& g, std::vector<int32_t>& order) {
+  const int64_t n = g.n;
+  order.clear();
+  order.reserve(n);
+  std::vector<int32_t> part(n, 0), level(n, 0), mark(n, 0);
+  int32_t next_part = 1, next_mark = 1;
+  struct Task {
+    std::vector<int32_t> verts;
+    bool emit;
+  };
+  std::vector<Task> stack;
+  {
+    Task t{std::vector<int32_t>(n), false};
+    std::iota(t.verts.begin(), t.verts.end(), 0);
+    stack.push_back(std::move(t));
+  }
+  // breadth-first search inside the part of src; records levels
+  auto bfs = [&](int32_t src, int32_t label, std::vector<int32_t>& seq) {
+    seq.clear();
+    seq.push_back(src);
+    level[src] = 0;
+    mark[src] = label;
+    const int32_t pt = part[src];
+    for (size_t hd = 0; hd < seq.size(); ++hd) {
+      const int32_t v = seq[hd];
+      for (int64_t k = g.xadj[v]; k < g.xadj[v + 1]; ++k) {
+        const int32_t w = g.adj[k];
+        if (part[w] != pt || mark[w] == label) continue;
+        mark[w] = label;
+        level[w] = level[v] + 1;
+        seq.push_back(w);
+      }
+    }
+  };
+  std::vector<int32_t> seq;
+  while (!stack.empty()) {
+    Task t = std::move(stack.back());
+    stack.pop_back();
+    if (t.emit || t.verts.size() <= 8) {
+      if (!t.emit) std::sort(t.verts.begin(), t.verts.end());
+      order.insert(order.end(), t.verts.begin(), t.verts.end());
+      continue;
+    }
+    const int32_t lab = next_part++;
+    for (int32_t v : t.verts) part[v] = lab;
+    // connected components of the part, ordered one after another
+    std::vector<std::vector<int32_t>> comps;
+    const int32_t cm = next_mark++;
+    for (int32_t v : t.verts) {
+      if (mark[v] == cm) continue;
+      bfs(v, cm, seq);
+      comps.push_back(seq);
+    }
+    if (comps.size() > 1) {
+      for (auto it = comps.rbegin(); it != comps.rend(); ++it)
+        stack.push_back(Task{std::move(*it), false});
+      continue;
+    }
+    // one connected part: pseudo-peripheral start vertex
+    const std::vector<int32_t> comp = std::move(comps[0]);
+    int32_t start = *std::min_element(comp.begin(), comp.end());
+    int32_t depth = -1;
+    for (int it = 0; it < 4; ++it) {
+      bfs(start, next_mark++, seq);
+      const int32_t far = seq.back();
+      if (level[far] <= depth) break;
+      depth = level[far];
+      start = far;
+    }
+    const int32_t lbl = next_mark++;
+    bfs(start, lbl, seq);
+    const int32_t maxlev = level[seq.back()];
+    if (maxlev < 2) {
+      std::vector<int32_t> v = comp;
+      std::sort(v.begin(), v.end());
+      order.insert(order.end(), v.begin(), v.end());
+      continue;
+    }
+    // separator level: the first whose cumulative size reaches half
+    std::vector<int64_t> cnt(maxlev + 1, 0);
+    for (int32_t v : seq) cnt[level[v]]++;
+    int64_t acc = 0;
+    int32_t mid = 1;
+    for (int32_t l = 0; l <= maxlev; ++l) {
+      acc += cnt[l];
+      if (2 * acc >= (int64_t)seq.size()) {
+        mid = std::min(std::max(l, 1), maxlev - 1);
+        break;
+      }
+    }
+    Task left{{}, false}, right{{}, false}, sep{{}, true};
+    for (int32_t v : seq) {
+      const int32_t l = level[v];
+      if (l < mid) {
+        left.verts.push_back(v);
+      } else if (l > mid) {
+        right.verts.push_back(v);
+      } else {
+        bool far_side = false;
+        for (int64_t k = g.xadj[v]; k < g.xadj[v + 1] && !far_side; ++k) {
+          const int32_t w = g.adj[k];
+          far_side = part[w] == lab && mark[w] == lbl && level[w] == mid + 1;
+        }
+        (far_side ? sep.verts : left.verts).push_back(v);
+      }
+    }
+    std::sort(sep.verts.begin(), sep.verts.end());
+    stack.push_back(std::move(sep));    // popped last: separator after both sides
+    stack.push_back(std::move(right));
+    stack.push_back(std::move(left));
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+bilu_status analyze_host(bilu_handle* h, int64_t n, const int64_t* rowptr,
+                         const int32_t* colind, const double* val) {
+  if (n <= 0 || !rowptr || !colind || !val) return fail(h, BILU_ERR_INVALID, "null CSR or n<=0");
+  if (n > INT32_MAX - 1) return fail(h, BILU_ERR_INVALID, "n exceeds int32 range");
+  if (rowptr[0] != 0) return fail(h, BILU_ERR_INVALID, "rowptr[0] != 0");
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return fail(h, BILU_ERR_INVALID, "rowptr not monotone");
+  const int64_t nnz = rowptr[n];
+  std::atomic<int> bad{0};
+  parallel_for(n, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi && !bad.load(std::memory_order_relaxed); ++i)
+      for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        if (colind[k] < 0 || colind[k] >= n) bad = 1;
+        else if (k > rowptr[i] && colind[k] <= colind[k - 1]) bad = 2;
+        else if (!std::isfinite(val[k])) bad = 3;
+      }
+  });
+  if (bad == 1) return fail(h, BILU_ERR_INVALID, "column index out of range");
+  if (bad == 2) return fail(h, BILU_ERR_INVALID, "column indices not strictly increasing");
+  if (bad == 3) return fail(h, BILU_ERR_INVALID, "non-finite value");
+
+  Csr a;
+  a.n = n;
+  a.rp.assign(rowptr, rowptr + n + 1);
+  a.ci.assign(colind, colind + nnz);
+  a.v.assign(val, val + nnz);
+  h->n = n;
+  h->nnz = nnz;
+  h->alpha = 0.0;
+  for (double x : a.v) h->alpha = std::max(h->alpha, std::fabs(x));
+
+  // optional caller pre-permutation
+  std::vector<int64_t> pre(n);
+  if (h->opt.pre_perm) {
+    std::vector<char> seen(n, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      int64_t p = h->opt.pre_perm[i];
+      if (p < 0 || p >= n || seen[p]) return fail(h, BILU_ERR_INVALID, "pre_perm is not a permutation");
+      seen[p] = 1;
+      pre[i] = p;
+    }
+  } else {
+    std::iota(pre.begin(), pre.end(), 0);
+  }
+  Csr a1 = h->opt.pre_perm ? permute(a, pre) : a;
+
+  // cosine groups
+  std::vector<int64_t> q, gs;
+  if (h->opt.use_cosine) {
+    Csr a1t = transpose(a1);
+    cosine(a1, a1t, h->opt.cos_eps, h->opt.max_block, q, gs);
+  } else {
+    q.resize(n);
+    std::iota(q.begin(), q.end(), 0);
+    gs.resize(n + 1);
+    std::iota(gs.begin(), gs.end(), 0);
+  }
+  const int64_t ng = (int64_t)gs.size() - 1;
+
+  // group order: natural, or nested dissection of the compressed graph
+  std::vector<int32_t> gorder(ng);
+  std::iota(gorder.begin(), gorder.end(), 0);
+  if (h->opt.ordering == BILU_ORDER_ND && ng > 8) {
+    std::vector<int32_t> gof(n);
+    for (int64_t g = 0; g < ng; ++g)
+      for (int64_t k = gs[g]; k < gs[g + 1]; ++k) gof[q[k]] = (int32_t)g;
+    // edges of B + B^T
+    std::vector<std::vector<int32_t>> nb(ng);
+    parallel_for(ng, [&](int64_t lo, int64_t hi) {
+      for (int64_t g = lo; g < hi; ++g) {
+        auto& v = nb[g];
+        for (int64_t k = gs[g]; k < gs[g + 1]; ++k) {
+          int64_t r = q[k];
+          for (int64_t m = a1.rp[r]; m < a1.rp[r + 1]; ++m) {
+            int32_t h2 = gof[a1.ci[m]];
+            if (h2 != g) v.push_back(h2);
+          }
+        }
+      }
+    });
+    Graph gr;
+    gr.n = ng;
+    {
+      std::vector<std::vector<int32_t>> sym(ng);
+      for (int64_t g = 0; g < ng; ++g)
+        for (int32_t h2 : nb[g]) {
+          sym[g].push_back(h2);
+          sym[h2].push_back((int32_t)g);
+        }
+      gr.xadj.assign(ng + 1, 0);
+      for (int64_t g = 0; g < ng; ++g) {
+        auto& v = sym[g];
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+        gr.xadj[g + 1] = gr.xadj[g] + (int64_t)v.size();
+      }
+      gr.adj.reserve(gr.xadj[ng]);
+      for (int64_t g = 0; g < ng; ++g) gr.adj.insert(gr.adj.end(), sym[g].begin(), sym[g].end());
+    }
+    nd_order(gr, gorder);
+    if ((int64_t)gorder.size() != ng) return fail(h, BILU_ERR_INTERNAL, "ordering lost vertices");
+  }
+  // expand: groups contiguous, members in their order
+  h->perm.resize(n);
+  h->group_starts.assign(1, 0);
+  int64_t at = 0;
+  for (int64_t gi = 0; gi < ng; ++gi) {
+    int64_t g = gorder[gi];
+    for (int64_t k = gs[g]; k < gs[g + 1]; ++k) h->perm[at++] = pre[q[k]];
+    h->group_starts.push_back(at);
+  }
+  Csr p = permute(a, h->perm);
+  Csr pt = transpose(p);
+  h->prp = std::move(p.rp);
+  h->pci = std::move(p.ci);
+  h->pv = std::move(p.v);
+  h->pcp = std::move(pt.rp);
+  h->pri = std::move(pt.ci);
+  h->pcv = std::move(pt.v);
+  return BILU_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 3.4: for every scalar k the estimated column pattern I~_k of L (rows
+// i > k with |a_ik| >= tau |a_kk|, plus rows i reached through an original
+// a_ij a_jk, j < k, with |a_ij a_jk| >= tau |a_jj a_kk|) and, symmetrically,
+// J~_k of U.  Blocks grow unit by unit (cosine groups) while the dense
+// block count f' = (r'+s'+l')*l' stays within 4/3 of the scalar count c' or
+// within c' + 4 l'; r', s' count the union rows/columns beyond the block.
+// ---------------------------------------------------------------------------
+int64_t ilu1t_partition(const bilu_handle* h, double tau, std::vector<int32_t>& bstart) {
+  const int64_t n = h->n;
+  const auto& gs = h->group_starts;
+  const int64_t nu = (int64_t)gs.size() - 1;
+  bstart.assign(1, 0);
+  if (!h->opt.use_ilu1t) {
+    for (int64_t u = 0; u < nu; ++u) bstart.push_back((int32_t)gs[u + 1]);
+    return nu;
+  }
+  const auto& rp = h->prp;
+  const auto& ci = h->pci;
+  const auto& rv = h->pv;
+  const auto& cp = h->pcp;
+  const auto& ri = h->pri;
+  const auto& cv = h->pcv;
+  std::vector<double> dg(n, 0.0);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] == i) dg[i] = rv[k];
+  // per-k sets, computed in parallel into per-range buffers
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  int64_t chunk = (n + nt - 1) / nt;
+  std::vector<std::vector<int32_t>> Ibuf(nt), Jbuf(nt);
+  std::vector<int64_t> Iptr(n + 1, 0), Jptr(n + 1, 0);
+  std::vector<int32_t> Icnt(n), Jcnt(n);
+  std::vector<std::thread> th;
+  for (unsigned t = 0; t < nt; ++t) {
+    th.emplace_back([&, t] {
+      int64_t lo = std::min<int64_t>(n, t * chunk), hi = std::min<int64_t>(n, lo + chunk);
+      std::vector<int32_t> stamp(n, -1);
+      auto& IB = Ibuf[t];
+      auto& JB = Jbuf[t];
+      for (int64_t k = lo; k < hi; ++k) {
+        const double akk = std::fabs(dg[k]);
+        size_t s0 = IB.size();
+        for (int64_t m = cp[k]; m < cp[k + 1]; ++m) {
+          int32_t i = ri[m];
+          if (i > k && std::fabs(cv[m]) >= tau * akk && stamp[i] != (int32_t)k) {
+            stamp[i] = (int32_t)k;
+            IB.push_back(i);
+          }
+        }
+        for (int64_t m = cp[k]; m < cp[k + 1]; ++m) {
+          int32_t j = ri[m];
+          if (j >= k) break;
+          const double ajk = cv[m];
+          const double thr = tau * std::fabs(dg[j] * dg[k]);
+          for (int64_t m2 = cp[j + 1] - 1; m2 >= cp[j]; --m2) {
+            int32_t i = ri[m2];
+            if (i <= k) break;
+            if (stamp[i] != (int32_t)k && std::fabs(cv[m2] * ajk) >= thr) {
+              stamp[i] = (int32_t)k;
+              IB.push_back(i);
+            }
+          }
+        }
+        Icnt[k] = (int32_t)(IB.size() - s0);
+        // row k of U, stamps shifted to keep them apart from the column pass
+        const int32_t sk = (int32_t)(k + n);
+        size_t t0 = JB.size();
+        for (int64_t m = rp[k]; m < rp[k + 1]; ++m) {
+          int32_t j = ci[m];
+          if (j > k && std::fabs(rv[m]) >= tau * akk && stamp[j] != sk) {
+            stamp[j] = sk;
+            JB.push_back(j);
+          }
+        }
+        for (int64_t m = rp[k]; m < rp[k + 1]; ++m) {
+          int32_t i = ci[m];
+          if (i >= k) break;
+          const double aki = rv[m];
+          const double thr = tau * std::fabs(dg[i] * dg[k]);
+          for (int64_t m2 = rp[i + 1] - 1; m2 >= rp[i]; --m2) {
+            int32_t j = ci[m2];
+            if (j <= k) break;
+            if (stamp[j] != sk && std::fabs(aki * rv[m2]) >= thr) {
+              stamp[j] = sk;
+              JB.push_back(j);
+            }
+          }
+        }
+        Jcnt[k] = (int32_t)(JB.size() - t0);
+      }
+    });
+  }
+  for (auto& x : th) x.join();
+  // flatten offsets (per-thread buffers are in k order)
+  for (int64_t k = 0; k < n; ++k) {
+    Iptr[k + 1] = Iptr[k] + Icnt[k];
+    Jptr[k + 1] = Jptr[k] + Jcnt[k];
+  }
+  std::vector<int32_t> Iall(Iptr[n]), Jall(Jptr[n]);
+  {
+    int64_t oi = 0, oj = 0;
+    for (unsigned t = 0; t < nt; ++t) {
+      std::copy(Ibuf[t].begin(), Ibuf[t].end(), Iall.begin() + oi);
+      std::copy(Jbuf[t].begin(), Jbuf[t].end(), Jall.begin() + oj);
+      oi += (int64_t)Ibuf[t].size();
+      oj += (int64_t)Jbuf[t].size();
+    }
+  }
+  // sequential growth with marker arrays: rows/cols of the running block
+  std::vector<int32_t> rmark(n, -1), cmark(n, -1);
+  std::vector<int32_t> rows, cols;
+  const int maxb = h->opt.max_block;
+  int64_t u = 0;
+  int32_t blk = 0;
+  auto count_beyond = [](const std::vector<int32_t>& v, int64_t last) {
+    int64_t c = 0;
+    for (int32_t x : v) c += x > last;
+    return c;
+  };
+  while (u < nu) {
+    rows.clear();
+    cols.clear();
+    const int64_t s0 = gs[u];
+    int64_t e = gs[u + 1];
+    int64_t scal = 0;
+    for (int64_t k = s0; k < e; ++k) {
+      for (int64_t m = Iptr[k]; m < Iptr[k + 1]; ++m)
+        if (rmark[Iall[m]] != blk) {
+          rmark[Iall[m]] = blk;
+          rows.push_back(Iall[m]);
+        }
+      for (int64_t m = Jptr[k]; m < Jptr[k + 1]; ++m)
+        if (cmark[Jall[m]] != blk) {
+          cmark[Jall[m]] = blk;
+          cols.push_back(Jall[m]);
+        }
+      scal += Icnt[k] + Jcnt[k] + 1;
+    }
+    ++u;
+    while (u < nu) {
+      const int64_t e2 = gs[u + 1];
+      const int64_t w2 = e2 - s0;
+      if (w2 > maxb) break;
+      // tentative: count the union beyond the new last index without
+      // committing the new unit's entries
+      int64_t r2 = count_beyond(rows, e2 - 1), c2cnt = count_beyond(cols, e2 - 1);
+      int64_t sc2 = scal;
+      std::vector<int32_t> addr, addc;
+      for (int64_t k = gs[u]; k < e2; ++k) {
+        for (int64_t m = Iptr[k]; m < Iptr[k + 1]; ++m) {
+          int32_t i = Iall[m];
+          if (rmark[i] != blk && rmark[i] != -2 - blk) {
+            rmark[i] = -2 - blk;  // tentative
+            addr.push_back(i);
+          }
+        }
+        for (int64_t m = Jptr[k]; m < Jptr[k + 1]; ++m) {
+          int32_t j = Jall[m];
+          if (cmark[j] != blk && cmark[j] != -2 - blk) {
+            cmark[j] = -2 - blk;
+            addc.push_back(j);
+          }
+        }
+        sc2 += Icnt[k] + Jcnt[k] + 1;
+      }
+      r2 += count_beyond(addr, e2 - 1);
+      c2cnt += count_beyond(addc, e2 - 1);
+      const int64_t f2 = (r2 + c2cnt + w2) * w2;
+      const bool grow = 3 * f2 <= 4 * sc2 || f2 <= sc2 + 4 * w2;
+      for (int32_t i : addr) rmark[i] = grow ? blk : -1;
+      for (int32_t j : addc) cmark[j] = grow ? blk : -1;
+      if (!grow) break;
+      rows.insert(rows.end(), addr.begin(), addr.end());
+      cols.insert(cols.end(), addc.begin(), addc.end());
+      scal = sc2;
+      e = e2;
+      ++u;
+    }
+    bstart.push_back((int32_t)e);
+    ++blk;
+  }
+  return (int64_t)bstart.size() - 1;
+}
+
+// ---------------------------------------------------------------------------
+// Block elimination tree of the symmetrized block graph (Liu's algorithm
+// with path compression).  Exact block LU only couples a block to its
+// descendants, and the incomplete factor's pattern lies inside the exact
+// one, so processing blocks by tree height is a valid schedule.
+// ---------------------------------------------------------------------------
+void block_etree_levels(const bilu_handle* h, const std::vector<int32_t>& bstart,
+                        std::vector<int32_t>& sched, std::vector<int32_t>& sched_ptr) {
+  const int64_t n = h->n;
+  const int32_t nb = (int32_t)bstart.size() - 1;
+  std::vector<int32_t> bof(n);
+  for (int32_t b = 0; b < nb; ++b)
+    for (int32_t i = bstart[b]; i < bstart[b + 1]; ++i) bof[i] = b;
+  std::vector<int32_t> parent(nb, -1), anc(nb, -1);
+  std::vector<int32_t> nbrs;
+  for (int32_t K = 0; K < nb; ++K) {
+    nbrs.clear();
+    for (int32_t i = bstart[K]; i < bstart[K + 1]; ++i) {
+      for (int64_t m = h->prp[i]; m < h->prp[i + 1]; ++m) {
+        int32_t J = bof[h->pci[m]];
+        if (J < K) nbrs.push_back(J);
+      }
+      for (int64_t m = h->pcp[i]; m < h->pcp[i + 1]; ++m) {
+        int32_t J = bof[h->pri[m]];
+        if (J < K) nbrs.push_back(J);
+      }
+    }
+    for (int32_t J : nbrs) {
+      int32_t r = J;
+      while (anc[r] != -1 && anc[r] != K) {
+        int32_t nx = anc[r];
+        anc[r] = K;
+        r = nx;
+      }
+      if (anc[r] == -1) {
+        anc[r] = K;
+        parent[r] = K;
+      }
+    }
+  }
+  std::vector<int32_t> height(nb, 0);
+  int32_t hmax = 0;
+  for (int32_t K = 0; K < nb; ++K) {
+    if (parent[K] >= 0) height[parent[K]] = std::max(height[parent[K]], height[K] + 1);
+    hmax = std::max(hmax, height[K]);
+  }
+  sched_ptr.assign(hmax + 2, 0);
+  for (int32_t K = 0; K < nb; ++K) sched_ptr[height[K] + 1]++;
+  std::partial_sum(sched_ptr.begin(), sched_ptr.end(), sched_ptr.begin());
+  sched.resize(nb);
+  std::vector<int32_t> fill(sched_ptr.begin(), sched_ptr.end() - 1);
+  for (int32_t K = 0; K < nb; ++K) sched[fill[height[K]]++] = K;
+}
+
+}  // namespace bilu

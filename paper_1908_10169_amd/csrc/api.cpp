@@ -1,0 +1,383 @@
+// C ABI of the BILU library (declared in include/bilu.h).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+
+#include "internal.h"
+
+namespace bilu {
+
+bilu_status fail(bilu_handle* h, bilu_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+bilu_status hip_check(bilu_handle* h, hipError_t e, const char* what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  if (e == hipErrorOutOfMemory) return fail(h, BILU_ERR_NO_MEMORY, msg);
+  return fail(h, BILU_ERR_DEVICE, msg);
+}
+
+}  // namespace bilu
+
+using namespace bilu;
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                                         \
+  }                                                                       \
+  catch (const std::bad_alloc&) {                                         \
+    return fail(h, BILU_ERR_NO_MEMORY, "host allocation failed");        \
+  }                                                                       \
+  catch (const std::exception& ex) {                                      \
+    return fail(h, BILU_ERR_INTERNAL, ex.what());                        \
+  }                                                                       \
+  catch (...) {                                                           \
+    return fail(h, BILU_ERR_INTERNAL, "unknown exception");              \
+  }
+
+extern "C" {
+
+void bilu_default_options(bilu_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->use_cosine = 1;
+  o->use_ilu1t = 1;
+  o->use_aggregation = 1;
+  o->max_block = 128;
+  o->cos_eps = 0.8;
+  o->ordering = BILU_ORDER_ND;
+  o->pre_perm = nullptr;
+  o->drop_norm = BILU_NORM_INF;
+  o->perturb_tau = 1e-2;
+  o->perturb_rho = 1e-1;
+  o->pivot_eps = 1e-12;
+  o->beta_one = 0;
+  o->update_precision = BILU_PREC_F64;
+  o->heap_bytes = 0;
+}
+
+bilu_status bilu_create(bilu_handle** out, const bilu_options* opt, void* stream) {
+  if (!out) return BILU_ERR_INVALID;
+  *out = nullptr;
+  bilu_handle* h = nullptr;
+  try {
+    h = new bilu_handle();
+  } catch (...) {
+    return BILU_ERR_NO_MEMORY;
+  }
+  if (opt)
+    h->opt = *opt;
+  else
+    bilu_default_options(&h->opt);
+  if (h->opt.max_block < 1 || h->opt.max_block > kMaxWidth || !(h->opt.cos_eps >= 0.0) ||
+      h->opt.cos_eps > 1.0 || h->opt.ordering < 0 || h->opt.ordering > 1 ||
+      h->opt.update_precision < 0 || h->opt.update_precision > 2 || h->opt.drop_norm < 0 ||
+      h->opt.drop_norm > 1) {
+    delete h;
+    return BILU_ERR_INVALID;
+  }
+  h->stream = reinterpret_cast<hipStream_t>(stream);
+  *out = h;
+  return BILU_OK;
+}
+
+void bilu_destroy(bilu_handle* h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+}
+
+bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr, const int32_t* colind,
+                         const double* val) {
+  if (!h) return BILU_ERR_INVALID;
+  GUARD_BEGIN
+  auto t0 = std::chrono::steady_clock::now();
+  h->state = 0;
+  bilu_status s = analyze_host(h, n, rowptr, colind, val);
+  if (s != BILU_OK) return s;
+  const int64_t nnz = h->nnz;
+  hipStream_t st = h->stream;
+#define CK(x)                                          \
+  do {                                                 \
+    hipError_t e_ = (x);                               \
+    if (e_ != hipSuccess) return hip_check(h, e_, #x); \
+  } while (0)
+  CK(h->d_rp.alloc(n + 1));
+  CK(h->d_ci.alloc(nnz));
+  CK(h->d_rv.alloc(nnz));
+  CK(h->d_cp.alloc(n + 1));
+  CK(h->d_ri.alloc(nnz));
+  CK(h->d_cv.alloc(nnz));
+  CK(h->d_perm.alloc(n));
+  std::vector<int32_t> p32(h->perm.begin(), h->perm.end());
+  CK(hipMemcpyAsync(h->d_rp.p, h->prp.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(h->d_ci.p, h->pci.data(), nnz * 4, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(h->d_rv.p, h->pv.data(), nnz * 8, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(h->d_cp.p, h->pcp.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(h->d_ri.p, h->pri.data(), nnz * 4, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(h->d_cv.p, h->pcv.data(), nnz * 8, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(h->d_perm.p, p32.data(), n * 4, hipMemcpyHostToDevice, st));
+  CK(hipStreamSynchronize(st));
+#undef CK
+  h->stats = bilu_stats{};
+  h->stats.n = n;
+  h->stats.nnz_a = nnz;
+  h->stats.ngroups = (int64_t)h->group_starts.size() - 1;
+  h->stats.t_analyze = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  h->state = 1;
+  return BILU_OK;
+  GUARD_END
+}
+
+bilu_status bilu_factor(bilu_handle* h, double tau) {
+  if (!h) return BILU_ERR_INVALID;
+  if (h->state < 1) return fail(h, BILU_ERR_STATE, "bilu_factor before bilu_analyze");
+  if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(h, BILU_ERR_INVALID, "tau must be >= 0");
+  GUARD_BEGIN
+  auto t0 = std::chrono::steady_clock::now();
+  h->state = 1;
+  h->d_apply_sched.release();
+  bilu_status s = factor_device(h, tau);
+  if (s != BILU_OK) return s;
+  h->nb = h->stats.nblocks_initial;
+  h->bstart = h->bstart0;
+  auto t1 = std::chrono::steady_clock::now();
+  if (h->opt.use_aggregation) {
+    s = aggregate_device(h);
+    if (s != BILU_OK) return s;
+  }
+  h->stats.t_aggregate =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
+  s = build_apply_plan(h);
+  if (s != BILU_OK) return s;
+  // block statistics and stored entries of the final factor
+  {
+    const int64_t nb = h->nb;
+    std::vector<int32_t> nr(nb), nc(nb);
+    if (hipMemcpy(nr.data(), h->d_nr.p, nb * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(nc.data(), h->d_nc.p, nb * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(h, BILU_ERR_DEVICE, "stats copy");
+    double sum = 0, sum2 = 0;
+    int64_t mx = 0, nl = 0, nw = 0, nd = 0, ir = 0, ic = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      int64_t q = h->bstart[b + 1] - h->bstart[b];
+      sum += q;
+      sum2 += double(q) * q;
+      mx = std::max(mx, q);
+      nl += nr[b] * q;
+      nw += nc[b] * q;
+      nd += q * q;
+      ir += nr[b];
+      ic += nc[b];
+    }
+    h->stats.nblocks = nb;
+    h->stats.max_width = mx;
+    h->stats.avg_width = sum / nb;
+    h->stats.std_width = std::sqrt(std::max(0.0, sum2 / nb - (sum / nb) * (sum / nb)));
+    h->stats.nnz_l = nl;
+    h->stats.nnz_w = nw;
+    h->stats.nnz_d = nd;
+    // one apply reads every stored value and row/column index once and
+    // streams x, t (written, then read) and y: 8 B values, 4 B indices
+    h->stats.bytes_apply = 8.0 * double(nl + nw + nd) + 4.0 * double(ir + ic) + 32.0 * h->n;
+  }
+  h->stats.t_factor = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  h->state = 2;
+  return h->stats.perturbed_blocks > 0 ? BILU_WARN_PERTURBED : BILU_OK;
+  GUARD_END
+}
+
+bilu_status bilu_apply(bilu_handle* h, const double* x, double* y) {
+  if (!h || !x || !y || x == y) return fail(h, BILU_ERR_INVALID, "bilu_apply: bad pointers");
+  if (h->state < 2) return fail(h, BILU_ERR_STATE, "bilu_apply before bilu_factor");
+  GUARD_BEGIN
+  const int64_t n = h->n;
+  if (h->w_cols < 3) {
+    if (h->w_vec.alloc((size_t)3 * n) != hipSuccess) return fail(h, BILU_ERR_NO_MEMORY, "workspace");
+    h->w_cols = 3;
+  }
+  double* xp = h->w_vec.p;
+  double* yp = xp + n;
+  double* tp = yp + n;
+  launch_gather(h->stream, n, h->d_perm.p, x, xp);
+  bilu_status s = apply_permuted(h, xp, yp, tp);
+  if (s != BILU_OK) return s;
+  launch_scatter(h->stream, n, h->d_perm.p, yp, y);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_check(h, e, "bilu_apply");
+  return BILU_OK;
+  GUARD_END
+}
+
+bilu_status bilu_spmv(bilu_handle* h, const double* x, double* y) {
+  if (!h || !x || !y || x == y) return fail(h, BILU_ERR_INVALID, "bilu_spmv: bad pointers");
+  if (h->state < 1) return fail(h, BILU_ERR_STATE, "bilu_spmv before bilu_analyze");
+  GUARD_BEGIN
+  const int64_t n = h->n;
+  if (h->w_cols < 3) {
+    if (h->w_vec.alloc((size_t)3 * n) != hipSuccess) return fail(h, BILU_ERR_NO_MEMORY, "workspace");
+    h->w_cols = 3;
+  }
+  double* xp = h->w_vec.p;
+  double* yp = xp + n;
+  launch_gather(h->stream, n, h->d_perm.p, x, xp);
+  spmv_permuted(h, xp, yp);
+  launch_scatter(h->stream, n, h->d_perm.p, yp, y);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_check(h, e, "bilu_spmv");
+  return BILU_OK;
+  GUARD_END
+}
+
+bilu_status bilu_fgmres_solve(bilu_handle* h, const double* b, double* x, int restart, double rtol,
+                              int maxit, bilu_solve_info* info) {
+  if (!h || !b || !x || b == x) return fail(h, BILU_ERR_INVALID, "bilu_fgmres_solve: bad pointers");
+  if (h->state < 2) return fail(h, BILU_ERR_STATE, "bilu_fgmres_solve before bilu_factor");
+  GUARD_BEGIN
+  return fgmres(h, b, x, restart, rtol, maxit, info);
+  GUARD_END
+}
+
+bilu_status bilu_preprocess(const bilu_options* opt, int64_t n, const int64_t* rowptr,
+                            const int32_t* colind, const double* val, double tau, int64_t* perm,
+                            int64_t* group_starts, int64_t* ngroups, int64_t* block_starts,
+                            int64_t* nblocks) {
+  if (!perm || !group_starts || !ngroups || !block_starts || !nblocks) return BILU_ERR_INVALID;
+  if (!(tau >= 0.0) || !std::isfinite(tau)) return BILU_ERR_INVALID;
+  bilu_handle tmp;
+  bilu_handle* h = &tmp;
+  if (opt)
+    h->opt = *opt;
+  else
+    bilu_default_options(&h->opt);
+  if (h->opt.max_block < 1 || h->opt.max_block > kMaxWidth) return BILU_ERR_INVALID;
+  GUARD_BEGIN
+  bilu_status s = analyze_host(h, n, rowptr, colind, val);
+  if (s != BILU_OK) return s;
+  std::copy(h->perm.begin(), h->perm.end(), perm);
+  std::copy(h->group_starts.begin(), h->group_starts.end(), group_starts);
+  *ngroups = (int64_t)h->group_starts.size() - 1;
+  std::vector<int32_t> bs;
+  *nblocks = ilu1t_partition(h, tau, bs);
+  std::copy(bs.begin(), bs.end(), block_starts);
+  return BILU_OK;
+  GUARD_END
+}
+
+bilu_status bilu_get_stats(const bilu_handle* h, bilu_stats* st) {
+  if (!h || !st) return BILU_ERR_INVALID;
+  *st = h->stats;
+  return BILU_OK;
+}
+
+bilu_status bilu_export_factors(const bilu_handle* hc, bilu_factors_host* out) {
+  bilu_handle* h = const_cast<bilu_handle*>(hc);
+  if (!h || !out) return BILU_ERR_INVALID;
+  if (h->state < 2) return fail(h, BILU_ERR_STATE, "export before factor");
+  GUARD_BEGIN
+  std::memset(out, 0, sizeof(*out));
+  const int64_t n = h->n, nb = h->nb;
+  std::vector<int32_t> nr(nb), nc(nb);
+  std::vector<int64_t> roff(nb), coff(nb), loff(nb), woff(nb);
+  if (hipMemcpy(nr.data(), h->d_nr.p, nb * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(nc.data(), h->d_nc.p, nb * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(roff.data(), h->d_roff.p, nb * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(coff.data(), h->d_coff.p, nb * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(loff.data(), h->d_loff.p, nb * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(woff.data(), h->d_woff.p, nb * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(h, BILU_ERR_DEVICE, "export copy");
+  int64_t tr = 0, tc = 0, tl = 0, tw = 0, td = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    int64_t q = h->bstart[b + 1] - h->bstart[b];
+    tr += nr[b];
+    tc += nc[b];
+    tl += nr[b] * q;
+    tw += nc[b] * q;
+    td += q * q;
+  }
+  std::vector<int32_t> idx(h->d_idx_heap.n);
+  std::vector<double> val;
+  // copy only what is referenced: gather per block from device heaps
+  out->n = n;
+  out->nblocks = nb;
+  out->nblocks_initial = (int64_t)h->bstart0.size() - 1;
+  out->ngroups = (int64_t)h->group_starts.size() - 1;
+  out->perm = new int64_t[n];
+  out->starts = new int64_t[nb + 1];
+  out->starts_initial = new int64_t[h->bstart0.size()];
+  out->group_starts = new int64_t[h->group_starts.size()];
+  out->r_ptr = new int64_t[nb + 1];
+  out->c_ptr = new int64_t[nb + 1];
+  out->r_idx = new int32_t[std::max<int64_t>(1, tr)];
+  out->c_idx = new int32_t[std::max<int64_t>(1, tc)];
+  out->l_val = new double[std::max<int64_t>(1, tl)];
+  out->w_val = new double[std::max<int64_t>(1, tw)];
+  out->d_val = new double[std::max<int64_t>(1, td)];
+  std::copy(h->perm.begin(), h->perm.end(), out->perm);
+  for (int64_t b = 0; b <= nb; ++b) out->starts[b] = h->bstart[b];
+  for (size_t b = 0; b < h->bstart0.size(); ++b) out->starts_initial[b] = h->bstart0[b];
+  std::copy(h->group_starts.begin(), h->group_starts.end(), out->group_starts);
+  // whole heaps are copied once (simple; export is a checking path)
+  std::vector<double> vheap(h->d_val_heap.n);
+  if (hipMemcpy(idx.data(), h->d_idx_heap.p, idx.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(vheap.data(), h->d_val_heap.p, vheap.size() * 8, hipMemcpyDeviceToHost) !=
+          hipSuccess ||
+      hipMemcpy(out->d_val, h->d_dval.p, td * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+    bilu_free_factors(out);
+    return fail(h, BILU_ERR_DEVICE, "export copy");
+  }
+  int64_t ar = 0, ac = 0, al = 0, aw = 0;
+  out->r_ptr[0] = out->c_ptr[0] = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    int64_t q = h->bstart[b + 1] - h->bstart[b];
+    std::copy(idx.begin() + roff[b], idx.begin() + roff[b] + nr[b], out->r_idx + ar);
+    std::copy(idx.begin() + coff[b], idx.begin() + coff[b] + nc[b], out->c_idx + ac);
+    std::copy(vheap.begin() + loff[b], vheap.begin() + loff[b] + nr[b] * q, out->l_val + al);
+    std::copy(vheap.begin() + woff[b], vheap.begin() + woff[b] + nc[b] * q, out->w_val + aw);
+    ar += nr[b];
+    ac += nc[b];
+    al += nr[b] * q;
+    aw += nc[b] * q;
+    out->r_ptr[b + 1] = ar;
+    out->c_ptr[b + 1] = ac;
+  }
+  return BILU_OK;
+  GUARD_END
+}
+
+void bilu_free_factors(bilu_factors_host* f) {
+  if (!f) return;
+  delete[] f->perm;
+  delete[] f->starts;
+  delete[] f->starts_initial;
+  delete[] f->group_starts;
+  delete[] f->r_ptr;
+  delete[] f->c_ptr;
+  delete[] f->r_idx;
+  delete[] f->c_idx;
+  delete[] f->l_val;
+  delete[] f->w_val;
+  delete[] f->d_val;
+  std::memset(f, 0, sizeof(*f));
+}
+
+const char* bilu_status_string(bilu_status s) {
+  switch (s) {
+    case BILU_OK: return "BILU_OK";
+    case BILU_WARN_PERTURBED: return "BILU_WARN_PERTURBED";
+    case BILU_WARN_NOT_CONVERGED: return "BILU_WARN_NOT_CONVERGED";
+    case BILU_ERR_INVALID: return "BILU_ERR_INVALID";
+    case BILU_ERR_NO_MEMORY: return "BILU_ERR_NO_MEMORY";
+    case BILU_ERR_STATE: return "BILU_ERR_STATE";
+    case BILU_ERR_SINGULAR: return "BILU_ERR_SINGULAR";
+    case BILU_ERR_DEVICE: return "BILU_ERR_DEVICE";
+    case BILU_ERR_INTERNAL: return "BILU_ERR_INTERNAL";
+  }
+  return "unknown status";
+}
+
+const char* bilu_last_error(const bilu_handle* h) { return h ? h->err.c_str() : "null handle"; }
+
+}  // extern "C"

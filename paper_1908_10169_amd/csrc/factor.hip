@@ -1,0 +1,779 @@
+// Numeric block Crout sweep (Sec. 2.2) on the GPU.
+//
+// One workgroup computes one block column K of L and block row K of U:
+//   1. the predecessors J whose stored block row has columns inside K (for
+//      the column panel) or whose block column has rows inside K (for the
+//      row panel) are read from K's predecessor lists, which every finished
+//      J appends itself to;
+//   2. candidate rows/columns (structural entries of A plus the stored
+//      rows/columns of those J) are deduplicated in an LDS hash and sorted;
+//   3. the panels are gathered from A and updated C -= L_J W_J for every J
+//      in increasing order (fixed order: results are run-to-run identical);
+//   4. the pivot block S_K is perturbed if needed (Sec. 3.6) and inverted by
+//      Gauss-Jordan elimination with partial pivoting (lowest row on ties);
+//   5. rows L(i,K) = C(i,K) D_K and columns D_K R(K,j) are dropped when
+//      their norm is <= tau, the kept ones compacted into the factor heap
+//      (L scaled, W = R unscaled), and K is appended to the predecessor lists
+//      of the blocks it will update.
+// Blocks are processed level by level along the block elimination tree;
+// blocks of one level are independent.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+
+#include "internal.h"
+#include "wg.h"
+
+namespace bilu {
+namespace {
+
+__device__ __forceinline__ void raise_error(const FactorArgs& a, int code, int blk) {
+  if (atomicCAS(a.err, 0, code) == 0) atomicExch(a.err_block, blk);
+}
+
+__device__ __forceinline__ unsigned hash_slot(int key) {
+  return (unsigned(key) * 2654435761u) & (kHashSlots - 1);
+}
+
+// Insert key into the LDS hash; counts new keys in *count.  Returns false
+// when the table is full.
+__device__ __forceinline__ bool hash_insert(int* table, int key, int* count) {
+  unsigned h = hash_slot(key);
+  for (int probe = 0; probe < kHashSlots; ++probe) {
+    int old = atomicCAS(&table[h], -1, key);
+    if (old == -1) {
+      atomicAdd(count, 1);
+      return true;
+    }
+    if (old == key) return true;
+    h = (h + 1) & (kHashSlots - 1);
+  }
+  return false;
+}
+
+// Read the predecessor list of a block (inline part + overflow chain) into
+// LDS and sort it.  Returns the count, or -1 on overflow.
+__device__ int load_preds(const FactorArgs& a, const int32_t* cnt_arr, const int32_t* list,
+                          const int32_t* ovf_head, int K, int* s_pred, int* s_misc) {
+  const int cnt = cnt_arr[K];
+  if (cnt > kPredCap) return -1;
+  const int inl = min(cnt, kListCap);
+  for (int t = threadIdx.x; t < inl; t += blockDim.x) s_pred[t] = list[(int64_t)K * kListCap + t];
+  if (threadIdx.x == 0) {
+    int node = ovf_head[K];
+    int at = kListCap;
+    while (node >= 0 && at < cnt) {
+      s_pred[at++] = a.ovf_j[node];
+      node = a.ovf_next[node];
+    }
+    s_misc[0] = (cnt > kListCap && at != cnt) ? 1 : 0;
+  }
+  __syncthreads();
+  if (s_misc[0]) return -1;
+  __syncthreads();
+  wg_bitonic_sort(s_pred, cnt);
+  return cnt;
+}
+
+// Append block K to the predecessor list of block B.
+__device__ __forceinline__ void push_pred(const FactorArgs& a, int32_t* cnt_arr, int32_t* list,
+                                          int32_t* ovf_head, int B, int K) {
+  int pos = atomicAdd(&cnt_arr[B], 1);
+  if (pos < kListCap) {
+    list[(int64_t)B * kListCap + pos] = K;
+    return;
+  }
+  int node = atomicAdd(a.ovf_top, 1);
+  if (node >= a.ovf_cap) {
+    raise_error(a, kDevListOverflow, K);
+    return;
+  }
+  a.ovf_j[node] = K;
+  a.ovf_next[node] = atomicExch(&ovf_head[B], node);
+}
+
+__device__ __forceinline__ double dot_strided(const double* x, const double* y, int p) {
+  double acc = 0.0;
+  for (int t = 0; t < p; ++t) acc = fma(x[t], y[t], acc);
+  return acc;
+}
+
+// Sec. 3.6 perturbation of column j of the q x q row-major matrix m: the
+// largest-magnitude entry (lowest row on ties), or the diagonal when
+// 2|m_jj| >= |m_kj|, becomes m_kj (1 + rho beta) + sign(m_kj) tau alpha.
+__device__ void perturb_column(double* m, int q, int j, const FactorArgs& a) {
+  int k = 0;
+  double dmax = -1.0;
+  for (int i = 0; i < q; ++i) {
+    double v = fabs(m[i * q + j]);
+    if (v > dmax) {
+      dmax = v;
+      k = i;
+    }
+  }
+  if (2.0 * fabs(m[j * q + j]) >= fabs(m[k * q + j])) k = j;
+  const double beta = a.beta_one ? 1.0 : dmax;
+  const double d = m[k * q + j];
+  m[k * q + j] = d * (1.0 + a.pert_rho * beta) + (d < 0.0 ? -1.0 : 1.0) * a.pert_tau * a.alpha;
+}
+
+__device__ void perturb_row(double* m, int q, int i, const FactorArgs& a) {
+  int k = 0;
+  double dmax = -1.0;
+  for (int j = 0; j < q; ++j) {
+    double v = fabs(m[i * q + j]);
+    if (v > dmax) {
+      dmax = v;
+      k = j;
+    }
+  }
+  if (2.0 * fabs(m[i * q + i]) >= fabs(m[i * q + k])) k = i;
+  const double beta = a.beta_one ? 1.0 : dmax;
+  const double d = m[i * q + k];
+  m[i * q + k] = d * (1.0 + a.pert_rho * beta) + (d < 0.0 ? -1.0 : 1.0) * a.pert_tau * a.alpha;
+}
+
+// In-place Gauss-Jordan inverse of the q x q row-major LDS matrix w with
+// partial pivoting.  Returns false (uniformly) when a pivot is not above
+// eps * smax.  s_f: q doubles, s_ip: q ints, s_misc: >= 4 ints.
+__device__ bool gauss_jordan_inverse(double* w, int q, double smax, double eps, double* s_f,
+                                     int* s_ip, int* s_misc) {
+  const int tid = threadIdx.x;
+  for (int k = 0; k < q; ++k) {
+    // pivot search by wave 0: max |w_ik|, i >= k, lowest i on ties
+    if (tid < 64) {
+      double bv = -1.0;
+      int bi = q;
+      for (int i = k + tid; i < q; i += 64) {
+        double v = fabs(w[i * q + k]);
+        if (v > bv || (v == bv && i < bi)) {
+          bv = v;
+          bi = i;
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        double ov = __shfl_xor(bv, o, 64);
+        int oi = __shfl_xor(bi, o, 64);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      if (tid == 0) {
+        s_misc[0] = bi;
+        double u = (bi < q) ? w[bi * q + k] : 0.0;
+        s_misc[1] = (bi < q && u != 0.0 && fabs(u) > eps * smax && isfinite(u)) ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    const int p = s_misc[0];
+    if (!s_misc[1]) return false;
+    if (p != k)
+      for (int j = tid; j < q; j += blockDim.x) {
+        double t = w[k * q + j];
+        w[k * q + j] = w[p * q + j];
+        w[p * q + j] = t;
+      }
+    if (tid == 0) s_ip[k] = p;
+    __syncthreads();
+    const double d = w[k * q + k];
+    __syncthreads();
+    for (int j = tid; j < q; j += blockDim.x) w[k * q + j] = (j == k ? 1.0 : w[k * q + j]) / d;
+    for (int i = tid; i < q; i += blockDim.x) s_f[i] = w[i * q + k];
+    __syncthreads();
+    for (int e = tid; e < q * q; e += blockDim.x) {
+      const int i = e / q, j = e - i * q;
+      if (i == k) continue;
+      const double base = (j == k) ? 0.0 : w[e];
+      w[e] = fma(-s_f[i], w[k * q + j], base);
+    }
+    __syncthreads();
+  }
+  for (int k = q - 1; k >= 0; --k) {
+    const int p = s_ip[k];
+    if (p != k)
+      for (int i = tid; i < q; i += blockDim.x) {
+        double t = w[i * q + k];
+        w[i * q + k] = w[i * q + p];
+        w[i * q + p] = t;
+      }
+    __syncthreads();
+  }
+  return true;
+}
+
+struct Lds {
+  int hash[kHashSlots];     // candidate dedup; reused as keep flags
+  int cand[kCandCap];       // sorted candidate rows
+  int candc[kCandCap];      // sorted candidate columns
+  int pred[kPredCap];
+  int misc[32];
+  int scan[20];
+  int ip[kMaxWidth];
+  double f[kMaxWidth];
+  double smax;
+  long long off[2];
+};
+
+// Build the sorted set of candidate indices into out[] from the structural
+// entries of A (lists given by ptr/idx over [lo, hi], keeping idx > thresh)
+// plus the stored index lists of the predecessors (keeping those > thresh2).
+// Returns the count or -1 on overflow.
+__device__ int build_candidates(Lds& s, int* out, const int64_t* ptr, const int32_t* idx, int lo,
+                                int hi, int min_keep, int npred, const FactorArgs& a, bool rows,
+                                int diag_first, int diag_last) {
+  for (int t = threadIdx.x; t < kHashSlots; t += blockDim.x) s.hash[t] = -1;
+  if (threadIdx.x == 0) {
+    s.misc[4] = 0;  // unique count
+    s.misc[5] = 0;  // overflow flag
+  }
+  __syncthreads();
+  // diagonal indices (column panel only)
+  for (int i = diag_first + (int)threadIdx.x; i <= diag_last; i += blockDim.x)
+    if (!hash_insert(s.hash, i, &s.misc[4])) s.misc[5] = 1;
+  // structural entries of A
+  for (int c = lo; c <= hi; ++c) {
+    const int64_t b = ptr[c], e = ptr[c + 1];
+    for (int64_t m = b + threadIdx.x; m < e; m += blockDim.x) {
+      int r = idx[m];
+      if (r >= min_keep)
+        if (!hash_insert(s.hash, r, &s.misc[4])) s.misc[5] = 1;
+    }
+  }
+  // stored rows (or columns) of the predecessors: one wave per predecessor
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int pi = wid; pi < npred; pi += nw) {
+    const int J = s.pred[pi];
+    const int cnt = rows ? a.nr[J] : a.nc[J];
+    const int32_t* lst = a.idx_heap + (rows ? a.roff[J] : a.coff[J]);
+    for (int t = lane; t < cnt; t += 64) {
+      int r = lst[t];
+      if (r >= min_keep)
+        if (!hash_insert(s.hash, r, &s.misc[4])) s.misc[5] = 1;
+    }
+  }
+  __syncthreads();
+  const int m = s.misc[4];
+  if (s.misc[5] || m > kCandCap) return -1;
+  if (threadIdx.x == 0) s.misc[6] = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < kHashSlots; t += blockDim.x) {
+    int k = s.hash[t];
+    if (k >= 0) out[atomicAdd(&s.misc[6], 1)] = k;
+  }
+  __syncthreads();
+  wg_bitonic_sort(out, m);
+  return m;
+}
+
+__device__ void factor_block(const FactorArgs& a, int K, int slot, Lds& s, double* s_dyn) {
+  const int tid = threadIdx.x;
+  const int f = a.bstart[K], l = a.bstart[K + 1] - 1, q = l - f + 1;
+  if (q > kMaxWidth) {
+    if (tid == 0) raise_error(a, kDevWidth, K);
+    return;
+  }
+  double* Cp = a.scratch + (int64_t)slot * a.slot_doubles;   // kCandCap x q, row-major
+  double* Rp = Cp + (int64_t)kCandCap * q;                     // q x kCandCap, column-major
+  double flops = 0.0;
+
+  // ---------------- column panel: rows >= f of block column K
+  int np = load_preds(a, a.col_cnt, a.col_list, a.col_ovf, K, s.pred, s.misc);
+  if (np < 0) {
+    if (tid == 0) raise_error(a, kDevPredOverflow, K);
+    return;
+  }
+  const int mc = build_candidates(s, s.cand, a.cp, a.ri, f, l, l + 1, np, a, true, f, l);
+  if (mc < 0) {
+    if (tid == 0) raise_error(a, kDevCandOverflow, K);
+    return;
+  }
+  for (int e = tid; e < mc * q; e += blockDim.x) Cp[e] = 0.0;
+  __syncthreads();
+  for (int c = f; c <= l; ++c) {
+    for (int64_t m = a.cp[c] + tid; m < a.cp[c + 1]; m += blockDim.x) {
+      int r = a.ri[m];
+      if (r >= f) Cp[(int64_t)lower_bound(s.cand, mc, r) * q + (c - f)] = a.cv[m];
+    }
+  }
+  __syncthreads();
+  for (int pi = 0; pi < np; ++pi) {
+    const int J = s.pred[pi];
+    const int pJ = a.bstart[J + 1] - a.bstart[J];
+    const int nRJ = a.nr[J], nCJ = a.nc[J];
+    const int32_t* RJ = a.idx_heap + a.roff[J];
+    const int32_t* CJ = a.idx_heap + a.coff[J];
+    const double* LJ = a.val_heap + a.loff[J];
+    const double* WJ = a.val_heap + a.woff[J];
+    if (tid == 0) {
+      s.misc[8] = 0;
+      s.misc[9] = 0;
+      s.misc[10] = 0;
+    }
+    __syncthreads();
+    int c0 = 0, c1 = 0, r0 = 0;
+    for (int t = tid; t < nCJ; t += blockDim.x) {
+      int c = CJ[t];
+      c0 += c < f;
+      c1 += c <= l;
+    }
+    for (int t = tid; t < nRJ; t += blockDim.x) r0 += RJ[t] < f;
+    c0 = wave_sum(c0);
+    c1 = wave_sum(c1);
+    r0 = wave_sum(r0);
+    if ((tid & 63) == 0) {
+      atomicAdd(&s.misc[8], c0);
+      atomicAdd(&s.misc[9], c1);
+      atomicAdd(&s.misc[10], r0);
+    }
+    __syncthreads();
+    c0 = s.misc[8];
+    c1 = s.misc[9];
+    r0 = s.misc[10];
+    const int ncol = c1 - c0, nrow = nRJ - r0;
+    const int work = ncol * nrow;
+    for (int w = tid; w < work; w += blockDim.x) {
+      const int ri = r0 + w / ncol, cj = c0 + w % ncol;
+      const int z = lower_bound(s.cand, mc, RJ[ri]);
+      const double acc = dot_strided(LJ + (int64_t)ri * pJ, WJ + (int64_t)cj * pJ, pJ);
+      Cp[(int64_t)z * q + (CJ[cj] - f)] -= acc;
+    }
+    flops += 2.0 * work * pJ;
+    __syncthreads();
+  }
+
+  // ---------------- row panel: columns > l of block row K
+  np = load_preds(a, a.row_cnt, a.row_list, a.row_ovf, K, s.pred, s.misc);
+  if (np < 0) {
+    if (tid == 0) raise_error(a, kDevPredOverflow, K);
+    return;
+  }
+  const int mcc = build_candidates(s, s.candc, a.rp, a.ci, f, l, l + 1, np, a, false, 1, 0);
+  if (mcc < 0) {
+    if (tid == 0) raise_error(a, kDevCandOverflow, K);
+    return;
+  }
+  for (int e = tid; e < mcc * q; e += blockDim.x) Rp[e] = 0.0;
+  __syncthreads();
+  for (int r = f; r <= l; ++r) {
+    for (int64_t m = a.rp[r] + tid; m < a.rp[r + 1]; m += blockDim.x) {
+      int c = a.ci[m];
+      if (c > l) Rp[(int64_t)lower_bound(s.candc, mcc, c) * q + (r - f)] = a.rv[m];
+    }
+  }
+  __syncthreads();
+  for (int pi = 0; pi < np; ++pi) {
+    const int J = s.pred[pi];
+    const int pJ = a.bstart[J + 1] - a.bstart[J];
+    const int nRJ = a.nr[J], nCJ = a.nc[J];
+    const int32_t* RJ = a.idx_heap + a.roff[J];
+    const int32_t* CJ = a.idx_heap + a.coff[J];
+    const double* LJ = a.val_heap + a.loff[J];
+    const double* WJ = a.val_heap + a.woff[J];
+    if (tid == 0) {
+      s.misc[8] = 0;
+      s.misc[9] = 0;
+      s.misc[10] = 0;
+    }
+    __syncthreads();
+    int r0 = 0, r1 = 0, c0 = 0;
+    for (int t = tid; t < nRJ; t += blockDim.x) {
+      int r = RJ[t];
+      r0 += r < f;
+      r1 += r <= l;
+    }
+    for (int t = tid; t < nCJ; t += blockDim.x) c0 += CJ[t] <= l;
+    r0 = wave_sum(r0);
+    r1 = wave_sum(r1);
+    c0 = wave_sum(c0);
+    if ((tid & 63) == 0) {
+      atomicAdd(&s.misc[8], r0);
+      atomicAdd(&s.misc[9], r1);
+      atomicAdd(&s.misc[10], c0);
+    }
+    __syncthreads();
+    r0 = s.misc[8];
+    r1 = s.misc[9];
+    c0 = s.misc[10];
+    const int nrow = r1 - r0, ncol = nCJ - c0;
+    const int work = nrow * ncol;
+    for (int w = tid; w < work; w += blockDim.x) {
+      const int ri = r0 + w % nrow, cj = c0 + w / nrow;
+      const int z = lower_bound(s.candc, mcc, CJ[cj]);
+      const double acc = dot_strided(LJ + (int64_t)ri * pJ, WJ + (int64_t)cj * pJ, pJ);
+      Rp[(int64_t)z * q + (RJ[ri] - f)] -= acc;
+    }
+    flops += 2.0 * work * pJ;
+    __syncthreads();
+  }
+
+  // ---------------- pivot block: perturb (Sec. 3.6) + invert
+  // q x q perturbed pivot block and work/inverse: LDS up to width 64,
+  // the slot's scratch beyond the panels for wider blocks
+  double* big = Rp + (int64_t)kCandCap * q;
+  double* sS = q <= kLdsPivotWidth ? s_dyn : big;
+  double* sW = q <= kLdsPivotWidth ? s_dyn + q * q : big + q * q;
+  for (int e = tid; e < q * q; e += blockDim.x) sS[e] = Cp[e];
+  if (tid == 0) s.misc[12] = 0;
+  __syncthreads();
+  // all-zero columns, then all-zero rows, are perturbed before factoring
+  for (int j = tid; j < q; j += blockDim.x) {
+    bool zero = true;
+    for (int i = 0; i < q; ++i) zero = zero && sS[i * q + j] == 0.0;
+    if (zero) {
+      perturb_column(sS, q, j, a);
+      s.misc[12] = 1;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < q; i += blockDim.x) {
+    bool zero = true;
+    for (int j = 0; j < q; ++j) zero = zero && sS[i * q + j] == 0.0;
+    if (zero) {
+      perturb_row(sS, q, i, a);
+      s.misc[12] = 1;
+    }
+  }
+  __syncthreads();
+  int rounds = s.misc[12];
+  for (int attempt = 0;; ++attempt) {
+    double mx = 0.0;
+    int finite = 1;
+    for (int e = tid; e < q * q; e += blockDim.x) {
+      double v = sS[e];
+      sW[e] = v;
+      if (!isfinite(v)) finite = 0;
+      mx = fmax(mx, fabs(v));
+    }
+    mx = wave_max(mx);
+    finite = __all(finite);
+    if (tid == 0) {
+      s.misc[13] = 1;
+      s.smax = 0.0;
+    }
+    __syncthreads();
+    if ((tid & 63) == 0) {
+      if (!finite) s.misc[13] = 0;
+      // non-negative doubles order like their bit patterns
+      atomicMax(reinterpret_cast<unsigned long long*>(&s.smax),
+                (unsigned long long)__double_as_longlong(mx));
+    }
+    __syncthreads();
+    const double smax = s.smax;
+    bool ok = s.misc[13] && gauss_jordan_inverse(sW, q, smax, a.pivot_eps, s.f, s.ip, s.misc);
+    __syncthreads();
+    if (ok) break;
+    if (attempt == 3) {
+      if (tid == 0) raise_error(a, kDevSingular, K);
+      return;
+    }
+    for (int j = tid; j < q; j += blockDim.x) perturb_column(sS, q, j, a);
+    __syncthreads();
+    for (int i = tid; i < q; i += blockDim.x) perturb_row(sS, q, i, a);
+    __syncthreads();
+    ++rounds;
+  }
+  if (tid == 0 && rounds > 0) atomicAdd(a.n_perturbed, 1);
+  for (int e = tid; e < q * q; e += blockDim.x) {
+    a.dval[a.doff[K] + e] = sW[e];
+    a.sval[a.doff[K] + e] = sS[e];
+  }
+
+  // ---------------- drop: rows of L (scaled) and columns of U (D R)
+  int* keep_r = s.hash;                 // flags for rows q..mc-1
+  int* keep_c = s.hash + kCandCap;      // flags for cols 0..mcc-1
+  const bool two = a.drop_norm == 1;
+  for (int z = q + tid; z < mc; z += blockDim.x) {
+    double* row = Cp + (int64_t)z * q;
+    double v[kMaxWidth > 16 ? 16 : kMaxWidth];
+    double nrm = 0.0;
+    // scaled row, q entries; computed in chunks of 16 to bound registers
+    for (int c0 = 0; c0 < q; c0 += 16) {
+      const int cn = min(16, q - c0);
+      for (int c = 0; c < cn; ++c) v[c] = 0.0;
+      for (int t = 0; t < q; ++t) {
+        const double x = row[t];
+        for (int c = 0; c < cn; ++c) v[c] = fma(x, sW[t * q + c0 + c], v[c]);
+      }
+      for (int c = 0; c < cn; ++c) nrm = two ? fma(v[c], v[c], nrm) : fmax(nrm, fabs(v[c]));
+    }
+    if (two) nrm = sqrt(nrm);
+    keep_r[z] = nrm > a.tau ? 1 : 0;
+  }
+  for (int z = tid; z < mcc; z += blockDim.x) {
+    const double* col = Rp + (int64_t)z * q;
+    double nrm = 0.0;
+    for (int r = 0; r < q; ++r) {
+      double acc = 0.0;
+      for (int t = 0; t < q; ++t) acc = fma(sW[r * q + t], col[t], acc);
+      nrm = two ? fma(acc, acc, nrm) : fmax(nrm, fabs(acc));
+    }
+    if (two) nrm = sqrt(nrm);
+    keep_c[z] = nrm > a.tau ? 1 : 0;
+  }
+  __syncthreads();
+  // compaction offsets: rows, then columns
+  constexpr int kPer = kCandCap / kThreads;  // flags per thread
+  int fr[kPer], fc[kPer];
+  int sr = 0, sc = 0;
+  for (int k = 0; k < kPer; ++k) {
+    const int z = tid * kPer + k;
+    fr[k] = (z >= q && z < mc) ? keep_r[z] : 0;
+    fc[k] = (z < mcc) ? keep_c[z] : 0;
+    sr += fr[k];
+    sc += fc[k];
+  }
+  int mk = 0, nk = 0;
+  const int pr = wg_exclusive_scan(sr, s.scan, &mk);
+  const int pc = wg_exclusive_scan(sc, s.scan, &nk);
+  if (tid == 0) {
+    unsigned long long vo = atomicAdd(a.val_top, (unsigned long long)(mk + nk) * q);
+    unsigned long long io = atomicAdd(a.idx_top, (unsigned long long)(mk + nk));
+    bool over = vo + (unsigned long long)(mk + nk) * q > (unsigned long long)a.val_cap ||
+                io + (unsigned long long)(mk + nk) > (unsigned long long)a.idx_cap;
+    s.misc[16] = over ? 1 : 0;
+    s.off[0] = (long long)vo;
+    s.off[1] = (long long)io;
+    if (over) raise_error(a, kDevHeapOverflow, K);
+  }
+  __syncthreads();
+  if (s.misc[16]) return;
+  const int64_t vo = s.off[0];
+  const int64_t io = s.off[1];
+  double* Lout = a.val_heap + vo;
+  double* Wout = Lout + (int64_t)mk * q;
+  int32_t* Rout = a.idx_heap + io;
+  int32_t* Cout = Rout + mk;
+  // write kept rows of L (recomputing the scaled row) and kept columns of W
+  {
+    int pos = pr;
+    for (int k = 0; k < kPer; ++k) {
+      if (!fr[k]) continue;
+      const int z = tid * kPer + k;
+      const double* row = Cp + (int64_t)z * q;
+      for (int c = 0; c < q; ++c) {
+        double acc = 0.0;
+        for (int t = 0; t < q; ++t) acc = fma(row[t], sW[t * q + c], acc);
+        Lout[(int64_t)pos * q + c] = acc;
+      }
+      Rout[pos] = s.cand[z];
+      ++pos;
+    }
+    pos = pc;
+    for (int k = 0; k < kPer; ++k) {
+      if (!fc[k]) continue;
+      const int z = tid * kPer + k;
+      for (int r = 0; r < q; ++r) Wout[(int64_t)pos * q + r] = Rp[(int64_t)z * q + r];
+      Cout[pos] = s.candc[z];
+      ++pos;
+    }
+  }
+  if (tid == 0) {
+    a.roff[K] = io;
+    a.nr[K] = mk;
+    a.coff[K] = io + mk;
+    a.nc[K] = nk;
+    a.loff[K] = vo;
+    a.woff[K] = vo + (int64_t)mk * q;
+    atomicAdd(a.flops, (unsigned long long)flops);
+  }
+  __syncthreads();
+  // K updates the row panels of the blocks holding its rows of L and the
+  // column panels of the blocks holding its columns of U.
+  for (int t = tid; t < mk; t += blockDim.x) {
+    const int b = a.blockOf[Rout[t]];
+    if (t == 0 || a.blockOf[Rout[t - 1]] != b) push_pred(a, a.row_cnt, a.row_list, a.row_ovf, b, K);
+  }
+  for (int t = tid; t < nk; t += blockDim.x) {
+    const int b = a.blockOf[Cout[t]];
+    if (t == 0 || a.blockOf[Cout[t - 1]] != b) push_pred(a, a.col_cnt, a.col_list, a.col_ovf, b, K);
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) factor_level_kernel(FactorArgs a) {
+  __shared__ Lds s;
+  extern __shared__ double s_dyn[];
+  for (int idx = a.begin + blockIdx.x; idx < a.end; idx += gridDim.x) {
+    // the whole workgroup leaves together once any block reported an error
+    if (threadIdx.x == 0) s.misc[31] = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (s.misc[31]) return;
+    factor_block(a, a.sched[idx], blockIdx.x, s, s_dyn);
+    __syncthreads();
+  }
+}
+
+__global__ void fill_block_of(const int32_t* bstart, int nb, int32_t* blockOf) {
+  int b = blockIdx.x * blockDim.y + threadIdx.y;
+  if (b >= nb) return;
+  for (int i = bstart[b] + threadIdx.x; i < bstart[b + 1]; i += blockDim.x) blockOf[i] = b;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host driver
+// ---------------------------------------------------------------------------
+bilu_status factor_device(bilu_handle* h, double tau) {
+  using clk = std::chrono::steady_clock;
+  auto t0 = clk::now();
+  const int64_t n = h->n;
+  std::vector<int32_t>& bs = h->bstart0;
+  const int64_t nb = ilu1t_partition(h, tau, bs);
+  auto t1 = clk::now();
+  h->stats.t_ilu1t = std::chrono::duration<double>(t1 - t0).count();
+  int32_t maxq = 0;
+  for (int64_t b = 0; b < nb; ++b) maxq = std::max(maxq, bs[b + 1] - bs[b]);
+  if (maxq > kMaxWidth) return fail(h, BILU_ERR_INVALID, "block wider than the kernel limit");
+  block_etree_levels(h, bs, h->sched, h->sched_ptr);
+  const int nlev = (int)h->sched_ptr.size() - 1;
+  h->sched_qmax.assign(nlev, 0);
+  for (int L = 0; L < nlev; ++L)
+    for (int i = h->sched_ptr[L]; i < h->sched_ptr[L + 1]; ++i) {
+      int K = h->sched[i];
+      h->sched_qmax[L] = std::max(h->sched_qmax[L], bs[K + 1] - bs[K]);
+    }
+  h->doff_h.assign(nb + 1, 0);
+  for (int64_t b = 0; b < nb; ++b) {
+    int64_t q = bs[b + 1] - bs[b];
+    h->doff_h[b + 1] = h->doff_h[b] + q * q;
+  }
+  hipStream_t st = h->stream;
+#define CK(x)                                              \
+  do {                                                     \
+    hipError_t e_ = (x);                                   \
+    if (e_ != hipSuccess) return hip_check(h, e_, #x);     \
+  } while (0)
+  CK(h->d_bstart.alloc(nb + 1));
+  CK(h->d_blockof.alloc(n));
+  CK(h->d_roff.alloc(nb));
+  CK(h->d_coff.alloc(nb));
+  CK(h->d_loff.alloc(nb));
+  CK(h->d_woff.alloc(nb));
+  CK(h->d_doff.alloc(nb + 1));
+  CK(h->d_nr.alloc(nb));
+  CK(h->d_nc.alloc(nb));
+  CK(h->d_dval.alloc(h->doff_h[nb]));
+  CK(h->d_sval.alloc(h->doff_h[nb]));
+  CK(h->d_col_cnt.alloc(nb));
+  CK(h->d_row_cnt.alloc(nb));
+  CK(h->d_col_list.alloc((size_t)nb * kListCap));
+  CK(h->d_row_list.alloc((size_t)nb * kListCap));
+  CK(h->d_col_ovf.alloc(nb));
+  CK(h->d_row_ovf.alloc(nb));
+  const int64_t ovf_cap = std::max<int64_t>(1 << 16, 4 * nb);
+  CK(h->d_ovf_j.alloc(ovf_cap));
+  CK(h->d_ovf_next.alloc(ovf_cap));
+  CK(h->d_status.alloc(8));
+  CK(h->d_counters.alloc(4));
+  CK(hipMemcpyAsync(h->d_bstart.p, bs.data(), (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(h->d_doff.p, h->doff_h.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  {
+    dim3 blk(64, 4);
+    fill_block_of<<<dim3((unsigned)((nb + 3) / 4)), blk, 0, st>>>(h->d_bstart.p, (int)nb, h->d_blockof.p);
+  }
+  // heap sizes: values and indices of L and W
+  int64_t val_cap = h->opt.heap_bytes ? (int64_t)(h->opt.heap_bytes / sizeof(double))
+                                      : std::max<int64_t>(1 << 20, 4 * h->nnz);
+  int64_t idx_cap = std::max<int64_t>(1 << 20, 2 * h->nnz);
+  // scratch: one slot per resident workgroup
+  int64_t widest_level = 1;
+  for (int L = 0; L < nlev; ++L)
+    widest_level = std::max<int64_t>(widest_level, h->sched_ptr[L + 1] - h->sched_ptr[L]);
+  const int64_t slots = std::min<int64_t>(2048, widest_level);
+  const int64_t mq = std::max<int32_t>(maxq, 1);
+  const int64_t slot_doubles = 2 * (int64_t)kCandCap * mq + 2 * mq * mq;
+  CK(h->d_scratch.alloc(slots * slot_doubles));
+  h->scratch_slots = slots;
+  h->slot_doubles = slot_doubles;
+  auto t2 = clk::now();
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    if ((int64_t)h->d_val_heap.n < val_cap) CK(h->d_val_heap.alloc(val_cap));
+    if ((int64_t)h->d_idx_heap.n < idx_cap) CK(h->d_idx_heap.alloc(idx_cap));
+    CK(hipMemsetAsync(h->d_col_cnt.p, 0, nb * sizeof(int32_t), st));
+    CK(hipMemsetAsync(h->d_row_cnt.p, 0, nb * sizeof(int32_t), st));
+    CK(hipMemsetAsync(h->d_col_ovf.p, 0xff, nb * sizeof(int32_t), st));
+    CK(hipMemsetAsync(h->d_row_ovf.p, 0xff, nb * sizeof(int32_t), st));
+    CK(hipMemsetAsync(h->d_status.p, 0, 8 * sizeof(int), st));
+    CK(hipMemsetAsync(h->d_counters.p, 0, 4 * sizeof(unsigned long long), st));
+    FactorArgs a{};
+    a.n = (int)n;
+    a.nb = (int)nb;
+    a.cp = h->d_cp.p; a.ri = h->d_ri.p; a.cv = h->d_cv.p;
+    a.rp = h->d_rp.p; a.ci = h->d_ci.p; a.rv = h->d_rv.p;
+    a.bstart = h->d_bstart.p;
+    a.blockOf = h->d_blockof.p;
+    a.tau = tau;
+    a.alpha = h->alpha;
+    a.pert_tau = h->opt.perturb_tau;
+    a.pert_rho = h->opt.perturb_rho;
+    a.pivot_eps = h->opt.pivot_eps;
+    a.beta_one = h->opt.beta_one;
+    a.drop_norm = h->opt.drop_norm;
+    a.update_prec = h->opt.update_precision;
+    a.roff = h->d_roff.p; a.nr = h->d_nr.p; a.coff = h->d_coff.p; a.nc = h->d_nc.p;
+    a.loff = h->d_loff.p; a.woff = h->d_woff.p; a.doff = h->d_doff.p;
+    a.dval = h->d_dval.p; a.sval = h->d_sval.p;
+    a.idx_heap = h->d_idx_heap.p; a.idx_cap = (int64_t)h->d_idx_heap.n; a.idx_top = h->d_counters.p + 0;
+    a.val_heap = h->d_val_heap.p; a.val_cap = (int64_t)h->d_val_heap.n; a.val_top = h->d_counters.p + 1;
+    a.lo_heap = nullptr;
+    a.col_cnt = h->d_col_cnt.p; a.col_list = h->d_col_list.p; a.col_ovf = h->d_col_ovf.p;
+    a.row_cnt = h->d_row_cnt.p; a.row_list = h->d_row_list.p; a.row_ovf = h->d_row_ovf.p;
+    a.ovf_j = h->d_ovf_j.p; a.ovf_next = h->d_ovf_next.p; a.ovf_top = h->d_status.p + 3;
+    a.ovf_cap = (int32_t)ovf_cap;
+    a.scratch = h->d_scratch.p;
+    a.slot_doubles = slot_doubles;
+    a.sched = nullptr;
+    a.err = h->d_status.p + 0;
+    a.err_block = h->d_status.p + 1;
+    a.n_perturbed = h->d_status.p + 2;
+    a.flops = h->d_counters.p + 2;
+    DevArray<int32_t> d_sched;
+    CK(d_sched.alloc(h->sched.size()));
+    CK(hipMemcpyAsync(d_sched.p, h->sched.data(), h->sched.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    a.sched = d_sched.p;
+    for (int L = 0; L < nlev; ++L) {
+      a.begin = h->sched_ptr[L];
+      a.end = h->sched_ptr[L + 1];
+      const int cnt = a.end - a.begin;
+      const int grid = (int)std::min<int64_t>(cnt, slots);
+      const int qm = h->sched_qmax[L];
+      const size_t dyn = qm <= kLdsPivotWidth ? 2 * sizeof(double) * qm * qm : 0;
+      factor_level_kernel<<<grid, kThreads, dyn, st>>>(a);
+    }
+    CK(hipGetLastError());
+    int status[8];
+    unsigned long long ctr[4];
+    CK(hipMemcpyAsync(status, h->d_status.p, sizeof(status), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(ctr, h->d_counters.p, sizeof(ctr), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (status[0] == kDevHeapOverflow) {
+      val_cap = std::max<int64_t>(val_cap * 2, (int64_t)ctr[1] * 2);
+      idx_cap = std::max<int64_t>(idx_cap * 2, (int64_t)ctr[0] * 2);
+      continue;
+    }
+    if (status[0] != kDevOk) {
+      static const char* what[] = {"ok", "candidate set exceeds the per-block capacity",
+                                   "predecessor list exceeds the per-block capacity",
+                                   "factor heap exhausted", "predecessor overflow pool exhausted",
+                                   "pivot block singular after perturbation",
+                                   "block wider than the kernel limit", "dependency wait timed out"};
+      std::string msg = std::string("factor kernel: ") + what[std::min(status[0], 7)] +
+                        " (block " + std::to_string(status[1]) + ")";
+      return fail(h, status[0] == kDevSingular ? BILU_ERR_SINGULAR : BILU_ERR_NO_MEMORY, msg);
+    }
+    h->stats.perturbed_blocks = status[2];
+    h->stats.flops_update = (double)ctr[2];
+    h->stats.factor_levels = nlev;
+    auto t3 = clk::now();
+    h->stats.t_factor_device = std::chrono::duration<double>(t3 - t2).count();
+    h->stats.nblocks_initial = nb;
+    return BILU_OK;
+  }
+  return fail(h, BILU_ERR_NO_MEMORY, "factor heap could not be sized");
+#undef CK
+}
+
+}  // namespace bilu

@@ -1,0 +1,194 @@
+// Internal declarations of the BILU library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bilu.h"
+
+namespace bilu {
+
+// Capacities of the per-block work of the factor kernel.
+constexpr int kThreads = 256;      // threads per workgroup (4 wave64)
+constexpr int kHashSlots = 4096;   // LDS hash of candidate rows/columns
+constexpr int kCandCap = 2048;     // unique candidate rows (or columns) per block
+constexpr int kPredCap = 1024;     // predecessors per block panel
+constexpr int kListCap = 24;       // inline capacity of a block's predecessor list
+constexpr int kMaxWidth = 128;     // widest pivot block
+constexpr int kLdsPivotWidth = 64; // pivot blocks up to this width live in LDS
+
+// Error codes written by kernels into the device status word.
+enum DevErr : int {
+  kDevOk = 0,
+  kDevCandOverflow = 1,
+  kDevPredOverflow = 2,
+  kDevHeapOverflow = 3,
+  kDevListOverflow = 4,
+  kDevSingular = 5,
+  kDevWidth = 6,
+  kDevSpin = 7,
+};
+
+template <class T>
+struct DevArray {
+  T* p = nullptr;
+  size_t n = 0;
+  ~DevArray() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t alloc(size_t count) {
+    release();
+    n = count;
+    if (count == 0) return hipSuccess;
+    return hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
+  }
+};
+
+// Everything the factor kernels read and write, passed by value.
+struct FactorArgs {
+  int n, nb;
+  const int64_t* cp;      // CSC of the permuted matrix
+  const int32_t* ri;
+  const double* cv;
+  const int64_t* rp;      // CSR of the permuted matrix
+  const int32_t* ci;
+  const double* rv;
+  const int32_t* bstart;  // [nb+1]
+  const int32_t* blockOf; // [n]
+  double tau, alpha, pert_tau, pert_rho, pivot_eps;
+  int beta_one, drop_norm, update_prec;
+  // factor storage, per block
+  int64_t* roff;  int32_t* nr;     // rows of L  : idx heap
+  int64_t* coff;  int32_t* nc;     // cols of U  : idx heap
+  int64_t* loff;  int64_t* woff;   // values     : val heap
+  const int64_t* doff;             // D / S      : prefix of q^2
+  double* dval;
+  double* sval;
+  int32_t* idx_heap; int64_t idx_cap; unsigned long long* idx_top;
+  double* val_heap;  int64_t val_cap; unsigned long long* val_top;
+  float* lo_heap;                  // low-precision copy of L/W (same offsets) or null
+  // predecessor lists: inline + overflow linked list
+  int32_t* col_cnt; int32_t* col_list; int32_t* col_ovf;
+  int32_t* row_cnt; int32_t* row_list; int32_t* row_ovf;
+  int32_t* ovf_j; int32_t* ovf_next; int32_t* ovf_top; int32_t ovf_cap;
+  // per-workgroup scratch (panels)
+  double* scratch; int64_t slot_doubles;
+  // schedule
+  const int32_t* sched; int begin, end;
+  // status / counters
+  int* err; int* err_block; int* n_perturbed;
+  unsigned long long* flops;
+};
+
+struct ApplyPlan;
+
+}  // namespace bilu
+
+struct bilu_handle {
+  bilu_options opt{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  int state = 0;  // 0 created, 1 analyzed, 2 factored
+  int64_t n = 0, nnz = 0;
+  double alpha = 0.0;
+
+  // ---- analyze (host)
+  std::vector<int64_t> perm;          // new -> old
+  std::vector<int64_t> group_starts;  // cosine groups, permuted numbering
+  std::vector<int64_t> prp;           // permuted CSR
+  std::vector<int32_t> pci;
+  std::vector<double> pv;
+  std::vector<int64_t> pcp;           // permuted CSC
+  std::vector<int32_t> pri;
+  std::vector<double> pcv;
+  // ---- analyze (device)
+  bilu::DevArray<int64_t> d_rp, d_cp;
+  bilu::DevArray<int32_t> d_ci, d_ri, d_perm;
+  bilu::DevArray<double> d_rv, d_cv;
+
+  // ---- factor: partition + schedule (host)
+  std::vector<int32_t> bstart0;       // initial partition
+  std::vector<int32_t> sched, sched_ptr;  // blocks by level
+  std::vector<int32_t> sched_qmax;    // widest block per level
+  std::vector<int64_t> doff_h;
+  // ---- factor storage (device)
+  bilu::DevArray<int32_t> d_bstart, d_blockof;
+  bilu::DevArray<int64_t> d_roff, d_coff, d_loff, d_woff, d_doff;
+  bilu::DevArray<int32_t> d_nr, d_nc;
+  bilu::DevArray<double> d_dval, d_sval;
+  bilu::DevArray<int32_t> d_idx_heap;
+  bilu::DevArray<double> d_val_heap;
+  bilu::DevArray<float> d_lo_heap;
+  bilu::DevArray<int32_t> d_col_cnt, d_col_list, d_col_ovf, d_row_cnt, d_row_list, d_row_ovf;
+  bilu::DevArray<int32_t> d_ovf_j, d_ovf_next;
+  bilu::DevArray<double> d_scratch;
+  bilu::DevArray<int> d_status;                  // err, err_block, n_perturbed, ovf_top
+  bilu::DevArray<unsigned long long> d_counters; // idx_top, val_top, flops
+  int64_t scratch_slots = 0, slot_doubles = 0;
+
+  // ---- final factor (after aggregation), used by apply
+  int64_t nb = 0;                    // final block count
+  std::vector<int32_t> bstart;       // final partition (host)
+  bilu::DevArray<int32_t> f_bstart, f_blockof, f_nr, f_nc;
+  bilu::DevArray<int64_t> f_roff, f_coff, f_loff, f_woff, f_doff;
+  bilu::DevArray<int32_t> f_idx;     // idx heap of the final factor
+  bilu::DevArray<double> f_val, f_dval;
+  bool final_is_initial = true;      // no merge happened: f_* alias the factor storage
+  // forward-solve predecessor lists of the final blocks: CSR (sorted by J)
+  bilu::DevArray<int32_t> fw_ptr, fw_j, fw_r0, fw_cnt;
+  std::vector<int32_t> apply_sched, apply_ptr;   // levels (forward); backward = reverse
+  bilu::DevArray<int32_t> d_apply_sched;
+  std::vector<int32_t> bapply_sched, bapply_ptr;
+
+  // ---- solver workspace
+  bilu::DevArray<double> w_vec;      // scratch vectors
+  bilu::DevArray<double> w_red;      // reduction partials
+  int64_t w_cols = 0;
+
+  bilu_stats stats{};
+};
+
+namespace bilu {
+
+// error helpers
+bilu_status fail(bilu_handle* h, bilu_status s, const std::string& msg);
+bilu_status hip_check(bilu_handle* h, hipError_t e, const char* what);
+
+// analyze.cpp
+bilu_status analyze_host(bilu_handle* h, int64_t n, const int64_t* rowptr,
+                         const int32_t* colind, const double* val);
+int64_t ilu1t_partition(const bilu_handle* h, double tau, std::vector<int32_t>& bstart);
+void block_etree_levels(const bilu_handle* h, const std::vector<int32_t>& bstart,
+                        std::vector<int32_t>& sched, std::vector<int32_t>& sched_ptr);
+
+// factor.hip
+bilu_status factor_device(bilu_handle* h, double tau);
+
+// aggregate.hip
+bilu_status aggregate_device(bilu_handle* h);
+
+// solve.hip
+bilu_status build_apply_plan(bilu_handle* h);
+bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t);
+bilu_status spmv_permuted(bilu_handle* h, const double* x, double* y);
+void launch_gather(hipStream_t s, int64_t n, const int32_t* perm, const double* x, double* y);
+void launch_scatter(hipStream_t s, int64_t n, const int32_t* perm, const double* x, double* y);
+void launch_axpy(hipStream_t s, int64_t n, const double* alpha_dev, double sign, const double* x,
+                 double* y);
+void launch_axpy_host(hipStream_t s, int64_t n, double alpha, const double* x, double* y);
+void launch_scale(hipStream_t s, int64_t n, double alpha, const double* x, double* y);
+void launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* partial,
+                double* out);
+void launch_sub(hipStream_t s, int64_t n, const double* b, const double* ax, double* r);
+
+// fgmres.cpp
+bilu_status fgmres(bilu_handle* h, const double* b, double* x, int restart, double rtol,
+                   int maxit, bilu_solve_info* info);
+
+}  // namespace bilu

@@ -1,0 +1,111 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol,
+and its host-only structural preprocessing equals the oracle's."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1908_10169_amd import bilu, matgen as mg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "bilu.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bilu_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = bilu.load()
+    names = declared_symbols()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(bilu.EXPORTED) == names
+
+
+def test_default_options_are_the_papers():
+    o = bilu.default_options()
+    assert (o.use_cosine, o.use_ilu1t, o.use_aggregation) == (1, 1, 1)
+    assert o.cos_eps == 0.8 and o.perturb_tau == 1e-2 and o.perturb_rho == 1e-1
+    assert o.max_block == 128
+
+
+WORKLOADS = ["cd2d_32x32_b3", "cd3d_12_b4", "el3d_10_b3"]
+
+
+@pytest.mark.parametrize("name", WORKLOADS)
+@pytest.mark.parametrize("blocking", [dict(), dict(use_cosine=False),
+                                      dict(use_ilu1t=False)])
+def test_preprocess_matches_oracle(name, blocking):
+    from oracle import Oracle, OracleOptions
+    w = mg.workload(name)
+    perm, gs, bs = bilu.preprocess(w.a, w.tau, pre_perm=w.perm, ordering=bilu.ORDER_NATURAL,
+                                   **blocking)
+    o = Oracle()
+    assert o.run(w.a, OracleOptions(tau=w.tau, use_aggregation=False, **blocking),
+                 pre_perm=w.perm) == 0
+    assert np.array_equal(perm, o.perm())
+    assert np.array_equal(gs, o.group_starts())
+    assert np.array_equal(bs, o.starts_initial())
+
+
+@pytest.mark.parametrize("tau", [0.0, 1e-3, 1e-1])
+def test_preprocess_tau_and_natural_numbering(tau):
+    from oracle import Oracle, OracleOptions
+    a = mg.grid2d_random_blocks(16, 2, 3.0, seed=5)
+    perm, gs, bs = bilu.preprocess(a, tau, ordering=bilu.ORDER_NATURAL)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=tau, use_aggregation=False)) == 0
+    assert np.array_equal(perm, o.perm()) and np.array_equal(bs, o.starts_initial())
+
+
+def test_nested_dissection_ordering_is_a_block_permutation():
+    a = mg.grid3d_convdiff(b=2, dims=(9, 8, 7), seed=3)
+    perm, gs, bs = bilu.preprocess(a, 1e-2, ordering=bilu.ORDER_ND)
+    assert np.array_equal(np.sort(perm), np.arange(a.n))
+    # every cosine group is one node: its members are consecutive old indices
+    for g in range(len(gs) - 1):
+        mem = perm[gs[g]:gs[g + 1]]
+        assert len(mem) == 2 and mem[1] == mem[0] + 1 and mem[0] % 2 == 0
+
+
+def test_nested_dissection_reduces_fill():
+    """The project ordering should beat the lexicographic one on a 3D grid
+    in exact (symbolic) block LU fill of the compressed graph."""
+    dims = (8, 8, 8)
+    a = mg.grid3d_convdiff(b=1, dims=dims, seed=3)
+    perm_nd, _, _ = bilu.preprocess(a, 1e-2, ordering=bilu.ORDER_ND, use_cosine=False)
+    A = a.to_dense() != 0
+
+    def fill(p):
+        F = A[np.ix_(p, p)].copy()
+        n = len(p)
+        for k in range(n):
+            rows = np.flatnonzero(F[k + 1:, k]) + k + 1
+            cols = np.flatnonzero(F[k, k + 1:]) + k + 1
+            F[np.ix_(rows, cols)] = True
+        return F.sum()
+
+    assert fill(perm_nd) < 0.8 * fill(np.arange(a.n))
+
+
+@pytest.mark.parametrize("bad", ["unsorted", "oob", "nan", "perm"])
+def test_invalid_input_is_rejected(bad):
+    a = mg.grid2d_random_blocks(4, 2, 3.0, seed=1)
+    rp, ci, v = a.rowptr.copy(), a.colind.copy(), a.val.copy()
+    pre = None
+    if bad == "unsorted":
+        ci[0], ci[1] = ci[1], ci[0]
+    elif bad == "oob":
+        ci[3] = a.n
+    elif bad == "nan":
+        v[5] = np.nan
+    else:
+        pre = np.zeros(a.n, dtype=np.int64)
+    b = mg.Csr(a.n, rp, ci, v)
+    with pytest.raises(bilu.BiluError) as e:
+        bilu.preprocess(b, 1e-2, pre_perm=pre)
+    assert e.value.status == bilu.BILU_ERR_INVALID

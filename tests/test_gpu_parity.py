@@ -1,0 +1,189 @@
+"""GPU path vs the FP64 oracle, element by element (through the C ABI).
+
+Bar (FP64 mode): block partition and every row/column pattern identical;
+L, W, D within 1e-10 relative (Frobenius, per factor); apply within 1e-10
+relative; equal FGMRES iteration counts and true residual <= rtol.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1908_10169_amd import matgen as mg
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_pair(a, tau, pre_perm=None, agg=False, **blocking):
+    from oracle import Oracle, OracleOptions
+    from paper_1908_10169_amd import bilu
+    o = Oracle()
+    rc = o.run(a, OracleOptions(tau=tau, use_aggregation=agg, **blocking), pre_perm=pre_perm)
+    assert rc == 0
+    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=agg, **blocking)
+    h.analyze(a, pre_perm=pre_perm)
+    h.factor(tau)
+    return o, h
+
+
+def compare_factors(o, h):
+    fo = o.factors()
+    fl = h.export()
+    assert np.array_equal(fl.perm, fo.perm)
+    assert np.array_equal(fl.starts_initial, fo.starts_initial)
+    assert np.array_equal(fl.starts, fo.starts)
+    num = {"L": 0.0, "W": 0.0, "D": 0.0}
+    den = {"L": 0.0, "W": 0.0, "D": 0.0}
+    for k in range(len(fo.starts) - 1):
+        assert np.array_equal(fl.R[k], fo.R[k]), f"rows of block {k}"
+        assert np.array_equal(fl.C[k], fo.C[k]), f"cols of block {k}"
+        for name in ("L", "W", "D"):
+            x, y = getattr(fl, name)[k], getattr(fo, name)[k]
+            num[name] += float(np.sum((x - y) ** 2))
+            den[name] += float(np.sum(y ** 2))
+    for name in num:
+        rel = np.sqrt(num[name] / max(den[name], 1e-300))
+        assert rel <= TOL, (name, rel)
+    return fl
+
+
+def check_apply_and_solve(o, h, a, restart=30):
+    torch = _torch()
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal(a.n)
+    yo = o.apply(x)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.empty_like(xd)
+    h.apply(xd, yd)
+    torch.cuda.synchronize()
+    yl = yd.cpu().numpy()
+    assert np.linalg.norm(yl - yo) <= TOL * np.linalg.norm(yo)
+    b = a.matvec(np.ones(a.n))
+    xo, info_o = o.fgmres(b, restart=restart, rtol=1e-8)
+    bd = torch.from_numpy(b).cuda()
+    xl = torch.zeros_like(bd)
+    info_l = h.fgmres(bd, xl, restart=restart, rtol=1e-8)
+    assert info_l["converged"] and info_o["converged"]
+    assert info_l["iterations"] == info_o["iterations"]
+    xh = xl.cpu().numpy()
+    res = np.linalg.norm(b - a.matvec(xh)) / np.linalg.norm(b)
+    assert res <= 1e-8
+    assert info_l["rel_residual"] <= 1e-8
+
+
+CASES = [
+    ("cd2d_natural", lambda: (mg.grid2d_random_blocks(32, 3, 4.5, seed=0), None), 1e-2, {}),
+    ("cd2d_nd", lambda: (mg.workload("cd2d_32x32_b3").a, mg.workload("cd2d_32x32_b3").perm),
+     1e-2, {}),
+    ("cd2d_scalar", lambda: (mg.grid2d_random_blocks(20, 3, 4.5, seed=0), None), 1e-2,
+     dict(use_cosine=False, use_ilu1t=False)),
+    ("cd2d_cosine_only", lambda: (mg.grid2d_random_blocks(24, 2, 3.5, seed=4), None), 3e-2,
+     dict(use_ilu1t=False)),
+    ("cd3d_12_nd", lambda: (mg.workload("cd3d_12_b4").a, mg.workload("cd3d_12_b4").perm), 1e-2, {}),
+    ("el3d_10_nd", lambda: (mg.workload("el3d_10_b3").a, mg.workload("el3d_10_b3").perm), 5e-3, {}),
+    ("random_sparse", lambda: (mg.random_sparse(400, 0.01, seed=5, diag_shift=3.0), None), 1e-2, {}),
+]
+
+
+@pytest.mark.parametrize("name,make,tau,blocking", CASES, ids=[c[0] for c in CASES])
+def test_factor_parity(name, make, tau, blocking):
+    _torch()
+    a, perm = make()
+    say(f"[parity] {name} n={a.n} nnz={a.nnz} tau={tau} {blocking}")
+    o, h = run_pair(a, tau, perm, **blocking)
+    compare_factors(o, h)
+    check_apply_and_solve(o, h, a)
+    h.close()
+
+
+def test_tau_zero_is_exact_lu():
+    torch = _torch()
+    a = mg.grid2d_random_blocks(12, 2, 4.0, seed=2)
+    say(f"[parity] tau0 n={a.n}")
+    o, h = run_pair(a, 0.0)
+    compare_factors(o, h)
+    b = a.matvec(np.ones(a.n)) + np.arange(a.n) / a.n
+    bd = torch.from_numpy(b).cuda()
+    yd = torch.empty_like(bd)
+    h.apply(bd, yd)
+    torch.cuda.synchronize()
+    x_ref = np.linalg.solve(a.to_dense(), b)
+    assert np.linalg.norm(yd.cpu().numpy() - x_ref) <= 1e-12 * np.linalg.norm(x_ref)
+    xl = torch.zeros_like(bd)
+    info = h.fgmres(bd, xl, restart=30, rtol=1e-8)
+    assert info["iterations"] == 1
+
+
+def test_perturbed_pivot_blocks():
+    torch = _torch()
+    # a few nodes get a singular (all-ones) diagonal block and exact-zero
+    # couplings to earlier nodes, so their pivot block is that singular
+    # block; one more gets an all-zero diagonal block (zero column path)
+    a = mg.grid2d_random_blocks(10, 2, 3.0, seed=9)
+    A = a.to_dense()
+    for node, val in ((0, 0.0), (17, 1.0), (40, 1.0), (63, -2.0)):
+        s = slice(2 * node, 2 * node + 2)
+        A[s, s] = val
+        A[s, :2 * node] = 0.0
+        A[:2 * node, s] = 0.0
+    mask = a.to_dense() != 0
+    b = mg.dense_to_csr(A, mask)
+    say(f"[parity] perturbed n={b.n}")
+    o, h = run_pair(b, 1e-2, use_ilu1t=False)
+    assert o.stats()["perturbed_blocks"] == 4
+    assert h.stats()["perturbed_blocks"] == o.stats()["perturbed_blocks"]
+    compare_factors(o, h)
+
+
+def test_tiny_and_ragged():
+    _torch()
+    for n in (1, 2, 5, 37):
+        a = mg.random_sparse(n, 0.3, seed=n, diag_shift=2.0)
+        say(f"[parity] tiny n={n}")
+        o, h = run_pair(a, 1e-2)
+        compare_factors(o, h)
+        check_apply_and_solve(o, h, a, restart=5)
+
+
+def test_deterministic_rerun():
+    torch = _torch()
+    w = mg.workload("cd3d_12_b4")
+    from paper_1908_10169_amd import bilu
+    outs = []
+    for _ in range(2):
+        h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=False)
+        h.analyze(w.a, pre_perm=w.perm)
+        h.factor(w.tau)
+        f = h.export()
+        outs.append(b"".join(x.tobytes() for x in f.L + f.W + f.D))
+        h.close()
+    assert outs[0] == outs[1]
+    del torch
+
+
+def test_state_errors():
+    torch = _torch()
+    from paper_1908_10169_amd import bilu
+    h = bilu.Bilu()
+    x = torch.zeros(10, dtype=torch.float64, device="cuda")
+    y = torch.zeros_like(x)
+    with pytest.raises(bilu.BiluError) as e:
+        h.apply(x, y)
+    assert e.value.status == bilu.BILU_ERR_STATE
+    with pytest.raises(bilu.BiluError) as e:
+        h.factor(1e-2)
+    assert e.value.status == bilu.BILU_ERR_STATE
