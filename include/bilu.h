@@ -142,6 +142,10 @@ bilu_status bilu_factor(bilu_handle* h, double tau);
  * successful factor. */
 bilu_status bilu_apply(bilu_handle* h, const double* x, double* y);
 
+/* Wait for the handle's stream; BILU_ERR_DEVICE if the runtime reports an
+ * error left by asynchronous calls (bilu_apply, bilu_spmv). */
+bilu_status bilu_sync(bilu_handle* h);
+
 /* y = A x with the analyzed matrix (original numbering), device arrays. */
 bilu_status bilu_spmv(bilu_handle* h, const double* x, double* y);
 

@@ -75,7 +75,7 @@ EXPORTED = [
     "bilu_default_options", "bilu_create", "bilu_analyze", "bilu_factor", "bilu_apply",
     "bilu_spmv", "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors",
     "bilu_free_factors", "bilu_destroy", "bilu_status_string", "bilu_last_error",
-    "bilu_preprocess",
+    "bilu_preprocess", "bilu_sync",
 ]
 
 _lib = None
@@ -107,10 +107,12 @@ def load(path: str = LIB_PATH):
     lib.bilu_status_string.restype = C.c_char_p
     lib.bilu_last_error.argtypes = [vp]
     lib.bilu_last_error.restype = C.c_char_p
+    lib.bilu_sync.argtypes = [vp]
     lib.bilu_preprocess.argtypes = [C.POINTER(Options), C.c_int64, vp, vp, vp, C.c_double,
                                     vp, vp, C.POINTER(C.c_int64), vp, C.POINTER(C.c_int64)]
     for f in ("bilu_create", "bilu_analyze", "bilu_factor", "bilu_apply", "bilu_spmv",
-              "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors", "bilu_preprocess"):
+              "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors", "bilu_preprocess",
+              "bilu_sync"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -233,6 +235,10 @@ class Bilu:
     def apply(self, x, y):
         """y = M^{-1} x; x, y: torch float64 CUDA tensors of length n."""
         return self._check(self._lib.bilu_apply(self._h, x.data_ptr(), y.data_ptr()), "bilu_apply")
+
+    def sync(self):
+        """Wait for the stream; raise if an asynchronous call reported an error."""
+        return self._check(self._lib.bilu_sync(self._h), "bilu_sync")
 
     def spmv(self, x, y):
         return self._check(self._lib.bilu_spmv(self._h, x.data_ptr(), y.data_ptr()), "bilu_spmv")

@@ -138,11 +138,24 @@ bilu_status bilu_factor(bilu_handle* h, double tau) {
   GUARD_BEGIN
   auto t0 = std::chrono::steady_clock::now();
   h->state = 1;
-  h->d_apply_sched.release();
   bilu_status s = factor_device(h, tau);
   if (s != BILU_OK) return s;
   h->nb = h->stats.nblocks_initial;
   h->bstart = h->bstart0;
+  h->fv = FactorView{};
+  h->fv.nb = (int)h->nb;
+  h->fv.bstart = h->d_bstart.p;
+  h->fv.blockOf = h->d_blockof.p;
+  h->fv.nr = h->d_nr.p;
+  h->fv.nc = h->d_nc.p;
+  h->fv.roff = h->d_roff.p;
+  h->fv.coff = h->d_coff.p;
+  h->fv.loff = h->d_loff.p;
+  h->fv.woff = h->d_woff.p;
+  h->fv.doff = h->d_doff.p;
+  h->fv.idx = h->d_idx_heap.p;
+  h->fv.val = h->d_val_heap.p;
+  h->fv.dval = h->d_dval.p;
   auto t1 = std::chrono::steady_clock::now();
   if (h->opt.use_aggregation) {
     s = aggregate_device(h);
@@ -156,8 +169,8 @@ bilu_status bilu_factor(bilu_handle* h, double tau) {
   {
     const int64_t nb = h->nb;
     std::vector<int32_t> nr(nb), nc(nb);
-    if (hipMemcpy(nr.data(), h->d_nr.p, nb * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(nc.data(), h->d_nc.p, nb * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpy(nr.data(), h->fv.nr, nb * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(nc.data(), h->fv.nc, nb * 4, hipMemcpyDeviceToHost) != hipSuccess)
       return fail(h, BILU_ERR_DEVICE, "stats copy");
     double sum = 0, sum2 = 0;
     int64_t mx = 0, nl = 0, nw = 0, nd = 0, ir = 0, ic = 0;
@@ -266,6 +279,13 @@ bilu_status bilu_preprocess(const bilu_options* opt, int64_t n, const int64_t* r
   GUARD_END
 }
 
+bilu_status bilu_sync(bilu_handle* h) {
+  if (!h) return BILU_ERR_INVALID;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_check(h, e, "bilu_sync");
+  return BILU_OK;
+}
+
 bilu_status bilu_get_stats(const bilu_handle* h, bilu_stats* st) {
   if (!h || !st) return BILU_ERR_INVALID;
   *st = h->stats;
@@ -281,12 +301,13 @@ bilu_status bilu_export_factors(const bilu_handle* hc, bilu_factors_host* out) {
   const int64_t n = h->n, nb = h->nb;
   std::vector<int32_t> nr(nb), nc(nb);
   std::vector<int64_t> roff(nb), coff(nb), loff(nb), woff(nb);
-  if (hipMemcpy(nr.data(), h->d_nr.p, nb * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(nc.data(), h->d_nc.p, nb * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(roff.data(), h->d_roff.p, nb * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(coff.data(), h->d_coff.p, nb * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(loff.data(), h->d_loff.p, nb * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(woff.data(), h->d_woff.p, nb * 8, hipMemcpyDeviceToHost) != hipSuccess)
+  const FactorView& fv = h->fv;
+  if (hipMemcpy(nr.data(), fv.nr, nb * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(nc.data(), fv.nc, nb * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(roff.data(), fv.roff, nb * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(coff.data(), fv.coff, nb * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(loff.data(), fv.loff, nb * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(woff.data(), fv.woff, nb * 8, hipMemcpyDeviceToHost) != hipSuccess)
     return fail(h, BILU_ERR_DEVICE, "export copy");
   int64_t tr = 0, tc = 0, tl = 0, tw = 0, td = 0;
   for (int64_t b = 0; b < nb; ++b) {
@@ -297,7 +318,13 @@ bilu_status bilu_export_factors(const bilu_handle* hc, bilu_factors_host* out) {
     tw += nc[b] * q;
     td += q * q;
   }
-  std::vector<int32_t> idx(h->d_idx_heap.n);
+  int64_t idx_len = 0, val_len = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    int64_t q = h->bstart[b + 1] - h->bstart[b];
+    idx_len = std::max(idx_len, std::max(roff[b] + nr[b], coff[b] + nc[b]));
+    val_len = std::max(val_len, std::max(loff[b] + nr[b] * q, woff[b] + nc[b] * q));
+  }
+  std::vector<int32_t> idx(idx_len);
   std::vector<double> val;
   // copy only what is referenced: gather per block from device heaps
   out->n = n;
@@ -320,11 +347,10 @@ bilu_status bilu_export_factors(const bilu_handle* hc, bilu_factors_host* out) {
   for (size_t b = 0; b < h->bstart0.size(); ++b) out->starts_initial[b] = h->bstart0[b];
   std::copy(h->group_starts.begin(), h->group_starts.end(), out->group_starts);
   // whole heaps are copied once (simple; export is a checking path)
-  std::vector<double> vheap(h->d_val_heap.n);
-  if (hipMemcpy(idx.data(), h->d_idx_heap.p, idx.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(vheap.data(), h->d_val_heap.p, vheap.size() * 8, hipMemcpyDeviceToHost) !=
-          hipSuccess ||
-      hipMemcpy(out->d_val, h->d_dval.p, td * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+  std::vector<double> vheap(val_len);
+  if (hipMemcpy(idx.data(), fv.idx, idx.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(vheap.data(), fv.val, vheap.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(out->d_val, fv.dval, td * 8, hipMemcpyDeviceToHost) != hipSuccess) {
     bilu_free_factors(out);
     return fail(h, BILU_ERR_DEVICE, "export copy");
   }

@@ -86,7 +86,26 @@ struct FactorArgs {
   unsigned long long* flops;
 };
 
-struct ApplyPlan;
+// Device view of a block factor (initial or aggregated), used by the apply
+// and by export.  Per block K: rows R_K (nr, at idx+roff), columns C_K
+// (nc, at idx+coff), L_K (nr x q row-major at val+loff), W_K (q x nc
+// column-major at val+woff), D_K (q x q row-major at dval+doff).
+struct FactorView {
+  int nb = 0;
+  const int32_t* bstart = nullptr;
+  const int32_t* blockOf = nullptr;
+  const int32_t* nr = nullptr;
+  const int32_t* nc = nullptr;
+  const int64_t* roff = nullptr;
+  const int64_t* coff = nullptr;
+  const int64_t* loff = nullptr;
+  const int64_t* woff = nullptr;
+  const int64_t* doff = nullptr;
+  const int32_t* idx = nullptr;
+  const double* val = nullptr;
+  const double* dval = nullptr;
+};
+
 
 }  // namespace bilu
 
@@ -140,11 +159,16 @@ struct bilu_handle {
   bilu::DevArray<int32_t> f_idx;     // idx heap of the final factor
   bilu::DevArray<double> f_val, f_dval;
   bool final_is_initial = true;      // no merge happened: f_* alias the factor storage
-  // forward-solve predecessor lists of the final blocks: CSR (sorted by J)
-  bilu::DevArray<int32_t> fw_ptr, fw_j, fw_r0, fw_cnt;
-  std::vector<int32_t> apply_sched, apply_ptr;   // levels (forward); backward = reverse
-  bilu::DevArray<int32_t> d_apply_sched;
-  std::vector<int32_t> bapply_sched, bapply_ptr;
+  bilu::FactorView fv;               // the factor the apply uses
+  // apply plan: predecessor blocks of the forward sweep (sorted, with the
+  // range of their rows inside the block), successor blocks of the backward
+  // sweep, and a row-major copy of L
+  bilu::DevArray<int32_t> fw_ptr, fw_j, fw_r0, fw_cnt, bw_ptr, bw_b;
+  bilu::DevArray<int64_t> lr_ptr;
+  bilu::DevArray<int32_t> lr_col;
+  bilu::DevArray<double> lr_val;
+  bilu::DevArray<int32_t> lev_f, lev_b;          // blocks by forward / backward level
+  std::vector<int32_t> lev_f_ptr, lev_b_ptr;
 
   // ---- solver workspace
   bilu::DevArray<double> w_vec;      // scratch vectors

@@ -18,127 +18,221 @@ namespace {
 
 constexpr int kDotBlocks = 512;
 
-struct ApplyArgs {
-  const int32_t* bstart;
-  const int32_t* nr;
-  const int32_t* nc;
-  const int64_t* roff;
-  const int64_t* coff;
-  const int64_t* loff;
-  const int64_t* woff;
-  const int64_t* doff;
-  const int32_t* idx;
-  const double* val;
-  const double* dval;
-  const int32_t* fw_ptr;
-  const int32_t* fw_j;
-  const int32_t* fw_r0;
-  const int32_t* fw_cnt;
+// ---------------------------------------------------------------------------
+// Apply plan builders (run once per factorization)
+// ---------------------------------------------------------------------------
+// Runs of consecutive rows of R_J that fall into one block K.
+__global__ void __launch_bounds__(256) fw_count(FactorView f, int32_t* cnt) {
+  const int J = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (J >= f.nb) return;
+  const int lane = threadIdx.x & 63;
+  const int32_t* R = f.idx + f.roff[J];
+  const int m = f.nr[J];
+  for (int i = lane; i < m; i += 64) {
+    const int K = f.blockOf[R[i]];
+    if (i == 0 || f.blockOf[R[i - 1]] != K) atomicAdd(&cnt[K], 1);
+  }
+}
+
+// Packed (J, first row index in R_J, row count) keys, sorted later per block.
+__global__ void __launch_bounds__(256) fw_fill(FactorView f, const int32_t* ptr, int32_t* fillc,
+                                               unsigned long long* keys) {
+  const int J = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (J >= f.nb) return;
+  const int lane = threadIdx.x & 63;
+  const int32_t* R = f.idx + f.roff[J];
+  const int m = f.nr[J];
+  for (int i = lane; i < m; i += 64) {
+    const int K = f.blockOf[R[i]];
+    if (i == 0 || f.blockOf[R[i - 1]] != K) {
+      int e = i + 1;
+      while (e < m && f.blockOf[R[e]] == K) ++e;
+      const int pos = atomicAdd(&fillc[K], 1);
+      keys[ptr[K] + pos] = ((unsigned long long)J << 32) | ((unsigned long long)i << 8) |
+                           (unsigned long long)(e - i);
+    }
+  }
+}
+
+// Sort each block's keys (ascending J) and unpack them.
+__global__ void __launch_bounds__(64) fw_sort(int nb, const int32_t* ptr, unsigned long long* keys,
+                                              int32_t* fw_j, int32_t* fw_r0, int32_t* fw_cnt) {
+  const int K = blockIdx.x;
+  if (K >= nb) return;
+  const int b = ptr[K], m = ptr[K + 1] - b;
+  if (threadIdx.x == 0) {
+    unsigned long long* k = keys + b;
+    for (int i = 1; i < m; ++i) {  // insertion sort: lists are short
+      unsigned long long v = k[i];
+      int j = i - 1;
+      while (j >= 0 && k[j] > v) {
+        k[j + 1] = k[j];
+        --j;
+      }
+      k[j + 1] = v;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const unsigned long long v = keys[b + i];
+    fw_j[b + i] = (int32_t)(v >> 32);
+    fw_r0[b + i] = (int32_t)((v >> 8) & 0xffffff);
+    fw_cnt[b + i] = (int32_t)(v & 0xff);
+  }
+}
+
+// Distinct blocks of C_K (successors of K in the backward sweep).
+__global__ void __launch_bounds__(256) bw_count(FactorView f, int32_t* cnt) {
+  const int K = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (K >= f.nb) return;
+  const int lane = threadIdx.x & 63;
+  const int32_t* Cc = f.idx + f.coff[K];
+  const int m = f.nc[K];
+  int c = 0;
+  for (int i = lane; i < m; i += 64) c += (i == 0 || f.blockOf[Cc[i - 1]] != f.blockOf[Cc[i]]);
+  c = wave_sum(c);
+  if (lane == 0) cnt[K] = c;
+}
+__global__ void __launch_bounds__(64) bw_fill(FactorView f, const int32_t* ptr, int32_t* bw_b) {
+  const int K = blockIdx.x;
+  if (K >= f.nb || threadIdx.x != 0) return;
+  const int32_t* Cc = f.idx + f.coff[K];
+  const int m = f.nc[K];
+  int at = ptr[K];
+  for (int i = 0; i < m; ++i) {
+    const int B = f.blockOf[Cc[i]];
+    if (i == 0 || f.blockOf[Cc[i - 1]] != B) bw_b[at++] = B;
+  }
+}
+
+// Row-major copy of L: row i lists, for every block J (ascending) whose L_J
+// holds row i, the q_J entries L_J(i, :) at columns first(J)..last(J).
+__global__ void __launch_bounds__(256) lr_count(FactorView f, const int32_t* fw_ptr,
+                                                const int32_t* fw_j, const int32_t* fw_r0,
+                                                const int32_t* fw_cnt, int64_t* lr_cnt) {
+  const int K = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (K >= f.nb) return;
+  const int lane = threadIdx.x & 63;
+  const int fK = f.bstart[K], q = f.bstart[K + 1] - fK;
+  for (int r = lane; r < q; r += 64) {
+    int64_t c = 0;
+    for (int e = fw_ptr[K]; e < fw_ptr[K + 1]; ++e) {
+      const int J = fw_j[e];
+      const int32_t* R = f.idx + f.roff[J];
+      for (int i = fw_r0[e]; i < fw_r0[e] + fw_cnt[e]; ++i)
+        if (R[i] == fK + r) c += f.bstart[J + 1] - f.bstart[J];
+    }
+    lr_cnt[fK + r] = c;
+  }
+}
+__global__ void __launch_bounds__(256) lr_fill(FactorView f, const int32_t* fw_ptr,
+                                               const int32_t* fw_j, const int32_t* fw_r0,
+                                               const int32_t* fw_cnt, const int64_t* lr_ptr,
+                                               int32_t* lr_col, double* lr_val) {
+  const int K = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (K >= f.nb) return;
+  const int lane = threadIdx.x & 63;
+  const int fK = f.bstart[K], q = f.bstart[K + 1] - fK;
+  for (int r = lane; r < q; r += 64) {
+    int64_t at = lr_ptr[fK + r];
+    for (int e = fw_ptr[K]; e < fw_ptr[K + 1]; ++e) {
+      const int J = fw_j[e];
+      const int fJ = f.bstart[J], pJ = f.bstart[J + 1] - fJ;
+      const int32_t* R = f.idx + f.roff[J];
+      const double* L = f.val + f.loff[J];
+      for (int i = fw_r0[e]; i < fw_r0[e] + fw_cnt[e]; ++i)
+        if (R[i] == fK + r)
+          for (int c = 0; c < pJ; ++c) {
+            lr_col[at] = fJ + c;
+            lr_val[at] = L[(int64_t)i * pJ + c];
+            ++at;
+          }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Level-scheduled sweeps.  Blocks are grouped by their depth in the actual
+// dependency graph of the factor (forward: predecessors J whose L_J has rows
+// in K; backward: blocks holding the columns of U_K); one launch per level,
+// one wave per block, no waiting inside a kernel.
+// ---------------------------------------------------------------------------
+struct SweepArgs {
+  FactorView f;
+  const int64_t* lr_ptr;
+  const int32_t* lr_col;
+  const double* lr_val;
   const int32_t* sched;
   int begin, end;
 };
 
-__global__ void __launch_bounds__(256) forward_level(ApplyArgs a, const double* x, double* t) {
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int idx = a.begin + w;
-  if (idx >= a.end) return;
+// forward: t_K = x_K - sum over stored L(i, j) t_j, rows of K from the
+// row-major copy (groups of lanes per row, fixed reduction tree)
+__global__ void __launch_bounds__(256) forward_level(SweepArgs a, const double* x, double* t) {
+  const int w = a.begin + blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= a.end) return;
   const int lane = threadIdx.x & 63;
-  const int K = a.sched[idx];
-  const int f = a.bstart[K], q = a.bstart[K + 1] - f;
-  for (int r = lane; r < q; r += 64) {
+  const int K = a.sched[w];
+  const int f = a.f.bstart[K], q = a.f.bstart[K + 1] - f;
+  int qp = 1;
+  while (qp < q && qp < 64) qp <<= 1;
+  const int g = 64 / qp;  // lanes per row
+  for (int r0 = 0; r0 < q; r0 += qp) {
+    const int r = r0 + lane / g, sub = lane % g;
     double acc = 0.0;
-    for (int e = a.fw_ptr[K]; e < a.fw_ptr[K + 1]; ++e) {
-      const int J = a.fw_j[e], r0 = a.fw_r0[e], cnt = a.fw_cnt[e];
-      const int fJ = a.bstart[J], pJ = a.bstart[J + 1] - fJ;
-      const int32_t* RJ = a.idx + a.roff[J];
-      const double* LJ = a.val + a.loff[J];
-      for (int ir = r0; ir < r0 + cnt; ++ir) {
-        if (RJ[ir] != f + r) continue;
-        const double* lr = LJ + (int64_t)ir * pJ;
-        for (int c = 0; c < pJ; ++c) acc = fma(lr[c], t[fJ + c], acc);
-      }
+    if (r < q) {
+      const int64_t b = a.lr_ptr[f + r], e = a.lr_ptr[f + r + 1];
+      for (int64_t k = b + sub; k < e; k += g) acc = fma(a.lr_val[k], t[a.lr_col[k]], acc);
     }
-    t[f + r] = x[f + r] - acc;
+    for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (r < q && sub == 0) t[f + r] = x[f + r] - acc;
   }
 }
 
-__global__ void __launch_bounds__(256) backward_level(ApplyArgs a, const double* t, double* z) {
+// backward: z_K = D_K (t_K - W_K z(C_K)); lanes over the columns of W_K,
+// 16 rows at a time, wave-wide reduction; v staged in LDS per wave
+__global__ void __launch_bounds__(256) backward_level(SweepArgs a, const double* t, double* z) {
   __shared__ double sv[4][kMaxWidth];
-  const int wv = threadIdx.x >> 6;
-  const int idx = a.begin + blockIdx.x * 4 + wv;
-  const bool active = idx < a.end;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int w = a.begin + blockIdx.x * 4 + wv;
+  const bool active = w < a.end;
   int K = 0, f = 0, q = 0;
   if (active) {
-    K = a.sched[idx];
-    f = a.bstart[K];
-    q = a.bstart[K + 1] - f;
-    const int nC = a.nc[K];
-    const int32_t* CK = a.idx + a.coff[K];
-    const double* WK = a.val + a.woff[K];
-    for (int r = lane; r < q; r += 64) {
-      double acc = 0.0;
-      for (int cj = 0; cj < nC; ++cj) acc = fma(WK[(int64_t)cj * q + r], z[CK[cj]], acc);
-      sv[wv][r] = t[f + r] - acc;
+    K = a.sched[w];
+    f = a.f.bstart[K];
+    q = a.f.bstart[K + 1] - f;
+    const int m = a.f.nc[K];
+    const int32_t* Cc = a.f.idx + a.f.coff[K];
+    const double* W = a.f.val + a.f.woff[K];
+    for (int c0 = 0; c0 < q; c0 += 16) {
+      const int cn = min(16, q - c0);
+      double p[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) p[r] = 0.0;
+      for (int j = lane; j < m; j += 64) {
+        const double zj = z[Cc[j]];
+        const double* wc = W + (int64_t)j * q + c0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          if (r < cn) p[r] = fma(wc[r], zj, p[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        double v = p[r];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == r && r < cn) sv[wv][c0 + r] = t[f + c0 + r] - v;
+      }
     }
   }
   __syncthreads();
   if (active) {
-    const double* DK = a.dval + a.doff[K];
+    const double* D = a.f.dval + a.f.doff[K];
     for (int r = lane; r < q; r += 64) {
       double acc = 0.0;
-      for (int c = 0; c < q; ++c) acc = fma(DK[r * q + c], sv[wv][c], acc);
+      for (int c = 0; c < q; ++c) acc = fma(D[r * q + c], sv[wv][c], acc);
       z[f + r] = acc;
     }
-  }
-}
-
-// Forward lists of each block: predecessors J with rows inside K, sorted, and
-// the range of those rows inside R_J.
-__global__ void __launch_bounds__(256) build_forward_lists(
-    int nb, const int32_t* bstart, const int32_t* cnt_arr, const int32_t* list,
-    const int32_t* ovf_head, const int32_t* ovf_j, const int32_t* ovf_next, const int32_t* nr,
-    const int64_t* roff, const int32_t* idx, const int32_t* fw_ptr, int32_t* fw_j,
-    int32_t* fw_r0, int32_t* fw_cnt, int* err) {
-  __shared__ int keys[kPredCap];
-  const int K = blockIdx.x;
-  if (K >= nb) return;
-  const int cnt = cnt_arr[K];
-  if (cnt > kPredCap) {
-    if (threadIdx.x == 0) atomicExch(err, kDevPredOverflow);
-    return;
-  }
-  const int inl = min(cnt, kListCap);
-  for (int t = threadIdx.x; t < inl; t += blockDim.x) keys[t] = list[(int64_t)K * kListCap + t];
-  if (threadIdx.x == 0) {
-    int node = ovf_head[K], at = kListCap;
-    while (node >= 0 && at < cnt) {
-      keys[at++] = ovf_j[node];
-      node = ovf_next[node];
-    }
-  }
-  __syncthreads();
-  wg_bitonic_sort(keys, cnt);
-  const int f = bstart[K], l = bstart[K + 1] - 1;
-  const int base = fw_ptr[K];
-  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
-    const int J = keys[e];
-    const int32_t* RJ = idx + roff[J];
-    const int m = nr[J];
-    int lo = 0, hi = m;
-    while (lo < hi) {
-      int mid = (lo + hi) >> 1;
-      if (RJ[mid] < f) lo = mid + 1; else hi = mid;
-    }
-    int r0 = lo;
-    hi = m;
-    while (lo < hi) {
-      int mid = (lo + hi) >> 1;
-      if (RJ[mid] <= l) lo = mid + 1; else hi = mid;
-    }
-    fw_j[base + e] = J;
-    fw_r0[base + e] = r0;
-    fw_cnt[base + e] = lo - r0;
   }
 }
 
@@ -245,82 +339,129 @@ bilu_status spmv_permuted(bilu_handle* h, const double* x, double* y) {
   return BILU_OK;
 }
 
-// Forward lists and apply levels for the final factor.
+// Apply plan of the factor in h->fv: forward/backward dependency lists and
+// the row-major copy of L.
 bilu_status build_apply_plan(bilu_handle* h) {
   hipStream_t st = h->stream;
-  const int64_t nb = h->nb;
+  const FactorView& f = h->fv;
+  const int64_t nb = f.nb, n = h->n;
 #define CK(x)                                          \
   do {                                                 \
     hipError_t e_ = (x);                               \
     if (e_ != hipSuccess) return hip_check(h, e_, #x); \
   } while (0)
-  std::vector<int32_t> cnt(nb), ptr(nb + 1, 0);
-  CK(hipMemcpyAsync(cnt.data(), h->d_row_cnt.p, nb * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  const unsigned gw = (unsigned)((nb + 3) / 4);  // one wave per block
+  DevArray<int32_t> cnt;
+  CK(cnt.alloc(nb + 1));
+  CK(hipMemsetAsync(cnt.p, 0, (nb + 1) * sizeof(int32_t), st));
+  fw_count<<<gw, 256, 0, st>>>(f, cnt.p);
+  std::vector<int32_t> hc(nb), ptr(nb + 1, 0);
+  CK(hipMemcpyAsync(hc.data(), cnt.p, nb * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
-  for (int64_t k = 0; k < nb; ++k) ptr[k + 1] = ptr[k] + cnt[k];
+  for (int64_t k = 0; k < nb; ++k) ptr[k + 1] = ptr[k] + hc[k];
+  const int64_t ne = std::max<int64_t>(1, ptr[nb]);
   CK(h->fw_ptr.alloc(nb + 1));
-  CK(h->fw_j.alloc(std::max<int32_t>(1, ptr[nb])));
-  CK(h->fw_r0.alloc(std::max<int32_t>(1, ptr[nb])));
-  CK(h->fw_cnt.alloc(std::max<int32_t>(1, ptr[nb])));
+  CK(h->fw_j.alloc(ne));
+  CK(h->fw_r0.alloc(ne));
+  CK(h->fw_cnt.alloc(ne));
+  DevArray<unsigned long long> keys;
+  CK(keys.alloc(ne));
   CK(hipMemcpyAsync(h->fw_ptr.p, ptr.data(), (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  int* err = h->d_status.p + 4;
-  CK(hipMemsetAsync(err, 0, sizeof(int), st));
-  build_forward_lists<<<(unsigned)nb, 256, 0, st>>>(
-      (int)nb, h->d_bstart.p, h->d_row_cnt.p, h->d_row_list.p, h->d_row_ovf.p, h->d_ovf_j.p,
-      h->d_ovf_next.p, h->d_nr.p, h->d_roff.p, h->d_idx_heap.p, h->fw_ptr.p, h->fw_j.p, h->fw_r0.p,
-      h->fw_cnt.p, err);
-  CK(hipGetLastError());
-  int e = 0;
-  CK(hipMemcpyAsync(&e, err, sizeof(int), hipMemcpyDeviceToHost, st));
+  CK(hipMemsetAsync(cnt.p, 0, (nb + 1) * sizeof(int32_t), st));
+  fw_fill<<<gw, 256, 0, st>>>(f, h->fw_ptr.p, cnt.p, keys.p);
+  fw_sort<<<(unsigned)nb, 64, 0, st>>>((int)nb, h->fw_ptr.p, keys.p, h->fw_j.p, h->fw_r0.p,
+                                       h->fw_cnt.p);
+  // backward successor blocks
+  bw_count<<<gw, 256, 0, st>>>(f, cnt.p);
+  CK(hipMemcpyAsync(hc.data(), cnt.p, nb * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
-  if (e) return fail(h, BILU_ERR_NO_MEMORY, "forward list exceeds capacity");
-  // schedule: the factorization's tree levels are valid for both sweeps
-  h->apply_sched = h->sched;
-  h->apply_ptr = h->sched_ptr;
-  h->stats.apply_levels_fwd = (int64_t)h->apply_ptr.size() - 1;
-  h->stats.apply_levels_bwd = h->stats.apply_levels_fwd;
+  for (int64_t k = 0; k < nb; ++k) ptr[k + 1] = ptr[k] + hc[k];
+  CK(h->bw_ptr.alloc(nb + 1));
+  CK(h->bw_b.alloc(std::max<int64_t>(1, ptr[nb])));
+  CK(hipMemcpyAsync(h->bw_ptr.p, ptr.data(), (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  bw_fill<<<(unsigned)nb, 64, 0, st>>>(f, h->bw_ptr.p, h->bw_b.p);
+  // row-major L
+  CK(h->lr_ptr.alloc(n + 1));
+  DevArray<int64_t> lc;
+  CK(lc.alloc(n));
+  lr_count<<<gw, 256, 0, st>>>(f, h->fw_ptr.p, h->fw_j.p, h->fw_r0.p, h->fw_cnt.p, lc.p);
+  std::vector<int64_t> hl(n), lp(n + 1, 0);
+  CK(hipMemcpyAsync(hl.data(), lc.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  for (int64_t i = 0; i < n; ++i) lp[i + 1] = lp[i] + hl[i];
+  CK(hipMemcpyAsync(h->lr_ptr.p, lp.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  CK(h->lr_col.alloc(std::max<int64_t>(1, lp[n])));
+  CK(h->lr_val.alloc(std::max<int64_t>(1, lp[n])));
+  lr_fill<<<gw, 256, 0, st>>>(f, h->fw_ptr.p, h->fw_j.p, h->fw_r0.p, h->fw_cnt.p, h->lr_ptr.p,
+                              h->lr_col.p, h->lr_val.p);
+  CK(hipGetLastError());
+  // dependency levels (actual graph of the factor), computed on the host
+  {
+    std::vector<int32_t> fp(nb + 1), fj, bp(nb + 1), bb;
+    CK(hipMemcpyAsync(fp.data(), h->fw_ptr.p, (nb + 1) * 4, hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(bp.data(), h->bw_ptr.p, (nb + 1) * 4, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    fj.resize(std::max<int32_t>(1, fp[nb]));
+    bb.resize(std::max<int32_t>(1, bp[nb]));
+    CK(hipMemcpyAsync(fj.data(), h->fw_j.p, fj.size() * 4, hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(bb.data(), h->bw_b.p, bb.size() * 4, hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    auto levels = [&](bool fwd, std::vector<int32_t>& sched, std::vector<int32_t>& lptr) {
+      std::vector<int32_t> lev(nb, 0);
+      int32_t top = 0;
+      for (int64_t s0 = 0; s0 < nb; ++s0) {
+        const int64_t K = fwd ? s0 : nb - 1 - s0;
+        int32_t l = 0;
+        if (fwd)
+          for (int32_t e = fp[K]; e < fp[K + 1]; ++e) l = std::max(l, lev[fj[e]] + 1);
+        else
+          for (int32_t e = bp[K]; e < bp[K + 1]; ++e) l = std::max(l, lev[bb[e]] + 1);
+        lev[K] = l;
+        top = std::max(top, l);
+      }
+      lptr.assign(top + 2, 0);
+      for (int64_t K = 0; K < nb; ++K) lptr[lev[K] + 1]++;
+      for (int32_t l = 0; l <= top; ++l) lptr[l + 1] += lptr[l];
+      sched.resize(nb);
+      std::vector<int32_t> at(lptr.begin(), lptr.end() - 1);
+      for (int64_t K = 0; K < nb; ++K) sched[at[lev[K]]++] = (int32_t)K;
+    };
+    std::vector<int32_t> sf, sb;
+    levels(true, sf, h->lev_f_ptr);
+    levels(false, sb, h->lev_b_ptr);
+    CK(h->lev_f.alloc(nb));
+    CK(h->lev_b.alloc(nb));
+    CK(hipMemcpyAsync(h->lev_f.p, sf.data(), nb * 4, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->lev_b.p, sb.data(), nb * 4, hipMemcpyHostToDevice, st));
+    h->stats.apply_levels_fwd = (int64_t)h->lev_f_ptr.size() - 1;
+    h->stats.apply_levels_bwd = (int64_t)h->lev_b_ptr.size() - 1;
+  }
   CK(h->w_red.alloc(kDotBlocks + 64));
+  CK(hipStreamSynchronize(st));
   return BILU_OK;
 #undef CK
 }
 
 bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t) {
   hipStream_t st = h->stream;
-  ApplyArgs a{};
-  a.bstart = h->d_bstart.p;
-  a.nr = h->d_nr.p;
-  a.nc = h->d_nc.p;
-  a.roff = h->d_roff.p;
-  a.coff = h->d_coff.p;
-  a.loff = h->d_loff.p;
-  a.woff = h->d_woff.p;
-  a.doff = h->d_doff.p;
-  a.idx = h->d_idx_heap.p;
-  a.val = h->d_val_heap.p;
-  a.dval = h->d_dval.p;
-  a.fw_ptr = h->fw_ptr.p;
-  a.fw_j = h->fw_j.p;
-  a.fw_r0 = h->fw_r0.p;
-  a.fw_cnt = h->fw_cnt.p;
-  if (!h->d_apply_sched.p) {
-    if (h->d_apply_sched.alloc(h->apply_sched.size()) != hipSuccess)
-      return fail(h, BILU_ERR_NO_MEMORY, "apply schedule");
-    (void)hipMemcpyAsync(h->d_apply_sched.p, h->apply_sched.data(),
-                         h->apply_sched.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+  SweepArgs a{};
+  a.f = h->fv;
+  a.lr_ptr = h->lr_ptr.p;
+  a.lr_col = h->lr_col.p;
+  a.lr_val = h->lr_val.p;
+  a.sched = h->lev_f.p;
+  const int nf = (int)h->lev_f_ptr.size() - 1;
+  for (int L = 0; L < nf; ++L) {
+    a.begin = h->lev_f_ptr[L];
+    a.end = h->lev_f_ptr[L + 1];
+    forward_level<<<(unsigned)((a.end - a.begin + 3) / 4), 256, 0, st>>>(a, x, t);
   }
-  a.sched = h->d_apply_sched.p;
-  const int nlev = (int)h->apply_ptr.size() - 1;
-  for (int L = 0; L < nlev; ++L) {
-    a.begin = h->apply_ptr[L];
-    a.end = h->apply_ptr[L + 1];
-    const int cnt = a.end - a.begin;
-    forward_level<<<(unsigned)((cnt + 3) / 4), 256, 0, st>>>(a, x, t);
-  }
-  for (int L = nlev - 1; L >= 0; --L) {
-    a.begin = h->apply_ptr[L];
-    a.end = h->apply_ptr[L + 1];
-    const int cnt = a.end - a.begin;
-    backward_level<<<(unsigned)((cnt + 3) / 4), 256, 0, st>>>(a, t, y);
+  a.sched = h->lev_b.p;
+  const int nbk = (int)h->lev_b_ptr.size() - 1;
+  for (int L = 0; L < nbk; ++L) {
+    a.begin = h->lev_b_ptr[L];
+    a.end = h->lev_b_ptr[L + 1];
+    backward_level<<<(unsigned)((a.end - a.begin + 3) / 4), 256, 0, st>>>(a, t, y);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_check(h, e, "apply launch");

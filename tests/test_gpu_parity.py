@@ -69,7 +69,7 @@ def check_apply_and_solve(o, h, a, restart=30):
     xd = torch.from_numpy(x).cuda()
     yd = torch.empty_like(xd)
     h.apply(xd, yd)
-    torch.cuda.synchronize()
+    h.sync()
     yl = yd.cpu().numpy()
     assert np.linalg.norm(yl - yo) <= TOL * np.linalg.norm(yo)
     b = a.matvec(np.ones(a.n))
@@ -120,7 +120,7 @@ def test_tau_zero_is_exact_lu():
     bd = torch.from_numpy(b).cuda()
     yd = torch.empty_like(bd)
     h.apply(bd, yd)
-    torch.cuda.synchronize()
+    h.sync()
     x_ref = np.linalg.solve(a.to_dense(), b)
     assert np.linalg.norm(yd.cpu().numpy() - x_ref) <= 1e-12 * np.linalg.norm(x_ref)
     xl = torch.zeros_like(bd)
