@@ -68,6 +68,7 @@ typedef struct {
   int beta_one;          /* 0: beta_j = max|column j| (default); 1: beta_j = 1        */
   int update_precision;  /* bilu_precision of the Schur-complement products (F64)    */
   size_t heap_bytes;     /* factor heap size; 0 = sized from nnz(A)                  */
+  int collect_timing;    /* 1: time kernels with HIP events on the handle's stream   */
 } bilu_options;
 
 typedef struct bilu_handle bilu_handle;
@@ -94,6 +95,11 @@ typedef struct {
   double flops_update;        /* counted Schur-update flops (2 m p q per product)    */
   double bytes_apply;         /* algorithmic bytes of one preconditioner apply        */
   double t_analyze, t_ilu1t, t_factor_device, t_aggregate, t_factor;  /* seconds   */
+  /* with collect_timing: device time (HIP events) of the factor kernels of
+   * the last bilu_factor, and of all applies / products since it */
+  double dev_ms_factor, dev_ms_apply, dev_ms_spmv;
+  int64_t n_factor_launches, n_apply, n_spmv;
+  double bytes_factor;        /* algorithmic bytes of the factor kernels             */
 } bilu_stats;
 
 /* Library-allocated host copy of the factors (for checking), final blocks. */

@@ -36,6 +36,7 @@ class Options(C.Structure):
         ("pre_perm", C.c_void_p), ("drop_norm", C.c_int), ("perturb_tau", C.c_double),
         ("perturb_rho", C.c_double), ("pivot_eps", C.c_double), ("beta_one", C.c_int),
         ("update_precision", C.c_int), ("heap_bytes", C.c_size_t),
+        ("collect_timing", C.c_int),
     ]
 
 
@@ -55,6 +56,9 @@ class Stats(C.Structure):
         ("flops_update", C.c_double), ("bytes_apply", C.c_double),
         ("t_analyze", C.c_double), ("t_ilu1t", C.c_double), ("t_factor_device", C.c_double),
         ("t_aggregate", C.c_double), ("t_factor", C.c_double),
+        ("dev_ms_factor", C.c_double), ("dev_ms_apply", C.c_double), ("dev_ms_spmv", C.c_double),
+        ("n_factor_launches", C.c_int64), ("n_apply", C.c_int64), ("n_spmv", C.c_int64),
+        ("bytes_factor", C.c_double),
     ]
 
 

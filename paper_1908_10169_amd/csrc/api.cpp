@@ -22,6 +22,41 @@ bilu_status hip_check(bilu_handle* h, hipError_t e, const char* what) {
 
 }  // namespace bilu
 
+hipEvent_t bilu_handle::ev_get() {
+  if (!ev_pool.empty()) {
+    hipEvent_t e = ev_pool.back();
+    ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void bilu_handle::ev_resolve() {
+  if (ev_pending.empty()) return;
+  (void)hipStreamSynchronize(stream);
+  for (const EventPair& p : ev_pending) {
+    float ms = 0.f;
+    if (p.a && p.b && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      if (p.kind == 0) stats.dev_ms_factor += ms;
+      if (p.kind == 1) { stats.dev_ms_apply += ms; stats.n_apply++; }
+      if (p.kind == 2) { stats.dev_ms_spmv += ms; stats.n_spmv++; }
+    }
+    if (p.a) ev_pool.push_back(p.a);
+    if (p.b) ev_pool.push_back(p.b);
+  }
+  ev_pending.clear();
+}
+
+bilu_handle::~bilu_handle() {
+  for (const EventPair& p : ev_pending) {
+    if (p.a) (void)hipEventDestroy(p.a);
+    if (p.b) (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+}
+
 using namespace bilu;
 
 #define GUARD_BEGIN try {
@@ -138,6 +173,9 @@ bilu_status bilu_factor(bilu_handle* h, double tau) {
   GUARD_BEGIN
   auto t0 = std::chrono::steady_clock::now();
   h->state = 1;
+  h->ev_resolve();
+  h->stats.dev_ms_factor = h->stats.dev_ms_apply = h->stats.dev_ms_spmv = 0.0;
+  h->stats.n_apply = h->stats.n_spmv = 0;
   bilu_status s = factor_device(h, tau);
   if (s != BILU_OK) return s;
   h->nb = h->stats.nblocks_initial;
@@ -195,6 +233,10 @@ bilu_status bilu_factor(bilu_handle* h, double tau) {
     // one apply reads every stored value and row/column index once and
     // streams x, t (written, then read) and y: 8 B values, 4 B indices
     h->stats.bytes_apply = 8.0 * double(nl + nw + nd) + 4.0 * double(ir + ic) + 32.0 * h->n;
+    // factor: A once (value + index), the L_J/W_J reads of the updates, the
+    // written factors and their indices
+    h->stats.bytes_factor += 12.0 * double(h->nnz) + 8.0 * double(nl + nw + nd) +
+                             4.0 * double(ir + ic);
   }
   h->stats.t_factor = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   h->state = 2;
@@ -286,8 +328,10 @@ bilu_status bilu_sync(bilu_handle* h) {
   return BILU_OK;
 }
 
-bilu_status bilu_get_stats(const bilu_handle* h, bilu_stats* st) {
+bilu_status bilu_get_stats(const bilu_handle* hc, bilu_stats* st) {
+  bilu_handle* h = const_cast<bilu_handle*>(hc);
   if (!h || !st) return BILU_ERR_INVALID;
+  h->ev_resolve();
   *st = h->stats;
   return BILU_OK;
 }

@@ -277,7 +277,7 @@ __device__ void factor_block(const FactorArgs& a, int K, int slot, Lds& s, doubl
   }
   double* Cp = a.scratch + (int64_t)slot * a.slot_doubles;   // kCandCap x q, row-major
   double* Rp = Cp + (int64_t)kCandCap * q;                     // q x kCandCap, column-major
-  double flops = 0.0;
+  double flops = 0.0, ubytes = 0.0;
 
   // ---------------- column panel: rows >= f of block column K
   int np = load_preds(a, a.col_cnt, a.col_list, a.col_ovf, K, s.pred, s.misc);
@@ -341,6 +341,7 @@ __device__ void factor_block(const FactorArgs& a, int K, int slot, Lds& s, doubl
       Cp[(int64_t)z * q + (CJ[cj] - f)] -= acc;
     }
     flops += 2.0 * work * pJ;
+    ubytes += 8.0 * pJ * (nrow + ncol);
     __syncthreads();
   }
 
@@ -406,6 +407,7 @@ __device__ void factor_block(const FactorArgs& a, int K, int slot, Lds& s, doubl
       Rp[(int64_t)z * q + (RJ[ri] - f)] -= acc;
     }
     flops += 2.0 * work * pJ;
+    ubytes += 8.0 * pJ * (nrow + ncol);
     __syncthreads();
   }
 
@@ -578,6 +580,7 @@ __device__ void factor_block(const FactorArgs& a, int K, int slot, Lds& s, doubl
     a.loff[K] = vo;
     a.woff[K] = vo + (int64_t)mk * q;
     atomicAdd(a.flops, (unsigned long long)flops);
+    atomicAdd(a.upd_bytes, (unsigned long long)ubytes);
   }
   __syncthreads();
   // K updates the row panels of the blocks holding its rows of L and the
@@ -730,10 +733,17 @@ bilu_status factor_device(bilu_handle* h, double tau) {
     a.err_block = h->d_status.p + 1;
     a.n_perturbed = h->d_status.p + 2;
     a.flops = h->d_counters.p + 2;
+    a.upd_bytes = h->d_counters.p + 3;
     DevArray<int32_t> d_sched;
     CK(d_sched.alloc(h->sched.size()));
     CK(hipMemcpyAsync(d_sched.p, h->sched.data(), h->sched.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     a.sched = d_sched.p;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->opt.collect_timing) {
+      e0 = h->ev_get();
+      e1 = h->ev_get();
+      if (e0) (void)hipEventRecord(e0, st);
+    }
     for (int L = 0; L < nlev; ++L) {
       a.begin = h->sched_ptr[L];
       a.end = h->sched_ptr[L + 1];
@@ -743,6 +753,11 @@ bilu_status factor_device(bilu_handle* h, double tau) {
       const size_t dyn = qm <= kLdsPivotWidth ? 2 * sizeof(double) * qm * qm : 0;
       factor_level_kernel<<<grid, kThreads, dyn, st>>>(a);
     }
+    if (h->opt.collect_timing) {
+      if (e1) (void)hipEventRecord(e1, st);
+      h->ev_record(0, e0, e1);
+    }
+    h->stats.n_factor_launches = nlev;
     CK(hipGetLastError());
     int status[8];
     unsigned long long ctr[4];
@@ -766,6 +781,7 @@ bilu_status factor_device(bilu_handle* h, double tau) {
     }
     h->stats.perturbed_blocks = status[2];
     h->stats.flops_update = (double)ctr[2];
+    h->stats.bytes_factor = (double)ctr[3];  // completed with A and output bytes by the caller
     h->stats.factor_levels = nlev;
     auto t3 = clk::now();
     h->stats.t_factor_device = std::chrono::duration<double>(t3 - t2).count();

@@ -84,6 +84,7 @@ struct FactorArgs {
   // status / counters
   int* err; int* err_block; int* n_perturbed;
   unsigned long long* flops;
+  unsigned long long* upd_bytes;  // bytes of L_J rows + W_J columns read by updates
 };
 
 // Device view of a block factor (initial or aggregated), used by the apply
@@ -176,6 +177,18 @@ struct bilu_handle {
   int64_t w_cols = 0;
 
   bilu_stats stats{};
+
+  // event timing (collect_timing): pending event pairs, resolved by stats
+  struct EventPair {
+    hipEvent_t a, b;
+    int kind;  // 0 factor, 1 apply, 2 spmv
+  };
+  std::vector<EventPair> ev_pending;
+  std::vector<hipEvent_t> ev_pool;
+  hipEvent_t ev_get();
+  void ev_record(int kind, hipEvent_t a, hipEvent_t b) { ev_pending.push_back({a, b, kind}); }
+  void ev_resolve();
+  ~bilu_handle();
 };
 
 namespace bilu {

@@ -334,8 +334,18 @@ void launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, doub
 
 bilu_status spmv_permuted(bilu_handle* h, const double* x, double* y) {
   const int64_t n = h->n;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->opt.collect_timing) {
+    e0 = h->ev_get();
+    e1 = h->ev_get();
+    if (e0) (void)hipEventRecord(e0, h->stream);
+  }
   spmv_csr<<<(unsigned)((n * 8 + 255) / 256), 256, 0, h->stream>>>(n, h->d_rp.p, h->d_ci.p,
                                                                    h->d_rv.p, x, y);
+  if (h->opt.collect_timing) {
+    if (e1) (void)hipEventRecord(e1, h->stream);
+    h->ev_record(2, e0, e1);
+  }
   return BILU_OK;
 }
 
@@ -450,6 +460,12 @@ bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t
   a.lr_col = h->lr_col.p;
   a.lr_val = h->lr_val.p;
   a.sched = h->lev_f.p;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->opt.collect_timing) {
+    e0 = h->ev_get();
+    e1 = h->ev_get();
+    if (e0) (void)hipEventRecord(e0, st);
+  }
   const int nf = (int)h->lev_f_ptr.size() - 1;
   for (int L = 0; L < nf; ++L) {
     a.begin = h->lev_f_ptr[L];
@@ -462,6 +478,10 @@ bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t
     a.begin = h->lev_b_ptr[L];
     a.end = h->lev_b_ptr[L + 1];
     backward_level<<<(unsigned)((a.end - a.begin + 3) / 4), 256, 0, st>>>(a, t, y);
+  }
+  if (h->opt.collect_timing) {
+    if (e1) (void)hipEventRecord(e1, st);
+    h->ev_record(1, e0, e1);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_check(h, e, "apply launch");
