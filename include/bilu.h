@@ -68,7 +68,8 @@ typedef struct {
   int beta_one;          /* 0: beta_j = max|column j| (default); 1: beta_j = 1        */
   int update_precision;  /* bilu_precision of the Schur-complement products (F64)    */
   size_t heap_bytes;     /* factor heap size; 0 = sized from nnz(A)                  */
-  int collect_timing;    /* 1: time kernels with HIP events on the handle's stream   */
+  int collect_timing;    /* 1: time kernels with HIP events on the handle's stream;  */
+                         /* 2: also trace every block of the factor kernel           */
 } bilu_options;
 
 typedef struct bilu_handle bilu_handle;
@@ -184,6 +185,16 @@ bilu_status bilu_get_stats(const bilu_handle* h, bilu_stats* st);
  * bilu_free_factors. */
 bilu_status bilu_export_factors(const bilu_handle* h, bilu_factors_host* out);
 void bilu_free_factors(bilu_factors_host* f);
+
+/* Per-block trace of the last factor kernel (collect_timing = 2): 8 values
+ * per initial block in block order, device wall-clock ticks: pushed to the
+ * ready queue, taken by a worker, announced, candidates built, done; then
+ * the block whose event made it ready, that event (0 tree child signalled,
+ * 1 update retracted) and the worker.  out may be NULL to query
+ * *nrecords; capacity counts uint64 values.  BILU_ERR_STATE without a
+ * trace. */
+bilu_status bilu_export_trace(const bilu_handle* h, uint64_t* out, int64_t capacity,
+                              int64_t* nrecords, double* ticks_per_second);
 
 void bilu_destroy(bilu_handle* h);
 const char* bilu_status_string(bilu_status s);

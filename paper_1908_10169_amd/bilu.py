@@ -79,7 +79,7 @@ EXPORTED = [
     "bilu_default_options", "bilu_create", "bilu_analyze", "bilu_factor", "bilu_apply",
     "bilu_spmv", "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors",
     "bilu_free_factors", "bilu_destroy", "bilu_status_string", "bilu_last_error",
-    "bilu_preprocess", "bilu_sync",
+    "bilu_preprocess", "bilu_sync", "bilu_export_trace",
 ]
 
 _lib = None
@@ -112,6 +112,9 @@ def load(path: str = LIB_PATH):
     lib.bilu_last_error.argtypes = [vp]
     lib.bilu_last_error.restype = C.c_char_p
     lib.bilu_sync.argtypes = [vp]
+    lib.bilu_export_trace.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_double)]
+    lib.bilu_export_trace.restype = C.c_int
     lib.bilu_preprocess.argtypes = [C.POINTER(Options), C.c_int64, vp, vp, vp, C.c_double,
                                     vp, vp, C.POINTER(C.c_int64), vp, C.POINTER(C.c_int64)]
     for f in ("bilu_create", "bilu_analyze", "bilu_factor", "bilu_apply", "bilu_spmv",
@@ -239,6 +242,16 @@ class Bilu:
     def apply(self, x, y):
         """y = M^{-1} x; x, y: torch float64 CUDA tensors of length n."""
         return self._check(self._lib.bilu_apply(self._h, x.data_ptr(), y.data_ptr()), "bilu_apply")
+
+    def trace(self):
+        """Per-block factor trace (collect_timing=2): (records x 8 uint64, ticks/s)."""
+        m, tps = C.c_int64(), C.c_double()
+        self._check(self._lib.bilu_export_trace(self._h, None, 0, C.byref(m), C.byref(tps)),
+                    "bilu_export_trace")
+        out = np.zeros(m.value * 8, dtype=np.uint64)
+        self._check(self._lib.bilu_export_trace(self._h, out.ctypes.data, out.size, C.byref(m),
+                                                C.byref(tps)), "bilu_export_trace")
+        return out.reshape(m.value, 8), tps.value
 
     def sync(self):
         """Wait for the stream; raise if an asynchronous call reported an error."""

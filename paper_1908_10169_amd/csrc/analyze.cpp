@@ -619,18 +619,20 @@ int64_t ilu1t_partition(const bilu_handle* h, double tau, std::vector<int32_t>& 
 
 // ---------------------------------------------------------------------------
 // Block elimination tree of the symmetrized block graph (Liu's algorithm
-// with path compression).  Exact block LU only couples a block to its
-// descendants, and the incomplete factor's pattern lies inside the exact
-// one, so processing blocks by tree height is a valid schedule.
+// with path compression).  Exact block LU couples a block only to its
+// ancestors, and the incomplete factor's pattern lies inside the exact one,
+// so a block can be updated only by its descendants.  Returns the tree
+// height; parent[K] = -1 for roots.
 // ---------------------------------------------------------------------------
-void block_etree_levels(const bilu_handle* h, const std::vector<int32_t>& bstart,
-                        std::vector<int32_t>& sched, std::vector<int32_t>& sched_ptr) {
+int32_t block_etree(const bilu_handle* h, const std::vector<int32_t>& bstart,
+                    std::vector<int32_t>& parent) {
   const int64_t n = h->n;
   const int32_t nb = (int32_t)bstart.size() - 1;
   std::vector<int32_t> bof(n);
   for (int32_t b = 0; b < nb; ++b)
     for (int32_t i = bstart[b]; i < bstart[b + 1]; ++i) bof[i] = b;
-  std::vector<int32_t> parent(nb, -1), anc(nb, -1);
+  parent.assign(nb, -1);
+  std::vector<int32_t> anc(nb, -1);
   std::vector<int32_t> nbrs;
   for (int32_t K = 0; K < nb; ++K) {
     nbrs.clear();
@@ -663,12 +665,7 @@ void block_etree_levels(const bilu_handle* h, const std::vector<int32_t>& bstart
     if (parent[K] >= 0) height[parent[K]] = std::max(height[parent[K]], height[K] + 1);
     hmax = std::max(hmax, height[K]);
   }
-  sched_ptr.assign(hmax + 2, 0);
-  for (int32_t K = 0; K < nb; ++K) sched_ptr[height[K] + 1]++;
-  std::partial_sum(sched_ptr.begin(), sched_ptr.end(), sched_ptr.begin());
-  sched.resize(nb);
-  std::vector<int32_t> fill(sched_ptr.begin(), sched_ptr.end() - 1);
-  for (int32_t K = 0; K < nb; ++K) sched[fill[height[K]]++] = K;
+  return hmax + 1;
 }
 
 }  // namespace bilu

@@ -417,6 +417,26 @@ bilu_status bilu_export_factors(const bilu_handle* hc, bilu_factors_host* out) {
   GUARD_END
 }
 
+bilu_status bilu_export_trace(const bilu_handle* hc, uint64_t* out, int64_t capacity,
+                              int64_t* nrecords, double* ticks_per_second) {
+  bilu_handle* h = const_cast<bilu_handle*>(hc);
+  if (!h || !nrecords) return BILU_ERR_INVALID;
+  if (!h->d_trace.p) return fail(h, BILU_ERR_STATE, "no trace: factor with collect_timing = 2");
+  const int64_t m = (int64_t)h->d_trace.n;
+  *nrecords = m / kTraceFields;
+  if (ticks_per_second) {
+    int dev = 0, khz = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    *ticks_per_second = khz > 0 ? 1e3 * khz : 1e8;
+  }
+  if (!out) return BILU_OK;
+  if (capacity < m) return fail(h, BILU_ERR_INVALID, "trace buffer too small");
+  if (hipMemcpy(out, h->d_trace.p, m * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(h, BILU_ERR_DEVICE, "trace copy");
+  return BILU_OK;
+}
+
 void bilu_free_factors(bilu_factors_host* f) {
   if (!f) return;
   delete[] f->perm;

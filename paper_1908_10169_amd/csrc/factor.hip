@@ -15,8 +15,18 @@
 //      their norm is <= tau, the kept ones compacted into the factor heap
 //      (L scaled, W = R unscaled), and K is appended to the predecessor lists
 //      of the blocks it will update.
-// Blocks are processed level by level along the block elimination tree;
-// blocks of one level are independent.
+// Scheduling: a block may only be updated by its descendants in the block
+// elimination tree.  After computing its candidate rows/columns a block K
+// announces itself to every block they fall into (it can update no other)
+// and signals its tree parent; when done it appends itself to the lists of
+// the blocks it does update and retracts the announcements.  A block is
+// ready once all its tree children have signalled (every possible updater
+// has announced) and no announcement to it is outstanding: its lists are
+// then complete.  The event that makes a block ready pushes it to a queue;
+// a fixed set of co-resident workgroups takes queue positions in turn, so
+// ready blocks are processed in readiness order and the critical path is
+// the longest chain of real updates and announcements, not the tree height.
+// Queue waits are bounded in wall-clock time and end on any reported error.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -208,7 +218,9 @@ struct Lds {
   int hash[kHashSlots];     // candidate dedup; reused as keep flags
   int cand[kCandCap];       // sorted candidate rows
   int candc[kCandCap];      // sorted candidate columns
-  int pred[kPredCap];
+  int pred[kPredCap];       // predecessors of the column panel
+  int rpred[kPredCap];      // predecessors of the row panel
+  int ann[kAnnCap];         // blocks this block announced itself to
   int misc[32];
   int scan[20];
   int ip[kMaxWidth];
@@ -218,22 +230,20 @@ struct Lds {
 };
 
 // Build the sorted set of candidate indices into out[] from the structural
-// entries of A (lists given by ptr/idx over [lo, hi], keeping idx > thresh)
-// plus the stored index lists of the predecessors (keeping those > thresh2).
+// entries of A (lists ptr/idx over [lo, hi], keeping idx >= min_keep) plus
+// the stored rows (or columns) of the predecessors preds[0..npred).
 // Returns the count or -1 on overflow.
 __device__ int build_candidates(Lds& s, int* out, const int64_t* ptr, const int32_t* idx, int lo,
-                                int hi, int min_keep, int npred, const FactorArgs& a, bool rows,
-                                int diag_first, int diag_last) {
+                                int hi, int min_keep, const int* preds, int npred,
+                                const FactorArgs& a, bool rows, int diag_first, int diag_last) {
   for (int t = threadIdx.x; t < kHashSlots; t += blockDim.x) s.hash[t] = -1;
   if (threadIdx.x == 0) {
     s.misc[4] = 0;  // unique count
     s.misc[5] = 0;  // overflow flag
   }
   __syncthreads();
-  // diagonal indices (column panel only)
   for (int i = diag_first + (int)threadIdx.x; i <= diag_last; i += blockDim.x)
     if (!hash_insert(s.hash, i, &s.misc[4])) s.misc[5] = 1;
-  // structural entries of A
   for (int c = lo; c <= hi; ++c) {
     const int64_t b = ptr[c], e = ptr[c + 1];
     for (int64_t m = b + threadIdx.x; m < e; m += blockDim.x) {
@@ -242,10 +252,9 @@ __device__ int build_candidates(Lds& s, int* out, const int64_t* ptr, const int3
         if (!hash_insert(s.hash, r, &s.misc[4])) s.misc[5] = 1;
     }
   }
-  // stored rows (or columns) of the predecessors: one wave per predecessor
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   for (int pi = wid; pi < npred; pi += nw) {
-    const int J = s.pred[pi];
+    const int J = preds[pi];
     const int cnt = rows ? a.nr[J] : a.nc[J];
     const int32_t* lst = a.idx_heap + (rows ? a.roff[J] : a.coff[J]);
     for (int t = lane; t < cnt; t += 64) {
@@ -268,28 +277,145 @@ __device__ int build_candidates(Lds& s, int* out, const int64_t* ptr, const int3
   return m;
 }
 
-__device__ void factor_block(const FactorArgs& a, int K, int slot, Lds& s, double* s_dyn) {
+__device__ __forceinline__ void trace_at(const FlowArgs& d, int K, int field,
+                                         unsigned long long v) {
+  if (d.trace) d.trace[(int64_t)K * kTraceFields + field] = v;
+}
+
+// Push block B to the ready queue (once); who and why are traced.
+__device__ __forceinline__ void push_ready(const FlowArgs& d, int B, int by, int why) {
+  if (atomicCAS(&d.enq[B], 0, 1) == 0) {
+    trace_at(d, B, 0, wall_clock64());
+    trace_at(d, B, 5, (unsigned long long)by);
+    trace_at(d, B, 6, (unsigned long long)why);
+    const int pos = atomicAdd(d.tail, 1);
+    __hip_atomic_store(&d.queue[pos], B, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Ready test after changing one of the two counters of B (the other is read
+// after a full fence, so of two concurrent last events at least one sees
+// both: the enqueued flag keeps the push unique).
+__device__ __forceinline__ void check_ready(const FlowArgs& d, int B, int by, int why) {
+  __threadfence();
+  const int r = __hip_atomic_load(&d.ready[B], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int p = __hip_atomic_load(&d.pending[B], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (r == d.nchild[B] && p == 0) push_ready(d, B, by, why);
+}
+
+// The blocks K can update: the distinct blocks of its candidate rows and
+// columns, i.e. the static blocks of A's pattern of K plus the row blocks
+// of its column-panel predecessors and the column blocks of its row-panel
+// predecessors.  Deduplicated in the LDS hash into s.ann; returns the count
+// or -1 on overflow.
+__device__ int announce_set(const FactorArgs& a, int K, Lds& s, int np, int npr) {
+  for (int t = threadIdx.x; t < kHashSlots; t += blockDim.x) s.hash[t] = -1;
+  if (threadIdx.x == 0) {
+    s.misc[4] = 0;
+    s.misc[5] = 0;
+  }
+  __syncthreads();
+  for (int64_t e = a.ablk_ptr[K] + threadIdx.x; e < a.ablk_ptr[K + 1]; e += blockDim.x)
+    if (!hash_insert(s.hash, a.ablk[e], &s.misc[4])) s.misc[5] = 1;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int pi = wid; pi < np + npr; pi += nw) {
+    const bool col = pi < np;
+    const int J = col ? s.pred[pi] : s.rpred[pi - np];
+    const int cnt = col ? a.ntr[J] : a.ntc[J];
+    const int32_t* lst = a.idx_heap + (col ? a.troff[J] : a.tcoff[J]);
+    for (int t = lane; t < cnt; t += 64) {
+      const int B = lst[t];
+      if (B > K)
+        if (!hash_insert(s.hash, B, &s.misc[4])) s.misc[5] = 1;
+    }
+  }
+  __syncthreads();
+  const int m = s.misc[4];
+  if (s.misc[5] || m > kAnnCap) return -1;
+  if (threadIdx.x == 0) s.misc[6] = 0;
+  __syncthreads();
+  for (int t = threadIdx.x; t < kHashSlots; t += blockDim.x) {
+    const int k = s.hash[t];
+    if (k >= 0) s.ann[atomicAdd(&s.misc[6], 1)] = k;
+  }
+  __syncthreads();
+  return m;
+}
+
+// Add delta (+1 announce, -1 retract) to the pending count of the blocks in
+// ann; a retraction that brings a count to zero checks readiness.
+__device__ void announce(const FlowArgs& d, const int* ann, int m, int delta, int K) {
+  for (int t = threadIdx.x; t < m; t += blockDim.x) {
+    const int B = ann[t];
+    if (atomicAdd(&d.pending[B], delta) + delta == 0 && delta < 0) check_ready(d, B, K, 1);
+  }
+}
+
+// Append block K to the predecessor list of block B (which must not have
+// started its numeric phase yet).
+__device__ __forceinline__ void push_checked(const FactorArgs& a, const FlowArgs& d,
+                                             int32_t* cnt_arr, int32_t* list, int32_t* ovf_head,
+                                             int B, int K) {
+  if (__hip_atomic_load(&d.started[B], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    raise_error(a, kDevProtocol, K);
+  push_pred(a, cnt_arr, list, ovf_head, B, K);
+}
+
+// Returns false (uniformly) when the block reported an error.
+__device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int slot, Lds& s,
+                             double* s_dyn) {
   const int tid = threadIdx.x;
   const int f = a.bstart[K], l = a.bstart[K + 1] - 1, q = l - f + 1;
   if (q > kMaxWidth) {
     if (tid == 0) raise_error(a, kDevWidth, K);
-    return;
+    return false;
   }
   double* Cp = a.scratch + (int64_t)slot * a.slot_doubles;   // kCandCap x q, row-major
   double* Rp = Cp + (int64_t)kCandCap * q;                     // q x kCandCap, column-major
   double flops = 0.0, ubytes = 0.0;
 
-  // ---------------- column panel: rows >= f of block column K
-  int np = load_preds(a, a.col_cnt, a.col_list, a.col_ovf, K, s.pred, s.misc);
+  // ---------------- predecessors, announcement, then candidates
+  const int np = load_preds(a, a.col_cnt, a.col_list, a.col_ovf, K, s.pred, s.misc);
   if (np < 0) {
     if (tid == 0) raise_error(a, kDevPredOverflow, K);
-    return;
+    return false;
   }
-  const int mc = build_candidates(s, s.cand, a.cp, a.ri, f, l, l + 1, np, a, true, f, l);
+  const int npr = load_preds(a, a.row_cnt, a.row_list, a.row_ovf, K, s.rpred, s.misc);
+  if (npr < 0) {
+    if (tid == 0) raise_error(a, kDevPredOverflow, K);
+    return false;
+  }
+  const int na = announce_set(a, K, s, np, npr);
+  if (na < 0) {
+    if (tid == 0) raise_error(a, kDevAnnOverflow, K);
+    return false;
+  }
+  announce(d, s.ann, na, +1, K);
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    __hip_atomic_store(&d.started[K], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int P = d.parent[K];
+    if (P >= 0) {
+      atomicAdd(&d.ready[P], 1);
+      check_ready(d, P, K, 0);
+    }
+    trace_at(d, K, 2, wall_clock64());
+  }
+  const int mc = build_candidates(s, s.cand, a.cp, a.ri, f, l, l + 1, s.pred, np, a, true, f, l);
   if (mc < 0) {
     if (tid == 0) raise_error(a, kDevCandOverflow, K);
-    return;
+    return false;
   }
+  const int mcc = build_candidates(s, s.candc, a.rp, a.ci, f, l, l + 1, s.rpred, npr, a, false,
+                                   1, 0);
+  if (mcc < 0) {
+    if (tid == 0) raise_error(a, kDevCandOverflow, K);
+    return false;
+  }
+  if (tid == 0) trace_at(d, K, 3, wall_clock64());
+
+  // ---------------- column panel: rows >= f of block column K
   for (int e = tid; e < mc * q; e += blockDim.x) Cp[e] = 0.0;
   __syncthreads();
   for (int c = f; c <= l; ++c) {
@@ -346,16 +472,6 @@ __device__ void factor_block(const FactorArgs& a, int K, int slot, Lds& s, doubl
   }
 
   // ---------------- row panel: columns > l of block row K
-  np = load_preds(a, a.row_cnt, a.row_list, a.row_ovf, K, s.pred, s.misc);
-  if (np < 0) {
-    if (tid == 0) raise_error(a, kDevPredOverflow, K);
-    return;
-  }
-  const int mcc = build_candidates(s, s.candc, a.rp, a.ci, f, l, l + 1, np, a, false, 1, 0);
-  if (mcc < 0) {
-    if (tid == 0) raise_error(a, kDevCandOverflow, K);
-    return;
-  }
   for (int e = tid; e < mcc * q; e += blockDim.x) Rp[e] = 0.0;
   __syncthreads();
   for (int r = f; r <= l; ++r) {
@@ -365,8 +481,8 @@ __device__ void factor_block(const FactorArgs& a, int K, int slot, Lds& s, doubl
     }
   }
   __syncthreads();
-  for (int pi = 0; pi < np; ++pi) {
-    const int J = s.pred[pi];
+  for (int pi = 0; pi < npr; ++pi) {
+    const int J = s.rpred[pi];
     const int pJ = a.bstart[J + 1] - a.bstart[J];
     const int nRJ = a.nr[J], nCJ = a.nc[J];
     const int32_t* RJ = a.idx_heap + a.roff[J];
@@ -469,7 +585,7 @@ __device__ void factor_block(const FactorArgs& a, int K, int slot, Lds& s, doubl
     if (ok) break;
     if (attempt == 3) {
       if (tid == 0) raise_error(a, kDevSingular, K);
-      return;
+      return false;
     }
     for (int j = tid; j < q; j += blockDim.x) perturb_column(sS, q, j, a);
     __syncthreads();
@@ -488,10 +604,9 @@ __device__ void factor_block(const FactorArgs& a, int K, int slot, Lds& s, doubl
   int* keep_c = s.hash + kCandCap;      // flags for cols 0..mcc-1
   const bool two = a.drop_norm == 1;
   for (int z = q + tid; z < mc; z += blockDim.x) {
-    double* row = Cp + (int64_t)z * q;
-    double v[kMaxWidth > 16 ? 16 : kMaxWidth];
+    const double* row = Cp + (int64_t)z * q;
+    double v[16];
     double nrm = 0.0;
-    // scaled row, q entries; computed in chunks of 16 to bound registers
     for (int c0 = 0; c0 < q; c0 += 16) {
       const int cn = min(16, q - c0);
       for (int c = 0; c < cn; ++c) v[c] = 0.0;
@@ -516,7 +631,6 @@ __device__ void factor_block(const FactorArgs& a, int K, int slot, Lds& s, doubl
     keep_c[z] = nrm > a.tau ? 1 : 0;
   }
   __syncthreads();
-  // compaction offsets: rows, then columns
   constexpr int kPer = kCandCap / kThreads;  // flags per thread
   int fr[kPer], fc[kPer];
   int sr = 0, sc = 0;
@@ -530,25 +644,64 @@ __device__ void factor_block(const FactorArgs& a, int K, int slot, Lds& s, doubl
   int mk = 0, nk = 0;
   const int pr = wg_exclusive_scan(sr, s.scan, &mk);
   const int pc = wg_exclusive_scan(sc, s.scan, &nk);
+  // distinct blocks of the kept rows (columns): a kept entry starts a new
+  // block when the previous kept entry lies in another block
+  int br = 0, bc = 0;
+  for (int k = 0; k < kPer; ++k) {
+    const int z = tid * kPer + k;
+    if (fr[k]) {
+      int y = z - 1;
+      while (y >= q && !keep_r[y]) --y;
+      br += y < q || a.blockOf[s.cand[y]] != a.blockOf[s.cand[z]];
+    }
+    if (fc[k]) {
+      int y = z - 1;
+      while (y >= 0 && !keep_c[y]) --y;
+      bc += y < 0 || a.blockOf[s.candc[y]] != a.blockOf[s.candc[z]];
+    }
+  }
+  int ntr = 0, ntc = 0;
+  const int pbr = wg_exclusive_scan(br, s.scan, &ntr);
+  const int pbc = wg_exclusive_scan(bc, s.scan, &ntc);
   if (tid == 0) {
+    const unsigned long long ni = (unsigned long long)(mk + nk + ntr + ntc);
     unsigned long long vo = atomicAdd(a.val_top, (unsigned long long)(mk + nk) * q);
-    unsigned long long io = atomicAdd(a.idx_top, (unsigned long long)(mk + nk));
+    unsigned long long io = atomicAdd(a.idx_top, ni);
     bool over = vo + (unsigned long long)(mk + nk) * q > (unsigned long long)a.val_cap ||
-                io + (unsigned long long)(mk + nk) > (unsigned long long)a.idx_cap;
+                io + ni > (unsigned long long)a.idx_cap;
     s.misc[16] = over ? 1 : 0;
     s.off[0] = (long long)vo;
     s.off[1] = (long long)io;
     if (over) raise_error(a, kDevHeapOverflow, K);
   }
   __syncthreads();
-  if (s.misc[16]) return;
+  if (s.misc[16]) return false;
   const int64_t vo = s.off[0];
   const int64_t io = s.off[1];
   double* Lout = a.val_heap + vo;
   double* Wout = Lout + (int64_t)mk * q;
   int32_t* Rout = a.idx_heap + io;
   int32_t* Cout = Rout + mk;
-  // write kept rows of L (recomputing the scaled row) and kept columns of W
+  int32_t* TRout = Cout + nk;
+  int32_t* TCout = TRout + ntr;
+  {
+    int posr = pbr, posc = pbc;
+    for (int k = 0; k < kPer; ++k) {
+      const int z = tid * kPer + k;
+      if (fr[k]) {
+        int y = z - 1;
+        while (y >= q && !keep_r[y]) --y;
+        const int B = a.blockOf[s.cand[z]];
+        if (y < q || a.blockOf[s.cand[y]] != B) TRout[posr++] = B;
+      }
+      if (fc[k]) {
+        int y = z - 1;
+        while (y >= 0 && !keep_c[y]) --y;
+        const int B = a.blockOf[s.candc[z]];
+        if (y < 0 || a.blockOf[s.candc[y]] != B) TCout[posc++] = B;
+      }
+    }
+  }
   {
     int pos = pr;
     for (int k = 0; k < kPer; ++k) {
@@ -579,6 +732,10 @@ __device__ void factor_block(const FactorArgs& a, int K, int slot, Lds& s, doubl
     a.nc[K] = nk;
     a.loff[K] = vo;
     a.woff[K] = vo + (int64_t)mk * q;
+    a.troff[K] = io + mk + nk;
+    a.ntr[K] = ntr;
+    a.tcoff[K] = io + mk + nk + ntr;
+    a.ntc[K] = ntc;
     atomicAdd(a.flops, (unsigned long long)flops);
     atomicAdd(a.upd_bytes, (unsigned long long)ubytes);
   }
@@ -587,23 +744,49 @@ __device__ void factor_block(const FactorArgs& a, int K, int slot, Lds& s, doubl
   // column panels of the blocks holding its columns of U.
   for (int t = tid; t < mk; t += blockDim.x) {
     const int b = a.blockOf[Rout[t]];
-    if (t == 0 || a.blockOf[Rout[t - 1]] != b) push_pred(a, a.row_cnt, a.row_list, a.row_ovf, b, K);
+    if (t == 0 || a.blockOf[Rout[t - 1]] != b)
+      push_checked(a, d, a.row_cnt, a.row_list, a.row_ovf, b, K);
   }
   for (int t = tid; t < nk; t += blockDim.x) {
     const int b = a.blockOf[Cout[t]];
-    if (t == 0 || a.blockOf[Cout[t - 1]] != b) push_pred(a, a.col_cnt, a.col_list, a.col_ovf, b, K);
+    if (t == 0 || a.blockOf[Cout[t - 1]] != b)
+      push_checked(a, d, a.col_cnt, a.col_list, a.col_ovf, b, K);
   }
+  // publish: every write of this block is visible before the retraction
+  __threadfence();
+  __syncthreads();
+  announce(d, s.ann, na, -1, K);
+  if (tid == 0) trace_at(d, K, 4, wall_clock64());
+  return true;
 }
 
-__global__ void __launch_bounds__(kThreads) factor_level_kernel(FactorArgs a) {
+// Worker: queue positions blockIdx.x, blockIdx.x + gridDim.x, ... (the
+// launch is cooperative: all workers are resident).  Position p holds the
+// p-th block to become ready; the workgroup waits until it is filled.
+__global__ void __launch_bounds__(kThreads) factor_worker_kernel(FactorArgs a, FlowArgs d) {
   __shared__ Lds s;
   extern __shared__ double s_dyn[];
-  for (int idx = a.begin + blockIdx.x; idx < a.end; idx += gridDim.x) {
-    // the whole workgroup leaves together once any block reported an error
-    if (threadIdx.x == 0) s.misc[31] = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    if (s.misc[31]) return;
-    factor_block(a, a.sched[idx], blockIdx.x, s, s_dyn);
+  const int slot = blockIdx.x;
+  for (int pos = blockIdx.x; pos < a.nb; pos += gridDim.x) {
+    const unsigned long long t0 = wall_clock64();
+    int K = -1;
+    while (true) {
+      K = __hip_atomic_load(&d.queue[pos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int stop = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                       wall_clock64() - t0 > d.wait_ticks;
+      if (__syncthreads_or(stop)) {
+        if (threadIdx.x == 0) raise_error(a, kDevSpin, pos);
+        return;
+      }
+      if (__syncthreads_and(K >= 0)) break;
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+    if (threadIdx.x == 0) {
+      trace_at(d, K, 1, wall_clock64());
+      trace_at(d, K, 7, (unsigned long long)blockIdx.x);
+    }
+    factor_block(a, d, K, slot, s, s_dyn);
     __syncthreads();
   }
 }
@@ -630,14 +813,11 @@ bilu_status factor_device(bilu_handle* h, double tau) {
   int32_t maxq = 0;
   for (int64_t b = 0; b < nb; ++b) maxq = std::max(maxq, bs[b + 1] - bs[b]);
   if (maxq > kMaxWidth) return fail(h, BILU_ERR_INVALID, "block wider than the kernel limit");
-  block_etree_levels(h, bs, h->sched, h->sched_ptr);
-  const int nlev = (int)h->sched_ptr.size() - 1;
-  h->sched_qmax.assign(nlev, 0);
-  for (int L = 0; L < nlev; ++L)
-    for (int i = h->sched_ptr[L]; i < h->sched_ptr[L + 1]; ++i) {
-      int K = h->sched[i];
-      h->sched_qmax[L] = std::max(h->sched_qmax[L], bs[K + 1] - bs[K]);
-    }
+  std::vector<int32_t> parent;
+  const int32_t height = block_etree(h, bs, parent);
+  std::vector<int32_t> nchild(nb, 0);
+  for (int64_t K = 0; K < nb; ++K)
+    if (parent[K] >= 0) nchild[parent[K]]++;
   h->doff_h.assign(nb + 1, 0);
   for (int64_t b = 0; b < nb; ++b) {
     int64_t q = bs[b + 1] - bs[b];
@@ -671,26 +851,79 @@ bilu_status factor_device(bilu_handle* h, double tau) {
   CK(h->d_ovf_next.alloc(ovf_cap));
   CK(h->d_status.alloc(8));
   CK(h->d_counters.alloc(4));
+  CK(h->d_parent.alloc(nb));
+  CK(h->d_nchild.alloc(nb));
+  CK(h->d_troff.alloc(nb));
+  CK(h->d_tcoff.alloc(nb));
+  CK(h->d_ntr.alloc(nb));
+  CK(h->d_ntc.alloc(nb));
+  {
+    // distinct blocks > K of the rows of A(:, K) and the columns of A(K, :)
+    std::vector<int32_t> bof(n);
+    for (int64_t b = 0; b < nb; ++b)
+      for (int32_t i = bs[b]; i < bs[b + 1]; ++i) bof[i] = (int32_t)b;
+    std::vector<int64_t> ptr(nb + 1, 0);
+    std::vector<int32_t> lst, tmp;
+    for (int64_t K = 0; K < nb; ++K) {
+      tmp.clear();
+      for (int32_t i = bs[K]; i < bs[K + 1]; ++i) {
+        for (int64_t m = h->pcp[i]; m < h->pcp[i + 1]; ++m)
+          if (bof[h->pri[m]] > K) tmp.push_back(bof[h->pri[m]]);
+        for (int64_t m = h->prp[i]; m < h->prp[i + 1]; ++m)
+          if (bof[h->pci[m]] > K) tmp.push_back(bof[h->pci[m]]);
+      }
+      std::sort(tmp.begin(), tmp.end());
+      tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+      lst.insert(lst.end(), tmp.begin(), tmp.end());
+      ptr[K + 1] = (int64_t)lst.size();
+    }
+    CK(h->d_ablk_ptr.alloc(nb + 1));
+    CK(h->d_ablk.alloc(std::max<size_t>(1, lst.size())));
+    CK(hipMemcpyAsync(h->d_ablk_ptr.p, ptr.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    if (!lst.empty())
+      CK(hipMemcpyAsync(h->d_ablk.p, lst.data(), lst.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    CK(hipStreamSynchronize(st));
+  }
+  CK(h->d_flow.alloc(5 * nb + 1));
+  // blocks without tree children are ready at the start: queue them in order
+  std::vector<int> init_queue(nb, -1), init_enq(nb, 0);
+  int nleaves = 0;
+  for (int64_t K = 0; K < nb; ++K)
+    if (nchild[K] == 0) {
+      init_queue[nleaves++] = (int)K;
+      init_enq[K] = 1;
+    }
   CK(hipMemcpyAsync(h->d_bstart.p, bs.data(), (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(h->d_doff.p, h->doff_h.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(h->d_parent.p, parent.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(h->d_nchild.p, nchild.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
   {
     dim3 blk(64, 4);
     fill_block_of<<<dim3((unsigned)((nb + 3) / 4)), blk, 0, st>>>(h->d_bstart.p, (int)nb, h->d_blockof.p);
   }
-  // heap sizes: values and indices of L and W
   int64_t val_cap = h->opt.heap_bytes ? (int64_t)(h->opt.heap_bytes / sizeof(double))
                                       : std::max<int64_t>(1 << 20, 4 * h->nnz);
   int64_t idx_cap = std::max<int64_t>(1 << 20, 2 * h->nnz);
-  // scratch: one slot per resident workgroup
-  int64_t widest_level = 1;
-  for (int L = 0; L < nlev; ++L)
-    widest_level = std::max<int64_t>(widest_level, h->sched_ptr[L + 1] - h->sched_ptr[L]);
-  const int64_t slots = std::min<int64_t>(2048, widest_level);
+  // workers: as many workgroups as can be resident at once (cooperative
+  // launch); each owns one scratch slot
+  const size_t dyn = maxq <= kLdsPivotWidth ? 2 * sizeof(double) * maxq * maxq : 0;
+  int dev = 0, cus = 0, per_cu = 0;
+  CK(hipGetDevice(&dev));
+  CK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, factor_worker_kernel, kThreads, dyn));
+  const int64_t workers = std::min<int64_t>(nb, std::max<int64_t>(1, (int64_t)cus * std::max(per_cu, 1)));
   const int64_t mq = std::max<int32_t>(maxq, 1);
   const int64_t slot_doubles = 2 * (int64_t)kCandCap * mq + 2 * mq * mq;
-  CK(h->d_scratch.alloc(slots * slot_doubles));
-  h->scratch_slots = slots;
+  if ((int64_t)h->d_scratch.n < workers * slot_doubles) CK(h->d_scratch.alloc(workers * slot_doubles));
+  h->scratch_slots = workers;
   h->slot_doubles = slot_doubles;
+  if (h->wait_ticks == 0) {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+      h->wait_ticks = (unsigned long long)(kWaitSeconds * 1e3 * khz);
+    else
+      h->wait_ticks = (unsigned long long)(kWaitSeconds * 1e8);
+  }
   auto t2 = clk::now();
   for (int attempt = 0; attempt < 4; ++attempt) {
     if ((int64_t)h->d_val_heap.n < val_cap) CK(h->d_val_heap.alloc(val_cap));
@@ -701,6 +934,10 @@ bilu_status factor_device(bilu_handle* h, double tau) {
     CK(hipMemsetAsync(h->d_row_ovf.p, 0xff, nb * sizeof(int32_t), st));
     CK(hipMemsetAsync(h->d_status.p, 0, 8 * sizeof(int), st));
     CK(hipMemsetAsync(h->d_counters.p, 0, 4 * sizeof(unsigned long long), st));
+    CK(hipMemsetAsync(h->d_flow.p, 0, 3 * nb * sizeof(int), st));
+    CK(hipMemcpyAsync(h->d_flow.p + 3 * nb, init_enq.data(), nb * sizeof(int), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->d_flow.p + 4 * nb, init_queue.data(), nb * sizeof(int), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->d_flow.p + 5 * nb, &nleaves, sizeof(int), hipMemcpyHostToDevice, st));
     FactorArgs a{};
     a.n = (int)n;
     a.nb = (int)nb;
@@ -729,35 +966,49 @@ bilu_status factor_device(bilu_handle* h, double tau) {
     a.scratch = h->d_scratch.p;
     a.slot_doubles = slot_doubles;
     a.sched = nullptr;
+    a.begin = 0;
+    a.end = (int)nb;
     a.err = h->d_status.p + 0;
     a.err_block = h->d_status.p + 1;
     a.n_perturbed = h->d_status.p + 2;
     a.flops = h->d_counters.p + 2;
     a.upd_bytes = h->d_counters.p + 3;
-    DevArray<int32_t> d_sched;
-    CK(d_sched.alloc(h->sched.size()));
-    CK(hipMemcpyAsync(d_sched.p, h->sched.data(), h->sched.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    a.sched = d_sched.p;
+    a.troff = h->d_troff.p;
+    a.ntr = h->d_ntr.p;
+    a.tcoff = h->d_tcoff.p;
+    a.ntc = h->d_ntc.p;
+    a.ablk_ptr = h->d_ablk_ptr.p;
+    a.ablk = h->d_ablk.p;
+    FlowArgs d{};
+    d.parent = h->d_parent.p;
+    d.nchild = h->d_nchild.p;
+    d.ready = h->d_flow.p;
+    d.pending = h->d_flow.p + nb;
+    d.started = h->d_flow.p + 2 * nb;
+    d.enq = h->d_flow.p + 3 * nb;
+    d.queue = h->d_flow.p + 4 * nb;
+    d.tail = h->d_flow.p + 5 * nb;
+    d.wait_ticks = h->wait_ticks;
+    d.trace = nullptr;
+    if (h->opt.collect_timing >= 2) {
+      CK(h->d_trace.alloc((size_t)nb * kTraceFields));
+      CK(hipMemsetAsync(h->d_trace.p, 0, (size_t)nb * kTraceFields * 8, st));
+      d.trace = h->d_trace.p;
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->opt.collect_timing) {
       e0 = h->ev_get();
       e1 = h->ev_get();
       if (e0) (void)hipEventRecord(e0, st);
     }
-    for (int L = 0; L < nlev; ++L) {
-      a.begin = h->sched_ptr[L];
-      a.end = h->sched_ptr[L + 1];
-      const int cnt = a.end - a.begin;
-      const int grid = (int)std::min<int64_t>(cnt, slots);
-      const int qm = h->sched_qmax[L];
-      const size_t dyn = qm <= kLdsPivotWidth ? 2 * sizeof(double) * qm * qm : 0;
-      factor_level_kernel<<<grid, kThreads, dyn, st>>>(a);
-    }
+    void* kargs[] = {&a, &d};
+    CK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(factor_worker_kernel),
+                                  dim3((unsigned)workers), dim3(kThreads), kargs, dyn, st));
     if (h->opt.collect_timing) {
       if (e1) (void)hipEventRecord(e1, st);
       h->ev_record(0, e0, e1);
     }
-    h->stats.n_factor_launches = nlev;
+    h->stats.n_factor_launches = 1;
     CK(hipGetLastError());
     int status[8];
     unsigned long long ctr[4];
@@ -774,15 +1025,22 @@ bilu_status factor_device(bilu_handle* h, double tau) {
                                    "predecessor list exceeds the per-block capacity",
                                    "factor heap exhausted", "predecessor overflow pool exhausted",
                                    "pivot block singular after perturbation",
-                                   "block wider than the kernel limit", "dependency wait timed out"};
-      std::string msg = std::string("factor kernel: ") + what[std::min(status[0], 7)] +
+                                   "block wider than the kernel limit", "dependency wait timed out",
+                                   "dependency protocol violated", "no free scratch slot",
+                                   "announcement set exceeds the per-block capacity"};
+      // kDevSpin reports the queue position that was never filled
+      std::string msg = std::string("factor kernel: ") + what[std::min(status[0], 10)] +
                         " (block " + std::to_string(status[1]) + ")";
-      return fail(h, status[0] == kDevSingular ? BILU_ERR_SINGULAR : BILU_ERR_NO_MEMORY, msg);
+      return fail(h, status[0] == kDevSingular ? BILU_ERR_SINGULAR
+                     : (status[0] == kDevSpin || status[0] == kDevProtocol || status[0] == kDevSlot)
+                         ? BILU_ERR_DEVICE
+                         : BILU_ERR_NO_MEMORY,
+                  msg);
     }
     h->stats.perturbed_blocks = status[2];
     h->stats.flops_update = (double)ctr[2];
     h->stats.bytes_factor = (double)ctr[3];  // completed with A and output bytes by the caller
-    h->stats.factor_levels = nlev;
+    h->stats.factor_levels = height;
     auto t3 = clk::now();
     h->stats.t_factor_device = std::chrono::duration<double>(t3 - t2).count();
     h->stats.nblocks_initial = nb;

@@ -30,6 +30,9 @@ enum DevErr : int {
   kDevSingular = 5,
   kDevWidth = 6,
   kDevSpin = 7,
+  kDevProtocol = 8,
+  kDevSlot = 9,
+  kDevAnnOverflow = 10,
 };
 
 template <class T>
@@ -85,7 +88,37 @@ struct FactorArgs {
   int* err; int* err_block; int* n_perturbed;
   unsigned long long* flops;
   unsigned long long* upd_bytes;  // bytes of L_J rows + W_J columns read by updates
+  // block-level patterns: distinct blocks of R_K (tr) and of C_K (tc) in the
+  // idx heap, and the static distinct blocks > K of A's pattern of K
+  int64_t* troff; int32_t* ntr;
+  int64_t* tcoff; int32_t* ntc;
+  const int64_t* ablk_ptr; const int32_t* ablk;
 };
+
+constexpr int kAnnCap = 2048;      // blocks one block may announce itself to
+
+// Dependency bookkeeping of the factor kernel.
+struct FlowArgs {
+  const int32_t* parent;   // elimination-tree parent, -1 for roots
+  const int32_t* nchild;
+  int* ready;              // children that have announced
+  int* pending;            // announced, unfinished possible updaters
+  int* started;            // numeric phase begun (checks the protocol)
+  int* enq;                // block pushed to the ready queue
+  int* queue;              // ready queue, filled in readiness order (-1 = empty)
+  int* tail;               // next free queue position
+  unsigned long long wait_ticks;
+  // optional per-block trace (kTraceFields per block, wall-clock ticks):
+  // pushed, popped, announced, candidates built, done, pusher block,
+  // pusher event (0 child signal, 1 retraction), worker
+  unsigned long long* trace;
+};
+
+constexpr int kTraceFields = 8;
+
+// Bound of one dependency wait in seconds: a wait that exceeds it reports
+// an error instead of hanging.
+constexpr double kWaitSeconds = 10.0;
 
 // Device view of a block factor (initial or aggregated), used by the apply
 // and by export.  Per block K: rows R_K (nr, at idx+roff), columns C_K
@@ -134,8 +167,12 @@ struct bilu_handle {
 
   // ---- factor: partition + schedule (host)
   std::vector<int32_t> bstart0;       // initial partition
-  std::vector<int32_t> sched, sched_ptr;  // blocks by level
-  std::vector<int32_t> sched_qmax;    // widest block per level
+  bilu::DevArray<int32_t> d_parent, d_nchild;  // block elimination tree
+  bilu::DevArray<int64_t> d_troff, d_tcoff, d_ablk_ptr;
+  bilu::DevArray<unsigned long long> d_trace;  // collect_timing == 2
+  bilu::DevArray<int32_t> d_ntr, d_ntc, d_ablk;
+  bilu::DevArray<int> d_flow;        // ready, pending, started, enqueued, queue, tail
+  unsigned long long wait_ticks = 0; // bound of one dependency wait (wall-clock ticks)
   std::vector<int64_t> doff_h;
   // ---- factor storage (device)
   bilu::DevArray<int32_t> d_bstart, d_blockof;
@@ -201,8 +238,8 @@ bilu_status hip_check(bilu_handle* h, hipError_t e, const char* what);
 bilu_status analyze_host(bilu_handle* h, int64_t n, const int64_t* rowptr,
                          const int32_t* colind, const double* val);
 int64_t ilu1t_partition(const bilu_handle* h, double tau, std::vector<int32_t>& bstart);
-void block_etree_levels(const bilu_handle* h, const std::vector<int32_t>& bstart,
-                        std::vector<int32_t>& sched, std::vector<int32_t>& sched_ptr);
+int32_t block_etree(const bilu_handle* h, const std::vector<int32_t>& bstart,
+                    std::vector<int32_t>& parent);
 
 // factor.hip
 bilu_status factor_device(bilu_handle* h, double tau);
