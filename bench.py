@@ -146,7 +146,7 @@ def main():
         "factor": {"nblocks": st["nblocks"], "nblocks_initial": st["nblocks_initial"],
                    "max_width": st["max_width"], "avg_width": round(st["avg_width"], 3),
                    "fill": round((st["nnz_l"] + st["nnz_w"] + st["nnz_d"]) / a.nnz, 4),
-                   "tree_levels": st["factor_levels"],
+                   "dependency_depth": st["factor_levels"],
                    "apply_levels": [st["apply_levels_fwd"], st["apply_levels_bwd"]]},
     }
     if not args.no_cpu_baseline:

@@ -91,7 +91,7 @@ typedef struct {
   double avg_width, std_width;
   int64_t nnz_l, nnz_w, nnz_d;/* stored factor entries                               */
   int64_t merges, perturbed_blocks;
-  int64_t factor_levels;      /* dependency levels of the factorization schedule     */
+  int64_t factor_levels;      /* longest chain of possible updaters in the sweep     */
   int64_t apply_levels_fwd, apply_levels_bwd;
   double flops_update;        /* counted Schur-update flops (2 m p q per product)    */
   double bytes_apply;         /* algorithmic bytes of one preconditioner apply        */
@@ -188,9 +188,9 @@ void bilu_free_factors(bilu_factors_host* f);
 
 /* Per-block trace of the last factor kernel (collect_timing = 2): 8 values
  * per initial block in block order, device wall-clock ticks: pushed to the
- * ready queue, taken by a worker, announced, candidates built, done; then
- * the block whose event made it ready, that event (0 tree child signalled,
- * 1 update retracted) and the worker.  out may be NULL to query
+ * ready queue, taken by a worker, its possible-update set built, candidates
+ * built, done; then the block whose retraction made it ready (0 for blocks
+ * ready at the start), the count that retraction removed, and the worker.  out may be NULL to query
  * *nrecords; capacity counts uint64 values.  BILU_ERR_STATE without a
  * trace. */
 bilu_status bilu_export_trace(const bilu_handle* h, uint64_t* out, int64_t capacity,

@@ -617,55 +617,4 @@ int64_t ilu1t_partition(const bilu_handle* h, double tau, std::vector<int32_t>& 
   return (int64_t)bstart.size() - 1;
 }
 
-// ---------------------------------------------------------------------------
-// Block elimination tree of the symmetrized block graph (Liu's algorithm
-// with path compression).  Exact block LU couples a block only to its
-// ancestors, and the incomplete factor's pattern lies inside the exact one,
-// so a block can be updated only by its descendants.  Returns the tree
-// height; parent[K] = -1 for roots.
-// ---------------------------------------------------------------------------
-int32_t block_etree(const bilu_handle* h, const std::vector<int32_t>& bstart,
-                    std::vector<int32_t>& parent) {
-  const int64_t n = h->n;
-  const int32_t nb = (int32_t)bstart.size() - 1;
-  std::vector<int32_t> bof(n);
-  for (int32_t b = 0; b < nb; ++b)
-    for (int32_t i = bstart[b]; i < bstart[b + 1]; ++i) bof[i] = b;
-  parent.assign(nb, -1);
-  std::vector<int32_t> anc(nb, -1);
-  std::vector<int32_t> nbrs;
-  for (int32_t K = 0; K < nb; ++K) {
-    nbrs.clear();
-    for (int32_t i = bstart[K]; i < bstart[K + 1]; ++i) {
-      for (int64_t m = h->prp[i]; m < h->prp[i + 1]; ++m) {
-        int32_t J = bof[h->pci[m]];
-        if (J < K) nbrs.push_back(J);
-      }
-      for (int64_t m = h->pcp[i]; m < h->pcp[i + 1]; ++m) {
-        int32_t J = bof[h->pri[m]];
-        if (J < K) nbrs.push_back(J);
-      }
-    }
-    for (int32_t J : nbrs) {
-      int32_t r = J;
-      while (anc[r] != -1 && anc[r] != K) {
-        int32_t nx = anc[r];
-        anc[r] = K;
-        r = nx;
-      }
-      if (anc[r] == -1) {
-        anc[r] = K;
-        parent[r] = K;
-      }
-    }
-  }
-  std::vector<int32_t> height(nb, 0);
-  int32_t hmax = 0;
-  for (int32_t K = 0; K < nb; ++K) {
-    if (parent[K] >= 0) height[parent[K]] = std::max(height[parent[K]], height[K] + 1);
-    hmax = std::max(hmax, height[K]);
-  }
-  return hmax + 1;
-}
-
 }  // namespace bilu

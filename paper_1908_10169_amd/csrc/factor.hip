@@ -15,18 +15,21 @@
 //      their norm is <= tau, the kept ones compacted into the factor heap
 //      (L scaled, W = R unscaled), and K is appended to the predecessor lists
 //      of the blocks it will update.
-// Scheduling: a block may only be updated by its descendants in the block
-// elimination tree.  After computing its candidate rows/columns a block K
-// announces itself to every block they fall into (it can update no other)
-// and signals its tree parent; when done it appends itself to the lists of
-// the blocks it does update and retracts the announcements.  A block is
-// ready once all its tree children have signalled (every possible updater
-// has announced) and no announcement to it is outstanding: its lists are
-// then complete.  The event that makes a block ready pushes it to a queue;
-// a fixed set of co-resident workgroups takes queue positions in turn, so
-// ready blocks are processed in readiness order and the critical path is
-// the longest chain of real updates and announcements, not the tree height.
-// Queue waits are bounded in wall-clock time and end on any reported error.
+// Scheduling.  J can update K > J only if K holds one of J's candidate rows
+// or columns, i.e. (a) A couples J and K, or (b) a predecessor I of J has
+// stored rows (columns) in K and J among its stored column (row) blocks.
+// pending[K] counts these possible updaters with multiplicity: (a) is set
+// on the host; (b) is added by I when it finishes, for every pair (J, K)
+// its stored patterns create, before I retracts its own counts; J retracts
+// all of its counts once its factor is written and it has appended itself
+// to the lists of the blocks it really updates.  Every possible updater of
+// K is therefore counted before its own cause is retracted, so pending[K]
+// reaches zero once, when K's predecessor lists are complete.  The
+// retraction that reaches zero pushes K to a queue; a fixed set of
+// co-resident workgroups takes queue positions in turn, so blocks run in
+// readiness order and the critical path is the longest chain of possible
+// updates after dropping, not the elimination-tree height.  Queue waits
+// are bounded in wall-clock time and end on any reported error.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -60,6 +63,21 @@ __device__ __forceinline__ bool hash_insert(int* table, int key, int* count) {
     h = (h + 1) & (kHashSlots - 1);
   }
   return false;
+}
+
+// As hash_insert, returning the slot of the key, or -1 when the table is full.
+__device__ __forceinline__ int hash_insert_at(int* table, int key, int* count) {
+  unsigned h = hash_slot(key);
+  for (int probe = 0; probe < kHashSlots; ++probe) {
+    int old = atomicCAS(&table[h], -1, key);
+    if (old == -1) {
+      atomicAdd(count, 1);
+      return (int)h;
+    }
+    if (old == key) return (int)h;
+    h = (h + 1) & (kHashSlots - 1);
+  }
+  return -1;
 }
 
 // Read the predecessor list of a block (inline part + overflow chain) into
@@ -220,7 +238,8 @@ struct Lds {
   int candc[kCandCap];      // sorted candidate columns
   int pred[kPredCap];       // predecessors of the column panel
   int rpred[kPredCap];      // predecessors of the row panel
-  int ann[kAnnCap];         // blocks this block announced itself to
+  int ann[kAnnCap];         // blocks this block may update
+  int annc[kAnnCap];        // ... and the count it retracts from each
   int misc[32];
   int scan[20];
   int ip[kMaxWidth];
@@ -228,6 +247,9 @@ struct Lds {
   double smax;
   long long off[2];
 };
+// updater_set counts per hash slot in cand[] followed by candc[]
+static_assert(2 * kCandCap >= kHashSlots, "count slots");
+static_assert(offsetof(Lds, candc) == offsetof(Lds, cand) + sizeof(int) * kCandCap, "layout");
 
 // Build the sorted set of candidate indices into out[] from the structural
 // entries of A (lists ptr/idx over [lo, hi], keeping idx >= min_keep) plus
@@ -293,40 +315,40 @@ __device__ __forceinline__ void push_ready(const FlowArgs& d, int B, int by, int
   }
 }
 
-// Ready test after changing one of the two counters of B (the other is read
-// after a full fence, so of two concurrent last events at least one sees
-// both: the enqueued flag keeps the push unique).
-__device__ __forceinline__ void check_ready(const FlowArgs& d, int B, int by, int why) {
-  __threadfence();
-  const int r = __hip_atomic_load(&d.ready[B], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const int p = __hip_atomic_load(&d.pending[B], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (r == d.nchild[B] && p == 0) push_ready(d, B, by, why);
-}
-
-// The blocks K can update: the distinct blocks of its candidate rows and
-// columns, i.e. the static blocks of A's pattern of K plus the row blocks
-// of its column-panel predecessors and the column blocks of its row-panel
-// predecessors.  Deduplicated in the LDS hash into s.ann; returns the count
-// or -1 on overflow.
-__device__ int announce_set(const FactorArgs& a, int K, Lds& s, int np, int npr) {
-  for (int t = threadIdx.x; t < kHashSlots; t += blockDim.x) s.hash[t] = -1;
+// The blocks K may update, each with the count K holds in its pending
+// counter: 1 for each distinct block > K of A's pattern of K, plus 1 for
+// every (column predecessor J, row block B > K of J) and (row predecessor J,
+// column block B > K of J).  Keys go to s.ann, counts to s.annc; returns the
+// number of keys or -1 on overflow.
+__device__ int updater_set(const FactorArgs& a, int K, Lds& s, int np, int npr) {
+  int* cnt = s.cand;  // per hash slot, over cand[] and candc[] (built later)
+  for (int t = threadIdx.x; t < kHashSlots; t += blockDim.x) {
+    s.hash[t] = -1;
+    cnt[t] = 0;
+  }
   if (threadIdx.x == 0) {
     s.misc[4] = 0;
     s.misc[5] = 0;
   }
   __syncthreads();
-  for (int64_t e = a.ablk_ptr[K] + threadIdx.x; e < a.ablk_ptr[K + 1]; e += blockDim.x)
-    if (!hash_insert(s.hash, a.ablk[e], &s.misc[4])) s.misc[5] = 1;
+  for (int64_t e = a.ablk_ptr[K] + threadIdx.x; e < a.ablk_ptr[K + 1]; e += blockDim.x) {
+    const int h = hash_insert_at(s.hash, a.ablk[e], &s.misc[4]);
+    if (h < 0) s.misc[5] = 1;
+    else atomicAdd(&cnt[h], 1);
+  }
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   for (int pi = wid; pi < np + npr; pi += nw) {
     const bool col = pi < np;
     const int J = col ? s.pred[pi] : s.rpred[pi - np];
-    const int cnt = col ? a.ntr[J] : a.ntc[J];
+    const int n = col ? a.ntr[J] : a.ntc[J];
     const int32_t* lst = a.idx_heap + (col ? a.troff[J] : a.tcoff[J]);
-    for (int t = lane; t < cnt; t += 64) {
+    for (int t = lane; t < n; t += 64) {
       const int B = lst[t];
-      if (B > K)
-        if (!hash_insert(s.hash, B, &s.misc[4])) s.misc[5] = 1;
+      if (B > K) {
+        const int h = hash_insert_at(s.hash, B, &s.misc[4]);
+        if (h < 0) s.misc[5] = 1;
+        else atomicAdd(&cnt[h], 1);
+      }
     }
   }
   __syncthreads();
@@ -336,18 +358,43 @@ __device__ int announce_set(const FactorArgs& a, int K, Lds& s, int np, int npr)
   __syncthreads();
   for (int t = threadIdx.x; t < kHashSlots; t += blockDim.x) {
     const int k = s.hash[t];
-    if (k >= 0) s.ann[atomicAdd(&s.misc[6], 1)] = k;
+    if (k >= 0) {
+      const int o = atomicAdd(&s.misc[6], 1);
+      s.ann[o] = k;
+      s.annc[o] = cnt[t];
+    }
   }
   __syncthreads();
   return m;
 }
 
-// Add delta (+1 announce, -1 retract) to the pending count of the blocks in
-// ann; a retraction that brings a count to zero checks readiness.
-__device__ void announce(const FlowArgs& d, const int* ann, int m, int delta, int K) {
+// Retract K's counts; the retraction that brings a count to zero makes that
+// block ready.  Every write of K is visible before this is called.
+__device__ void retract(const FactorArgs& a, const FlowArgs& d, const Lds& s, int m, int K) {
+  const int dK = __hip_atomic_load(&d.depth[K], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
   for (int t = threadIdx.x; t < m; t += blockDim.x) {
-    const int B = ann[t];
-    if (atomicAdd(&d.pending[B], delta) + delta == 0 && delta < 0) check_ready(d, B, K, 1);
+    const int B = s.ann[t], c = s.annc[t];
+    atomicMax(&d.depth[B], dK);
+    const int old = atomicSub(&d.pending[B], c);
+    if (old < c) raise_error(a, kDevProtocol, K);
+    if (old == c) {
+      __threadfence();
+      push_ready(d, B, K, c);
+    }
+  }
+}
+
+// Count, for every block B of K's stored rows (columns), the blocks J < B
+// of K's stored columns (rows): each such J becomes a possible updater of
+// B once K is done.  B's own count from K is still held, so B cannot have
+// started.
+__device__ void add_successor_counts(const FactorArgs& a, const FlowArgs& d, const int32_t* tr,
+                                     int ntr, const int32_t* tc, int ntc, int K) {
+  for (int t = threadIdx.x; t < ntr + ntc; t += blockDim.x) {
+    const bool row = t < ntr;
+    const int B = row ? tr[t] : tc[t - ntr];
+    const int c = row ? lower_bound(tc, ntc, B) : lower_bound(tr, ntr, B);
+    if (c > 0 && atomicAdd(&d.pending[B], c) <= 0) raise_error(a, kDevProtocol, K);
   }
 }
 
@@ -385,23 +432,16 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
     if (tid == 0) raise_error(a, kDevPredOverflow, K);
     return false;
   }
-  const int na = announce_set(a, K, s, np, npr);
+  if (tid == 0) {
+    __hip_atomic_store(&d.started[K], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    atomicMax(d.max_depth, __hip_atomic_load(&d.depth[K], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1);
+  }
+  const int na = updater_set(a, K, s, np, npr);
   if (na < 0) {
     if (tid == 0) raise_error(a, kDevAnnOverflow, K);
     return false;
   }
-  announce(d, s.ann, na, +1, K);
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    __hip_atomic_store(&d.started[K], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int P = d.parent[K];
-    if (P >= 0) {
-      atomicAdd(&d.ready[P], 1);
-      check_ready(d, P, K, 0);
-    }
-    trace_at(d, K, 2, wall_clock64());
-  }
+  if (tid == 0) trace_at(d, K, 2, wall_clock64());
   const int mc = build_candidates(s, s.cand, a.cp, a.ri, f, l, l + 1, s.pred, np, a, true, f, l);
   if (mc < 0) {
     if (tid == 0) raise_error(a, kDevCandOverflow, K);
@@ -752,10 +792,13 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
     if (t == 0 || a.blockOf[Cout[t - 1]] != b)
       push_checked(a, d, a.col_cnt, a.col_list, a.col_ovf, b, K);
   }
-  // publish: every write of this block is visible before the retraction
+  __syncthreads();
+  add_successor_counts(a, d, TRout, ntr, TCout, ntc, K);
+  // publish: every write and count of this block is visible before the
+  // retraction
   __threadfence();
   __syncthreads();
-  announce(d, s.ann, na, -1, K);
+  retract(a, d, s, na, K);
   if (tid == 0) trace_at(d, K, 4, wall_clock64());
   return true;
 }
@@ -813,11 +856,6 @@ bilu_status factor_device(bilu_handle* h, double tau) {
   int32_t maxq = 0;
   for (int64_t b = 0; b < nb; ++b) maxq = std::max(maxq, bs[b + 1] - bs[b]);
   if (maxq > kMaxWidth) return fail(h, BILU_ERR_INVALID, "block wider than the kernel limit");
-  std::vector<int32_t> parent;
-  const int32_t height = block_etree(h, bs, parent);
-  std::vector<int32_t> nchild(nb, 0);
-  for (int64_t K = 0; K < nb; ++K)
-    if (parent[K] >= 0) nchild[parent[K]]++;
   h->doff_h.assign(nb + 1, 0);
   for (int64_t b = 0; b < nb; ++b) {
     int64_t q = bs[b + 1] - bs[b];
@@ -851,14 +889,14 @@ bilu_status factor_device(bilu_handle* h, double tau) {
   CK(h->d_ovf_next.alloc(ovf_cap));
   CK(h->d_status.alloc(8));
   CK(h->d_counters.alloc(4));
-  CK(h->d_parent.alloc(nb));
-  CK(h->d_nchild.alloc(nb));
   CK(h->d_troff.alloc(nb));
   CK(h->d_tcoff.alloc(nb));
   CK(h->d_ntr.alloc(nb));
   CK(h->d_ntc.alloc(nb));
+  // static possible updaters: J counts once in pending[K] for every K in the
+  // distinct blocks > J of the rows of A(:, J) and the columns of A(J, :)
+  std::vector<int> pending0(nb, 0);
   {
-    // distinct blocks > K of the rows of A(:, K) and the columns of A(K, :)
     std::vector<int32_t> bof(n);
     for (int64_t b = 0; b < nb; ++b)
       for (int32_t i = bs[b]; i < bs[b + 1]; ++i) bof[i] = (int32_t)b;
@@ -876,6 +914,7 @@ bilu_status factor_device(bilu_handle* h, double tau) {
       tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
       lst.insert(lst.end(), tmp.begin(), tmp.end());
       ptr[K + 1] = (int64_t)lst.size();
+      for (int32_t B : tmp) pending0[B]++;
     }
     CK(h->d_ablk_ptr.alloc(nb + 1));
     CK(h->d_ablk.alloc(std::max<size_t>(1, lst.size())));
@@ -884,19 +923,17 @@ bilu_status factor_device(bilu_handle* h, double tau) {
       CK(hipMemcpyAsync(h->d_ablk.p, lst.data(), lst.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
     CK(hipStreamSynchronize(st));
   }
-  CK(h->d_flow.alloc(5 * nb + 1));
-  // blocks without tree children are ready at the start: queue them in order
+  CK(h->d_flow.alloc(5 * nb + 2));
+  // blocks that nothing can update are ready at the start: queue them in order
   std::vector<int> init_queue(nb, -1), init_enq(nb, 0);
   int nleaves = 0;
   for (int64_t K = 0; K < nb; ++K)
-    if (nchild[K] == 0) {
+    if (pending0[K] == 0) {
       init_queue[nleaves++] = (int)K;
       init_enq[K] = 1;
     }
   CK(hipMemcpyAsync(h->d_bstart.p, bs.data(), (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(h->d_doff.p, h->doff_h.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(h->d_parent.p, parent.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(h->d_nchild.p, nchild.data(), nb * sizeof(int32_t), hipMemcpyHostToDevice, st));
   {
     dim3 blk(64, 4);
     fill_block_of<<<dim3((unsigned)((nb + 3) / 4)), blk, 0, st>>>(h->d_bstart.p, (int)nb, h->d_blockof.p);
@@ -934,10 +971,13 @@ bilu_status factor_device(bilu_handle* h, double tau) {
     CK(hipMemsetAsync(h->d_row_ovf.p, 0xff, nb * sizeof(int32_t), st));
     CK(hipMemsetAsync(h->d_status.p, 0, 8 * sizeof(int), st));
     CK(hipMemsetAsync(h->d_counters.p, 0, 4 * sizeof(unsigned long long), st));
-    CK(hipMemsetAsync(h->d_flow.p, 0, 3 * nb * sizeof(int), st));
-    CK(hipMemcpyAsync(h->d_flow.p + 3 * nb, init_enq.data(), nb * sizeof(int), hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->d_flow.p, pending0.data(), nb * sizeof(int), hipMemcpyHostToDevice, st));
+    CK(hipMemsetAsync(h->d_flow.p + nb, 0, nb * sizeof(int), st));
+    CK(hipMemcpyAsync(h->d_flow.p + 2 * nb, init_enq.data(), nb * sizeof(int), hipMemcpyHostToDevice, st));
+    CK(hipMemsetAsync(h->d_flow.p + 3 * nb, 0, nb * sizeof(int), st));
     CK(hipMemcpyAsync(h->d_flow.p + 4 * nb, init_queue.data(), nb * sizeof(int), hipMemcpyHostToDevice, st));
-    CK(hipMemcpyAsync(h->d_flow.p + 5 * nb, &nleaves, sizeof(int), hipMemcpyHostToDevice, st));
+    const int tail_depth[2] = {nleaves, 0};
+    CK(hipMemcpyAsync(h->d_flow.p + 5 * nb, tail_depth, sizeof(tail_depth), hipMemcpyHostToDevice, st));
     FactorArgs a{};
     a.n = (int)n;
     a.nb = (int)nb;
@@ -980,14 +1020,13 @@ bilu_status factor_device(bilu_handle* h, double tau) {
     a.ablk_ptr = h->d_ablk_ptr.p;
     a.ablk = h->d_ablk.p;
     FlowArgs d{};
-    d.parent = h->d_parent.p;
-    d.nchild = h->d_nchild.p;
-    d.ready = h->d_flow.p;
-    d.pending = h->d_flow.p + nb;
-    d.started = h->d_flow.p + 2 * nb;
-    d.enq = h->d_flow.p + 3 * nb;
+    d.pending = h->d_flow.p;
+    d.started = h->d_flow.p + nb;
+    d.enq = h->d_flow.p + 2 * nb;
+    d.depth = h->d_flow.p + 3 * nb;
     d.queue = h->d_flow.p + 4 * nb;
     d.tail = h->d_flow.p + 5 * nb;
+    d.max_depth = h->d_flow.p + 5 * nb + 1;
     d.wait_ticks = h->wait_ticks;
     d.trace = nullptr;
     if (h->opt.collect_timing >= 2) {
@@ -1014,6 +1053,8 @@ bilu_status factor_device(bilu_handle* h, double tau) {
     unsigned long long ctr[4];
     CK(hipMemcpyAsync(status, h->d_status.p, sizeof(status), hipMemcpyDeviceToHost, st));
     CK(hipMemcpyAsync(ctr, h->d_counters.p, sizeof(ctr), hipMemcpyDeviceToHost, st));
+    int max_depth = 0;
+    CK(hipMemcpyAsync(&max_depth, h->d_flow.p + 5 * nb + 1, sizeof(int), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
     if (status[0] == kDevHeapOverflow) {
       val_cap = std::max<int64_t>(val_cap * 2, (int64_t)ctr[1] * 2);
@@ -1040,7 +1081,7 @@ bilu_status factor_device(bilu_handle* h, double tau) {
     h->stats.perturbed_blocks = status[2];
     h->stats.flops_update = (double)ctr[2];
     h->stats.bytes_factor = (double)ctr[3];  // completed with A and output bytes by the caller
-    h->stats.factor_levels = height;
+    h->stats.factor_levels = max_depth;
     auto t3 = clk::now();
     h->stats.t_factor_device = std::chrono::duration<double>(t3 - t2).count();
     h->stats.nblocks_initial = nb;

@@ -95,22 +95,21 @@ struct FactorArgs {
   const int64_t* ablk_ptr; const int32_t* ablk;
 };
 
-constexpr int kAnnCap = 2048;      // blocks one block may announce itself to
+constexpr int kAnnCap = 2048;      // distinct blocks one block may still update
 
 // Dependency bookkeeping of the factor kernel.
 struct FlowArgs {
-  const int32_t* parent;   // elimination-tree parent, -1 for roots
-  const int32_t* nchild;
-  int* ready;              // children that have announced
-  int* pending;            // announced, unfinished possible updaters
+  int* pending;            // unfinished possible updaters (with multiplicity)
+  int* depth;              // longest chain of possible updaters ending at the block
+  int* max_depth;
   int* started;            // numeric phase begun (checks the protocol)
   int* enq;                // block pushed to the ready queue
   int* queue;              // ready queue, filled in readiness order (-1 = empty)
   int* tail;               // next free queue position
   unsigned long long wait_ticks;
   // optional per-block trace (kTraceFields per block, wall-clock ticks):
-  // pushed, popped, announced, candidates built, done, pusher block,
-  // pusher event (0 child signal, 1 retraction), worker
+  // pushed, popped, updater set built, candidates built, done, the block
+  // whose retraction made it ready, the count it retracted, worker
   unsigned long long* trace;
 };
 
@@ -167,11 +166,10 @@ struct bilu_handle {
 
   // ---- factor: partition + schedule (host)
   std::vector<int32_t> bstart0;       // initial partition
-  bilu::DevArray<int32_t> d_parent, d_nchild;  // block elimination tree
   bilu::DevArray<int64_t> d_troff, d_tcoff, d_ablk_ptr;
   bilu::DevArray<unsigned long long> d_trace;  // collect_timing == 2
   bilu::DevArray<int32_t> d_ntr, d_ntc, d_ablk;
-  bilu::DevArray<int> d_flow;        // ready, pending, started, enqueued, queue, tail
+  bilu::DevArray<int> d_flow;        // pending, started, enqueued, depth, queue, tail, max depth
   unsigned long long wait_ticks = 0; // bound of one dependency wait (wall-clock ticks)
   std::vector<int64_t> doff_h;
   // ---- factor storage (device)
@@ -238,8 +236,6 @@ bilu_status hip_check(bilu_handle* h, hipError_t e, const char* what);
 bilu_status analyze_host(bilu_handle* h, int64_t n, const int64_t* rowptr,
                          const int32_t* colind, const double* val);
 int64_t ilu1t_partition(const bilu_handle* h, double tau, std::vector<int32_t>& bstart);
-int32_t block_etree(const bilu_handle* h, const std::vector<int32_t>& bstart,
-                    std::vector<int32_t>& parent);
 
 // factor.hip
 bilu_status factor_device(bilu_handle* h, double tau);
