@@ -101,6 +101,11 @@ typedef struct {
   double dev_ms_factor, dev_ms_apply, dev_ms_spmv;
   int64_t n_factor_launches, n_apply, n_spmv;
   double bytes_factor;        /* algorithmic bytes of the factor kernels             */
+  /* host wall time of the phases of the last bilu_factor (seconds):
+   * [0] ILU(1,tau) sets, [1] ILU(1,tau) block growth, [2] factor launch
+   * preparation, [3] factor kernel to completion, [4] aggregation, [5] apply
+   * plan, [6] final statistics, [7] unused */
+  double t_phase[8];
 } bilu_stats;
 
 /* Library-allocated host copy of the factors (for checking), final blocks. */
@@ -186,11 +191,15 @@ bilu_status bilu_get_stats(const bilu_handle* h, bilu_stats* st);
 bilu_status bilu_export_factors(const bilu_handle* h, bilu_factors_host* out);
 void bilu_free_factors(bilu_factors_host* f);
 
-/* Per-block trace of the last factor kernel (collect_timing = 2): 8 values
+/* Per-block trace of the last factor kernel (collect_timing = 2): 20 values
  * per initial block in block order, device wall-clock ticks: pushed to the
  * ready queue, taken by a worker, its possible-update set built, candidates
  * built, done; then the block whose retraction made it ready (0 for blocks
- * ready at the start), the count that retraction removed, and the worker.  out may be NULL to query
+ * ready at the start), the count that retraction removed, and the worker;
+ * fields 8..15 time the end of the column panel, row panel, pivot, drop
+ * norms, heap allocation, factor writes, list pushes and successor counts;
+ * fields 16..19 are the numbers of column and row predecessors and of
+ * candidate rows and columns (20 values per block).  out may be NULL to query
  * *nrecords; capacity counts uint64 values.  BILU_ERR_STATE without a
  * trace. */
 bilu_status bilu_export_trace(const bilu_handle* h, uint64_t* out, int64_t capacity,

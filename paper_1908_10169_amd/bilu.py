@@ -58,7 +58,7 @@ class Stats(C.Structure):
         ("t_aggregate", C.c_double), ("t_factor", C.c_double),
         ("dev_ms_factor", C.c_double), ("dev_ms_apply", C.c_double), ("dev_ms_spmv", C.c_double),
         ("n_factor_launches", C.c_int64), ("n_apply", C.c_int64), ("n_spmv", C.c_int64),
-        ("bytes_factor", C.c_double),
+        ("bytes_factor", C.c_double), ("t_phase", C.c_double * 8),
     ]
 
 
@@ -244,14 +244,14 @@ class Bilu:
         return self._check(self._lib.bilu_apply(self._h, x.data_ptr(), y.data_ptr()), "bilu_apply")
 
     def trace(self):
-        """Per-block factor trace (collect_timing=2): (records x 8 uint64, ticks/s)."""
+        """Per-block factor trace (collect_timing=2): (records x 20 uint64, ticks/s)."""
         m, tps = C.c_int64(), C.c_double()
         self._check(self._lib.bilu_export_trace(self._h, None, 0, C.byref(m), C.byref(tps)),
                     "bilu_export_trace")
-        out = np.zeros(m.value * 8, dtype=np.uint64)
+        out = np.zeros(m.value * 20, dtype=np.uint64)
         self._check(self._lib.bilu_export_trace(self._h, out.ctypes.data, out.size, C.byref(m),
                                                 C.byref(tps)), "bilu_export_trace")
-        return out.reshape(m.value, 8), tps.value
+        return out.reshape(m.value, 20), tps.value
 
     def sync(self):
         """Wait for the stream; raise if an asynchronous call reported an error."""
@@ -272,7 +272,9 @@ class Bilu:
     def stats(self) -> dict:
         s = Stats()
         self._check(self._lib.bilu_get_stats(self._h, C.byref(s)), "bilu_get_stats")
-        return {f: getattr(s, f) for f, _ in Stats._fields_}
+        out = {f: getattr(s, f) for f, _ in Stats._fields_}
+        out["t_phase"] = list(s.t_phase)
+        return out
 
     def export(self) -> Factors:
         fh = FactorsHost()

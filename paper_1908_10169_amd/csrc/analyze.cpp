@@ -6,6 +6,7 @@
 //   - the block elimination tree that schedules the numeric sweep.
 // Integer and comparison work only; all numeric factorization runs on the GPU.
 #include <algorithm>
+#include <chrono>
 #include <atomic>
 #include <cmath>
 #include <numeric>
@@ -440,7 +441,9 @@ bilu_status analyze_host(bilu_handle* h, int64_t n, const int64_t* rowptr,
 // block count f' = (r'+s'+l')*l' stays within 4/3 of the scalar count c' or
 // within c' + 4 l'; r', s' count the union rows/columns beyond the block.
 // ---------------------------------------------------------------------------
-int64_t ilu1t_partition(const bilu_handle* h, double tau, std::vector<int32_t>& bstart) {
+int64_t ilu1t_partition(const bilu_handle* h, double tau, std::vector<int32_t>& bstart,
+                        double* t_sets) {
+  const auto t_start = std::chrono::steady_clock::now();
   const int64_t n = h->n;
   const auto& gs = h->group_starts;
   const int64_t nu = (int64_t)gs.size() - 1;
@@ -541,79 +544,93 @@ int64_t ilu1t_partition(const bilu_handle* h, double tau, std::vector<int32_t>& 
       oj += (int64_t)Jbuf[t].size();
     }
   }
-  // sequential growth with marker arrays: rows/cols of the running block
-  std::vector<int32_t> rmark(n, -1), cmark(n, -1);
-  std::vector<int32_t> rows, cols;
+  if (t_sets)
+    *t_sets = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  // Growth.  Whether unit u joins the block that starts at unit s depends
+  // only on s and u, so the end g(s) of a block started at s is computed for
+  // every s in parallel; the partition then follows s -> g(s) from s = 0,
+  // which is exactly the sequential greedy growth.  Marks: 2s = row (column)
+  // of the block started at s, 2s+1 = tentatively added by the next unit.
   const int maxb = h->opt.max_block;
-  int64_t u = 0;
-  int32_t blk = 0;
+  std::vector<int64_t> gend(nu);
   auto count_beyond = [](const std::vector<int32_t>& v, int64_t last) {
     int64_t c = 0;
     for (int32_t x : v) c += x > last;
     return c;
   };
-  while (u < nu) {
-    rows.clear();
-    cols.clear();
-    const int64_t s0 = gs[u];
-    int64_t e = gs[u + 1];
-    int64_t scal = 0;
-    for (int64_t k = s0; k < e; ++k) {
-      for (int64_t m = Iptr[k]; m < Iptr[k + 1]; ++m)
-        if (rmark[Iall[m]] != blk) {
-          rmark[Iall[m]] = blk;
-          rows.push_back(Iall[m]);
-        }
-      for (int64_t m = Jptr[k]; m < Jptr[k + 1]; ++m)
-        if (cmark[Jall[m]] != blk) {
-          cmark[Jall[m]] = blk;
-          cols.push_back(Jall[m]);
-        }
-      scal += Icnt[k] + Jcnt[k] + 1;
-    }
-    ++u;
-    while (u < nu) {
-      const int64_t e2 = gs[u + 1];
-      const int64_t w2 = e2 - s0;
-      if (w2 > maxb) break;
-      // tentative: count the union beyond the new last index without
-      // committing the new unit's entries
-      int64_t r2 = count_beyond(rows, e2 - 1), c2cnt = count_beyond(cols, e2 - 1);
-      int64_t sc2 = scal;
-      std::vector<int32_t> addr, addc;
-      for (int64_t k = gs[u]; k < e2; ++k) {
-        for (int64_t m = Iptr[k]; m < Iptr[k + 1]; ++m) {
-          int32_t i = Iall[m];
-          if (rmark[i] != blk && rmark[i] != -2 - blk) {
-            rmark[i] = -2 - blk;  // tentative
-            addr.push_back(i);
+  auto grow_range = [&](int64_t ulo, int64_t uhi) {
+    std::vector<uint32_t> rmark(n, UINT32_MAX), cmark(n, UINT32_MAX);
+    std::vector<int32_t> rows, cols, addr, addc;
+    for (int64_t s = ulo; s < uhi; ++s) {
+      const uint32_t mk = (uint32_t)(2 * s), tent = mk + 1;
+      rows.clear();
+      cols.clear();
+      const int64_t s0 = gs[s];
+      int64_t scal = 0;
+      for (int64_t k = s0; k < gs[s + 1]; ++k) {
+        for (int64_t m = Iptr[k]; m < Iptr[k + 1]; ++m)
+          if (rmark[Iall[m]] != mk) {
+            rmark[Iall[m]] = mk;
+            rows.push_back(Iall[m]);
           }
-        }
-        for (int64_t m = Jptr[k]; m < Jptr[k + 1]; ++m) {
-          int32_t j = Jall[m];
-          if (cmark[j] != blk && cmark[j] != -2 - blk) {
-            cmark[j] = -2 - blk;
-            addc.push_back(j);
+        for (int64_t m = Jptr[k]; m < Jptr[k + 1]; ++m)
+          if (cmark[Jall[m]] != mk) {
+            cmark[Jall[m]] = mk;
+            cols.push_back(Jall[m]);
           }
-        }
-        sc2 += Icnt[k] + Jcnt[k] + 1;
+        scal += Icnt[k] + Jcnt[k] + 1;
       }
-      r2 += count_beyond(addr, e2 - 1);
-      c2cnt += count_beyond(addc, e2 - 1);
-      const int64_t f2 = (r2 + c2cnt + w2) * w2;
-      const bool grow = 3 * f2 <= 4 * sc2 || f2 <= sc2 + 4 * w2;
-      for (int32_t i : addr) rmark[i] = grow ? blk : -1;
-      for (int32_t j : addc) cmark[j] = grow ? blk : -1;
-      if (!grow) break;
-      rows.insert(rows.end(), addr.begin(), addr.end());
-      cols.insert(cols.end(), addc.begin(), addc.end());
-      scal = sc2;
-      e = e2;
-      ++u;
+      int64_t u = s + 1;
+      while (u < nu) {
+        const int64_t e2 = gs[u + 1];
+        const int64_t w2 = e2 - s0;
+        if (w2 > maxb) break;
+        // union beyond the new last index, the new unit's entries tentative
+        int64_t r2 = count_beyond(rows, e2 - 1), c2 = count_beyond(cols, e2 - 1);
+        int64_t sc2 = scal;
+        addr.clear();
+        addc.clear();
+        for (int64_t k = gs[u]; k < e2; ++k) {
+          for (int64_t m = Iptr[k]; m < Iptr[k + 1]; ++m) {
+            const int32_t i = Iall[m];
+            if (rmark[i] != mk && rmark[i] != tent) {
+              rmark[i] = tent;
+              addr.push_back(i);
+            }
+          }
+          for (int64_t m = Jptr[k]; m < Jptr[k + 1]; ++m) {
+            const int32_t j = Jall[m];
+            if (cmark[j] != mk && cmark[j] != tent) {
+              cmark[j] = tent;
+              addc.push_back(j);
+            }
+          }
+          sc2 += Icnt[k] + Jcnt[k] + 1;
+        }
+        r2 += count_beyond(addr, e2 - 1);
+        c2 += count_beyond(addc, e2 - 1);
+        const int64_t f2 = (r2 + c2 + w2) * w2;
+        if (!(3 * f2 <= 4 * sc2 || f2 <= sc2 + 4 * w2)) break;
+        for (int32_t i : addr) rmark[i] = mk;
+        for (int32_t j : addc) cmark[j] = mk;
+        rows.insert(rows.end(), addr.begin(), addr.end());
+        cols.insert(cols.end(), addc.begin(), addc.end());
+        scal = sc2;
+        ++u;
+      }
+      gend[s] = u;
     }
-    bstart.push_back((int32_t)e);
-    ++blk;
+  };
+  {
+    const int64_t uchunk = (nu + nt - 1) / nt;
+    std::vector<std::thread> tg;
+    for (unsigned t = 0; t < nt; ++t) {
+      const int64_t lo = std::min<int64_t>(nu, t * uchunk), hi = std::min<int64_t>(nu, lo + uchunk);
+      if (lo < hi) tg.emplace_back(grow_range, lo, hi);
+    }
+    for (auto& x : tg) x.join();
   }
+  for (int64_t u = 0; u < nu; u = gend[u]) bstart.push_back((int32_t)gs[gend[u]]);
   return (int64_t)bstart.size() - 1;
 }
 

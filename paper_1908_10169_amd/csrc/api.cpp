@@ -199,10 +199,13 @@ bilu_status bilu_factor(bilu_handle* h, double tau) {
     s = aggregate_device(h);
     if (s != BILU_OK) return s;
   }
-  h->stats.t_aggregate =
-      std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count();
+  auto t2 = std::chrono::steady_clock::now();
+  h->stats.t_aggregate = std::chrono::duration<double>(t2 - t1).count();
+  h->stats.t_phase[4] = h->stats.t_aggregate;
   s = build_apply_plan(h);
   if (s != BILU_OK) return s;
+  auto t3 = std::chrono::steady_clock::now();
+  h->stats.t_phase[5] = std::chrono::duration<double>(t3 - t2).count();
   // block statistics and stored entries of the final factor
   {
     const int64_t nb = h->nb;
@@ -238,7 +241,11 @@ bilu_status bilu_factor(bilu_handle* h, double tau) {
     h->stats.bytes_factor += 12.0 * double(h->nnz) + 8.0 * double(nl + nw + nd) +
                              4.0 * double(ir + ic);
   }
-  h->stats.t_factor = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  {
+    auto t4 = std::chrono::steady_clock::now();
+    h->stats.t_phase[6] = std::chrono::duration<double>(t4 - t3).count();
+    h->stats.t_factor = std::chrono::duration<double>(t4 - t0).count();
+  }
   h->state = 2;
   return h->stats.perturbed_blocks > 0 ? BILU_WARN_PERTURBED : BILU_OK;
   GUARD_END

@@ -18,8 +18,9 @@
 // Scheduling.  J can update K > J only if K holds one of J's candidate rows
 // or columns, i.e. (a) A couples J and K, or (b) a predecessor I of J has
 // stored rows (columns) in K and J among its stored column (row) blocks.
-// pending[K] counts these possible updaters with multiplicity: (a) is set
-// on the host; (b) is added by I when it finishes, for every pair (J, K)
+// pending[K] counts these possible updaters with multiplicity: (a) once per
+// entry of A coupling K to an earlier block, set before the sweep; (b) is
+// added by I when it finishes, for every pair (J, K)
 // its stored patterns create, before I retracts its own counts; J retracts
 // all of its counts once its factor is written and it has appended itself
 // to the lists of the blocks it really updates.  Every possible updater of
@@ -316,9 +317,9 @@ __device__ __forceinline__ void push_ready(const FlowArgs& d, int B, int by, int
 }
 
 // The blocks K may update, each with the count K holds in its pending
-// counter: 1 for each distinct block > K of A's pattern of K, plus 1 for
-// every (column predecessor J, row block B > K of J) and (row predecessor J,
-// column block B > K of J).  Keys go to s.ann, counts to s.annc; returns the
+// counter: 1 for every entry of A's block column and block row K that lies
+// in a block B > K, plus 1 for every (column predecessor J, row block B > K
+// of J) and (row predecessor J, column block B > K of J).  Keys go to s.ann, counts to s.annc; returns the
 // number of keys or -1 on overflow.
 __device__ int updater_set(const FactorArgs& a, int K, Lds& s, int np, int npr) {
   int* cnt = s.cand;  // per hash slot, over cand[] and candc[] (built later)
@@ -331,10 +332,24 @@ __device__ int updater_set(const FactorArgs& a, int K, Lds& s, int np, int npr) 
     s.misc[5] = 0;
   }
   __syncthreads();
-  for (int64_t e = a.ablk_ptr[K] + threadIdx.x; e < a.ablk_ptr[K + 1]; e += blockDim.x) {
-    const int h = hash_insert_at(s.hash, a.ablk[e], &s.misc[4]);
-    if (h < 0) s.misc[5] = 1;
-    else atomicAdd(&cnt[h], 1);
+  const int f = a.bstart[K], l = a.bstart[K + 1] - 1;
+  for (int c = f; c <= l; ++c) {
+    for (int64_t m = a.cp[c] + threadIdx.x; m < a.cp[c + 1]; m += blockDim.x) {
+      const int B = a.bri[m];
+      if (B > K) {
+        const int h = hash_insert_at(s.hash, B, &s.misc[4]);
+        if (h < 0) s.misc[5] = 1;
+        else atomicAdd(&cnt[h], 1);
+      }
+    }
+    for (int64_t m = a.rp[c] + threadIdx.x; m < a.rp[c + 1]; m += blockDim.x) {
+      const int B = a.bci[m];
+      if (B > K) {
+        const int h = hash_insert_at(s.hash, B, &s.misc[4]);
+        if (h < 0) s.misc[5] = 1;
+        else atomicAdd(&cnt[h], 1);
+      }
+    }
   }
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   for (int pi = wid; pi < np + npr; pi += nw) {
@@ -453,7 +468,13 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
     if (tid == 0) raise_error(a, kDevCandOverflow, K);
     return false;
   }
-  if (tid == 0) trace_at(d, K, 3, wall_clock64());
+  if (tid == 0) {
+    trace_at(d, K, 3, wall_clock64());
+    trace_at(d, K, 16, (unsigned long long)np);
+    trace_at(d, K, 17, (unsigned long long)npr);
+    trace_at(d, K, 18, (unsigned long long)mc);
+    trace_at(d, K, 19, (unsigned long long)mcc);
+  }
 
   // ---------------- column panel: rows >= f of block column K
   for (int e = tid; e < mc * q; e += blockDim.x) Cp[e] = 0.0;
@@ -511,6 +532,7 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
     __syncthreads();
   }
 
+  if (tid == 0) trace_at(d, K, 8, wall_clock64());
   // ---------------- row panel: columns > l of block row K
   for (int e = tid; e < mcc * q; e += blockDim.x) Rp[e] = 0.0;
   __syncthreads();
@@ -567,6 +589,7 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
     __syncthreads();
   }
 
+  if (tid == 0) trace_at(d, K, 9, wall_clock64());
   // ---------------- pivot block: perturb (Sec. 3.6) + invert
   // q x q perturbed pivot block and work/inverse: LDS up to width 64,
   // the slot's scratch beyond the panels for wider blocks
@@ -639,6 +662,7 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
     a.sval[a.doff[K] + e] = sS[e];
   }
 
+  if (tid == 0) trace_at(d, K, 10, wall_clock64());
   // ---------------- drop: rows of L (scaled) and columns of U (D R)
   int* keep_r = s.hash;                 // flags for rows q..mc-1
   int* keep_c = s.hash + kCandCap;      // flags for cols 0..mcc-1
@@ -671,6 +695,7 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
     keep_c[z] = nrm > a.tau ? 1 : 0;
   }
   __syncthreads();
+  if (tid == 0) trace_at(d, K, 11, wall_clock64());
   constexpr int kPer = kCandCap / kThreads;  // flags per thread
   int fr[kPer], fc[kPer];
   int sr = 0, sc = 0;
@@ -716,6 +741,7 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
   }
   __syncthreads();
   if (s.misc[16]) return false;
+  if (tid == 0) trace_at(d, K, 12, wall_clock64());
   const int64_t vo = s.off[0];
   const int64_t io = s.off[1];
   double* Lout = a.val_heap + vo;
@@ -780,6 +806,7 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
     atomicAdd(a.upd_bytes, (unsigned long long)ubytes);
   }
   __syncthreads();
+  if (tid == 0) trace_at(d, K, 13, wall_clock64());
   // K updates the row panels of the blocks holding its rows of L and the
   // column panels of the blocks holding its columns of U.
   for (int t = tid; t < mk; t += blockDim.x) {
@@ -793,11 +820,13 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
       push_checked(a, d, a.col_cnt, a.col_list, a.col_ovf, b, K);
   }
   __syncthreads();
+  if (tid == 0) trace_at(d, K, 14, wall_clock64());
   add_successor_counts(a, d, TRout, ntr, TCout, ntc, K);
   // publish: every write and count of this block is visible before the
   // retraction
   __threadfence();
   __syncthreads();
+  if (tid == 0) trace_at(d, K, 15, wall_clock64());
   retract(a, d, s, na, K);
   if (tid == 0) trace_at(d, K, 4, wall_clock64());
   return true;
@@ -840,6 +869,34 @@ __global__ void fill_block_of(const int32_t* bstart, int nb, int32_t* blockOf) {
   for (int i = bstart[b] + threadIdx.x; i < bstart[b + 1]; i += blockDim.x) blockOf[i] = b;
 }
 
+// out[m] = blockOf[idx[m]] for every stored entry.
+__global__ void map_blocks(const int32_t* idx, int64_t nnz, const int32_t* blockOf, int32_t* out) {
+  for (int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; m < nnz;
+       m += (int64_t)gridDim.x * blockDim.x)
+    out[m] = blockOf[idx[m]];
+}
+
+// pending[K] += entries of A's rows and columns of K that lie in earlier
+// blocks (one thread per index i: row i and column i).
+__global__ void static_pending(int n, const int64_t* rp, const int32_t* bci, const int64_t* cp,
+                               const int32_t* bri, const int32_t* blockOf, int* pending) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int K = blockOf[i];
+  int c = 0;
+  for (int64_t m = rp[i]; m < rp[i + 1]; ++m) c += bci[m] < K;
+  for (int64_t m = cp[i]; m < cp[i + 1]; ++m) c += bri[m] < K;
+  if (c) atomicAdd(&pending[K], c);
+}
+
+// Blocks that nothing can update start in the ready queue.
+__global__ void seed_queue(int nb, const int* pending, int* enq, int* queue, int* tail) {
+  const int K = blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= nb || pending[K] != 0) return;
+  enq[K] = 1;
+  queue[atomicAdd(tail, 1)] = K;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -850,9 +907,12 @@ bilu_status factor_device(bilu_handle* h, double tau) {
   auto t0 = clk::now();
   const int64_t n = h->n;
   std::vector<int32_t>& bs = h->bstart0;
-  const int64_t nb = ilu1t_partition(h, tau, bs);
+  double t_sets = 0.0;
+  const int64_t nb = ilu1t_partition(h, tau, bs, &t_sets);
   auto t1 = clk::now();
   h->stats.t_ilu1t = std::chrono::duration<double>(t1 - t0).count();
+  h->stats.t_phase[0] = t_sets;
+  h->stats.t_phase[1] = h->stats.t_ilu1t - t_sets;
   int32_t maxq = 0;
   for (int64_t b = 0; b < nb; ++b) maxq = std::max(maxq, bs[b + 1] - bs[b]);
   if (maxq > kMaxWidth) return fail(h, BILU_ERR_INVALID, "block wider than the kernel limit");
@@ -893,50 +953,19 @@ bilu_status factor_device(bilu_handle* h, double tau) {
   CK(h->d_tcoff.alloc(nb));
   CK(h->d_ntr.alloc(nb));
   CK(h->d_ntc.alloc(nb));
-  // static possible updaters: J counts once in pending[K] for every K in the
-  // distinct blocks > J of the rows of A(:, J) and the columns of A(J, :)
-  std::vector<int> pending0(nb, 0);
-  {
-    std::vector<int32_t> bof(n);
-    for (int64_t b = 0; b < nb; ++b)
-      for (int32_t i = bs[b]; i < bs[b + 1]; ++i) bof[i] = (int32_t)b;
-    std::vector<int64_t> ptr(nb + 1, 0);
-    std::vector<int32_t> lst, tmp;
-    for (int64_t K = 0; K < nb; ++K) {
-      tmp.clear();
-      for (int32_t i = bs[K]; i < bs[K + 1]; ++i) {
-        for (int64_t m = h->pcp[i]; m < h->pcp[i + 1]; ++m)
-          if (bof[h->pri[m]] > K) tmp.push_back(bof[h->pri[m]]);
-        for (int64_t m = h->prp[i]; m < h->prp[i + 1]; ++m)
-          if (bof[h->pci[m]] > K) tmp.push_back(bof[h->pci[m]]);
-      }
-      std::sort(tmp.begin(), tmp.end());
-      tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
-      lst.insert(lst.end(), tmp.begin(), tmp.end());
-      ptr[K + 1] = (int64_t)lst.size();
-      for (int32_t B : tmp) pending0[B]++;
-    }
-    CK(h->d_ablk_ptr.alloc(nb + 1));
-    CK(h->d_ablk.alloc(std::max<size_t>(1, lst.size())));
-    CK(hipMemcpyAsync(h->d_ablk_ptr.p, ptr.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
-    if (!lst.empty())
-      CK(hipMemcpyAsync(h->d_ablk.p, lst.data(), lst.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
-    CK(hipStreamSynchronize(st));
-  }
   CK(h->d_flow.alloc(5 * nb + 2));
-  // blocks that nothing can update are ready at the start: queue them in order
-  std::vector<int> init_queue(nb, -1), init_enq(nb, 0);
-  int nleaves = 0;
-  for (int64_t K = 0; K < nb; ++K)
-    if (pending0[K] == 0) {
-      init_queue[nleaves++] = (int)K;
-      init_enq[K] = 1;
-    }
   CK(hipMemcpyAsync(h->d_bstart.p, bs.data(), (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(h->d_doff.p, h->doff_h.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
   {
     dim3 blk(64, 4);
     fill_block_of<<<dim3((unsigned)((nb + 3) / 4)), blk, 0, st>>>(h->d_bstart.p, (int)nb, h->d_blockof.p);
+    const int64_t nnz = h->nnz;
+    CK(h->d_bri.alloc(std::max<int64_t>(1, nnz)));
+    CK(h->d_bci.alloc(std::max<int64_t>(1, nnz)));
+    const unsigned g = (unsigned)std::min<int64_t>(65536, (nnz + 255) / 256 + 1);
+    map_blocks<<<g, 256, 0, st>>>(h->d_ri.p, nnz, h->d_blockof.p, h->d_bri.p);
+    map_blocks<<<g, 256, 0, st>>>(h->d_ci.p, nnz, h->d_blockof.p, h->d_bci.p);
+    CK(hipGetLastError());
   }
   int64_t val_cap = h->opt.heap_bytes ? (int64_t)(h->opt.heap_bytes / sizeof(double))
                                       : std::max<int64_t>(1 << 20, 4 * h->nnz);
@@ -962,6 +991,7 @@ bilu_status factor_device(bilu_handle* h, double tau) {
       h->wait_ticks = (unsigned long long)(kWaitSeconds * 1e8);
   }
   auto t2 = clk::now();
+  h->stats.t_phase[2] = std::chrono::duration<double>(t2 - t1).count();
   for (int attempt = 0; attempt < 4; ++attempt) {
     if ((int64_t)h->d_val_heap.n < val_cap) CK(h->d_val_heap.alloc(val_cap));
     if ((int64_t)h->d_idx_heap.n < idx_cap) CK(h->d_idx_heap.alloc(idx_cap));
@@ -971,13 +1001,15 @@ bilu_status factor_device(bilu_handle* h, double tau) {
     CK(hipMemsetAsync(h->d_row_ovf.p, 0xff, nb * sizeof(int32_t), st));
     CK(hipMemsetAsync(h->d_status.p, 0, 8 * sizeof(int), st));
     CK(hipMemsetAsync(h->d_counters.p, 0, 4 * sizeof(unsigned long long), st));
-    CK(hipMemcpyAsync(h->d_flow.p, pending0.data(), nb * sizeof(int), hipMemcpyHostToDevice, st));
-    CK(hipMemsetAsync(h->d_flow.p + nb, 0, nb * sizeof(int), st));
-    CK(hipMemcpyAsync(h->d_flow.p + 2 * nb, init_enq.data(), nb * sizeof(int), hipMemcpyHostToDevice, st));
-    CK(hipMemsetAsync(h->d_flow.p + 3 * nb, 0, nb * sizeof(int), st));
-    CK(hipMemcpyAsync(h->d_flow.p + 4 * nb, init_queue.data(), nb * sizeof(int), hipMemcpyHostToDevice, st));
-    const int tail_depth[2] = {nleaves, 0};
-    CK(hipMemcpyAsync(h->d_flow.p + 5 * nb, tail_depth, sizeof(tail_depth), hipMemcpyHostToDevice, st));
+    // pending, started, enqueued, depth = 0; queue = -1; tail, max depth = 0
+    CK(hipMemsetAsync(h->d_flow.p, 0, 4 * nb * sizeof(int), st));
+    CK(hipMemsetAsync(h->d_flow.p + 4 * nb, 0xff, nb * sizeof(int), st));
+    CK(hipMemsetAsync(h->d_flow.p + 5 * nb, 0, 2 * sizeof(int), st));
+    static_pending<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+        (int)n, h->d_rp.p, h->d_bci.p, h->d_cp.p, h->d_bri.p, h->d_blockof.p, h->d_flow.p);
+    seed_queue<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(
+        (int)nb, h->d_flow.p, h->d_flow.p + 2 * nb, h->d_flow.p + 4 * nb, h->d_flow.p + 5 * nb);
+    CK(hipGetLastError());
     FactorArgs a{};
     a.n = (int)n;
     a.nb = (int)nb;
@@ -1017,8 +1049,8 @@ bilu_status factor_device(bilu_handle* h, double tau) {
     a.ntr = h->d_ntr.p;
     a.tcoff = h->d_tcoff.p;
     a.ntc = h->d_ntc.p;
-    a.ablk_ptr = h->d_ablk_ptr.p;
-    a.ablk = h->d_ablk.p;
+    a.bri = h->d_bri.p;
+    a.bci = h->d_bci.p;
     FlowArgs d{};
     d.pending = h->d_flow.p;
     d.started = h->d_flow.p + nb;
@@ -1084,6 +1116,7 @@ bilu_status factor_device(bilu_handle* h, double tau) {
     h->stats.factor_levels = max_depth;
     auto t3 = clk::now();
     h->stats.t_factor_device = std::chrono::duration<double>(t3 - t2).count();
+    h->stats.t_phase[3] = h->stats.t_factor_device;
     h->stats.nblocks_initial = nb;
     return BILU_OK;
   }

@@ -35,21 +35,33 @@ enum DevErr : int {
   kDevAnnOverflow = 10,
 };
 
+// Device array owned by a handle.  alloc() keeps the existing allocation
+// when it is large enough (refactoring does not free and reallocate).
 template <class T>
 struct DevArray {
   T* p = nullptr;
-  size_t n = 0;
+  size_t n = 0;    // elements in use
+  size_t cap = 0;  // elements allocated
   ~DevArray() { release(); }
   void release() {
     if (p) (void)hipFree(p);
     p = nullptr;
-    n = 0;
+    n = cap = 0;
   }
   hipError_t alloc(size_t count) {
+    if (count <= cap && p) {
+      n = count;
+      return hipSuccess;
+    }
     release();
-    n = count;
     if (count == 0) return hipSuccess;
-    return hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T));
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    n = cap = count;
+    return hipSuccess;
   }
 };
 
@@ -92,7 +104,8 @@ struct FactorArgs {
   // idx heap, and the static distinct blocks > K of A's pattern of K
   int64_t* troff; int32_t* ntr;
   int64_t* tcoff; int32_t* ntc;
-  const int64_t* ablk_ptr; const int32_t* ablk;
+  // block of the row (column) of every CSC (CSR) entry of A
+  const int32_t* bri; const int32_t* bci;
 };
 
 constexpr int kAnnCap = 2048;      // distinct blocks one block may still update
@@ -109,11 +122,14 @@ struct FlowArgs {
   unsigned long long wait_ticks;
   // optional per-block trace (kTraceFields per block, wall-clock ticks):
   // pushed, popped, updater set built, candidates built, done, the block
-  // whose retraction made it ready, the count it retracted, worker
+  // whose retraction made it ready, the count it retracted, worker; then
+  // the end of the column panel, row panel, pivot, drop norms, heap
+  // allocation, factor writes, list pushes, successor counts; then the
+  // numbers of column and row predecessors, candidate rows and columns
   unsigned long long* trace;
 };
 
-constexpr int kTraceFields = 8;
+constexpr int kTraceFields = 20;
 
 // Bound of one dependency wait in seconds: a wait that exceeds it reports
 // an error instead of hanging.
@@ -166,9 +182,9 @@ struct bilu_handle {
 
   // ---- factor: partition + schedule (host)
   std::vector<int32_t> bstart0;       // initial partition
-  bilu::DevArray<int64_t> d_troff, d_tcoff, d_ablk_ptr;
+  bilu::DevArray<int64_t> d_troff, d_tcoff;
   bilu::DevArray<unsigned long long> d_trace;  // collect_timing == 2
-  bilu::DevArray<int32_t> d_ntr, d_ntc, d_ablk;
+  bilu::DevArray<int32_t> d_ntr, d_ntc, d_bri, d_bci;
   bilu::DevArray<int> d_flow;        // pending, started, enqueued, depth, queue, tail, max depth
   unsigned long long wait_ticks = 0; // bound of one dependency wait (wall-clock ticks)
   std::vector<int64_t> doff_h;
@@ -235,7 +251,8 @@ bilu_status hip_check(bilu_handle* h, hipError_t e, const char* what);
 // analyze.cpp
 bilu_status analyze_host(bilu_handle* h, int64_t n, const int64_t* rowptr,
                          const int32_t* colind, const double* val);
-int64_t ilu1t_partition(const bilu_handle* h, double tau, std::vector<int32_t>& bstart);
+int64_t ilu1t_partition(const bilu_handle* h, double tau, std::vector<int32_t>& bstart,
+                        double* t_sets = nullptr);
 
 // factor.hip
 bilu_status factor_device(bilu_handle* h, double tau);
