@@ -70,6 +70,9 @@ typedef struct {
   size_t heap_bytes;     /* factor heap size; 0 = sized from nnz(A)                  */
   int collect_timing;    /* 1: time kernels with HIP events on the handle's stream;  */
                          /* 2: also trace every block of the factor kernel           */
+  int factor_path;       /* 0: narrow blocks use the LDS-resident kernel path        */
+                         /* (default); 1: every block uses the general path. Both    */
+                         /* compute identical bits                                   */
 } bilu_options;
 
 typedef struct bilu_handle bilu_handle;

@@ -42,6 +42,13 @@
 namespace bilu {
 namespace {
 
+// Device-scope ordering.  A block's results become visible to blocks on
+// other XCDs by a release (L2 write-back) before it retracts its counts; a
+// worker acquires (L2 invalidate) once after taking a block from the queue.
+// Both are whole-cache operations, so each block issues exactly one of each.
+__device__ __forceinline__ void release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
 __device__ __forceinline__ void raise_error(const FactorArgs& a, int code, int blk) {
   if (atomicCAS(a.err, 0, code) == 0) atomicExch(a.err_block, blk);
 }
@@ -83,7 +90,7 @@ __device__ __forceinline__ int hash_insert_at(int* table, int key, int* count) {
 
 // Read the predecessor list of a block (inline part + overflow chain) into
 // LDS and sort it.  Returns the count, or -1 on overflow.
-__device__ int load_preds(const FactorArgs& a, const int32_t* cnt_arr, const int32_t* list,
+__device__ __forceinline__ int load_preds(const FactorArgs& a, const int32_t* cnt_arr, const int32_t* list,
                           const int32_t* ovf_head, int K, int* s_pred, int* s_misc) {
   const int cnt = cnt_arr[K];
   if (cnt > kPredCap) return -1;
@@ -131,7 +138,7 @@ __device__ __forceinline__ double dot_strided(const double* x, const double* y, 
 // Sec. 3.6 perturbation of column j of the q x q row-major matrix m: the
 // largest-magnitude entry (lowest row on ties), or the diagonal when
 // 2|m_jj| >= |m_kj|, becomes m_kj (1 + rho beta) + sign(m_kj) tau alpha.
-__device__ void perturb_column(double* m, int q, int j, const FactorArgs& a) {
+__device__ __forceinline__ void perturb_column(double* m, int q, int j, const FactorArgs& a) {
   int k = 0;
   double dmax = -1.0;
   for (int i = 0; i < q; ++i) {
@@ -147,7 +154,7 @@ __device__ void perturb_column(double* m, int q, int j, const FactorArgs& a) {
   m[k * q + j] = d * (1.0 + a.pert_rho * beta) + (d < 0.0 ? -1.0 : 1.0) * a.pert_tau * a.alpha;
 }
 
-__device__ void perturb_row(double* m, int q, int i, const FactorArgs& a) {
+__device__ __forceinline__ void perturb_row(double* m, int q, int i, const FactorArgs& a) {
   int k = 0;
   double dmax = -1.0;
   for (int j = 0; j < q; ++j) {
@@ -163,12 +170,31 @@ __device__ void perturb_row(double* m, int q, int i, const FactorArgs& a) {
   m[i * q + k] = d * (1.0 + a.pert_rho * beta) + (d < 0.0 ? -1.0 : 1.0) * a.pert_tau * a.alpha;
 }
 
+// Thread group of a cooperative step: the whole workgroup, or wave 0 alone
+// (wave-synchronous: LDS accesses of one wave complete in order, so a fence
+// that stops compiler reordering is the only synchronisation needed).
+template <bool kWave>
+struct Group {
+  __device__ static int id() { return kWave ? (int)(threadIdx.x & 63) : (int)threadIdx.x; }
+  __device__ static int size() { return kWave ? 64 : (int)blockDim.x; }
+  __device__ static void sync() {
+    if (kWave) {
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+    } else {
+      __syncthreads();
+    }
+  }
+};
+
 // In-place Gauss-Jordan inverse of the q x q row-major LDS matrix w with
 // partial pivoting.  Returns false (uniformly) when a pivot is not above
-// eps * smax.  s_f: q doubles, s_ip: q ints, s_misc: >= 4 ints.
-__device__ bool gauss_jordan_inverse(double* w, int q, double smax, double eps, double* s_f,
+// eps * smax.  kWave: run by wave 0 alone (no workgroup barriers).  s_f: q doubles, s_ip: q ints, s_misc: >= 4 ints.
+template <bool kWave>
+__device__ __forceinline__ bool gauss_jordan_inverse(double* w, int q, double smax, double eps, double* s_f,
                                      int* s_ip, int* s_misc) {
-  const int tid = threadIdx.x;
+  using G = Group<kWave>;
+  const int tid = G::id(), nth = G::size();
   for (int k = 0; k < q; ++k) {
     // pivot search by wave 0: max |w_ik|, i >= k, lowest i on ties
     if (tid < 64) {
@@ -196,51 +222,83 @@ __device__ bool gauss_jordan_inverse(double* w, int q, double smax, double eps, 
         s_misc[1] = (bi < q && u != 0.0 && fabs(u) > eps * smax && isfinite(u)) ? 1 : 0;
       }
     }
-    __syncthreads();
+    G::sync();
     const int p = s_misc[0];
     if (!s_misc[1]) return false;
     if (p != k)
-      for (int j = tid; j < q; j += blockDim.x) {
+      for (int j = tid; j < q; j += nth) {
         double t = w[k * q + j];
         w[k * q + j] = w[p * q + j];
         w[p * q + j] = t;
       }
     if (tid == 0) s_ip[k] = p;
-    __syncthreads();
+    G::sync();
     const double d = w[k * q + k];
-    __syncthreads();
-    for (int j = tid; j < q; j += blockDim.x) w[k * q + j] = (j == k ? 1.0 : w[k * q + j]) / d;
-    for (int i = tid; i < q; i += blockDim.x) s_f[i] = w[i * q + k];
-    __syncthreads();
-    for (int e = tid; e < q * q; e += blockDim.x) {
+    G::sync();
+    for (int j = tid; j < q; j += nth) w[k * q + j] = (j == k ? 1.0 : w[k * q + j]) / d;
+    for (int i = tid; i < q; i += nth) s_f[i] = w[i * q + k];
+    G::sync();
+    for (int e = tid; e < q * q; e += nth) {
       const int i = e / q, j = e - i * q;
       if (i == k) continue;
       const double base = (j == k) ? 0.0 : w[e];
       w[e] = fma(-s_f[i], w[k * q + j], base);
     }
-    __syncthreads();
+    G::sync();
   }
   for (int k = q - 1; k >= 0; --k) {
     const int p = s_ip[k];
     if (p != k)
-      for (int i = tid; i < q; i += blockDim.x) {
+      for (int i = tid; i < q; i += nth) {
         double t = w[i * q + k];
         w[i * q + k] = w[i * q + p];
         w[i * q + p] = t;
       }
-    __syncthreads();
+    G::sync();
   }
   return true;
 }
+
+// Fast path limits: blocks up to kFastWidth wide with at most kFastPreds
+// predecessors, whose predecessor lists, candidates and panels fit in LDS.
+constexpr int kFastWidth = 16;
+constexpr int kFastPreds = 120;     // column + row predecessors
+constexpr int kFastStage = 3072;    // staged list entries
+constexpr int kFastBuf = 2048;      // doubles: panels + update terms
+constexpr int kFastExtra = 256;     // candidate rows (columns) beyond the block
+constexpr int kFastSegs = 2 + 2 * kFastPreds;
+
+// Per-predecessor data of the fast path.  lo/hi/lo2 are positions in J's
+// lists: for a column predecessor, C_J[lo, hi) lie inside K and R_J[lo2, nr)
+// are rows >= first(K); for a row predecessor, R_J[lo, hi) lie inside K and
+// C_J[lo2, nc) are columns > last(K).  ioff: first update term of J.
+struct PredMeta {
+  long long roff, coff, loff, woff, troff, tcoff;
+  int nr, nc, p, ntr, ntc, lo, hi, lo2, ioff, pad;
+};
 
 struct Lds {
   int hash[kHashSlots];     // candidate dedup; reused as keep flags
   int cand[kCandCap];       // sorted candidate rows
   int candc[kCandCap];      // sorted candidate columns
-  int pred[kPredCap];       // predecessors of the column panel
-  int rpred[kPredCap];      // predecessors of the row panel
-  int ann[kAnnCap];         // blocks this block may update
-  int annc[kAnnCap];        // ... and the count it retracts from each
+  union {
+    struct {                // general path
+      int pred[kPredCap];   // predecessors of the column panel
+      int rpred[kPredCap];  // predecessors of the row panel
+      int ann[kAnnCap];     // blocks this block may update
+      int annc[kAnnCap];    // ... and the count it retracts from each
+    } g;
+    struct {                // fast path
+      double buf[kFastBuf];           // panels, then update terms
+      PredMeta meta[kFastPreds];      // column predecessors, then row ones
+      int stage[kFastStage];          // staged lists (see factor_block_fast)
+      int segoff[kFastSegs + 1];
+      int pred[kFastPreds];
+      int rpred[kFastPreds];
+      long long cpk[kFastWidth + 1];  // A's column (row) pointers of K
+      long long rpk[kFastWidth + 1];
+    } x;
+  };
   int misc[32];
   int scan[20];
   int ip[kMaxWidth];
@@ -251,12 +309,16 @@ struct Lds {
 // updater_set counts per hash slot in cand[] followed by candc[]
 static_assert(2 * kCandCap >= kHashSlots, "count slots");
 static_assert(offsetof(Lds, candc) == offsetof(Lds, cand) + sizeof(int) * kCandCap, "layout");
+static_assert(kFastWidth + kFastExtra <= 512 && 2560 + kFastExtra <= kFastStage, "stage layout");
+static_assert(2 + 2 * kFastPreds <= kThreads && kFastPreds <= kThreads, "one thread per segment");
+static_assert(2 * kFastExtra <= kFastBuf * 2, "candidate staging in buf");
+static_assert(kThreads >= 192 && kListCap <= 64 && kFastWidth + 1 <= 32, "round-1 thread map");
 
 // Build the sorted set of candidate indices into out[] from the structural
 // entries of A (lists ptr/idx over [lo, hi], keeping idx >= min_keep) plus
 // the stored rows (or columns) of the predecessors preds[0..npred).
 // Returns the count or -1 on overflow.
-__device__ int build_candidates(Lds& s, int* out, const int64_t* ptr, const int32_t* idx, int lo,
+__device__ __forceinline__ int build_candidates(Lds& s, int* out, const int64_t* ptr, const int32_t* idx, int lo,
                                 int hi, int min_keep, const int* preds, int npred,
                                 const FactorArgs& a, bool rows, int diag_first, int diag_last) {
   for (int t = threadIdx.x; t < kHashSlots; t += blockDim.x) s.hash[t] = -1;
@@ -319,9 +381,9 @@ __device__ __forceinline__ void push_ready(const FlowArgs& d, int B, int by, int
 // The blocks K may update, each with the count K holds in its pending
 // counter: 1 for every entry of A's block column and block row K that lies
 // in a block B > K, plus 1 for every (column predecessor J, row block B > K
-// of J) and (row predecessor J, column block B > K of J).  Keys go to s.ann, counts to s.annc; returns the
+// of J) and (row predecessor J, column block B > K of J).  Keys go to s.g.ann, counts to s.g.annc; returns the
 // number of keys or -1 on overflow.
-__device__ int updater_set(const FactorArgs& a, int K, Lds& s, int np, int npr) {
+__device__ __forceinline__ int updater_set(const FactorArgs& a, int K, Lds& s, int np, int npr) {
   int* cnt = s.cand;  // per hash slot, over cand[] and candc[] (built later)
   for (int t = threadIdx.x; t < kHashSlots; t += blockDim.x) {
     s.hash[t] = -1;
@@ -354,7 +416,7 @@ __device__ int updater_set(const FactorArgs& a, int K, Lds& s, int np, int npr) 
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   for (int pi = wid; pi < np + npr; pi += nw) {
     const bool col = pi < np;
-    const int J = col ? s.pred[pi] : s.rpred[pi - np];
+    const int J = col ? s.g.pred[pi] : s.g.rpred[pi - np];
     const int n = col ? a.ntr[J] : a.ntc[J];
     const int32_t* lst = a.idx_heap + (col ? a.troff[J] : a.tcoff[J]);
     for (int t = lane; t < n; t += 64) {
@@ -375,8 +437,8 @@ __device__ int updater_set(const FactorArgs& a, int K, Lds& s, int np, int npr) 
     const int k = s.hash[t];
     if (k >= 0) {
       const int o = atomicAdd(&s.misc[6], 1);
-      s.ann[o] = k;
-      s.annc[o] = cnt[t];
+      s.g.ann[o] = k;
+      s.g.annc[o] = cnt[t];
     }
   }
   __syncthreads();
@@ -385,17 +447,14 @@ __device__ int updater_set(const FactorArgs& a, int K, Lds& s, int np, int npr) 
 
 // Retract K's counts; the retraction that brings a count to zero makes that
 // block ready.  Every write of K is visible before this is called.
-__device__ void retract(const FactorArgs& a, const FlowArgs& d, const Lds& s, int m, int K) {
+__device__ __forceinline__ void retract(const FactorArgs& a, const FlowArgs& d, const Lds& s, int m, int K) {
   const int dK = __hip_atomic_load(&d.depth[K], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
   for (int t = threadIdx.x; t < m; t += blockDim.x) {
-    const int B = s.ann[t], c = s.annc[t];
+    const int B = s.g.ann[t], c = s.g.annc[t];
     atomicMax(&d.depth[B], dK);
     const int old = atomicSub(&d.pending[B], c);
     if (old < c) raise_error(a, kDevProtocol, K);
-    if (old == c) {
-      __threadfence();
-      push_ready(d, B, K, c);
-    }
+    if (old == c) push_ready(d, B, K, c);
   }
 }
 
@@ -403,7 +462,7 @@ __device__ void retract(const FactorArgs& a, const FlowArgs& d, const Lds& s, in
 // of K's stored columns (rows): each such J becomes a possible updater of
 // B once K is done.  B's own count from K is still held, so B cannot have
 // started.
-__device__ void add_successor_counts(const FactorArgs& a, const FlowArgs& d, const int32_t* tr,
+__device__ __forceinline__ void add_successor_counts(const FactorArgs& a, const FlowArgs& d, const int32_t* tr,
                                      int ntr, const int32_t* tc, int ntc, int K) {
   for (int t = threadIdx.x; t < ntr + ntc; t += blockDim.x) {
     const bool row = t < ntr;
@@ -423,8 +482,120 @@ __device__ __forceinline__ void push_checked(const FactorArgs& a, const FlowArgs
   push_pred(a, cnt_arr, list, ovf_head, B, K);
 }
 
+// Pivot block (Sec. 3.6, Sec. 2.2): copy the q x q leading rows of the
+// column panel into sS, perturb all-zero columns and rows, then invert into
+// sW by Gauss-Jordan; a failed inversion perturbs every column and row of
+// sS and retries (at most 3 rounds).  Stores D_K and S_K.  Returns false
+// (uniformly) after reporting a block that stays singular.  kWave: run by
+// wave 0 alone.
+template <bool kWave>
+__device__ __forceinline__ bool pivot_block(const FactorArgs& a, int K, int q, const double* Cp, double* sS,
+                            double* sW, Lds& s) {
+  using G = Group<kWave>;
+  const int tid = G::id(), nth = G::size();
+  for (int e = tid; e < q * q; e += nth) sS[e] = Cp[e];
+  if (tid == 0) s.misc[12] = 0;
+  G::sync();
+  // all-zero columns, then all-zero rows, are perturbed before factoring
+  for (int j = tid; j < q; j += nth) {
+    bool zero = true;
+    for (int i = 0; i < q; ++i) zero = zero && sS[i * q + j] == 0.0;
+    if (zero) {
+      perturb_column(sS, q, j, a);
+      s.misc[12] = 1;
+    }
+  }
+  G::sync();
+  for (int i = tid; i < q; i += nth) {
+    bool zero = true;
+    for (int j = 0; j < q; ++j) zero = zero && sS[i * q + j] == 0.0;
+    if (zero) {
+      perturb_row(sS, q, i, a);
+      s.misc[12] = 1;
+    }
+  }
+  G::sync();
+  int rounds = s.misc[12];
+  for (int attempt = 0;; ++attempt) {
+    double mx = 0.0;
+    int finite = 1;
+    for (int e = tid; e < q * q; e += nth) {
+      double v = sS[e];
+      sW[e] = v;
+      if (!isfinite(v)) finite = 0;
+      mx = fmax(mx, fabs(v));
+    }
+    mx = wave_max(mx);
+    finite = __all(finite);
+    if (tid == 0) {
+      s.misc[13] = 1;
+      s.smax = 0.0;
+    }
+    G::sync();
+    if ((tid & 63) == 0) {
+      if (!finite) s.misc[13] = 0;
+      // non-negative doubles order like their bit patterns
+      atomicMax(reinterpret_cast<unsigned long long*>(&s.smax),
+                (unsigned long long)__double_as_longlong(mx));
+    }
+    G::sync();
+    const double smax = s.smax;
+    bool ok = s.misc[13] && gauss_jordan_inverse<kWave>(sW, q, smax, a.pivot_eps, s.f, s.ip, s.misc);
+    G::sync();
+    if (ok) break;
+    if (attempt == 3) {
+      if (tid == 0) raise_error(a, kDevSingular, K);
+      return false;
+    }
+    for (int j = tid; j < q; j += nth) perturb_column(sS, q, j, a);
+    G::sync();
+    for (int i = tid; i < q; i += nth) perturb_row(sS, q, i, a);
+    G::sync();
+    ++rounds;
+  }
+  if (tid == 0 && rounds > 0) atomicAdd(a.n_perturbed, 1);
+  for (int e = tid; e < q * q; e += nth) {
+    a.dval[a.doff[K] + e] = sW[e];
+    a.sval[a.doff[K] + e] = sS[e];
+  }
+
+  G::sync();
+  return true;
+}
+
+// Drop test (Alg. 1 in block form): row z of L is kept iff the norm of
+// C(z, K) D_K exceeds tau, column z of U iff the norm of D_K R(K, z) does.
+__device__ __forceinline__ void drop_flags(const FactorArgs& a, const double* Cp, const double* Rp, int mc, int mcc,
+                           int q, const double* sW, int* keep_r, int* keep_c) {
+  const int tid = threadIdx.x;
+  const bool two = a.drop_norm == 1;
+  for (int z = q + tid; z < mc; z += blockDim.x) {
+    const double* row = Cp + (int64_t)z * q;
+    double nrm = 0.0;
+    for (int c = 0; c < q; ++c) {
+      double v = 0.0;
+      for (int t = 0; t < q; ++t) v = fma(row[t], sW[t * q + c], v);
+      nrm = two ? fma(v, v, nrm) : fmax(nrm, fabs(v));
+    }
+    if (two) nrm = sqrt(nrm);
+    keep_r[z] = nrm > a.tau ? 1 : 0;
+  }
+  for (int z = tid; z < mcc; z += blockDim.x) {
+    const double* col = Rp + (int64_t)z * q;
+    double nrm = 0.0;
+    for (int r = 0; r < q; ++r) {
+      double acc = 0.0;
+      for (int t = 0; t < q; ++t) acc = fma(sW[r * q + t], col[t], acc);
+      nrm = two ? fma(acc, acc, nrm) : fmax(nrm, fabs(acc));
+    }
+    if (two) nrm = sqrt(nrm);
+    keep_c[z] = nrm > a.tau ? 1 : 0;
+  }
+  __syncthreads();
+}
+
 // Returns false (uniformly) when the block reported an error.
-__device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int slot, Lds& s,
+__device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int slot, Lds& s,
                              double* s_dyn) {
   const int tid = threadIdx.x;
   const int f = a.bstart[K], l = a.bstart[K + 1] - 1, q = l - f + 1;
@@ -437,12 +608,12 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
   double flops = 0.0, ubytes = 0.0;
 
   // ---------------- predecessors, announcement, then candidates
-  const int np = load_preds(a, a.col_cnt, a.col_list, a.col_ovf, K, s.pred, s.misc);
+  const int np = load_preds(a, a.col_cnt, a.col_list, a.col_ovf, K, s.g.pred, s.misc);
   if (np < 0) {
     if (tid == 0) raise_error(a, kDevPredOverflow, K);
     return false;
   }
-  const int npr = load_preds(a, a.row_cnt, a.row_list, a.row_ovf, K, s.rpred, s.misc);
+  const int npr = load_preds(a, a.row_cnt, a.row_list, a.row_ovf, K, s.g.rpred, s.misc);
   if (npr < 0) {
     if (tid == 0) raise_error(a, kDevPredOverflow, K);
     return false;
@@ -457,12 +628,12 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
     return false;
   }
   if (tid == 0) trace_at(d, K, 2, wall_clock64());
-  const int mc = build_candidates(s, s.cand, a.cp, a.ri, f, l, l + 1, s.pred, np, a, true, f, l);
+  const int mc = build_candidates(s, s.cand, a.cp, a.ri, f, l, l + 1, s.g.pred, np, a, true, f, l);
   if (mc < 0) {
     if (tid == 0) raise_error(a, kDevCandOverflow, K);
     return false;
   }
-  const int mcc = build_candidates(s, s.candc, a.rp, a.ci, f, l, l + 1, s.rpred, npr, a, false,
+  const int mcc = build_candidates(s, s.candc, a.rp, a.ci, f, l, l + 1, s.g.rpred, npr, a, false,
                                    1, 0);
   if (mcc < 0) {
     if (tid == 0) raise_error(a, kDevCandOverflow, K);
@@ -487,7 +658,7 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
   }
   __syncthreads();
   for (int pi = 0; pi < np; ++pi) {
-    const int J = s.pred[pi];
+    const int J = s.g.pred[pi];
     const int pJ = a.bstart[J + 1] - a.bstart[J];
     const int nRJ = a.nr[J], nCJ = a.nc[J];
     const int32_t* RJ = a.idx_heap + a.roff[J];
@@ -544,7 +715,7 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
   }
   __syncthreads();
   for (int pi = 0; pi < npr; ++pi) {
-    const int J = s.rpred[pi];
+    const int J = s.g.rpred[pi];
     const int pJ = a.bstart[J + 1] - a.bstart[J];
     const int nRJ = a.nr[J], nCJ = a.nc[J];
     const int32_t* RJ = a.idx_heap + a.roff[J];
@@ -594,107 +765,16 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
   // q x q perturbed pivot block and work/inverse: LDS up to width 64,
   // the slot's scratch beyond the panels for wider blocks
   double* big = Rp + (int64_t)kCandCap * q;
-  double* sS = q <= kLdsPivotWidth ? s_dyn : big;
-  double* sW = q <= kLdsPivotWidth ? s_dyn + q * q : big + q * q;
-  for (int e = tid; e < q * q; e += blockDim.x) sS[e] = Cp[e];
-  if (tid == 0) s.misc[12] = 0;
-  __syncthreads();
-  // all-zero columns, then all-zero rows, are perturbed before factoring
-  for (int j = tid; j < q; j += blockDim.x) {
-    bool zero = true;
-    for (int i = 0; i < q; ++i) zero = zero && sS[i * q + j] == 0.0;
-    if (zero) {
-      perturb_column(sS, q, j, a);
-      s.misc[12] = 1;
-    }
-  }
-  __syncthreads();
-  for (int i = tid; i < q; i += blockDim.x) {
-    bool zero = true;
-    for (int j = 0; j < q; ++j) zero = zero && sS[i * q + j] == 0.0;
-    if (zero) {
-      perturb_row(sS, q, i, a);
-      s.misc[12] = 1;
-    }
-  }
-  __syncthreads();
-  int rounds = s.misc[12];
-  for (int attempt = 0;; ++attempt) {
-    double mx = 0.0;
-    int finite = 1;
-    for (int e = tid; e < q * q; e += blockDim.x) {
-      double v = sS[e];
-      sW[e] = v;
-      if (!isfinite(v)) finite = 0;
-      mx = fmax(mx, fabs(v));
-    }
-    mx = wave_max(mx);
-    finite = __all(finite);
-    if (tid == 0) {
-      s.misc[13] = 1;
-      s.smax = 0.0;
-    }
-    __syncthreads();
-    if ((tid & 63) == 0) {
-      if (!finite) s.misc[13] = 0;
-      // non-negative doubles order like their bit patterns
-      atomicMax(reinterpret_cast<unsigned long long*>(&s.smax),
-                (unsigned long long)__double_as_longlong(mx));
-    }
-    __syncthreads();
-    const double smax = s.smax;
-    bool ok = s.misc[13] && gauss_jordan_inverse(sW, q, smax, a.pivot_eps, s.f, s.ip, s.misc);
-    __syncthreads();
-    if (ok) break;
-    if (attempt == 3) {
-      if (tid == 0) raise_error(a, kDevSingular, K);
-      return false;
-    }
-    for (int j = tid; j < q; j += blockDim.x) perturb_column(sS, q, j, a);
-    __syncthreads();
-    for (int i = tid; i < q; i += blockDim.x) perturb_row(sS, q, i, a);
-    __syncthreads();
-    ++rounds;
-  }
-  if (tid == 0 && rounds > 0) atomicAdd(a.n_perturbed, 1);
-  for (int e = tid; e < q * q; e += blockDim.x) {
-    a.dval[a.doff[K] + e] = sW[e];
-    a.sval[a.doff[K] + e] = sS[e];
-  }
+  const bool lds = a.lds_pivot && q <= kLdsPivotWidth;
+  double* sS = lds ? s_dyn : big;
+  double* sW = lds ? s_dyn + q * q : big + q * q;
+  if (!pivot_block<false>(a, K, q, Cp, sS, sW, s)) return false;
 
   if (tid == 0) trace_at(d, K, 10, wall_clock64());
   // ---------------- drop: rows of L (scaled) and columns of U (D R)
   int* keep_r = s.hash;                 // flags for rows q..mc-1
   int* keep_c = s.hash + kCandCap;      // flags for cols 0..mcc-1
-  const bool two = a.drop_norm == 1;
-  for (int z = q + tid; z < mc; z += blockDim.x) {
-    const double* row = Cp + (int64_t)z * q;
-    double v[16];
-    double nrm = 0.0;
-    for (int c0 = 0; c0 < q; c0 += 16) {
-      const int cn = min(16, q - c0);
-      for (int c = 0; c < cn; ++c) v[c] = 0.0;
-      for (int t = 0; t < q; ++t) {
-        const double x = row[t];
-        for (int c = 0; c < cn; ++c) v[c] = fma(x, sW[t * q + c0 + c], v[c]);
-      }
-      for (int c = 0; c < cn; ++c) nrm = two ? fma(v[c], v[c], nrm) : fmax(nrm, fabs(v[c]));
-    }
-    if (two) nrm = sqrt(nrm);
-    keep_r[z] = nrm > a.tau ? 1 : 0;
-  }
-  for (int z = tid; z < mcc; z += blockDim.x) {
-    const double* col = Rp + (int64_t)z * q;
-    double nrm = 0.0;
-    for (int r = 0; r < q; ++r) {
-      double acc = 0.0;
-      for (int t = 0; t < q; ++t) acc = fma(sW[r * q + t], col[t], acc);
-      nrm = two ? fma(acc, acc, nrm) : fmax(nrm, fabs(acc));
-    }
-    if (two) nrm = sqrt(nrm);
-    keep_c[z] = nrm > a.tau ? 1 : 0;
-  }
-  __syncthreads();
+  drop_flags(a, Cp, Rp, mc, mcc, q, sW, keep_r, keep_c);
   if (tid == 0) trace_at(d, K, 11, wall_clock64());
   constexpr int kPer = kCandCap / kThreads;  // flags per thread
   int fr[kPer], fc[kPer];
@@ -824,7 +904,7 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
   add_successor_counts(a, d, TRout, ntr, TCout, ntc, K);
   // publish: every write and count of this block is visible before the
   // retraction
-  __threadfence();
+  release_agent();
   __syncthreads();
   if (tid == 0) trace_at(d, K, 15, wall_clock64());
   retract(a, d, s, na, K);
@@ -832,10 +912,583 @@ __device__ bool factor_block(const FactorArgs& a, const FlowArgs& d, int K, int 
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// Fast path for narrow blocks (q <= kFastWidth, at most kFastPreds
+// predecessors, lists, candidates and panels within LDS).  Same arithmetic
+// in the same order as factor_block, so both paths give identical bits; it
+// differs in how data moves: a few batched rounds of global loads instead of
+// one round per predecessor, panels in LDS, rank sorts, and the update terms
+// L_J(i,:) W_J(:,j) computed for all predecessors at once, then subtracted
+// in predecessor order.  Returns kFastFallback (before any global side
+// effect other than the started flag) when the block does not fit.
+// ---------------------------------------------------------------------------
+enum FastResult : int { kFastDone = 0, kFastFallback = 1, kFastError = 2 };
+
+// Segments of the staged lists: 0 rows of A's block column K (CSC), 1 columns
+// of A's block row K (CSR), then R_J and C_J of every column predecessor,
+// then R_J and C_J of every row predecessor.
+__device__ __forceinline__ const int32_t* fast_list(const FactorArgs& a, const Lds& s, int sg,
+                                                    int np, int npr) {
+  if (sg == 0) return a.ri + s.x.cpk[0];
+  if (sg == 1) return a.ci + s.x.rpk[0];
+  int t = sg - 2;
+  if (t < np) return a.idx_heap + s.x.meta[t].roff;
+  t -= np;
+  if (t < np) return a.idx_heap + s.x.meta[t].coff;
+  t -= np;
+  if (t < npr) return a.idx_heap + s.x.meta[np + t].roff;
+  t -= npr;
+  return a.idx_heap + s.x.meta[np + t].coff;
+}
+
+// Last s in [0, n) with off[s] <= e (off ascending, off[n] > e).
+__device__ __forceinline__ int last_le(const int* off, int n, int e) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= e)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const FlowArgs& d, int K, Lds& s,
+                                 double* s_dyn) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  constexpr int kBatch = kFastStage / kThreads;
+  int* stage = s.x.stage;
+  // ---- round 1: predecessor counts and inline lists, block range
+  int* rawc = stage;
+  int* rawr = stage + kFastPreds;
+  if (tid < kListCap) {
+    rawc[tid] = a.col_list[(int64_t)K * kListCap + tid];
+  } else if (tid >= 64 && tid < 64 + kListCap) {
+    rawr[tid - 64] = a.row_list[(int64_t)K * kListCap + tid - 64];
+  } else if (tid == 128) {
+    s.misc[0] = a.col_cnt[K];
+  } else if (tid == 129) {
+    s.misc[1] = a.row_cnt[K];
+  } else if (tid == 130) {
+    s.misc[2] = a.bstart[K];
+  } else if (tid == 131) {
+    s.misc[3] = a.bstart[K + 1];
+  } else if (tid == 132) {
+    __hip_atomic_store(&d.started[K], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    atomicMax(d.max_depth, __hip_atomic_load(&d.depth[K], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1);
+  }
+  if (tid == 0) s.misc[8] = 0;
+  __syncthreads();
+  const int np = s.misc[0], npr = s.misc[1];
+  const int f = s.misc[2], l = s.misc[3] - 1, q = l - f + 1;
+  if (q > kFastWidth || np + npr > kFastPreds || !a.lds_pivot) return kFastFallback;
+  if (np > kListCap || npr > kListCap) {
+    // overflow chains: one serial walk per list
+    if ((tid == 0 && np > kListCap) || (tid == 64 && npr > kListCap)) {
+      const bool col = tid == 0;
+      const int cnt = col ? np : npr;
+      int* raw = col ? rawc : rawr;
+      int node = col ? a.col_ovf[K] : a.row_ovf[K];
+      int at = kListCap;
+      while (node >= 0 && at < cnt) {
+        raw[at++] = a.ovf_j[node];
+        node = a.ovf_next[node];
+      }
+      if (at != cnt) s.misc[8] = 1;
+    }
+    __syncthreads();
+    if (s.misc[8]) return kFastFallback;  // the general path reports it
+  }
+  // ascending predecessor order (entries are distinct): rank sort
+  for (int t = tid; t < np + npr; t += nt) {
+    const bool col = t < np;
+    const int* raw = col ? rawc : rawr;
+    const int m = col ? np : npr, i = col ? t : t - np;
+    const int v = raw[i];
+    int r = 0;
+    for (int u = 0; u < m; ++u) r += raw[u] < v;
+    (col ? s.x.pred : s.x.rpred)[r] = v;
+  }
+  __syncthreads();
+
+  // ---- round 2: predecessor data, A's pointers of K; clear the hash
+  for (int t = tid; t < np + npr; t += nt) {
+    const int J = t < np ? s.x.pred[t] : s.x.rpred[t - np];
+    PredMeta& m = s.x.meta[t];
+    m.roff = a.roff[J];
+    m.coff = a.coff[J];
+    m.loff = a.loff[J];
+    m.woff = a.woff[J];
+    m.troff = a.troff[J];
+    m.tcoff = a.tcoff[J];
+    m.nr = a.nr[J];
+    m.nc = a.nc[J];
+    m.ntr = a.ntr[J];
+    m.ntc = a.ntc[J];
+    m.p = a.bstart[J + 1] - a.bstart[J];
+  }
+  if (tid >= 128 && tid <= 128 + q) s.x.cpk[tid - 128] = a.cp[f + tid - 128];
+  if (tid >= 160 && tid <= 160 + q) s.x.rpk[tid - 160] = a.rp[f + tid - 160];
+  for (int t = tid; t < kHashSlots; t += nt) s.hash[t] = -1;
+  if (tid == 0) {
+    s.misc[4] = 0;
+    s.misc[5] = 0;
+    s.misc[6] = 0;
+    s.misc[7] = 0;
+  }
+  __syncthreads();
+  if (tid == 0) trace_at(d, K, 2, wall_clock64());
+  const int nseg = 2 + 2 * (np + npr);
+  {
+    int len = 0;
+    if (tid == 0) {
+      len = (int)(s.x.cpk[q] - s.x.cpk[0]);
+    } else if (tid == 1) {
+      len = (int)(s.x.rpk[q] - s.x.rpk[0]);
+    } else if (tid < nseg) {
+      int t = tid - 2;
+      if (t < np) {
+        len = s.x.meta[t].nr;
+      } else if ((t -= np) < np) {
+        len = s.x.meta[t].nc;
+      } else if ((t -= np) < npr) {
+        len = s.x.meta[np + t].nr;
+      } else {
+        t -= npr;
+        len = s.x.meta[np + t].nc;
+      }
+    }
+    int total = 0;
+    const int off = wg_exclusive_scan(len, s.scan, &total);
+    if (tid < nseg) s.x.segoff[tid] = off;
+    if (tid == 0) s.x.segoff[nseg] = total;
+    if (total > kFastStage) return kFastFallback;
+    __syncthreads();
+  }
+  const int* segoff = s.x.segoff;
+  const int total = segoff[nseg];
+
+  // ---- round 3: stage every list; candidate rows (keys r) and columns
+  // (keys ~c) beyond the block go to one hash
+  {
+    int v[kBatch];
+    for (int k = 0; k < kBatch; ++k) {
+      const int e = tid + k * nt;
+      if (e < total) {
+        const int sg = last_le(segoff, nseg, e);
+        v[k] = fast_list(a, s, sg, np, npr)[e - segoff[sg]];
+      }
+    }
+    for (int k = 0; k < kBatch; ++k) {
+      const int e = tid + k * nt;
+      if (e >= total) break;
+      stage[e] = v[k];
+      const int sg = last_le(segoff, nseg, e);
+      const bool rowc = sg == 0 || (sg >= 2 && sg < 2 + np);
+      const bool colc = sg == 1 || sg >= 2 + 2 * np + npr;
+      if ((rowc || colc) && v[k] > l)
+        if (!hash_insert(s.hash, rowc ? v[k] : ~v[k], &s.misc[4])) s.misc[5] = 1;
+    }
+  }
+  __syncthreads();
+  if (s.misc[5] || s.misc[4] > 2 * kFastExtra) return kFastFallback;
+  // positions inside the predecessors' sorted lists
+  for (int t = tid; t < np + npr; t += nt) {
+    PredMeta& m = s.x.meta[t];
+    if (t < np) {
+      const int* R = stage + segoff[2 + t];
+      const int* C = stage + segoff[2 + np + t];
+      m.lo = lower_bound(C, m.nc, f);
+      m.hi = lower_bound(C, m.nc, l + 1);
+      m.lo2 = lower_bound(R, m.nr, f);
+    } else {
+      const int u = t - np;
+      const int* R = stage + segoff[2 + 2 * np + u];
+      const int* C = stage + segoff[2 + 2 * np + npr + u];
+      m.lo = lower_bound(R, m.nr, f);
+      m.hi = lower_bound(R, m.nr, l + 1);
+      m.lo2 = lower_bound(C, m.nc, l + 1);
+    }
+  }
+  int* tmpR = reinterpret_cast<int*>(s.x.buf);
+  int* tmpC = tmpR + kFastExtra;
+  for (int t = tid; t < kHashSlots; t += nt) {
+    const int key = s.hash[t];
+    if (key >= 0) {
+      const int o = atomicAdd(&s.misc[6], 1);
+      if (o < kFastExtra) tmpR[o] = key;
+    } else if (key <= -2) {
+      const int o = atomicAdd(&s.misc[7], 1);
+      if (o < kFastExtra) tmpC[o] = ~key;
+    }
+  }
+  __syncthreads();
+  const int nrow = s.misc[6], ncol = s.misc[7];
+  const int mc = q + nrow, mcc = ncol;
+  if (nrow > kFastExtra || ncol > kFastExtra || (mc + mcc) * q > kFastBuf - kThreads)
+    return kFastFallback;
+  for (int t = tid; t < nrow + ncol; t += nt) {
+    const bool row = t < nrow;
+    const int* src = row ? tmpR : tmpC;
+    const int m = row ? nrow : ncol, i = row ? t : t - nrow;
+    const int v = src[i];
+    int r = 0;
+    for (int u = 0; u < m; ++u) r += src[u] < v;
+    if (row)
+      s.cand[q + r] = v;
+    else
+      s.candc[r] = v;
+  }
+  for (int t = tid; t < q; t += nt) s.cand[t] = f + t;
+  // update terms per predecessor: column panel (rows >= f) x (columns in K),
+  // row panel (rows in K) x (columns > l)
+  int terms = 0;
+  if (tid < np + npr) {
+    const PredMeta& m = s.x.meta[tid];
+    terms = tid < np ? (m.nr - m.lo2) * (m.hi - m.lo) : (m.hi - m.lo) * (m.nc - m.lo2);
+  }
+  int nterms = 0;
+  const int toff = wg_exclusive_scan(terms, s.scan, &nterms);
+  if (tid < np + npr) s.x.meta[tid].ioff = toff;
+  __syncthreads();
+  if (tid == 0) {
+    trace_at(d, K, 3, wall_clock64());
+    trace_at(d, K, 16, (unsigned long long)np);
+    trace_at(d, K, 17, (unsigned long long)npr);
+    trace_at(d, K, 18, (unsigned long long)mc);
+    trace_at(d, K, 19, (unsigned long long)mcc);
+  }
+
+  // ---- round 4: A's values into the panels, update terms (chunked)
+  double* Cp = s.x.buf;                 // mc x q, row-major
+  double* Rp = Cp + mc * q;             // mcc x q (column z of the row panel)
+  double* Tm = Rp + mcc * q;            // update terms
+  const int cap = kFastBuf - (mc + mcc) * q;
+  for (int e = tid; e < (mc + mcc) * q; e += nt) Cp[e] = 0.0;
+  __syncthreads();
+  {
+    const int nA0 = segoff[1], nA1 = segoff[2] - segoff[1];
+    for (int e = tid; e < nA0 + nA1; e += nt) {
+      if (e < nA0) {
+        const int r = stage[e];
+        if (r >= f) {
+          const long long m = s.x.cpk[0] + e;
+          int c = 0;
+          while (s.x.cpk[c + 1] <= m) ++c;
+          Cp[lower_bound(s.cand, mc, r) * q + c] = a.cv[m];
+        }
+      } else {
+        const int e1 = e - nA0;
+        const int c = stage[nA0 + e1];
+        if (c > l) {
+          const long long m = s.x.rpk[0] + e1;
+          int r = 0;
+          while (s.x.rpk[r + 1] <= m) ++r;
+          Rp[lower_bound(s.candc, mcc, c) * q + r] = a.rv[m];
+        }
+      }
+    }
+  }
+  const int npt = np + npr;
+  for (int i0 = 0; i0 < nterms; i0 += cap) {
+    const int i1 = min(nterms, i0 + cap);
+    for (int e = i0 + tid; e < i1; e += nt) {
+      int t = 0;
+      {
+        int lo = 0, hi = npt;  // last t with ioff <= e
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s.x.meta[mid].ioff <= e)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        t = lo;
+      }
+      const PredMeta& m = s.x.meta[t];
+      const int w = e - m.ioff;
+      int ri, cj;
+      if (t < np) {
+        const int nc = m.hi - m.lo;
+        ri = m.lo2 + w / nc;
+        cj = m.lo + w % nc;
+      } else {
+        const int nr = m.hi - m.lo;
+        ri = m.lo + w % nr;
+        cj = m.lo2 + w / nr;
+      }
+      Tm[e - i0] = dot_strided(a.val_heap + m.loff + (int64_t)ri * m.p,
+                               a.val_heap + m.woff + (int64_t)cj * m.p, m.p);
+    }
+    __syncthreads();
+    for (int t = 0; t < npt; ++t) {
+      const PredMeta& m = s.x.meta[t];
+      const int t0 = max(i0, m.ioff);
+      const int t1 = min(i1, t + 1 < npt ? s.x.meta[t + 1].ioff : nterms);
+      if (t0 >= t1) continue;
+      for (int e = t0 + tid; e < t1; e += nt) {
+        const int w = e - m.ioff;
+        if (t < np) {
+          const int nc = m.hi - m.lo;
+          const int r = stage[segoff[2 + t] + m.lo2 + w / nc];
+          const int c = stage[segoff[2 + np + t] + m.lo + w % nc] - f;
+          Cp[lower_bound(s.cand, mc, r) * q + c] -= Tm[e - i0];
+        } else {
+          const int u = t - np;
+          const int nr = m.hi - m.lo;
+          const int r = stage[segoff[2 + 2 * np + u] + m.lo + w % nr] - f;
+          const int c = stage[segoff[2 + 2 * np + npr + u] + m.lo2 + w / nr];
+          Rp[lower_bound(s.candc, mcc, c) * q + r] -= Tm[e - i0];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned long long now = wall_clock64();
+    trace_at(d, K, 8, now);
+    trace_at(d, K, 9, now);
+  }
+
+  // ---- pivot block and drop test (shared with the general path)
+  double* sS = s_dyn;
+  double* sW = s_dyn + q * q;
+  if (tid < 64) {
+    const bool ok = pivot_block<true>(a, K, q, Cp, sS, sW, s);
+    if (tid == 0) s.misc[14] = ok ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s.misc[14]) return kFastError;
+  if (tid == 0) trace_at(d, K, 10, wall_clock64());
+  int* keep_r = s.hash;
+  int* keep_c = s.hash + kCandCap;
+  int* rblk = stage;            // block of candidate row z
+  int* cblk = stage + 512;      // block of candidate column z
+  int* rbp = stage + 1024;      // position in TR_K of the first kept row of a block
+  int* cbp = stage + 1536;
+  int* trL = stage + 2048;      // TR_K and TC_K
+  int* tcL = stage + 2560;
+  for (int z = q + tid; z < mc; z += nt) rblk[z] = a.blockOf[s.cand[z]];
+  for (int z = tid; z < mcc; z += nt) cblk[z] = a.blockOf[s.candc[z]];
+  drop_flags(a, Cp, Rp, mc, mcc, q, sW, keep_r, keep_c);
+  if (tid == 0) trace_at(d, K, 11, wall_clock64());
+
+  // ---- positions of kept rows / columns and of their distinct blocks
+  // (one wave, 64 candidates per step)
+  if (tid < 64) {
+    const unsigned long long lt = (1ull << tid) - 1ull;
+    for (int side = 0; side < 2; ++side) {
+      int* keep = side ? keep_c : keep_r;
+      const int* blk = side ? cblk : rblk;
+      int* bp = side ? cbp : rbp;
+      const int z0 = side ? 0 : q, z1 = side ? mcc : mc;
+      int cpos = 0, cb = 0, lastb = -1;
+      for (int zb = z0; zb < z1; zb += 64) {
+        const int z = zb + tid;
+        const bool in = z < z1;
+        const int kp = in ? keep[z] : 0;
+        const int b = in ? blk[z] : -1;
+        const unsigned long long m = __ballot(kp);
+        const unsigned long long below = m & lt;
+        const int pl = below ? 63 - __clzll(below) : 0;
+        const int pb = __shfl(b, pl, 64);
+        const bool nb = kp && (below ? pb : lastb) != b;
+        const unsigned long long bm = __ballot(nb);
+        if (in) {
+          keep[z] = kp ? cpos + __popcll(below) : -1;
+          bp[z] = nb ? cb + __popcll(bm & lt) : -1;
+        }
+        if (m) lastb = __shfl(b, 63 - __clzll(m), 64);
+        cpos += __popcll(m);
+        cb += __popcll(bm);
+      }
+      if (tid == 0) {
+        s.misc[20 + 2 * side] = cpos;
+        s.misc[21 + 2 * side] = cb;
+      }
+    }
+  }
+  __syncthreads();
+  const int mk = s.misc[20], ntr = s.misc[21], nk = s.misc[22], ntc = s.misc[23];
+  if (tid == 0) {
+    const unsigned long long ni = (unsigned long long)(mk + nk + ntr + ntc);
+    unsigned long long vo = atomicAdd(a.val_top, (unsigned long long)(mk + nk) * q);
+    unsigned long long io = atomicAdd(a.idx_top, ni);
+    bool over = vo + (unsigned long long)(mk + nk) * q > (unsigned long long)a.val_cap ||
+                io + ni > (unsigned long long)a.idx_cap;
+    s.misc[16] = over ? 1 : 0;
+    s.off[0] = (long long)vo;
+    s.off[1] = (long long)io;
+    if (over) raise_error(a, kDevHeapOverflow, K);
+  }
+  __syncthreads();
+  if (s.misc[16]) return kFastError;
+  if (tid == 0) trace_at(d, K, 12, wall_clock64());
+  const int64_t vo = s.off[0];
+  const int64_t io = s.off[1];
+  double* Lout = a.val_heap + vo;
+  double* Wout = Lout + (int64_t)mk * q;
+  int32_t* Rout = a.idx_heap + io;
+  int32_t* Cout = Rout + mk;
+  int32_t* TRout = Cout + nk;
+  int32_t* TCout = TRout + ntr;
+  for (int w = tid; w < (mc - q) * q; w += nt) {
+    const int z = q + w / q, c = w % q;
+    const int p = keep_r[z];
+    if (p >= 0) {
+      double acc = 0.0;
+      for (int t = 0; t < q; ++t) acc = fma(Cp[z * q + t], sW[t * q + c], acc);
+      Lout[(int64_t)p * q + c] = acc;
+    }
+  }
+  for (int w = tid; w < mcc * q; w += nt) {
+    const int z = w / q, r = w % q;
+    const int p = keep_c[z];
+    if (p >= 0) Wout[(int64_t)p * q + r] = Rp[z * q + r];
+  }
+  for (int z = q + tid; z < mc; z += nt) {
+    const int p = keep_r[z];
+    if (p >= 0) {
+      Rout[p] = s.cand[z];
+      const int b = rbp[z];
+      if (b >= 0) {
+        TRout[b] = rblk[z];
+        trL[b] = rblk[z];
+      }
+    }
+  }
+  for (int z = tid; z < mcc; z += nt) {
+    const int p = keep_c[z];
+    if (p >= 0) {
+      Cout[p] = s.candc[z];
+      const int b = cbp[z];
+      if (b >= 0) {
+        TCout[b] = cblk[z];
+        tcL[b] = cblk[z];
+      }
+    }
+  }
+  if (tid == 0) {
+    a.roff[K] = io;
+    a.nr[K] = mk;
+    a.coff[K] = io + mk;
+    a.nc[K] = nk;
+    a.loff[K] = vo;
+    a.woff[K] = vo + (int64_t)mk * q;
+    a.troff[K] = io + mk + nk;
+    a.ntr[K] = ntr;
+    a.tcoff[K] = io + mk + nk + ntr;
+    a.ntc[K] = ntc;
+    double flops = 0.0, ubytes = 0.0;
+    for (int t = 0; t < npt; ++t) {
+      const PredMeta& m = s.x.meta[t];
+      const int nr = t < np ? m.nr - m.lo2 : m.hi - m.lo;
+      const int nc = t < np ? m.hi - m.lo : m.nc - m.lo2;
+      flops += 2.0 * nr * nc * m.p;
+      ubytes += 8.0 * m.p * (nr + nc);
+    }
+    atomicAdd(a.flops, (unsigned long long)flops);
+    atomicAdd(a.upd_bytes, (unsigned long long)ubytes);
+  }
+  __syncthreads();
+  if (tid == 0) trace_at(d, K, 13, wall_clock64());
+  // K updates the row panels of the blocks of its rows of L and the column
+  // panels of the blocks of its columns of U
+  for (int t = tid; t < ntr + ntc; t += nt) {
+    if (t < ntr)
+      push_checked(a, d, a.row_cnt, a.row_list, a.row_ovf, trL[t], K);
+    else
+      push_checked(a, d, a.col_cnt, a.col_list, a.col_ovf, tcL[t - ntr], K);
+  }
+  __syncthreads();
+  if (tid == 0) trace_at(d, K, 14, wall_clock64());
+  add_successor_counts(a, d, trL, ntr, tcL, ntc, K);
+
+  // ---- K's own counts (as updater_set): A's entries of K in later blocks,
+  // TR_J > K of column predecessors, TC_J > K of row predecessors
+  int* cnt = s.cand;  // per hash slot, over cand[] and candc[]
+  for (int t = tid; t < kHashSlots; t += nt) {
+    s.hash[t] = -1;
+    cnt[t] = 0;
+  }
+  if (tid == 0) {
+    s.misc[4] = 0;
+    s.misc[5] = 0;
+  }
+  const int nseg2 = 2 + npt;
+  {
+    int len = 0;
+    if (tid == 0)
+      len = (int)(s.x.cpk[q] - s.x.cpk[0]);
+    else if (tid == 1)
+      len = (int)(s.x.rpk[q] - s.x.rpk[0]);
+    else if (tid < nseg2)
+      len = tid - 2 < np ? s.x.meta[tid - 2].ntr : s.x.meta[tid - 2].ntc;
+    int tot = 0;
+    const int off = wg_exclusive_scan(len, s.scan, &tot);
+    if (tid < nseg2) s.x.segoff[tid] = off;
+    if (tid == 0) s.x.segoff[nseg2] = tot;
+    __syncthreads();
+  }
+  const int tot2 = s.x.segoff[nseg2];
+  for (int base = 0; base < tot2; base += kBatch * nt) {
+    int v[kBatch];
+    for (int k = 0; k < kBatch; ++k) {
+      const int e = base + tid + k * nt;
+      if (e < tot2) {
+        const int sg = last_le(s.x.segoff, nseg2, e);
+        const int i = e - s.x.segoff[sg];
+        if (sg == 0)
+          v[k] = a.bri[s.x.cpk[0] + i];
+        else if (sg == 1)
+          v[k] = a.bci[s.x.rpk[0] + i];
+        else if (sg - 2 < np)
+          v[k] = a.idx_heap[s.x.meta[sg - 2].troff + i];
+        else
+          v[k] = a.idx_heap[s.x.meta[sg - 2].tcoff + i];
+      }
+    }
+    for (int k = 0; k < kBatch; ++k) {
+      const int e = base + tid + k * nt;
+      if (e < tot2 && v[k] > K) {
+        const int h = hash_insert_at(s.hash, v[k], &s.misc[4]);
+        if (h < 0)
+          s.misc[5] = 1;
+        else
+          atomicAdd(&cnt[h], 1);
+      }
+    }
+  }
+  __syncthreads();
+  if (s.misc[5]) {
+    if (tid == 0) raise_error(a, kDevAnnOverflow, K);
+    return kFastError;
+  }
+  if (tid == 0) trace_at(d, K, 15, wall_clock64());
+  // publish: every write and count of this block is visible before the
+  // retraction
+  release_agent();
+  __syncthreads();
+  const int dK = __hip_atomic_load(&d.depth[K], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+  for (int t = tid; t < kHashSlots; t += nt) {
+    const int B = s.hash[t];
+    if (B < 0) continue;
+    const int c = cnt[t];
+    atomicMax(&d.depth[B], dK);
+    const int old = atomicSub(&d.pending[B], c);
+    if (old < c) raise_error(a, kDevProtocol, K);
+    if (old == c) push_ready(d, B, K, c);
+  }
+  if (tid == 0) trace_at(d, K, 4, wall_clock64());
+  return kFastDone;
+}
+
 // Worker: queue positions blockIdx.x, blockIdx.x + gridDim.x, ... (the
 // launch is cooperative: all workers are resident).  Position p holds the
 // p-th block to become ready; the workgroup waits until it is filled.
-__global__ void __launch_bounds__(kThreads) factor_worker_kernel(FactorArgs a, FlowArgs d) {
+__global__ void __launch_bounds__(kThreads, 2) factor_worker_kernel(FactorArgs a, FlowArgs d) {
   __shared__ Lds s;
   extern __shared__ double s_dyn[];
   const int slot = blockIdx.x;
@@ -853,12 +1506,15 @@ __global__ void __launch_bounds__(kThreads) factor_worker_kernel(FactorArgs a, F
       if (__syncthreads_and(K >= 0)) break;
       __builtin_amdgcn_s_sleep(2);
     }
-    __threadfence();
+    acquire_agent();
     if (threadIdx.x == 0) {
       trace_at(d, K, 1, wall_clock64());
       trace_at(d, K, 7, (unsigned long long)blockIdx.x);
     }
-    factor_block(a, d, K, slot, s, s_dyn);
+    if (!a.fast_path || factor_block_fast(a, d, K, s, s_dyn) == kFastFallback) {
+      __syncthreads();
+      factor_block(a, d, K, slot, s, s_dyn);
+    }
     __syncthreads();
   }
 }
@@ -1025,6 +1681,8 @@ bilu_status factor_device(bilu_handle* h, double tau) {
     a.beta_one = h->opt.beta_one;
     a.drop_norm = h->opt.drop_norm;
     a.update_prec = h->opt.update_precision;
+    a.fast_path = h->opt.factor_path == 0 ? 1 : 0;
+    a.lds_pivot = dyn > 0 ? 1 : 0;
     a.roff = h->d_roff.p; a.nr = h->d_nr.p; a.coff = h->d_coff.p; a.nc = h->d_nc.p;
     a.loff = h->d_loff.p; a.woff = h->d_woff.p; a.doff = h->d_doff.p;
     a.dval = h->d_dval.p; a.sval = h->d_sval.p;

@@ -78,6 +78,8 @@ struct FactorArgs {
   const int32_t* blockOf; // [n]
   double tau, alpha, pert_tau, pert_rho, pivot_eps;
   int beta_one, drop_norm, update_prec;
+  int fast_path;                   // narrow blocks take the LDS-resident path
+  int lds_pivot;                   // dynamic LDS holds 2 q^2 doubles for every block
   // factor storage, per block
   int64_t* roff;  int32_t* nr;     // rows of L  : idx heap
   int64_t* coff;  int32_t* nc;     // cols of U  : idx heap

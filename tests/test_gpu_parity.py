@@ -96,6 +96,8 @@ CASES = [
     ("cd3d_12_nd", lambda: (mg.workload("cd3d_12_b4").a, mg.workload("cd3d_12_b4").perm), 1e-2, {}),
     ("el3d_10_nd", lambda: (mg.workload("el3d_10_b3").a, mg.workload("el3d_10_b3").perm), 5e-3, {}),
     ("random_sparse", lambda: (mg.random_sparse(400, 0.01, seed=5, diag_shift=3.0), None), 1e-2, {}),
+    # dense rows: ILU(1,tau) grows blocks wider than 64 (pivots outside LDS)
+    ("wide_blocks", lambda: (mg.random_sparse(200, 0.5, seed=3, diag_shift=8.0), None), 1e-2, {}),
 ]
 
 
@@ -173,6 +175,26 @@ def test_deterministic_rerun():
         h.close()
     assert outs[0] == outs[1]
     del torch
+
+
+@pytest.mark.parametrize("name", ["cd3d_12_b4", "el3d_10_b3", "cd2d_32x32_b3"])
+def test_fast_and_general_paths_identical(name):
+    """The LDS-resident path for narrow blocks and the general path perform
+    the same arithmetic in the same order: the factors agree bit for bit."""
+    _torch()
+    from paper_1908_10169_amd import bilu
+    w = mg.workload(name)
+    say(f"[paths] {name} n={w.a.n}")
+    outs = []
+    for path in (0, 1):
+        h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=False, factor_path=path)
+        h.analyze(w.a, pre_perm=w.perm)
+        h.factor(w.tau)
+        f = h.export()
+        outs.append((f.starts.tobytes(), [r.tobytes() for r in f.R], [c.tobytes() for c in f.C],
+                     b"".join(x.tobytes() for x in f.L + f.W + f.D)))
+        h.close()
+    assert outs[0] == outs[1]
 
 
 def test_state_errors():
