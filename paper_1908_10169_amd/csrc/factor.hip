@@ -1564,7 +1564,13 @@ bilu_status factor_device(bilu_handle* h, double tau) {
   const int64_t n = h->n;
   std::vector<int32_t>& bs = h->bstart0;
   double t_sets = 0.0;
-  const int64_t nb = ilu1t_partition(h, tau, bs, &t_sets);
+  // ILU(1,tau) on the device; the host computation when a kernel capacity
+  // was exceeded (or the step is off)
+  int64_t nb = h->opt.use_ilu1t ? ilu1t_partition_device(h, tau, bs, &t_sets) : -1;
+  if (nb < 0) {
+    (void)hipGetLastError();
+    nb = ilu1t_partition(h, tau, bs, &t_sets);
+  }
   auto t1 = clk::now();
   h->stats.t_ilu1t = std::chrono::duration<double>(t1 - t0).count();
   h->stats.t_phase[0] = t_sets;

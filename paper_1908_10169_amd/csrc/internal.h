@@ -186,6 +186,10 @@ struct bilu_handle {
   std::vector<int32_t> bstart0;       // initial partition
   bilu::DevArray<int64_t> d_troff, d_tcoff;
   bilu::DevArray<unsigned long long> d_trace;  // collect_timing == 2
+  // ILU(1,tau) on the device: unit starts, diagonal, padded sets, counts
+  bilu::DevArray<int64_t> d_ilu_gs;
+  bilu::DevArray<double> d_ilu_dg;
+  bilu::DevArray<int32_t> d_ilu_set, d_ilu_cnt;
   bilu::DevArray<int32_t> d_ntr, d_ntc, d_bri, d_bci;
   bilu::DevArray<int> d_flow;        // pending, started, enqueued, depth, queue, tail, max depth
   unsigned long long wait_ticks = 0; // bound of one dependency wait (wall-clock ticks)
@@ -255,6 +259,10 @@ bilu_status analyze_host(bilu_handle* h, int64_t n, const int64_t* rowptr,
                          const int32_t* colind, const double* val);
 int64_t ilu1t_partition(const bilu_handle* h, double tau, std::vector<int32_t>& bstart,
                         double* t_sets = nullptr);
+
+// ilu1t.hip
+int64_t ilu1t_partition_device(bilu_handle* h, double tau, std::vector<int32_t>& bstart,
+                               double* t_sets);
 
 // factor.hip
 bilu_status factor_device(bilu_handle* h, double tau);
