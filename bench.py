@@ -101,7 +101,7 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
     kd = kernels[dom]
     achieved = kd["bytes"] / (kd["ms"] * 1e-3) / 1e9 if kd["ms"] > 0 else 0.0
-    roofline = {"kernel": {"factor": "factor_level_kernel",
+    roofline = {"kernel": {"factor": "factor_worker_kernel",
                            "apply": "forward_level+backward_level"}[dom],
                 "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None}
@@ -136,8 +136,12 @@ def main():
                          "device_ms_per_step": round(ko["ms"] / args.steps, 3)},
         "schur_update": {"tflops": round(upd_tflops, 6), "peak": FP64_PEAK_TFLOPS,
                          "frac": round(upd_tflops / FP64_PEAK_TFLOPS, 8)},
-        "phases_s": {"analyze": round(t_analyze, 4), "ilu1t_host": round(st["t_ilu1t"], 4),
+        "phases_s": {"analyze": round(t_analyze, 4), "ilu1t": round(st["t_ilu1t"], 4),
                      "factor": round(st["t_factor"], 4),
+                     "factor_host_phases": dict(zip(
+                         ["ilu1t_sets", "ilu1t_growth", "launch_prep", "factor_kernel",
+                          "aggregation", "apply_plan", "statistics"],
+                         [round(x, 4) for x in st["t_phase"][:7]])),
                      "factor_device_ms": round(dev["factor_ms"] / args.steps, 3),
                      "solve": round(info["seconds"], 4),
                      "apply_device_ms_each": round(dev["apply_ms"] / max(1, dev["n_apply"]), 4)},

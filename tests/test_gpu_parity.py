@@ -209,3 +209,39 @@ def test_state_errors():
     with pytest.raises(bilu.BiluError) as e:
         h.factor(1e-2)
     assert e.value.status == bilu.BILU_ERR_STATE
+
+
+def test_full_size_cd3d_64():
+    """The 64^3 x 4 convection-diffusion workload at full size, in the
+    benchmark's configuration: partition, every pattern, factors within the
+    tolerance and the FGMRES iteration count equal the oracle's."""
+    torch = _torch()
+    from oracle import Oracle, OracleOptions
+    from paper_1908_10169_amd import bilu
+    w = mg.workload("cd3d_64_b4")
+    say(f"[full] cd3d_64_b4 n={w.a.n} nnz={w.a.nnz}")
+    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=False)
+    h.analyze(w.a, pre_perm=w.perm)
+    h.factor(w.tau)
+    o = Oracle()
+    assert o.run(w.a, OracleOptions(tau=w.tau, use_aggregation=False), pre_perm=w.perm) == 0
+    say("[full] oracle done")
+    fl, fo = h.export(), o.factors()
+    assert np.array_equal(fl.perm, fo.perm)
+    assert np.array_equal(fl.starts_initial, fo.starts_initial)
+    assert np.array_equal(fl.starts, fo.starts)
+    for name in ("R", "C"):
+        x, y = getattr(fl, name), getattr(fo, name)
+        assert np.array_equal([len(v) for v in x], [len(v) for v in y]), name
+        assert np.array_equal(np.concatenate(x), np.concatenate(y)), name
+    for name in ("L", "W", "D"):
+        x = np.concatenate([v.ravel() for v in getattr(fl, name)])
+        y = np.concatenate([v.ravel() for v in getattr(fo, name)])
+        assert np.linalg.norm(x - y) <= TOL * np.linalg.norm(y), name
+    b = w.a.matvec(np.ones(w.a.n))
+    _, info_o = o.fgmres(b, restart=w.restart, rtol=1e-8)
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd)
+    info_l = h.fgmres(bd, xd, restart=w.restart, rtol=1e-8)
+    assert info_l["converged"] and info_l["iterations"] == info_o["iterations"]
+    h.close()
