@@ -34,11 +34,30 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--aggregation", type=int, default=-1,
                    help="1/0 forces progressive aggregation on/off (default: library default)")
+    p.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                   help="only copy BYTES between two device buffers twice (reference for the "
+                        "HBM byte counters of a profiler) and exit")
     return p.parse_args()
+
+
+def calibrate_copy(nbytes):
+    """A plain device-to-device copy of known size, for scaling FETCH_SIZE /
+    WRITE_SIZE counters: each copy reads and writes nbytes once."""
+    import torch
+    torch.cuda.set_device(0)
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": nbytes // 8 * 8, "copies": 2}), flush=True)
 
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: "
               f"sharding one factorization over several GPUs is not built.", flush=True)
@@ -104,7 +123,8 @@ def main():
     roofline = {"kernel": {"factor": "factor_worker_kernel",
                            "apply": "forward_level+backward_level"}[dom],
                 "bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6), "traffic": None}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
+                "traffic": measured_traffic(roofline_kernel_name(dom), w.name)}
     other = "apply" if dom == "factor" else "factor"
     ko = kernels[other]
     other_gbs = ko["bytes"] / (ko["ms"] * 1e-3) / 1e9 if ko["ms"] > 0 else 0.0
@@ -156,6 +176,31 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, agg, restart, rtol)
     print(json.dumps(out), flush=True)
+
+
+def roofline_kernel_name(dom):
+    return {"factor": "factor_worker_kernel", "apply": "forward_level+backward_level"}[dom]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE profile
+    of this kernel and workload (scaled by a plain copy), or None when there
+    is none or the kernel's sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{workload}_{kernel}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.startswith("{"):
+            rec = json.loads(line)
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return rec["traffic_bytes"] if h.hexdigest() == rec["sources_sha256"] else None
 
 
 def cpu_baseline(w, agg, restart, rtol):
