@@ -223,7 +223,7 @@ def cpu_baseline(w, agg, restart, rtol):
                          "solve": round(t_solve, 4)}}
 
 
-AGGREGATION_DEFAULT = False  # progressive aggregation on the GPU is enabled once built
+AGGREGATION_DEFAULT = True  # the full method: cosine + ILU(1,tau) blocking + progressive aggregation
 
 if __name__ == "__main__":
     main()

@@ -217,6 +217,7 @@ struct bilu_handle {
   bilu::DevArray<int32_t> f_idx;     // idx heap of the final factor
   bilu::DevArray<double> f_val, f_dval;
   bool final_is_initial = true;      // no merge happened: f_* alias the factor storage
+  bilu::DevArray<double> d_agg_scratch;  // merge workspace (4 w^2 doubles per slot)
   bilu::FactorView fv;               // the factor the apply uses
   // apply plan: predecessor blocks of the forward sweep (sorted, with the
   // range of their rows inside the block), successor blocks of the backward

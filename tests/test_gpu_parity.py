@@ -112,6 +112,41 @@ def test_factor_parity(name, make, tau, blocking):
     h.close()
 
 
+AGG_CASES = [c for c in CASES if c[0] in ("cd2d_nd", "cd2d_scalar", "cd3d_12_nd", "el3d_10_nd",
+                                          "random_sparse", "wide_blocks")]
+
+
+@pytest.mark.parametrize("name,make,tau,blocking", AGG_CASES, ids=[c[0] for c in AGG_CASES])
+def test_aggregated_parity(name, make, tau, blocking):
+    """Progressive aggregation (Sec. 3.5): the final partition and patterns
+    equal the oracle's (which merges during its sweep), the merged factors
+    agree within the tolerance, and the solver takes the same iterations."""
+    _torch()
+    a, perm = make()
+    say(f"[agg] {name} n={a.n} tau={tau} {blocking}")
+    o, h = run_pair(a, tau, perm, agg=True, **blocking)
+    assert h.stats()["merges"] == o.stats()["merges"]
+    fl = compare_factors(o, h)
+    assert len(fl.starts) < len(fl.starts_initial) or o.stats()["merges"] == 0
+    check_apply_and_solve(o, h, a)
+    h.close()
+
+
+def test_aggregation_to_the_cap():
+    """Diagonal input (everything kept): every block merges with the next
+    until the width cap, as the closed form of the decision says."""
+    _torch()
+    from paper_1908_10169_amd import bilu
+    n = 300
+    a = mg.dense_to_csr(np.diag(np.linspace(1.0, 2.0, n)))
+    say(f"[agg] diagonal n={n}")
+    o, h = run_pair(a, 0.0, None, agg=True, use_cosine=False, use_ilu1t=False)
+    st = h.export().starts
+    assert np.array_equal(np.diff(st), [128, 128, 44])
+    compare_factors(o, h)
+    del bilu
+
+
 def test_tau_zero_is_exact_lu():
     torch = _torch()
     a = mg.grid2d_random_blocks(12, 2, 4.0, seed=2)
@@ -211,7 +246,8 @@ def test_state_errors():
     assert e.value.status == bilu.BILU_ERR_STATE
 
 
-def test_full_size_cd3d_64():
+@pytest.mark.parametrize("agg", [False, True], ids=["plain", "aggregated"])
+def test_full_size_cd3d_64(agg):
     """The 64^3 x 4 convection-diffusion workload at full size, in the
     benchmark's configuration: partition, every pattern, factors within the
     tolerance and the FGMRES iteration count equal the oracle's."""
@@ -219,12 +255,13 @@ def test_full_size_cd3d_64():
     from oracle import Oracle, OracleOptions
     from paper_1908_10169_amd import bilu
     w = mg.workload("cd3d_64_b4")
-    say(f"[full] cd3d_64_b4 n={w.a.n} nnz={w.a.nnz}")
-    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=False)
+    say(f"[full] cd3d_64_b4 n={w.a.n} nnz={w.a.nnz} aggregation={agg}")
+    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=agg)
     h.analyze(w.a, pre_perm=w.perm)
     h.factor(w.tau)
     o = Oracle()
-    assert o.run(w.a, OracleOptions(tau=w.tau, use_aggregation=False), pre_perm=w.perm) == 0
+    assert o.run(w.a, OracleOptions(tau=w.tau, use_aggregation=agg), pre_perm=w.perm) == 0
+    assert h.stats()["merges"] == o.stats()["merges"]
     say("[full] oracle done")
     fl, fo = h.export(), o.factors()
     assert np.array_equal(fl.perm, fo.perm)
