@@ -135,6 +135,39 @@ __device__ __forceinline__ double dot_strided(const double* x, const double* y, 
   return acc;
 }
 
+// bfloat16 by round-to-nearest-even of the float value (NaN stays NaN).
+__device__ __forceinline__ uint16_t to_bf16(double x) {
+  uint32_t u = __float_as_uint((float)x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// One Schur-update term L_J(i,:) W_J(:,j) of length p, from value-heap
+// offsets lo (row of L_J) and wo (column of W_J): FP64, or FP32 / BF16 inputs
+// (the block's low-precision copy) with FP32 accumulation.
+__device__ __forceinline__ double update_term(const FactorArgs& a, int64_t lo, int64_t wo, int p) {
+  if (a.update_prec == 1) {
+    float acc = 0.0f;
+    for (int t = 0; t < p; ++t) acc = fmaf(a.lo32[lo + t], a.lo32[wo + t], acc);
+    return (double)acc;
+  }
+  if (a.update_prec == 2) {
+    float acc = 0.0f;
+    for (int t = 0; t < p; ++t) acc = fmaf(from_bf16(a.lo16[lo + t]), from_bf16(a.lo16[wo + t]), acc);
+    return (double)acc;
+  }
+  return dot_strided(a.val_heap + lo, a.val_heap + wo, p);
+}
+
+// Store a factor value (and its low-precision copy) at value-heap offset o.
+__device__ __forceinline__ void store_factor(const FactorArgs& a, int64_t o, double v) {
+  a.val_heap[o] = v;
+  if (a.update_prec == 1) a.lo32[o] = (float)v;
+  else if (a.update_prec == 2) a.lo16[o] = to_bf16(v);
+}
+
 // Sec. 3.6 perturbation of column j of the q x q row-major matrix m: the
 // largest-magnitude entry (lowest row on ties), or the diagonal when
 // 2|m_jj| >= |m_kj|, becomes m_kj (1 + rho beta) + sign(m_kj) tau alpha.
@@ -695,11 +728,12 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
     for (int w = tid; w < work; w += blockDim.x) {
       const int ri = r0 + w / ncol, cj = c0 + w % ncol;
       const int z = lower_bound(s.cand, mc, RJ[ri]);
-      const double acc = dot_strided(LJ + (int64_t)ri * pJ, WJ + (int64_t)cj * pJ, pJ);
+      const double acc =
+          update_term(a, a.loff[J] + (int64_t)ri * pJ, a.woff[J] + (int64_t)cj * pJ, pJ);
       Cp[(int64_t)z * q + (CJ[cj] - f)] -= acc;
     }
     flops += 2.0 * work * pJ;
-    ubytes += 8.0 * pJ * (nrow + ncol);
+    ubytes += (double)a.elem_bytes * pJ * (nrow + ncol);
     __syncthreads();
   }
 
@@ -752,11 +786,12 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
     for (int w = tid; w < work; w += blockDim.x) {
       const int ri = r0 + w % nrow, cj = c0 + w / nrow;
       const int z = lower_bound(s.candc, mcc, CJ[cj]);
-      const double acc = dot_strided(LJ + (int64_t)ri * pJ, WJ + (int64_t)cj * pJ, pJ);
+      const double acc =
+          update_term(a, a.loff[J] + (int64_t)ri * pJ, a.woff[J] + (int64_t)cj * pJ, pJ);
       Rp[(int64_t)z * q + (RJ[ri] - f)] -= acc;
     }
     flops += 2.0 * work * pJ;
-    ubytes += 8.0 * pJ * (nrow + ncol);
+    ubytes += (double)a.elem_bytes * pJ * (nrow + ncol);
     __syncthreads();
   }
 
@@ -824,8 +859,6 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
   if (tid == 0) trace_at(d, K, 12, wall_clock64());
   const int64_t vo = s.off[0];
   const int64_t io = s.off[1];
-  double* Lout = a.val_heap + vo;
-  double* Wout = Lout + (int64_t)mk * q;
   int32_t* Rout = a.idx_heap + io;
   int32_t* Cout = Rout + mk;
   int32_t* TRout = Cout + nk;
@@ -857,7 +890,7 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
       for (int c = 0; c < q; ++c) {
         double acc = 0.0;
         for (int t = 0; t < q; ++t) acc = fma(row[t], sW[t * q + c], acc);
-        Lout[(int64_t)pos * q + c] = acc;
+        store_factor(a, vo + (int64_t)pos * q + c, acc);
       }
       Rout[pos] = s.cand[z];
       ++pos;
@@ -866,7 +899,8 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
     for (int k = 0; k < kPer; ++k) {
       if (!fc[k]) continue;
       const int z = tid * kPer + k;
-      for (int r = 0; r < q; ++r) Wout[(int64_t)pos * q + r] = Rp[(int64_t)z * q + r];
+      for (int r = 0; r < q; ++r)
+        store_factor(a, vo + (int64_t)mk * q + (int64_t)pos * q + r, Rp[(int64_t)z * q + r]);
       Cout[pos] = s.candc[z];
       ++pos;
     }
@@ -1218,8 +1252,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
         ri = m.lo + w % nr;
         cj = m.lo2 + w / nr;
       }
-      Tm[e - i0] = dot_strided(a.val_heap + m.loff + (int64_t)ri * m.p,
-                               a.val_heap + m.woff + (int64_t)cj * m.p, m.p);
+      Tm[e - i0] = update_term(a, m.loff + (int64_t)ri * m.p, m.woff + (int64_t)cj * m.p, m.p);
     }
     __syncthreads();
     for (int t = 0; t < npt; ++t) {
@@ -1328,8 +1361,6 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   if (tid == 0) trace_at(d, K, 12, wall_clock64());
   const int64_t vo = s.off[0];
   const int64_t io = s.off[1];
-  double* Lout = a.val_heap + vo;
-  double* Wout = Lout + (int64_t)mk * q;
   int32_t* Rout = a.idx_heap + io;
   int32_t* Cout = Rout + mk;
   int32_t* TRout = Cout + nk;
@@ -1340,13 +1371,13 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     if (p >= 0) {
       double acc = 0.0;
       for (int t = 0; t < q; ++t) acc = fma(Cp[z * q + t], sW[t * q + c], acc);
-      Lout[(int64_t)p * q + c] = acc;
+      store_factor(a, vo + (int64_t)p * q + c, acc);
     }
   }
   for (int w = tid; w < mcc * q; w += nt) {
     const int z = w / q, r = w % q;
     const int p = keep_c[z];
-    if (p >= 0) Wout[(int64_t)p * q + r] = Rp[z * q + r];
+    if (p >= 0) store_factor(a, vo + (int64_t)mk * q + (int64_t)p * q + r, Rp[z * q + r]);
   }
   for (int z = q + tid; z < mc; z += nt) {
     const int p = keep_r[z];
@@ -1387,7 +1418,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       const int nr = t < np ? m.nr - m.lo2 : m.hi - m.lo;
       const int nc = t < np ? m.hi - m.lo : m.nc - m.lo2;
       flops += 2.0 * nr * nc * m.p;
-      ubytes += 8.0 * m.p * (nr + nc);
+      ubytes += (double)a.elem_bytes * m.p * (nr + nc);
     }
     atomicAdd(a.flops, (unsigned long long)flops);
     atomicAdd(a.upd_bytes, (unsigned long long)ubytes);
@@ -1694,7 +1725,18 @@ bilu_status factor_device(bilu_handle* h, double tau) {
     a.dval = h->d_dval.p; a.sval = h->d_sval.p;
     a.idx_heap = h->d_idx_heap.p; a.idx_cap = (int64_t)h->d_idx_heap.n; a.idx_top = h->d_counters.p + 0;
     a.val_heap = h->d_val_heap.p; a.val_cap = (int64_t)h->d_val_heap.n; a.val_top = h->d_counters.p + 1;
-    a.lo_heap = nullptr;
+    a.lo32 = nullptr;
+    a.lo16 = nullptr;
+    a.elem_bytes = 8;
+    if (a.update_prec == 1) {
+      CK(h->d_lo32.alloc(h->d_val_heap.n));
+      a.lo32 = h->d_lo32.p;
+      a.elem_bytes = 4;
+    } else if (a.update_prec == 2) {
+      CK(h->d_lo16.alloc(h->d_val_heap.n));
+      a.lo16 = h->d_lo16.p;
+      a.elem_bytes = 2;
+    }
     a.col_cnt = h->d_col_cnt.p; a.col_list = h->d_col_list.p; a.col_ovf = h->d_col_ovf.p;
     a.row_cnt = h->d_row_cnt.p; a.row_list = h->d_row_list.p; a.row_ovf = h->d_row_ovf.p;
     a.ovf_j = h->d_ovf_j.p; a.ovf_next = h->d_ovf_next.p; a.ovf_top = h->d_status.p + 3;

@@ -89,7 +89,9 @@ struct FactorArgs {
   double* sval;
   int32_t* idx_heap; int64_t idx_cap; unsigned long long* idx_top;
   double* val_heap;  int64_t val_cap; unsigned long long* val_top;
-  float* lo_heap;                  // low-precision copy of L/W (same offsets) or null
+  float* lo32;                     // FP32 copy of L/W (same offsets) or null
+  uint16_t* lo16;                  // BF16 copy of L/W (same offsets) or null
+  int elem_bytes;                  // bytes of one update input (8, 4 or 2)
   // predecessor lists: inline + overflow linked list
   int32_t* col_cnt; int32_t* col_list; int32_t* col_ovf;
   int32_t* row_cnt; int32_t* row_list; int32_t* row_ovf;
@@ -201,7 +203,8 @@ struct bilu_handle {
   bilu::DevArray<double> d_dval, d_sval;
   bilu::DevArray<int32_t> d_idx_heap;
   bilu::DevArray<double> d_val_heap;
-  bilu::DevArray<float> d_lo_heap;
+  bilu::DevArray<float> d_lo32;
+  bilu::DevArray<uint16_t> d_lo16;
   bilu::DevArray<int32_t> d_col_cnt, d_col_list, d_col_ovf, d_row_cnt, d_row_list, d_row_ovf;
   bilu::DevArray<int32_t> d_ovf_j, d_ovf_next;
   bilu::DevArray<double> d_scratch;
