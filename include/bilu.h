@@ -151,6 +151,20 @@ bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr,
  * (no analyze), BILU_ERR_NO_MEMORY, BILU_ERR_DEVICE.  Synchronous. */
 bilu_status bilu_factor(bilu_handle* h, double tau);
 
+/* Factor count independent analyzed handles in one launch of the factor
+ * sweep (many matrices at once).  hs[i] is factored with drop tolerance
+ * taus[i]; every handle ends as bilu_factor(hs[i], taus[i]) would leave it,
+ * with the same factor bit for bit.  The handles must be distinct, on the
+ * same device, and agree in drop_norm, beta_one, perturb_tau, perturb_rho,
+ * pivot_eps, update_precision and factor_path (BILU_ERR_INVALID
+ * otherwise); blocking and aggregation options may differ.  The launch runs
+ * on hs[0]'s stream.  The device counters of the launch (flops_update, the
+ * update part of bytes_factor, dev_ms_factor, factor_levels) describe the
+ * whole batch in every handle's statistics.  Returns the first error, else
+ * BILU_WARN_PERTURBED if any handle perturbed a pivot block, else BILU_OK;
+ * errors of the common launch are reported on hs[0].  Synchronous. */
+bilu_status bilu_factor_batched(bilu_handle** hs, int count, const double* taus);
+
 /* Sec. 3.7: y = M^{-1} x = P (L S U)^{-1} P^T x, multiplying by D_K
  * (Sec. 2.2).  x, y: device arrays of n doubles in the original numbering,
  * x != y.  Asynchronous on the handle's stream.  BILU_ERR_STATE before a

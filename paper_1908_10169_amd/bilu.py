@@ -79,7 +79,7 @@ EXPORTED = [
     "bilu_default_options", "bilu_create", "bilu_analyze", "bilu_factor", "bilu_apply",
     "bilu_spmv", "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors",
     "bilu_free_factors", "bilu_destroy", "bilu_status_string", "bilu_last_error",
-    "bilu_preprocess", "bilu_sync", "bilu_export_trace",
+    "bilu_preprocess", "bilu_sync", "bilu_export_trace", "bilu_factor_batched",
 ]
 
 _lib = None
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
     lib.bilu_create.argtypes = [C.POINTER(vp), C.POINTER(Options), vp]
     lib.bilu_analyze.argtypes = [vp, C.c_int64, vp, vp, vp]
     lib.bilu_factor.argtypes = [vp, C.c_double]
+    lib.bilu_factor_batched.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_double)]
     lib.bilu_apply.argtypes = [vp, vp, vp]
     lib.bilu_spmv.argtypes = [vp, vp, vp]
     lib.bilu_fgmres_solve.argtypes = [vp, vp, vp, C.c_int, C.c_double, C.c_int,
@@ -117,7 +118,8 @@ def load(path: str = LIB_PATH):
     lib.bilu_export_trace.restype = C.c_int
     lib.bilu_preprocess.argtypes = [C.POINTER(Options), C.c_int64, vp, vp, vp, C.c_double,
                                     vp, vp, C.POINTER(C.c_int64), vp, C.POINTER(C.c_int64)]
-    for f in ("bilu_create", "bilu_analyze", "bilu_factor", "bilu_apply", "bilu_spmv",
+    for f in ("bilu_create", "bilu_analyze", "bilu_factor", "bilu_factor_batched", "bilu_apply",
+              "bilu_spmv",
               "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors", "bilu_preprocess",
               "bilu_sync"):
         getattr(lib, f).restype = C.c_int
@@ -159,6 +161,18 @@ def _stream_ptr(stream):
         import torch
         return torch.cuda.current_stream().cuda_stream
     return stream
+
+
+def factor_batched(handles, taus):
+    """Factor analyzed handles in one launch (bilu_factor_batched)."""
+    lib = load()
+    hs = (C.c_void_p * len(handles))(*[h._h.value for h in handles])
+    ts = (C.c_double * len(handles))(*[float(t) for t in taus])
+    st = lib.bilu_factor_batched(hs, len(handles), ts)
+    if st not in (BILU_OK, BILU_WARN_PERTURBED):
+        errs = "; ".join(lib.bilu_last_error(h._h).decode() for h in handles)
+        raise BiluError(st, f"bilu_factor_batched: {errs}")
+    return st
 
 
 def preprocess(a, tau: float, pre_perm=None, **kw):

@@ -72,6 +72,86 @@ using namespace bilu;
     return fail(h, BILU_ERR_INTERNAL, "unknown exception");              \
   }
 
+namespace bilu {
+
+// After the sweep: the sweep's factor becomes the handle's, then
+// aggregation (Sec. 3.5), the apply plan and the statistics.
+bilu_status finish_factor(bilu_handle* h, std::chrono::steady_clock::time_point t0) {
+  bilu_status s = BILU_OK;
+  h->nb = h->stats.nblocks_initial;
+  h->bstart = h->bstart0;
+  h->fv = FactorView{};
+  h->fv.nb = (int)h->nb;
+  h->fv.bstart = h->d_bstart.p;
+  h->fv.blockOf = h->d_blockof.p;
+  h->fv.nr = h->d_nr.p;
+  h->fv.nc = h->d_nc.p;
+  h->fv.roff = h->d_roff.p;
+  h->fv.coff = h->d_coff.p;
+  h->fv.loff = h->d_loff.p;
+  h->fv.woff = h->d_woff.p;
+  h->fv.doff = h->d_doff.p;
+  h->fv.idx = h->d_idx_heap.p;
+  h->fv.val = h->d_val_heap.p;
+  h->fv.dval = h->d_dval.p;
+  auto t1 = std::chrono::steady_clock::now();
+  if (h->opt.use_aggregation) {
+    s = aggregate_device(h);
+    if (s != BILU_OK) return s;
+  }
+  auto t2 = std::chrono::steady_clock::now();
+  h->stats.t_aggregate = std::chrono::duration<double>(t2 - t1).count();
+  h->stats.t_phase[4] = h->stats.t_aggregate;
+  s = build_apply_plan(h);
+  if (s != BILU_OK) return s;
+  auto t3 = std::chrono::steady_clock::now();
+  h->stats.t_phase[5] = std::chrono::duration<double>(t3 - t2).count();
+  // block statistics and stored entries of the final factor
+  {
+    const int64_t nb = h->nb;
+    std::vector<int32_t> nr(nb), nc(nb);
+    if (hipMemcpy(nr.data(), h->fv.nr, nb * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(nc.data(), h->fv.nc, nb * 4, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(h, BILU_ERR_DEVICE, "stats copy");
+    double sum = 0, sum2 = 0;
+    int64_t mx = 0, nl = 0, nw = 0, nd = 0, ir = 0, ic = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+      int64_t q = h->bstart[b + 1] - h->bstart[b];
+      sum += q;
+      sum2 += double(q) * q;
+      mx = std::max(mx, q);
+      nl += nr[b] * q;
+      nw += nc[b] * q;
+      nd += q * q;
+      ir += nr[b];
+      ic += nc[b];
+    }
+    h->stats.nblocks = nb;
+    h->stats.max_width = mx;
+    h->stats.avg_width = sum / nb;
+    h->stats.std_width = std::sqrt(std::max(0.0, sum2 / nb - (sum / nb) * (sum / nb)));
+    h->stats.nnz_l = nl;
+    h->stats.nnz_w = nw;
+    h->stats.nnz_d = nd;
+    // one apply reads every stored value and row/column index once and
+    // streams x, t (written, then read) and y: 8 B values, 4 B indices
+    h->stats.bytes_apply = 8.0 * double(nl + nw + nd) + 4.0 * double(ir + ic) + 32.0 * h->n;
+    // factor: A once (value + index), the L_J/W_J reads of the updates, the
+    // written factors and their indices
+    h->stats.bytes_factor += 12.0 * double(h->nnz) + 8.0 * double(nl + nw + nd) +
+                             4.0 * double(ir + ic);
+  }
+  {
+    auto t4 = std::chrono::steady_clock::now();
+    h->stats.t_phase[6] = std::chrono::duration<double>(t4 - t3).count();
+    h->stats.t_factor = std::chrono::duration<double>(t4 - t0).count();
+  }
+  h->state = 2;
+  return h->stats.perturbed_blocks > 0 ? BILU_WARN_PERTURBED : BILU_OK;
+}
+
+}  // namespace bilu
+
 extern "C" {
 
 void bilu_default_options(bilu_options* o) {
@@ -166,6 +246,7 @@ bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr, const
   GUARD_END
 }
 
+
 bilu_status bilu_factor(bilu_handle* h, double tau) {
   if (!h) return BILU_ERR_INVALID;
   if (h->state < 1) return fail(h, BILU_ERR_STATE, "bilu_factor before bilu_analyze");
@@ -178,77 +259,27 @@ bilu_status bilu_factor(bilu_handle* h, double tau) {
   h->stats.n_apply = h->stats.n_spmv = 0;
   bilu_status s = factor_device(h, tau);
   if (s != BILU_OK) return s;
-  h->nb = h->stats.nblocks_initial;
-  h->bstart = h->bstart0;
-  h->fv = FactorView{};
-  h->fv.nb = (int)h->nb;
-  h->fv.bstart = h->d_bstart.p;
-  h->fv.blockOf = h->d_blockof.p;
-  h->fv.nr = h->d_nr.p;
-  h->fv.nc = h->d_nc.p;
-  h->fv.roff = h->d_roff.p;
-  h->fv.coff = h->d_coff.p;
-  h->fv.loff = h->d_loff.p;
-  h->fv.woff = h->d_woff.p;
-  h->fv.doff = h->d_doff.p;
-  h->fv.idx = h->d_idx_heap.p;
-  h->fv.val = h->d_val_heap.p;
-  h->fv.dval = h->d_dval.p;
-  auto t1 = std::chrono::steady_clock::now();
-  if (h->opt.use_aggregation) {
-    s = aggregate_device(h);
-    if (s != BILU_OK) return s;
-  }
-  auto t2 = std::chrono::steady_clock::now();
-  h->stats.t_aggregate = std::chrono::duration<double>(t2 - t1).count();
-  h->stats.t_phase[4] = h->stats.t_aggregate;
-  s = build_apply_plan(h);
-  if (s != BILU_OK) return s;
-  auto t3 = std::chrono::steady_clock::now();
-  h->stats.t_phase[5] = std::chrono::duration<double>(t3 - t2).count();
-  // block statistics and stored entries of the final factor
-  {
-    const int64_t nb = h->nb;
-    std::vector<int32_t> nr(nb), nc(nb);
-    if (hipMemcpy(nr.data(), h->fv.nr, nb * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(nc.data(), h->fv.nc, nb * 4, hipMemcpyDeviceToHost) != hipSuccess)
-      return fail(h, BILU_ERR_DEVICE, "stats copy");
-    double sum = 0, sum2 = 0;
-    int64_t mx = 0, nl = 0, nw = 0, nd = 0, ir = 0, ic = 0;
-    for (int64_t b = 0; b < nb; ++b) {
-      int64_t q = h->bstart[b + 1] - h->bstart[b];
-      sum += q;
-      sum2 += double(q) * q;
-      mx = std::max(mx, q);
-      nl += nr[b] * q;
-      nw += nc[b] * q;
-      nd += q * q;
-      ir += nr[b];
-      ic += nc[b];
-    }
-    h->stats.nblocks = nb;
-    h->stats.max_width = mx;
-    h->stats.avg_width = sum / nb;
-    h->stats.std_width = std::sqrt(std::max(0.0, sum2 / nb - (sum / nb) * (sum / nb)));
-    h->stats.nnz_l = nl;
-    h->stats.nnz_w = nw;
-    h->stats.nnz_d = nd;
-    // one apply reads every stored value and row/column index once and
-    // streams x, t (written, then read) and y: 8 B values, 4 B indices
-    h->stats.bytes_apply = 8.0 * double(nl + nw + nd) + 4.0 * double(ir + ic) + 32.0 * h->n;
-    // factor: A once (value + index), the L_J/W_J reads of the updates, the
-    // written factors and their indices
-    h->stats.bytes_factor += 12.0 * double(h->nnz) + 8.0 * double(nl + nw + nd) +
-                             4.0 * double(ir + ic);
-  }
-  {
-    auto t4 = std::chrono::steady_clock::now();
-    h->stats.t_phase[6] = std::chrono::duration<double>(t4 - t3).count();
-    h->stats.t_factor = std::chrono::duration<double>(t4 - t0).count();
-  }
-  h->state = 2;
-  return h->stats.perturbed_blocks > 0 ? BILU_WARN_PERTURBED : BILU_OK;
+  return finish_factor(h, t0);
   GUARD_END
+}
+
+bilu_status bilu_factor_batched(bilu_handle** hs, int count, const double* taus) {
+  if (!hs || !taus || count < 1) return BILU_ERR_INVALID;
+  for (int i = 0; i < count; ++i) {
+    if (!hs[i]) return BILU_ERR_INVALID;
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(hs[i], BILU_ERR_INVALID, "a handle appears twice in the batch");
+    if (hs[i]->state < 1) return fail(hs[i], BILU_ERR_STATE, "bilu_factor_batched before bilu_analyze");
+    if (!(taus[i] >= 0.0) || !std::isfinite(taus[i]))
+      return fail(hs[i], BILU_ERR_INVALID, "tau must be >= 0");
+  }
+  try {
+    return factor_batched(hs, count, taus);
+  } catch (const std::bad_alloc&) {
+    return fail(hs[0], BILU_ERR_NO_MEMORY, "host allocation failed");
+  } catch (...) {
+    return fail(hs[0], BILU_ERR_INTERNAL, "unexpected exception");
+  }
 }
 
 bilu_status bilu_apply(bilu_handle* h, const double* x, double* y) {

@@ -171,7 +171,8 @@ __device__ __forceinline__ void store_factor(const FactorArgs& a, int64_t o, dou
 // Sec. 3.6 perturbation of column j of the q x q row-major matrix m: the
 // largest-magnitude entry (lowest row on ties), or the diagonal when
 // 2|m_jj| >= |m_kj|, becomes m_kj (1 + rho beta) + sign(m_kj) tau alpha.
-__device__ __forceinline__ void perturb_column(double* m, int q, int j, const FactorArgs& a) {
+__device__ __forceinline__ void perturb_column(double* m, int q, int j, const FactorArgs& a,
+                                               double alpha) {
   int k = 0;
   double dmax = -1.0;
   for (int i = 0; i < q; ++i) {
@@ -184,10 +185,11 @@ __device__ __forceinline__ void perturb_column(double* m, int q, int j, const Fa
   if (2.0 * fabs(m[j * q + j]) >= fabs(m[k * q + j])) k = j;
   const double beta = a.beta_one ? 1.0 : dmax;
   const double d = m[k * q + j];
-  m[k * q + j] = d * (1.0 + a.pert_rho * beta) + (d < 0.0 ? -1.0 : 1.0) * a.pert_tau * a.alpha;
+  m[k * q + j] = d * (1.0 + a.pert_rho * beta) + (d < 0.0 ? -1.0 : 1.0) * a.pert_tau * alpha;
 }
 
-__device__ __forceinline__ void perturb_row(double* m, int q, int i, const FactorArgs& a) {
+__device__ __forceinline__ void perturb_row(double* m, int q, int i, const FactorArgs& a,
+                                            double alpha) {
   int k = 0;
   double dmax = -1.0;
   for (int j = 0; j < q; ++j) {
@@ -200,7 +202,7 @@ __device__ __forceinline__ void perturb_row(double* m, int q, int i, const Facto
   if (2.0 * fabs(m[i * q + i]) >= fabs(m[i * q + k])) k = i;
   const double beta = a.beta_one ? 1.0 : dmax;
   const double d = m[i * q + k];
-  m[i * q + k] = d * (1.0 + a.pert_rho * beta) + (d < 0.0 ? -1.0 : 1.0) * a.pert_tau * a.alpha;
+  m[i * q + k] = d * (1.0 + a.pert_rho * beta) + (d < 0.0 ? -1.0 : 1.0) * a.pert_tau * alpha;
 }
 
 // Thread group of a cooperative step: the whole workgroup, or wave 0 alone
@@ -526,6 +528,7 @@ __device__ __forceinline__ bool pivot_block(const FactorArgs& a, int K, int q, c
                             double* sW, Lds& s) {
   using G = Group<kWave>;
   const int tid = G::id(), nth = G::size();
+  const double alpha = a.alpha_blk ? a.alpha_blk[K] : a.alpha;
   for (int e = tid; e < q * q; e += nth) sS[e] = Cp[e];
   if (tid == 0) s.misc[12] = 0;
   G::sync();
@@ -534,7 +537,7 @@ __device__ __forceinline__ bool pivot_block(const FactorArgs& a, int K, int q, c
     bool zero = true;
     for (int i = 0; i < q; ++i) zero = zero && sS[i * q + j] == 0.0;
     if (zero) {
-      perturb_column(sS, q, j, a);
+      perturb_column(sS, q, j, a, alpha);
       s.misc[12] = 1;
     }
   }
@@ -543,7 +546,7 @@ __device__ __forceinline__ bool pivot_block(const FactorArgs& a, int K, int q, c
     bool zero = true;
     for (int j = 0; j < q; ++j) zero = zero && sS[i * q + j] == 0.0;
     if (zero) {
-      perturb_row(sS, q, i, a);
+      perturb_row(sS, q, i, a, alpha);
       s.misc[12] = 1;
     }
   }
@@ -580,13 +583,16 @@ __device__ __forceinline__ bool pivot_block(const FactorArgs& a, int K, int q, c
       if (tid == 0) raise_error(a, kDevSingular, K);
       return false;
     }
-    for (int j = tid; j < q; j += nth) perturb_column(sS, q, j, a);
+    for (int j = tid; j < q; j += nth) perturb_column(sS, q, j, a, alpha);
     G::sync();
-    for (int i = tid; i < q; i += nth) perturb_row(sS, q, i, a);
+    for (int i = tid; i < q; i += nth) perturb_row(sS, q, i, a, alpha);
     G::sync();
     ++rounds;
   }
-  if (tid == 0 && rounds > 0) atomicAdd(a.n_perturbed, 1);
+  if (tid == 0 && rounds > 0) {
+    atomicAdd(a.n_perturbed, 1);
+    if (a.pflag) a.pflag[K] = 1;
+  }
   for (int e = tid; e < q * q; e += nth) {
     a.dval[a.doff[K] + e] = sW[e];
     a.sval[a.doff[K] + e] = sS[e];
@@ -599,7 +605,7 @@ __device__ __forceinline__ bool pivot_block(const FactorArgs& a, int K, int q, c
 // Drop test (Alg. 1 in block form): row z of L is kept iff the norm of
 // C(z, K) D_K exceeds tau, column z of U iff the norm of D_K R(K, z) does.
 __device__ __forceinline__ void drop_flags(const FactorArgs& a, const double* Cp, const double* Rp, int mc, int mcc,
-                           int q, const double* sW, int* keep_r, int* keep_c) {
+                           int q, const double* sW, int* keep_r, int* keep_c, double tau) {
   const int tid = threadIdx.x;
   const bool two = a.drop_norm == 1;
   for (int z = q + tid; z < mc; z += blockDim.x) {
@@ -611,7 +617,7 @@ __device__ __forceinline__ void drop_flags(const FactorArgs& a, const double* Cp
       nrm = two ? fma(v, v, nrm) : fmax(nrm, fabs(v));
     }
     if (two) nrm = sqrt(nrm);
-    keep_r[z] = nrm > a.tau ? 1 : 0;
+    keep_r[z] = nrm > tau ? 1 : 0;
   }
   for (int z = tid; z < mcc; z += blockDim.x) {
     const double* col = Rp + (int64_t)z * q;
@@ -622,7 +628,7 @@ __device__ __forceinline__ void drop_flags(const FactorArgs& a, const double* Cp
       nrm = two ? fma(acc, acc, nrm) : fmax(nrm, fabs(acc));
     }
     if (two) nrm = sqrt(nrm);
-    keep_c[z] = nrm > a.tau ? 1 : 0;
+    keep_c[z] = nrm > tau ? 1 : 0;
   }
   __syncthreads();
 }
@@ -809,7 +815,7 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
   // ---------------- drop: rows of L (scaled) and columns of U (D R)
   int* keep_r = s.hash;                 // flags for rows q..mc-1
   int* keep_c = s.hash + kCandCap;      // flags for cols 0..mcc-1
-  drop_flags(a, Cp, Rp, mc, mcc, q, sW, keep_r, keep_c);
+  drop_flags(a, Cp, Rp, mc, mcc, q, sW, keep_r, keep_c, a.tau_blk ? a.tau_blk[K] : a.tau);
   if (tid == 0) trace_at(d, K, 11, wall_clock64());
   constexpr int kPer = kCandCap / kThreads;  // flags per thread
   int fr[kPer], fc[kPer];
@@ -1305,7 +1311,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   int* tcL = stage + 2560;
   for (int z = q + tid; z < mc; z += nt) rblk[z] = a.blockOf[s.cand[z]];
   for (int z = tid; z < mcc; z += nt) cblk[z] = a.blockOf[s.candc[z]];
-  drop_flags(a, Cp, Rp, mc, mcc, q, sW, keep_r, keep_c);
+  drop_flags(a, Cp, Rp, mc, mcc, q, sW, keep_r, keep_c, a.tau_blk ? a.tau_blk[K] : a.tau);
   if (tid == 0) trace_at(d, K, 11, wall_clock64());
 
   // ---- positions of kept rows / columns and of their distinct blocks
@@ -1589,10 +1595,9 @@ __global__ void seed_queue(int nb, const int* pending, int* enq, int* queue, int
 // ---------------------------------------------------------------------------
 // Host driver
 // ---------------------------------------------------------------------------
-bilu_status factor_device(bilu_handle* h, double tau) {
+int64_t factor_partition(bilu_handle* h, double tau) {
   using clk = std::chrono::steady_clock;
   auto t0 = clk::now();
-  const int64_t n = h->n;
   std::vector<int32_t>& bs = h->bstart0;
   double t_sets = 0.0;
   // ILU(1,tau) on the device; the host computation when a kernel capacity
@@ -1602,10 +1607,24 @@ bilu_status factor_device(bilu_handle* h, double tau) {
     (void)hipGetLastError();
     nb = ilu1t_partition(h, tau, bs, &t_sets);
   }
-  auto t1 = clk::now();
-  h->stats.t_ilu1t = std::chrono::duration<double>(t1 - t0).count();
+  h->stats.t_ilu1t = std::chrono::duration<double>(clk::now() - t0).count();
   h->stats.t_phase[0] = t_sets;
   h->stats.t_phase[1] = h->stats.t_ilu1t - t_sets;
+  return nb;
+}
+
+bilu_status factor_device(bilu_handle* h, double tau) {
+  if (factor_partition(h, tau) < 0) return fail(h, BILU_ERR_INTERNAL, "partition failed");
+  return factor_sweep(h, tau, nullptr, nullptr);
+}
+
+bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* tau_blk,
+                         const std::vector<double>* alpha_blk) {
+  using clk = std::chrono::steady_clock;
+  auto t1 = clk::now();
+  const int64_t n = h->n;
+  const std::vector<int32_t>& bs = h->bstart0;
+  const int64_t nb = (int64_t)bs.size() - 1;
   int32_t maxq = 0;
   for (int64_t b = 0; b < nb; ++b) maxq = std::max(maxq, bs[b + 1] - bs[b]);
   if (maxq > kMaxWidth) return fail(h, BILU_ERR_INVALID, "block wider than the kernel limit");
@@ -1712,6 +1731,20 @@ bilu_status factor_device(bilu_handle* h, double tau) {
     a.blockOf = h->d_blockof.p;
     a.tau = tau;
     a.alpha = h->alpha;
+    a.tau_blk = nullptr;
+    a.alpha_blk = nullptr;
+    a.pflag = nullptr;
+    if (tau_blk && alpha_blk) {
+      CK(h->d_tau_blk.alloc(nb));
+      CK(h->d_alpha_blk.alloc(nb));
+      CK(h->d_pflag.alloc(nb));
+      CK(hipMemcpyAsync(h->d_tau_blk.p, tau_blk->data(), nb * 8, hipMemcpyHostToDevice, st));
+      CK(hipMemcpyAsync(h->d_alpha_blk.p, alpha_blk->data(), nb * 8, hipMemcpyHostToDevice, st));
+      CK(hipMemsetAsync(h->d_pflag.p, 0, nb * sizeof(int), st));
+      a.tau_blk = h->d_tau_blk.p;
+      a.alpha_blk = h->d_alpha_blk.p;
+      a.pflag = h->d_pflag.p;
+    }
     a.pert_tau = h->opt.perturb_tau;
     a.pert_rho = h->opt.perturb_rho;
     a.pivot_eps = h->opt.pivot_eps;

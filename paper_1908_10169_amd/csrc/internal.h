@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -77,6 +78,9 @@ struct FactorArgs {
   const int32_t* bstart;  // [nb+1]
   const int32_t* blockOf; // [n]
   double tau, alpha, pert_tau, pert_rho, pivot_eps;
+  const double* tau_blk;           // per-block tau and alpha (batched factorization) or null
+  const double* alpha_blk;
+  int* pflag;                      // per-block perturbed flag or null
   int beta_one, drop_norm, update_prec;
   int fast_path;                   // narrow blocks take the LDS-resident path
   int lds_pivot;                   // dynamic LDS holds 2 q^2 doubles for every block
@@ -221,6 +225,8 @@ struct bilu_handle {
   bilu::DevArray<double> f_val, f_dval;
   bool final_is_initial = true;      // no merge happened: f_* alias the factor storage
   bilu::DevArray<double> d_agg_scratch;  // merge workspace (4 w^2 doubles per slot)
+  bilu::DevArray<double> d_tau_blk, d_alpha_blk;  // batched factorization only
+  bilu::DevArray<int> d_pflag;
   bilu::FactorView fv;               // the factor the apply uses
   // apply plan: predecessor blocks of the forward sweep (sorted, with the
   // range of their rows inside the block), successor blocks of the backward
@@ -270,6 +276,15 @@ int64_t ilu1t_partition_device(bilu_handle* h, double tau, std::vector<int32_t>&
 
 // factor.hip
 bilu_status factor_device(bilu_handle* h, double tau);
+int64_t factor_partition(bilu_handle* h, double tau);   // a3 into h->bstart0
+bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* tau_blk,
+                         const std::vector<double>* alpha_blk);
+
+// batch.hip
+bilu_status factor_batched(bilu_handle** hs, int count, const double* taus);
+
+// api.cpp
+bilu_status finish_factor(bilu_handle* h, std::chrono::steady_clock::time_point t0);
 
 // aggregate.hip
 bilu_status aggregate_device(bilu_handle* h);
