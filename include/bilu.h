@@ -70,8 +70,10 @@ typedef struct {
   size_t heap_bytes;     /* factor heap size; 0 = sized from nnz(A)                  */
   int collect_timing;    /* 1: time kernels with HIP events on the handle's stream;  */
                          /* 2: also trace every block of the factor kernel           */
-  int factor_path;       /* 0: narrow blocks use the LDS-resident kernel path        */
-                         /* (default); 1: every block uses the general path. Both    */
+  int factor_path;       /* 0 (default): blocks up to 16 wide stage their data in    */
+                         /* LDS, or in global scratch when it does not fit; others  */
+                         /* take the general path.  1: every block takes the general */
+                         /* path.  2: global staging wherever it fits.  All three   */
                          /* compute identical bits                                   */
 } bilu_options;
 

@@ -302,6 +302,12 @@ constexpr int kFastStage = 3072;    // staged list entries
 constexpr int kFastBuf = 2048;      // doubles: panels + update terms
 constexpr int kFastExtra = 256;     // candidate rows (columns) beyond the block
 constexpr int kFastSegs = 2 + 2 * kFastPreds;
+// The same path with its staged lists and panels in the worker's global
+// slot, for blocks beyond the LDS capacities; the per-predecessor data stays
+// in LDS (in the space the LDS variant uses for lists and panels).
+constexpr int kBigPreds = 300;
+constexpr int kBigStage = 65536;
+constexpr int kBigBuf = 65536;
 
 // Per-predecessor data of the fast path.  lo/hi/lo2 are positions in J's
 // lists: for a column predecessor, C_J[lo, hi) lie inside K and R_J[lo2, nr)
@@ -347,6 +353,15 @@ static_assert(offsetof(Lds, candc) == offsetof(Lds, cand) + sizeof(int) * kCandC
 static_assert(kFastWidth + kFastExtra <= 512 && 2560 + kFastExtra <= kFastStage, "stage layout");
 static_assert(2 + 2 * kFastPreds <= kThreads && kFastPreds <= kThreads, "one thread per segment");
 static_assert(2 * kFastExtra <= kFastBuf * 2, "candidate staging in buf");
+static_assert(6 * kCandCap <= kBigStage && 2 * kCandCap <= 2 * kBigBuf, "global stage layout");
+static_assert(sizeof(PredMeta) % 8 == 0, "PredMeta alignment");
+// doubles of a worker slot used by the global variant of the fast path
+constexpr int64_t kBigSlotDoubles = kBigBuf + kBigStage / 2 + 8;
+static_assert(kBigPreds * sizeof(PredMeta) <= sizeof(double) * kFastBuf + sizeof(PredMeta) * kFastPreds,
+              "global variant: predecessor data in LDS");
+static_assert(2 * kBigPreds + 4 + 2 * kBigPreds <= kFastStage, "global variant: offsets in LDS");
+static_assert(offsetof(Lds, x.meta) == offsetof(Lds, x.buf) + sizeof(double) * kFastBuf,
+              "global variant: the predecessor data spans buf and meta");
 static_assert(kThreads >= 192 && kListCap <= 64 && kFastWidth + 1 <= 32, "round-1 thread map");
 
 // Build the sorted set of candidate indices into out[] from the structural
@@ -962,23 +977,39 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
 // in predecessor order.  Returns kFastFallback (before any global side
 // effect other than the started flag) when the block does not fit.
 // ---------------------------------------------------------------------------
-enum FastResult : int { kFastDone = 0, kFastFallback = 1, kFastError = 2 };
+enum FastResult : int { kFastDone = 0, kFastFallback = 1, kFastError = 2, kFastBig = 3 };
 
 // Segments of the staged lists: 0 rows of A's block column K (CSC), 1 columns
 // of A's block row K (CSR), then R_J and C_J of every column predecessor,
 // then R_J and C_J of every row predecessor.
-__device__ __forceinline__ const int32_t* fast_list(const FactorArgs& a, const Lds& s, int sg,
-                                                    int np, int npr) {
+__device__ __forceinline__ const int32_t* fast_list(const FactorArgs& a, const Lds& s,
+                                                    const PredMeta* meta, int sg, int np, int npr) {
   if (sg == 0) return a.ri + s.x.cpk[0];
   if (sg == 1) return a.ci + s.x.rpk[0];
   int t = sg - 2;
-  if (t < np) return a.idx_heap + s.x.meta[t].roff;
+  if (t < np) return a.idx_heap + meta[t].roff;
   t -= np;
-  if (t < np) return a.idx_heap + s.x.meta[t].coff;
+  if (t < np) return a.idx_heap + meta[t].coff;
   t -= np;
-  if (t < npr) return a.idx_heap + s.x.meta[np + t].roff;
+  if (t < npr) return a.idx_heap + meta[np + t].roff;
   t -= npr;
-  return a.idx_heap + s.x.meta[np + t].coff;
+  return a.idx_heap + meta[np + t].coff;
+}
+
+// In-place exclusive prefix of v[0..m) for any m (all threads); returns the
+// total.
+__device__ __forceinline__ int wg_scan_array(int* v, int m, int* tmp) {
+  int carry = 0;
+  for (int base = 0; base < m; base += blockDim.x) {
+    const int i = base + threadIdx.x;
+    const int x = i < m ? v[i] : 0;
+    int tot = 0;
+    const int ex = wg_exclusive_scan(x, tmp, &tot);
+    if (i < m) v[i] = carry + ex;
+    carry += tot;
+  }
+  __syncthreads();
+  return carry;
 }
 
 // Last s in [0, n) with off[s] <= e (off ascending, off[n] > e).
@@ -994,14 +1025,42 @@ __device__ __forceinline__ int last_le(const int* off, int n, int e) {
   return lo;
 }
 
-__device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const FlowArgs& d, int K, Lds& s,
-                                 double* s_dyn) {
+template <bool kG>
+__device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const FlowArgs& d, int K,
+                                                 Lds& s, double* s_dyn, double* gslot) {
   const int tid = threadIdx.x, nt = blockDim.x;
   constexpr int kBatch = kFastStage / kThreads;
-  int* stage = s.x.stage;
+  // storage: LDS, or (kG) the worker's global slot for blocks beyond the LDS
+  // capacities; per-candidate arrays sit at multiples of cSpace in stage
+  constexpr int cStage = kG ? kBigStage : kFastStage;
+  constexpr int cPreds = kG ? kBigPreds : kFastPreds;
+  constexpr int cBuf = kG ? kBigBuf : kFastBuf;
+  constexpr int cExtra = kG ? kCandCap - kFastWidth : kFastExtra;
+  constexpr int cSpace = kG ? kCandCap : 512;
+  const int fallback = kG ? kFastFallback : kFastBig;
+  double* fbuf;
+  PredMeta* fmeta;
+  int *stage, *fseg, *fpred, *frpred;
+  if (kG) {
+    // global: panels and staged lists; LDS: predecessor data over the LDS
+    // variant's panel, metadata and stage space
+    fbuf = gslot;
+    stage = reinterpret_cast<int*>(gslot + kBigBuf);
+    fmeta = reinterpret_cast<PredMeta*>(s.x.buf);
+    fseg = s.x.stage;
+    fpred = fseg + 2 * kBigPreds + 4;
+    frpred = fpred + kBigPreds;
+  } else {
+    fbuf = s.x.buf;
+    fmeta = s.x.meta;
+    stage = s.x.stage;
+    fseg = s.x.segoff;
+    fpred = s.x.pred;
+    frpred = s.x.rpred;
+  }
   // ---- round 1: predecessor counts and inline lists, block range
   int* rawc = stage;
-  int* rawr = stage + kFastPreds;
+  int* rawr = stage + cPreds;
   if (tid < kListCap) {
     rawc[tid] = a.col_list[(int64_t)K * kListCap + tid];
   } else if (tid >= 64 && tid < 64 + kListCap) {
@@ -1022,7 +1081,8 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   __syncthreads();
   const int np = s.misc[0], npr = s.misc[1];
   const int f = s.misc[2], l = s.misc[3] - 1, q = l - f + 1;
-  if (q > kFastWidth || np + npr > kFastPreds || !a.lds_pivot) return kFastFallback;
+  if (q > kFastWidth || !a.lds_pivot) return kFastFallback;
+  if (np + npr > cPreds) return fallback;
   if (np > kListCap || npr > kListCap) {
     // overflow chains: one serial walk per list
     if ((tid == 0 && np > kListCap) || (tid == 64 && npr > kListCap)) {
@@ -1048,14 +1108,14 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     const int v = raw[i];
     int r = 0;
     for (int u = 0; u < m; ++u) r += raw[u] < v;
-    (col ? s.x.pred : s.x.rpred)[r] = v;
+    (col ? fpred : frpred)[r] = v;
   }
   __syncthreads();
 
   // ---- round 2: predecessor data, A's pointers of K; clear the hash
   for (int t = tid; t < np + npr; t += nt) {
-    const int J = t < np ? s.x.pred[t] : s.x.rpred[t - np];
-    PredMeta& m = s.x.meta[t];
+    const int J = t < np ? fpred[t] : frpred[t - np];
+    PredMeta& m = fmeta[t];
     m.roff = a.roff[J];
     m.coff = a.coff[J];
     m.loff = a.loff[J];
@@ -1081,47 +1141,49 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   if (tid == 0) trace_at(d, K, 2, wall_clock64());
   const int nseg = 2 + 2 * (np + npr);
   {
-    int len = 0;
-    if (tid == 0) {
-      len = (int)(s.x.cpk[q] - s.x.cpk[0]);
-    } else if (tid == 1) {
-      len = (int)(s.x.rpk[q] - s.x.rpk[0]);
-    } else if (tid < nseg) {
-      int t = tid - 2;
-      if (t < np) {
-        len = s.x.meta[t].nr;
-      } else if ((t -= np) < np) {
-        len = s.x.meta[t].nc;
-      } else if ((t -= np) < npr) {
-        len = s.x.meta[np + t].nr;
+    for (int g = tid; g < nseg; g += nt) {
+      int len;
+      if (g == 0) {
+        len = (int)(s.x.cpk[q] - s.x.cpk[0]);
+      } else if (g == 1) {
+        len = (int)(s.x.rpk[q] - s.x.rpk[0]);
       } else {
-        t -= npr;
-        len = s.x.meta[np + t].nc;
+        int t = g - 2;
+        if (t < np) {
+          len = fmeta[t].nr;
+        } else if ((t -= np) < np) {
+          len = fmeta[t].nc;
+        } else if ((t -= np) < npr) {
+          len = fmeta[np + t].nr;
+        } else {
+          t -= npr;
+          len = fmeta[np + t].nc;
+        }
       }
+      fseg[g] = len;
     }
-    int total = 0;
-    const int off = wg_exclusive_scan(len, s.scan, &total);
-    if (tid < nseg) s.x.segoff[tid] = off;
-    if (tid == 0) s.x.segoff[nseg] = total;
-    if (total > kFastStage) return kFastFallback;
+    __syncthreads();
+    const int total = wg_scan_array(fseg, nseg, s.scan);
+    if (tid == 0) fseg[nseg] = total;
+    if (total > cStage) return fallback;
     __syncthreads();
   }
-  const int* segoff = s.x.segoff;
+  const int* segoff = fseg;
   const int total = segoff[nseg];
 
   // ---- round 3: stage every list; candidate rows (keys r) and columns
   // (keys ~c) beyond the block go to one hash
-  {
+  for (int base = 0; base < total; base += kBatch * nt) {
     int v[kBatch];
     for (int k = 0; k < kBatch; ++k) {
-      const int e = tid + k * nt;
+      const int e = base + tid + k * nt;
       if (e < total) {
         const int sg = last_le(segoff, nseg, e);
-        v[k] = fast_list(a, s, sg, np, npr)[e - segoff[sg]];
+        v[k] = fast_list(a, s, fmeta, sg, np, npr)[e - segoff[sg]];
       }
     }
     for (int k = 0; k < kBatch; ++k) {
-      const int e = tid + k * nt;
+      const int e = base + tid + k * nt;
       if (e >= total) break;
       stage[e] = v[k];
       const int sg = last_le(segoff, nseg, e);
@@ -1132,10 +1194,10 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     }
   }
   __syncthreads();
-  if (s.misc[5] || s.misc[4] > 2 * kFastExtra) return kFastFallback;
+  if (s.misc[5] || s.misc[4] > 2 * cExtra) return fallback;
   // positions inside the predecessors' sorted lists
   for (int t = tid; t < np + npr; t += nt) {
-    PredMeta& m = s.x.meta[t];
+    PredMeta& m = fmeta[t];
     if (t < np) {
       const int* R = stage + segoff[2 + t];
       const int* C = stage + segoff[2 + np + t];
@@ -1151,46 +1213,58 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       m.lo2 = lower_bound(C, m.nc, l + 1);
     }
   }
-  int* tmpR = reinterpret_cast<int*>(s.x.buf);
-  int* tmpC = tmpR + kFastExtra;
+  int* tmpR = reinterpret_cast<int*>(fbuf);
+  int* tmpC = tmpR + cExtra;
   for (int t = tid; t < kHashSlots; t += nt) {
     const int key = s.hash[t];
     if (key >= 0) {
       const int o = atomicAdd(&s.misc[6], 1);
-      if (o < kFastExtra) tmpR[o] = key;
+      if (o < cExtra) tmpR[o] = key;
     } else if (key <= -2) {
       const int o = atomicAdd(&s.misc[7], 1);
-      if (o < kFastExtra) tmpC[o] = ~key;
+      if (o < cExtra) tmpC[o] = ~key;
     }
   }
   __syncthreads();
   const int nrow = s.misc[6], ncol = s.misc[7];
   const int mc = q + nrow, mcc = ncol;
-  if (nrow > kFastExtra || ncol > kFastExtra || (mc + mcc) * q > kFastBuf - kThreads)
-    return kFastFallback;
-  for (int t = tid; t < nrow + ncol; t += nt) {
-    const bool row = t < nrow;
-    const int* src = row ? tmpR : tmpC;
-    const int m = row ? nrow : ncol, i = row ? t : t - nrow;
-    const int v = src[i];
-    int r = 0;
-    for (int u = 0; u < m; ++u) r += src[u] < v;
-    if (row)
-      s.cand[q + r] = v;
-    else
-      s.candc[r] = v;
+  if (nrow > cExtra || ncol > cExtra || (mc + mcc) * q > cBuf - kThreads) return fallback;
+  int p2r = 1, p2c = 1;
+  while (p2r < nrow) p2r <<= 1;
+  while (p2c < ncol) p2c <<= 1;
+  const bool rank_sort = nrow <= 256 && ncol <= 256;
+  if (!rank_sort && (q + p2r > kCandCap || p2c > kCandCap)) return kFastFallback;
+  if (rank_sort) {
+    for (int t = tid; t < nrow + ncol; t += nt) {
+      const bool row = t < nrow;
+      const int* src = row ? tmpR : tmpC;
+      const int m = row ? nrow : ncol, i = row ? t : t - nrow;
+      const int v = src[i];
+      int r = 0;
+      for (int u = 0; u < m; ++u) r += src[u] < v;
+      if (row)
+        s.cand[q + r] = v;
+      else
+        s.candc[r] = v;
+    }
+  } else {
+    for (int t = tid; t < nrow; t += nt) s.cand[q + t] = tmpR[t];
+    for (int t = tid; t < ncol; t += nt) s.candc[t] = tmpC[t];
+    __syncthreads();
+    wg_bitonic_sort(s.cand + q, nrow);
+    wg_bitonic_sort(s.candc, ncol);
   }
   for (int t = tid; t < q; t += nt) s.cand[t] = f + t;
   // update terms per predecessor: column panel (rows >= f) x (columns in K),
   // row panel (rows in K) x (columns > l)
-  int terms = 0;
-  if (tid < np + npr) {
-    const PredMeta& m = s.x.meta[tid];
-    terms = tid < np ? (m.nr - m.lo2) * (m.hi - m.lo) : (m.hi - m.lo) * (m.nc - m.lo2);
+  __syncthreads();
+  for (int t = tid; t < np + npr; t += nt) {
+    const PredMeta& m = fmeta[t];
+    fpred[t] = t < np ? (m.nr - m.lo2) * (m.hi - m.lo) : (m.hi - m.lo) * (m.nc - m.lo2);
   }
-  int nterms = 0;
-  const int toff = wg_exclusive_scan(terms, s.scan, &nterms);
-  if (tid < np + npr) s.x.meta[tid].ioff = toff;
+  __syncthreads();
+  const int nterms = wg_scan_array(fpred, np + npr, s.scan);
+  for (int t = tid; t < np + npr; t += nt) fmeta[t].ioff = fpred[t];
   __syncthreads();
   if (tid == 0) {
     trace_at(d, K, 3, wall_clock64());
@@ -1201,10 +1275,10 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   }
 
   // ---- round 4: A's values into the panels, update terms (chunked)
-  double* Cp = s.x.buf;                 // mc x q, row-major
+  double* Cp = fbuf;                    // mc x q, row-major
   double* Rp = Cp + mc * q;             // mcc x q (column z of the row panel)
   double* Tm = Rp + mcc * q;            // update terms
-  const int cap = kFastBuf - (mc + mcc) * q;
+  const int cap = cBuf - (mc + mcc) * q;
   for (int e = tid; e < (mc + mcc) * q; e += nt) Cp[e] = 0.0;
   __syncthreads();
   {
@@ -1239,14 +1313,14 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
         int lo = 0, hi = npt;  // last t with ioff <= e
         while (hi - lo > 1) {
           const int mid = (lo + hi) >> 1;
-          if (s.x.meta[mid].ioff <= e)
+          if (fmeta[mid].ioff <= e)
             lo = mid;
           else
             hi = mid;
         }
         t = lo;
       }
-      const PredMeta& m = s.x.meta[t];
+      const PredMeta& m = fmeta[t];
       const int w = e - m.ioff;
       int ri, cj;
       if (t < np) {
@@ -1262,9 +1336,9 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     }
     __syncthreads();
     for (int t = 0; t < npt; ++t) {
-      const PredMeta& m = s.x.meta[t];
+      const PredMeta& m = fmeta[t];
       const int t0 = max(i0, m.ioff);
-      const int t1 = min(i1, t + 1 < npt ? s.x.meta[t + 1].ioff : nterms);
+      const int t1 = min(i1, t + 1 < npt ? fmeta[t + 1].ioff : nterms);
       if (t0 >= t1) continue;
       for (int e = t0 + tid; e < t1; e += nt) {
         const int w = e - m.ioff;
@@ -1303,12 +1377,12 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   if (tid == 0) trace_at(d, K, 10, wall_clock64());
   int* keep_r = s.hash;
   int* keep_c = s.hash + kCandCap;
-  int* rblk = stage;            // block of candidate row z
-  int* cblk = stage + 512;      // block of candidate column z
-  int* rbp = stage + 1024;      // position in TR_K of the first kept row of a block
-  int* cbp = stage + 1536;
-  int* trL = stage + 2048;      // TR_K and TC_K
-  int* tcL = stage + 2560;
+  int* rblk = stage;                // block of candidate row z
+  int* cblk = stage + cSpace;       // block of candidate column z
+  int* rbp = stage + 2 * cSpace;    // position in TR_K of the first kept row of a block
+  int* cbp = stage + 3 * cSpace;
+  int* trL = stage + 4 * cSpace;    // TR_K and TC_K
+  int* tcL = stage + 5 * cSpace;
   for (int z = q + tid; z < mc; z += nt) rblk[z] = a.blockOf[s.cand[z]];
   for (int z = tid; z < mcc; z += nt) cblk[z] = a.blockOf[s.candc[z]];
   drop_flags(a, Cp, Rp, mc, mcc, q, sW, keep_r, keep_c, a.tau_blk ? a.tau_blk[K] : a.tau);
@@ -1420,7 +1494,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     a.ntc[K] = ntc;
     double flops = 0.0, ubytes = 0.0;
     for (int t = 0; t < npt; ++t) {
-      const PredMeta& m = s.x.meta[t];
+      const PredMeta& m = fmeta[t];
       const int nr = t < np ? m.nr - m.lo2 : m.hi - m.lo;
       const int nc = t < np ? m.hi - m.lo : m.nc - m.lo2;
       flops += 2.0 * nr * nc * m.p;
@@ -1431,17 +1505,29 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   }
   __syncthreads();
   if (tid == 0) trace_at(d, K, 13, wall_clock64());
+  // TR_K and TC_K in LDS for the lookups below (the candidate lists are no
+  // longer needed)
+  const int* trS = trL;
+  const int* tcS = tcL;
+  if (kG) {
+    for (int t = tid; t < ntr; t += nt) s.cand[t] = trL[t];
+    for (int t = tid; t < ntc; t += nt) s.candc[t] = tcL[t];
+    trS = s.cand;
+    tcS = s.candc;
+    __syncthreads();
+  }
   // K updates the row panels of the blocks of its rows of L and the column
   // panels of the blocks of its columns of U
   for (int t = tid; t < ntr + ntc; t += nt) {
     if (t < ntr)
-      push_checked(a, d, a.row_cnt, a.row_list, a.row_ovf, trL[t], K);
+      push_checked(a, d, a.row_cnt, a.row_list, a.row_ovf, trS[t], K);
     else
-      push_checked(a, d, a.col_cnt, a.col_list, a.col_ovf, tcL[t - ntr], K);
+      push_checked(a, d, a.col_cnt, a.col_list, a.col_ovf, tcS[t - ntr], K);
   }
   __syncthreads();
   if (tid == 0) trace_at(d, K, 14, wall_clock64());
-  add_successor_counts(a, d, trL, ntr, tcL, ntc, K);
+  add_successor_counts(a, d, trS, ntr, tcS, ntc, K);
+  if (kG) __syncthreads();  // trS / tcS overlay the counts cleared below
 
   // ---- K's own counts (as updater_set): A's entries of K in later blocks,
   // TR_J > K of column predecessors, TC_J > K of row predecessors
@@ -1456,35 +1542,32 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   }
   const int nseg2 = 2 + npt;
   {
-    int len = 0;
-    if (tid == 0)
-      len = (int)(s.x.cpk[q] - s.x.cpk[0]);
-    else if (tid == 1)
-      len = (int)(s.x.rpk[q] - s.x.rpk[0]);
-    else if (tid < nseg2)
-      len = tid - 2 < np ? s.x.meta[tid - 2].ntr : s.x.meta[tid - 2].ntc;
-    int tot = 0;
-    const int off = wg_exclusive_scan(len, s.scan, &tot);
-    if (tid < nseg2) s.x.segoff[tid] = off;
-    if (tid == 0) s.x.segoff[nseg2] = tot;
+    for (int g = tid; g < nseg2; g += nt)
+      fseg[g] = g == 0   ? (int)(s.x.cpk[q] - s.x.cpk[0])
+                : g == 1 ? (int)(s.x.rpk[q] - s.x.rpk[0])
+                : g - 2 < np ? fmeta[g - 2].ntr
+                             : fmeta[g - 2].ntc;
+    __syncthreads();
+    const int tot = wg_scan_array(fseg, nseg2, s.scan);
+    if (tid == 0) fseg[nseg2] = tot;
     __syncthreads();
   }
-  const int tot2 = s.x.segoff[nseg2];
+  const int tot2 = fseg[nseg2];
   for (int base = 0; base < tot2; base += kBatch * nt) {
     int v[kBatch];
     for (int k = 0; k < kBatch; ++k) {
       const int e = base + tid + k * nt;
       if (e < tot2) {
-        const int sg = last_le(s.x.segoff, nseg2, e);
-        const int i = e - s.x.segoff[sg];
+        const int sg = last_le(fseg, nseg2, e);
+        const int i = e - fseg[sg];
         if (sg == 0)
           v[k] = a.bri[s.x.cpk[0] + i];
         else if (sg == 1)
           v[k] = a.bci[s.x.rpk[0] + i];
         else if (sg - 2 < np)
-          v[k] = a.idx_heap[s.x.meta[sg - 2].troff + i];
+          v[k] = a.idx_heap[fmeta[sg - 2].troff + i];
         else
-          v[k] = a.idx_heap[s.x.meta[sg - 2].tcoff + i];
+          v[k] = a.idx_heap[fmeta[sg - 2].tcoff + i];
       }
     }
     for (int k = 0; k < kBatch; ++k) {
@@ -1548,7 +1631,13 @@ __global__ void __launch_bounds__(kThreads, 2) factor_worker_kernel(FactorArgs a
       trace_at(d, K, 1, wall_clock64());
       trace_at(d, K, 7, (unsigned long long)blockIdx.x);
     }
-    if (!a.fast_path || factor_block_fast(a, d, K, s, s_dyn) == kFastFallback) {
+    int r = kFastFallback;
+    if (a.fast_path == 1) r = factor_block_fast<false>(a, d, K, s, s_dyn, nullptr);
+    if (r == kFastBig || a.fast_path == 2) {
+      __syncthreads();
+      r = factor_block_fast<true>(a, d, K, s, s_dyn, a.scratch + (int64_t)slot * a.slot_doubles);
+    }
+    if (r == kFastFallback) {
       __syncthreads();
       factor_block(a, d, K, slot, s, s_dyn);
     }
@@ -1656,9 +1745,7 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
   CK(h->d_row_list.alloc((size_t)nb * kListCap));
   CK(h->d_col_ovf.alloc(nb));
   CK(h->d_row_ovf.alloc(nb));
-  const int64_t ovf_cap = std::max<int64_t>(1 << 16, 4 * nb);
-  CK(h->d_ovf_j.alloc(ovf_cap));
-  CK(h->d_ovf_next.alloc(ovf_cap));
+  int64_t ovf_cap = std::max<int64_t>(1 << 16, 2 * nb);
   CK(h->d_status.alloc(8));
   CK(h->d_counters.alloc(4));
   CK(h->d_troff.alloc(nb));
@@ -1691,7 +1778,8 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
   CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, factor_worker_kernel, kThreads, dyn));
   const int64_t workers = std::min<int64_t>(nb, std::max<int64_t>(1, (int64_t)cus * std::max(per_cu, 1)));
   const int64_t mq = std::max<int32_t>(maxq, 1);
-  const int64_t slot_doubles = 2 * (int64_t)kCandCap * mq + 2 * mq * mq;
+  const int64_t slot_doubles = std::max<int64_t>(2 * (int64_t)kCandCap * mq + 2 * mq * mq,
+                                                  h->opt.factor_path != 1 ? kBigSlotDoubles : 0);
   if ((int64_t)h->d_scratch.n < workers * slot_doubles) CK(h->d_scratch.alloc(workers * slot_doubles));
   h->scratch_slots = workers;
   h->slot_doubles = slot_doubles;
@@ -1706,6 +1794,8 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
   h->stats.t_phase[2] = std::chrono::duration<double>(t2 - t1).count();
   for (int attempt = 0; attempt < 4; ++attempt) {
     if ((int64_t)h->d_val_heap.n < val_cap) CK(h->d_val_heap.alloc(val_cap));
+    CK(h->d_ovf_j.alloc(ovf_cap));
+    CK(h->d_ovf_next.alloc(ovf_cap));
     if ((int64_t)h->d_idx_heap.n < idx_cap) CK(h->d_idx_heap.alloc(idx_cap));
     CK(hipMemsetAsync(h->d_col_cnt.p, 0, nb * sizeof(int32_t), st));
     CK(hipMemsetAsync(h->d_row_cnt.p, 0, nb * sizeof(int32_t), st));
@@ -1751,7 +1841,7 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     a.beta_one = h->opt.beta_one;
     a.drop_norm = h->opt.drop_norm;
     a.update_prec = h->opt.update_precision;
-    a.fast_path = h->opt.factor_path == 0 ? 1 : 0;
+    a.fast_path = h->opt.factor_path == 0 ? 1 : h->opt.factor_path == 2 ? 2 : 0;
     a.lds_pivot = dyn > 0 ? 1 : 0;
     a.roff = h->d_roff.p; a.nr = h->d_nr.p; a.coff = h->d_coff.p; a.nc = h->d_nc.p;
     a.loff = h->d_loff.p; a.woff = h->d_woff.p; a.doff = h->d_doff.p;
@@ -1830,6 +1920,10 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     if (status[0] == kDevHeapOverflow) {
       val_cap = std::max<int64_t>(val_cap * 2, (int64_t)ctr[1] * 2);
       idx_cap = std::max<int64_t>(idx_cap * 2, (int64_t)ctr[0] * 2);
+      continue;
+    }
+    if (status[0] == kDevListOverflow && ovf_cap < INT32_MAX / 4) {
+      ovf_cap *= 4;
       continue;
     }
     if (status[0] != kDevOk) {

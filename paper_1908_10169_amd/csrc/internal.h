@@ -17,7 +17,7 @@ constexpr int kThreads = 256;      // threads per workgroup (4 wave64)
 constexpr int kHashSlots = 4096;   // LDS hash of candidate rows/columns
 constexpr int kCandCap = 2048;     // unique candidate rows (or columns) per block
 constexpr int kPredCap = 1024;     // predecessors per block panel
-constexpr int kListCap = 24;       // inline capacity of a block's predecessor list
+constexpr int kListCap = 64;       // inline capacity of a block's predecessor list
 constexpr int kMaxWidth = 128;     // widest pivot block
 constexpr int kLdsPivotWidth = 64; // pivot blocks up to this width live in LDS
 
@@ -82,7 +82,7 @@ struct FactorArgs {
   const double* alpha_blk;
   int* pflag;                      // per-block perturbed flag or null
   int beta_one, drop_norm, update_prec;
-  int fast_path;                   // narrow blocks take the LDS-resident path
+  int fast_path;                   // 1: LDS staging where it fits, 2: global staging, 0: general only
   int lds_pivot;                   // dynamic LDS holds 2 q^2 doubles for every block
   // factor storage, per block
   int64_t* roff;  int32_t* nr;     // rows of L  : idx heap

@@ -214,14 +214,15 @@ def test_deterministic_rerun():
 
 @pytest.mark.parametrize("name", ["cd3d_12_b4", "el3d_10_b3", "cd2d_32x32_b3"])
 def test_fast_and_general_paths_identical(name):
-    """The LDS-resident path for narrow blocks and the general path perform
-    the same arithmetic in the same order: the factors agree bit for bit."""
+    """The staged path for narrow blocks (data in LDS, or in global scratch)
+    and the general path perform the same arithmetic in the same order: the
+    factors agree bit for bit."""
     _torch()
     from paper_1908_10169_amd import bilu
     w = mg.workload(name)
     say(f"[paths] {name} n={w.a.n}")
     outs = []
-    for path in (0, 1):
+    for path in (0, 1, 2):
         h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=False, factor_path=path)
         h.analyze(w.a, pre_perm=w.perm)
         h.factor(w.tau)
@@ -229,7 +230,7 @@ def test_fast_and_general_paths_identical(name):
         outs.append((f.starts.tobytes(), [r.tobytes() for r in f.R], [c.tobytes() for c in f.C],
                      b"".join(x.tobytes() for x in f.L + f.W + f.D)))
         h.close()
-    assert outs[0] == outs[1]
+    assert outs[0] == outs[1] == outs[2]
 
 
 def test_state_errors():
