@@ -535,7 +535,7 @@ __device__ __forceinline__ void push_checked(const FactorArgs& a, const FlowArgs
 // Pivot block (Sec. 3.6, Sec. 2.2): copy the q x q leading rows of the
 // column panel into sS, perturb all-zero columns and rows, then invert into
 // sW by Gauss-Jordan; a failed inversion perturbs every column and row of
-// sS and retries (at most 3 rounds).  Stores D_K and S_K.  Returns false
+// sS and retries (at most 3 rounds).  Returns false
 // (uniformly) after reporting a block that stays singular.  kWave: run by
 // wave 0 alone.
 template <bool kWave>
@@ -608,13 +608,18 @@ __device__ __forceinline__ bool pivot_block(const FactorArgs& a, int K, int q, c
     atomicAdd(a.n_perturbed, 1);
     if (a.pflag) a.pflag[K] = 1;
   }
-  for (int e = tid; e < q * q; e += nth) {
+  G::sync();
+  return true;
+}
+
+// D_K (sW) and the pivot block used (sS) into the factor storage; called in
+// the write phase with the other factor stores.
+__device__ __forceinline__ void store_pivot(const FactorArgs& a, int K, int q, const double* sS,
+                                            const double* sW) {
+  for (int e = threadIdx.x; e < q * q; e += blockDim.x) {
     a.dval[a.doff[K] + e] = sW[e];
     a.sval[a.doff[K] + e] = sS[e];
   }
-
-  G::sync();
-  return true;
 }
 
 // Drop test (Alg. 1 in block form): row z of L is kept iff the norm of
@@ -879,6 +884,7 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
   if (s.misc[16]) return false;
   if (tid == 0) trace_at(d, K, 12, wall_clock64());
   const int64_t vo = s.off[0];
+  store_pivot(a, K, q, sS, sW);
   const int64_t io = s.off[1];
   int32_t* Rout = a.idx_heap + io;
   int32_t* Cout = Rout + mk;
@@ -1440,6 +1446,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   if (s.misc[16]) return kFastError;
   if (tid == 0) trace_at(d, K, 12, wall_clock64());
   const int64_t vo = s.off[0];
+  store_pivot(a, K, q, sS, sW);
   const int64_t io = s.off[1];
   int32_t* Rout = a.idx_heap + io;
   int32_t* Cout = Rout + mk;
