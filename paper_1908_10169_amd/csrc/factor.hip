@@ -73,6 +73,36 @@ __device__ __forceinline__ bool hash_insert(int* table, int key, int* count) {
   return false;
 }
 
+// Insert into a table of n slots (a power of two); false when full.
+__device__ __forceinline__ bool hash_insert_n(int* table, int n, int key, int* count) {
+  unsigned h = (unsigned(key) * 2654435761u) & (unsigned)(n - 1);
+  for (int probe = 0; probe < n; ++probe) {
+    int old = atomicCAS(&table[h], -1, key);
+    if (old == -1) {
+      atomicAdd(count, 1);
+      return true;
+    }
+    if (old == key) return true;
+    h = (h + 1) & (unsigned)(n - 1);
+  }
+  return false;
+}
+
+// As hash_insert_n, returning the slot of the key, or -1 when the table is full.
+__device__ __forceinline__ int hash_insert_at_n(int* table, int n, int key, int* count) {
+  unsigned h = (unsigned(key) * 2654435761u) & (unsigned)(n - 1);
+  for (int probe = 0; probe < n; ++probe) {
+    int old = atomicCAS(&table[h], -1, key);
+    if (old == -1) {
+      atomicAdd(count, 1);
+      return (int)h;
+    }
+    if (old == key) return (int)h;
+    h = (h + 1) & (unsigned)(n - 1);
+  }
+  return -1;
+}
+
 // As hash_insert, returning the slot of the key, or -1 when the table is full.
 __device__ __forceinline__ int hash_insert_at(int* table, int key, int* count) {
   unsigned h = hash_slot(key);
@@ -302,6 +332,13 @@ constexpr int kFastStage = 3072;    // staged list entries
 constexpr int kFastBuf = 2048;      // doubles: panels + update terms
 constexpr int kFastExtra = 256;     // candidate rows (columns) beyond the block
 constexpr int kFastSegs = 2 + 2 * kFastPreds;
+// LDS variant: candidates hash in s.hash[0, kFastCandSlots); K's own counts
+// (blocks it may update) in a second table of kFastOwnSlots keys followed by
+// their counts.
+constexpr int kFastCandSlots = 2048;
+constexpr int kFastOwnSlots = 512;
+constexpr int kFastOwn = kFastCandSlots;                  // keys
+constexpr int kFastOwnCnt = kFastCandSlots + kFastOwnSlots;  // counts
 // The same path with its staged lists and panels in the worker's global
 // slot, for blocks beyond the LDS capacities; the per-predecessor data stays
 // in LDS (in the space the LDS variant uses for lists and panels).
@@ -334,6 +371,7 @@ struct Lds {
       PredMeta meta[kFastPreds];      // column predecessors, then row ones
       int stage[kFastStage];          // staged lists (see factor_block_fast)
       int segoff[kFastSegs + 1];
+      int useg[2 + kFastPreds + 1];   // offsets of the lists of K's own counts
       int pred[kFastPreds];
       int rpred[kFastPreds];
       long long cpk[kFastWidth + 1];  // A's column (row) pointers of K
@@ -363,6 +401,9 @@ static_assert(2 * kBigPreds + 4 + 2 * kBigPreds <= kFastStage, "global variant: 
 static_assert(offsetof(Lds, x.meta) == offsetof(Lds, x.buf) + sizeof(double) * kFastBuf,
               "global variant: the predecessor data spans buf and meta");
 static_assert(kThreads >= 192 && kListCap <= 64 && kFastWidth + 1 <= 32, "round-1 thread map");
+static_assert(kFastOwnCnt + kFastOwnSlots <= kHashSlots && 2 * kFastExtra <= kFastCandSlots / 2 &&
+                  1024 + kFastExtra <= kFastCandSlots,
+              "LDS variant hash layout");
 
 // Build the sorted set of candidate indices into out[] from the structural
 // entries of A (lists ptr/idx over [lo, hi], keeping idx >= min_keep) plus
@@ -1136,12 +1177,14 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   }
   if (tid >= 128 && tid <= 128 + q) s.x.cpk[tid - 128] = a.cp[f + tid - 128];
   if (tid >= 160 && tid <= 160 + q) s.x.rpk[tid - 160] = a.rp[f + tid - 160];
-  for (int t = tid; t < kHashSlots; t += nt) s.hash[t] = -1;
+  for (int t = tid; t < kHashSlots; t += nt) s.hash[t] = (!kG && t >= kFastOwnCnt) ? 0 : -1;
   if (tid == 0) {
     s.misc[4] = 0;
     s.misc[5] = 0;
     s.misc[6] = 0;
     s.misc[7] = 0;
+    s.misc[9] = 0;
+    s.misc[10] = 0;
   }
   __syncthreads();
   if (tid == 0) trace_at(d, K, 2, wall_clock64());
@@ -1168,9 +1211,19 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       }
       fseg[g] = len;
     }
+    if (!kG)
+      for (int g = tid; g < 2 + np + npr; g += nt)
+        s.x.useg[g] = g == 0   ? (int)(s.x.cpk[q] - s.x.cpk[0])
+                      : g == 1 ? (int)(s.x.rpk[q] - s.x.rpk[0])
+                      : g - 2 < np ? fmeta[g - 2].ntr
+                                   : fmeta[g - 2].ntc;
     __syncthreads();
     const int total = wg_scan_array(fseg, nseg, s.scan);
     if (tid == 0) fseg[nseg] = total;
+    if (!kG) {
+      const int tot = wg_scan_array(s.x.useg, 2 + np + npr, s.scan);
+      if (tid == 0) s.x.useg[2 + np + npr] = tot;
+    }
     if (total > cStage) return fallback;
     __syncthreads();
   }
@@ -1196,10 +1249,46 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       const bool rowc = sg == 0 || (sg >= 2 && sg < 2 + np);
       const bool colc = sg == 1 || sg >= 2 + 2 * np + npr;
       if ((rowc || colc) && v[k] > l)
-        if (!hash_insert(s.hash, rowc ? v[k] : ~v[k], &s.misc[4])) s.misc[5] = 1;
+        if (!hash_insert_n(s.hash, kG ? kHashSlots : kFastCandSlots, rowc ? v[k] : ~v[k],
+                           &s.misc[4]))
+          s.misc[5] = 1;
+    }
+  }
+  if (!kG) {
+    // K's own counts: A's entries of K in later blocks, TR_J > K of column
+    // predecessors, TC_J > K of row predecessors
+    const int nu = 2 + np + npr, totu = s.x.useg[nu];
+    for (int base = 0; base < totu; base += kBatch * nt) {
+      int v[kBatch];
+      for (int k = 0; k < kBatch; ++k) {
+        const int e = base + tid + k * nt;
+        if (e < totu) {
+          const int sg = last_le(s.x.useg, nu, e);
+          const int i = e - s.x.useg[sg];
+          if (sg == 0)
+            v[k] = a.bri[s.x.cpk[0] + i];
+          else if (sg == 1)
+            v[k] = a.bci[s.x.rpk[0] + i];
+          else if (sg - 2 < np)
+            v[k] = a.idx_heap[fmeta[sg - 2].troff + i];
+          else
+            v[k] = a.idx_heap[fmeta[sg - 2].tcoff + i];
+        }
+      }
+      for (int k = 0; k < kBatch; ++k) {
+        const int e = base + tid + k * nt;
+        if (e < totu && v[k] > K) {
+          const int h = hash_insert_at_n(s.hash + kFastOwn, kFastOwnSlots, v[k], &s.misc[9]);
+          if (h < 0)
+            s.misc[10] = 1;
+          else
+            atomicAdd(&s.hash[kFastOwnCnt + h], 1);
+        }
+      }
     }
   }
   __syncthreads();
+  if (!kG && s.misc[10]) return kFastBig;
   if (s.misc[5] || s.misc[4] > 2 * cExtra) return fallback;
   // positions inside the predecessors' sorted lists
   for (int t = tid; t < np + npr; t += nt) {
@@ -1221,7 +1310,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   }
   int* tmpR = reinterpret_cast<int*>(fbuf);
   int* tmpC = tmpR + cExtra;
-  for (int t = tid; t < kHashSlots; t += nt) {
+  for (int t = tid; t < (kG ? kHashSlots : kFastCandSlots); t += nt) {
     const int key = s.hash[t];
     if (key >= 0) {
       const int o = atomicAdd(&s.misc[6], 1);
@@ -1382,7 +1471,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   if (!s.misc[14]) return kFastError;
   if (tid == 0) trace_at(d, K, 10, wall_clock64());
   int* keep_r = s.hash;
-  int* keep_c = s.hash + kCandCap;
+  int* keep_c = s.hash + (kG ? kCandCap : 1024);  // below the own-count table
   int* rblk = stage;                // block of candidate row z
   int* cblk = stage + cSpace;       // block of candidate column z
   int* rbp = stage + 2 * cSpace;    // position in TR_K of the first kept row of a block
@@ -1537,8 +1626,12 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   if (kG) __syncthreads();  // trS / tcS overlay the counts cleared below
 
   // ---- K's own counts (as updater_set): A's entries of K in later blocks,
-  // TR_J > K of column predecessors, TC_J > K of row predecessors
-  int* cnt = s.cand;  // per hash slot, over cand[] and candc[]
+  // TR_J > K of column predecessors, TC_J > K of row predecessors; the LDS
+  // variant built them while staging
+  int* own = kG ? s.hash : s.hash + kFastOwn;
+  int* cnt = kG ? s.cand : s.hash + kFastOwnCnt;  // per hash slot
+  const int own_slots = kG ? kHashSlots : kFastOwnSlots;
+  if (kG) {
   for (int t = tid; t < kHashSlots; t += nt) {
     s.hash[t] = -1;
     cnt[t] = 0;
@@ -1593,14 +1686,15 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     if (tid == 0) raise_error(a, kDevAnnOverflow, K);
     return kFastError;
   }
+  }
   if (tid == 0) trace_at(d, K, 15, wall_clock64());
   // publish: every write and count of this block is visible before the
   // retraction
   release_agent();
   __syncthreads();
   const int dK = __hip_atomic_load(&d.depth[K], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
-  for (int t = tid; t < kHashSlots; t += nt) {
-    const int B = s.hash[t];
+  for (int t = tid; t < own_slots; t += nt) {
+    const int B = own[t];
     if (B < 0) continue;
     const int c = cnt[t];
     atomicMax(&d.depth[B], dK);
@@ -1666,16 +1760,22 @@ __global__ void map_blocks(const int32_t* idx, int64_t nnz, const int32_t* block
 }
 
 // pending[K] += entries of A's rows and columns of K that lie in earlier
-// blocks (one thread per index i: row i and column i).
-__global__ void static_pending(int n, const int64_t* rp, const int32_t* bci, const int64_t* cp,
-                               const int32_t* bri, const int32_t* blockOf, int* pending) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int K = blockOf[i];
-  int c = 0;
-  for (int64_t m = rp[i]; m < rp[i + 1]; ++m) c += bci[m] < K;
-  for (int64_t m = cp[i]; m < cp[i + 1]; ++m) c += bri[m] < K;
-  if (c) atomicAdd(&pending[K], c);
+// blocks.  16 lanes per index i (row i and column i), reading its entries
+// contiguously.
+__global__ void __launch_bounds__(256) static_pending(int n, const int64_t* rp, const int32_t* bci,
+                                                      const int64_t* cp, const int32_t* bri,
+                                                      const int32_t* blockOf, int* pending) {
+  const int i = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int sub = threadIdx.x & 15;
+  int c = 0, K = 0;
+  if (i < n) {
+    K = blockOf[i];
+    for (int64_t m = rp[i] + sub; m < rp[i + 1]; m += 16) c += bci[m] < K;
+    for (int64_t m = cp[i] + sub; m < cp[i + 1]; m += 16) c += bri[m] < K;
+  }
+#pragma unroll
+  for (int o = 8; o > 0; o >>= 1) c += __shfl_xor(c, o, 16);
+  if (i < n && sub == 0 && c) atomicAdd(&pending[K], c);
 }
 
 // Blocks that nothing can update start in the ready queue.
@@ -1814,7 +1914,7 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     CK(hipMemsetAsync(h->d_flow.p, 0, 4 * nb * sizeof(int), st));
     CK(hipMemsetAsync(h->d_flow.p + 4 * nb, 0xff, nb * sizeof(int), st));
     CK(hipMemsetAsync(h->d_flow.p + 5 * nb, 0, 2 * sizeof(int), st));
-    static_pending<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+    static_pending<<<(unsigned)((n + 15) / 16), 256, 0, st>>>(
         (int)n, h->d_rp.p, h->d_bci.p, h->d_cp.p, h->d_bri.p, h->d_blockof.p, h->d_flow.p);
     seed_queue<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(
         (int)nb, h->d_flow.p, h->d_flow.p + 2 * nb, h->d_flow.p + 4 * nb, h->d_flow.p + 5 * nb);

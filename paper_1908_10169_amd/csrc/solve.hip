@@ -10,6 +10,8 @@
 #include <algorithm>
 #include <numeric>
 
+#include <hipcub/hipcub.hpp>
+
 #include "internal.h"
 #include "wg.h"
 
@@ -351,6 +353,25 @@ bilu_status spmv_permuted(bilu_handle* h, const double* x, double* y) {
 
 // Apply plan of the factor in h->fv: forward/backward dependency lists and
 // the row-major copy of L.
+// Exclusive prefix of in[0..count) into out[0..count] on the device (out[count]
+// is the total); returns the total.
+template <class T>
+static hipError_t device_scan(bilu_handle* h, const T* in, T* out, int64_t count, T* total) {
+  hipStream_t st = h->stream;
+  size_t bytes = 0;
+  hipError_t e = hipcub::DeviceScan::InclusiveSum(nullptr, bytes, in, out + 1, (int)count, st);
+  if (e != hipSuccess) return e;
+  if ((e = h->d_scan_tmp.alloc(bytes + 1)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(out, 0, sizeof(T), st)) != hipSuccess) return e;
+  if (count > 0 &&
+      (e = hipcub::DeviceScan::InclusiveSum(h->d_scan_tmp.p, bytes, in, out + 1, (int)count, st)) !=
+          hipSuccess)
+    return e;
+  if ((e = hipMemcpyAsync(total, out + count, sizeof(T), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return e;
+  return hipStreamSynchronize(st);
+}
+
 bilu_status build_apply_plan(bilu_handle* h) {
   hipStream_t st = h->stream;
   const FactorView& f = h->fv;
@@ -365,54 +386,44 @@ bilu_status build_apply_plan(bilu_handle* h) {
   CK(cnt.alloc(nb + 1));
   CK(hipMemsetAsync(cnt.p, 0, (nb + 1) * sizeof(int32_t), st));
   fw_count<<<gw, 256, 0, st>>>(f, cnt.p);
-  std::vector<int32_t> hc(nb), ptr(nb + 1, 0);
-  CK(hipMemcpyAsync(hc.data(), cnt.p, nb * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  CK(hipStreamSynchronize(st));
-  for (int64_t k = 0; k < nb; ++k) ptr[k + 1] = ptr[k] + hc[k];
-  const int64_t ne = std::max<int64_t>(1, ptr[nb]);
   CK(h->fw_ptr.alloc(nb + 1));
+  int32_t nfw = 0;
+  CK(device_scan<int32_t>(h, cnt.p, h->fw_ptr.p, nb, &nfw));
+  const int64_t ne = std::max<int64_t>(1, nfw);
   CK(h->fw_j.alloc(ne));
   CK(h->fw_r0.alloc(ne));
   CK(h->fw_cnt.alloc(ne));
   DevArray<unsigned long long> keys;
   CK(keys.alloc(ne));
-  CK(hipMemcpyAsync(h->fw_ptr.p, ptr.data(), (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
   CK(hipMemsetAsync(cnt.p, 0, (nb + 1) * sizeof(int32_t), st));
   fw_fill<<<gw, 256, 0, st>>>(f, h->fw_ptr.p, cnt.p, keys.p);
   fw_sort<<<(unsigned)nb, 64, 0, st>>>((int)nb, h->fw_ptr.p, keys.p, h->fw_j.p, h->fw_r0.p,
                                        h->fw_cnt.p);
   // backward successor blocks
   bw_count<<<gw, 256, 0, st>>>(f, cnt.p);
-  CK(hipMemcpyAsync(hc.data(), cnt.p, nb * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  CK(hipStreamSynchronize(st));
-  for (int64_t k = 0; k < nb; ++k) ptr[k + 1] = ptr[k] + hc[k];
   CK(h->bw_ptr.alloc(nb + 1));
-  CK(h->bw_b.alloc(std::max<int64_t>(1, ptr[nb])));
-  CK(hipMemcpyAsync(h->bw_ptr.p, ptr.data(), (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
+  int32_t nbw = 0;
+  CK(device_scan<int32_t>(h, cnt.p, h->bw_ptr.p, nb, &nbw));
+  CK(h->bw_b.alloc(std::max<int32_t>(1, nbw)));
   bw_fill<<<(unsigned)nb, 64, 0, st>>>(f, h->bw_ptr.p, h->bw_b.p);
   // row-major L
   CK(h->lr_ptr.alloc(n + 1));
   DevArray<int64_t> lc;
   CK(lc.alloc(n));
   lr_count<<<gw, 256, 0, st>>>(f, h->fw_ptr.p, h->fw_j.p, h->fw_r0.p, h->fw_cnt.p, lc.p);
-  std::vector<int64_t> hl(n), lp(n + 1, 0);
-  CK(hipMemcpyAsync(hl.data(), lc.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-  CK(hipStreamSynchronize(st));
-  for (int64_t i = 0; i < n; ++i) lp[i + 1] = lp[i] + hl[i];
-  CK(hipMemcpyAsync(h->lr_ptr.p, lp.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
-  CK(h->lr_col.alloc(std::max<int64_t>(1, lp[n])));
-  CK(h->lr_val.alloc(std::max<int64_t>(1, lp[n])));
+  int64_t nlr = 0;
+  CK(device_scan<int64_t>(h, lc.p, h->lr_ptr.p, n, &nlr));
+  CK(h->lr_col.alloc(std::max<int64_t>(1, nlr)));
+  CK(h->lr_val.alloc(std::max<int64_t>(1, nlr)));
   lr_fill<<<gw, 256, 0, st>>>(f, h->fw_ptr.p, h->fw_j.p, h->fw_r0.p, h->fw_cnt.p, h->lr_ptr.p,
                               h->lr_col.p, h->lr_val.p);
   CK(hipGetLastError());
   // dependency levels (actual graph of the factor), computed on the host
   {
-    std::vector<int32_t> fp(nb + 1), fj, bp(nb + 1), bb;
+    std::vector<int32_t> fp(nb + 1), fj(std::max<int32_t>(1, nfw)), bp(nb + 1),
+        bb(std::max<int32_t>(1, nbw));
     CK(hipMemcpyAsync(fp.data(), h->fw_ptr.p, (nb + 1) * 4, hipMemcpyDeviceToHost, st));
     CK(hipMemcpyAsync(bp.data(), h->bw_ptr.p, (nb + 1) * 4, hipMemcpyDeviceToHost, st));
-    CK(hipStreamSynchronize(st));
-    fj.resize(std::max<int32_t>(1, fp[nb]));
-    bb.resize(std::max<int32_t>(1, bp[nb]));
     CK(hipMemcpyAsync(fj.data(), h->fw_j.p, fj.size() * 4, hipMemcpyDeviceToHost, st));
     CK(hipMemcpyAsync(bb.data(), h->bw_b.p, bb.size() * 4, hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
