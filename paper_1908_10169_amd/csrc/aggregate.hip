@@ -174,6 +174,7 @@ struct MergeArgs {
   int32_t* fidx; double* fval; double* fdval;
   double* scratch; int64_t slot_doubles;   // per workgroup: 4 w^2 doubles
   int* err;
+  int copy_all;   // 0: blocks that merged with nothing stay in place (only D_K is copied)
 };
 
 struct MergeLds {
@@ -246,8 +247,12 @@ __global__ void __launch_bounds__(kMergeThreads) agg_merge_kernel(MergeArgs a) {
     double* Dout = a.fdval + a.fdoff[g];
     const int nrg = a.fnr[g], ncg = a.fnc[g];
     if (b1 - b0 == 1) {
-      // a block that merged with nothing: copy
+      // a block that merged with nothing: copy (D_K only when it stays in place)
       const int J = b0;
+      if (!a.copy_all) {
+        for (int t = tid; t < w * w; t += nt) Dout[t] = a.in.dval[a.in.doff[J] + t];
+        continue;
+      }
       for (int t = tid; t < nrg; t += nt) Rout[t] = a.in.idx[a.in.roff[J] + t];
       for (int t = tid; t < ncg; t += nt) Cout[t] = a.in.idx[a.in.coff[J] + t];
       for (int t = tid; t < nrg * w; t += nt) Lout[t] = a.in.val[a.in.loff[J] + t];
@@ -372,6 +377,30 @@ __global__ void __launch_bounds__(kMergeThreads) agg_merge_kernel(MergeArgs a) {
   }
 }
 
+// Offsets of the final blocks when the unmerged ones stay in place: every
+// group first takes its first member's offsets, then the merged groups get
+// theirs from the compact list (group, rows, columns, L, W offsets).
+__global__ void agg_offsets(int ng, const int32_t* gfirst, FactorView in, int64_t* roff,
+                            int64_t* coff, int64_t* loff, int64_t* woff) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  const int J = gfirst[g];
+  roff[g] = in.roff[J];
+  coff[g] = in.coff[J];
+  loff[g] = in.loff[J];
+  woff[g] = in.woff[J];
+}
+__global__ void agg_offsets_merged(int m, const int64_t* list, int64_t* roff, int64_t* coff,
+                                   int64_t* loff, int64_t* woff) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int64_t* e = list + 5 * (int64_t)i;
+  roff[e[0]] = e[1];
+  coff[e[0]] = e[2];
+  loff[e[0]] = e[3];
+  woff[e[0]] = e[4];
+}
+
 __global__ void agg_block_of(const int32_t* bstart, int nb, int32_t* blockOf) {
   const int b = blockIdx.x * blockDim.y + threadIdx.y;
   if (b >= nb) return;
@@ -445,6 +474,18 @@ bilu_status aggregate_device(bilu_handle* h) {
   fbs[ng] = (int32_t)n;
   h->stats.merges = nb - ng;
   if (ng == nb) return BILU_OK;  // nothing merged: the sweep's factor is final
+  // merged blocks go after the sweep's data in its own heaps when they fit;
+  // blocks that merged with nothing then stay where they are
+  std::vector<int64_t> mlist;
+  int64_t mi = h->idx_used, mv = h->val_used;
+  for (int64_t g = 0; g < ng; ++g) {
+    if (gfirst[g + 1] - gfirst[g] == 1) continue;
+    const int64_t w = h->bstart0[gfirst[g + 1]] - h->bstart0[gfirst[g]];
+    mlist.insert(mlist.end(), {g, mi, mi + fnr[g], mv, mv + (int64_t)fnr[g] * w});
+    mi += fnr[g] + fnc[g];
+    mv += (int64_t)(fnr[g] + fnc[g]) * w;
+  }
+  const bool in_place = mi <= (int64_t)h->d_idx_heap.n && mv <= (int64_t)h->d_val_heap.n;
   CK(h->f_bstart.alloc(ng + 1));
   CK(h->f_blockof.alloc(n));
   CK(h->f_nr.alloc(ng));
@@ -454,8 +495,10 @@ bilu_status aggregate_device(bilu_handle* h) {
   CK(h->f_loff.alloc(ng));
   CK(h->f_woff.alloc(ng));
   CK(h->f_doff.alloc(ng + 1));
-  CK(h->f_idx.alloc(std::max<int64_t>(1, io)));
-  CK(h->f_val.alloc(std::max<int64_t>(1, vo)));
+  if (!in_place) {
+    CK(h->f_idx.alloc(std::max<int64_t>(1, io)));
+    CK(h->f_val.alloc(std::max<int64_t>(1, vo)));
+  }
   CK(h->f_dval.alloc(fdoff[ng]));
   DevArray<int32_t> d_gfirst;
   CK(d_gfirst.alloc(ng + 1));
@@ -463,10 +506,24 @@ bilu_status aggregate_device(bilu_handle* h) {
   CK(hipMemcpyAsync(h->f_bstart.p, fbs.data(), (ng + 1) * 4, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(h->f_nr.p, fnr.data(), ng * 4, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(h->f_nc.p, fnc.data(), ng * 4, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(h->f_roff.p, froff.data(), ng * 8, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(h->f_coff.p, fcoff.data(), ng * 8, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(h->f_loff.p, floff.data(), ng * 8, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(h->f_woff.p, fwoff.data(), ng * 8, hipMemcpyHostToDevice, st));
+  DevArray<int64_t> d_mlist;
+  if (in_place) {
+    const int64_t m = (int64_t)mlist.size() / 5;
+    agg_offsets<<<(unsigned)((ng + 255) / 256), 256, 0, st>>>((int)ng, d_gfirst.p, h->fv, h->f_roff.p,
+                                                             h->f_coff.p, h->f_loff.p, h->f_woff.p);
+    if (m > 0) {
+      CK(d_mlist.alloc(mlist.size()));
+      CK(hipMemcpyAsync(d_mlist.p, mlist.data(), mlist.size() * 8, hipMemcpyHostToDevice, st));
+      agg_offsets_merged<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(
+          (int)m, d_mlist.p, h->f_roff.p, h->f_coff.p, h->f_loff.p, h->f_woff.p);
+    }
+    CK(hipGetLastError());
+  } else {
+    CK(hipMemcpyAsync(h->f_roff.p, froff.data(), ng * 8, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->f_coff.p, fcoff.data(), ng * 8, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->f_loff.p, floff.data(), ng * 8, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->f_woff.p, fwoff.data(), ng * 8, hipMemcpyHostToDevice, st));
+  }
   CK(hipMemcpyAsync(h->f_doff.p, fdoff.data(), (ng + 1) * 8, hipMemcpyHostToDevice, st));
   {
     dim3 blk(64, 4);
@@ -491,8 +548,9 @@ bilu_status aggregate_device(bilu_handle* h) {
   ma.fdoff = h->f_doff.p;
   ma.fnr = h->f_nr.p;
   ma.fnc = h->f_nc.p;
-  ma.fidx = h->f_idx.p;
-  ma.fval = h->f_val.p;
+  ma.fidx = in_place ? h->d_idx_heap.p : h->f_idx.p;
+  ma.fval = in_place ? h->d_val_heap.p : h->f_val.p;
+  ma.copy_all = in_place ? 0 : 1;
   ma.fdval = h->f_dval.p;
   ma.scratch = h->d_agg_scratch.p;
   ma.slot_doubles = slot_doubles;
@@ -518,8 +576,8 @@ bilu_status aggregate_device(bilu_handle* h) {
   f.loff = h->f_loff.p;
   f.woff = h->f_woff.p;
   f.doff = h->f_doff.p;
-  f.idx = h->f_idx.p;
-  f.val = h->f_val.p;
+  f.idx = in_place ? h->d_idx_heap.p : h->f_idx.p;
+  f.val = in_place ? h->d_val_heap.p : h->f_val.p;
   f.dval = h->f_dval.p;
   return BILU_OK;
 #undef CK

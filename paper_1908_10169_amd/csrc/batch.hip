@@ -224,6 +224,8 @@ bilu_status factor_batched(bilu_handle** hs, int count, const double* taus) {
     CK(hipGetLastError());
     // device counters of the one launch describe the whole batch
     h->stats.nblocks_initial = nbi;
+    h->idx_used = io;
+    h->val_used = vo;
     h->stats.perturbed_blocks = perturbed;
     h->stats.flops_update = sys.stats.flops_update;
     h->stats.bytes_factor = sys.stats.bytes_factor;

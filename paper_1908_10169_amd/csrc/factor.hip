@@ -2058,6 +2058,8 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     h->stats.t_factor_device = std::chrono::duration<double>(t3 - t2).count();
     h->stats.t_phase[3] = h->stats.t_factor_device;
     h->stats.nblocks_initial = nb;
+    h->idx_used = (int64_t)ctr[0];
+    h->val_used = (int64_t)ctr[1];
     return BILU_OK;
   }
   return fail(h, BILU_ERR_NO_MEMORY, "factor heap could not be sized");

@@ -215,6 +215,7 @@ struct bilu_handle {
   bilu::DevArray<int> d_status;                  // err, err_block, n_perturbed, ovf_top
   bilu::DevArray<unsigned long long> d_counters; // idx_top, val_top, flops
   int64_t scratch_slots = 0, slot_doubles = 0;
+  int64_t idx_used = 0, val_used = 0;  // heap entries the last sweep allocated
 
   // ---- final factor (after aggregation), used by apply
   int64_t nb = 0;                    // final block count

@@ -220,10 +220,11 @@ __global__ void __launch_bounds__(256) backward_level(SweepArgs a, const double*
       }
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
+        if (r >= cn) break;  // wave-uniform
         double v = p[r];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == r && r < cn) sv[wv][c0 + r] = t[f + c0 + r] - v;
+        if (lane == r) sv[wv][c0 + r] = t[f + c0 + r] - v;
       }
     }
   }
