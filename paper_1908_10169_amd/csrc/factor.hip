@@ -45,9 +45,33 @@ namespace {
 // Device-scope ordering.  A block's results become visible to blocks on
 // other XCDs by a release (L2 write-back) before it retracts its counts; a
 // worker acquires (L2 invalidate) once after taking a block from the queue.
-// Both are whole-cache operations, so each block issues exactly one of each.
+// Both act on whole caches that every wave of the workgroup shares (its
+// CU's L1 and its XCD's L2), so wave 0 issues them for the workgroup, one
+// of each per block.
 __device__ __forceinline__ void release_agent() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ __forceinline__ void acquire_agent() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+// The cache operation of wave 0 has completed (it counts as a vector memory
+// operation) before the barrier lets the other waves go on.
+__device__ __forceinline__ void wait_vector_memory() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// Every wave waits until its own stores are acknowledged (they are in the
+// L2), then wave 0 writes the L2 back; no wave goes on before that is done.
+__device__ __forceinline__ void wg_release_agent() {
+  wait_vector_memory();
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    release_agent();
+    wait_vector_memory();
+  }
+  __syncthreads();
+}
+// Wave 0 invalidates; the barrier keeps every wave's later loads after it.
+__device__ __forceinline__ void wg_acquire_agent() {
+  if (threadIdx.x < 64) {
+    acquire_agent();
+    wait_vector_memory();
+  }
+  __syncthreads();
+}
 
 __device__ __forceinline__ void raise_error(const FactorArgs& a, int code, int blk) {
   if (atomicCAS(a.err, 0, code) == 0) atomicExch(a.err_block, blk);
@@ -143,9 +167,8 @@ __device__ __forceinline__ int load_preds(const FactorArgs& a, const int32_t* cn
 }
 
 // Append block K to the predecessor list of block B.
-__device__ __forceinline__ void push_pred(const FactorArgs& a, int32_t* cnt_arr, int32_t* list,
-                                          int32_t* ovf_head, int B, int K) {
-  int pos = atomicAdd(&cnt_arr[B], 1);
+__device__ __forceinline__ void push_pred_at(const FactorArgs& a, int32_t* list, int32_t* ovf_head, int B,
+                                             int K, int pos) {
   if (pos < kListCap) {
     list[(int64_t)B * kListCap + pos] = K;
     return;
@@ -157,6 +180,10 @@ __device__ __forceinline__ void push_pred(const FactorArgs& a, int32_t* cnt_arr,
   }
   a.ovf_j[node] = K;
   a.ovf_next[node] = atomicExch(&ovf_head[B], node);
+}
+__device__ __forceinline__ void push_pred(const FactorArgs& a, int32_t* cnt_arr, int32_t* list,
+                                          int32_t* ovf_head, int B, int K) {
+  push_pred_at(a, list, ovf_head, B, K, atomicAdd(&cnt_arr[B], 1));
 }
 
 __device__ __forceinline__ double dot_strided(const double* x, const double* y, int p) {
@@ -383,7 +410,9 @@ struct Lds {
   int ip[kMaxWidth];
   double f[kMaxWidth];
   double smax;
+  double tau_k, alpha_k;    // drop tolerance and perturbation scale of the block
   long long off[2];
+  long long hcur[2], hend[2];  // the worker's heap chunks (values, indices); kept across blocks
 };
 // updater_set counts per hash slot in cand[] followed by candc[]
 static_assert(2 * kCandCap >= kHashSlots, "count slots");
@@ -458,15 +487,21 @@ __device__ __forceinline__ void trace_at(const FlowArgs& d, int K, int field,
   if (d.trace) d.trace[(int64_t)K * kTraceFields + field] = v;
 }
 
-// Push block B to the ready queue (once); who and why are traced.
-__device__ __forceinline__ void push_ready(const FlowArgs& d, int B, int by, int why) {
-  if (atomicCAS(&d.enq[B], 0, 1) == 0) {
-    trace_at(d, B, 0, wall_clock64());
-    trace_at(d, B, 5, (unsigned long long)by);
-    trace_at(d, B, 6, (unsigned long long)why);
-    const int pos = atomicAdd(d.tail, 1);
-    __hip_atomic_store(&d.queue[pos], B, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Push block B to the ready queue; who and why are traced.  Only the
+// retraction that brings B's count to zero calls this, so a second push of B
+// is a protocol error; the mark and the queue slot are taken together.
+__device__ __forceinline__ void push_ready(const FactorArgs& a, const FlowArgs& d, int B, int by,
+                                           int why) {
+  const int again = atomicExch(&d.enq[B], 1);
+  const int pos = atomicAdd(d.tail, 1);
+  trace_at(d, B, 0, wall_clock64());
+  trace_at(d, B, 5, (unsigned long long)by);
+  trace_at(d, B, 6, (unsigned long long)why);
+  if (again != 0 || pos >= a.nb) {
+    raise_error(a, kDevProtocol, by);
+    return;
   }
+  __hip_atomic_store(&d.queue[pos], B, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // The blocks K may update, each with the count K holds in its pending
@@ -545,7 +580,7 @@ __device__ __forceinline__ void retract(const FactorArgs& a, const FlowArgs& d, 
     atomicMax(&d.depth[B], dK);
     const int old = atomicSub(&d.pending[B], c);
     if (old < c) raise_error(a, kDevProtocol, K);
-    if (old == c) push_ready(d, B, K, c);
+    if (old == c) push_ready(a, d, B, K, c);
   }
 }
 
@@ -581,10 +616,9 @@ __device__ __forceinline__ void push_checked(const FactorArgs& a, const FlowArgs
 // wave 0 alone.
 template <bool kWave>
 __device__ __forceinline__ bool pivot_block(const FactorArgs& a, int K, int q, const double* Cp, double* sS,
-                            double* sW, Lds& s) {
+                            double* sW, Lds& s, double alpha) {
   using G = Group<kWave>;
   const int tid = G::id(), nth = G::size();
-  const double alpha = a.alpha_blk ? a.alpha_blk[K] : a.alpha;
   for (int e = tid; e < q * q; e += nth) sS[e] = Cp[e];
   if (tid == 0) s.misc[12] = 0;
   G::sync();
@@ -692,6 +726,35 @@ __device__ __forceinline__ void drop_flags(const FactorArgs& a, const double* Cp
     keep_c[z] = nrm > tau ? 1 : 0;
   }
   __syncthreads();
+}
+
+// Heap space for one block (run by one thread): nv values and ni indices from
+// the worker's current chunks; a chunk that runs short is replaced by a new
+// one of at least a.val_chunk (a.idx_chunk) entries from the shared top.
+// Offsets go to s.off; false when the heap is exhausted.
+__device__ __forceinline__ bool heap_take(const FactorArgs& a, Lds& s, long long nv, long long ni) {
+  const bool nv_new = s.hcur[0] + nv > s.hend[0];
+  const bool ni_new = s.hcur[1] + ni > s.hend[1];
+  const long long tv = max(nv, (long long)a.val_chunk), ti = max(ni, (long long)a.idx_chunk);
+  // both atomics in flight together
+  const long long bv = nv_new ? (long long)atomicAdd(a.val_top, (unsigned long long)tv) : 0;
+  const long long bi = ni_new ? (long long)atomicAdd(a.idx_top, (unsigned long long)ti) : 0;
+  bool ok = true;
+  if (nv_new) {
+    s.hcur[0] = bv;
+    s.hend[0] = min(bv + tv, (long long)a.val_cap);
+    ok = ok && bv + nv <= a.val_cap;
+  }
+  if (ni_new) {
+    s.hcur[1] = bi;
+    s.hend[1] = min(bi + ti, (long long)a.idx_cap);
+    ok = ok && bi + ni <= a.idx_cap;
+  }
+  s.off[0] = s.hcur[0];
+  s.off[1] = s.hcur[1];
+  s.hcur[0] += nv;
+  s.hcur[1] += ni;
+  return ok;
 }
 
 // Returns false (uniformly) when the block reported an error.
@@ -870,7 +933,7 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
   const bool lds = a.lds_pivot && q <= kLdsPivotWidth;
   double* sS = lds ? s_dyn : big;
   double* sW = lds ? s_dyn + q * q : big + q * q;
-  if (!pivot_block<false>(a, K, q, Cp, sS, sW, s)) return false;
+  if (!pivot_block<false>(a, K, q, Cp, sS, sW, s, a.alpha_blk ? a.alpha_blk[K] : a.alpha)) return false;
 
   if (tid == 0) trace_at(d, K, 10, wall_clock64());
   // ---------------- drop: rows of L (scaled) and columns of U (D R)
@@ -911,14 +974,8 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
   const int pbr = wg_exclusive_scan(br, s.scan, &ntr);
   const int pbc = wg_exclusive_scan(bc, s.scan, &ntc);
   if (tid == 0) {
-    const unsigned long long ni = (unsigned long long)(mk + nk + ntr + ntc);
-    unsigned long long vo = atomicAdd(a.val_top, (unsigned long long)(mk + nk) * q);
-    unsigned long long io = atomicAdd(a.idx_top, ni);
-    bool over = vo + (unsigned long long)(mk + nk) * q > (unsigned long long)a.val_cap ||
-                io + ni > (unsigned long long)a.idx_cap;
+    const bool over = !heap_take(a, s, (long long)(mk + nk) * q, (long long)(mk + nk + ntr + ntc));
     s.misc[16] = over ? 1 : 0;
-    s.off[0] = (long long)vo;
-    s.off[1] = (long long)io;
     if (over) raise_error(a, kDevHeapOverflow, K);
   }
   __syncthreads();
@@ -1006,8 +1063,7 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
   add_successor_counts(a, d, TRout, ntr, TCout, ntc, K);
   // publish: every write and count of this block is visible before the
   // retraction
-  release_agent();
-  __syncthreads();
+  wg_release_agent();
   if (tid == 0) trace_at(d, K, 15, wall_clock64());
   retract(a, d, s, na, K);
   if (tid == 0) trace_at(d, K, 4, wall_clock64());
@@ -1074,9 +1130,11 @@ __device__ __forceinline__ int last_le(const int* off, int n, int e) {
 
 template <bool kG>
 __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const FlowArgs& d, int K,
-                                                 Lds& s, double* s_dyn, double* gslot) {
+                                                 Lds& s, double* s_dyn, double* gslot, int next_pos) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  constexpr int kBatch = kFastStage / kThreads;
+  // entries per thread and pass of the staging loops: a pass covers a
+  // typical block; the unrolled body stays small for the instruction cache
+  constexpr int kBatch = 4;
   // storage: LDS, or (kG) the worker's global slot for blocks beyond the LDS
   // capacities; per-candidate arrays sit at multiples of cSpace in stage
   constexpr int cStage = kG ? kBigStage : kFastStage;
@@ -1122,7 +1180,14 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     s.misc[3] = a.bstart[K + 1];
   } else if (tid == 132) {
     __hip_atomic_store(&d.started[K], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    atomicMax(d.max_depth, __hip_atomic_load(&d.depth[K], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1);
+    // every updater's depth is in: K became ready after their retractions
+    const int dep = __hip_atomic_load(&d.depth[K], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s.misc[24] = dep;
+    atomicMax(d.max_depth, dep + 1);
+  } else if (tid == 133) {
+    s.tau_k = a.tau_blk ? a.tau_blk[K] : a.tau;
+  } else if (tid == 134) {
+    s.alpha_k = a.alpha_blk ? a.alpha_blk[K] : a.alpha;
   }
   if (tid == 0) s.misc[8] = 0;
   __syncthreads();
@@ -1373,7 +1438,9 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   double* Cp = fbuf;                    // mc x q, row-major
   double* Rp = Cp + mc * q;             // mcc x q (column z of the row panel)
   double* Tm = Rp + mcc * q;            // update terms
-  const int cap = cBuf - (mc + mcc) * q;
+  // a chunk holds cap terms and, after them, each term's panel position
+  const int cap = (cBuf - (mc + mcc) * q) * 2 / 3;
+  int* Ti = reinterpret_cast<int*>(Tm + cap);
   for (int e = tid; e < (mc + mcc) * q; e += nt) Cp[e] = 0.0;
   __syncthreads();
   {
@@ -1400,56 +1467,106 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     }
   }
   const int npt = np + npr;
+  constexpr int kU = 4;  // terms per thread in flight
   for (int i0 = 0; i0 < nterms; i0 += cap) {
     const int i1 = min(nterms, i0 + cap);
-    for (int e = i0 + tid; e < i1; e += nt) {
-      int t = 0;
-      {
-        int lo = 0, hi = npt;  // last t with ioff <= e
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (fmeta[mid].ioff <= e)
-            lo = mid;
-          else
-            hi = mid;
+    for (int e0 = i0 + tid; e0 < i1; e0 += kU * nt) {
+      // (1) the predecessor and the (row, column) pair of each term
+      int64_t lo[kU], wo[kU];
+      int pp[kU], sr[kU], sc[kU];
+      bool colp[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int e = e0 + u * nt;
+        lo[u] = wo[u] = 0;
+        pp[u] = 0;
+        sr[u] = sc[u] = 0;
+        colp[u] = true;
+        if (e < i1) {
+          int lo_t = 0, hi_t = npt;  // last t with ioff <= e
+          while (hi_t - lo_t > 1) {
+            const int mid = (lo_t + hi_t) >> 1;
+            if (fmeta[mid].ioff <= e)
+              lo_t = mid;
+            else
+              hi_t = mid;
+          }
+          const int t = lo_t;
+          const PredMeta& m = fmeta[t];
+          const int w = e - m.ioff;
+          int ri, cj;
+          if (t < np) {
+            const int nc = m.hi - m.lo;
+            ri = m.lo2 + w / nc;
+            cj = m.lo + w % nc;
+            sr[u] = segoff[2 + t] + ri;
+            sc[u] = segoff[2 + np + t] + cj;
+          } else {
+            const int nr = m.hi - m.lo;
+            ri = m.lo + w % nr;
+            cj = m.lo2 + w / nr;
+            sr[u] = segoff[2 + 2 * np + (t - np)] + ri;
+            sc[u] = segoff[2 + 2 * np + npr + (t - np)] + cj;
+            colp[u] = false;
+          }
+          lo[u] = m.loff + (int64_t)ri * m.p;
+          wo[u] = m.woff + (int64_t)cj * m.p;
+          pp[u] = m.p;
         }
-        t = lo;
       }
-      const PredMeta& m = fmeta[t];
-      const int w = e - m.ioff;
-      int ri, cj;
-      if (t < np) {
-        const int nc = m.hi - m.lo;
-        ri = m.lo2 + w / nc;
-        cj = m.lo + w % nc;
+      // (2) all loads first: row and column indices, then L_J and W_J values
+      int rr[kU], cc[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        rr[u] = stage[sr[u]];
+        cc[u] = stage[sc[u]];
+      }
+      double acc[kU];
+      if (a.update_prec == 0) {
+        int pmax = 0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) pmax = max(pmax, pp[u]);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) acc[u] = 0.0;
+        for (int t0 = 0; t0 < pmax; t0 += 2) {
+          double x[kU][2], y[kU][2];
+#pragma unroll
+          for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+              // clamped in range; the products past p are not taken
+              const int t = min(t0 + k, max(pp[u] - 1, 0));
+              x[u][k] = a.val_heap[lo[u] + t];
+              y[u][k] = a.val_heap[wo[u] + t];
+            }
+#pragma unroll
+          for (int u = 0; u < kU; ++u)
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+              if (t0 + k < pp[u]) acc[u] = fma(x[u][k], y[u][k], acc[u]);
+        }
       } else {
-        const int nr = m.hi - m.lo;
-        ri = m.lo + w % nr;
-        cj = m.lo2 + w / nr;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) acc[u] = pp[u] ? update_term(a, lo[u], wo[u], pp[u]) : 0.0;
       }
-      Tm[e - i0] = update_term(a, m.loff + (int64_t)ri * m.p, m.woff + (int64_t)cj * m.p, m.p);
+      // (3) positions in the panels
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int e = e0 + u * nt;
+        if (e < i1) {
+          Tm[e - i0] = acc[u];
+          Ti[e - i0] = colp[u] ? lower_bound(s.cand, mc, rr[u]) * q + (cc[u] - f)
+                               : mc * q + lower_bound(s.candc, mcc, cc[u]) * q + (rr[u] - f);
+        }
+      }
     }
     __syncthreads();
+    // (4) in predecessor order (a predecessor's terms hit distinct entries)
     for (int t = 0; t < npt; ++t) {
-      const PredMeta& m = fmeta[t];
-      const int t0 = max(i0, m.ioff);
+      const int t0 = max(i0, fmeta[t].ioff);
       const int t1 = min(i1, t + 1 < npt ? fmeta[t + 1].ioff : nterms);
       if (t0 >= t1) continue;
-      for (int e = t0 + tid; e < t1; e += nt) {
-        const int w = e - m.ioff;
-        if (t < np) {
-          const int nc = m.hi - m.lo;
-          const int r = stage[segoff[2 + t] + m.lo2 + w / nc];
-          const int c = stage[segoff[2 + np + t] + m.lo + w % nc] - f;
-          Cp[lower_bound(s.cand, mc, r) * q + c] -= Tm[e - i0];
-        } else {
-          const int u = t - np;
-          const int nr = m.hi - m.lo;
-          const int r = stage[segoff[2 + 2 * np + u] + m.lo + w % nr] - f;
-          const int c = stage[segoff[2 + 2 * np + npr + u] + m.lo2 + w / nr];
-          Rp[lower_bound(s.candc, mcc, c) * q + r] -= Tm[e - i0];
-        }
-      }
+      for (int e = t0 + tid; e < t1; e += nt) fbuf[Ti[e - i0]] -= Tm[e - i0];
       __syncthreads();
     }
   }
@@ -1463,13 +1580,8 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   // ---- pivot block and drop test (shared with the general path)
   double* sS = s_dyn;
   double* sW = s_dyn + q * q;
-  if (tid < 64) {
-    const bool ok = pivot_block<true>(a, K, q, Cp, sS, sW, s);
-    if (tid == 0) s.misc[14] = ok ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s.misc[14]) return kFastError;
-  if (tid == 0) trace_at(d, K, 10, wall_clock64());
+  // wave 0 takes the pivot block; the other waves meanwhile look up the
+  // blocks of the candidate rows and columns (the staged lists are done)
   int* keep_r = s.hash;
   int* keep_c = s.hash + (kG ? kCandCap : 1024);  // below the own-count table
   int* rblk = stage;                // block of candidate row z
@@ -1478,9 +1590,17 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   int* cbp = stage + 3 * cSpace;
   int* trL = stage + 4 * cSpace;    // TR_K and TC_K
   int* tcL = stage + 5 * cSpace;
-  for (int z = q + tid; z < mc; z += nt) rblk[z] = a.blockOf[s.cand[z]];
-  for (int z = tid; z < mcc; z += nt) cblk[z] = a.blockOf[s.candc[z]];
-  drop_flags(a, Cp, Rp, mc, mcc, q, sW, keep_r, keep_c, a.tau_blk ? a.tau_blk[K] : a.tau);
+  if (tid < 64) {
+    const bool ok = pivot_block<true>(a, K, q, Cp, sS, sW, s, s.alpha_k);
+    if (tid == 0) s.misc[14] = ok ? 1 : 0;
+  } else {
+    for (int z = q + tid - 64; z < mc; z += nt - 64) rblk[z] = a.blockOf[s.cand[z]];
+    for (int z = tid - 64; z < mcc; z += nt - 64) cblk[z] = a.blockOf[s.candc[z]];
+  }
+  __syncthreads();
+  if (!s.misc[14]) return kFastError;
+  if (tid == 0) trace_at(d, K, 10, wall_clock64());
+  drop_flags(a, Cp, Rp, mc, mcc, q, sW, keep_r, keep_c, s.tau_k);
   if (tid == 0) trace_at(d, K, 11, wall_clock64());
 
   // ---- positions of kept rows / columns and of their distinct blocks
@@ -1521,14 +1641,8 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   __syncthreads();
   const int mk = s.misc[20], ntr = s.misc[21], nk = s.misc[22], ntc = s.misc[23];
   if (tid == 0) {
-    const unsigned long long ni = (unsigned long long)(mk + nk + ntr + ntc);
-    unsigned long long vo = atomicAdd(a.val_top, (unsigned long long)(mk + nk) * q);
-    unsigned long long io = atomicAdd(a.idx_top, ni);
-    bool over = vo + (unsigned long long)(mk + nk) * q > (unsigned long long)a.val_cap ||
-                io + ni > (unsigned long long)a.idx_cap;
+    const bool over = !heap_take(a, s, (long long)(mk + nk) * q, (long long)(mk + nk + ntr + ntc));
     s.misc[16] = over ? 1 : 0;
-    s.off[0] = (long long)vo;
-    s.off[1] = (long long)io;
     if (over) raise_error(a, kDevHeapOverflow, K);
   }
   __syncthreads();
@@ -1613,16 +1727,22 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     __syncthreads();
   }
   // K updates the row panels of the blocks of its rows of L and the column
-  // panels of the blocks of its columns of U
+  // panels of the blocks of its columns of U; with the same pass, the
+  // successor counts (as add_successor_counts)
   for (int t = tid; t < ntr + ntc; t += nt) {
-    if (t < ntr)
-      push_checked(a, d, a.row_cnt, a.row_list, a.row_ovf, trS[t], K);
-    else
-      push_checked(a, d, a.col_cnt, a.col_list, a.col_ovf, tcS[t - ntr], K);
+    const bool row = t < ntr;
+    const int B = row ? trS[t] : tcS[t - ntr];
+    const int c = row ? lower_bound(tcS, ntc, B) : lower_bound(trS, ntr, B);
+    int32_t* cnt_arr = row ? a.row_cnt : a.col_cnt;
+    // the three accesses are independent: all in flight before any result
+    // is used
+    const int started = __hip_atomic_load(&d.started[B], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int pos = atomicAdd(&cnt_arr[B], 1);
+    const int before = atomicAdd(&d.pending[B], c);
+    if (started || (c > 0 && before <= 0)) raise_error(a, kDevProtocol, K);
+    push_pred_at(a, row ? a.row_list : a.col_list, row ? a.row_ovf : a.col_ovf, B, K, pos);
   }
-  __syncthreads();
   if (tid == 0) trace_at(d, K, 14, wall_clock64());
-  add_successor_counts(a, d, trS, ntr, tcS, ntc, K);
   if (kG) __syncthreads();  // trS / tcS overlay the counts cleared below
 
   // ---- K's own counts (as updater_set): A's entries of K in later blocks,
@@ -1690,9 +1810,14 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   if (tid == 0) trace_at(d, K, 15, wall_clock64());
   // publish: every write and count of this block is visible before the
   // retraction
-  release_agent();
-  __syncthreads();
-  const int dK = __hip_atomic_load(&d.depth[K], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+  wg_release_agent();
+  const int dK = s.misc[24] + 1;
+  // the worker's next queue position, read while the retractions are in
+  // flight (-1: not filled yet)
+  if (tid == nt - 1)
+    s.misc[25] = next_pos < a.nb
+                     ? __hip_atomic_load(&d.queue[next_pos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : -1;
   for (int t = tid; t < own_slots; t += nt) {
     const int B = own[t];
     if (B < 0) continue;
@@ -1700,7 +1825,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     atomicMax(&d.depth[B], dK);
     const int old = atomicSub(&d.pending[B], c);
     if (old < c) raise_error(a, kDevProtocol, K);
-    if (old == c) push_ready(d, B, K, c);
+    if (old == c) push_ready(a, d, B, K, c);
   }
   if (tid == 0) trace_at(d, K, 4, wall_clock64());
   return kFastDone;
@@ -1709,40 +1834,54 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
 // Worker: queue positions blockIdx.x, blockIdx.x + gridDim.x, ... (the
 // launch is cooperative: all workers are resident).  Position p holds the
 // p-th block to become ready; the workgroup waits until it is filled.
-__global__ void __launch_bounds__(kThreads, 2) factor_worker_kernel(FactorArgs a, FlowArgs d) {
+// One instance per update precision (0 FP64, 1 FP32, 2 BF16): the constant
+// removes the other precisions' code from the instance that runs.
+template <int kPrec>
+__global__ void __launch_bounds__(kThreads, 2) factor_worker_kernel(FactorArgs a_in, FlowArgs d) {
+  FactorArgs a = a_in;
+  a.update_prec = kPrec;
   __shared__ Lds s;
   extern __shared__ double s_dyn[];
   const int slot = blockIdx.x;
+  if (threadIdx.x == 0) s.hcur[0] = s.hcur[1] = s.hend[0] = s.hend[1] = 0;
+  __syncthreads();
+  int next = -1;  // this worker's next block when already known
   for (int pos = blockIdx.x; pos < a.nb; pos += gridDim.x) {
     const unsigned long long t0 = wall_clock64();
-    int K = -1;
-    while (true) {
-      K = __hip_atomic_load(&d.queue[pos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int stop = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-                       wall_clock64() - t0 > d.wait_ticks;
-      if (__syncthreads_or(stop)) {
-        if (threadIdx.x == 0) raise_error(a, kDevSpin, pos);
-        return;
+    int K = next;  // uniform: read from LDS after a barrier
+    if (K < 0) {
+      while (true) {
+        K = __hip_atomic_load(&d.queue[pos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int stop = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                         wall_clock64() - t0 > d.wait_ticks;
+        if (__syncthreads_or(stop)) {
+          if (threadIdx.x == 0) raise_error(a, kDevSpin, pos);
+          return;
+        }
+        if (__syncthreads_and(K >= 0)) break;
+        __builtin_amdgcn_s_sleep(2);
       }
-      if (__syncthreads_and(K >= 0)) break;
-      __builtin_amdgcn_s_sleep(2);
     }
-    acquire_agent();
+    wg_acquire_agent();
     if (threadIdx.x == 0) {
       trace_at(d, K, 1, wall_clock64());
       trace_at(d, K, 7, (unsigned long long)blockIdx.x);
     }
+    if (threadIdx.x == 0) s.misc[25] = -1;
+    const int np_ = pos + gridDim.x;
     int r = kFastFallback;
-    if (a.fast_path == 1) r = factor_block_fast<false>(a, d, K, s, s_dyn, nullptr);
+    if (a.fast_path == 1) r = factor_block_fast<false>(a, d, K, s, s_dyn, nullptr, np_);
     if (r == kFastBig || a.fast_path == 2) {
       __syncthreads();
-      r = factor_block_fast<true>(a, d, K, s, s_dyn, a.scratch + (int64_t)slot * a.slot_doubles);
+      r = factor_block_fast<true>(a, d, K, s, s_dyn, a.scratch + (int64_t)slot * a.slot_doubles, np_);
     }
     if (r == kFastFallback) {
       __syncthreads();
       factor_block(a, d, K, slot, s, s_dyn);
     }
     __syncthreads();
+    next = s.misc[25];
+    __syncthreads();  // s.misc[25] is reset by the next round
   }
 }
 
@@ -1882,7 +2021,10 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
   int dev = 0, cus = 0, per_cu = 0;
   CK(hipGetDevice(&dev));
   CK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, factor_worker_kernel, kThreads, dyn));
+  const void* worker = h->opt.update_precision == 1   ? reinterpret_cast<const void*>(factor_worker_kernel<1>)
+                      : h->opt.update_precision == 2 ? reinterpret_cast<const void*>(factor_worker_kernel<2>)
+                                                     : reinterpret_cast<const void*>(factor_worker_kernel<0>);
+  CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, worker, kThreads, dyn));
   const int64_t workers = std::min<int64_t>(nb, std::max<int64_t>(1, (int64_t)cus * std::max(per_cu, 1)));
   const int64_t mq = std::max<int32_t>(maxq, 1);
   const int64_t slot_doubles = std::max<int64_t>(2 * (int64_t)kCandCap * mq + 2 * mq * mq,
@@ -1955,6 +2097,9 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     a.dval = h->d_dval.p; a.sval = h->d_sval.p;
     a.idx_heap = h->d_idx_heap.p; a.idx_cap = (int64_t)h->d_idx_heap.n; a.idx_top = h->d_counters.p + 0;
     a.val_heap = h->d_val_heap.p; a.val_cap = (int64_t)h->d_val_heap.n; a.val_top = h->d_counters.p + 1;
+    // per-worker chunks: at most an eighth of either heap sits unused in them
+    a.val_chunk = std::min<int64_t>(8192, a.val_cap / (8 * workers));
+    a.idx_chunk = std::min<int64_t>(4096, a.idx_cap / (8 * workers));
     a.lo32 = nullptr;
     a.lo16 = nullptr;
     a.elem_bytes = 8;
@@ -2009,7 +2154,7 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
       if (e0) (void)hipEventRecord(e0, st);
     }
     void* kargs[] = {&a, &d};
-    CK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(factor_worker_kernel),
+    CK(hipLaunchCooperativeKernel(worker,
                                   dim3((unsigned)workers), dim3(kThreads), kargs, dyn, st));
     if (h->opt.collect_timing) {
       if (e1) (void)hipEventRecord(e1, st);

@@ -93,6 +93,7 @@ struct FactorArgs {
   double* sval;
   int32_t* idx_heap; int64_t idx_cap; unsigned long long* idx_top;
   double* val_heap;  int64_t val_cap; unsigned long long* val_top;
+  int64_t idx_chunk, val_chunk;    // entries a worker takes from a heap top at once
   float* lo32;                     // FP32 copy of L/W (same offsets) or null
   uint16_t* lo16;                  // BF16 copy of L/W (same offsets) or null
   int elem_bytes;                  // bytes of one update input (8, 4 or 2)
