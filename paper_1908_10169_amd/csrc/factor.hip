@@ -112,6 +112,23 @@ __device__ __forceinline__ bool hash_insert_n(int* table, int n, int key, int* c
   return false;
 }
 
+// As hash_insert_n; a new key also goes to list[count] (when below cap).
+__device__ __forceinline__ bool hash_insert_list(int* table, int n, int key, int* count, int* list,
+                                                 int cap) {
+  unsigned h = (unsigned(key) * 2654435761u) & (unsigned)(n - 1);
+  for (int probe = 0; probe < n; ++probe) {
+    int old = atomicCAS(&table[h], -1, key);
+    if (old == -1) {
+      const int o = atomicAdd(count, 1);
+      if (o < cap) list[o] = key;
+      return true;
+    }
+    if (old == key) return true;
+    h = (h + 1) & (unsigned)(n - 1);
+  }
+  return false;
+}
+
 // As hash_insert_n, returning the slot of the key, or -1 when the table is full.
 __device__ __forceinline__ int hash_insert_at_n(int* table, int n, int key, int* count) {
   unsigned h = (unsigned(key) * 2654435761u) & (unsigned)(n - 1);
@@ -687,6 +704,64 @@ __device__ __forceinline__ bool pivot_block(const FactorArgs& a, int K, int q, c
   return true;
 }
 
+// Pivot block of width q <= 8 in wave 0's registers (lane i q + j holds
+// entry (i, j)), for the common case only: no all-zero row or column, every
+// entry finite and every pivot above eps * smax.  Returns false (uniformly,
+// nothing written) otherwise; the caller then runs pivot_block, which also
+// perturbs.  The inverse takes the operations of gauss_jordan_inverse in the
+// same order, so both give the same bits.
+__device__ __forceinline__ bool pivot_regs(const FactorArgs& a, int q, const double* Cp, double* sS,
+                                           double* sW) {
+  const int lane = threadIdx.x & 63;
+  const bool in = lane < q * q;
+  const int i = in ? lane / q : 0, j = in ? lane - i * q : 0;
+  const double c0 = in ? Cp[lane] : 0.0;
+  double v = c0;
+  const unsigned long long nz = __ballot(in && v != 0.0);
+  for (int c = 0; c < q; ++c) {
+    unsigned long long colm = 0, rowm = 0;
+    for (int r = 0; r < q; ++r) {
+      colm |= 1ull << (r * q + c);
+      rowm |= 1ull << (c * q + r);
+    }
+    if ((nz & colm) == 0 || (nz & rowm) == 0) return false;
+  }
+  if (!__all(!in || isfinite(v))) return false;
+  const double smax = wave_max(in ? fabs(v) : 0.0);
+  unsigned piv = 0;  // 3 bits per step
+  for (int k = 0; k < q; ++k) {
+    // max |w_rk| over r >= k, lowest r on ties
+    double bv = -1.0;
+    int bi = q;
+    for (int r = k; r < q; ++r) {
+      const double x = fabs(__shfl(v, r * q + k, 64));
+      if (x > bv) {
+        bv = x;
+        bi = r;
+      }
+    }
+    if (bi >= q) return false;
+    const double u = __shfl(v, bi * q + k, 64);
+    if (!(u != 0.0 && fabs(u) > a.pivot_eps * smax && isfinite(u))) return false;
+    piv |= (unsigned)bi << (3 * k);
+    if (bi != k) v = __shfl(v, i == k ? bi * q + j : (i == bi ? k * q + j : lane), 64);
+    const double dk = __shfl(v, k * q + k, 64);
+    if (i == k) v = (j == k ? 1.0 : v) / dk;
+    const double fi = __shfl(v, i * q + k, 64);
+    const double wk = __shfl(v, k * q + j, 64);
+    if (i != k) v = fma(-fi, wk, j == k ? 0.0 : v);
+  }
+  for (int k = q - 1; k >= 0; --k) {
+    const int p = (int)((piv >> (3 * k)) & 7u);
+    if (p != k) v = __shfl(v, j == k ? i * q + p : (j == p ? i * q + k : lane), 64);
+  }
+  if (in) {
+    sW[lane] = v;
+    sS[lane] = c0;
+  }
+  return true;
+}
+
 // D_K (sW) and the pivot block used (sS) into the factor storage; called in
 // the write phase with the other factor stores.
 __device__ __forceinline__ void store_pivot(const FactorArgs& a, int K, int q, const double* sS,
@@ -1115,6 +1190,20 @@ __device__ __forceinline__ int wg_scan_array(int* v, int m, int* tmp) {
   return carry;
 }
 
+// Exclusive prefix of v[0..m), m <= 64, by one wave; the total goes to *tot.
+__device__ __forceinline__ void wave_scan_array(int* v, int m, int* tot) {
+  const int lane = threadIdx.x & 63;
+  const int x = lane < m ? v[lane] : 0;
+  int incl = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  if (lane < m) v[lane] = incl - x;
+  if (lane == 63) *tot = incl;
+}
+
 // Last s in [0, n) with off[s] <= e (off ascending, off[n] > e).
 __device__ __forceinline__ int last_le(const int* off, int n, int e) {
   int lo = 0, hi = n;
@@ -1283,20 +1372,32 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
                       : g - 2 < np ? fmeta[g - 2].ntr
                                    : fmeta[g - 2].ntc;
     __syncthreads();
-    const int total = wg_scan_array(fseg, nseg, s.scan);
-    if (tid == 0) fseg[nseg] = total;
-    if (!kG) {
-      const int tot = wg_scan_array(s.x.useg, 2 + np + npr, s.scan);
-      if (tid == 0) s.x.useg[2 + np + npr] = tot;
+    const int nu = 2 + np + npr;
+    if (nseg <= 64 && nu <= 64) {
+      // both offset arrays at once, by waves 0 and 1
+      if (tid < 64)
+        wave_scan_array(fseg, nseg, &fseg[nseg]);
+      else if (!kG && tid < 128)
+        wave_scan_array(s.x.useg, nu, &s.x.useg[nu]);
+      __syncthreads();
+      if (fseg[nseg] > cStage) return fallback;
+    } else {
+      const int total = wg_scan_array(fseg, nseg, s.scan);
+      if (tid == 0) fseg[nseg] = total;
+      if (!kG) {
+        const int tot = wg_scan_array(s.x.useg, nu, s.scan);
+        if (tid == 0) s.x.useg[nu] = tot;
+      }
+      if (total > cStage) return fallback;
+      __syncthreads();
     }
-    if (total > cStage) return fallback;
-    __syncthreads();
   }
   const int* segoff = fseg;
   const int total = segoff[nseg];
 
   // ---- round 3: stage every list; candidate rows (keys r) and columns
-  // (keys ~c) beyond the block go to one hash
+  // (keys ~c) beyond the block go to one hash, and each new key to keys[]
+  int* keys = reinterpret_cast<int*>(fbuf) + 2 * cExtra;
   for (int base = 0; base < total; base += kBatch * nt) {
     int v[kBatch];
     for (int k = 0; k < kBatch; ++k) {
@@ -1314,8 +1415,8 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       const bool rowc = sg == 0 || (sg >= 2 && sg < 2 + np);
       const bool colc = sg == 1 || sg >= 2 + 2 * np + npr;
       if ((rowc || colc) && v[k] > l)
-        if (!hash_insert_n(s.hash, kG ? kHashSlots : kFastCandSlots, rowc ? v[k] : ~v[k],
-                           &s.misc[4]))
+        if (!hash_insert_list(s.hash, kG ? kHashSlots : kFastCandSlots, rowc ? v[k] : ~v[k],
+                              &s.misc[4], keys, 2 * cExtra))
           s.misc[5] = 1;
     }
   }
@@ -1373,16 +1474,33 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       m.lo2 = lower_bound(C, m.nc, l + 1);
     }
   }
+  // candidate rows to tmpR, columns to tmpC (wave-compacted)
   int* tmpR = reinterpret_cast<int*>(fbuf);
   int* tmpC = tmpR + cExtra;
-  for (int t = tid; t < (kG ? kHashSlots : kFastCandSlots); t += nt) {
-    const int key = s.hash[t];
-    if (key >= 0) {
-      const int o = atomicAdd(&s.misc[6], 1);
-      if (o < cExtra) tmpR[o] = key;
-    } else if (key <= -2) {
-      const int o = atomicAdd(&s.misc[7], 1);
-      if (o < cExtra) tmpC[o] = ~key;
+  {
+    const int nkeys = s.misc[4];
+    const int lane = tid & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int t0 = 0; t0 < nkeys; t0 += nt) {
+      const int t = t0 + tid;
+      const int key = t < nkeys ? keys[t] : -1;
+      const bool isr = t < nkeys && key >= 0, isc = t < nkeys && key <= -2;
+      const unsigned long long mr = __ballot(isr), mcl = __ballot(isc);
+      int br = 0, bc = 0;
+      if (lane == 0) {
+        if (mr) br = atomicAdd(&s.misc[6], __popcll(mr));
+        if (mcl) bc = atomicAdd(&s.misc[7], __popcll(mcl));
+      }
+      br = __shfl(br, 0, 64);
+      bc = __shfl(bc, 0, 64);
+      if (isr) {
+        const int o = br + __popcll(mr & below);
+        if (o < cExtra) tmpR[o] = key;
+      }
+      if (isc) {
+        const int o = bc + __popcll(mcl & below);
+        if (o < cExtra) tmpC[o] = ~key;
+      }
     }
   }
   __syncthreads();
@@ -1416,16 +1534,38 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   }
   for (int t = tid; t < q; t += nt) s.cand[t] = f + t;
   // update terms per predecessor: column panel (rows >= f) x (columns in K),
-  // row panel (rows in K) x (columns > l)
-  __syncthreads();
-  for (int t = tid; t < np + npr; t += nt) {
-    const PredMeta& m = fmeta[t];
-    fpred[t] = t < np ? (m.nr - m.lo2) * (m.hi - m.lo) : (m.hi - m.lo) * (m.nc - m.lo2);
+  // row panel (rows in K) x (columns > l); their offsets by one wave when
+  // there are at most 64 predecessors
+  int nterms;
+  if (np + npr <= 64) {
+    if (tid < 64) {
+      int x = 0;
+      if (tid < np + npr) {
+        const PredMeta& m = fmeta[tid];
+        x = tid < np ? (m.nr - m.lo2) * (m.hi - m.lo) : (m.hi - m.lo) * (m.nc - m.lo2);
+      }
+      int incl = x;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (tid >= o) incl += t;
+      }
+      if (tid < np + npr) fmeta[tid].ioff = incl - x;
+      if (tid == 63) s.misc[26] = incl;
+    }
+    __syncthreads();
+    nterms = s.misc[26];
+  } else {
+    __syncthreads();
+    for (int t = tid; t < np + npr; t += nt) {
+      const PredMeta& m = fmeta[t];
+      fpred[t] = t < np ? (m.nr - m.lo2) * (m.hi - m.lo) : (m.hi - m.lo) * (m.nc - m.lo2);
+    }
+    __syncthreads();
+    nterms = wg_scan_array(fpred, np + npr, s.scan);
+    for (int t = tid; t < np + npr; t += nt) fmeta[t].ioff = fpred[t];
+    __syncthreads();
   }
-  __syncthreads();
-  const int nterms = wg_scan_array(fpred, np + npr, s.scan);
-  for (int t = tid; t < np + npr; t += nt) fmeta[t].ioff = fpred[t];
-  __syncthreads();
   if (tid == 0) {
     trace_at(d, K, 3, wall_clock64());
     trace_at(d, K, 16, (unsigned long long)np);
@@ -1591,7 +1731,8 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   int* trL = stage + 4 * cSpace;    // TR_K and TC_K
   int* tcL = stage + 5 * cSpace;
   if (tid < 64) {
-    const bool ok = pivot_block<true>(a, K, q, Cp, sS, sW, s, s.alpha_k);
+    const bool ok = (q <= 8 && pivot_regs(a, q, Cp, sS, sW)) ||
+                    pivot_block<true>(a, K, q, Cp, sS, sW, s, s.alpha_k);
     if (tid == 0) s.misc[14] = ok ? 1 : 0;
   } else {
     for (int z = q + tid - 64; z < mc; z += nt - 64) rblk[z] = a.blockOf[s.cand[z]];
