@@ -107,49 +107,160 @@ __global__ void __launch_bounds__(64) bw_fill(FactorView f, const int32_t* ptr, 
   }
 }
 
+// Dependency levels of the apply: level(K) = 1 + the largest level of the
+// blocks K depends on (0 without any); forward over fw lists (J < K),
+// backward over bw lists (B > K).  The first half of the waves takes the
+// forward direction, the rest the backward one; wave w handles blocks
+// w, w + W, ... in dependency order (ascending forward, descending
+// backward), so the lowest unfinished block always has its dependencies
+// done and, with every wave resident (cooperative launch), each wait ends.
+// Waits are bounded; a timeout sets *err.  Levels start at -1; top[0] and
+// top[1] receive the largest level of each direction (one atomic per wave).
+__global__ void __launch_bounds__(256) apply_levels(int nb, const int32_t* fptr, const int32_t* fj,
+                                                    const int32_t* bptr, const int32_t* bb, int* lf,
+                                                    int* lb, int* top, int* err,
+                                                    unsigned long long wait_ticks) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
+  const int nw = (int)((gridDim.x * (unsigned)blockDim.x) >> 6);
+  const int half = nw >> 1;
+  const bool fwd = wave < half;
+  const int w = fwd ? wave : wave - half, W = fwd ? half : nw - half;
+  const int32_t* ptr = fwd ? fptr : bptr;
+  const int32_t* adj = fwd ? fj : bb;
+  int* lev = fwd ? lf : lb;
+  int wmax = 0;
+  for (int s = w; s < nb; s += W) {
+    const int K = fwd ? s : nb - 1 - s;
+    const int e0 = ptr[K], e1 = ptr[K + 1];
+    int l = 0;
+    for (int e = e0; e < e1; e += 64) {
+      const int J = e + lane < e1 ? adj[e + lane] : -1;
+      int v = J >= 0 ? __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+      const unsigned long long t0 = wall_clock64();
+      while (!__all(v >= 0)) {
+        if (wall_clock64() - t0 > wait_ticks ||
+            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          if (lane == 0) atomicExch(err, 1);
+          return;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if (v < 0) v = __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (J >= 0) l = max(l, v + 1);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) l = max(l, __shfl_xor(l, o, 64));
+    if (lane == 0) __hip_atomic_store(&lev[K], l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    wmax = max(wmax, l);
+  }
+  if (lane == 0) atomicMax(&top[fwd ? 0 : 1], wmax);
+}
+// First position of every level in the sorted levels (every level from 0 to
+// the largest one holds a block: a block of level l depends on one of l - 1).
+__global__ void level_starts(int nb, const int* sorted, int* start) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  if (i == 0 || sorted[i - 1] != sorted[i]) start[sorted[i]] = i;
+  if (i == nb - 1) start[sorted[i] + 1] = nb;
+}
+__global__ void iota_k(int n, int32_t* v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = i;
+}
+
 // Row-major copy of L: row i lists, for every block J (ascending) whose L_J
 // holds row i, the q_J entries L_J(i, :) at columns first(J)..last(J).
-__global__ void __launch_bounds__(256) lr_count(FactorView f, const int32_t* fw_ptr,
+// One wave per block K: the dependencies of K (ascending J) are read 64 at
+// a time, then their rows in K 64 at a time; lane r (and r + 64) then takes
+// row r of K through them in that order.  kFill = false counts the entries
+// of each row into lr_cnt; kFill = true writes them from lr_ptr on.
+template <bool kFill>
+__global__ void __launch_bounds__(256) lr_build(FactorView f, const int32_t* fw_ptr,
                                                 const int32_t* fw_j, const int32_t* fw_r0,
-                                                const int32_t* fw_cnt, int64_t* lr_cnt) {
-  const int K = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (K >= f.nb) return;
-  const int lane = threadIdx.x & 63;
+                                                const int32_t* fw_cnt, const int64_t* lr_ptr,
+                                                int64_t* lr_cnt, int32_t* lr_col, double* lr_val) {
+  __shared__ int sOff[4][65];             // prefix of the dependencies' row counts
+  __shared__ int sR0[4][64], sF[4][64], sP[4][64];
+  __shared__ long long sRoff[4][64], sLoff[4][64];
+  __shared__ int sRow[4][64], sLe[4][64], sI[4][64];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int K = blockIdx.x * 4 + wv;
+  if (K >= f.nb) return;  // no workgroup barrier below
   const int fK = f.bstart[K], q = f.bstart[K + 1] - fK;
-  for (int r = lane; r < q; r += 64) {
-    int64_t c = 0;
-    for (int e = fw_ptr[K]; e < fw_ptr[K + 1]; ++e) {
-      const int J = fw_j[e];
-      const int32_t* R = f.idx + f.roff[J];
-      for (int i = fw_r0[e]; i < fw_r0[e] + fw_cnt[e]; ++i)
-        if (R[i] == fK + r) c += f.bstart[J + 1] - f.bstart[J];
-    }
-    lr_cnt[fK + r] = c;
+  const int e0 = fw_ptr[K], e1 = fw_ptr[K + 1];
+  int64_t at0 = 0, at1 = 0;  // rows lane and lane + 64: next position, or count
+  if (kFill) {
+    if (lane < q) at0 = lr_ptr[fK + lane];
+    if (lane + 64 < q) at1 = lr_ptr[fK + lane + 64];
   }
-}
-__global__ void __launch_bounds__(256) lr_fill(FactorView f, const int32_t* fw_ptr,
-                                               const int32_t* fw_j, const int32_t* fw_r0,
-                                               const int32_t* fw_cnt, const int64_t* lr_ptr,
-                                               int32_t* lr_col, double* lr_val) {
-  const int K = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (K >= f.nb) return;
-  const int lane = threadIdx.x & 63;
-  const int fK = f.bstart[K], q = f.bstart[K + 1] - fK;
-  for (int r = lane; r < q; r += 64) {
-    int64_t at = lr_ptr[fK + r];
-    for (int e = fw_ptr[K]; e < fw_ptr[K + 1]; ++e) {
+  auto wave_sync = []() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+  };
+  for (int c0 = e0; c0 < e1; c0 += 64) {
+    const int e = c0 + lane;
+    int cnt = 0;
+    if (e < e1) {
       const int J = fw_j[e];
-      const int fJ = f.bstart[J], pJ = f.bstart[J + 1] - fJ;
-      const int32_t* R = f.idx + f.roff[J];
-      const double* L = f.val + f.loff[J];
-      for (int i = fw_r0[e]; i < fw_r0[e] + fw_cnt[e]; ++i)
-        if (R[i] == fK + r)
-          for (int c = 0; c < pJ; ++c) {
-            lr_col[at] = fJ + c;
-            lr_val[at] = L[(int64_t)i * pJ + c];
-            ++at;
-          }
+      cnt = fw_cnt[e];
+      const int fJ = f.bstart[J];
+      sR0[wv][lane] = fw_r0[e];
+      sF[wv][lane] = fJ;
+      sP[wv][lane] = f.bstart[J + 1] - fJ;
+      sRoff[wv][lane] = f.roff[J];
+      sLoff[wv][lane] = f.loff[J];
     }
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    sOff[wv][lane + 1] = incl;
+    if (lane == 0) sOff[wv][0] = 0;
+    const int mc = __shfl(incl, 63, 64);
+    wave_sync();
+    for (int t0 = 0; t0 < mc; t0 += 64) {
+      const int t = t0 + lane;
+      if (t < mc) {
+        int lo = 0, hi = 64;  // last dependency with sOff <= t
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (sOff[wv][mid] <= t)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        const int i = sR0[wv][lo] + (t - sOff[wv][lo]);
+        sRow[wv][lane] = f.idx[sRoff[wv][lo] + i] - fK;
+        sLe[wv][lane] = lo;
+        sI[wv][lane] = i;
+      }
+      wave_sync();
+      const int tn = min(64, mc - t0);
+      for (int u = 0; u < tn; ++u) {
+        const int r = sRow[wv][u];
+        if (r != lane && r != lane + 64) continue;
+        const int le = sLe[wv][u];
+        const int pJ = sP[wv][le];
+        int64_t& at = r == lane ? at0 : at1;
+        if (kFill) {
+          const int fJ = sF[wv][le];
+          const double* L = f.val + sLoff[wv][le] + (int64_t)sI[wv][u] * pJ;
+          for (int c = 0; c < pJ; ++c) {
+            lr_col[at + c] = fJ + c;
+            lr_val[at + c] = L[c];
+          }
+        }
+        at += pJ;
+      }
+      wave_sync();
+    }
+  }
+  if (!kFill) {
+    if (lane < q) lr_cnt[fK + lane] = at0;
+    if (lane + 64 < q) lr_cnt[fK + lane + 64] = at1;
   }
 }
 
@@ -411,50 +522,80 @@ bilu_status build_apply_plan(bilu_handle* h) {
   CK(h->lr_ptr.alloc(n + 1));
   DevArray<int64_t> lc;
   CK(lc.alloc(n));
-  lr_count<<<gw, 256, 0, st>>>(f, h->fw_ptr.p, h->fw_j.p, h->fw_r0.p, h->fw_cnt.p, lc.p);
+  lr_build<false><<<gw, 256, 0, st>>>(f, h->fw_ptr.p, h->fw_j.p, h->fw_r0.p, h->fw_cnt.p, nullptr,
+                                       lc.p, nullptr, nullptr);
   int64_t nlr = 0;
   CK(device_scan<int64_t>(h, lc.p, h->lr_ptr.p, n, &nlr));
   CK(h->lr_col.alloc(std::max<int64_t>(1, nlr)));
   CK(h->lr_val.alloc(std::max<int64_t>(1, nlr)));
-  lr_fill<<<gw, 256, 0, st>>>(f, h->fw_ptr.p, h->fw_j.p, h->fw_r0.p, h->fw_cnt.p, h->lr_ptr.p,
-                              h->lr_col.p, h->lr_val.p);
+  lr_build<true><<<gw, 256, 0, st>>>(f, h->fw_ptr.p, h->fw_j.p, h->fw_r0.p, h->fw_cnt.p,
+                                      h->lr_ptr.p, nullptr, h->lr_col.p, h->lr_val.p);
   CK(hipGetLastError());
-  // dependency levels (actual graph of the factor), computed on the host
+  // dependency levels (actual graph of the factor) on the device, then the
+  // blocks of each direction ordered by (level, index)
   {
-    std::vector<int32_t> fp(nb + 1), fj(std::max<int32_t>(1, nfw)), bp(nb + 1),
-        bb(std::max<int32_t>(1, nbw));
-    CK(hipMemcpyAsync(fp.data(), h->fw_ptr.p, (nb + 1) * 4, hipMemcpyDeviceToHost, st));
-    CK(hipMemcpyAsync(bp.data(), h->bw_ptr.p, (nb + 1) * 4, hipMemcpyDeviceToHost, st));
-    CK(hipMemcpyAsync(fj.data(), h->fw_j.p, fj.size() * 4, hipMemcpyDeviceToHost, st));
-    CK(hipMemcpyAsync(bb.data(), h->bw_b.p, bb.size() * 4, hipMemcpyDeviceToHost, st));
+    DevArray<int> lev, misc;
+    CK(lev.alloc(2 * nb));
+    CK(misc.alloc(4));
+    CK(hipMemsetAsync(lev.p, 0xff, 2 * nb * sizeof(int), st));
+    CK(hipMemsetAsync(misc.p, 0, 4 * sizeof(int), st));
+    int dev = 0, cus = 0, per_cu = 0;
+    CK(hipGetDevice(&dev));
+    CK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, apply_levels, 256, 0));
+    // no more waves than blocks (two per direction at least)
+    const int64_t groups = std::max<int64_t>(
+        1, std::min<int64_t>((int64_t)cus * std::max(per_cu, 1), (2 * nb + 255) / 256));
+    unsigned long long wait = h->wait_ticks ? h->wait_ticks : (unsigned long long)1e9;
+    int nbi = (int)nb;
+    int* lf = lev.p;
+    int* lb = lev.p + nb;
+    int* top = misc.p;
+    int* err = misc.p + 2;
+    const int32_t* fp = h->fw_ptr.p;
+    const int32_t* fj = h->fw_j.p;
+    const int32_t* bp = h->bw_ptr.p;
+    const int32_t* bb = h->bw_b.p;
+    void* args[] = {&nbi, &fp, &fj, &bp, &bb, &lf, &lb, &top, &err, &wait};
+    CK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(apply_levels), dim3((unsigned)groups),
+                                  dim3(256), args, 0, st));
+    int hm[4];
+    CK(hipMemcpyAsync(hm, misc.p, sizeof(hm), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
-    auto levels = [&](bool fwd, std::vector<int32_t>& sched, std::vector<int32_t>& lptr) {
-      std::vector<int32_t> lev(nb, 0);
-      int32_t top = 0;
-      for (int64_t s0 = 0; s0 < nb; ++s0) {
-        const int64_t K = fwd ? s0 : nb - 1 - s0;
-        int32_t l = 0;
-        if (fwd)
-          for (int32_t e = fp[K]; e < fp[K + 1]; ++e) l = std::max(l, lev[fj[e]] + 1);
-        else
-          for (int32_t e = bp[K]; e < bp[K + 1]; ++e) l = std::max(l, lev[bb[e]] + 1);
-        lev[K] = l;
-        top = std::max(top, l);
-      }
-      lptr.assign(top + 2, 0);
-      for (int64_t K = 0; K < nb; ++K) lptr[lev[K] + 1]++;
-      for (int32_t l = 0; l <= top; ++l) lptr[l + 1] += lptr[l];
-      sched.resize(nb);
-      std::vector<int32_t> at(lptr.begin(), lptr.end() - 1);
-      for (int64_t K = 0; K < nb; ++K) sched[at[lev[K]]++] = (int32_t)K;
-    };
-    std::vector<int32_t> sf, sb;
-    levels(true, sf, h->lev_f_ptr);
-    levels(false, sb, h->lev_b_ptr);
+    if (hm[2]) return fail(h, BILU_ERR_DEVICE, "apply plan: a dependency wait timed out");
+    // (level, index) order: stable radix sort of the levels with the indices
+    DevArray<int32_t> idx, keys_out, starts;
+    CK(idx.alloc(nb));
+    CK(keys_out.alloc(2 * nb));
+    CK(starts.alloc((int64_t)hm[0] + hm[1] + 4));
     CK(h->lev_f.alloc(nb));
     CK(h->lev_b.alloc(nb));
-    CK(hipMemcpyAsync(h->lev_f.p, sf.data(), nb * 4, hipMemcpyHostToDevice, st));
-    CK(hipMemcpyAsync(h->lev_b.p, sb.data(), nb * 4, hipMemcpyHostToDevice, st));
+    iota_k<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nbi, idx.p);
+    CK(hipGetLastError());
+    int bits = 1;
+    while ((1 << bits) <= std::max(hm[0], hm[1])) ++bits;
+    size_t bytes = 0;
+    CK(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, lf, keys_out.p, idx.p, h->lev_f.p, nbi, 0,
+                                          bits, st));
+    CK(h->d_scan_tmp.alloc(bytes + 1));
+    CK(hipcub::DeviceRadixSort::SortPairs(h->d_scan_tmp.p, bytes, lf, keys_out.p, idx.p, h->lev_f.p,
+                                          nbi, 0, bits, st));
+    CK(hipcub::DeviceRadixSort::SortPairs(h->d_scan_tmp.p, bytes, lb, keys_out.p + nb, idx.p,
+                                          h->lev_b.p, nbi, 0, bits, st));
+    int* sf = starts.p;
+    int* sb = starts.p + hm[0] + 2;
+    level_starts<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nbi, keys_out.p, sf);
+    level_starts<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nbi, keys_out.p + nb, sb);
+    CK(hipGetLastError());
+    h->lev_f_ptr.assign(hm[0] + 2, 0);
+    h->lev_b_ptr.assign(hm[1] + 2, 0);
+    CK(hipMemcpyAsync(h->lev_f_ptr.data(), sf, (hm[0] + 2) * sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(h->lev_b_ptr.data(), sb, (hm[1] + 2) * sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    for (const auto* v : {&h->lev_f_ptr, &h->lev_b_ptr})
+      for (size_t l = 0; l + 1 < v->size(); ++l)
+        if ((*v)[l] >= (*v)[l + 1] || v->back() != nb)
+          return fail(h, BILU_ERR_INTERNAL, "apply plan: inconsistent dependency levels");
     h->stats.apply_levels_fwd = (int64_t)h->lev_f_ptr.size() - 1;
     h->stats.apply_levels_bwd = (int64_t)h->lev_b_ptr.size() - 1;
   }
