@@ -1398,58 +1398,49 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   // ---- round 3: stage every list; candidate rows (keys r) and columns
   // (keys ~c) beyond the block go to one hash, and each new key to keys[]
   int* keys = reinterpret_cast<int*>(fbuf) + 2 * cExtra;
-  for (int base = 0; base < total; base += kBatch * nt) {
+  // K's own counts come with the same pass (LDS variant): A's entries of K
+  // in later blocks, TR_J > K of column predecessors, TC_J > K of row
+  // predecessors; entries [total, total + totu) of the combined index range
+  const int nu = 2 + np + npr, totu = kG ? 0 : s.x.useg[nu];
+  const int tall = total + totu;
+  for (int base = 0; base < tall; base += kBatch * nt) {
     int v[kBatch];
     for (int k = 0; k < kBatch; ++k) {
       const int e = base + tid + k * nt;
       if (e < total) {
         const int sg = last_le(segoff, nseg, e);
         v[k] = fast_list(a, s, fmeta, sg, np, npr)[e - segoff[sg]];
+      } else if (!kG && e < tall) {
+        const int sg = last_le(s.x.useg, nu, e - total);
+        const int i = e - total - s.x.useg[sg];
+        if (sg == 0)
+          v[k] = a.bri[s.x.cpk[0] + i];
+        else if (sg == 1)
+          v[k] = a.bci[s.x.rpk[0] + i];
+        else if (sg - 2 < np)
+          v[k] = a.idx_heap[fmeta[sg - 2].troff + i];
+        else
+          v[k] = a.idx_heap[fmeta[sg - 2].tcoff + i];
       }
     }
     for (int k = 0; k < kBatch; ++k) {
       const int e = base + tid + k * nt;
-      if (e >= total) break;
-      stage[e] = v[k];
-      const int sg = last_le(segoff, nseg, e);
-      const bool rowc = sg == 0 || (sg >= 2 && sg < 2 + np);
-      const bool colc = sg == 1 || sg >= 2 + 2 * np + npr;
-      if ((rowc || colc) && v[k] > l)
-        if (!hash_insert_list(s.hash, kG ? kHashSlots : kFastCandSlots, rowc ? v[k] : ~v[k],
-                              &s.misc[4], keys, 2 * cExtra))
-          s.misc[5] = 1;
-    }
-  }
-  if (!kG) {
-    // K's own counts: A's entries of K in later blocks, TR_J > K of column
-    // predecessors, TC_J > K of row predecessors
-    const int nu = 2 + np + npr, totu = s.x.useg[nu];
-    for (int base = 0; base < totu; base += kBatch * nt) {
-      int v[kBatch];
-      for (int k = 0; k < kBatch; ++k) {
-        const int e = base + tid + k * nt;
-        if (e < totu) {
-          const int sg = last_le(s.x.useg, nu, e);
-          const int i = e - s.x.useg[sg];
-          if (sg == 0)
-            v[k] = a.bri[s.x.cpk[0] + i];
-          else if (sg == 1)
-            v[k] = a.bci[s.x.rpk[0] + i];
-          else if (sg - 2 < np)
-            v[k] = a.idx_heap[fmeta[sg - 2].troff + i];
-          else
-            v[k] = a.idx_heap[fmeta[sg - 2].tcoff + i];
-        }
-      }
-      for (int k = 0; k < kBatch; ++k) {
-        const int e = base + tid + k * nt;
-        if (e < totu && v[k] > K) {
-          const int h = hash_insert_at_n(s.hash + kFastOwn, kFastOwnSlots, v[k], &s.misc[9]);
-          if (h < 0)
-            s.misc[10] = 1;
-          else
-            atomicAdd(&s.hash[kFastOwnCnt + h], 1);
-        }
+      if (e >= tall) break;
+      if (e < total) {
+        stage[e] = v[k];
+        const int sg = last_le(segoff, nseg, e);
+        const bool rowc = sg == 0 || (sg >= 2 && sg < 2 + np);
+        const bool colc = sg == 1 || sg >= 2 + 2 * np + npr;
+        if ((rowc || colc) && v[k] > l)
+          if (!hash_insert_list(s.hash, kG ? kHashSlots : kFastCandSlots, rowc ? v[k] : ~v[k],
+                                &s.misc[4], keys, 2 * cExtra))
+            s.misc[5] = 1;
+      } else if (!kG && v[k] > K) {
+        const int h = hash_insert_at_n(s.hash + kFastOwn, kFastOwnSlots, v[k], &s.misc[9]);
+        if (h < 0)
+          s.misc[10] = 1;
+        else
+          atomicAdd(&s.hash[kFastOwnCnt + h], 1);
       }
     }
   }
