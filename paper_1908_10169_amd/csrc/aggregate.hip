@@ -401,6 +401,20 @@ __global__ void agg_offsets_merged(int m, const int64_t* list, int64_t* roff, in
   woff[e[0]] = e[4];
 }
 
+// Rows, columns and first index of every final block, from its first
+// initial block (index ng gives the end of the last one).
+__global__ void agg_gather(int ng, const int32_t* gfirst, const int32_t* gnr, const int32_t* gnc,
+                           const int32_t* bstart0, int32_t* fnr, int32_t* fnc, int32_t* fbs) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g > ng) return;
+  const int J = gfirst[g];
+  fbs[g] = bstart0[J];
+  if (g < ng) {
+    fnr[g] = gnr[J];
+    fnc[g] = gnc[J];
+  }
+}
+
 __global__ void agg_block_of(const int32_t* bstart, int nb, int32_t* blockOf) {
   const int b = blockIdx.x * blockDim.y + threadIdx.y;
   if (b >= nb) return;
@@ -438,52 +452,64 @@ bilu_status aggregate_device(bilu_handle* h) {
   const unsigned g1 = (unsigned)std::min<int64_t>((nb + kAggWaves - 1) / kAggWaves, 65536);
   agg_decide_kernel<<<g1, 64 * kAggWaves, 0, st>>>(da);
   CK(hipGetLastError());
-  std::vector<int32_t> hdec(3 * nb + 1);
-  CK(hipMemcpyAsync(hdec.data(), dec.p, hdec.size() * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  hipError_t pe = hipSuccess;
+  int32_t* hdec = h->pin_dec.get<int32_t>(3 * nb + 1, &pe);
+  CK(pe);
+  CK(hipMemcpyAsync(hdec, dec.p, (3 * nb + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   CK(hipStreamSynchronize(st));
   if (hdec[3 * nb] != 0)
     return fail(h, BILU_ERR_NO_MEMORY, "aggregation: a merged block exceeds the decision capacity");
+  const int32_t* gnr = hdec + nb;  // rows / columns of a group, by its first block
+  const int32_t* gnc = hdec + 2 * nb;
   // ---- groups: follow the ends from block 0
-  std::vector<int32_t> gfirst;
-  std::vector<int32_t> fnr, fnc;
+  std::vector<int32_t>& gfirst = h->agg_gfirst;
+  gfirst.clear();
   for (int64_t a0 = 0; a0 < nb;) {
     const int64_t e = hdec[a0];
     if (e <= a0 || e > nb) return fail(h, BILU_ERR_INTERNAL, "aggregation: bad group end");
     gfirst.push_back((int32_t)a0);
-    fnr.push_back(hdec[nb + a0]);
-    fnc.push_back(hdec[2 * nb + a0]);
     a0 = e;
   }
   const int64_t ng = (int64_t)gfirst.size();
   gfirst.push_back((int32_t)nb);
-  std::vector<int32_t> fbs(ng + 1);
-  std::vector<int64_t> froff(ng), fcoff(ng), floff(ng), fwoff(ng), fdoff(ng + 1, 0);
-  int64_t io = 0, vo = 0, wmax = 1;
+  h->stats.merges = nb - ng;
+  if (ng == nb) return BILU_OK;  // nothing merged: the sweep's factor is final
+  std::vector<int32_t>& fbs = h->agg_fbs;
+  fbs.resize(ng + 1);
+  // staged uploads: group firsts, then D offsets, then the merged-group list
+  int64_t nmerged = 0;
+  for (int64_t g = 0; g < ng; ++g) nmerged += gfirst[g + 1] - gfirst[g] > 1;
+  const size_t up_words = (size_t)(ng + 2) / 2 + 1 + (size_t)(ng + 1) + 5 * (size_t)nmerged;
+  int64_t* up = h->pin_up.get<int64_t>(up_words, &pe);
+  CK(pe);
+  int32_t* up_gfirst = reinterpret_cast<int32_t*>(up);
+  int64_t* fdoff = up + (ng + 2) / 2 + 1;
+  int64_t* mlist = fdoff + ng + 1;
+  std::copy(gfirst.begin(), gfirst.end(), up_gfirst);
+  fdoff[0] = 0;
+  int64_t wmax = 1;
   for (int64_t g = 0; g < ng; ++g) {
     fbs[g] = h->bstart0[gfirst[g]];
     const int64_t w = h->bstart0[gfirst[g + 1]] - h->bstart0[gfirst[g]];
     wmax = std::max(wmax, w);
-    froff[g] = io;
-    fcoff[g] = io + fnr[g];
-    io += fnr[g] + fnc[g];
-    floff[g] = vo;
-    fwoff[g] = vo + (int64_t)fnr[g] * w;
-    vo += (int64_t)(fnr[g] + fnc[g]) * w;
     fdoff[g + 1] = fdoff[g] + w * w;
   }
   fbs[ng] = (int32_t)n;
-  h->stats.merges = nb - ng;
-  if (ng == nb) return BILU_OK;  // nothing merged: the sweep's factor is final
   // merged blocks go after the sweep's data in its own heaps when they fit;
   // blocks that merged with nothing then stay where they are
-  std::vector<int64_t> mlist;
-  int64_t mi = h->idx_used, mv = h->val_used;
+  int64_t mi = h->idx_used, mv = h->val_used, m = 0;
   for (int64_t g = 0; g < ng; ++g) {
     if (gfirst[g + 1] - gfirst[g] == 1) continue;
-    const int64_t w = h->bstart0[gfirst[g + 1]] - h->bstart0[gfirst[g]];
-    mlist.insert(mlist.end(), {g, mi, mi + fnr[g], mv, mv + (int64_t)fnr[g] * w});
-    mi += fnr[g] + fnc[g];
-    mv += (int64_t)(fnr[g] + fnc[g]) * w;
+    const int64_t w = fbs[g + 1] - fbs[g];
+    const int64_t r = gnr[gfirst[g]], c = gnc[gfirst[g]];
+    int64_t* e = mlist + 5 * m++;
+    e[0] = g;
+    e[1] = mi;
+    e[2] = mi + r;
+    e[3] = mv;
+    e[4] = mv + r * w;
+    mi += r + c;
+    mv += (r + c) * w;
   }
   const bool in_place = mi <= (int64_t)h->d_idx_heap.n && mv <= (int64_t)h->d_val_heap.n;
   CK(h->f_bstart.alloc(ng + 1));
@@ -495,36 +521,48 @@ bilu_status aggregate_device(bilu_handle* h) {
   CK(h->f_loff.alloc(ng));
   CK(h->f_woff.alloc(ng));
   CK(h->f_doff.alloc(ng + 1));
-  if (!in_place) {
-    CK(h->f_idx.alloc(std::max<int64_t>(1, io)));
-    CK(h->f_val.alloc(std::max<int64_t>(1, vo)));
-  }
   CK(h->f_dval.alloc(fdoff[ng]));
   DevArray<int32_t> d_gfirst;
   CK(d_gfirst.alloc(ng + 1));
-  CK(hipMemcpyAsync(d_gfirst.p, gfirst.data(), (ng + 1) * 4, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(h->f_bstart.p, fbs.data(), (ng + 1) * 4, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(h->f_nr.p, fnr.data(), ng * 4, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(h->f_nc.p, fnc.data(), ng * 4, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(d_gfirst.p, up_gfirst, (ng + 1) * 4, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(h->f_doff.p, fdoff, (ng + 1) * 8, hipMemcpyHostToDevice, st));
+  agg_gather<<<(unsigned)((ng + 256) / 256), 256, 0, st>>>((int)ng, d_gfirst.p, dec.p + nb,
+                                                           dec.p + 2 * nb, h->d_bstart.p, h->f_nr.p,
+                                                           h->f_nc.p, h->f_bstart.p);
+  CK(hipGetLastError());
   DevArray<int64_t> d_mlist;
   if (in_place) {
-    const int64_t m = (int64_t)mlist.size() / 5;
     agg_offsets<<<(unsigned)((ng + 255) / 256), 256, 0, st>>>((int)ng, d_gfirst.p, h->fv, h->f_roff.p,
                                                              h->f_coff.p, h->f_loff.p, h->f_woff.p);
     if (m > 0) {
-      CK(d_mlist.alloc(mlist.size()));
-      CK(hipMemcpyAsync(d_mlist.p, mlist.data(), mlist.size() * 8, hipMemcpyHostToDevice, st));
+      CK(d_mlist.alloc(5 * m));
+      CK(hipMemcpyAsync(d_mlist.p, mlist, 5 * m * 8, hipMemcpyHostToDevice, st));
       agg_offsets_merged<<<(unsigned)((m + 255) / 256), 256, 0, st>>>(
           (int)m, d_mlist.p, h->f_roff.p, h->f_coff.p, h->f_loff.p, h->f_woff.p);
     }
     CK(hipGetLastError());
   } else {
-    CK(hipMemcpyAsync(h->f_roff.p, froff.data(), ng * 8, hipMemcpyHostToDevice, st));
-    CK(hipMemcpyAsync(h->f_coff.p, fcoff.data(), ng * 8, hipMemcpyHostToDevice, st));
-    CK(hipMemcpyAsync(h->f_loff.p, floff.data(), ng * 8, hipMemcpyHostToDevice, st));
-    CK(hipMemcpyAsync(h->f_woff.p, fwoff.data(), ng * 8, hipMemcpyHostToDevice, st));
+    // every block is copied: consecutive offsets
+    std::vector<int64_t>& off = h->agg_off;
+    off.resize(4 * ng);
+    int64_t io = 0, vo = 0;
+    for (int64_t g = 0; g < ng; ++g) {
+      const int64_t w = fbs[g + 1] - fbs[g];
+      const int64_t r = gnr[gfirst[g]], c = gnc[gfirst[g]];
+      off[g] = io;
+      off[ng + g] = io + r;
+      off[2 * ng + g] = vo;
+      off[3 * ng + g] = vo + r * w;
+      io += r + c;
+      vo += (r + c) * w;
+    }
+    CK(h->f_idx.alloc(std::max<int64_t>(1, io)));
+    CK(h->f_val.alloc(std::max<int64_t>(1, vo)));
+    CK(hipMemcpyAsync(h->f_roff.p, off.data(), ng * 8, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->f_coff.p, off.data() + ng, ng * 8, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->f_loff.p, off.data() + 2 * ng, ng * 8, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->f_woff.p, off.data() + 3 * ng, ng * 8, hipMemcpyHostToDevice, st));
   }
-  CK(hipMemcpyAsync(h->f_doff.p, fdoff.data(), (ng + 1) * 8, hipMemcpyHostToDevice, st));
   {
     dim3 blk(64, 4);
     agg_block_of<<<dim3((unsigned)((ng + 3) / 4)), blk, 0, st>>>(h->f_bstart.p, (int)ng,

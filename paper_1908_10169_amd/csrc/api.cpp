@@ -210,6 +210,7 @@ bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr, const
   GUARD_BEGIN
   auto t0 = std::chrono::steady_clock::now();
   h->state = 0;
+  h->ilu_static = false;
   bilu_status s = analyze_host(h, n, rowptr, colind, val);
   if (s != BILU_OK) return s;
   const int64_t nnz = h->nnz;

@@ -288,11 +288,18 @@ int64_t ilu1t_partition_device(bilu_handle* h, double tau, std::vector<int32_t>&
   const auto& gs = h->group_starts;
   const int64_t nu = (int64_t)gs.size() - 1;
   hipStream_t st = h->stream;
-  if (h->d_ilu_gs.alloc(gs.size()) != hipSuccess ||
-      hipMemcpyAsync(h->d_ilu_gs.p, gs.data(), gs.size() * sizeof(int64_t), hipMemcpyHostToDevice,
-                     st) != hipSuccess)
-    return -1;
-  if (h->d_ilu_dg.alloc(n) != hipSuccess || h->d_ilu_set.alloc(2 * n * kSetCap) != hipSuccess ||
+  // the unit starts and the diagonal depend on the analyzed matrix only
+  if (!h->ilu_static) {
+    if (h->d_ilu_gs.alloc(gs.size()) != hipSuccess || h->d_ilu_dg.alloc(n) != hipSuccess ||
+        hipMemcpyAsync(h->d_ilu_gs.p, gs.data(), gs.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                       st) != hipSuccess)
+      return -1;
+    diag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>((int)n, h->d_rp.p, h->d_ci.p, h->d_rv.p,
+                                                             h->d_ilu_dg.p);
+    if (hipGetLastError() != hipSuccess) return -1;
+    h->ilu_static = true;
+  }
+  if (h->d_ilu_set.alloc(2 * n * kSetCap) != hipSuccess ||
       h->d_ilu_cnt.alloc(2 * n + nu + 1) != hipSuccess)
     return -1;
   IluArgs a{};
@@ -311,8 +318,6 @@ int64_t ilu1t_partition_device(bilu_handle* h, double tau, std::vector<int32_t>&
   a.gend = h->d_ilu_cnt.p + 2 * n;
   a.overflow = h->d_ilu_cnt.p + 2 * n + nu;
   if (hipMemsetAsync(a.overflow, 0, sizeof(int), st) != hipSuccess) return -1;
-  diag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>((int)n, a.rp, a.ci, a.rv,
-                                                           h->d_ilu_dg.p);
   const unsigned g1 = (unsigned)std::min<int64_t>((n + kWaves - 1) / kWaves, 65536);
   ilu_sets_kernel<<<g1, 64 * kWaves, 0, st>>>(a);
   if (hipStreamSynchronize(st) != hipSuccess) return -1;

@@ -38,6 +38,36 @@ enum DevErr : int {
 
 // Device array owned by a handle.  alloc() keeps the existing allocation
 // when it is large enough (refactoring does not free and reallocate).
+// Pinned host memory that only grows (hipHostMalloc); used for staging
+// copies between host and device without a pageable bounce.
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  PinnedBuf() = default;
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  template <class T>
+  T* get(size_t count, hipError_t* err) {
+    const size_t b = count * sizeof(T);
+    if (b > bytes) {
+      if (p) (void)hipHostFree(p);
+      p = nullptr;
+      bytes = 0;
+      *err = hipHostMalloc(&p, b, hipHostMallocDefault);
+      if (*err != hipSuccess) {
+        p = nullptr;
+        return nullptr;
+      }
+      bytes = b;
+    }
+    *err = hipSuccess;
+    return static_cast<T*>(p);
+  }
+};
+
 template <class T>
 struct DevArray {
   T* p = nullptr;
@@ -226,6 +256,10 @@ struct bilu_handle {
   bilu::DevArray<int32_t> f_idx;     // idx heap of the final factor
   bilu::DevArray<double> f_val, f_dval;
   bool final_is_initial = true;      // no merge happened: f_* alias the factor storage
+  bool ilu_static = false;
+  bilu::PinnedBuf pin_dec, pin_up;     // aggregation: decisions down, group data up
+  std::vector<int32_t> agg_gfirst, agg_fbs;
+  std::vector<int64_t> agg_off;        // final offsets (copying path) and D offsets           // unit starts and diagonal of the analyzed matrix on the device
   bilu::DevArray<double> d_agg_scratch;  // merge workspace (4 w^2 doubles per slot)
   bilu::DevArray<double> d_tau_blk, d_alpha_blk;  // batched factorization only
   bilu::DevArray<int> d_pflag;
