@@ -34,7 +34,8 @@ namespace {
 
 constexpr int kSetCap = 96;        // entries of one set (per k and side)
 constexpr int kSetHash = 256;      // LDS hash slots of one wave (sets)
-constexpr int kSrcCap = 256;       // fill sources (entries before the diagonal)
+constexpr int kSrcCap = 128;       // fill sources (entries before the diagonal)
+constexpr int kCandBatch = 4;      // fill candidates per lane in flight
 constexpr int kGrowHash = 512;     // LDS hash slots of one wave per side (growth)
 constexpr int kWaves = 4;          // waves per workgroup
 
@@ -85,6 +86,8 @@ struct SetLds {
   int hash[kWaves][kSetHash];
   int src[kWaves][kSrcCap];        // fill source index j (L) / i (U)
   double srcv[kWaves][kSrcCap];    // a_jk (L) / a_ki (U)
+  double srcd[kWaves][kSrcCap];    // a_jj of the source
+  long long srcp[kWaves][kSrcCap]; // start of the source's column (row)
   int off[kWaves][kSrcCap + 1];    // prefix of the source lengths
   int misc[kWaves][4];
 };
@@ -129,7 +132,10 @@ __device__ int one_set(const IluArgs& a, const int64_t* ptr, const int32_t* idx,
     int len = 0;
     if (t < nsrc) {
       const int j = s.src[w][t];
-      len = (int)(ptr[j + 1] - ptr[j]);
+      const int64_t p0 = ptr[j];
+      len = (int)(ptr[j + 1] - p0);
+      s.srcp[w][t] = p0;
+      s.srcd[w][t] = a.dg[j];
     }
     int incl = len;
 #pragma unroll
@@ -143,23 +149,37 @@ __device__ int one_set(const IluArgs& a, const int64_t* ptr, const int32_t* idx,
   if (lane == 0) s.off[w][nsrc] = base;
   wave_sync();
   const int total = base;
-  for (int x = lane; x < total; x += 64) {
-    // source t with off[t] <= x < off[t+1]
-    int lo = 0, hi = nsrc;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (s.off[w][mid] <= x)
-        lo = mid;
-      else
-        hi = mid;
+  const double dk = a.dg[k];
+  for (int x0 = 0; x0 < total; x0 += 64 * kCandBatch) {
+    // sources first (LDS), then every candidate's loads, then the tests
+    int iv[kCandBatch], sl[kCandBatch];
+    double vv[kCandBatch];
+#pragma unroll
+    for (int u = 0; u < kCandBatch; ++u) {
+      const int x = x0 + u * 64 + lane;
+      sl[u] = -1;
+      if (x < total) {
+        // source t with off[t] <= x < off[t+1]
+        int lo = 0, hi = nsrc;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s.off[w][mid] <= x)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        const int64_t m2 = s.srcp[w][lo] + (x - s.off[w][lo]);
+        iv[u] = idx[m2];
+        vv[u] = val[m2];
+        sl[u] = lo;
+      }
     }
-    const int j = s.src[w][lo];
-    const int64_t m2 = ptr[j] + (x - s.off[w][lo]);
-    const int i = idx[m2];
-    if (i > k) {
-      const double thr = a.tau * fabs(a.dg[j] * a.dg[k]);
-      if (fabs(val[m2] * s.srcv[w][lo]) >= thr)
-        if (!wave_insert(hash, kSetHash, i, &misc[0])) misc[1] = 1;
+#pragma unroll
+    for (int u = 0; u < kCandBatch; ++u) {
+      if (sl[u] < 0 || iv[u] <= k) continue;
+      const double thr = a.tau * fabs(s.srcd[w][sl[u]] * dk);
+      if (fabs(vv[u] * s.srcv[w][sl[u]]) >= thr)
+        if (!wave_insert(hash, kSetHash, iv[u], &misc[0])) misc[1] = 1;
     }
   }
   wave_sync();
