@@ -302,8 +302,10 @@ __global__ void __launch_bounds__(256) forward_level(SweepArgs a, const double* 
   }
 }
 
-// backward: z_K = D_K (t_K - W_K z(C_K)); lanes over the columns of W_K,
-// 16 rows at a time, wave-wide reduction; v staged in LDS per wave
+// backward: z_K = D_K (t_K - W_K z(C_K)); as in the forward sweep, groups
+// of lanes per row: lane (jj, r) takes row r of W_K over the columns
+// jj, jj + g, ... (W_K is column-major, so a wave reads it contiguously),
+// then a fixed reduction tree over jj; v staged in LDS per wave
 __global__ void __launch_bounds__(256) backward_level(SweepArgs a, const double* t, double* z) {
   __shared__ double sv[4][kMaxWidth];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -317,26 +319,16 @@ __global__ void __launch_bounds__(256) backward_level(SweepArgs a, const double*
     const int m = a.f.nc[K];
     const int32_t* Cc = a.f.idx + a.f.coff[K];
     const double* W = a.f.val + a.f.woff[K];
-    for (int c0 = 0; c0 < q; c0 += 16) {
-      const int cn = min(16, q - c0);
-      double p[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) p[r] = 0.0;
-      for (int j = lane; j < m; j += 64) {
-        const double zj = z[Cc[j]];
-        const double* wc = W + (int64_t)j * q + c0;
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-          if (r < cn) p[r] = fma(wc[r], zj, p[r]);
-      }
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        if (r >= cn) break;  // wave-uniform
-        double v = p[r];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        if (lane == r) sv[wv][c0 + r] = t[f + c0 + r] - v;
-      }
+    int qp = 1;
+    while (qp < q && qp < 64) qp <<= 1;
+    const int g = 64 / qp;  // column groups
+    for (int r0 = 0; r0 < q; r0 += qp) {
+      const int r = r0 + (lane & (qp - 1)), jj = lane / qp;
+      double acc = 0.0;
+      if (r < q)
+        for (int j = jj; j < m; j += g) acc = fma(W[(int64_t)j * q + r], z[Cc[j]], acc);
+      for (int o = 32; o >= qp; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (jj == 0 && r < q) sv[wv][r] = t[f + r] - acc;
     }
   }
   __syncthreads();
