@@ -272,6 +272,7 @@ struct bilu_handle {
   bilu::DevArray<int32_t> lr_col;
   bilu::DevArray<double> lr_val;
   bilu::DevArray<int32_t> lev_f, lev_b;          // blocks by forward / backward level
+  bilu::DevArray<int2> lev_f_fq;                 // first row and width of lev_f's blocks
   bilu::DevArray<unsigned char> d_scan_tmp;      // device-scan workspace
   std::vector<int32_t> lev_f_ptr, lev_b_ptr;
 

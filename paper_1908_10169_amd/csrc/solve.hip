@@ -164,6 +164,12 @@ __global__ void level_starts(int nb, const int* sorted, int* start) {
   if (i == 0 || sorted[i - 1] != sorted[i]) start[sorted[i]] = i;
   if (i == nb - 1) start[sorted[i] + 1] = nb;
 }
+__global__ void slot_rows(int nb, const int32_t* sched, const int32_t* bstart, int2* fq) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const int K = sched[i];
+  fq[i] = make_int2(bstart[K], bstart[K + 1] - bstart[K]);
+}
 __global__ void iota_k(int n, int32_t* v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = i;
@@ -276,6 +282,7 @@ struct SweepArgs {
   const int32_t* lr_col;
   const double* lr_val;
   const int32_t* sched;
+  const int2* fq;  // forward: first row and width of each scheduled block
   int begin, end;
 };
 
@@ -285,8 +292,8 @@ __global__ void __launch_bounds__(256) forward_level(SweepArgs a, const double* 
   const int w = a.begin + blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= a.end) return;
   const int lane = threadIdx.x & 63;
-  const int K = a.sched[w];
-  const int f = a.f.bstart[K], q = a.f.bstart[K + 1] - f;
+  const int2 fq = a.fq[w];
+  const int f = fq.x, q = fq.y;
   int qp = 1;
   while (qp < q && qp < 64) qp <<= 1;
   const int g = 64 / qp;  // lanes per row
@@ -577,6 +584,8 @@ bilu_status build_apply_plan(bilu_handle* h) {
     int* sf = starts.p;
     int* sb = starts.p + hm[0] + 2;
     level_starts<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nbi, keys_out.p, sf);
+    CK(h->lev_f_fq.alloc(nb));
+    slot_rows<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nbi, h->lev_f.p, f.bstart, h->lev_f_fq.p);
     level_starts<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nbi, keys_out.p + nb, sb);
     CK(hipGetLastError());
     h->lev_f_ptr.assign(hm[0] + 2, 0);
@@ -605,6 +614,7 @@ bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t
   a.lr_col = h->lr_col.p;
   a.lr_val = h->lr_val.p;
   a.sched = h->lev_f.p;
+  a.fq = h->lev_f_fq.p;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (h->opt.collect_timing) {
     e0 = h->ev_get();
