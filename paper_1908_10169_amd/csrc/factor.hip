@@ -1221,9 +1221,10 @@ template <bool kG>
 __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const FlowArgs& d, int K,
                                                  Lds& s, double* s_dyn, double* gslot, int next_pos) {
   const int tid = threadIdx.x, nt = blockDim.x;
-  // entries per thread and pass of the staging loops: a pass covers a
-  // typical block; the unrolled body stays small for the instruction cache
-  constexpr int kBatch = 4;
+  // entries per thread and pass of the staging loop: a pass covers a
+  // typical LDS-variant block and the unrolled body stays small for the
+  // instruction cache; the global variant stages far longer lists
+  constexpr int kBatch = kG ? 12 : 4;
   // storage: LDS, or (kG) the worker's global slot for blocks beyond the LDS
   // capacities; per-candidate arrays sit at multiples of cSpace in stage
   constexpr int cStage = kG ? kBigStage : kFastStage;
@@ -1447,23 +1448,46 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   __syncthreads();
   if (!kG && s.misc[10]) return kFastBig;
   if (s.misc[5] || s.misc[4] > 2 * cExtra) return fallback;
-  // positions inside the predecessors' sorted lists
+  // positions inside the predecessors' sorted lists (the three searches of
+  // a predecessor step together, so their loads overlap)
   for (int t = tid; t < np + npr; t += nt) {
     PredMeta& m = fmeta[t];
+    const int* A;
+    const int* B;
+    int na, nb_, ka, kb;
     if (t < np) {
-      const int* R = stage + segoff[2 + t];
-      const int* C = stage + segoff[2 + np + t];
-      m.lo = lower_bound(C, m.nc, f);
-      m.hi = lower_bound(C, m.nc, l + 1);
-      m.lo2 = lower_bound(R, m.nr, f);
+      A = stage + segoff[2 + np + t];  // C: lo, hi
+      B = stage + segoff[2 + t];       // R: lo2
+      na = m.nc;
+      nb_ = m.nr;
+      ka = f;
+      kb = f;
     } else {
       const int u = t - np;
-      const int* R = stage + segoff[2 + 2 * np + u];
-      const int* C = stage + segoff[2 + 2 * np + npr + u];
-      m.lo = lower_bound(R, m.nr, f);
-      m.hi = lower_bound(R, m.nr, l + 1);
-      m.lo2 = lower_bound(C, m.nc, l + 1);
+      A = stage + segoff[2 + 2 * np + u];        // R: lo, hi
+      B = stage + segoff[2 + 2 * np + npr + u];  // C: lo2
+      na = m.nr;
+      nb_ = m.nc;
+      ka = f;
+      kb = l + 1;
     }
+    int lo0 = 0, hi0 = na, lo1 = 0, hi1 = na, lo2 = 0, hi2 = nb_;
+    while (lo0 < hi0 || lo1 < hi1 || lo2 < hi2) {
+      const int m0 = (lo0 + hi0) >> 1, m1 = (lo1 + hi1) >> 1, m2 = (lo2 + hi2) >> 1;
+      const int v0 = lo0 < hi0 ? A[m0] : 0, v1 = lo1 < hi1 ? A[m1] : 0, v2 = lo2 < hi2 ? B[m2] : 0;
+      if (lo0 < hi0) {
+        if (v0 < ka) lo0 = m0 + 1; else hi0 = m0;
+      }
+      if (lo1 < hi1) {
+        if (v1 < l + 1) lo1 = m1 + 1; else hi1 = m1;
+      }
+      if (lo2 < hi2) {
+        if (v2 < kb) lo2 = m2 + 1; else hi2 = m2;
+      }
+    }
+    m.lo = lo0;
+    m.hi = lo1;
+    m.lo2 = lo2;
   }
   // candidate rows to tmpR, columns to tmpC (wave-compacted)
   int* tmpR = reinterpret_cast<int*>(fbuf);
