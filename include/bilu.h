@@ -75,6 +75,11 @@ typedef struct {
                          /* take the general path.  1: every block takes the general */
                          /* path.  2: global staging wherever it fits.  All three   */
                          /* compute identical bits                                   */
+  int apply_path;        /* 0 (default): the apply runs as one dataflow launch; if a */
+                         /* dependency wait times out (a device that cannot keep    */
+                         /* every workgroup resident) the handle switches to 1 for  */
+                         /* good.  1: one launch per dependency level.  Both        */
+                         /* compute identical bits                                   */
 } bilu_options;
 
 typedef struct bilu_handle bilu_handle;

@@ -273,6 +273,9 @@ struct bilu_handle {
   bilu::DevArray<double> lr_val;
   bilu::DevArray<int32_t> lev_f, lev_b;          // blocks by forward / backward level
   bilu::DevArray<int2> lev_f_fq;                 // first row and width of lev_f's blocks
+  bilu::DevArray<int> d_apply_err;              // dataflow apply: a wait timed out
+  int64_t apply_groups = 1;                      // its resident workgroups
+  bool apply_by_levels = false;                  // the dataflow apply timed out once
   bilu::DevArray<unsigned char> d_scan_tmp;      // device-scan workspace
   std::vector<int32_t> lev_f_ptr, lev_b_ptr;
 

@@ -349,6 +349,155 @@ __global__ void __launch_bounds__(256) backward_level(SweepArgs a, const double*
   }
 }
 
+// ---------------------------------------------------------------------------
+// Dataflow apply: one cooperative launch runs every forward block, then
+// every backward block, in the plan's level order (slots 0..nb-1 forward,
+// nb..2nb-1 backward); wave w takes slots w, w + W, ... in order, every
+// workgroup resident.  A value of t (z) is its own
+// ready mark: both start as kPending, a bit pattern (a signalling NaN) that
+// no arithmetic produces, and a consumer polls the value with device-scope
+// atomic loads until the producer's atomic store replaces it.  Every
+// dependency of a slot sits at a lower slot and a wave finishes its lower
+// slots first, so the lowest unfinished slot always completes and every wait
+// ends; waits are bounded anyway (*err).
+// The arithmetic is that of forward_level and backward_level, in the same
+// order.
+// ---------------------------------------------------------------------------
+// both halves 0x7ff4b11e: a signalling NaN, set with a 32-bit fill
+constexpr unsigned kPendingHalf = 0x7ff4b11eu;
+constexpr unsigned long long kPending = ((unsigned long long)kPendingHalf << 32) | kPendingHalf;
+// LDS requested (unused) per workgroup so that at most four share a CU: every
+// workgroup is then resident, which the static slot order relies on
+constexpr size_t kFlowLds = 36 * 1024;
+
+struct FlowApplyArgs {
+  FactorView f;
+  const int64_t* lr_ptr;
+  const int32_t* lr_col;
+  const double* lr_val;
+  const int2* fq;        // forward slots: first row and width
+  const int32_t* lev_b;  // backward slots: block
+  int nb;
+  const double* x;
+  unsigned long long* t;
+  unsigned long long* z;
+  int* err;             // [0] set on a timeout; [1] slot, [2] side, [3] awaited index
+  unsigned long long wait_ticks;
+};
+
+// Values of t (side 0) or z (side 1) at idx for the lanes with has set, once
+// every one of them is published; the whole wave waits together (no lane
+// spins on its own).  On a timeout the first one records where it waited.
+__device__ __forceinline__ double await_values(const FlowApplyArgs& a, int side, bool has, int64_t idx,
+                                               unsigned long long t0, bool& bad, int slot) {
+  unsigned long long* p = (side ? a.z : a.t) + (has ? idx : 0);
+  unsigned long long v = has ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+  while (!__all(!has || v != kPending)) {
+    if (__any(bad)) {
+      bad = true;
+      return 0.0;
+    }
+    if (wall_clock64() - t0 > a.wait_ticks) {
+      if (has && v == kPending && atomicCAS(&a.err[0], 0, 1) == 0) {
+        a.err[1] = slot;
+        a.err[2] = side;
+        a.err[3] = (int)idx;
+      }
+      bad = true;
+      return 0.0;
+    }
+    if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      bad = true;
+      return 0.0;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    if (has && v == kPending) v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return __longlong_as_double((long long)v);
+}
+__device__ __forceinline__ void publish_value(unsigned long long* p, double v) {
+  __hip_atomic_store(p, (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int wave_max_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs a) {
+  __shared__ double sv[4][kMaxWidth];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wave = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
+  const int nw = (int)((gridDim.x * (unsigned)blockDim.x) >> 6);
+  for (int s = wave; s < 2 * a.nb; s += nw) {
+    const unsigned long long t0 = wall_clock64();
+    bool bad = false;
+    if (s < a.nb) {
+      const int2 fq = a.fq[s];
+      const int f = fq.x, q = fq.y;
+      int qp = 1;
+      while (qp < q && qp < 64) qp <<= 1;
+      const int g = 64 / qp;  // lanes per row
+      for (int r0 = 0; r0 < q; r0 += qp) {
+        const int r = r0 + lane / g, sub = lane % g;
+        int64_t b = 0, e = 0;
+        if (r < q) {
+          b = a.lr_ptr[f + r] + sub;
+          e = a.lr_ptr[f + r + 1];
+        }
+        const int steps = wave_max_int(b < e ? (int)((e - b + g - 1) / g) : 0);
+        double acc = 0.0;
+        for (int i = 0; i < steps; ++i) {
+          const int64_t k = b + (int64_t)i * g;
+          const bool has = k < e;
+          const int col = has ? a.lr_col[k] : 0;
+          const double tv = await_values(a, 0, has, col, t0, bad, s);
+          if (has) acc = fma(a.lr_val[k], tv, acc);
+        }
+        for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (r < q && sub == 0) publish_value(&a.t[f + r], a.x[f + r] - acc);
+      }
+    } else {
+      const int K = a.lev_b[s - a.nb];
+      const int f = a.f.bstart[K], q = a.f.bstart[K + 1] - f;
+      const int m = a.f.nc[K];
+      const int32_t* Cc = a.f.idx + a.f.coff[K];
+      const double* W = a.f.val + a.f.woff[K];
+      int qp = 1;
+      while (qp < q && qp < 64) qp <<= 1;
+      const int g = 64 / qp;  // column groups
+      const int steps = (m + g - 1) / g;
+      for (int r0 = 0; r0 < q; r0 += qp) {
+        const int r = r0 + (lane & (qp - 1)), jj = lane / qp;
+        double acc = 0.0;
+        for (int i = 0; i < steps; ++i) {
+          const int j = jj + i * g;
+          const bool has = r < q && j < m;
+          const int col = has ? Cc[j] : 0;
+          const double zv = await_values(a, 1, has, col, t0, bad, s);
+          if (has) acc = fma(W[(int64_t)j * q + r], zv, acc);
+        }
+        for (int o = 32; o >= qp; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        const bool own = jj == 0 && r < q;
+        const double tv = await_values(a, 0, own, f + r, t0, bad, s);
+        if (own) sv[wv][r] = tv - acc;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      const double* D = a.f.dval + a.f.doff[K];
+      for (int r = lane; r < q; r += 64) {
+        double acc = 0.0;
+        for (int c = 0; c < q; ++c) acc = fma(D[r * q + c], sv[wv][c], acc);
+        publish_value(&a.z[f + r], acc);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (__any(bad)) return;
+  }
+}
+
 // y = A x, CSR, 8 lanes per row.
 __global__ void __launch_bounds__(256) spmv_csr(int64_t n, const int64_t* rp, const int32_t* ci,
                                                 const double* v, const double* x, double* y) {
@@ -601,12 +750,24 @@ bilu_status build_apply_plan(bilu_handle* h) {
     h->stats.apply_levels_bwd = (int64_t)h->lev_b_ptr.size() - 1;
   }
   CK(h->w_red.alloc(kDotBlocks + 64));
+  CK(h->d_apply_err.alloc(4));
+  {
+    // workgroups of the dataflow apply: what fits at once, no more than its
+    // slots need
+    int dev = 0, cus = 0, per_cu = 0;
+    CK(hipGetDevice(&dev));
+    CK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, apply_flow, 256, kFlowLds));
+    h->apply_groups = std::max<int64_t>(
+        1, std::min<int64_t>((int64_t)cus * std::max(per_cu, 1), (2 * nb + 3) / 4));
+  }
   CK(hipStreamSynchronize(st));
   return BILU_OK;
 #undef CK
 }
 
-bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t) {
+// One launch per dependency level (forward_level, backward_level).
+static void apply_levels_launch(bilu_handle* h, const double* x, double* y, double* t) {
   hipStream_t st = h->stream;
   SweepArgs a{};
   a.f = h->fv;
@@ -615,12 +776,6 @@ bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t
   a.lr_val = h->lr_val.p;
   a.sched = h->lev_f.p;
   a.fq = h->lev_f_fq.p;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (h->opt.collect_timing) {
-    e0 = h->ev_get();
-    e1 = h->ev_get();
-    if (e0) (void)hipEventRecord(e0, st);
-  }
   const int nf = (int)h->lev_f_ptr.size() - 1;
   for (int L = 0; L < nf; ++L) {
     a.begin = h->lev_f_ptr[L];
@@ -634,13 +789,63 @@ bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t
     a.end = h->lev_b_ptr[L + 1];
     backward_level<<<(unsigned)((a.end - a.begin + 3) / 4), 256, 0, st>>>(a, t, y);
   }
+}
+
+bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t) {
+  hipStream_t st = h->stream;
+  const int64_t n = h->n;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->opt.collect_timing) {
+    e0 = h->ev_get();
+    e1 = h->ev_get();
+    if (e0) (void)hipEventRecord(e0, st);
+  }
+#define CK(x)                                          \
+  do {                                                 \
+    hipError_t e_ = (x);                               \
+    if (e_ != hipSuccess) return hip_check(h, e_, #x); \
+  } while (0)
+  bool by_levels = h->opt.apply_path == 1 || h->apply_by_levels;
+  if (!by_levels) {
+    FlowApplyArgs a{};
+    a.f = h->fv;
+    a.lr_ptr = h->lr_ptr.p;
+    a.lr_col = h->lr_col.p;
+    a.lr_val = h->lr_val.p;
+    a.fq = h->lev_f_fq.p;
+    a.lev_b = h->lev_b.p;
+    a.nb = (int)h->fv.nb;
+    a.x = x;
+    a.t = reinterpret_cast<unsigned long long*>(t);
+    a.z = reinterpret_cast<unsigned long long*>(y);
+    a.err = h->d_apply_err.p;
+    // a stalled wait means a workgroup that never ran: two seconds
+    a.wait_ticks = (h->wait_ticks ? h->wait_ticks : (unsigned long long)1e9) / 5;
+    CK(hipMemsetAsync(a.err, 0, 4 * sizeof(int), st));
+    CK(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(a.t), (int)kPendingHalf, 2 * n, st));
+    CK(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(a.z), (int)kPendingHalf, 2 * n, st));
+    void* args[] = {&a};
+    CK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(apply_flow),
+                                  dim3((unsigned)h->apply_groups), dim3(256), args, kFlowLds, st));
+    int herr = 0;
+    CK(hipMemcpyAsync(&herr, a.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (herr) {
+      // recomputed by levels, here and from now on
+      h->apply_by_levels = true;
+      by_levels = true;
+    }
+  }
+  if (by_levels) {
+    apply_levels_launch(h, x, y, t);
+    CK(hipGetLastError());
+  }
   if (h->opt.collect_timing) {
     if (e1) (void)hipEventRecord(e1, st);
     h->ev_record(1, e0, e1);
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_check(h, e, "apply launch");
   return BILU_OK;
+#undef CK
 }
 
 }  // namespace bilu

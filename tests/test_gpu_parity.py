@@ -233,6 +233,31 @@ def test_fast_and_general_paths_identical(name):
     assert outs[0] == outs[1] == outs[2]
 
 
+@pytest.mark.parametrize("name", ["cd3d_12_b4", "cd3d_24_b4", "el3d_16_b3"])
+def test_apply_paths_identical(name):
+    """The apply as one dataflow launch and as one launch per dependency
+    level give the same bits; at 24^3 x 4 and 16^3 x 3 every wave of the
+    dataflow launch takes several slots."""
+    torch = _torch()
+    from paper_1908_10169_amd import bilu
+    w = mg.workload(name)
+    say(f"[apply paths] {name} n={w.a.n}")
+    rng = np.random.default_rng(11)
+    x = torch.from_numpy(rng.standard_normal(w.a.n)).cuda()
+    outs = []
+    for path in (0, 1):
+        h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, apply_path=path)
+        h.analyze(w.a, pre_perm=w.perm)
+        h.factor(w.tau)
+        y = torch.empty_like(x)
+        for _ in range(2):  # a second call reuses the plan and buffers
+            h.apply(x, y)
+        h.sync()
+        outs.append(y.cpu().numpy().tobytes())
+        h.close()
+    assert outs[0] == outs[1]
+
+
 def test_state_errors():
     torch = _torch()
     from paper_1908_10169_amd import bilu
