@@ -430,6 +430,9 @@ struct Lds {
   double tau_k, alpha_k;    // drop tolerance and perturbation scale of the block
   long long off[2];
   long long hcur[2], hend[2];  // the worker's heap chunks (values, indices); kept across blocks
+  // the worker's share of the launch counters, added once when it ends
+  unsigned long long acc_flops, acc_bytes;
+  int acc_depth;
 };
 // updater_set counts per hash slot in cand[] followed by candc[]
 static_assert(2 * kCandCap >= kHashSlots, "count slots");
@@ -858,7 +861,8 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
   }
   if (tid == 0) {
     __hip_atomic_store(&d.started[K], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    atomicMax(d.max_depth, __hip_atomic_load(&d.depth[K], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1);
+    s.acc_depth = max(s.acc_depth,
+                      __hip_atomic_load(&d.depth[K], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1);
   }
   const int na = updater_set(a, K, s, np, npr);
   if (na < 0) {
@@ -1116,8 +1120,8 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
     a.ntr[K] = ntr;
     a.tcoff[K] = io + mk + nk + ntr;
     a.ntc[K] = ntc;
-    atomicAdd(a.flops, (unsigned long long)flops);
-    atomicAdd(a.upd_bytes, (unsigned long long)ubytes);
+    s.acc_flops += (unsigned long long)flops;
+    s.acc_bytes += (unsigned long long)ubytes;
   }
   __syncthreads();
   if (tid == 0) trace_at(d, K, 13, wall_clock64());
@@ -1217,6 +1221,36 @@ __device__ __forceinline__ int last_le(const int* off, int n, int e) {
   return lo;
 }
 
+// Entry e of A's columns (e < nA0) or rows of block K in the staged lists:
+// where its value is and its position in the panels (-1: outside them).
+struct AEntry {
+  const double* src;
+  int tgt;
+};
+__device__ __forceinline__ AEntry a_entry(const FactorArgs& a, const Lds& s, const int* stage, int e,
+                                          int nA0, int f, int l, int q, int mc, int mcc) {
+  if (e < nA0) {
+    const int r = stage[e];
+    const long long m = s.x.cpk[0] + e;
+    int tgt = -1;
+    if (r >= f) {
+      int c = 0;
+      while (s.x.cpk[c + 1] <= m) ++c;
+      tgt = lower_bound(s.cand, mc, r) * q + c;
+    }
+    return {a.cv + m, tgt};
+  }
+  const int c = stage[e];
+  const long long m = s.x.rpk[0] + (e - nA0);
+  int tgt = -1;
+  if (c > l) {
+    int r = 0;
+    while (s.x.rpk[r + 1] <= m) ++r;
+    tgt = mc * q + lower_bound(s.candc, mcc, c) * q + r;
+  }
+  return {a.rv + m, tgt};
+}
+
 template <bool kG>
 __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const FlowArgs& d, int K,
                                                  Lds& s, double* s_dyn, double* gslot, int next_pos) {
@@ -1273,7 +1307,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     // every updater's depth is in: K became ready after their retractions
     const int dep = __hip_atomic_load(&d.depth[K], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     s.misc[24] = dep;
-    atomicMax(d.max_depth, dep + 1);
+    s.acc_depth = max(s.acc_depth, dep + 1);
   } else if (tid == 133) {
     s.tau_k = a.tau_blk ? a.tau_blk[K] : a.tau;
   } else if (tid == 134) {
@@ -1598,28 +1632,20 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   int* Ti = reinterpret_cast<int*>(Tm + cap);
   for (int e = tid; e < (mc + mcc) * q; e += nt) Cp[e] = 0.0;
   __syncthreads();
-  {
-    const int nA0 = segoff[1], nA1 = segoff[2] - segoff[1];
-    for (int e = tid; e < nA0 + nA1; e += nt) {
-      if (e < nA0) {
-        const int r = stage[e];
-        if (r >= f) {
-          const long long m = s.x.cpk[0] + e;
-          int c = 0;
-          while (s.x.cpk[c + 1] <= m) ++c;
-          Cp[lower_bound(s.cand, mc, r) * q + c] = a.cv[m];
-        }
-      } else {
-        const int e1 = e - nA0;
-        const int c = stage[nA0 + e1];
-        if (c > l) {
-          const long long m = s.x.rpk[0] + e1;
-          int r = 0;
-          while (s.x.rpk[r + 1] <= m) ++r;
-          Rp[lower_bound(s.candc, mcc, c) * q + r] = a.rv[m];
-        }
-      }
-    }
+  // A's entries of K: panel position (-1: outside the panels) and value
+  const int nA0 = segoff[1], nA = segoff[2];
+  for (int e = nt + tid; e < nA; e += nt) {  // beyond the first nt entries (rare)
+    const AEntry x = a_entry(a, s, stage, e, nA0, f, l, q, mc, mcc);
+    if (x.tgt >= 0) fbuf[x.tgt] = *x.src;
+  }
+  // the first nt: loaded now, stored with the first chunk of terms, so both
+  // loads share one round trip
+  int a_tgt = -1;
+  double a_val = 0.0;
+  if (tid < nA) {
+    const AEntry x = a_entry(a, s, stage, tid, nA0, f, l, q, mc, mcc);
+    a_tgt = x.tgt;
+    if (a_tgt >= 0) a_val = *x.src;
   }
   const int npt = np + npr;
   constexpr int kU = 4;  // terms per thread in flight
@@ -1715,6 +1741,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
         }
       }
     }
+    if (i0 == 0 && a_tgt >= 0) fbuf[a_tgt] = a_val;
     __syncthreads();
     // (4) in predecessor order (a predecessor's terms hit distinct entries)
     for (int t = 0; t < npt; ++t) {
@@ -1725,6 +1752,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       __syncthreads();
     }
   }
+  if (nterms == 0 && a_tgt >= 0) fbuf[a_tgt] = a_val;
   __syncthreads();
   if (tid == 0) {
     const unsigned long long now = wall_clock64();
@@ -1866,8 +1894,8 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       flops += 2.0 * nr * nc * m.p;
       ubytes += (double)a.elem_bytes * m.p * (nr + nc);
     }
-    atomicAdd(a.flops, (unsigned long long)flops);
-    atomicAdd(a.upd_bytes, (unsigned long long)ubytes);
+    s.acc_flops += (unsigned long long)flops;
+    s.acc_bytes += (unsigned long long)ubytes;
   }
   __syncthreads();
   if (tid == 0) trace_at(d, K, 13, wall_clock64());
@@ -1999,7 +2027,11 @@ __global__ void __launch_bounds__(kThreads, 2) factor_worker_kernel(FactorArgs a
   __shared__ Lds s;
   extern __shared__ double s_dyn[];
   const int slot = blockIdx.x;
-  if (threadIdx.x == 0) s.hcur[0] = s.hcur[1] = s.hend[0] = s.hend[1] = 0;
+  if (threadIdx.x == 0) {
+    s.hcur[0] = s.hcur[1] = s.hend[0] = s.hend[1] = 0;
+    s.acc_flops = s.acc_bytes = 0;
+    s.acc_depth = 0;
+  }
   __syncthreads();
   int next = -1;  // this worker's next block when already known
   for (int pos = blockIdx.x; pos < a.nb; pos += gridDim.x) {
@@ -2038,6 +2070,11 @@ __global__ void __launch_bounds__(kThreads, 2) factor_worker_kernel(FactorArgs a
     __syncthreads();
     next = s.misc[25];
     __syncthreads();  // s.misc[25] is reset by the next round
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(a.flops, s.acc_flops);
+    atomicAdd(a.upd_bytes, s.acc_bytes);
+    atomicMax(d.max_depth, s.acc_depth);
   }
 }
 
