@@ -366,9 +366,9 @@ __global__ void __launch_bounds__(256) backward_level(SweepArgs a, const double*
 // both halves 0x7ff4b11e: a signalling NaN, set with a 32-bit fill
 constexpr unsigned kPendingHalf = 0x7ff4b11eu;
 constexpr unsigned long long kPending = ((unsigned long long)kPendingHalf << 32) | kPendingHalf;
-// LDS requested (unused) per workgroup so that at most four share a CU: every
+// LDS requested (unused) per workgroup so that at most six share a CU: every
 // workgroup is then resident, which the static slot order relies on
-constexpr size_t kFlowLds = 36 * 1024;
+constexpr size_t kFlowLds = 22 * 1024;
 
 struct FlowApplyArgs {
   FactorView f;
@@ -388,10 +388,16 @@ struct FlowApplyArgs {
 // Values of t (side 0) or z (side 1) at idx for the lanes with has set, once
 // every one of them is published; the whole wave waits together (no lane
 // spins on its own).  On a timeout the first one records where it waited.
-__device__ __forceinline__ double await_values(const FlowApplyArgs& a, int side, bool has, int64_t idx,
-                                               unsigned long long t0, bool& bad, int slot) {
+__device__ __forceinline__ unsigned long long peek_value(const FlowApplyArgs& a, int side, bool has,
+                                                         int64_t idx) {
+  return has ? __hip_atomic_load((side ? a.z : a.t) + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+             : 0ull;
+}
+// As await_values, from a value v read before (peek_value).
+__device__ __forceinline__ double await_from(const FlowApplyArgs& a, int side, bool has, int64_t idx,
+                                             unsigned long long v, unsigned long long t0, bool& bad,
+                                             int slot) {
   unsigned long long* p = (side ? a.z : a.t) + (has ? idx : 0);
-  unsigned long long v = has ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
   while (!__all(!has || v != kPending)) {
     if (__any(bad)) {
       bad = true;
@@ -415,6 +421,10 @@ __device__ __forceinline__ double await_values(const FlowApplyArgs& a, int side,
   }
   return __longlong_as_double((long long)v);
 }
+__device__ __forceinline__ double await_values(const FlowApplyArgs& a, int side, bool has, int64_t idx,
+                                               unsigned long long t0, bool& bad, int slot) {
+  return await_from(a, side, has, idx, peek_value(a, side, has, idx), t0, bad, slot);
+}
 __device__ __forceinline__ void publish_value(unsigned long long* p, double v) {
   __hip_atomic_store(p, (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
@@ -430,12 +440,20 @@ __global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs a) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int wave = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
   const int nw = (int)((gridDim.x * (unsigned)blockDim.x) >> 6);
+  // a slot's header (forward: first row and width; backward: the block) is
+  // read one slot ahead
+  auto header = [&](int s) -> int2 {
+    if (s >= 2 * a.nb) return make_int2(0, 0);
+    return s < a.nb ? a.fq[s] : make_int2(a.lev_b[s - a.nb], 0);
+  };
+  int2 hdr = header(wave);
   for (int s = wave; s < 2 * a.nb; s += nw) {
     const unsigned long long t0 = wall_clock64();
+    const int2 cur = hdr;
+    hdr = header(s + nw);
     bool bad = false;
     if (s < a.nb) {
-      const int2 fq = a.fq[s];
-      const int f = fq.x, q = fq.y;
+      const int f = cur.x, q = cur.y;
       int qp = 1;
       while (qp < q && qp < 64) qp <<= 1;
       const int g = 64 / qp;  // lanes per row
@@ -447,6 +465,7 @@ __global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs a) {
           e = a.lr_ptr[f + r + 1];
         }
         const int steps = wave_max_int(b < e ? (int)((e - b + g - 1) / g) : 0);
+        const double xv = r < q && sub == 0 ? a.x[f + r] : 0.0;
         double acc = 0.0;
         for (int i = 0; i < steps; ++i) {
           const int64_t k = b + (int64_t)i * g;
@@ -456,10 +475,10 @@ __global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs a) {
           if (has) acc = fma(a.lr_val[k], tv, acc);
         }
         for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        if (r < q && sub == 0) publish_value(&a.t[f + r], a.x[f + r] - acc);
+        if (r < q && sub == 0) publish_value(&a.t[f + r], xv - acc);
       }
     } else {
-      const int K = a.lev_b[s - a.nb];
+      const int K = cur.x;
       const int f = a.f.bstart[K], q = a.f.bstart[K + 1] - f;
       const int m = a.f.nc[K];
       const int32_t* Cc = a.f.idx + a.f.coff[K];
@@ -470,6 +489,8 @@ __global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs a) {
       const int steps = (m + g - 1) / g;
       for (int r0 = 0; r0 < q; r0 += qp) {
         const int r = r0 + (lane & (qp - 1)), jj = lane / qp;
+        const bool own = jj == 0 && r < q;
+        const unsigned long long tv0 = peek_value(a, 0, own, f + r);  // usually there
         double acc = 0.0;
         for (int i = 0; i < steps; ++i) {
           const int j = jj + i * g;
@@ -479,8 +500,7 @@ __global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs a) {
           if (has) acc = fma(W[(int64_t)j * q + r], zv, acc);
         }
         for (int o = 32; o >= qp; o >>= 1) acc += __shfl_xor(acc, o, 64);
-        const bool own = jj == 0 && r < q;
-        const double tv = await_values(a, 0, own, f + r, t0, bad, s);
+        const double tv = await_from(a, 0, own, f + r, tv0, t0, bad, s);
         if (own) sv[wv][r] = tv - acc;
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
