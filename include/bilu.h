@@ -206,6 +206,19 @@ bilu_status bilu_preprocess(const bilu_options* opt, int64_t n, const int64_t* r
                             int64_t* perm, int64_t* group_starts, int64_t* ngroups,
                             int64_t* block_starts, int64_t* nblocks);
 
+/* Sec. 3.1, eq. (mwm): maximum weight matching (a maximum product
+ * transversal) of the n x n CSR matrix A and the diagonal scalings with
+ * which D_l A D_r Pi has |entries| <= 1 and unit diagonal magnitudes.
+ * Host-only (no handle, no GPU).  rowptr [n+1], colind [nnz] (0-based,
+ * any order within a row), val [nnz]; caller-allocated outputs: sigma [n]
+ * (the column matched to row i, i.e. Pi[sigma(i), i] = 1, so column i of
+ * A Pi is column sigma(i) of A), dl [n] and dr [n] (the diagonals of D_l,
+ * D_r).  Entries equal to zero do not count.  BILU_ERR_SINGULAR when A has
+ * no perfect matching on its nonzero entries (or an empty row or column),
+ * BILU_ERR_INVALID on bad arguments. */
+bilu_status bilu_mwm(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* val,
+                     int64_t* sigma, double* dl, double* dr);
+
 /* Statistics of the last analyze/factor (block sizes as in the paper's
  * tables of Sec. 3.2-3.5: number, max, average, standard deviation). */
 bilu_status bilu_get_stats(const bilu_handle* h, bilu_stats* st);

@@ -79,7 +79,7 @@ EXPORTED = [
     "bilu_default_options", "bilu_create", "bilu_analyze", "bilu_factor", "bilu_apply",
     "bilu_spmv", "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors",
     "bilu_free_factors", "bilu_destroy", "bilu_status_string", "bilu_last_error",
-    "bilu_preprocess", "bilu_sync", "bilu_export_trace", "bilu_factor_batched",
+    "bilu_preprocess", "bilu_sync", "bilu_export_trace", "bilu_factor_batched", "bilu_mwm",
 ]
 
 _lib = None
@@ -116,6 +116,7 @@ def load(path: str = LIB_PATH):
     lib.bilu_export_trace.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64),
                                       C.POINTER(C.c_double)]
     lib.bilu_export_trace.restype = C.c_int
+    lib.bilu_mwm.argtypes = [C.c_int64, vp, vp, vp, vp, vp, vp]
     lib.bilu_preprocess.argtypes = [C.POINTER(Options), C.c_int64, vp, vp, vp, C.c_double,
                                     vp, vp, C.POINTER(C.c_int64), vp, C.POINTER(C.c_int64)]
     for f in ("bilu_create", "bilu_analyze", "bilu_factor", "bilu_factor_batched", "bilu_apply",
@@ -196,6 +197,23 @@ def preprocess(a, tau: float, pre_perm=None, **kw):
     if st != BILU_OK:
         raise BiluError(st, "bilu_preprocess")
     return perm, gs[:ng.value + 1].copy(), bs[:nb.value + 1].copy()
+
+
+def mwm(a):
+    """Sec. 3.1 maximum weight matching on the host: (sigma, dl, dr) with
+    D_l A D_r Pi of unit diagonal magnitudes, Pi[sigma(i), i] = 1."""
+    lib = load()
+    rp = np.ascontiguousarray(a.rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(a.colind, dtype=np.int32)
+    v = np.ascontiguousarray(a.val, dtype=np.float64)
+    sigma = np.empty(a.n, dtype=np.int64)
+    dl = np.empty(a.n)
+    dr = np.empty(a.n)
+    st = lib.bilu_mwm(C.c_int64(a.n), rp.ctypes.data, ci.ctypes.data, v.ctypes.data,
+                      sigma.ctypes.data, dl.ctypes.data, dr.ctypes.data)
+    if st != BILU_OK:
+        raise BiluError(st, "bilu_mwm")
+    return sigma, dl, dr
 
 
 class Bilu:

@@ -335,6 +335,23 @@ bilu_status bilu_fgmres_solve(bilu_handle* h, const double* b, double* x, int re
   GUARD_END
 }
 
+bilu_status bilu_mwm(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* val,
+                     int64_t* sigma, double* dl, double* dr) {
+  if (n < 0) return BILU_ERR_INVALID;
+  if (n == 0) return BILU_OK;
+  if (!rowptr || !colind || !val || !sigma || !dl || !dr || rowptr[0] != 0) return BILU_ERR_INVALID;
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return BILU_ERR_INVALID;
+  try {
+    std::string why;
+    return bilu::mwm_host(n, rowptr, colind, val, sigma, dl, dr, &why);
+  } catch (const std::bad_alloc&) {
+    return BILU_ERR_NO_MEMORY;
+  } catch (...) {
+    return BILU_ERR_INTERNAL;
+  }
+}
+
 bilu_status bilu_preprocess(const bilu_options* opt, int64_t n, const int64_t* rowptr,
                             const int32_t* colind, const double* val, double tau, int64_t* perm,
                             int64_t* group_starts, int64_t* ngroups, int64_t* block_starts,

@@ -332,6 +332,10 @@ bilu_status aggregate_device(bilu_handle* h);
 
 // solve.hip
 bilu_status build_apply_plan(bilu_handle* h);
+// Sec. 3.1 maximum weight matching on the host (mwm.cpp); *why explains a
+// failure.
+bilu_status mwm_host(int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
+                     int64_t* sigma, double* dl, double* dr, std::string* why);
 bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t);
 bilu_status spmv_permuted(bilu_handle* h, const double* x, double* y);
 void launch_gather(hipStream_t s, int64_t n, const int32_t* perm, const double* x, double* y);
