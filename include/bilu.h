@@ -80,6 +80,9 @@ typedef struct {
                          /* every workgroup resident) the handle switches to 1 for  */
                          /* good.  1: one launch per dependency level.  Both        */
                          /* compute identical bits                                   */
+  int use_mwm;           /* 1: Sec. 3.1 first: the handle factors D_l A D_r Pi     */
+                         /* (bilu_mwm) instead of A; apply, spmv and fgmres still   */
+                         /* act on A in its own numbering (default 0)               */
 } bilu_options;
 
 typedef struct bilu_handle bilu_handle;

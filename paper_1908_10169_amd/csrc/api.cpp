@@ -1,4 +1,5 @@
 // C ABI of the BILU library (declared in include/bilu.h).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -190,7 +191,7 @@ bilu_status bilu_create(bilu_handle** out, const bilu_options* opt, void* stream
       h->opt.cos_eps > 1.0 || h->opt.ordering < 0 || h->opt.ordering > 1 ||
       h->opt.update_precision < 0 || h->opt.update_precision > 2 || h->opt.drop_norm < 0 ||
       h->opt.drop_norm > 1 || h->opt.factor_path < 0 || h->opt.factor_path > 2 ||
-      h->opt.apply_path < 0 || h->opt.apply_path > 1) {
+      h->opt.apply_path < 0 || h->opt.apply_path > 1 || h->opt.use_mwm < 0 || h->opt.use_mwm > 1) {
     delete h;
     return BILU_ERR_INVALID;
   }
@@ -212,6 +213,49 @@ bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr, const
   auto t0 = std::chrono::steady_clock::now();
   h->state = 0;
   h->ilu_static = false;
+  h->mwm = false;
+  // Sec. 3.1 (use_mwm): analyze D_l A D_r Pi instead of A
+  std::vector<int64_t> sigma;
+  std::vector<double> dl, dr;
+  std::vector<int64_t> m_rp;
+  std::vector<int32_t> m_ci;
+  std::vector<double> m_v;
+  if (h->opt.use_mwm) {
+    if (n <= 0 || !rowptr || !colind || !val || rowptr[0] != 0)
+      return fail(h, BILU_ERR_INVALID, "null CSR or n<=0");
+    for (int64_t i = 0; i < n; ++i)
+      if (rowptr[i + 1] < rowptr[i]) return fail(h, BILU_ERR_INVALID, "rowptr not monotone");
+    sigma.resize(n);
+    dl.resize(n);
+    dr.resize(n);
+    std::string why;
+    const bilu_status ms = mwm_host(n, rowptr, colind, val, sigma.data(), dl.data(), dr.data(), &why);
+    if (ms != BILU_OK) return fail(h, ms, "maximum weight matching: " + why);
+    // column j of A becomes column sigma^{-1}(j); rows keep their order and
+    // are re-sorted by the new column index
+    std::vector<int32_t> pos(n);
+    for (int64_t k = 0; k < n; ++k) pos[sigma[k]] = (int32_t)k;
+    m_rp.assign(rowptr, rowptr + n + 1);
+    m_ci.resize(rowptr[n]);
+    m_v.resize(rowptr[n]);
+    std::vector<std::pair<int32_t, double>> row;
+    for (int64_t i = 0; i < n; ++i) {
+      row.clear();
+      for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k)
+        row.push_back({pos[colind[k]], (dl[i] * val[k]) * dr[colind[k]]});
+      std::sort(row.begin(), row.end(),
+                [](const std::pair<int32_t, double>& x, const std::pair<int32_t, double>& y) {
+                  return x.first < y.first;
+                });
+      for (size_t t = 0; t < row.size(); ++t) {
+        m_ci[rowptr[i] + t] = row[t].first;
+        m_v[rowptr[i] + t] = row[t].second;
+      }
+    }
+    rowptr = m_rp.data();
+    colind = m_ci.data();
+    val = m_v.data();
+  }
   bilu_status s = analyze_host(h, n, rowptr, colind, val);
   if (s != BILU_OK) return s;
   const int64_t nnz = h->nnz;
@@ -236,6 +280,31 @@ bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr, const
   CK(hipMemcpyAsync(h->d_ri.p, h->pri.data(), nnz * 4, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(h->d_cv.p, h->pcv.data(), nnz * 8, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(h->d_perm.p, p32.data(), n * 4, hipMemcpyHostToDevice, st));
+  if (h->opt.use_mwm) {
+    // boundary of the scaled system: rows by perm with D_l, columns by
+    // sigma o perm with D_r
+    std::vector<int32_t> pc(n);
+    std::vector<double> sl(n), sli(n), sr(n), sri(n);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t p = h->perm[i], c = sigma[p];
+      pc[i] = (int32_t)c;
+      sl[i] = dl[p];
+      sli[i] = 1.0 / dl[p];
+      sr[i] = dr[c];
+      sri[i] = 1.0 / dr[c];
+    }
+    CK(h->d_perm_col.alloc(n));
+    CK(h->d_sl.alloc(n));
+    CK(h->d_sl_inv.alloc(n));
+    CK(h->d_sr.alloc(n));
+    CK(h->d_sr_inv.alloc(n));
+    CK(hipMemcpyAsync(h->d_perm_col.p, pc.data(), n * 4, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->d_sl.p, sl.data(), n * 8, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->d_sl_inv.p, sli.data(), n * 8, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->d_sr.p, sr.data(), n * 8, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->d_sr_inv.p, sri.data(), n * 8, hipMemcpyHostToDevice, st));
+    h->mwm = true;
+  }
   CK(hipStreamSynchronize(st));
 #undef CK
   h->stats = bilu_stats{};
@@ -296,10 +365,11 @@ bilu_status bilu_apply(bilu_handle* h, const double* x, double* y) {
   double* xp = h->w_vec.p;
   double* yp = xp + n;
   double* tp = yp + n;
-  launch_gather(h->stream, n, h->d_perm.p, x, xp);
+  // x lives in A's row space, y in its column space
+  launch_gather(h->stream, n, h->d_perm.p, h->sl(), x, xp);
   bilu_status s = apply_permuted(h, xp, yp, tp);
   if (s != BILU_OK) return s;
-  launch_scatter(h->stream, n, h->d_perm.p, yp, y);
+  launch_scatter(h->stream, n, h->perm_col(), h->sr(), yp, y);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_check(h, e, "bilu_apply");
   return BILU_OK;
@@ -317,9 +387,10 @@ bilu_status bilu_spmv(bilu_handle* h, const double* x, double* y) {
   }
   double* xp = h->w_vec.p;
   double* yp = xp + n;
-  launch_gather(h->stream, n, h->d_perm.p, x, xp);
+  // x lives in A's column space, y in its row space
+  launch_gather(h->stream, n, h->perm_col(), h->sr_inv(), x, xp);
   spmv_permuted(h, xp, yp);
-  launch_scatter(h->stream, n, h->d_perm.p, yp, y);
+  launch_scatter(h->stream, n, h->d_perm.p, h->sl_inv(), yp, y);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_check(h, e, "bilu_spmv");
   return BILU_OK;

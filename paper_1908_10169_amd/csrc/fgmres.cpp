@@ -38,18 +38,32 @@ bilu_status fgmres(bilu_handle* h, const double* b_orig, double* x_orig, int m, 
   DevArray<double> hcol;             // device column of H: m+3 scalars
   if (hcol.alloc(m + 3) != hipSuccess) return fail(h, BILU_ERR_NO_MEMORY, "solver workspace");
 
-  launch_gather(st, n, h->d_perm.p, b_orig, b);
-  launch_gather(st, n, h->d_perm.p, x_orig, x);
+  // b in A's row space, x in its column space (with use_mwm the iteration
+  // runs on the scaled system; the stopping test uses A's own residual)
+  launch_gather(st, n, h->d_perm.p, h->sl(), b_orig, b);
+  launch_gather(st, n, h->perm_col(), h->sr_inv(), x_orig, x);
   auto norm = [&](const double* v, double* slot) {
     launch_dot(st, n, v, v, red, slot);
   };
+  // 2-norm of the residual of A x = b behind the permuted one (tmp is free
+  // outside the applies)
+  auto true_norm = [&](const double* v, double* slot) {
+    if (h->sl_inv()) {
+      launch_mul(st, n, h->sl_inv(), v, tmp);
+      norm(tmp, slot);
+    } else {
+      norm(v, slot);
+    }
+  };
   double hbuf[2];
   norm(b, hcol.p);
-  if (hipMemcpyAsync(hbuf, hcol.p, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+  true_norm(b, hcol.p + 1);
+  if (hipMemcpyAsync(hbuf, hcol.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return fail(h, BILU_ERR_DEVICE, "solver: device error");
-  const double bnorm = std::sqrt(hbuf[0]);
+  const double bnorm = std::sqrt(hbuf[1]);
   const double target = rtol * bnorm;
+  const double target_inner = rtol * std::sqrt(hbuf[0]);  // same as target without use_mwm
 
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), col(m + 3);
   int64_t it = 0, cycles = 0;
@@ -59,12 +73,13 @@ bilu_status fgmres(bilu_handle* h, const double* b_orig, double* x_orig, int m, 
     spmv_permuted(h, x, r);
     launch_sub(st, n, b, r, r);
     norm(r, hcol.p);
-    if (hipMemcpyAsync(hbuf, hcol.p, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+    true_norm(r, hcol.p + 1);
+    if (hipMemcpyAsync(hbuf, hcol.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       return fail(h, BILU_ERR_DEVICE, "solver: device error");
     const double beta = std::sqrt(hbuf[0]);
-    resid = beta;
-    if (beta <= target) {
+    resid = std::sqrt(hbuf[1]);
+    if (resid <= target) {
       converged = 1;
       break;
     }
@@ -119,7 +134,7 @@ bilu_status fgmres(bilu_handle* h, const double* b_orig, double* x_orig, int m, 
       const bool breakdown = hn <= 1e-14 * wn0;
       if (!breakdown) launch_scale(st, n, 1.0 / hn, w, V(j + 1));
       jend = j + 1;
-      if (est <= target || breakdown || it >= maxit) break;
+      if (est <= target_inner || breakdown || it >= maxit) break;
     }
     for (int i = jend - 1; i >= 0; --i) {
       double acc = g[i];
@@ -128,7 +143,7 @@ bilu_status fgmres(bilu_handle* h, const double* b_orig, double* x_orig, int m, 
     }
     for (int i = 0; i < jend; ++i) launch_axpy_host(st, n, y[i], Z(i), x);
   }
-  launch_scatter(st, n, h->d_perm.p, x, x_orig);
+  launch_scatter(st, n, h->perm_col(), h->sr(), x, x_orig);
   if (hipStreamSynchronize(st) != hipSuccess) return fail(h, BILU_ERR_DEVICE, "solver: device error");
   if (info) {
     info->iterations = it;

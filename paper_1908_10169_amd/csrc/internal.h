@@ -257,6 +257,17 @@ struct bilu_handle {
   bilu::DevArray<double> f_val, f_dval;
   bool final_is_initial = true;      // no merge happened: f_* alias the factor storage
   bool ilu_static = false;
+  // Sec. 3.1 (use_mwm): the factored matrix is D_l A D_r Pi.  Vectors cross
+  // the boundary by row (perm, sl / sl_inv) or by column (perm_col = sigma o
+  // perm, sr / sr_inv); without it perm_col = perm and no scaling.
+  bool mwm = false;
+  bilu::DevArray<int32_t> d_perm_col;
+  bilu::DevArray<double> d_sl, d_sl_inv, d_sr, d_sr_inv;
+  const int32_t* perm_col() const { return mwm ? d_perm_col.p : d_perm.p; }
+  const double* sl() const { return mwm ? d_sl.p : nullptr; }
+  const double* sl_inv() const { return mwm ? d_sl_inv.p : nullptr; }
+  const double* sr() const { return mwm ? d_sr.p : nullptr; }
+  const double* sr_inv() const { return mwm ? d_sr_inv.p : nullptr; }
   bilu::PinnedBuf pin_dec, pin_up;     // aggregation: decisions down, group data up
   std::vector<int32_t> agg_gfirst, agg_fbs;
   std::vector<int64_t> agg_off;        // final offsets (copying path) and D offsets           // unit starts and diagonal of the analyzed matrix on the device
@@ -338,8 +349,13 @@ bilu_status mwm_host(int64_t n, const int64_t* rp, const int32_t* ci, const doub
                      int64_t* sigma, double* dl, double* dr, std::string* why);
 bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t);
 bilu_status spmv_permuted(bilu_handle* h, const double* x, double* y);
-void launch_gather(hipStream_t s, int64_t n, const int32_t* perm, const double* x, double* y);
-void launch_scatter(hipStream_t s, int64_t n, const int32_t* perm, const double* x, double* y);
+// y[i] = x[perm[i]] (times scale[i] when given); scatter: y[perm[i]] = x[i]
+// (times scale[i])
+void launch_gather(hipStream_t s, int64_t n, const int32_t* perm, const double* scale, const double* x,
+                   double* y);
+void launch_scatter(hipStream_t s, int64_t n, const int32_t* perm, const double* scale,
+                    const double* x, double* y);
+void launch_mul(hipStream_t s, int64_t n, const double* w, const double* x, double* y);  // y = w .* x
 void launch_axpy(hipStream_t s, int64_t n, const double* alpha_dev, double sign, const double* x,
                  double* y);
 void launch_axpy_host(hipStream_t s, int64_t n, double alpha, const double* x, double* y);

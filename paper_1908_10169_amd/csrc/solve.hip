@@ -532,13 +532,15 @@ __global__ void __launch_bounds__(256) spmv_csr(int64_t n, const int64_t* rp, co
   if (row < n && sub == 0) y[row] = acc;
 }
 
-__global__ void gather_k(int64_t n, const int32_t* perm, const double* x, double* y) {
+__global__ void gather_k(int64_t n, const int32_t* perm, const double* scale, const double* x,
+                         double* y) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = x[perm[i]];
+    y[i] = (perm ? x[perm[i]] : x[i]) * (scale ? scale[i] : 1.0);
 }
-__global__ void scatter_k(int64_t n, const int32_t* perm, const double* x, double* y) {
+__global__ void scatter_k(int64_t n, const int32_t* perm, const double* scale, const double* x,
+                          double* y) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[perm[i]] = x[i];
+    y[perm[i]] = scale ? x[i] * scale[i] : x[i];
 }
 __global__ void axpy_dev_k(int64_t n, const double* alpha, double sign, const double* x, double* y) {
   const double a = sign * *alpha;
@@ -589,11 +591,16 @@ inline unsigned grid_for(int64_t n) {
 
 }  // namespace
 
-void launch_gather(hipStream_t s, int64_t n, const int32_t* perm, const double* x, double* y) {
-  gather_k<<<grid_for(n), 256, 0, s>>>(n, perm, x, y);
+void launch_gather(hipStream_t s, int64_t n, const int32_t* perm, const double* scale, const double* x,
+                   double* y) {
+  gather_k<<<grid_for(n), 256, 0, s>>>(n, perm, scale, x, y);
 }
-void launch_scatter(hipStream_t s, int64_t n, const int32_t* perm, const double* x, double* y) {
-  scatter_k<<<grid_for(n), 256, 0, s>>>(n, perm, x, y);
+void launch_scatter(hipStream_t s, int64_t n, const int32_t* perm, const double* scale,
+                    const double* x, double* y) {
+  scatter_k<<<grid_for(n), 256, 0, s>>>(n, perm, scale, x, y);
+}
+void launch_mul(hipStream_t s, int64_t n, const double* w, const double* x, double* y) {
+  gather_k<<<grid_for(n), 256, 0, s>>>(n, nullptr, w, x, y);
 }
 void launch_axpy(hipStream_t s, int64_t n, const double* alpha_dev, double sign, const double* x,
                  double* y) {
