@@ -83,6 +83,12 @@ typedef struct {
   int use_mwm;           /* 1: Sec. 3.1 first: the handle factors D_l A D_r Pi     */
                          /* (bilu_mwm) instead of A; apply, spmv and fgmres still   */
                          /* act on A in its own numbering (default 0)               */
+  int analyze_path;      /* 0 (default): bilu_analyze checks the entries, searches  */
+                         /* the cosine candidates and builds P A P^T on the device  */
+                         /* (the host keeps the limits, the greedy replay and the   */
+                         /* ordering); 1: all on the host.  Both give the same      */
+                         /* permutation, groups and matrix bit for bit.  nnz >= 2^31 */
+                         /* takes the host path                                      */
 } bilu_options;
 
 typedef struct bilu_handle bilu_handle;
@@ -152,6 +158,17 @@ bilu_status bilu_create(bilu_handle** h, const bilu_options* opt, void* hip_stre
  * non-finite value, bad pre_perm), BILU_ERR_NO_MEMORY. */
 bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr,
                          const int32_t* colind, const double* val);
+
+/* bilu_analyze for a matrix already in device memory (Sec. 3.2-3.3, as
+ * bilu_analyze): rowptr (n+1), colind and val (rowptr[n] entries each) are
+ * device arrays owned by the caller, read during the call only.  rowptr is
+ * copied to the host and checked there before any entry is read; the entries
+ * are checked on the device.  With use_mwm = 1, analyze_path = 1 or
+ * nnz >= 2^31 the matrix is copied to the host and analyzed as by
+ * bilu_analyze.  The handle ends as bilu_analyze would leave it, bit for bit.
+ * Same errors as bilu_analyze, plus BILU_ERR_DEVICE.  Synchronous. */
+bilu_status bilu_analyze_device(bilu_handle* h, int64_t n, const int64_t* rowptr,
+                                const int32_t* colind, const double* val);
 
 /* Sec. 3.4-3.6 and Sec. 2.2: guess the initial blocks with ILU(1,tau), run
  * the block Crout sweep on the GPU with drop tolerance tau >= 0 (tau = 0

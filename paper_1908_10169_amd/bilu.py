@@ -37,7 +37,7 @@ class Options(C.Structure):
         ("perturb_rho", C.c_double), ("pivot_eps", C.c_double), ("beta_one", C.c_int),
         ("update_precision", C.c_int), ("heap_bytes", C.c_size_t),
         ("collect_timing", C.c_int), ("factor_path", C.c_int), ("apply_path", C.c_int),
-        ("use_mwm", C.c_int),
+        ("use_mwm", C.c_int), ("analyze_path", C.c_int),
     ]
 
 
@@ -81,6 +81,7 @@ EXPORTED = [
     "bilu_spmv", "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors",
     "bilu_free_factors", "bilu_destroy", "bilu_status_string", "bilu_last_error",
     "bilu_preprocess", "bilu_sync", "bilu_export_trace", "bilu_factor_batched", "bilu_mwm",
+    "bilu_analyze_device",
 ]
 
 _lib = None
@@ -118,9 +119,10 @@ def load(path: str = LIB_PATH):
                                       C.POINTER(C.c_double)]
     lib.bilu_export_trace.restype = C.c_int
     lib.bilu_mwm.argtypes = [C.c_int64, vp, vp, vp, vp, vp, vp]
+    lib.bilu_analyze_device.argtypes = [vp, C.c_int64, vp, vp, vp]
     lib.bilu_preprocess.argtypes = [C.POINTER(Options), C.c_int64, vp, vp, vp, C.c_double,
                                     vp, vp, C.POINTER(C.c_int64), vp, C.POINTER(C.c_int64)]
-    for f in ("bilu_create", "bilu_analyze", "bilu_factor", "bilu_factor_batched", "bilu_apply",
+    for f in ("bilu_create", "bilu_analyze", "bilu_analyze_device", "bilu_factor", "bilu_factor_batched", "bilu_apply",
               "bilu_spmv",
               "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors", "bilu_preprocess",
               "bilu_sync"):
@@ -267,6 +269,24 @@ class Bilu:
         self.n = a.n
         return self._check(self._lib.bilu_analyze(self._h, a.n, rp.ctypes.data, ci.ctypes.data,
                                                   v.ctypes.data), "bilu_analyze")
+
+    def analyze_device(self, n, rowptr, colind, val, pre_perm=None):
+        """bilu_analyze_device: rowptr (int64, n+1), colind (int32) and val
+        (float64) are device tensors."""
+        if pre_perm is not None:
+            self._pre = np.ascontiguousarray(pre_perm, dtype=np.int64)
+            self._opts.pre_perm = self._pre.ctypes.data
+        else:
+            self._opts.pre_perm = None
+        self.close()
+        st = self._lib.bilu_create(C.byref(self._h), C.byref(self._opts),
+                                   C.c_void_p(_stream_ptr(None)))
+        if st != BILU_OK:
+            raise BiluError(st, "bilu_create")
+        self.n = n
+        return self._check(self._lib.bilu_analyze_device(self._h, n, rowptr.data_ptr(),
+                                                         colind.data_ptr(), val.data_ptr()),
+                           "bilu_analyze_device")
 
     def factor(self, tau: float):
         return self._check(self._lib.bilu_factor(self._h, tau), "bilu_factor",

@@ -15,6 +15,22 @@
 #include "internal.h"
 
 namespace bilu {
+
+// Sec. 3.2: rows (columns) with more than mu + 2 sigma entries stay out of
+// the cosine groups; mu is the mean entry count, sigma the standard
+// deviation of the row (column) counts, summed in index order.
+void cosine_limits(int64_t n, int64_t nnz, const int64_t* rc, const int64_t* cc, double* lim_r,
+                   double* lim_c) {
+  const double mean = double(nnz) / double(n);
+  double vr = 0.0, vc = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    vr += (rc[i] - mean) * (rc[i] - mean);
+    vc += (cc[i] - mean) * (cc[i] - mean);
+  }
+  *lim_r = mean + 2.0 * std::sqrt(vr / n);
+  *lim_c = mean + 2.0 * std::sqrt(vc / n);
+}
+
 namespace {
 
 // Run body(lo, hi) over [0, n) on the host's cores.
@@ -107,13 +123,8 @@ void cosine(const Csr& a, const Csr& at, double eps, int max_block, std::vector<
     rc[i] = a.rp[i + 1] - a.rp[i];
     cc[i] = at.rp[i + 1] - at.rp[i];
   }
-  const double mean = double(a.rp[n]) / double(n);
-  double vr = 0.0, vc = 0.0;
-  for (int64_t i = 0; i < n; ++i) {
-    vr += (rc[i] - mean) * (rc[i] - mean);
-    vc += (cc[i] - mean) * (cc[i] - mean);
-  }
-  const double lim_r = mean + 2.0 * std::sqrt(vr / n), lim_c = mean + 2.0 * std::sqrt(vc / n);
+  double lim_r, lim_c;
+  cosine_limits(n, a.rp[n], rc.data(), cc.data(), &lim_r, &lim_c);
   std::vector<char> skip(n);
   for (int64_t i = 0; i < n; ++i) skip[i] = rc[i] > lim_r || cc[i] > lim_c;
 
@@ -310,64 +321,14 @@ void nd_order(const Graph& g, std::vector<int32_t>& order) {
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-bilu_status analyze_host(bilu_handle* h, int64_t n, const int64_t* rowptr,
-                         const int32_t* colind, const double* val) {
-  if (n <= 0 || !rowptr || !colind || !val) return fail(h, BILU_ERR_INVALID, "null CSR or n<=0");
-  if (n > INT32_MAX - 1) return fail(h, BILU_ERR_INVALID, "n exceeds int32 range");
-  if (rowptr[0] != 0) return fail(h, BILU_ERR_INVALID, "rowptr[0] != 0");
-  for (int64_t i = 0; i < n; ++i)
-    if (rowptr[i + 1] < rowptr[i]) return fail(h, BILU_ERR_INVALID, "rowptr not monotone");
-  const int64_t nnz = rowptr[n];
-  std::atomic<int> bad{0};
-  parallel_for(n, [&](int64_t lo, int64_t hi) {
-    for (int64_t i = lo; i < hi && !bad.load(std::memory_order_relaxed); ++i)
-      for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-        if (colind[k] < 0 || colind[k] >= n) bad = 1;
-        else if (k > rowptr[i] && colind[k] <= colind[k - 1]) bad = 2;
-        else if (!std::isfinite(val[k])) bad = 3;
-      }
-  });
-  if (bad == 1) return fail(h, BILU_ERR_INVALID, "column index out of range");
-  if (bad == 2) return fail(h, BILU_ERR_INVALID, "column indices not strictly increasing");
-  if (bad == 3) return fail(h, BILU_ERR_INVALID, "non-finite value");
-
-  Csr a;
-  a.n = n;
-  a.rp.assign(rowptr, rowptr + n + 1);
-  a.ci.assign(colind, colind + nnz);
-  a.v.assign(val, val + nnz);
-  h->n = n;
-  h->nnz = nnz;
-  h->alpha = 0.0;
-  for (double x : a.v) h->alpha = std::max(h->alpha, std::fabs(x));
-
-  // optional caller pre-permutation
-  std::vector<int64_t> pre(n);
-  if (h->opt.pre_perm) {
-    std::vector<char> seen(n, 0);
-    for (int64_t i = 0; i < n; ++i) {
-      int64_t p = h->opt.pre_perm[i];
-      if (p < 0 || p >= n || seen[p]) return fail(h, BILU_ERR_INVALID, "pre_perm is not a permutation");
-      seen[p] = 1;
-      pre[i] = p;
-    }
-  } else {
-    std::iota(pre.begin(), pre.end(), 0);
-  }
-  Csr a1 = h->opt.pre_perm ? permute(a, pre) : a;
-
-  // cosine groups
-  std::vector<int64_t> q, gs;
-  if (h->opt.use_cosine) {
-    Csr a1t = transpose(a1);
-    cosine(a1, a1t, h->opt.cos_eps, h->opt.max_block, q, gs);
-  } else {
-    q.resize(n);
-    std::iota(q.begin(), q.end(), 0);
-    gs.resize(n + 1);
-    std::iota(gs.begin(), gs.end(), 0);
-  }
+// Sec. 3.3: order the groups (natural, or nested dissection of the
+// compressed graph, built from the rows rp1/ci1 of A(pre, pre); the column
+// order inside a row does not matter) and expand them: perm (new -> old)
+// lists the groups contiguously, members in their order.
+bilu_status order_and_expand(bilu_handle* h, const int64_t* rp1, const int32_t* ci1,
+                             const std::vector<int64_t>& pre, const std::vector<int64_t>& q,
+                             const std::vector<int64_t>& gs) {
+  const int64_t n = h->n;
   const int64_t ng = (int64_t)gs.size() - 1;
 
   // group order: natural, or nested dissection of the compressed graph
@@ -384,8 +345,8 @@ bilu_status analyze_host(bilu_handle* h, int64_t n, const int64_t* rowptr,
         auto& v = nb[g];
         for (int64_t k = gs[g]; k < gs[g + 1]; ++k) {
           int64_t r = q[k];
-          for (int64_t m = a1.rp[r]; m < a1.rp[r + 1]; ++m) {
-            int32_t h2 = gof[a1.ci[m]];
+          for (int64_t m = rp1[r]; m < rp1[r + 1]; ++m) {
+            int32_t h2 = gof[ci1[m]];
             if (h2 != g) v.push_back(h2);
           }
         }
@@ -422,6 +383,77 @@ bilu_status analyze_host(bilu_handle* h, int64_t n, const int64_t* rowptr,
     for (int64_t k = gs[g]; k < gs[g + 1]; ++k) h->perm[at++] = pre[q[k]];
     h->group_starts.push_back(at);
   }
+  return BILU_OK;
+}
+
+// The caller's pre-permutation (identity when absent); false when it is not
+// a permutation.
+bool pre_permutation(const bilu_handle* h, int64_t n, std::vector<int64_t>& pre) {
+  pre.resize(n);
+  if (!h->opt.pre_perm) {
+    std::iota(pre.begin(), pre.end(), 0);
+    return true;
+  }
+  std::vector<char> seen(n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t p = h->opt.pre_perm[i];
+    if (p < 0 || p >= n || seen[p]) return false;
+    seen[p] = 1;
+    pre[i] = p;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+bilu_status analyze_host(bilu_handle* h, int64_t n, const int64_t* rowptr,
+                         const int32_t* colind, const double* val) {
+  if (n <= 0 || !rowptr || !colind || !val) return fail(h, BILU_ERR_INVALID, "null CSR or n<=0");
+  if (n > INT32_MAX - 1) return fail(h, BILU_ERR_INVALID, "n exceeds int32 range");
+  if (rowptr[0] != 0) return fail(h, BILU_ERR_INVALID, "rowptr[0] != 0");
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return fail(h, BILU_ERR_INVALID, "rowptr not monotone");
+  const int64_t nnz = rowptr[n];
+  std::atomic<int> bad{0};
+  parallel_for(n, [&](int64_t lo, int64_t hi) {
+    for (int64_t i = lo; i < hi && !bad.load(std::memory_order_relaxed); ++i)
+      for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        if (colind[k] < 0 || colind[k] >= n) bad = 1;
+        else if (k > rowptr[i] && colind[k] <= colind[k - 1]) bad = 2;
+        else if (!std::isfinite(val[k])) bad = 3;
+      }
+  });
+  if (bad == 1) return fail(h, BILU_ERR_INVALID, "column index out of range");
+  if (bad == 2) return fail(h, BILU_ERR_INVALID, "column indices not strictly increasing");
+  if (bad == 3) return fail(h, BILU_ERR_INVALID, "non-finite value");
+
+  Csr a;
+  a.n = n;
+  a.rp.assign(rowptr, rowptr + n + 1);
+  a.ci.assign(colind, colind + nnz);
+  a.v.assign(val, val + nnz);
+  h->n = n;
+  h->nnz = nnz;
+  h->alpha = 0.0;
+  for (double x : a.v) h->alpha = std::max(h->alpha, std::fabs(x));
+
+  // optional caller pre-permutation
+  std::vector<int64_t> pre;
+  if (!pre_permutation(h, n, pre)) return fail(h, BILU_ERR_INVALID, "pre_perm is not a permutation");
+  Csr a1 = h->opt.pre_perm ? permute(a, pre) : a;
+
+  // cosine groups
+  std::vector<int64_t> q, gs;
+  if (h->opt.use_cosine) {
+    Csr a1t = transpose(a1);
+    cosine(a1, a1t, h->opt.cos_eps, h->opt.max_block, q, gs);
+  } else {
+    q.resize(n);
+    std::iota(q.begin(), q.end(), 0);
+    gs.resize(n + 1);
+    std::iota(gs.begin(), gs.end(), 0);
+  }
+  const bilu_status os = order_and_expand(h, a1.rp.data(), a1.ci.data(), pre, q, gs);
+  if (os != BILU_OK) return os;
   Csr p = permute(a, h->perm);
   Csr pt = transpose(p);
   h->prp = std::move(p.rp);

@@ -153,6 +153,25 @@ bilu_status finish_factor(bilu_handle* h, std::chrono::steady_clock::time_point 
 
 }  // namespace bilu
 
+namespace {
+
+bool rowptr_monotone(int64_t n, const int64_t* rp) {
+  for (int64_t i = 0; i < n; ++i)
+    if (rp[i + 1] < rp[i]) return false;
+  return true;
+}
+
+void analyze_done(bilu_handle* h, std::chrono::steady_clock::time_point t0) {
+  h->stats = bilu_stats{};
+  h->stats.n = h->n;
+  h->stats.nnz_a = h->nnz;
+  h->stats.ngroups = (int64_t)h->group_starts.size() - 1;
+  h->stats.t_analyze = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  h->state = 1;
+}
+
+}  // namespace
+
 extern "C" {
 
 void bilu_default_options(bilu_options* o) {
@@ -191,7 +210,8 @@ bilu_status bilu_create(bilu_handle** out, const bilu_options* opt, void* stream
       h->opt.cos_eps > 1.0 || h->opt.ordering < 0 || h->opt.ordering > 1 ||
       h->opt.update_precision < 0 || h->opt.update_precision > 2 || h->opt.drop_norm < 0 ||
       h->opt.drop_norm > 1 || h->opt.factor_path < 0 || h->opt.factor_path > 2 ||
-      h->opt.apply_path < 0 || h->opt.apply_path > 1 || h->opt.use_mwm < 0 || h->opt.use_mwm > 1) {
+      h->opt.apply_path < 0 || h->opt.apply_path > 1 || h->opt.use_mwm < 0 || h->opt.use_mwm > 1 ||
+      h->opt.analyze_path < 0 || h->opt.analyze_path > 1) {
     delete h;
     return BILU_ERR_INVALID;
   }
@@ -256,30 +276,48 @@ bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr, const
     colind = m_ci.data();
     val = m_v.data();
   }
-  bilu_status s = analyze_host(h, n, rowptr, colind, val);
-  if (s != BILU_OK) return s;
-  const int64_t nnz = h->nnz;
   hipStream_t st = h->stream;
 #define CK(x)                                          \
   do {                                                 \
     hipError_t e_ = (x);                               \
     if (e_ != hipSuccess) return hip_check(h, e_, #x); \
   } while (0)
-  CK(h->d_rp.alloc(n + 1));
-  CK(h->d_ci.alloc(nnz));
-  CK(h->d_rv.alloc(nnz));
-  CK(h->d_cp.alloc(n + 1));
-  CK(h->d_ri.alloc(nnz));
-  CK(h->d_cv.alloc(nnz));
-  CK(h->d_perm.alloc(n));
-  std::vector<int32_t> p32(h->perm.begin(), h->perm.end());
-  CK(hipMemcpyAsync(h->d_rp.p, h->prp.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(h->d_ci.p, h->pci.data(), nnz * 4, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(h->d_rv.p, h->pv.data(), nnz * 8, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(h->d_cp.p, h->pcp.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(h->d_ri.p, h->pri.data(), nnz * 4, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(h->d_cv.p, h->pcv.data(), nnz * 8, hipMemcpyHostToDevice, st));
-  CK(hipMemcpyAsync(h->d_perm.p, p32.data(), n * 4, hipMemcpyHostToDevice, st));
+  if (h->opt.analyze_path == 0 && n > 0 && n <= INT32_MAX - 1 && rowptr && colind && val &&
+      rowptr[0] == 0 && rowptr_monotone(n, rowptr) && rowptr[n] <= INT32_MAX) {
+    // the matrix goes to HBM as it is; checks, cosine search and P A P^T there
+    const int64_t nnz = rowptr[n];
+    DevArray<int64_t> a_rp;
+    DevArray<int32_t> a_ci;
+    DevArray<double> a_v;
+    CK(a_rp.alloc(n + 1));
+    CK(a_ci.alloc(std::max<int64_t>(1, nnz)));
+    CK(a_v.alloc(std::max<int64_t>(1, nnz)));
+    CK(hipMemcpyAsync(a_rp.p, rowptr, (n + 1) * 8, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(a_ci.p, colind, nnz * 4, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(a_v.p, val, nnz * 8, hipMemcpyHostToDevice, st));
+    bilu_status s = analyze_device(h, n, a_rp.p, a_ci.p, a_v.p, rowptr);
+    if (s != BILU_OK) return s;
+  } else {
+    bilu_status s = analyze_host(h, n, rowptr, colind, val);
+    if (s != BILU_OK) return s;
+    const int64_t nnz = h->nnz;
+    CK(h->d_rp.alloc(n + 1));
+    CK(h->d_ci.alloc(nnz));
+    CK(h->d_rv.alloc(nnz));
+    CK(h->d_cp.alloc(n + 1));
+    CK(h->d_ri.alloc(nnz));
+    CK(h->d_cv.alloc(nnz));
+    CK(h->d_perm.alloc(n));
+    std::vector<int32_t> p32(h->perm.begin(), h->perm.end());
+    CK(hipMemcpyAsync(h->d_rp.p, h->prp.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->d_ci.p, h->pci.data(), nnz * 4, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->d_rv.p, h->pv.data(), nnz * 8, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->d_cp.p, h->pcp.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->d_ri.p, h->pri.data(), nnz * 4, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->d_cv.p, h->pcv.data(), nnz * 8, hipMemcpyHostToDevice, st));
+    CK(hipMemcpyAsync(h->d_perm.p, p32.data(), n * 4, hipMemcpyHostToDevice, st));
+    CK(hipStreamSynchronize(st));
+  }
   if (h->opt.use_mwm) {
     // boundary of the scaled system: rows by perm with D_l, columns by
     // sigma o perm with D_r
@@ -307,12 +345,46 @@ bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr, const
   }
   CK(hipStreamSynchronize(st));
 #undef CK
-  h->stats = bilu_stats{};
-  h->stats.n = n;
-  h->stats.nnz_a = nnz;
-  h->stats.ngroups = (int64_t)h->group_starts.size() - 1;
-  h->stats.t_analyze = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  h->state = 1;
+  analyze_done(h, t0);
+  return BILU_OK;
+  GUARD_END
+}
+
+bilu_status bilu_analyze_device(bilu_handle* h, int64_t n, const int64_t* rowptr,
+                                const int32_t* colind, const double* val) {
+  if (!h) return BILU_ERR_INVALID;
+  GUARD_BEGIN
+  auto t0 = std::chrono::steady_clock::now();
+  if (n <= 0 || !rowptr || !colind || !val) return fail(h, BILU_ERR_INVALID, "null CSR or n<=0");
+  if (n > INT32_MAX - 1) return fail(h, BILU_ERR_INVALID, "n exceeds int32 range");
+  hipStream_t st = h->stream;
+  std::vector<int64_t> rp(n + 1);
+  hipError_t e = hipMemcpyAsync(rp.data(), rowptr, (n + 1) * 8, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_check(h, e, "bilu_analyze_device: rowptr");
+  if (rp[0] != 0) return fail(h, BILU_ERR_INVALID, "rowptr[0] != 0");
+  if (!rowptr_monotone(n, rp.data())) return fail(h, BILU_ERR_INVALID, "rowptr not monotone");
+  const int64_t nnz = rp[n];
+  if (h->opt.use_mwm || h->opt.analyze_path == 1 || nnz > INT32_MAX) {
+    // the host route, on a host copy of the matrix
+    std::vector<int32_t> ci(nnz);
+    std::vector<double> v(nnz);
+    if (nnz > 0) {
+      e = hipMemcpyAsync(ci.data(), colind, nnz * 4, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(v.data(), val, nnz * 8, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return hip_check(h, e, "bilu_analyze_device: entries");
+    }
+    const bilu_status s = bilu_analyze(h, n, rp.data(), ci.data(), v.data());
+    if (s == BILU_OK) h->stats.t_analyze = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return s;
+  }
+  h->state = 0;
+  h->ilu_static = false;
+  h->mwm = false;
+  const bilu_status s = analyze_device(h, n, rowptr, colind, val, rp.data());
+  if (s != BILU_OK) return s;
+  analyze_done(h, t0);
   return BILU_OK;
   GUARD_END
 }

@@ -2133,6 +2133,7 @@ int64_t factor_partition(bilu_handle* h, double tau) {
   int64_t nb = h->opt.use_ilu1t ? ilu1t_partition_device(h, tau, bs, &t_sets) : -1;
   if (nb < 0) {
     (void)hipGetLastError();
+    if (ensure_host_matrix(h) != BILU_OK) return -1;
     nb = ilu1t_partition(h, tau, bs, &t_sets);
   }
   h->stats.t_ilu1t = std::chrono::duration<double>(clk::now() - t0).count();

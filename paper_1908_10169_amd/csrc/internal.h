@@ -321,6 +321,17 @@ bilu_status analyze_host(bilu_handle* h, int64_t n, const int64_t* rowptr,
                          const int32_t* colind, const double* val);
 int64_t ilu1t_partition(const bilu_handle* h, double tau, std::vector<int32_t>& bstart,
                         double* t_sets = nullptr);
+void cosine_limits(int64_t n, int64_t nnz, const int64_t* rc, const int64_t* cc, double* lim_r,
+                   double* lim_c);
+bool pre_permutation(const bilu_handle* h, int64_t n, std::vector<int64_t>& pre);
+bilu_status order_and_expand(bilu_handle* h, const int64_t* rp1, const int32_t* ci1,
+                             const std::vector<int64_t>& pre, const std::vector<int64_t>& q,
+                             const std::vector<int64_t>& gs);
+
+// analyze_dev.hip
+bilu_status analyze_device(bilu_handle* h, int64_t n, const int64_t* d_rowptr,
+                           const int32_t* d_colind, const double* d_val, const int64_t* rowptr);
+bilu_status ensure_host_matrix(bilu_handle* h);
 
 // ilu1t.hip
 int64_t ilu1t_partition_device(bilu_handle* h, double tau, std::vector<int32_t>& bstart,
