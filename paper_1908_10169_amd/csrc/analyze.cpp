@@ -197,8 +197,8 @@ void cosine(const Csr& a, const Csr& at, double eps, int max_block, std::vector<
 // connected part is found by repeated breadth-first search; the middle
 // level (the first level holding half of the part) is the separator,
 // reduced to the vertices that touch the far side; both sides are ordered
-// first and the separator last.  Parts of at most 8 vertices keep their
-// input order.
+// first and the separator last.  Parts of at most 8 vertices are listed in
+// ascending order.
 // ---------------------------------------------------------------------------
 struct Graph {
   int64_t n = 0;
@@ -206,117 +206,187 @@ struct Graph {
   std::vector<int32_t> adj;
 };
 
+// Shared state of one ordering.  Concurrent tasks own disjoint vertex sets:
+// level and mark are only touched for a task's own vertices, and part is
+// read for foreign vertices only to see that they are foreign (any label of
+// another task differs from the reader's own).
+struct NdState {
+  const Graph& g;
+  std::vector<std::atomic<int32_t>> part;
+  std::vector<int32_t> level, mark;
+  std::atomic<int32_t> next_label{1};
+  std::atomic<int> threads{1};
+  int max_threads = 1;
+  int32_t* out;
+  NdState(const Graph& gr, int32_t* o) : g(gr), part(gr.n), level(gr.n, 0), mark(gr.n, 0), out(o) {
+    for (auto& x : part) x.store(0, std::memory_order_relaxed);
+  }
+  int32_t label() { return next_label.fetch_add(1, std::memory_order_relaxed); }
+  int32_t part_of(int32_t v) const { return part[v].load(std::memory_order_relaxed); }
+};
+
+struct NdTask {
+  std::vector<int32_t> verts;
+  bool emit;    // a separator, already sorted
+  int64_t off;  // where its order starts
+};
+
+// Breadth-first search inside the part of src; records levels.
+void nd_bfs(NdState& S, int32_t src, int32_t label, std::vector<int32_t>& seq) {
+  seq.clear();
+  seq.push_back(src);
+  S.level[src] = 0;
+  S.mark[src] = label;
+  const int32_t pt = S.part_of(src);
+  for (size_t hd = 0; hd < seq.size(); ++hd) {
+    const int32_t v = seq[hd];
+    for (int64_t k = S.g.xadj[v]; k < S.g.xadj[v + 1]; ++k) {
+      const int32_t w = S.g.adj[k];
+      if (S.part_of(w) != pt || S.mark[w] == label) continue;
+      S.mark[w] = label;
+      S.level[w] = S.level[v] + 1;
+      seq.push_back(w);
+    }
+  }
+}
+
+// One step on a task: either its order is written (a separator, a part of at
+// most 8 vertices, or a part without a level structure of depth 2), or its
+// children are returned in output order with their offsets.
+void nd_step(NdState& S, NdTask& t, std::vector<NdTask>& kids, std::vector<int32_t>& seq) {
+  kids.clear();
+  auto write = [&](std::vector<int32_t>& v) {
+    std::copy(v.begin(), v.end(), S.out + t.off);
+  };
+  if (t.emit || t.verts.size() <= 8) {
+    if (!t.emit) std::sort(t.verts.begin(), t.verts.end());
+    write(t.verts);
+    return;
+  }
+  const int32_t lab = S.label();
+  for (int32_t v : t.verts) S.part[v].store(lab, std::memory_order_relaxed);
+  // connected components of the part, ordered one after another
+  std::vector<std::vector<int32_t>> comps;
+  const int32_t cm = S.label();
+  for (int32_t v : t.verts) {
+    if (S.mark[v] == cm) continue;
+    nd_bfs(S, v, cm, seq);
+    comps.push_back(seq);
+  }
+  if (comps.size() > 1) {
+    int64_t at = t.off;
+    for (auto& c : comps) {
+      const int64_t sz = (int64_t)c.size();
+      kids.push_back(NdTask{std::move(c), false, at});
+      at += sz;
+    }
+    return;
+  }
+  // one connected part: pseudo-peripheral start vertex
+  std::vector<int32_t> comp = std::move(comps[0]);
+  int32_t start = *std::min_element(comp.begin(), comp.end());
+  int32_t depth = -1;
+  for (int it = 0; it < 4; ++it) {
+    nd_bfs(S, start, S.label(), seq);
+    const int32_t far = seq.back();
+    if (S.level[far] <= depth) break;
+    depth = S.level[far];
+    start = far;
+  }
+  const int32_t lbl = S.label();
+  nd_bfs(S, start, lbl, seq);
+  const int32_t maxlev = S.level[seq.back()];
+  if (maxlev < 2) {
+    std::sort(comp.begin(), comp.end());
+    write(comp);
+    return;
+  }
+  // separator level: the first whose cumulative size reaches half
+  std::vector<int64_t> cnt(maxlev + 1, 0);
+  for (int32_t v : seq) cnt[S.level[v]]++;
+  int64_t acc = 0;
+  int32_t mid = 1;
+  for (int32_t l = 0; l <= maxlev; ++l) {
+    acc += cnt[l];
+    if (2 * acc >= (int64_t)seq.size()) {
+      mid = std::min(std::max(l, 1), maxlev - 1);
+      break;
+    }
+  }
+  NdTask left{{}, false, 0}, right{{}, false, 0}, sep{{}, true, 0};
+  for (int32_t v : seq) {
+    const int32_t l = S.level[v];
+    if (l < mid) {
+      left.verts.push_back(v);
+    } else if (l > mid) {
+      right.verts.push_back(v);
+    } else {
+      bool far_side = false;
+      for (int64_t k = S.g.xadj[v]; k < S.g.xadj[v + 1] && !far_side; ++k) {
+        const int32_t w = S.g.adj[k];
+        far_side = S.part_of(w) == lab && S.mark[w] == lbl && S.level[w] == mid + 1;
+      }
+      (far_side ? sep.verts : left.verts).push_back(v);
+    }
+  }
+  std::sort(sep.verts.begin(), sep.verts.end());
+  // both sides first, the separator last
+  left.off = t.off;
+  right.off = left.off + (int64_t)left.verts.size();
+  sep.off = right.off + (int64_t)right.verts.size();
+  kids.push_back(std::move(left));
+  kids.push_back(std::move(right));
+  kids.push_back(std::move(sep));
+}
+
+// A subtree on the calling thread, with an explicit stack.
+void nd_serial(NdState& S, NdTask root) {
+  std::vector<NdTask> stack, kids;
+  std::vector<int32_t> seq;
+  stack.push_back(std::move(root));
+  while (!stack.empty()) {
+    NdTask t = std::move(stack.back());
+    stack.pop_back();
+    nd_step(S, t, kids, seq);
+    for (auto& k : kids) stack.push_back(std::move(k));
+  }
+}
+
+// Large parts hand their children to other threads while threads are free;
+// each child writes its own range of the order, so the result does not
+// depend on the schedule.
+void nd_parallel(NdState& S, NdTask t) {
+  constexpr size_t kSpawn = 16384;  // smallest part worth a thread
+  std::vector<NdTask> kids;
+  std::vector<int32_t> seq;
+  nd_step(S, t, kids, seq);
+  std::vector<std::thread> th;
+  for (size_t i = 0; i < kids.size(); ++i) {
+    NdTask& k = kids[i];
+    const bool big = k.verts.size() >= kSpawn && !k.emit;
+    if (big && i + 1 < kids.size() &&
+        S.threads.fetch_add(1, std::memory_order_relaxed) < S.max_threads) {
+      th.emplace_back([&S, task = std::move(k)]() mutable {
+        nd_parallel(S, std::move(task));
+        S.threads.fetch_sub(1, std::memory_order_relaxed);
+      });
+      continue;
+    }
+    if (big && i + 1 < kids.size()) S.threads.fetch_sub(1, std::memory_order_relaxed);
+    if (big) nd_parallel(S, std::move(k));
+    else nd_serial(S, std::move(k));
+  }
+  for (auto& x : th) x.join();
+}
+
 void nd_order(const Graph& g, std::vector<int32_t>& order) {
   const int64_t n = g.n;
-  order.clear();
-  order.reserve(n);
-  std::vector<int32_t> part(n, 0), level(n, 0), mark(n, 0);
-  int32_t next_part = 1, next_mark = 1;
-  struct Task {
-    std::vector<int32_t> verts;
-    bool emit;
-  };
-  std::vector<Task> stack;
-  {
-    Task t{std::vector<int32_t>(n), false};
-    std::iota(t.verts.begin(), t.verts.end(), 0);
-    stack.push_back(std::move(t));
-  }
-  // breadth-first search inside the part of src; records levels
-  auto bfs = [&](int32_t src, int32_t label, std::vector<int32_t>& seq) {
-    seq.clear();
-    seq.push_back(src);
-    level[src] = 0;
-    mark[src] = label;
-    const int32_t pt = part[src];
-    for (size_t hd = 0; hd < seq.size(); ++hd) {
-      const int32_t v = seq[hd];
-      for (int64_t k = g.xadj[v]; k < g.xadj[v + 1]; ++k) {
-        const int32_t w = g.adj[k];
-        if (part[w] != pt || mark[w] == label) continue;
-        mark[w] = label;
-        level[w] = level[v] + 1;
-        seq.push_back(w);
-      }
-    }
-  };
-  std::vector<int32_t> seq;
-  while (!stack.empty()) {
-    Task t = std::move(stack.back());
-    stack.pop_back();
-    if (t.emit || t.verts.size() <= 8) {
-      if (!t.emit) std::sort(t.verts.begin(), t.verts.end());
-      order.insert(order.end(), t.verts.begin(), t.verts.end());
-      continue;
-    }
-    const int32_t lab = next_part++;
-    for (int32_t v : t.verts) part[v] = lab;
-    // connected components of the part, ordered one after another
-    std::vector<std::vector<int32_t>> comps;
-    const int32_t cm = next_mark++;
-    for (int32_t v : t.verts) {
-      if (mark[v] == cm) continue;
-      bfs(v, cm, seq);
-      comps.push_back(seq);
-    }
-    if (comps.size() > 1) {
-      for (auto it = comps.rbegin(); it != comps.rend(); ++it)
-        stack.push_back(Task{std::move(*it), false});
-      continue;
-    }
-    // one connected part: pseudo-peripheral start vertex
-    const std::vector<int32_t> comp = std::move(comps[0]);
-    int32_t start = *std::min_element(comp.begin(), comp.end());
-    int32_t depth = -1;
-    for (int it = 0; it < 4; ++it) {
-      bfs(start, next_mark++, seq);
-      const int32_t far = seq.back();
-      if (level[far] <= depth) break;
-      depth = level[far];
-      start = far;
-    }
-    const int32_t lbl = next_mark++;
-    bfs(start, lbl, seq);
-    const int32_t maxlev = level[seq.back()];
-    if (maxlev < 2) {
-      std::vector<int32_t> v = comp;
-      std::sort(v.begin(), v.end());
-      order.insert(order.end(), v.begin(), v.end());
-      continue;
-    }
-    // separator level: the first whose cumulative size reaches half
-    std::vector<int64_t> cnt(maxlev + 1, 0);
-    for (int32_t v : seq) cnt[level[v]]++;
-    int64_t acc = 0;
-    int32_t mid = 1;
-    for (int32_t l = 0; l <= maxlev; ++l) {
-      acc += cnt[l];
-      if (2 * acc >= (int64_t)seq.size()) {
-        mid = std::min(std::max(l, 1), maxlev - 1);
-        break;
-      }
-    }
-    Task left{{}, false}, right{{}, false}, sep{{}, true};
-    for (int32_t v : seq) {
-      const int32_t l = level[v];
-      if (l < mid) {
-        left.verts.push_back(v);
-      } else if (l > mid) {
-        right.verts.push_back(v);
-      } else {
-        bool far_side = false;
-        for (int64_t k = g.xadj[v]; k < g.xadj[v + 1] && !far_side; ++k) {
-          const int32_t w = g.adj[k];
-          far_side = part[w] == lab && mark[w] == lbl && level[w] == mid + 1;
-        }
-        (far_side ? sep.verts : left.verts).push_back(v);
-      }
-    }
-    std::sort(sep.verts.begin(), sep.verts.end());
-    stack.push_back(std::move(sep));    // popped last: separator after both sides
-    stack.push_back(std::move(right));
-    stack.push_back(std::move(left));
-  }
+  order.assign(n, 0);
+  NdState S(g, order.data());
+  S.max_threads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  NdTask root{std::vector<int32_t>(n), false, 0};
+  std::iota(root.verts.begin(), root.verts.end(), 0);
+  nd_parallel(S, std::move(root));
 }
 
 }  // namespace
@@ -338,7 +408,7 @@ bilu_status order_and_expand(bilu_handle* h, const int64_t* rp1, const int32_t* 
     std::vector<int32_t> gof(n);
     for (int64_t g = 0; g < ng; ++g)
       for (int64_t k = gs[g]; k < gs[g + 1]; ++k) gof[q[k]] = (int32_t)g;
-    // edges of B + B^T
+    // edges of B + B^T: the out-neighbours of each group, sorted and unique
     std::vector<std::vector<int32_t>> nb(ng);
     parallel_for(ng, [&](int64_t lo, int64_t hi) {
       for (int64_t g = lo; g < hi; ++g) {
@@ -350,27 +420,52 @@ bilu_status order_and_expand(bilu_handle* h, const int64_t* rp1, const int32_t* 
             if (h2 != g) v.push_back(h2);
           }
         }
-      }
-    });
-    Graph gr;
-    gr.n = ng;
-    {
-      std::vector<std::vector<int32_t>> sym(ng);
-      for (int64_t g = 0; g < ng; ++g)
-        for (int32_t h2 : nb[g]) {
-          sym[g].push_back(h2);
-          sym[h2].push_back((int32_t)g);
-        }
-      gr.xadj.assign(ng + 1, 0);
-      for (int64_t g = 0; g < ng; ++g) {
-        auto& v = sym[g];
         std::sort(v.begin(), v.end());
         v.erase(std::unique(v.begin(), v.end()), v.end());
-        gr.xadj[g + 1] = gr.xadj[g] + (int64_t)v.size();
       }
-      gr.adj.reserve(gr.xadj[ng]);
-      for (int64_t g = 0; g < ng; ++g) gr.adj.insert(gr.adj.end(), sym[g].begin(), sym[g].end());
+    });
+    // in-neighbours, ascending by construction
+    std::vector<int64_t> iptr(ng + 1, 0);
+    for (int64_t g = 0; g < ng; ++g)
+      for (int32_t h2 : nb[g]) iptr[h2 + 1]++;
+    std::partial_sum(iptr.begin(), iptr.end(), iptr.begin());
+    std::vector<int32_t> iadj(iptr[ng]);
+    {
+      std::vector<int64_t> fill(iptr.begin(), iptr.end() - 1);
+      for (int64_t g = 0; g < ng; ++g)
+        for (int32_t h2 : nb[g]) iadj[fill[h2]++] = (int32_t)g;
     }
+    // the union of both lists per group
+    Graph gr;
+    gr.n = ng;
+    gr.xadj.assign(ng + 1, 0);
+    auto merge = [&](int64_t g, int32_t* out) {
+      const auto& a = nb[g];
+      const int32_t* b = iadj.data() + iptr[g];
+      const int32_t* be = iadj.data() + iptr[g + 1];
+      size_t i = 0;
+      int64_t c = 0;
+      while (i < a.size() || b < be) {
+        int32_t x;
+        if (b == be || (i < a.size() && a[i] < *b)) x = a[i++];
+        else if (i == a.size() || *b < a[i]) x = *b++;
+        else {
+          x = a[i++];
+          ++b;
+        }
+        if (out) out[c] = x;
+        ++c;
+      }
+      return c;
+    };
+    parallel_for(ng, [&](int64_t lo, int64_t hi) {
+      for (int64_t g = lo; g < hi; ++g) gr.xadj[g + 1] = merge(g, nullptr);
+    });
+    std::partial_sum(gr.xadj.begin(), gr.xadj.end(), gr.xadj.begin());
+    gr.adj.resize(gr.xadj[ng]);
+    parallel_for(ng, [&](int64_t lo, int64_t hi) {
+      for (int64_t g = lo; g < hi; ++g) merge(g, gr.adj.data() + gr.xadj[g]);
+    });
     nd_order(gr, gorder);
     if ((int64_t)gorder.size() != ng) return fail(h, BILU_ERR_INTERNAL, "ordering lost vertices");
   }
