@@ -178,6 +178,19 @@ bilu_status bilu_analyze_device(bilu_handle* h, int64_t n, const int64_t* rowptr
  * (no analyze), BILU_ERR_NO_MEMORY, BILU_ERR_DEVICE.  Synchronous. */
 bilu_status bilu_factor(bilu_handle* h, double tau);
 
+/* Numeric refactorization for a sequence of matrices with one pattern
+ * (the paper's time-step matrices, Sec. 4): val (device array, rowptr[n]
+ * doubles in the entry order of the matrix given to bilu_analyze) replaces
+ * A's values; the block Crout sweep of Sec. 2.2 (dropping with tau,
+ * perturbation, aggregation) runs again on the initial blocks of the last
+ * bilu_factor, without the cosine step, the ordering or ILU(1,tau).  The
+ * result is what the sweep gives on that partition, so it equals the last
+ * factor bit for bit when val holds the same values and tau is the same.
+ * Errors: BILU_ERR_STATE before bilu_factor, BILU_ERR_INVALID (non-finite
+ * value: nothing changes; use_mwm; nnz >= 2^31), and those of bilu_factor.
+ * Synchronous. */
+bilu_status bilu_refactor(bilu_handle* h, double tau, const double* val);
+
 /* Factor count independent analyzed handles in one launch of the factor
  * sweep (many matrices at once).  hs[i] is factored with drop tolerance
  * taus[i]; every handle ends as bilu_factor(hs[i], taus[i]) would leave it,

@@ -81,7 +81,7 @@ EXPORTED = [
     "bilu_spmv", "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors",
     "bilu_free_factors", "bilu_destroy", "bilu_status_string", "bilu_last_error",
     "bilu_preprocess", "bilu_sync", "bilu_export_trace", "bilu_factor_batched", "bilu_mwm",
-    "bilu_analyze_device",
+    "bilu_analyze_device", "bilu_refactor",
 ]
 
 _lib = None
@@ -120,9 +120,10 @@ def load(path: str = LIB_PATH):
     lib.bilu_export_trace.restype = C.c_int
     lib.bilu_mwm.argtypes = [C.c_int64, vp, vp, vp, vp, vp, vp]
     lib.bilu_analyze_device.argtypes = [vp, C.c_int64, vp, vp, vp]
+    lib.bilu_refactor.argtypes = [vp, C.c_double, vp]
     lib.bilu_preprocess.argtypes = [C.POINTER(Options), C.c_int64, vp, vp, vp, C.c_double,
                                     vp, vp, C.POINTER(C.c_int64), vp, C.POINTER(C.c_int64)]
-    for f in ("bilu_create", "bilu_analyze", "bilu_analyze_device", "bilu_factor", "bilu_factor_batched", "bilu_apply",
+    for f in ("bilu_create", "bilu_analyze", "bilu_analyze_device", "bilu_refactor", "bilu_factor", "bilu_factor_batched", "bilu_apply",
               "bilu_spmv",
               "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors", "bilu_preprocess",
               "bilu_sync"):
@@ -290,6 +291,12 @@ class Bilu:
 
     def factor(self, tau: float):
         return self._check(self._lib.bilu_factor(self._h, tau), "bilu_factor",
+                           ok=(BILU_OK, BILU_WARN_PERTURBED))
+
+    def refactor(self, tau: float, val):
+        """bilu_refactor: val is a float64 device tensor of nnz values in the
+        analyzed matrix's entry order."""
+        return self._check(self._lib.bilu_refactor(self._h, tau, val.data_ptr()), "bilu_refactor",
                            ok=(BILU_OK, BILU_WARN_PERTURBED))
 
     def apply(self, x, y):

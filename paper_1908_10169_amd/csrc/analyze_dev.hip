@@ -243,15 +243,56 @@ __global__ __launch_bounds__(kT) void entry_keys(int64_t n, const int64_t* __res
   }
 }
 
-// Sorted keys -> index array (the low field) and values.
-__global__ void sorted_entries(int64_t nnz, const unsigned long long* __restrict__ key,
-                               const int32_t* __restrict__ idx, const double* __restrict__ v,
-                               unsigned long long mask, int32_t* __restrict__ out_i,
-                               double* __restrict__ out_v) {
+// Sorted keys -> index array (the low field).
+__global__ void key_low(int64_t nnz, const unsigned long long* __restrict__ key,
+                        unsigned long long mask, int32_t* __restrict__ out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nnz; t += stride)
+    out[t] = (int32_t)(key[t] & mask);
+}
+
+// Values of P A P^T through the maps: out_r[t] = v[mr[t]], out_c[t] = v[mc[t]].
+__global__ void gather_values(int64_t nnz, const double* __restrict__ v,
+                              const int32_t* __restrict__ mr, const int32_t* __restrict__ mc,
+                              double* __restrict__ out_r, double* __restrict__ out_c) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nnz; t += stride) {
-    out_i[t] = (int32_t)(key[t] & mask);
-    out_v[t] = v[idx[t]];
+    out_r[t] = v[mr[t]];
+    out_c[t] = v[mc[t]];
+  }
+}
+
+// Values finite (bit 4 of bad otherwise) and max |v|.
+__global__ __launch_bounds__(kT) void values_check(int64_t nnz, const double* __restrict__ v,
+                                                   int* __restrict__ bad,
+                                                   unsigned long long* __restrict__ amax) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int f = 0;
+  double mx = 0.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nnz; t += stride) {
+    const double x = v[t];
+    if (!isfinite(x)) f = 4;
+    else mx = fmax(mx, fabs(x));
+  }
+  for (int o = 32; o; o >>= 1) {
+    f |= __shfl_xor(f, o);
+    mx = fmax(mx, __shfl_xor(mx, o));
+  }
+  __shared__ int sf[kT / 64];
+  __shared__ double sm[kT / 64];
+  const int lane = threadIdx.x & 63;
+  if (lane == 0) {
+    sf[threadIdx.x >> 6] = f;
+    sm[threadIdx.x >> 6] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kT / 64; ++w) {
+      f |= sf[w];
+      mx = fmax(mx, sm[w]);
+    }
+    if (f) atomicOr(bad, f);
+    if (mx > 0.0) atomicMax(amax, (unsigned long long)__double_as_longlong(mx));
   }
 }
 
@@ -347,7 +388,6 @@ bilu_status analyze_device(bilu_handle* h, int64_t n, const int64_t* d_a_rp,
   std::vector<int64_t> pre;
   if (!pre_permutation(h, n, pre)) return fail(h, BILU_ERR_INVALID, "pre_perm is not a permutation");
   const bool ident = h->opt.pre_perm == nullptr;
-  const int nbits = std::max(1, 64 - __builtin_clzll((unsigned long long)std::max<int64_t>(1, n - 1)));
 
   // 2. A1 = A(pre, pre), when the cosine step or the ordering reads it
   const bool need_nd = h->opt.ordering == BILU_ORDER_ND;
@@ -514,44 +554,118 @@ bilu_status analyze_device(bilu_handle* h, int64_t n, const int64_t* d_a_rp,
   CK(h->d_ri.alloc(nnz));
   CK(h->d_cv.alloc(nnz));
   CK(h->d_perm.alloc(n));
-  CK(d_inv.alloc(n));
   CK(hipMemcpyAsync(h->d_perm.p, perm32.data(), n * 4, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(h->d_rp.p, prp.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(h->d_cp.p, pcp.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
-  invert_perm<<<flat_grid(n), kT, 0, st>>>(n, h->d_perm.p, d_inv.p);
-  CK(hipGetLastError());
+  {
+    const bilu_status ms = value_maps(h, d_a_rp, d_a_ci, true);
+    if (ms != BILU_OK) return ms;
+  }
   if (nnz > 0) {
-    DevArray<unsigned long long> k_in, k_out;
-    DevArray<int32_t> i_in, i_out;
-    CK(k_in.alloc(nnz));
-    CK(k_out.alloc(nnz));
-    CK(i_in.alloc(nnz));
-    CK(i_out.alloc(nnz));
-    const int end_bit = 2 * nbits;
-    size_t tb = 0;
-    CK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k_in.p, k_out.p, i_in.p, i_out.p,
-                                          (int)nnz, 0, end_bit, st));
-    DevArray<char> tmp;
-    CK(tmp.alloc(std::max<size_t>(tb, 1)));
-    const unsigned long long mask = (1ull << nbits) - 1ull;
-    for (int pass = 0; pass < 2; ++pass) {
-      if (pass == 0)
-        entry_keys<false><<<stream_grid(n), kT, 0, st>>>(n, d_a_rp, d_a_ci, d_inv.p, nbits,
-                                                          k_in.p, i_in.p);
-      else
-        entry_keys<true><<<stream_grid(n), kT, 0, st>>>(n, d_a_rp, d_a_ci, d_inv.p, nbits,
-                                                         k_in.p, i_in.p);
-      CK(hipGetLastError());
-      CK(hipcub::DeviceRadixSort::SortPairs(tmp.p, tb, k_in.p, k_out.p, i_in.p, i_out.p,
-                                            (int)nnz, 0, end_bit, st));
-      sorted_entries<<<flat_grid(nnz), kT, 0, st>>>(nnz, k_out.p, i_out.p, d_a_v, mask,
-                                                    pass == 0 ? h->d_ci.p : h->d_ri.p,
-                                                    pass == 0 ? h->d_rv.p : h->d_cv.p);
-      CK(hipGetLastError());
-    }
+    gather_values<<<flat_grid(nnz), kT, 0, st>>>(nnz, d_a_v, h->d_vmap_r.p, h->d_vmap_c.p,
+                                                 h->d_rv.p, h->d_cv.p);
+    CK(hipGetLastError());
   }
   CK(hipStreamSynchronize(st));
 #undef CK
+  return BILU_OK;
+}
+
+// For every position of the CSR (and of the CSC) of P A P^T the index of
+// the entry of A it holds, from d_perm (new -> old) and A's pattern in device
+// memory; with write_idx also the column (row) index arrays.  Two radix
+// sorts of (row, column) and (column, row) keys, payload the entry index;
+// the keys are unique, so CSR rows ascend by column and CSC columns by row.
+bilu_status value_maps(bilu_handle* h, const int64_t* d_a_rp, const int32_t* d_a_ci,
+                       bool write_idx) {
+  const int64_t n = h->n, nnz = h->nnz;
+  h->d_vmap_r.release();
+  h->d_vmap_c.release();
+  if (nnz > INT32_MAX) return BILU_OK;  // no maps: bilu_refactor reports it
+  hipStream_t st = h->stream;
+#define CK(x)                                          \
+  do {                                                 \
+    hipError_t e_ = (x);                               \
+    if (e_ != hipSuccess) return hip_check(h, e_, #x); \
+  } while (0)
+  CK(h->d_vmap_r.alloc(std::max<int64_t>(1, nnz)));
+  CK(h->d_vmap_c.alloc(std::max<int64_t>(1, nnz)));
+  if (nnz == 0) return BILU_OK;
+  const int nbits = std::max(1, 64 - __builtin_clzll((unsigned long long)std::max<int64_t>(1, n - 1)));
+  DevArray<int32_t> d_inv, i_in;
+  DevArray<unsigned long long> k_in, k_out;
+  CK(d_inv.alloc(n));
+  CK(k_in.alloc(nnz));
+  CK(k_out.alloc(nnz));
+  CK(i_in.alloc(nnz));
+  invert_perm<<<flat_grid(n), kT, 0, st>>>(n, h->d_perm.p, d_inv.p);
+  CK(hipGetLastError());
+  const int end_bit = 2 * nbits;
+  size_t tb = 0;
+  CK(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, k_in.p, k_out.p, i_in.p, h->d_vmap_r.p,
+                                        (int)nnz, 0, end_bit, st));
+  DevArray<char> tmp;
+  CK(tmp.alloc(std::max<size_t>(tb, 1)));
+  const unsigned long long mask = (1ull << nbits) - 1ull;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 0)
+      entry_keys<false><<<stream_grid(n), kT, 0, st>>>(n, d_a_rp, d_a_ci, d_inv.p, nbits, k_in.p,
+                                                        i_in.p);
+    else
+      entry_keys<true><<<stream_grid(n), kT, 0, st>>>(n, d_a_rp, d_a_ci, d_inv.p, nbits, k_in.p,
+                                                       i_in.p);
+    CK(hipGetLastError());
+    CK(hipcub::DeviceRadixSort::SortPairs(tmp.p, tb, k_in.p, k_out.p, i_in.p,
+                                          pass == 0 ? h->d_vmap_r.p : h->d_vmap_c.p, (int)nnz, 0,
+                                          end_bit, st));
+    if (write_idx) {
+      key_low<<<flat_grid(nnz), kT, 0, st>>>(nnz, k_out.p, mask, pass == 0 ? h->d_ci.p : h->d_ri.p);
+      CK(hipGetLastError());
+    }
+  }
+  CK(hipStreamSynchronize(st));  // the temporaries end here
+#undef CK
+  return BILU_OK;
+}
+
+// New values of the analyzed pattern (device array, A's own entry order)
+// into P A P^T's CSR and CSC; max |a_ij| for the perturbation scale.
+bilu_status refactor_values(bilu_handle* h, const double* d_val) {
+  const int64_t nnz = h->nnz;
+  hipStream_t st = h->stream;
+#define CK(x)                                          \
+  do {                                                 \
+    hipError_t e_ = (x);                               \
+    if (e_ != hipSuccess) return hip_check(h, e_, #x); \
+  } while (0)
+  DevArray<int> d_bad;
+  DevArray<unsigned long long> d_amax;
+  CK(d_bad.alloc(1));
+  CK(d_amax.alloc(1));
+  CK(hipMemsetAsync(d_bad.p, 0, sizeof(int), st));
+  CK(hipMemsetAsync(d_amax.p, 0, sizeof(unsigned long long), st));
+  if (nnz > 0) {
+    values_check<<<flat_grid(nnz), kT, 0, st>>>(nnz, d_val, d_bad.p, d_amax.p);
+    CK(hipGetLastError());
+  }
+  int bad = 0;
+  unsigned long long amax = 0;
+  CK(hipMemcpyAsync(&bad, d_bad.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(&amax, d_amax.p, sizeof(amax), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  if (bad) return fail(h, BILU_ERR_INVALID, "non-finite value");
+  if (nnz > 0) {
+    gather_values<<<flat_grid(nnz), kT, 0, st>>>(nnz, d_val, h->d_vmap_r.p, h->d_vmap_c.p,
+                                                 h->d_rv.p, h->d_cv.p);
+    CK(hipGetLastError());
+  }
+  CK(hipStreamSynchronize(st));
+#undef CK
+  double alpha;
+  std::memcpy(&alpha, &amax, sizeof(alpha));
+  h->alpha = alpha;
+  h->prp.clear();          // host copies, if any, hold the old values
+  h->ilu_static = false;   // so does the diagonal kept for ILU(1,tau)
   return BILU_OK;
 }
 

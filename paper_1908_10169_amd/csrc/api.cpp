@@ -316,6 +316,17 @@ bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr, const
     CK(hipMemcpyAsync(h->d_ri.p, h->pri.data(), nnz * 4, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(h->d_cv.p, h->pcv.data(), nnz * 8, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(h->d_perm.p, p32.data(), n * 4, hipMemcpyHostToDevice, st));
+    // value maps for bilu_refactor, from A's pattern on the device
+    if (nnz <= INT32_MAX) {
+      DevArray<int64_t> a_rp;
+      DevArray<int32_t> a_ci;
+      CK(a_rp.alloc(n + 1));
+      CK(a_ci.alloc(std::max<int64_t>(1, nnz)));
+      CK(hipMemcpyAsync(a_rp.p, rowptr, (n + 1) * 8, hipMemcpyHostToDevice, st));
+      CK(hipMemcpyAsync(a_ci.p, colind, nnz * 4, hipMemcpyHostToDevice, st));
+      s = value_maps(h, a_rp.p, a_ci.p, false);
+      if (s != BILU_OK) return s;
+    }
     CK(hipStreamSynchronize(st));
   }
   if (h->opt.use_mwm) {
@@ -401,6 +412,29 @@ bilu_status bilu_factor(bilu_handle* h, double tau) {
   h->stats.dev_ms_factor = h->stats.dev_ms_apply = h->stats.dev_ms_spmv = 0.0;
   h->stats.n_apply = h->stats.n_spmv = 0;
   bilu_status s = factor_device(h, tau);
+  if (s != BILU_OK) return s;
+  return finish_factor(h, t0);
+  GUARD_END
+}
+
+bilu_status bilu_refactor(bilu_handle* h, double tau, const double* val) {
+  if (!h) return BILU_ERR_INVALID;
+  if (h->state < 2) return fail(h, BILU_ERR_STATE, "bilu_refactor before bilu_factor");
+  if (!val) return fail(h, BILU_ERR_INVALID, "bilu_refactor: null values");
+  if (!(tau >= 0.0) || !std::isfinite(tau)) return fail(h, BILU_ERR_INVALID, "tau must be >= 0");
+  if (h->mwm) return fail(h, BILU_ERR_INVALID, "bilu_refactor: not with use_mwm");
+  if (h->nnz > 0 && !h->d_vmap_r.p) return fail(h, BILU_ERR_INVALID, "bilu_refactor: nnz >= 2^31");
+  GUARD_BEGIN
+  auto t0 = std::chrono::steady_clock::now();
+  bilu_status s = refactor_values(h, val);
+  if (s != BILU_OK) return s;  // nothing changed: the previous factor stands
+  h->state = 1;
+  h->ev_resolve();
+  h->stats.dev_ms_factor = h->stats.dev_ms_apply = h->stats.dev_ms_spmv = 0.0;
+  h->stats.n_apply = h->stats.n_spmv = 0;
+  h->stats.t_ilu1t = 0.0;
+  h->stats.t_phase[0] = h->stats.t_phase[1] = 0.0;
+  s = factor_sweep(h, tau, nullptr, nullptr);
   if (s != BILU_OK) return s;
   return finish_factor(h, t0);
   GUARD_END

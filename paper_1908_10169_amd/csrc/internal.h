@@ -218,6 +218,8 @@ struct bilu_handle {
   bilu::DevArray<int64_t> d_rp, d_cp;
   bilu::DevArray<int32_t> d_ci, d_ri, d_perm;
   bilu::DevArray<double> d_rv, d_cv;
+  // entry of A held by each position of the CSR / CSC (bilu_refactor)
+  bilu::DevArray<int32_t> d_vmap_r, d_vmap_c;
 
   // ---- factor: partition + schedule (host)
   std::vector<int32_t> bstart0;       // initial partition
@@ -332,6 +334,9 @@ bilu_status order_and_expand(bilu_handle* h, const int64_t* rp1, const int32_t* 
 bilu_status analyze_device(bilu_handle* h, int64_t n, const int64_t* d_rowptr,
                            const int32_t* d_colind, const double* d_val, const int64_t* rowptr);
 bilu_status ensure_host_matrix(bilu_handle* h);
+bilu_status value_maps(bilu_handle* h, const int64_t* d_a_rp, const int32_t* d_a_ci,
+                       bool write_idx);
+bilu_status refactor_values(bilu_handle* h, const double* d_val);
 
 // ilu1t.hip
 int64_t ilu1t_partition_device(bilu_handle* h, double tau, std::vector<int32_t>& bstart,
