@@ -245,21 +245,31 @@ __global__ void __launch_bounds__(256) lr_build(FactorView f, const int32_t* fw_
       }
       wave_sync();
       const int tn = min(64, mc - t0);
-      for (int u = 0; u < tn; ++u) {
-        const int r = sRow[wv][u];
-        if (r != lane && r != lane + 64) continue;
-        const int le = sLe[wv][u];
-        const int pJ = sP[wv][le];
-        int64_t& at = r == lane ? at0 : at1;
-        if (kFill) {
-          const int fJ = sF[wv][le];
-          const double* L = f.val + sLoff[wv][le] + (int64_t)sI[wv][u] * pJ;
+      if (kFill) {
+        // lane u copies item u: its row's next position plus the items of
+        // the same row before it in this chunk
+        const int myr = lane < tn ? sRow[wv][lane] : 0;
+        const long long b0 = __shfl((long long)at0, myr & 63, 64);
+        const long long b1 = __shfl((long long)at1, myr & 63, 64);
+        if (lane < tn) {
+          int64_t pos = myr < 64 ? b0 : b1;
+          for (int u = 0; u < lane; ++u)
+            if (sRow[wv][u] == myr) pos += sP[wv][sLe[wv][u]];
+          const int le = sLe[wv][lane];
+          const int pJ = sP[wv][le], fJ = sF[wv][le];
+          const double* L = f.val + sLoff[wv][le] + (int64_t)sI[wv][lane] * pJ;
           for (int c = 0; c < pJ; ++c) {
-            lr_col[at + c] = fJ + c;
-            lr_val[at + c] = L[c];
+            lr_col[pos + c] = fJ + c;
+            lr_val[pos + c] = L[c];
           }
         }
-        at += pJ;
+      }
+      // the rows' owner lanes advance past this chunk's items
+      for (int u = 0; u < tn; ++u) {
+        const int r = sRow[wv][u];
+        const int pJ = sP[wv][sLe[wv][u]];
+        if (r == lane) at0 += pJ;
+        else if (r == lane + 64) at1 += pJ;
       }
       wave_sync();
     }
