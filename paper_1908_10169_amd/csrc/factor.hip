@@ -1438,11 +1438,18 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   // predecessors; entries [total, total + totu) of the combined index range
   const int nu = 2 + np + npr, totu = kG ? 0 : s.x.useg[nu];
   const int tall = total + totu;
-  for (int base = 0; base < tall; base += kBatch * nt) {
+  // the column lists of column predecessors and the row lists of row
+  // predecessors (one contiguous range of segments) are only searched for
+  // the block's own range, which is read from the heap: they are not staged
+  const int gA = segoff[2 + np], gap = segoff[2 + 2 * np + npr] - gA;
+  const int tv = tall - gap;
+  for (int base = 0; base < tv; base += kBatch * nt) {
     int v[kBatch];
     for (int k = 0; k < kBatch; ++k) {
-      const int e = base + tid + k * nt;
-      if (e < total) {
+      const int ev = base + tid + k * nt;
+      const int e = ev < gA ? ev : ev + gap;
+      if (ev >= tv) {
+      } else if (e < total) {
         const int sg = last_le(segoff, nseg, e);
         v[k] = fast_list(a, s, fmeta, sg, np, npr)[e - segoff[sg]];
       } else if (!kG && e < tall) {
@@ -1459,8 +1466,9 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       }
     }
     for (int k = 0; k < kBatch; ++k) {
-      const int e = base + tid + k * nt;
-      if (e >= tall) break;
+      const int ev = base + tid + k * nt;
+      if (ev >= tv) break;
+      const int e = ev < gA ? ev : ev + gap;
       if (e < total) {
         stage[e] = v[k];
         const int sg = last_le(segoff, nseg, e);
@@ -1490,7 +1498,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     const int* B;
     int na, nb_, ka, kb;
     if (t < np) {
-      A = stage + segoff[2 + np + t];  // C: lo, hi
+      A = a.idx_heap + m.coff;         // C: lo, hi
       B = stage + segoff[2 + t];       // R: lo2
       na = m.nc;
       nb_ = m.nr;
@@ -1498,7 +1506,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       kb = f;
     } else {
       const int u = t - np;
-      A = stage + segoff[2 + 2 * np + u];        // R: lo, hi
+      A = a.idx_heap + m.roff;                   // R: lo, hi
       B = stage + segoff[2 + 2 * np + npr + u];  // C: lo2
       na = m.nr;
       nb_ = m.nc;
@@ -1653,15 +1661,17 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     const int i1 = min(nterms, i0 + cap);
     for (int e0 = i0 + tid; e0 < i1; e0 += kU * nt) {
       // (1) the predecessor and the (row, column) pair of each term
-      int64_t lo[kU], wo[kU];
-      int pp[kU], sr[kU], sc[kU];
+      // each term's row and column index: one from the staged lists (so),
+      // the one inside K from the heap (ho)
+      int64_t lo[kU], wo[kU], ho[kU];
+      int pp[kU], so[kU];
       bool colp[kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int e = e0 + u * nt;
-        lo[u] = wo[u] = 0;
+        lo[u] = wo[u] = ho[u] = 0;
         pp[u] = 0;
-        sr[u] = sc[u] = 0;
+        so[u] = 0;
         colp[u] = true;
         if (e < i1) {
           int lo_t = 0, hi_t = npt;  // last t with ioff <= e
@@ -1680,14 +1690,14 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
             const int nc = m.hi - m.lo;
             ri = m.lo2 + w / nc;
             cj = m.lo + w % nc;
-            sr[u] = segoff[2 + t] + ri;
-            sc[u] = segoff[2 + np + t] + cj;
+            so[u] = segoff[2 + t] + ri;
+            ho[u] = m.coff + cj;
           } else {
             const int nr = m.hi - m.lo;
             ri = m.lo + w % nr;
             cj = m.lo2 + w / nr;
-            sr[u] = segoff[2 + 2 * np + (t - np)] + ri;
-            sc[u] = segoff[2 + 2 * np + npr + (t - np)] + cj;
+            so[u] = segoff[2 + 2 * np + npr + (t - np)] + cj;
+            ho[u] = m.roff + ri;
             colp[u] = false;
           }
           lo[u] = m.loff + (int64_t)ri * m.p;
@@ -1699,8 +1709,10 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       int rr[kU], cc[kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        rr[u] = stage[sr[u]];
-        cc[u] = stage[sc[u]];
+        const int sv = stage[so[u]];
+        const int hv = a.idx_heap[ho[u]];
+        rr[u] = colp[u] ? sv : hv;
+        cc[u] = colp[u] ? hv : sv;
       }
       double acc[kU];
       if (a.update_prec == 0) {
