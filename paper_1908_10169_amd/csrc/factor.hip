@@ -1755,12 +1755,26 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     }
     if (i0 == 0 && a_tgt >= 0) fbuf[a_tgt] = a_val;
     __syncthreads();
-    // (4) in predecessor order (a predecessor's terms hit distinct entries)
-    for (int t = 0; t < npt; ++t) {
-      const int t0 = max(i0, fmeta[t].ioff);
-      const int t1 = min(i1, t + 1 < npt ? fmeta[t + 1].ioff : nterms);
-      if (t0 >= t1) continue;
-      for (int e = t0 + tid; e < t1; e += nt) fbuf[Ti[e - i0]] -= Tm[e - i0];
+    // (4) in predecessor order (a predecessor's terms hit distinct
+    // entries).  Column predecessors update only the column panel and row
+    // predecessors only the row panel, so the k-th of each go together.
+    for (int k = 0; k < max(np, npr); ++k) {
+      int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+      if (k < np) {
+        a0 = max(i0, fmeta[k].ioff);
+        a1 = min(i1, k + 1 < npt ? fmeta[k + 1].ioff : nterms);
+      }
+      if (k < npr) {
+        const int t = np + k;
+        b0 = max(i0, fmeta[t].ioff);
+        b1 = min(i1, t + 1 < npt ? fmeta[t + 1].ioff : nterms);
+      }
+      const int na = max(0, a1 - a0), nab = na + max(0, b1 - b0);
+      if (nab == 0) continue;
+      for (int x = tid; x < nab; x += nt) {
+        const int e = x < na ? a0 + x : b0 + (x - na);
+        fbuf[Ti[e - i0]] -= Tm[e - i0];
+      }
       __syncthreads();
     }
   }
