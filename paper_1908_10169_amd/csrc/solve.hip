@@ -445,6 +445,8 @@ __device__ __forceinline__ int wave_max_int(int v) {
   return v;
 }
 
+constexpr int kPre = 4;  // dependency steps of the dataflow apply loaded together
+
 __global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs a) {
   __shared__ double sv[4][kMaxWidth];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -477,12 +479,27 @@ __global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs a) {
         const int steps = wave_max_int(b < e ? (int)((e - b + g - 1) / g) : 0);
         const double xv = r < q && sub == 0 ? a.x[f + r] : 0.0;
         double acc = 0.0;
-        for (int i = 0; i < steps; ++i) {
-          const int64_t k = b + (int64_t)i * g;
-          const bool has = k < e;
-          const int col = has ? a.lr_col[k] : 0;
-          const double tv = await_values(a, 0, has, col, t0, bad, s);
-          if (has) acc = fma(a.lr_val[k], tv, acc);
+        // kPre steps at a time: their index, value and t loads go out
+        // together, then the sum runs in step order
+        for (int i0 = 0; i0 < steps; i0 += kPre) {
+          int col[kPre];
+          double lv[kPre];
+          unsigned long long tv0[kPre];
+          bool has[kPre];
+#pragma unroll
+          for (int u = 0; u < kPre; ++u) {
+            const int64_t k = b + (int64_t)(i0 + u) * g;
+            has[u] = i0 + u < steps && k < e;
+            col[u] = has[u] ? a.lr_col[k] : 0;
+            lv[u] = has[u] ? a.lr_val[k] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < kPre; ++u) tv0[u] = peek_value(a, 0, has[u], col[u]);
+#pragma unroll
+          for (int u = 0; u < kPre; ++u) {
+            const double tv = await_from(a, 0, has[u], col[u], tv0[u], t0, bad, s);
+            if (has[u]) acc = fma(lv[u], tv, acc);
+          }
         }
         for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
         if (r < q && sub == 0) publish_value(&a.t[f + r], xv - acc);
@@ -502,12 +519,25 @@ __global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs a) {
         const bool own = jj == 0 && r < q;
         const unsigned long long tv0 = peek_value(a, 0, own, f + r);  // usually there
         double acc = 0.0;
-        for (int i = 0; i < steps; ++i) {
-          const int j = jj + i * g;
-          const bool has = r < q && j < m;
-          const int col = has ? Cc[j] : 0;
-          const double zv = await_values(a, 1, has, col, t0, bad, s);
-          if (has) acc = fma(W[(int64_t)j * q + r], zv, acc);
+        for (int i0 = 0; i0 < steps; i0 += kPre) {
+          int col[kPre];
+          double wv[kPre];
+          unsigned long long zv0[kPre];
+          bool has[kPre];
+#pragma unroll
+          for (int u = 0; u < kPre; ++u) {
+            const int j = jj + (i0 + u) * g;
+            has[u] = i0 + u < steps && r < q && j < m;
+            col[u] = has[u] ? Cc[j] : 0;
+            wv[u] = has[u] ? W[(int64_t)j * q + r] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < kPre; ++u) zv0[u] = peek_value(a, 1, has[u], col[u]);
+#pragma unroll
+          for (int u = 0; u < kPre; ++u) {
+            const double zv = await_from(a, 1, has[u], col[u], zv0[u], t0, bad, s);
+            if (has[u]) acc = fma(wv[u], zv, acc);
+          }
         }
         for (int o = 32; o >= qp; o >>= 1) acc += __shfl_xor(acc, o, 64);
         const double tv = await_from(a, 0, own, f + r, tv0, t0, bad, s);
