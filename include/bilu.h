@@ -153,9 +153,13 @@ bilu_status bilu_create(bilu_handle** h, const bilu_options* opt, void* hip_stre
 
 /* Sec. 3.2-3.3 (preprocessing steps 2-3 of Sec. 3.7): validate the CSR,
  * cosine-group the rows, compress, order the compressed graph, expand the
- * permutation, and upload the permuted matrix.  Host arrays.  Synchronous.
- * Errors: BILU_ERR_INVALID (n <= 0, unsorted/duplicate/out-of-range column,
- * non-finite value, bad pre_perm), BILU_ERR_NO_MEMORY. */
+ * permutation, and keep the permuted matrix (CSR and CSC) in device memory.
+ * Host arrays (rowptr n+1 entries, colind and val rowptr[n] each), read
+ * during the call only.  With analyze_path = 0 the matrix is copied to the
+ * device first and the entry checks, the cosine search and the permutation
+ * run there.  Synchronous.  Errors: BILU_ERR_INVALID (n <= 0,
+ * unsorted/duplicate/out-of-range column, non-finite value, bad pre_perm),
+ * BILU_ERR_NO_MEMORY, BILU_ERR_DEVICE. */
 bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr,
                          const int32_t* colind, const double* val);
 
