@@ -8,6 +8,7 @@
 // Sums run over J in increasing order and over stored entries in storage
 // order, so results are run-to-run identical.
 #include <algorithm>
+#include <climits>
 #include <numeric>
 
 #include <hipcub/hipcub.hpp>
@@ -130,29 +131,97 @@ __global__ void __launch_bounds__(256) apply_levels(int nb, const int32_t* fptr,
   const int32_t* adj = fwd ? fj : bb;
   int* lev = fwd ? lf : lb;
   int wmax = 0;
-  for (int s = w; s < nb; s += W) {
-    const int K = fwd ? s : nb - 1 - s;
-    const int e0 = ptr[K], e1 = ptr[K + 1];
-    int l = 0;
-    for (int e = e0; e < e1; e += 64) {
-      const int J = e + lane < e1 ? adj[e + lane] : -1;
-      int v = J >= 0 ? __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
-      const unsigned long long t0 = wall_clock64();
-      while (!__all(v >= 0)) {
-        if (wall_clock64() - t0 > wait_ticks ||
-            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-          if (lane == 0) atomicExch(err, 1);
-          return;
-        }
-        __builtin_amdgcn_s_sleep(1);
-        if (v < 0) v = __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      if (J >= 0) l = max(l, v + 1);
+  // A window of kWin of the wave's blocks (w, w + W, ... in turn): each
+  // round polls every block of the window once and finishes those whose
+  // dependencies are all known, so a block that waits does not hold up the
+  // ones behind it.  A block with more than 64 dependencies is finished
+  // only as the wave's lowest unfinished block, with blocking waits (its
+  // dependencies then all sit at lower positions of other waves).
+  constexpr int kWin = 4;
+  // window state in LDS (indexed by entry): position, block, dependency
+  // count, and each lane's first dependency
+  __shared__ int sSeq[4][kWin], sK[4][kWin], sN[4][kWin], sJ[4][kWin][64];
+  const int wv = threadIdx.x >> 6;
+  int* seqn = sSeq[wv];
+  int* Kw = sK[wv];
+  int* nw_ = sN[wv];
+  int next = 0;  // next position in the wave's sequence
+  auto load = [&](int u) {
+    const int s = w + next * W;
+    int sq = INT_MAX, K = -1, cnt = 0, J = -1;
+    if (s < nb) {
+      K = fwd ? s : nb - 1 - s;
+      const int e0 = ptr[K], e1 = ptr[K + 1];
+      sq = next;
+      cnt = e1 - e0;
+      J = e0 + lane < e1 ? adj[e0 + lane] : -1;
     }
+    if (lane == 0) {
+      seqn[u] = sq;
+      Kw[u] = K;
+      nw_[u] = cnt;
+    }
+    sJ[wv][u][lane] = J;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    ++next;
+  };
+  for (int u = 0; u < kWin; ++u) load(u);
+  unsigned long long t0 = wall_clock64();
+  while (true) {
+    int low = INT_MAX;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) l = max(l, __shfl_xor(l, o, 64));
-    if (lane == 0) __hip_atomic_store(&lev[K], l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    wmax = max(wmax, l);
+    for (int u = 0; u < kWin; ++u) low = min(low, seqn[u]);
+    if (low == INT_MAX) break;
+    bool progressed = false;
+#pragma unroll
+    for (int u = 0; u < kWin; ++u) {
+      if (Kw[u] < 0) continue;
+      int l = 0;
+      if (nw_[u] <= 64) {
+        const int J = sJ[wv][u][lane];
+        const int v = J >= 0 ? __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        if (!__all(v >= 0)) continue;
+        if (J >= 0) l = v + 1;
+      } else {
+        if (seqn[u] != low) continue;
+        const int K = Kw[u];
+        const int e0 = ptr[K], e1 = ptr[K + 1];
+        for (int e = e0; e < e1; e += 64) {
+          const int J = e + lane < e1 ? adj[e + lane] : -1;
+          int v = J >= 0 ? __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+          const unsigned long long tb = wall_clock64();
+          while (!__all(v >= 0)) {
+            if (wall_clock64() - tb > wait_ticks ||
+                __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+              if (lane == 0) atomicExch(err, 1);
+              return;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            if (v < 0) v = __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          if (J >= 0) l = max(l, v + 1);
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) l = max(l, __shfl_xor(l, o, 64));
+      if (lane == 0) __hip_atomic_store(&lev[Kw[u]], l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      wmax = max(wmax, l);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      load(u);
+      progressed = true;
+    }
+    if (progressed) {
+      t0 = wall_clock64();
+    } else {
+      if (wall_clock64() - t0 > wait_ticks ||
+          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        if (lane == 0) atomicExch(err, 1);
+        return;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
   }
   if (lane == 0) atomicMax(&top[fwd ? 0 : 1], wmax);
 }
