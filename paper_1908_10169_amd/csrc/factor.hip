@@ -1570,9 +1570,20 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   const bool rank_sort = nrow <= 256 && ncol <= 256;
   if (!rank_sort && (q + p2r > kCandCap || p2c > kCandCap)) return kFastFallback;
   if (rank_sort) {
+    const int* srcR = tmpR;
+    const int* srcC = tmpC;
+    if (kG) {
+      // the lists sit in global scratch: rank them from LDS (the candidate
+      // hash is no longer needed)
+      for (int t = tid; t < nrow; t += nt) s.hash[t] = tmpR[t];
+      for (int t = tid; t < ncol; t += nt) s.hash[256 + t] = tmpC[t];
+      __syncthreads();
+      srcR = s.hash;
+      srcC = s.hash + 256;
+    }
     for (int t = tid; t < nrow + ncol; t += nt) {
       const bool row = t < nrow;
-      const int* src = row ? tmpR : tmpC;
+      const int* src = row ? srcR : srcC;
       const int m = row ? nrow : ncol, i = row ? t : t - nrow;
       const int v = src[i];
       int r = 0;
