@@ -33,6 +33,10 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="cd3d_64_b4")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--ordering", choices=["caller", "project"], default="caller",
+                   help="caller: the workload's geometric nested dissection as pre_perm, groups "
+                        "in that order; project: the library's nested dissection of the "
+                        "compressed graph (no cpu_baseline)")
     p.add_argument("--aggregation", type=int, default=-1,
                    help="1/0 forces progressive aggregation on/off (default: library default)")
     p.add_argument("--update-precision", choices=["f64", "f32", "bf16"], default="f64",
@@ -75,12 +79,14 @@ def main():
     w = mg.workload(args.workload)
     a = w.a
     prec = {"f64": bilu.PREC_F64, "f32": bilu.PREC_F32, "bf16": bilu.PREC_BF16}[args.update_precision]
-    opts = dict(ordering=bilu.ORDER_NATURAL, collect_timing=1, update_precision=prec)
+    project = args.ordering == "project"
+    opts = dict(ordering=bilu.ORDER_ND if project else bilu.ORDER_NATURAL, collect_timing=1,
+                update_precision=prec)
     agg = AGGREGATION_DEFAULT if args.aggregation < 0 else bool(args.aggregation)
     opts["use_aggregation"] = agg
     h = bilu.Bilu(**opts)
     t0 = time.perf_counter()
-    h.analyze(a, pre_perm=w.perm)
+    h.analyze(a, pre_perm=None if project else w.perm)
     t_analyze = time.perf_counter() - t0
     b_host = a.matvec(np.ones(a.n))
     b = torch.from_numpy(b_host).cuda()
@@ -161,7 +167,9 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": w.name, "n": a.n, "nnz": a.nnz, "tau": w.tau, "restart": restart,
-            "rtol": rtol, "ordering": "geometric nested dissection (caller permutation)",
+            "rtol": rtol,
+            "ordering": "nested dissection of the compressed graph (library)" if project
+            else "geometric nested dissection (caller permutation)",
             "update_precision": args.update_precision, "aggregation": agg,
             "parallelism": "single GPU",
         },
@@ -189,7 +197,7 @@ def main():
                    "dependency_depth": st["factor_levels"],
                    "apply_levels": [st["apply_levels_fwd"], st["apply_levels_bwd"]]},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not project:
         out["cpu_baseline"] = cpu_baseline(w, agg, restart, rtol)
     print(json.dumps(out), flush=True)
 
