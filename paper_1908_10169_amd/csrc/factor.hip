@@ -36,6 +36,8 @@
 #include <cmath>
 #include <numeric>
 
+#include <hipcub/hipcub.hpp>
+
 #include "internal.h"
 #include "wg.h"
 
@@ -2052,9 +2054,32 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   return kFastDone;
 }
 
-// Worker: queue positions blockIdx.x, blockIdx.x + gridDim.x, ... (the
-// launch is cooperative: all workers are resident).  Position p holds the
-// p-th block to become ready; the workgroup waits until it is filled.
+// The next seeded block for the calling workgroup, or -1 when they are all
+// taken.  The counter moves only while seeded blocks are left, so it stays
+// within the seeded count (misc[28]) plus the number of workers.
+__device__ __forceinline__ int take_seeded(const FlowArgs& d, Lds& s) {
+  if (threadIdx.x == 0) {
+    const int L = s.misc[28];
+    const int li = __hip_atomic_load(d.leaf_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < L
+                       ? atomicAdd(d.leaf_head, 1)
+                       : L;
+    s.misc[27] =
+        li < L ? __hip_atomic_load(&d.queue[li], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
+  }
+  __syncthreads();
+  const int KS = s.misc[27];
+  __syncthreads();
+  return KS;
+}
+
+// Worker.  The blocks that nothing can update are seeded at queue positions
+// [0, L) before the launch; any worker that would otherwise wait takes the
+// next of them from a shared counter.  Positions L + blockIdx.x,
+// L + blockIdx.x + gridDim.x, ... (filled in the order blocks become ready
+// during the sweep) belong to this worker, which waits for each in turn
+// (the launch is cooperative: all workers are resident).  So a block made
+// ready during the sweep waits at most for its worker's current block, not
+// behind the seeded ones.
 // One instance per update precision (0 FP64, 1 FP32, 2 BF16): the constant
 // removes the other precisions' code from the instance that runs.
 template <int kPrec>
@@ -2070,12 +2095,21 @@ __global__ void __launch_bounds__(kThreads, 2) factor_worker_kernel(FactorArgs a
     s.acc_depth = 0;
   }
   __syncthreads();
-  int next = -1;  // this worker's next block when already known
-  for (int pos = blockIdx.x; pos < a.nb; pos += gridDim.x) {
-    const unsigned long long t0 = wall_clock64();
-    int K = next;  // uniform: read from LDS after a barrier
-    if (K < 0) {
-      while (true) {
+  // the seeded count, kept in LDS (misc[28]) to spare registers
+  if (threadIdx.x == 0)
+    s.misc[28] = __hip_atomic_load(d.nleaves, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  int next = -1;  // the block at position pos when already known
+  int pos = s.misc[28] + blockIdx.x;
+  while (true) {
+    // pick the next block: the one at this worker's position, or a seeded
+    // one while that position is still empty or once the positions are done
+    int K = -1, next_pos = a.nb;
+    if (pos < a.nb) {
+      const unsigned long long t0 = wall_clock64();
+      K = next;  // uniform: read from LDS after a barrier
+      bool seeded = false;
+      while (K < 0) {
         K = __hip_atomic_load(&d.queue[pos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int stop = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
                          wall_clock64() - t0 > d.wait_ticks;
@@ -2084,21 +2118,37 @@ __global__ void __launch_bounds__(kThreads, 2) factor_worker_kernel(FactorArgs a
           return;
         }
         if (__syncthreads_and(K >= 0)) break;
+        K = take_seeded(d, s);
+        if (K >= 0) {
+          seeded = true;
+          break;
+        }
         __builtin_amdgcn_s_sleep(2);
       }
+      if (seeded) {
+        next_pos = pos;  // still this worker's position
+      } else {
+        next_pos = pos + gridDim.x;
+        pos = next_pos;
+      }
+    } else {
+      K = take_seeded(d, s);
+      if (K < 0) break;
     }
+    // the block; next is the block at queue position next_pos if it is
+    // already there, else -1
     wg_acquire_agent();
     if (threadIdx.x == 0) {
       trace_at(d, K, 1, wall_clock64());
       trace_at(d, K, 7, (unsigned long long)blockIdx.x);
     }
     if (threadIdx.x == 0) s.misc[25] = -1;
-    const int np_ = pos + gridDim.x;
     int r = kFastFallback;
-    if (a.fast_path == 1) r = factor_block_fast<false>(a, d, K, s, s_dyn, nullptr, np_);
+    if (a.fast_path == 1) r = factor_block_fast<false>(a, d, K, s, s_dyn, nullptr, next_pos);
     if (r == kFastBig || a.fast_path == 2) {
       __syncthreads();
-      r = factor_block_fast<true>(a, d, K, s, s_dyn, a.scratch + (int64_t)slot * a.slot_doubles, np_);
+      r = factor_block_fast<true>(a, d, K, s, s_dyn, a.scratch + (int64_t)slot * a.slot_doubles,
+                                  next_pos);
     }
     if (r == kFastFallback) {
       __syncthreads();
@@ -2106,7 +2156,7 @@ __global__ void __launch_bounds__(kThreads, 2) factor_worker_kernel(FactorArgs a
     }
     __syncthreads();
     next = s.misc[25];
-    __syncthreads();  // s.misc[25] is reset by the next round
+    __syncthreads();  // s.misc[25] is reset by the next block
   }
   if (threadIdx.x == 0) {
     atomicAdd(a.flops, s.acc_flops);
@@ -2147,12 +2197,14 @@ __global__ void __launch_bounds__(256) static_pending(int n, const int64_t* rp, 
   if (i < n && sub == 0 && c) atomicAdd(&pending[K], c);
 }
 
-// Blocks that nothing can update start in the ready queue.
-__global__ void seed_queue(int nb, const int* pending, int* enq, int* queue, int* tail) {
+// Blocks that nothing can update start in the ready queue: flagged here,
+// listed in ascending order by a device select.
+__global__ void seed_flags(int nb, const int* pending, int* enq, unsigned char* flag) {
   const int K = blockIdx.x * blockDim.x + threadIdx.x;
-  if (K >= nb || pending[K] != 0) return;
-  enq[K] = 1;
-  queue[atomicAdd(tail, 1)] = K;
+  if (K >= nb) return;
+  const bool seed = pending[K] == 0;
+  flag[K] = seed ? 1 : 0;
+  if (seed) enq[K] = 1;
 }
 
 }  // namespace
@@ -2229,7 +2281,7 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
   CK(h->d_tcoff.alloc(nb));
   CK(h->d_ntr.alloc(nb));
   CK(h->d_ntc.alloc(nb));
-  CK(h->d_flow.alloc(5 * nb + 2));
+  CK(h->d_flow.alloc(5 * nb + 4));
   CK(hipMemcpyAsync(h->d_bstart.p, bs.data(), (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(h->d_doff.p, h->doff_h.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
   {
@@ -2283,15 +2335,31 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     CK(hipMemsetAsync(h->d_row_ovf.p, 0xff, nb * sizeof(int32_t), st));
     CK(hipMemsetAsync(h->d_status.p, 0, 8 * sizeof(int), st));
     CK(hipMemsetAsync(h->d_counters.p, 0, 4 * sizeof(unsigned long long), st));
-    // pending, started, enqueued, depth = 0; queue = -1; tail, max depth = 0
+    // pending, started, enqueued, depth = 0; queue = -1; tail, max depth,
+    // seeded-block counter, seeded count = 0
     CK(hipMemsetAsync(h->d_flow.p, 0, 4 * nb * sizeof(int), st));
     CK(hipMemsetAsync(h->d_flow.p + 4 * nb, 0xff, nb * sizeof(int), st));
-    CK(hipMemsetAsync(h->d_flow.p + 5 * nb, 0, 2 * sizeof(int), st));
+    CK(hipMemsetAsync(h->d_flow.p + 5 * nb, 0, 4 * sizeof(int), st));
     static_pending<<<(unsigned)((n + 15) / 16), 256, 0, st>>>(
         (int)n, h->d_rp.p, h->d_bci.p, h->d_cp.p, h->d_bri.p, h->d_blockof.p, h->d_flow.p);
-    seed_queue<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(
-        (int)nb, h->d_flow.p, h->d_flow.p + 2 * nb, h->d_flow.p + 4 * nb, h->d_flow.p + 5 * nb);
-    CK(hipGetLastError());
+    {
+      DevArray<unsigned char> flag;
+      CK(flag.alloc(nb));
+      seed_flags<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>((int)nb, h->d_flow.p,
+                                                               h->d_flow.p + 2 * nb, flag.p);
+      CK(hipGetLastError());
+      hipcub::CountingInputIterator<int> ids(0);
+      size_t bytes = 0;
+      CK(hipcub::DeviceSelect::Flagged(nullptr, bytes, ids, flag.p, h->d_flow.p + 4 * nb,
+                                       h->d_flow.p + 5 * nb, (int)nb, st));
+      CK(h->d_scan_tmp.alloc(bytes + 1));
+      CK(hipcub::DeviceSelect::Flagged(h->d_scan_tmp.p, bytes, ids, flag.p, h->d_flow.p + 4 * nb,
+                                       h->d_flow.p + 5 * nb, (int)nb, st));
+      CK(hipStreamSynchronize(st));  // the flags end here
+    }
+    // the seeded count: the tail before any block has run
+    CK(hipMemcpyAsync(h->d_flow.p + 5 * nb + 3, h->d_flow.p + 5 * nb, sizeof(int),
+                      hipMemcpyDeviceToDevice, st));
     FactorArgs a{};
     a.n = (int)n;
     a.nb = (int)nb;
@@ -2371,6 +2439,8 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     d.queue = h->d_flow.p + 4 * nb;
     d.tail = h->d_flow.p + 5 * nb;
     d.max_depth = h->d_flow.p + 5 * nb + 1;
+    d.leaf_head = h->d_flow.p + 5 * nb + 2;
+    d.nleaves = h->d_flow.p + 5 * nb + 3;
     d.wait_ticks = h->wait_ticks;
     d.trace = nullptr;
     if (h->opt.collect_timing >= 2) {

@@ -158,6 +158,8 @@ struct FlowArgs {
   int* enq;                // block pushed to the ready queue
   int* queue;              // ready queue, filled in readiness order (-1 = empty)
   int* tail;               // next free queue position
+  int* leaf_head;          // next of the seeded positions [0, *nleaves) to take
+  const int* nleaves;      // blocks seeded before the launch
   unsigned long long wait_ticks;
   // optional per-block trace (kTraceFields per block, wall-clock ticks):
   // pushed, popped, updater set built, candidates built, done, the block
