@@ -109,3 +109,33 @@ def test_invalid_input_is_rejected(bad):
     with pytest.raises(bilu.BiluError) as e:
         bilu.preprocess(b, 1e-2, pre_perm=pre)
     assert e.value.status == bilu.BILU_ERR_INVALID
+
+
+def test_geometric_nd_orders():
+    """The workloads' geometric nested dissection is a permutation of the grid
+    nodes in both separator forms, and it is a nested dissection: the last
+    nodes (the top separator plane) split the rest into two groups that no
+    stencil couples (all 27 neighbours)."""
+    dims = (9, 8, 7)
+    n = int(np.prod(dims))
+    coords = np.stack(np.unravel_index(np.arange(n), dims[::-1]), axis=1)[:, ::-1]
+    for sep in (True, False):
+        order = mg.grid_nd_node_order(dims, dissect_separators=sep)
+        assert np.array_equal(np.sort(order), np.arange(n))
+        # top separator: the middle plane of the longest axis, ordered last
+        ax = int(np.argmax(dims))
+        mid = dims[ax] // 2
+        plane = coords[:, ax] == mid
+        k = int(plane.sum())
+        assert np.array_equal(np.sort(order[-k:]), np.flatnonzero(plane))
+        left = set(np.flatnonzero(coords[:, ax] < mid).tolist())
+        first = order[:-k]
+        pos = {v: i for i, v in enumerate(first)}
+        # every node below the plane comes before every node above it
+        above = [pos[v] for v in first if v not in left]
+        below = [pos[v] for v in first if v in left]
+        assert max(below) < min(above)
+    # the two forms differ only inside separators
+    a = mg.grid_nd_node_order(dims, dissect_separators=True)
+    b = mg.grid_nd_node_order(dims, dissect_separators=False)
+    assert not np.array_equal(a, b)
