@@ -1442,8 +1442,10 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   const int tall = total + totu;
   // the column lists of column predecessors and the row lists of row
   // predecessors (one contiguous range of segments) are only searched for
-  // the block's own range, which is read from the heap: they are not staged
-  const int gA = segoff[2 + np], gap = segoff[2 + 2 * np + npr] - gA;
+  // the block's own range: the global variant reads them from the heap and
+  // does not stage them; the LDS variant stages them (searches in LDS are
+  // cheaper than in the heap)
+  const int gA = segoff[2 + np], gap = kG ? segoff[2 + 2 * np + npr] - gA : 0;
   const int tv = tall - gap;
   for (int base = 0; base < tv; base += kBatch * nt) {
     int v[kBatch];
@@ -1500,7 +1502,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     const int* B;
     int na, nb_, ka, kb;
     if (t < np) {
-      A = a.idx_heap + m.coff;         // C: lo, hi
+      A = kG ? a.idx_heap + m.coff : stage + segoff[2 + np + t];  // C: lo, hi
       B = stage + segoff[2 + t];       // R: lo2
       na = m.nc;
       nb_ = m.nr;
@@ -1508,7 +1510,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       kb = f;
     } else {
       const int u = t - np;
-      A = a.idx_heap + m.roff;                   // R: lo, hi
+      A = kG ? a.idx_heap + m.roff : stage + segoff[2 + 2 * np + u];  // R: lo, hi
       B = stage + segoff[2 + 2 * np + npr + u];  // C: lo2
       na = m.nr;
       nb_ = m.nc;
@@ -1675,7 +1677,8 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     for (int e0 = i0 + tid; e0 < i1; e0 += kU * nt) {
       // (1) the predecessor and the (row, column) pair of each term
       // each term's row and column index: one from the staged lists (so),
-      // the one inside K from the heap (ho)
+      // the one inside K (ho) from the heap in the global variant, from the
+      // staged lists in the LDS variant
       int64_t lo[kU], wo[kU], ho[kU];
       int pp[kU], so[kU];
       bool colp[kU];
@@ -1704,13 +1707,13 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
             ri = m.lo2 + w / nc;
             cj = m.lo + w % nc;
             so[u] = segoff[2 + t] + ri;
-            ho[u] = m.coff + cj;
+            ho[u] = kG ? m.coff + cj : (int64_t)segoff[2 + np + t] + cj;
           } else {
             const int nr = m.hi - m.lo;
             ri = m.lo + w % nr;
             cj = m.lo2 + w / nr;
             so[u] = segoff[2 + 2 * np + npr + (t - np)] + cj;
-            ho[u] = m.roff + ri;
+            ho[u] = kG ? m.roff + ri : (int64_t)segoff[2 + 2 * np + (t - np)] + ri;
             colp[u] = false;
           }
           lo[u] = m.loff + (int64_t)ri * m.p;
@@ -1723,7 +1726,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int sv = stage[so[u]];
-        const int hv = a.idx_heap[ho[u]];
+        const int hv = kG ? a.idx_heap[ho[u]] : stage[ho[u]];
         rr[u] = colp[u] ? sv : hv;
         cc[u] = colp[u] ? hv : sv;
       }
