@@ -1227,9 +1227,14 @@ extern "C" {
 
 void orc_fgmres(const orc_handle* h, const double* b, double* x, int restart, double rtol,
                 int maxit, orc_solve_info* info) {
+  orc_fgmres_hist(h, b, x, restart, rtol, maxit, info, nullptr);
+}
+
+void orc_fgmres_hist(const orc_handle* h, const double* b, double* x, int restart, double rtol,
+                     int maxit, orc_solve_info* info, double* resid_history) {
   fgmres(
       h->A, [h](const double* in, double* out) { orc_apply(h, in, out); }, b, x, restart, rtol,
-      maxit, info, nullptr);
+      maxit, info, resid_history);
 }
 
 void orc_fgmres_plain(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* val,
@@ -1328,6 +1333,19 @@ double orc_kept_residual(const orc_handle* h) {
       }
   }
   return std::sqrt(num / den);
+}
+
+// Test hook of the pins, not part of the method: adds delta to the stored
+// value pos of L_K (which = 0, row-major) or W_K (which = 1, column-major) of
+// final block k, so that a pin can show the kept-pattern residual responds
+// to a defect.  Returns 0, or -1 when the position does not exist.
+int orc_plant(orc_handle* h, int which, int64_t k, int64_t pos, double delta) {
+  if (k < 0 || k >= (int64_t)h->live.size()) return -1;
+  Block& B = h->blocks[h->live[k]];
+  std::vector<double>& v = which == 0 ? B.L : B.W;
+  if (which < 0 || which > 1 || pos < 0 || pos >= (int64_t)v.size()) return -1;
+  v[pos] += delta;
+  return 0;
 }
 
 void orc_get_times(const orc_handle* h, double* t3) {

@@ -128,6 +128,10 @@ typedef struct {
  * initial guess on entry. */
 void orc_fgmres(const orc_handle* h, const double* b, double* x, int restart,
                 double rtol, int maxit, orc_solve_info* info);
+/* orc_fgmres that also writes the residual estimate after every Arnoldi
+ * step (maxit entries at most) to resid_history (may be NULL). */
+void orc_fgmres_hist(const orc_handle* h, const double* b, double* x, int restart,
+                     double rtol, int maxit, orc_solve_info* info, double* resid_history);
 /* FGMRES with M = I (unpreconditioned), on any CSR matrix. */
 void orc_fgmres_plain(int64_t n, const int64_t* rowptr, const int32_t* colind,
                       const double* val, const double* b, double* x,
@@ -138,6 +142,10 @@ void orc_fgmres_plain(int64_t n, const int64_t* rowptr, const int32_t* colind,
 double orc_kept_residual(const orc_handle* h);
 /* y = (L S U) x in the permuted numbering. */
 void orc_lsu_matvec(const orc_handle* h, const double* x, double* y);
+
+/* Test hook of the pins (not part of the method): adds delta to stored value
+ * pos of L_K (which 0) or W_K (which 1) of final block k; 0 or -1. */
+int orc_plant(orc_handle* h, int which, int64_t k, int64_t pos, double delta);
 
 /* timings of the last run, seconds: analyze, ilu1t, factor */
 void orc_get_times(const orc_handle* h, double* t3);

@@ -75,12 +75,16 @@ def load():
     lib.orc_get_mergelog.restype = C.c_int64
     lib.orc_apply.argtypes = [vp, _F64P, _F64P]
     lib.orc_fgmres.argtypes = [vp, _F64P, _F64P, C.c_int, C.c_double, C.c_int, C.POINTER(_Info)]
+    lib.orc_fgmres_hist.argtypes = [vp, _F64P, _F64P, C.c_int, C.c_double, C.c_int,
+                                    C.POINTER(_Info), _F64P]
     lib.orc_fgmres_plain.argtypes = [C.c_int64, _I64P, _I32P, _F64P, _F64P, _F64P, C.c_int,
                                      C.c_double, C.c_int, C.POINTER(_Info), _F64P]
     lib.orc_kept_residual.argtypes = [vp]
     lib.orc_kept_residual.restype = C.c_double
     lib.orc_lsu_matvec.argtypes = [vp, _F64P, _F64P]
     lib.orc_get_times.argtypes = [vp, _F64P]
+    lib.orc_plant.argtypes = [vp, C.c_int, C.c_int64, C.c_int64, C.c_double]
+    lib.orc_plant.restype = C.c_int
     _lib = lib
     return lib
 
@@ -239,16 +243,25 @@ class Oracle:
         self._lib.orc_lsu_matvec(self._h, x, y)
         return y
 
-    def fgmres(self, b, x0=None, restart=30, rtol=1e-8, maxit=2000):
+    def fgmres(self, b, x0=None, restart=30, rtol=1e-8, maxit=2000, history=False):
         b = np.ascontiguousarray(b, dtype=np.float64)
         x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
         info = _Info()
-        self._lib.orc_fgmres(self._h, b, x, restart, rtol, maxit, C.byref(info))
-        return x, dict(iterations=info.iterations, restarts=info.restarts,
-                       rel_residual=info.rel_residual, converged=bool(info.converged))
+        hist = np.zeros(max(maxit, 1))
+        self._lib.orc_fgmres_hist(self._h, b, x, restart, rtol, maxit, C.byref(info), hist)
+        out = dict(iterations=info.iterations, restarts=info.restarts,
+                   rel_residual=info.rel_residual, converged=bool(info.converged))
+        if history:
+            return x, out, hist[:info.iterations].copy()
+        return x, out
 
     def kept_residual(self) -> float:
         return self._lib.orc_kept_residual(self._h)
+
+    def plant(self, which: str, block: int, pos: int, delta: float) -> None:
+        """Test hook: add delta to one stored value of L_K ("L") or W_K ("W")."""
+        if self._lib.orc_plant(self._h, {"L": 0, "W": 1}[which], block, pos, delta) != 0:
+            raise IndexError((which, block, pos))
 
     def times(self):
         t = np.zeros(3)

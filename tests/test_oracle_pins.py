@@ -218,21 +218,25 @@ def test_p5_kept_pattern_identity(tau, agg):
 # recomputed densely from the factors (Schur complement of the leading part)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("tau", [2e-1, 3e-2])
-def test_p6_drop_rule(tau):
+@pytest.mark.parametrize("norm", ["inf", "two"])
+def test_p6_drop_rule(tau, norm):
     a = mg.grid2d_random_blocks(8, 2, 3.0, seed=2)
     o = Oracle()
-    assert o.run(a, OracleOptions(tau=tau, use_aggregation=False)) == 0
+    assert o.run(a, OracleOptions(tau=tau, use_aggregation=False,
+                                  drop_norm=0 if norm == "inf" else 1)) == 0
+    rnorm = (lambda X, ax: np.abs(X).max(axis=ax)) if norm == "inf" else \
+        (lambda X, ax: np.sqrt((X * X).sum(axis=ax)))
     L, S, U, f = assemble(o)
     P = permuted_dense(a, f.perm)
     W = S @ U
     n = a.n
-    checked = 0
+    checked = differs = 0
     for k in range(len(f.starts) - 1):
         s, e = f.starts[k], f.starts[k + 1]
         D = f.D[k]
         Cpan = P[e:, s:e] - L[e:, :s] @ W[:s, s:e]
         Lc = Cpan @ D
-        nr = np.abs(Lc).max(axis=1)
+        nr = rnorm(Lc, 1)
         kept = np.zeros(n - e, bool)
         kept[f.R[k] - e] = True
         margin = 1e-12 * max(1.0, np.abs(Lc).max(initial=0))
@@ -241,14 +245,18 @@ def test_p6_drop_rule(tau):
         assert np.allclose(f.L[k], Lc[kept], rtol=1e-11, atol=1e-13)
         Rpan = P[s:e, e:] - L[s:e, :s] @ W[:s, e:]
         Uc = D @ Rpan
-        nc = np.abs(Uc).max(axis=0)
+        nc = rnorm(Uc, 0)
         keptc = np.zeros(n - e, bool)
         keptc[f.C[k] - e] = True
         assert np.all(nc[keptc] > tau - margin)
         assert np.all(nc[~keptc] <= tau + margin)
         assert np.allclose(f.W[k], Rpan[:, keptc], rtol=1e-11, atol=1e-13)
         checked += (~kept).sum() + (~keptc).sum()
+        # kept by the 2-norm although the max-abs norm is below tau
+        differs += int(np.sum(kept & (np.abs(Lc).max(axis=1) <= tau)))
+        differs += int(np.sum(keptc & (np.abs(Uc).max(axis=0) <= tau)))
     assert checked > 0
+    assert (differs > 0) == (norm == "two")
 
 
 # ---------------------------------------------------------------------------
@@ -475,6 +483,134 @@ def test_p13_fgmres_minimal_residual():
         rmin = np.linalg.norm(b - AQ @ y)
         assert hist[j - 1] == pytest.approx(rmin, rel=1e-8)
     assert np.all(np.diff(hist) <= 1e-12 * hist[0])
+
+
+def _krylov_cycle(Op, r, m):
+    """Residuals after 1..m steps of the minimal-residual method from residual
+    r over the Krylov space K_m(Op, r), by dense least squares on an
+    orthonormal basis built by repeated QR; also the coefficient vector in
+    that basis after m steps.  Independent of any Givens/Hessenberg code."""
+    K = np.zeros((len(r), m))
+    v = r / np.linalg.norm(r)
+    for j in range(m):
+        K[:, j] = v
+        Q, _ = np.linalg.qr(K[:, :j + 1])
+        v = Op @ Q[:, j]
+    res = []
+    for j in range(1, m + 1):
+        Q, _ = np.linalg.qr(K[:, :j])
+        y, *_ = np.linalg.lstsq(Op @ Q, r, rcond=None)
+        res.append(np.linalg.norm(r - Op @ (Q @ y)))
+    return np.array(res), Q @ y
+
+
+# ---------------------------------------------------------------------------
+# P13b: restarted FGMRES(m) with M = I.  Every cycle restarts from its own
+# true residual b - A x_c and minimises over K_m(A, r_c); x_{c+1} is the
+# minimiser.  Several full cycles, then a partial one.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m", [2, 3, 5])
+def test_p13_restart_cycles_plain(m):
+    a = mg.random_sparse(70, 0.08, seed=31, diag_shift=0.6)
+    A = a.to_dense()
+    b = np.random.default_rng(5).standard_normal(a.n)
+    cycles = 4
+    maxit = cycles * m + (m - 1 if m > 1 else 0)
+    x_o, info, hist = fgmres_plain(a, b, restart=m, rtol=1e-15, maxit=maxit)
+    assert info["iterations"] == maxit
+    assert info["restarts"] == cycles + (1 if maxit % m else 0)
+    x = np.zeros(a.n)
+    it = 0
+    for c in range(info["restarts"]):
+        steps = min(m, maxit - it)
+        r = b - A @ x
+        res, d = _krylov_cycle(A, r, steps)
+        # the Givens estimate of every step equals the cycle's least-squares
+        # minimum from its own starting residual
+        assert hist[it:it + steps] == pytest.approx(res, rel=1e-7)
+        assert np.all(np.diff(res) <= 1e-12 * res[0])
+        it += steps
+        x = x + d
+        # the next cycle restarts from the true residual of the minimiser
+        assert np.linalg.norm(b - A @ x) == pytest.approx(res[-1], rel=1e-7)
+    assert np.linalg.norm(x_o - x) <= 1e-7 * np.linalg.norm(x)
+    assert info["rel_residual"] == pytest.approx(np.linalg.norm(b - A @ x) / np.linalg.norm(b),
+                                                 rel=1e-6)
+    # restarting stagnates above what unrestarted GMRES reaches in as many steps
+    _, info_full, hist_full = fgmres_plain(a, b, restart=maxit, rtol=1e-15, maxit=maxit)
+    assert info_full["restarts"] == 1
+    assert hist_full[-1] <= hist[-1] * (1 + 1e-9)
+
+
+# ---------------------------------------------------------------------------
+# P13c: restarted FGMRES with the block ILU as (fixed) right preconditioner:
+# cycle c minimises ||r_c - A M^{-1} Q y|| over K_m(A M^{-1}, r_c) and moves x
+# by M^{-1} Q y, with M assembled densely from the factors (as in P12)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("m", [2, 3])
+def test_p13_restart_cycles_preconditioned(m):
+    a = mg.grid2d_random_blocks(8, 3, 3.0, seed=12)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=3e-1, use_aggregation=True)) in (0,)
+    L, S, U, f = assemble(o)
+    Pm = np.eye(a.n)[:, f.perm]
+    Minv = np.linalg.inv(Pm @ (L @ S @ U) @ Pm.T)
+    A = a.to_dense()
+    b = A @ np.ones(a.n)
+    maxit = 4 * m + 1
+    x_o, info, hist = o.fgmres(b, restart=m, rtol=1e-15, maxit=maxit, history=True)
+    assert info["iterations"] == maxit and info["restarts"] == 5
+    x = np.zeros(a.n)
+    it = 0
+    AM = A @ Minv
+    for c in range(info["restarts"]):
+        steps = min(m, maxit - it)
+        r = b - A @ x
+        res, d = _krylov_cycle(AM, r, steps)
+        assert hist[it:it + steps] == pytest.approx(res, rel=1e-6)
+        it += steps
+        x = x + Minv @ d
+    assert np.linalg.norm(x_o - x) <= 1e-6 * np.linalg.norm(x)
+    # and to convergence: several cycles, true residual confirmed
+    x_c, info_c = o.fgmres(b, restart=m, rtol=1e-8, maxit=500)
+    assert info_c["converged"] and info_c["restarts"] >= 2
+    assert np.linalg.norm(b - A @ x_c) <= 1e-8 * np.linalg.norm(b)
+    assert info_c["rel_residual"] == pytest.approx(
+        np.linalg.norm(b - A @ x_c) / np.linalg.norm(b), rel=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# P5b: the kept-pattern residual itself, against a dense computation of
+# ||(L S U - A)_Omega||_F / ||A||_F from the exported factors, also with a
+# defect planted in one stored value (so a zero sum or a wrong Omega fails)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["L", "W"])
+def test_p5_kept_residual_dense(which):
+    a = mg.grid2d_random_blocks(7, 2, 3.0, seed=4)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=5e-2, use_aggregation=False)) == 0
+
+    def dense_kept():
+        L, S, U, f = assemble(o)
+        P = permuted_dense(a, f.perm)
+        omega = np.zeros((a.n, a.n), bool)
+        for k in range(len(f.starts) - 1):
+            s_, e_ = f.starts[k], f.starts[k + 1]
+            omega[s_:e_, s_:e_] = True
+            omega[np.ix_(f.R[k], np.arange(s_, e_))] = True
+            omega[np.ix_(np.arange(s_, e_), f.C[k])] = True
+        E = (L @ S @ U - P)[omega]
+        return np.linalg.norm(E) / np.linalg.norm(a.val), omega, P
+
+    base, omega, P = dense_kept()
+    assert base <= 1e-13 and o.kept_residual() <= 1e-13
+    # Omega is strictly smaller than the full pattern of L S U (dropping)
+    f = o.factors()
+    k = next(k for k in range(len(f.starts) - 1) if (len(f.R[k]) if which == "L" else len(f.C[k])))
+    o.plant(which, k, 0, 1e-3)
+    planted, _, _ = dense_kept()
+    assert planted > 1e-6
+    assert o.kept_residual() == pytest.approx(planted, rel=1e-9)
 
 
 # ---------------------------------------------------------------------------
