@@ -161,6 +161,37 @@ class Factors:
     D: list
 
 
+def _check_tensor(t, name, dtype, numel=None):
+    """Reject what would make a kernel read or write out of bounds: the
+    library takes raw device pointers and cannot check them itself."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {numel}")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a device (cuda) tensor")
+    return t.data_ptr()
+
+
+def _check_vectors(n, *named):
+    """Every (name, tensor) is a contiguous float64 device vector of n
+    entries; outputs (the last one) share no memory with the inputs."""
+    import torch
+    out_name, out = named[-1]
+    for name, t in named[:-1]:
+        if isinstance(t, torch.Tensor) and isinstance(out, torch.Tensor):
+            a0, a1 = t.data_ptr(), t.data_ptr() + t.element_size() * t.numel()
+            b0, b1 = out.data_ptr(), out.data_ptr() + out.element_size() * out.numel()
+            if a0 < b1 and b0 < a1:
+                raise ValueError(f"{out_name} overlaps {name}")
+    return [_check_tensor(t, name, torch.float64, n) for name, t in named]
+
+
 def _stream_ptr(stream):
     if stream is None:
         import torch
@@ -284,6 +315,13 @@ class Bilu:
                                    C.c_void_p(_stream_ptr(None)))
         if st != BILU_OK:
             raise BiluError(st, "bilu_create")
+        import torch
+        _check_tensor(rowptr, "rowptr", torch.int64, n + 1)
+        _check_tensor(colind, "colind", torch.int32)
+        _check_tensor(val, "val", torch.float64, colind.numel())
+        nnz = int(rowptr[-1].item())
+        if nnz != colind.numel():
+            raise ValueError(f"rowptr[n] = {nnz} but colind and val hold {colind.numel()} entries")
         self.n = n
         return self._check(self._lib.bilu_analyze_device(self._h, n, rowptr.data_ptr(),
                                                          colind.data_ptr(), val.data_ptr()),
@@ -296,12 +334,15 @@ class Bilu:
     def refactor(self, tau: float, val):
         """bilu_refactor: val is a float64 device tensor of nnz values in the
         analyzed matrix's entry order."""
+        import torch
+        _check_tensor(val, "val", torch.float64, self.stats()["nnz_a"])
         return self._check(self._lib.bilu_refactor(self._h, tau, val.data_ptr()), "bilu_refactor",
                            ok=(BILU_OK, BILU_WARN_PERTURBED))
 
     def apply(self, x, y):
         """y = M^{-1} x; x, y: torch float64 CUDA tensors of length n."""
-        return self._check(self._lib.bilu_apply(self._h, x.data_ptr(), y.data_ptr()), "bilu_apply")
+        px, py = _check_vectors(self.n, ("x", x), ("y", y))
+        return self._check(self._lib.bilu_apply(self._h, px, py), "bilu_apply")
 
     def trace(self):
         """Per-block factor trace (collect_timing=2): (records x 20 uint64, ticks/s)."""
@@ -318,12 +359,13 @@ class Bilu:
         return self._check(self._lib.bilu_sync(self._h), "bilu_sync")
 
     def spmv(self, x, y):
-        return self._check(self._lib.bilu_spmv(self._h, x.data_ptr(), y.data_ptr()), "bilu_spmv")
+        px, py = _check_vectors(self.n, ("x", x), ("y", y))
+        return self._check(self._lib.bilu_spmv(self._h, px, py), "bilu_spmv")
 
     def fgmres(self, b, x, restart=30, rtol=1e-8, maxit=2000):
+        pb, px = _check_vectors(self.n, ("b", b), ("x", x))
         info = SolveInfo()
-        st = self._lib.bilu_fgmres_solve(self._h, b.data_ptr(), x.data_ptr(), restart, rtol,
-                                         maxit, C.byref(info))
+        st = self._lib.bilu_fgmres_solve(self._h, pb, px, restart, rtol, maxit, C.byref(info))
         self._check(st, "bilu_fgmres_solve", ok=(BILU_OK, BILU_WARN_NOT_CONVERGED))
         return dict(iterations=info.iterations, restarts=info.restarts,
                     rel_residual=info.rel_residual, seconds=info.seconds,

@@ -139,3 +139,26 @@ def test_geometric_nd_orders():
     a = mg.grid_nd_node_order(dims, dissect_separators=True)
     b = mg.grid_nd_node_order(dims, dissect_separators=False)
     assert not np.array_equal(a, b)
+
+
+def test_binding_rejects_bad_tensors():
+    """The binding refuses tensors that would make a kernel access memory out
+    of bounds, before anything reaches the library (raw pointers cross it)."""
+    import torch
+    from paper_1908_10169_amd.bilu import _check_vectors
+    n = 16
+    ok = torch.zeros(n, dtype=torch.float64)
+    cases = [
+        ((("x", torch.zeros(n, dtype=torch.float32)), ("y", ok.clone())), "dtype"),
+        ((("x", torch.zeros(n + 1, dtype=torch.float64)), ("y", ok.clone())), "elements"),
+        ((("x", torch.zeros(2 * n, dtype=torch.float64)[::2]), ("y", ok.clone())), "contiguous"),
+        ((("x", ok), ("y", ok)), "overlaps"),
+        ((("x", torch.zeros(2 * n, dtype=torch.float64)[:n]), ("y", ok.clone())), "device"),
+        ((("x", np.zeros(n)), ("y", ok.clone())), "torch tensor"),
+    ]
+    for named, what in cases:
+        with pytest.raises((ValueError, TypeError), match=what):
+            _check_vectors(n, *named)
+    buf = torch.zeros(2 * n, dtype=torch.float64)
+    with pytest.raises(ValueError, match="overlaps"):
+        _check_vectors(n, ("x", buf[:n]), ("y", buf[n // 2:n // 2 + n]))
