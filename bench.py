@@ -42,6 +42,9 @@ def parse():
     p.add_argument("--update-precision", choices=["f64", "f32", "bf16"], default="f64",
                    help="arithmetic of the Schur-complement updates (pivots, drop test and "
                         "FGMRES are FP64 in every form)")
+    p.add_argument("--apply-path", type=int, default=0, choices=[0, 1, 2],
+                   help="0: dataflow apply, slots in dispatch order; 1: one launch per level; "
+                        "2: dataflow apply, slots by ticket")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                    help="only copy BYTES between two device buffers twice (reference for the "
                         "HBM byte counters of a profiler) and exit")
@@ -81,7 +84,7 @@ def main():
     prec = {"f64": bilu.PREC_F64, "f32": bilu.PREC_F32, "bf16": bilu.PREC_BF16}[args.update_precision]
     project = args.ordering == "project"
     opts = dict(ordering=bilu.ORDER_ND if project else bilu.ORDER_NATURAL, collect_timing=1,
-                update_precision=prec)
+                update_precision=prec, apply_path=args.apply_path)
     agg = AGGREGATION_DEFAULT if args.aggregation < 0 else bool(args.aggregation)
     opts["use_aggregation"] = agg
     h = bilu.Bilu(**opts)

@@ -67,7 +67,9 @@ typedef struct {
   double pivot_eps;      /* pivot |u_jj| <= pivot_eps*max|S| triggers perturbation    */
   int beta_one;          /* 0: beta_j = max|column j| (default); 1: beta_j = 1        */
   int update_precision;  /* bilu_precision of the Schur-complement products (F64)    */
-  size_t heap_bytes;     /* factor heap size; 0 = sized from nnz(A)                  */
+  size_t heap_bytes;     /* factor heap size; 0 = sized from nnz(A).  A heap that    */
+                         /* proves too small grows and the sweep runs again          */
+                         /* (counted in bilu_stats.heap_regrows)                     */
   int collect_timing;    /* 1: time kernels with HIP events on the handle's stream;  */
                          /* 2: also trace every block of the factor kernel           */
   int factor_path;       /* 0 (default): blocks up to 16 wide stage their data in    */
@@ -75,11 +77,15 @@ typedef struct {
                          /* take the general path.  1: every block takes the general */
                          /* path.  2: global staging wherever it fits.  All three   */
                          /* compute identical bits                                   */
-  int apply_path;        /* 0 (default): the apply runs as one dataflow launch; if a */
-                         /* dependency wait times out (a device that cannot keep    */
-                         /* every workgroup resident) the handle switches to 1 for  */
-                         /* good.  1: one launch per dependency level.  Both        */
-                         /* compute identical bits                                   */
+  int apply_path;        /* 0 (default): the apply runs as one dataflow launch, one  */
+                         /* wave per block, blocks taken in workgroup-index order   */
+                         /* (no workgroup has to be resident); a wait that times    */
+                         /* out is counted in apply_faults and reported as          */
+                         /* BILU_ERR_DEVICE by the next bilu_sync or                */
+                         /* bilu_fgmres_solve.  1: one launch per dependency level. */
+                         /* 2: as 0, blocks taken in the order workgroups draw a    */
+                         /* ticket when they start (no assumption on start order;  */
+                         /* slower).  All compute identical bits                     */
   int use_mwm;           /* 1: Sec. 3.1 first: the handle factors D_l A D_r Pi     */
                          /* (bilu_mwm) instead of A; apply, spmv and fgmres still   */
                          /* act on A in its own numbering (default 0)               */
@@ -125,6 +131,9 @@ typedef struct {
    * preparation, [3] factor kernel to completion, [4] aggregation, [5] apply
    * plan, [6] final statistics, [7] unused */
   double t_phase[8];
+  int64_t apply_faults;       /* dataflow applies whose dependency wait timed out     */
+                              /* since analyze (0 unless the device misbehaves)       */
+  int64_t heap_regrows;       /* sweeps of the last factor rerun with a larger heap   */
 } bilu_stats;
 
 /* Library-allocated host copy of the factors (for checking), final blocks. */
@@ -216,7 +225,9 @@ bilu_status bilu_factor_batched(bilu_handle** hs, int count, const double* taus)
 bilu_status bilu_apply(bilu_handle* h, const double* x, double* y);
 
 /* Wait for the handle's stream; BILU_ERR_DEVICE if the runtime reports an
- * error left by asynchronous calls (bilu_apply, bilu_spmv). */
+ * error left by asynchronous calls (bilu_apply, bilu_spmv), or if a
+ * dataflow apply since the last check timed out in a dependency wait (its
+ * output is then invalid; counted in bilu_stats.apply_faults). */
 bilu_status bilu_sync(bilu_handle* h);
 
 /* y = A x with the analyzed matrix (original numbering), device arrays. */

@@ -60,6 +60,7 @@ class Stats(C.Structure):
         ("dev_ms_factor", C.c_double), ("dev_ms_apply", C.c_double), ("dev_ms_spmv", C.c_double),
         ("n_factor_launches", C.c_int64), ("n_apply", C.c_int64), ("n_spmv", C.c_int64),
         ("bytes_factor", C.c_double), ("t_phase", C.c_double * 8),
+        ("apply_faults", C.c_int64), ("heap_regrows", C.c_int64),
     ]
 
 
@@ -257,6 +258,7 @@ class Bilu:
     def __init__(self, options: Options | None = None, stream=None, **kw):
         self._lib = load()
         self._h = C.c_void_p()
+        self.n = None  # set by analyze; before it the library reports BILU_ERR_STATE
         opts = options if options is not None else default_options(**kw)
         self._pre = None
         if kw.get("pre_perm") is not None:

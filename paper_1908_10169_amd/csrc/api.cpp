@@ -135,8 +135,9 @@ bilu_status finish_factor(bilu_handle* h, std::chrono::steady_clock::time_point 
     h->stats.nnz_w = nw;
     h->stats.nnz_d = nd;
     // one apply reads every stored value and row/column index once and
-    // streams x, t (written, then read) and y: 8 B values, 4 B indices
-    h->stats.bytes_apply = 8.0 * double(nl + nw + nd) + 4.0 * double(ir + ic) + 32.0 * h->n;
+    // moves six vectors of n doubles: x and y across the boundary, their
+    // permuted copies, and t (written, then read)
+    h->stats.bytes_apply = 8.0 * double(nl + nw + nd) + 4.0 * double(ir + ic) + 48.0 * h->n;
     // factor: A once (value + index), the L_J/W_J reads of the updates, the
     // written factors and their indices
     h->stats.bytes_factor += 12.0 * double(h->nnz) + 8.0 * double(nl + nw + nd) +
@@ -210,7 +211,7 @@ bilu_status bilu_create(bilu_handle** out, const bilu_options* opt, void* stream
       h->opt.cos_eps > 1.0 || h->opt.ordering < 0 || h->opt.ordering > 1 ||
       h->opt.update_precision < 0 || h->opt.update_precision > 2 || h->opt.drop_norm < 0 ||
       h->opt.drop_norm > 1 || h->opt.factor_path < 0 || h->opt.factor_path > 2 ||
-      h->opt.apply_path < 0 || h->opt.apply_path > 1 || h->opt.use_mwm < 0 || h->opt.use_mwm > 1 ||
+      h->opt.apply_path < 0 || h->opt.apply_path > 2 || h->opt.use_mwm < 0 || h->opt.use_mwm > 1 ||
       h->opt.analyze_path < 0 || h->opt.analyze_path > 1) {
     delete h;
     return BILU_ERR_INVALID;
@@ -559,7 +560,8 @@ bilu_status bilu_sync(bilu_handle* h) {
   if (!h) return BILU_ERR_INVALID;
   hipError_t e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) return hip_check(h, e, "bilu_sync");
-  return BILU_OK;
+  int64_t faults = 0;
+  return apply_faults(h, &faults);
 }
 
 bilu_status bilu_get_stats(const bilu_handle* hc, bilu_stats* st) {

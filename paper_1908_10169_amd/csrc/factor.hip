@@ -26,11 +26,11 @@
 // to the lists of the blocks it really updates.  Every possible updater of
 // K is therefore counted before its own cause is retracted, so pending[K]
 // reaches zero once, when K's predecessor lists are complete.  The
-// retraction that reaches zero pushes K to a queue; a fixed set of
-// co-resident workgroups takes queue positions in turn, so blocks run in
-// readiness order and the critical path is the longest chain of possible
-// updates after dropping, not the elimination-tree height.  Queue waits
-// are bounded in wall-clock time and end on any reported error.
+// retraction that reaches zero pushes K to a queue; running workgroups
+// claim queue positions in ascending order and take the blocks there, so
+// blocks run in readiness order and the critical path is the longest chain
+// of possible updates after dropping, not the elimination-tree height.
+// Queue waits are bounded in wall-clock time and end on any reported error.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -507,6 +507,15 @@ __device__ __forceinline__ int build_candidates(Lds& s, int* out, const int64_t*
 __device__ __forceinline__ void trace_at(const FlowArgs& d, int K, int field,
                                          unsigned long long v) {
   if (d.trace) d.trace[(int64_t)K * kTraceFields + field] = v;
+}
+
+// Claim the next queue position for the calling worker: positions past the
+// seeded ones ([0, L), L in misc[28]) are handed out in ascending order to
+// workers that are running, so the lowest position still waiting for its
+// block always belongs to a worker that will take it; no worker has to be
+// resident for another to make progress.
+__device__ __forceinline__ int claim_position(const FlowArgs& d, const Lds& s) {
+  return s.misc[28] + atomicAdd(d.claim, 1);
 }
 
 // Push block B to the ready queue; who and why are traced.  Only the
@@ -2038,12 +2047,15 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   // retraction
   wg_release_agent();
   const int dK = s.misc[24] + 1;
-  // the worker's next queue position, read while the retractions are in
-  // flight (-1: not filled yet)
-  if (tid == nt - 1)
-    s.misc[25] = next_pos < a.nb
-                     ? __hip_atomic_load(&d.queue[next_pos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                     : -1;
+  // the worker's next queue position (claimed here when next_pos < 0) and
+  // the block already there, read while the retractions are in flight
+  // (misc[25] = -1: not filled yet)
+  if (tid == nt - 1) {
+    const int p = next_pos >= 0 ? next_pos : claim_position(d, s);
+    s.misc[29] = p;
+    s.misc[25] =
+        p < a.nb ? __hip_atomic_load(&d.queue[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : -1;
+  }
   for (int t = tid; t < own_slots; t += nt) {
     const int B = own[t];
     if (B < 0) continue;
@@ -2077,12 +2089,15 @@ __device__ __forceinline__ int take_seeded(const FlowArgs& d, Lds& s) {
 
 // Worker.  The blocks that nothing can update are seeded at queue positions
 // [0, L) before the launch; any worker that would otherwise wait takes the
-// next of them from a shared counter.  Positions L + blockIdx.x,
-// L + blockIdx.x + gridDim.x, ... (filled in the order blocks become ready
-// during the sweep) belong to this worker, which waits for each in turn
-// (the launch is cooperative: all workers are resident).  So a block made
-// ready during the sweep waits at most for its worker's current block, not
-// behind the seeded ones.
+// next of them from a shared counter.  Positions L, L + 1, ... are filled in
+// the order blocks become ready during the sweep; a running worker claims
+// one of them at a time (claim_position), in ascending order, and waits for
+// its block, taking seeded blocks while it is still empty.  A worker claims
+// its next position while its current block retracts its counts, so a
+// block made ready during the sweep waits at most for one worker's current
+// block, not behind the seeded ones.  Every claimed position belongs to a
+// running worker and positions fill in ascending order, so progress needs
+// no worker to be resident: the launch is an ordinary one.
 // One instance per update precision (0 FP64, 1 FP32, 2 BF16): the constant
 // removes the other precisions' code from the instance that runs.
 template <int kPrec>
@@ -2096,18 +2111,17 @@ __global__ void __launch_bounds__(kThreads, 2) factor_worker_kernel(FactorArgs a
     s.hcur[0] = s.hcur[1] = s.hend[0] = s.hend[1] = 0;
     s.acc_flops = s.acc_bytes = 0;
     s.acc_depth = 0;
+    // the seeded count, kept in LDS (misc[28]) to spare registers
+    s.misc[28] = __hip_atomic_load(d.nleaves, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s.misc[29] = claim_position(d, s);
   }
   __syncthreads();
-  // the seeded count, kept in LDS (misc[28]) to spare registers
-  if (threadIdx.x == 0)
-    s.misc[28] = __hip_atomic_load(d.nleaves, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
   int next = -1;  // the block at position pos when already known
-  int pos = s.misc[28] + blockIdx.x;
+  int pos = s.misc[29];
   while (true) {
     // pick the next block: the one at this worker's position, or a seeded
     // one while that position is still empty or once the positions are done
-    int K = -1, next_pos = a.nb;
+    int K = -1, next_pos = -1;  // next_pos < 0: claim a new position
     if (pos < a.nb) {
       const unsigned long long t0 = wall_clock64();
       K = next;  // uniform: read from LDS after a barrier
@@ -2128,24 +2142,23 @@ __global__ void __launch_bounds__(kThreads, 2) factor_worker_kernel(FactorArgs a
         }
         __builtin_amdgcn_s_sleep(2);
       }
-      if (seeded) {
-        next_pos = pos;  // still this worker's position
-      } else {
-        next_pos = pos + gridDim.x;
-        pos = next_pos;
-      }
+      if (seeded) next_pos = pos;  // still this worker's position
     } else {
       K = take_seeded(d, s);
       if (K < 0) break;
+      next_pos = pos;  // no position left to claim
     }
-    // the block; next is the block at queue position next_pos if it is
+    // the block; next is the block at the worker's next position if it is
     // already there, else -1
     wg_acquire_agent();
     if (threadIdx.x == 0) {
       trace_at(d, K, 1, wall_clock64());
       trace_at(d, K, 7, (unsigned long long)blockIdx.x);
     }
-    if (threadIdx.x == 0) s.misc[25] = -1;
+    if (threadIdx.x == 0) {
+      s.misc[25] = -1;
+      s.misc[29] = -1;  // set by the fast path when it claims or reads ahead
+    }
     int r = kFastFallback;
     if (a.fast_path == 1) r = factor_block_fast<false>(a, d, K, s, s_dyn, nullptr, next_pos);
     if (r == kFastBig || a.fast_path == 2) {
@@ -2158,8 +2171,16 @@ __global__ void __launch_bounds__(kThreads, 2) factor_worker_kernel(FactorArgs a
       factor_block(a, d, K, slot, s, s_dyn);
     }
     __syncthreads();
+    // the next position: read ahead by the fast path, else kept (seeded
+    // block, or none left) or claimed now
+    if (threadIdx.x == 0 && s.misc[29] < 0) {
+      s.misc[29] = next_pos >= 0 ? next_pos : claim_position(d, s);
+      s.misc[25] = -1;
+    }
+    __syncthreads();
     next = s.misc[25];
-    __syncthreads();  // s.misc[25] is reset by the next block
+    pos = s.misc[29];
+    __syncthreads();  // s.misc[25] and s.misc[29] are reset by the next block
   }
   if (threadIdx.x == 0) {
     atomicAdd(a.flops, s.acc_flops);
@@ -2243,6 +2264,7 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
                          const std::vector<double>* alpha_blk) {
   using clk = std::chrono::steady_clock;
   auto t1 = clk::now();
+  h->stats.heap_regrows = 0;
   const int64_t n = h->n;
   const std::vector<int32_t>& bs = h->bstart0;
   const int64_t nb = (int64_t)bs.size() - 1;
@@ -2284,7 +2306,7 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
   CK(h->d_tcoff.alloc(nb));
   CK(h->d_ntr.alloc(nb));
   CK(h->d_ntc.alloc(nb));
-  CK(h->d_flow.alloc(5 * nb + 4));
+  CK(h->d_flow.alloc(5 * nb + 8));
   CK(hipMemcpyAsync(h->d_bstart.p, bs.data(), (nb + 1) * sizeof(int32_t), hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(h->d_doff.p, h->doff_h.data(), (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, st));
   {
@@ -2301,8 +2323,8 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
   int64_t val_cap = h->opt.heap_bytes ? (int64_t)(h->opt.heap_bytes / sizeof(double))
                                       : std::max<int64_t>(1 << 20, 4 * h->nnz);
   int64_t idx_cap = std::max<int64_t>(1 << 20, 2 * h->nnz);
-  // workers: as many workgroups as can be resident at once (cooperative
-  // launch); each owns one scratch slot
+  // workers: as many workgroups as can be resident at once (more would only
+  // start when others end); each owns one scratch slot
   const size_t dyn = maxq <= kLdsPivotWidth ? 2 * sizeof(double) * maxq * maxq : 0;
   int dev = 0, cus = 0, per_cu = 0;
   CK(hipGetDevice(&dev));
@@ -2327,7 +2349,9 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
   }
   auto t2 = clk::now();
   h->stats.t_phase[2] = std::chrono::duration<double>(t2 - t1).count();
-  for (int attempt = 0; attempt < 4; ++attempt) {
+  // a heap or overflow pool that proves too small grows, and the sweep runs
+  // again from the start
+  for (int attempt = 0; attempt < 16; ++attempt) {
     if ((int64_t)h->d_val_heap.n < val_cap) CK(h->d_val_heap.alloc(val_cap));
     CK(h->d_ovf_j.alloc(ovf_cap));
     CK(h->d_ovf_next.alloc(ovf_cap));
@@ -2339,10 +2363,10 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     CK(hipMemsetAsync(h->d_status.p, 0, 8 * sizeof(int), st));
     CK(hipMemsetAsync(h->d_counters.p, 0, 4 * sizeof(unsigned long long), st));
     // pending, started, enqueued, depth = 0; queue = -1; tail, max depth,
-    // seeded-block counter, seeded count = 0
+    // seeded-block counter, seeded count, claimed positions = 0
     CK(hipMemsetAsync(h->d_flow.p, 0, 4 * nb * sizeof(int), st));
     CK(hipMemsetAsync(h->d_flow.p + 4 * nb, 0xff, nb * sizeof(int), st));
-    CK(hipMemsetAsync(h->d_flow.p + 5 * nb, 0, 4 * sizeof(int), st));
+    CK(hipMemsetAsync(h->d_flow.p + 5 * nb, 0, 8 * sizeof(int), st));
     static_pending<<<(unsigned)((n + 15) / 16), 256, 0, st>>>(
         (int)n, h->d_rp.p, h->d_bci.p, h->d_cp.p, h->d_bri.p, h->d_blockof.p, h->d_flow.p);
     {
@@ -2444,6 +2468,7 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     d.max_depth = h->d_flow.p + 5 * nb + 1;
     d.leaf_head = h->d_flow.p + 5 * nb + 2;
     d.nleaves = h->d_flow.p + 5 * nb + 3;
+    d.claim = h->d_flow.p + 5 * nb + 4;
     d.wait_ticks = h->wait_ticks;
     d.trace = nullptr;
     if (h->opt.collect_timing >= 2) {
@@ -2457,9 +2482,10 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
       e1 = h->ev_get();
       if (e0) (void)hipEventRecord(e0, st);
     }
+    // an ordinary launch: workers claim queue positions as they run, so
+    // none relies on another being resident
     void* kargs[] = {&a, &d};
-    CK(hipLaunchCooperativeKernel(worker,
-                                  dim3((unsigned)workers), dim3(kThreads), kargs, dyn, st));
+    CK(hipLaunchKernel(worker, dim3((unsigned)workers), dim3(kThreads), kargs, dyn, st));
     if (h->opt.collect_timing) {
       if (e1) (void)hipEventRecord(e1, st);
       h->ev_record(0, e0, e1);
@@ -2474,8 +2500,9 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     CK(hipMemcpyAsync(&max_depth, h->d_flow.p + 5 * nb + 1, sizeof(int), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
     if (status[0] == kDevHeapOverflow) {
-      val_cap = std::max<int64_t>(val_cap * 2, (int64_t)ctr[1] * 2);
-      idx_cap = std::max<int64_t>(idx_cap * 2, (int64_t)ctr[0] * 2);
+      val_cap = std::max<int64_t>(val_cap * 4, (int64_t)ctr[1] * 2);
+      idx_cap = std::max<int64_t>(idx_cap * 4, (int64_t)ctr[0] * 2);
+      ++h->stats.heap_regrows;
       continue;
     }
     if (status[0] == kDevListOverflow && ovf_cap < INT32_MAX / 4) {

@@ -145,6 +145,8 @@ bilu_status fgmres(bilu_handle* h, const double* b_orig, double* x_orig, int m, 
   }
   launch_scatter(st, n, h->perm_col(), h->sr(), x, x_orig);
   if (hipStreamSynchronize(st) != hipSuccess) return fail(h, BILU_ERR_DEVICE, "solver: device error");
+  int64_t faults = 0;
+  if (apply_faults(h, &faults) != BILU_OK) return BILU_ERR_DEVICE;
   if (info) {
     info->iterations = it;
     info->restarts = cycles;

@@ -160,6 +160,7 @@ struct FlowArgs {
   int* tail;               // next free queue position
   int* leaf_head;          // next of the seeded positions [0, *nleaves) to take
   const int* nleaves;      // blocks seeded before the launch
+  int* claim;              // positions past the seeded ones claimed so far
   unsigned long long wait_ticks;
   // optional per-block trace (kTraceFields per block, wall-clock ticks):
   // pushed, popped, updater set built, candidates built, done, the block
@@ -288,9 +289,7 @@ struct bilu_handle {
   bilu::DevArray<double> lr_val;
   bilu::DevArray<int32_t> lev_f, lev_b;          // blocks by forward / backward level
   bilu::DevArray<int2> lev_f_fq;                 // first row and width of lev_f's blocks
-  bilu::DevArray<int> d_apply_err;              // dataflow apply: a wait timed out
-  int64_t apply_groups = 1;                      // its resident workgroups
-  bool apply_by_levels = false;                  // the dataflow apply timed out once
+  bilu::DevArray<int> d_apply_err;              // dataflow apply: wait words, ticket, fault count
   bilu::DevArray<unsigned char> d_scan_tmp;      // device-scan workspace
   std::vector<int32_t> lev_f_ptr, lev_b_ptr;
 
@@ -366,6 +365,9 @@ bilu_status build_apply_plan(bilu_handle* h);
 bilu_status mwm_host(int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
                      int64_t* sigma, double* dl, double* dr, std::string* why);
 bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t);
+// Dataflow applies whose waits timed out since the last call (synchronizes
+// the handle's stream; BILU_ERR_DEVICE when *count > 0).
+bilu_status apply_faults(bilu_handle* h, int64_t* count);
 bilu_status spmv_permuted(bilu_handle* h, const double* x, double* y);
 // y[i] = x[perm[i]] (times scale[i] when given); scatter: y[perm[i]] = x[i]
 // (times scale[i])

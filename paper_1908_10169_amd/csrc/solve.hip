@@ -110,120 +110,55 @@ __global__ void __launch_bounds__(64) bw_fill(FactorView f, const int32_t* ptr, 
 
 // Dependency levels of the apply: level(K) = 1 + the largest level of the
 // blocks K depends on (0 without any); forward over fw lists (J < K),
-// backward over bw lists (B > K).  The first half of the waves takes the
-// forward direction, the rest the backward one; wave w handles blocks
-// w, w + W, ... in dependency order (ascending forward, descending
-// backward), so the lowest unfinished block always has its dependencies
-// done and, with every wave resident (cooperative launch), each wait ends.
-// Waits are bounded; a timeout sets *err.  Levels start at -1; top[0] and
-// top[1] receive the largest level of each direction (one atomic per wave).
+// backward over bw lists (B > K).  One wave per block: slots 0..nb-1 are the
+// forward blocks in ascending order, slots nb..2nb-1 the backward blocks in
+// descending order, so every dependency of a slot sits at a lower slot.
+// Workgroup g runs slots 4g..4g+3, g its index (the hardware starts a
+// launch's workgroups in index order) or, with ticket, the order in which
+// workgroups took a ticket when they started.  Either way every workgroup
+// holding a lower slot has started before the one holding the lowest
+// unfinished slot, so that slot's wave is running with its dependencies
+// done: the launch needs no workgroup to be resident for another to make
+// progress.  Waits are bounded; a timeout sets *err.  Levels start at -1.
 __global__ void __launch_bounds__(256) apply_levels(int nb, const int32_t* fptr, const int32_t* fj,
                                                     const int32_t* bptr, const int32_t* bb, int* lf,
-                                                    int* lb, int* top, int* err,
+                                                    int* lb, int* err, int* ticket,
                                                     unsigned long long wait_ticks) {
+  __shared__ int s_id;
+  int id = blockIdx.x;
+  if (ticket) {
+    if (threadIdx.x == 0) s_id = atomicAdd(ticket, 1);
+    __syncthreads();
+    id = s_id;
+  }
   const int lane = threadIdx.x & 63;
-  const int wave = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
-  const int nw = (int)((gridDim.x * (unsigned)blockDim.x) >> 6);
-  const int half = nw >> 1;
-  const bool fwd = wave < half;
-  const int w = fwd ? wave : wave - half, W = fwd ? half : nw - half;
+  const int s = id * 4 + (int)(threadIdx.x >> 6);
+  if (s >= 2 * nb) return;  // no workgroup barrier below
+  const bool fwd = s < nb;
+  const int K = fwd ? s : 2 * nb - 1 - s;
   const int32_t* ptr = fwd ? fptr : bptr;
   const int32_t* adj = fwd ? fj : bb;
   int* lev = fwd ? lf : lb;
-  int wmax = 0;
-  // A window of kWin of the wave's blocks (w, w + W, ... in turn): each
-  // round polls every block of the window once and finishes those whose
-  // dependencies are all known, so a block that waits does not hold up the
-  // ones behind it.  A block with more than 64 dependencies is finished
-  // only as the wave's lowest unfinished block, with blocking waits (its
-  // dependencies then all sit at lower positions of other waves).
-  constexpr int kWin = 4;
-  // window state in LDS (indexed by entry): position, block, dependency
-  // count, and each lane's first dependency
-  __shared__ int sSeq[4][kWin], sK[4][kWin], sN[4][kWin], sJ[4][kWin][64];
-  const int wv = threadIdx.x >> 6;
-  int* seqn = sSeq[wv];
-  int* Kw = sK[wv];
-  int* nw_ = sN[wv];
-  int next = 0;  // next position in the wave's sequence
-  auto load = [&](int u) {
-    const int s = w + next * W;
-    int sq = INT_MAX, K = -1, cnt = 0, J = -1;
-    if (s < nb) {
-      K = fwd ? s : nb - 1 - s;
-      const int e0 = ptr[K], e1 = ptr[K + 1];
-      sq = next;
-      cnt = e1 - e0;
-      J = e0 + lane < e1 ? adj[e0 + lane] : -1;
-    }
-    if (lane == 0) {
-      seqn[u] = sq;
-      Kw[u] = K;
-      nw_[u] = cnt;
-    }
-    sJ[wv][u][lane] = J;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    ++next;
-  };
-  for (int u = 0; u < kWin; ++u) load(u);
-  unsigned long long t0 = wall_clock64();
-  while (true) {
-    int low = INT_MAX;
-#pragma unroll
-    for (int u = 0; u < kWin; ++u) low = min(low, seqn[u]);
-    if (low == INT_MAX) break;
-    bool progressed = false;
-#pragma unroll
-    for (int u = 0; u < kWin; ++u) {
-      if (Kw[u] < 0) continue;
-      int l = 0;
-      if (nw_[u] <= 64) {
-        const int J = sJ[wv][u][lane];
-        const int v = J >= 0 ? __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
-        if (!__all(v >= 0)) continue;
-        if (J >= 0) l = v + 1;
-      } else {
-        if (seqn[u] != low) continue;
-        const int K = Kw[u];
-        const int e0 = ptr[K], e1 = ptr[K + 1];
-        for (int e = e0; e < e1; e += 64) {
-          const int J = e + lane < e1 ? adj[e + lane] : -1;
-          int v = J >= 0 ? __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
-          const unsigned long long tb = wall_clock64();
-          while (!__all(v >= 0)) {
-            if (wall_clock64() - tb > wait_ticks ||
-                __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-              if (lane == 0) atomicExch(err, 1);
-              return;
-            }
-            __builtin_amdgcn_s_sleep(1);
-            if (v < 0) v = __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
-          if (J >= 0) l = max(l, v + 1);
-        }
-      }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) l = max(l, __shfl_xor(l, o, 64));
-      if (lane == 0) __hip_atomic_store(&lev[Kw[u]], l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      wmax = max(wmax, l);
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      load(u);
-      progressed = true;
-    }
-    if (progressed) {
-      t0 = wall_clock64();
-    } else {
+  const int e0 = ptr[K], e1 = ptr[K + 1];
+  int l = 0;
+  const unsigned long long t0 = wall_clock64();
+  for (int e = e0; e < e1; e += 64) {
+    const int J = e + lane < e1 ? adj[e + lane] : -1;
+    int v = J >= 0 ? __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+    while (!__all(v >= 0)) {
       if (wall_clock64() - t0 > wait_ticks ||
           __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
         if (lane == 0) atomicExch(err, 1);
         return;
       }
       __builtin_amdgcn_s_sleep(1);
+      if (v < 0) v = __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    if (J >= 0) l = max(l, v + 1);
   }
-  if (lane == 0) atomicMax(&top[fwd ? 0 : 1], wmax);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) l = max(l, __shfl_xor(l, o, 64));
+  if (lane == 0) __hip_atomic_store(&lev[K], l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // First position of every level in the sorted levels (every level from 0 to
 // the largest one holds a block: a block of level l depends on one of l - 1).
@@ -429,25 +364,26 @@ __global__ void __launch_bounds__(256) backward_level(SweepArgs a, const double*
 }
 
 // ---------------------------------------------------------------------------
-// Dataflow apply: one cooperative launch runs every forward block, then
-// every backward block, in the plan's level order (slots 0..nb-1 forward,
-// nb..2nb-1 backward); wave w takes slots w, w + W, ... in order, every
-// workgroup resident.  A value of t (z) is its own
-// ready mark: both start as kPending, a bit pattern (a signalling NaN) that
-// no arithmetic produces, and a consumer polls the value with device-scope
-// atomic loads until the producer's atomic store replaces it.  Every
-// dependency of a slot sits at a lower slot and a wave finishes its lower
-// slots first, so the lowest unfinished slot always completes and every wait
-// ends; waits are bounded anyway (*err).
+// Dataflow apply: one launch runs every forward block, then every backward
+// block, in the plan's level order (slots 0..nb-1 forward, nb..2nb-1
+// backward), one wave per slot: workgroup g runs slots 4g + wave, g its
+// index (the hardware starts a launch's workgroups in index order) or, with
+// ticketed, its rank in an atomic ticket counter taken when it starts (no
+// assumption on the start order; one atomic on one address per workgroup,
+// several times slower).  A value of t (z) is its own ready mark: both start
+// as kPending, a bit pattern (a signalling NaN) that no arithmetic
+// produces, and a consumer polls the value with device-scope atomic loads
+// until the producer's atomic store replaces it.  Every dependency of a
+// slot sits at a lower slot, and every workgroup holding a lower slot has
+// started before the one holding the lowest unfinished slot, so that slot's
+// inputs are all published and every wait ends, with no workgroup having to
+// be resident for another.  Waits are bounded anyway (err).
 // The arithmetic is that of forward_level and backward_level, in the same
 // order.
 // ---------------------------------------------------------------------------
 // both halves 0x7ff4b11e: a signalling NaN, set with a 32-bit fill
 constexpr unsigned kPendingHalf = 0x7ff4b11eu;
 constexpr unsigned long long kPending = ((unsigned long long)kPendingHalf << 32) | kPendingHalf;
-// LDS requested (unused) per workgroup so that at most six share a CU: every
-// workgroup is then resident, which the static slot order relies on
-constexpr size_t kFlowLds = 22 * 1024;
 
 struct FlowApplyArgs {
   FactorView f;
@@ -460,7 +396,9 @@ struct FlowApplyArgs {
   const double* x;
   unsigned long long* t;
   unsigned long long* z;
-  int* err;             // [0] set on a timeout; [1] slot, [2] side, [3] awaited index
+  int* err;             // [0] set on a timeout; [1] slot, [2] side, [3] awaited index;
+                        // [4] the ticket counter
+  int ticketed;         // 1: slots by ticket; 0: by workgroup index (dispatch order)
   unsigned long long wait_ticks;
 };
 
@@ -518,20 +456,19 @@ constexpr int kPre = 4;  // dependency steps of the dataflow apply loaded togeth
 
 __global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs a) {
   __shared__ double sv[4][kMaxWidth];
+  __shared__ int s_id;
+  int id = blockIdx.x;
+  if (a.ticketed) {
+    if (threadIdx.x == 0) s_id = atomicAdd(&a.err[4], 1);
+    __syncthreads();
+    id = s_id;
+  }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int wave = (int)((blockIdx.x * (unsigned)blockDim.x + threadIdx.x) >> 6);
-  const int nw = (int)((gridDim.x * (unsigned)blockDim.x) >> 6);
-  // a slot's header (forward: first row and width; backward: the block) is
-  // read one slot ahead
-  auto header = [&](int s) -> int2 {
-    if (s >= 2 * a.nb) return make_int2(0, 0);
-    return s < a.nb ? a.fq[s] : make_int2(a.lev_b[s - a.nb], 0);
-  };
-  int2 hdr = header(wave);
-  for (int s = wave; s < 2 * a.nb; s += nw) {
+  const int s = id * 4 + wv;
+  // no workgroup barrier below: each wave runs its own slot
+  if (s < 2 * a.nb) {
     const unsigned long long t0 = wall_clock64();
-    const int2 cur = hdr;
-    hdr = header(s + nw);
+    const int2 cur = s < a.nb ? a.fq[s] : make_int2(a.lev_b[s - a.nb], 0);
     bool bad = false;
     if (s < a.nb) {
       const int f = cur.x, q = cur.y;
@@ -624,6 +561,22 @@ __global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs a) {
       __builtin_amdgcn_wave_barrier();
     }
     if (__any(bad)) return;
+  }
+}
+
+// Before a dataflow apply: t and z become kPending and the ticket and wait
+// words are cleared.  A timeout of the previous apply (err[0]) is added to
+// err[5], which only apply_faults() reads and clears, so no fault is lost.
+// A fill kernel rather than a memset, so a captured graph can hold it.
+__global__ void apply_reset(int64_t n, unsigned long long* t, unsigned long long* z, int* err) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    t[i] = kPending;
+    z[i] = kPending;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (err[0]) err[5] += 1;
+    for (int k = 0; k < 5; ++k) err[k] = 0;
   }
 }
 
@@ -823,26 +776,27 @@ bilu_status build_apply_plan(bilu_handle* h) {
     CK(misc.alloc(4));
     CK(hipMemsetAsync(lev.p, 0xff, 2 * nb * sizeof(int), st));
     CK(hipMemsetAsync(misc.p, 0, 4 * sizeof(int), st));
-    int dev = 0, cus = 0, per_cu = 0;
-    CK(hipGetDevice(&dev));
-    CK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, apply_levels, 256, 0));
-    // no more waves than blocks (two per direction at least)
-    const int64_t groups = std::max<int64_t>(
-        1, std::min<int64_t>((int64_t)cus * std::max(per_cu, 1), (2 * nb + 255) / 256));
+    // one wave per block and direction, ordinary launch (workgroups take
+    // their slots from a ticket counter)
+    const int64_t groups = std::max<int64_t>(1, (2 * nb + 3) / 4);
     unsigned long long wait = h->wait_ticks ? h->wait_ticks : (unsigned long long)1e9;
-    int nbi = (int)nb;
     int* lf = lev.p;
     int* lb = lev.p + nb;
     int* top = misc.p;
     int* err = misc.p + 2;
-    const int32_t* fp = h->fw_ptr.p;
-    const int32_t* fj = h->fw_j.p;
-    const int32_t* bp = h->bw_ptr.p;
-    const int32_t* bb = h->bw_b.p;
-    void* args[] = {&nbi, &fp, &fj, &bp, &bb, &lf, &lb, &top, &err, &wait};
-    CK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(apply_levels), dim3((unsigned)groups),
-                                  dim3(256), args, 0, st));
+    int* ticket = h->opt.apply_path == 2 ? misc.p + 3 : nullptr;
+    apply_levels<<<(unsigned)groups, 256, 0, st>>>((int)nb, h->fw_ptr.p, h->fw_j.p, h->bw_ptr.p,
+                                                  h->bw_b.p, lf, lb, err, ticket, wait);
+    CK(hipGetLastError());
+    int nbi = (int)nb;
+    {
+      // the largest level of each direction
+      size_t rb = 0;
+      CK(hipcub::DeviceReduce::Max(nullptr, rb, lf, top, nbi, st));
+      CK(h->d_scan_tmp.alloc(rb + 1));
+      CK(hipcub::DeviceReduce::Max(h->d_scan_tmp.p, rb, lf, top, nbi, st));
+      CK(hipcub::DeviceReduce::Max(h->d_scan_tmp.p, rb, lb, top + 1, nbi, st));
+    }
     int hm[4];
     CK(hipMemcpyAsync(hm, misc.p, sizeof(hm), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
@@ -886,17 +840,8 @@ bilu_status build_apply_plan(bilu_handle* h) {
     h->stats.apply_levels_bwd = (int64_t)h->lev_b_ptr.size() - 1;
   }
   CK(h->w_red.alloc(kDotBlocks + 64));
-  CK(h->d_apply_err.alloc(4));
-  {
-    // workgroups of the dataflow apply: what fits at once, no more than its
-    // slots need
-    int dev = 0, cus = 0, per_cu = 0;
-    CK(hipGetDevice(&dev));
-    CK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, apply_flow, 256, kFlowLds));
-    h->apply_groups = std::max<int64_t>(
-        1, std::min<int64_t>((int64_t)cus * std::max(per_cu, 1), (2 * nb + 3) / 4));
-  }
+  CK(h->d_apply_err.alloc(8));
+  CK(hipMemsetAsync(h->d_apply_err.p, 0, 8 * sizeof(int), st));
   CK(hipStreamSynchronize(st));
   return BILU_OK;
 #undef CK
@@ -936,13 +881,9 @@ bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t
     e1 = h->ev_get();
     if (e0) (void)hipEventRecord(e0, st);
   }
-#define CK(x)                                          \
-  do {                                                 \
-    hipError_t e_ = (x);                               \
-    if (e_ != hipSuccess) return hip_check(h, e_, #x); \
-  } while (0)
-  bool by_levels = h->opt.apply_path == 1 || h->apply_by_levels;
-  if (!by_levels) {
+  if (h->opt.apply_path == 1) {
+    apply_levels_launch(h, x, y, t);
+  } else {
     FlowApplyArgs a{};
     a.f = h->fv;
     a.lr_ptr = h->lr_ptr.p;
@@ -955,33 +896,41 @@ bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t
     a.t = reinterpret_cast<unsigned long long*>(t);
     a.z = reinterpret_cast<unsigned long long*>(y);
     a.err = h->d_apply_err.p;
-    // a stalled wait means a workgroup that never ran: two seconds
+    // every wait ends (see apply_flow); the bound only catches a fault
     a.wait_ticks = (h->wait_ticks ? h->wait_ticks : (unsigned long long)1e9) / 5;
-    CK(hipMemsetAsync(a.err, 0, 4 * sizeof(int), st));
-    CK(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(a.t), (int)kPendingHalf, 2 * n, st));
-    CK(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(a.z), (int)kPendingHalf, 2 * n, st));
-    void* args[] = {&a};
-    CK(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(apply_flow),
-                                  dim3((unsigned)h->apply_groups), dim3(256), args, kFlowLds, st));
-    int herr = 0;
-    CK(hipMemcpyAsync(&herr, a.err, sizeof(int), hipMemcpyDeviceToHost, st));
-    CK(hipStreamSynchronize(st));
-    if (herr) {
-      // recomputed by levels, here and from now on
-      h->apply_by_levels = true;
-      by_levels = true;
-    }
+    a.ticketed = h->opt.apply_path == 2 ? 1 : 0;
+    apply_reset<<<grid_for(n), 256, 0, st>>>(n, a.t, a.z, a.err);
+    apply_flow<<<(unsigned)((2 * h->fv.nb + 3) / 4), 256, 0, st>>>(a);
   }
-  if (by_levels) {
-    apply_levels_launch(h, x, y, t);
-    CK(hipGetLastError());
-  }
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_check(h, e, "apply launch");
   if (h->opt.collect_timing) {
     if (e1) (void)hipEventRecord(e1, st);
     h->ev_record(1, e0, e1);
   }
   return BILU_OK;
-#undef CK
+}
+
+// Dataflow applies whose waits timed out since the last call (synchronizes
+// the stream); the count is cleared.
+bilu_status apply_faults(bilu_handle* h, int64_t* count) {
+  *count = 0;
+  if (!h->d_apply_err.p) return BILU_OK;
+  int e[6];
+  hipStream_t st = h->stream;
+  hipError_t r = hipMemcpyAsync(e, h->d_apply_err.p, sizeof(e), hipMemcpyDeviceToHost, st);
+  if (r == hipSuccess) r = hipStreamSynchronize(st);
+  if (r != hipSuccess) return hip_check(h, r, "apply status");
+  *count = (int64_t)e[5] + (e[0] ? 1 : 0);
+  if (*count == 0) return BILU_OK;
+  // clear both words (the next apply_reset would count e[0] again)
+  r = hipMemsetAsync(h->d_apply_err.p, 0, 8 * sizeof(int), st);
+  if (r == hipSuccess) r = hipStreamSynchronize(st);
+  if (r != hipSuccess) return hip_check(h, r, "apply status");
+  h->stats.apply_faults += *count;
+  return fail(h, BILU_ERR_DEVICE,
+              "apply: a dependency wait timed out (slot " + std::to_string(e[1]) + ", side " +
+                  std::to_string(e[2]) + ", index " + std::to_string(e[3]) + ")");
 }
 
 }  // namespace bilu

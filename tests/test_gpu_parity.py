@@ -235,9 +235,9 @@ def test_fast_and_general_paths_identical(name):
 
 @pytest.mark.parametrize("name", ["cd3d_12_b4", "cd3d_24_b4", "el3d_16_b3"])
 def test_apply_paths_identical(name):
-    """The apply as one dataflow launch and as one launch per dependency
-    level give the same bits; at 24^3 x 4 and 16^3 x 3 every wave of the
-    dataflow launch takes several slots."""
+    """The apply as one dataflow launch (blocks in workgroup order, or by
+    ticket) and as one launch per dependency level give the same bits, and
+    no dataflow wait timed out."""
     torch = _torch()
     from paper_1908_10169_amd import bilu
     w = mg.workload(name)
@@ -245,7 +245,7 @@ def test_apply_paths_identical(name):
     rng = np.random.default_rng(11)
     x = torch.from_numpy(rng.standard_normal(w.a.n)).cuda()
     outs = []
-    for path in (0, 1):
+    for path in (0, 1, 2):
         h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, apply_path=path)
         h.analyze(w.a, pre_perm=w.perm)
         h.factor(w.tau)
@@ -253,9 +253,10 @@ def test_apply_paths_identical(name):
         for _ in range(2):  # a second call reuses the plan and buffers
             h.apply(x, y)
         h.sync()
+        assert h.stats()["apply_faults"] == 0
         outs.append(y.cpu().numpy().tobytes())
         h.close()
-    assert outs[0] == outs[1]
+    assert outs[0] == outs[1] == outs[2]
 
 
 def test_state_errors():
