@@ -66,7 +66,9 @@ typedef struct {
   double perturb_rho;    /* Sec. 3.6 relative tolerance (default 1e-1)                */
   double pivot_eps;      /* pivot |u_jj| <= pivot_eps*max|S| triggers perturbation    */
   int beta_one;          /* 0: beta_j = max|column j| (default); 1: beta_j = 1        */
-  int update_precision;  /* bilu_precision of the Schur-complement products (F64)    */
+  int update_precision;  /* bilu_precision of the Schur-complement products (F64),   */
+                         /* also the precision L and W are stored in; pivot blocks,  */
+                         /* drop norms and the solver stay FP64                      */
   size_t heap_bytes;     /* factor heap size; 0 = sized from nnz(A).  A heap that    */
                          /* proves too small grows and the sweep runs again          */
                          /* (counted in bilu_stats.heap_regrows)                     */
@@ -95,6 +97,11 @@ typedef struct {
                          /* ordering); 1: all on the host.  Both give the same      */
                          /* permutation, groups and matrix bit for bit.  nnz >= 2^31 */
                          /* takes the host path                                      */
+  int apply_precision;   /* bilu_precision the apply reads L and W in: F64 (default) */
+                         /* or F32 (an FP32 copy made after the factorization).     */
+                         /* With FP32 or BF16 updates, L and W are stored in that   */
+                         /* precision and the apply reads them as stored; D and the */
+                         /* vectors are FP64 in every form                           */
 } bilu_options;
 
 typedef struct bilu_handle bilu_handle;

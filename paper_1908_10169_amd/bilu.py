@@ -37,7 +37,7 @@ class Options(C.Structure):
         ("perturb_rho", C.c_double), ("pivot_eps", C.c_double), ("beta_one", C.c_int),
         ("update_precision", C.c_int), ("heap_bytes", C.c_size_t),
         ("collect_timing", C.c_int), ("factor_path", C.c_int), ("apply_path", C.c_int),
-        ("use_mwm", C.c_int), ("analyze_path", C.c_int),
+        ("use_mwm", C.c_int), ("analyze_path", C.c_int), ("apply_precision", C.c_int),
     ]
 
 

@@ -171,7 +171,7 @@ struct MergeArgs {
   const int64_t* froff; const int64_t* fcoff; const int64_t* floff; const int64_t* fwoff;
   const int64_t* fdoff;
   const int32_t* fnr; const int32_t* fnc;
-  int32_t* fidx; double* fval; double* fdval;
+  int32_t* fidx; void* fval; double* fdval;   // fval in the precision in.vprec
   double* scratch; int64_t slot_doubles;   // per workgroup: 4 w^2 doubles
   int* err;
   int copy_all;   // 0: blocks that merged with nothing stay in place (only D_K is copied)
@@ -242,8 +242,8 @@ __global__ void __launch_bounds__(kMergeThreads) agg_merge_kernel(MergeArgs a) {
     const int f0 = a.in.bstart[b0], last = a.in.bstart[b1] - 1, w = last - f0 + 1;
     int32_t* Rout = a.fidx + a.froff[g];
     int32_t* Cout = a.fidx + a.fcoff[g];
-    double* Lout = a.fval + a.floff[g];
-    double* Wout = a.fval + a.fwoff[g];
+    const int64_t lout = a.floff[g], wout = a.fwoff[g];  // L^, W^ offsets in fval
+    const int vp = a.in.vprec;
     double* Dout = a.fdval + a.fdoff[g];
     const int nrg = a.fnr[g], ncg = a.fnc[g];
     if (b1 - b0 == 1) {
@@ -255,8 +255,10 @@ __global__ void __launch_bounds__(kMergeThreads) agg_merge_kernel(MergeArgs a) {
       }
       for (int t = tid; t < nrg; t += nt) Rout[t] = a.in.idx[a.in.roff[J] + t];
       for (int t = tid; t < ncg; t += nt) Cout[t] = a.in.idx[a.in.coff[J] + t];
-      for (int t = tid; t < nrg * w; t += nt) Lout[t] = a.in.val[a.in.loff[J] + t];
-      for (int t = tid; t < ncg * w; t += nt) Wout[t] = a.in.val[a.in.woff[J] + t];
+      for (int t = tid; t < nrg * w; t += nt)
+        value_store(a.fval, vp, lout + t, value_load(a.in.val, vp, a.in.loff[J] + t));
+      for (int t = tid; t < ncg * w; t += nt)
+        value_store(a.fval, vp, wout + t, value_load(a.in.val, vp, a.in.woff[J] + t));
       for (int t = tid; t < w * w; t += nt) Dout[t] = a.in.dval[a.in.doff[J] + t];
       continue;
     }
@@ -275,20 +277,20 @@ __global__ void __launch_bounds__(kMergeThreads) agg_merge_kernel(MergeArgs a) {
       const int nr = a.in.nr[J], nc = a.in.nc[J];
       const int32_t* RJ = a.in.idx + a.in.roff[J];
       const int32_t* CJ = a.in.idx + a.in.coff[J];
-      const double* LJ = a.in.val + a.in.loff[J];
-      const double* WJ = a.in.val + a.in.woff[J];
+      const int64_t LJ = a.in.loff[J], WJ = a.in.woff[J];
       const double* DJ = a.in.dval + a.in.doff[J];
       for (int e = tid; e < nr * qJ; e += nt) {
         const int z = e / qJ, c = e % qJ;
         const int x = RJ[z];
-        if (x <= last) Lg[(x - f0) * w + oJ + c] = LJ[(int64_t)z * qJ + c];
+        if (x <= last) Lg[(x - f0) * w + oJ + c] = value_load(a.in.val, vp, LJ + (int64_t)z * qJ + c);
       }
       for (int e = tid; e < nc * qJ; e += nt) {
         const int z = e / qJ, r = e % qJ;
         const int y = CJ[z];
         if (y <= last) {
           double acc = 0.0;
-          for (int t = 0; t < qJ; ++t) acc = fma(DJ[r * qJ + t], WJ[(int64_t)z * qJ + t], acc);
+          for (int t = 0; t < qJ; ++t)
+            acc = fma(DJ[r * qJ + t], value_load(a.in.val, vp, WJ + (int64_t)z * qJ + t), acc);
           Ug[(oJ + r) * w + (y - f0)] = acc;
         }
       }
@@ -345,10 +347,11 @@ __global__ void __launch_bounds__(kMergeThreads) agg_merge_kernel(MergeArgs a) {
         if (oJ + qJ <= y) continue;  // L_GG^{-1} is lower triangular
         const int pz = find_sorted(a.in.idx + a.in.roff[J], a.in.nr[J], i);
         if (pz < 0) continue;
-        const double* row = a.in.val + a.in.loff[J] + (int64_t)pz * qJ;
-        for (int c = 0; c < qJ; ++c) acc = fma(row[c], Li[(oJ + c) * w + y], acc);
+        const int64_t row = a.in.loff[J] + (int64_t)pz * qJ;
+        for (int c = 0; c < qJ; ++c)
+          acc = fma(value_load(a.in.val, vp, row + c), Li[(oJ + c) * w + y], acc);
       }
-      Lout[(int64_t)z * w + y] = acc;
+      value_store(a.fval, vp, lout + (int64_t)z * w + y, acc);
     }
     __syncthreads();
     // columns: W^ = L_GG W_{G,C}
@@ -368,10 +371,11 @@ __global__ void __launch_bounds__(kMergeThreads) agg_merge_kernel(MergeArgs a) {
         if (oJ > x) break;  // L_GG is lower triangular
         const int pz = find_sorted(a.in.idx + a.in.coff[J], a.in.nc[J], j);
         if (pz < 0) continue;
-        const double* col = a.in.val + a.in.woff[J] + (int64_t)pz * qJ;
-        for (int c = 0; c < qJ; ++c) acc = fma(Lg[x * w + oJ + c], col[c], acc);
+        const int64_t col = a.in.woff[J] + (int64_t)pz * qJ;
+        for (int c = 0; c < qJ; ++c)
+          acc = fma(Lg[x * w + oJ + c], value_load(a.in.val, vp, col + c), acc);
       }
-      Wout[(int64_t)z * w + x] = acc;
+      value_store(a.fval, vp, wout + (int64_t)z * w + x, acc);
     }
     __syncthreads();
   }
@@ -511,7 +515,9 @@ bilu_status aggregate_device(bilu_handle* h) {
     mi += r + c;
     mv += (r + c) * w;
   }
-  const bool in_place = mi <= (int64_t)h->d_idx_heap.n && mv <= (int64_t)h->d_val_heap.n;
+  const int vbytes = value_bytes(h->fv.vprec);
+  const bool in_place =
+      mi <= (int64_t)h->d_idx_heap.n && mv * vbytes <= (int64_t)h->d_val_heap.n;
   CK(h->f_bstart.alloc(ng + 1));
   CK(h->f_blockof.alloc(n));
   CK(h->f_nr.alloc(ng));
@@ -531,6 +537,7 @@ bilu_status aggregate_device(bilu_handle* h) {
                                                            h->f_nc.p, h->f_bstart.p);
   CK(hipGetLastError());
   DevArray<int64_t> d_mlist;
+  int64_t vo_total = 0;  // values of the separate storage (not in place)
   if (in_place) {
     agg_offsets<<<(unsigned)((ng + 255) / 256), 256, 0, st>>>((int)ng, d_gfirst.p, h->fv, h->f_roff.p,
                                                              h->f_coff.p, h->f_loff.p, h->f_woff.p);
@@ -557,7 +564,8 @@ bilu_status aggregate_device(bilu_handle* h) {
       vo += (r + c) * w;
     }
     CK(h->f_idx.alloc(std::max<int64_t>(1, io)));
-    CK(h->f_val.alloc(std::max<int64_t>(1, vo)));
+    CK(h->f_val.alloc(std::max<int64_t>(1, vo) * vbytes));
+    vo_total = vo;
     CK(hipMemcpyAsync(h->f_roff.p, off.data(), ng * 8, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(h->f_coff.p, off.data() + ng, ng * 8, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(h->f_loff.p, off.data() + 2 * ng, ng * 8, hipMemcpyHostToDevice, st));
@@ -616,6 +624,7 @@ bilu_status aggregate_device(bilu_handle* h) {
   f.doff = h->f_doff.p;
   f.idx = in_place ? h->d_idx_heap.p : h->f_idx.p;
   f.val = in_place ? h->d_val_heap.p : h->f_val.p;
+  h->f_val_len = in_place ? mv : vo_total;
   f.dval = h->f_dval.p;
   return BILU_OK;
 #undef CK

@@ -94,7 +94,9 @@ bilu_status finish_factor(bilu_handle* h, std::chrono::steady_clock::time_point 
   h->fv.doff = h->d_doff.p;
   h->fv.idx = h->d_idx_heap.p;
   h->fv.val = h->d_val_heap.p;
+  h->fv.vprec = h->opt.update_precision;
   h->fv.dval = h->d_dval.p;
+  h->f_val_len = h->val_used;
   auto t1 = std::chrono::steady_clock::now();
   if (h->opt.use_aggregation) {
     s = aggregate_device(h);
@@ -212,7 +214,8 @@ bilu_status bilu_create(bilu_handle** out, const bilu_options* opt, void* stream
       h->opt.update_precision < 0 || h->opt.update_precision > 2 || h->opt.drop_norm < 0 ||
       h->opt.drop_norm > 1 || h->opt.factor_path < 0 || h->opt.factor_path > 2 ||
       h->opt.apply_path < 0 || h->opt.apply_path > 2 || h->opt.use_mwm < 0 || h->opt.use_mwm > 1 ||
-      h->opt.analyze_path < 0 || h->opt.analyze_path > 1) {
+      h->opt.analyze_path < 0 || h->opt.analyze_path > 1 || h->opt.apply_precision < 0 ||
+      h->opt.apply_precision > 1) {
     delete h;
     return BILU_ERR_INVALID;
   }
@@ -626,13 +629,32 @@ bilu_status bilu_export_factors(const bilu_handle* hc, bilu_factors_host* out) {
   for (int64_t b = 0; b <= nb; ++b) out->starts[b] = h->bstart[b];
   for (size_t b = 0; b < h->bstart0.size(); ++b) out->starts_initial[b] = h->bstart0[b];
   std::copy(h->group_starts.begin(), h->group_starts.end(), out->group_starts);
-  // whole heaps are copied once (simple; export is a checking path)
+  // whole heaps are copied once (simple; export is a checking path); stored
+  // FP32 / BF16 values are widened to double exactly
   std::vector<double> vheap(val_len);
+  const int vb = value_bytes(fv.vprec);
+  std::vector<unsigned char> raw((size_t)val_len * vb);
   if (hipMemcpy(idx.data(), fv.idx, idx.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(vheap.data(), fv.val, vheap.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(raw.data(), fv.val, raw.size(), hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(out->d_val, fv.dval, td * 8, hipMemcpyDeviceToHost) != hipSuccess) {
     bilu_free_factors(out);
     return fail(h, BILU_ERR_DEVICE, "export copy");
+  }
+  for (int64_t i = 0; i < val_len; ++i) {
+    if (vb == 8) {
+      std::memcpy(&vheap[i], raw.data() + 8 * i, 8);
+    } else if (vb == 4) {
+      float x;
+      std::memcpy(&x, raw.data() + 4 * i, 4);
+      vheap[i] = x;
+    } else {
+      uint16_t b;
+      std::memcpy(&b, raw.data() + 2 * i, 2);
+      const uint32_t u = (uint32_t)b << 16;
+      float x;
+      std::memcpy(&x, &u, 4);
+      vheap[i] = x;
+    }
   }
   int64_t ar = 0, ac = 0, al = 0, aw = 0;
   out->r_ptr[0] = out->c_ptr[0] = 0;

@@ -43,9 +43,10 @@ struct SplitArgs {
   const int32_t* bstart;                // system partition
   const int32_t* nr; const int32_t* nc; // system per-block counts
   const int64_t* roff; const int64_t* coff; const int64_t* loff; const int64_t* woff;
-  const int32_t* idx; const double* val;
+  const int32_t* idx; const void* val;
   const int64_t* new_roff; const int64_t* new_loff;  // handle layout: rows, columns; L, W
-  int32_t* out_idx; double* out_val;
+  int32_t* out_idx; void* out_val;
+  int vprec;                                          // precision of the stored L, W
 };
 
 // One workgroup per block: copy R_K, C_K (rebased), L_K, W_K.
@@ -58,9 +59,11 @@ __global__ void split_blocks(SplitArgs a) {
     for (int t = threadIdx.x; t < nr; t += blockDim.x) a.out_idx[ro + t] = a.idx[a.roff[K] + t] - a.n0;
     for (int t = threadIdx.x; t < nc; t += blockDim.x)
       a.out_idx[ro + nr + t] = a.idx[a.coff[K] + t] - a.n0;
-    for (int t = threadIdx.x; t < nr * q; t += blockDim.x) a.out_val[lo + t] = a.val[a.loff[K] + t];
+    for (int t = threadIdx.x; t < nr * q; t += blockDim.x)
+      value_store(a.out_val, a.vprec, lo + t, value_load(a.val, a.vprec, a.loff[K] + t));
     for (int t = threadIdx.x; t < nc * q; t += blockDim.x)
-      a.out_val[lo + (int64_t)nr * q + t] = a.val[a.woff[K] + t];
+      value_store(a.out_val, a.vprec, lo + (int64_t)nr * q + t,
+                  value_load(a.val, a.vprec, a.woff[K] + t));
   }
 }
 
@@ -186,7 +189,7 @@ bilu_status factor_batched(bilu_handle** hs, int count, const double* taus) {
     CK(h->d_dval.alloc(h->doff_h[nbi]));
     CK(h->d_sval.alloc(h->doff_h[nbi]));
     CK(h->d_idx_heap.alloc(std::max<int64_t>(1, io)));
-    CK(h->d_val_heap.alloc(std::max<int64_t>(1, vo)));
+    CK(h->d_val_heap.alloc(std::max<int64_t>(1, vo) * value_bytes(h->opt.update_precision)));
     CK(hipMemcpyAsync(h->d_bstart.p, bs.data(), (nbi + 1) * 4, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(h->d_roff.p, roff.data(), nbi * 8, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(h->d_coff.p, coff.data(), nbi * 8, hipMemcpyHostToDevice, st));
@@ -220,6 +223,7 @@ bilu_status factor_batched(bilu_handle** hs, int count, const double* taus) {
     sa.new_loff = h->d_loff.p;
     sa.out_idx = h->d_idx_heap.p;
     sa.out_val = h->d_val_heap.p;
+    sa.vprec = h->opt.update_precision;
     split_blocks<<<(unsigned)std::min<int64_t>(nbi, 4096), 64, 0, st>>>(sa);
     CK(hipGetLastError());
     // device counters of the one launch describe the whole batch

@@ -211,37 +211,36 @@ __device__ __forceinline__ double dot_strided(const double* x, const double* y, 
   return acc;
 }
 
-// bfloat16 by round-to-nearest-even of the float value (NaN stays NaN).
-__device__ __forceinline__ uint16_t to_bf16(double x) {
-  uint32_t u = __float_as_uint((float)x);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+// One stored factor value (L or W) as a double: the heap holds them in the
+// update precision.
+__device__ __forceinline__ double load_factor(const FactorArgs& a, int64_t o) {
+  return value_load(a.val_heap, a.update_prec, o);
 }
-__device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // One Schur-update term L_J(i,:) W_J(:,j) of length p, from value-heap
-// offsets lo (row of L_J) and wo (column of W_J): FP64, or FP32 / BF16 inputs
-// (the block's low-precision copy) with FP32 accumulation.
+// offsets lo (row of L_J) and wo (column of W_J): FP64, or FP32 / BF16
+// inputs (the stored values) with FP32 accumulation.
 __device__ __forceinline__ double update_term(const FactorArgs& a, int64_t lo, int64_t wo, int p) {
   if (a.update_prec == 1) {
+    const float* v = static_cast<const float*>(a.val_heap);
     float acc = 0.0f;
-    for (int t = 0; t < p; ++t) acc = fmaf(a.lo32[lo + t], a.lo32[wo + t], acc);
+    for (int t = 0; t < p; ++t) acc = fmaf(v[lo + t], v[wo + t], acc);
     return (double)acc;
   }
   if (a.update_prec == 2) {
+    const uint16_t* v = static_cast<const uint16_t*>(a.val_heap);
     float acc = 0.0f;
-    for (int t = 0; t < p; ++t) acc = fmaf(from_bf16(a.lo16[lo + t]), from_bf16(a.lo16[wo + t]), acc);
+    for (int t = 0; t < p; ++t) acc = fmaf(bf16_float(v[lo + t]), bf16_float(v[wo + t]), acc);
     return (double)acc;
   }
-  return dot_strided(a.val_heap + lo, a.val_heap + wo, p);
+  const double* v = static_cast<const double*>(a.val_heap);
+  return dot_strided(v + lo, v + wo, p);
 }
 
-// Store a factor value (and its low-precision copy) at value-heap offset o.
+// Store a factor value at value-heap offset o, rounded to the update
+// precision (the drop test has already seen the FP64 value).
 __device__ __forceinline__ void store_factor(const FactorArgs& a, int64_t o, double v) {
-  a.val_heap[o] = v;
-  if (a.update_prec == 1) a.lo32[o] = (float)v;
-  else if (a.update_prec == 2) a.lo16[o] = to_bf16(v);
+  value_store(a.val_heap, a.update_prec, o, v);
 }
 
 // Sec. 3.6 perturbation of column j of the q x q row-major matrix m: the
@@ -916,8 +915,6 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
     const int nRJ = a.nr[J], nCJ = a.nc[J];
     const int32_t* RJ = a.idx_heap + a.roff[J];
     const int32_t* CJ = a.idx_heap + a.coff[J];
-    const double* LJ = a.val_heap + a.loff[J];
-    const double* WJ = a.val_heap + a.woff[J];
     if (tid == 0) {
       s.misc[8] = 0;
       s.misc[9] = 0;
@@ -974,8 +971,6 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
     const int nRJ = a.nr[J], nCJ = a.nc[J];
     const int32_t* RJ = a.idx_heap + a.roff[J];
     const int32_t* CJ = a.idx_heap + a.coff[J];
-    const double* LJ = a.val_heap + a.loff[J];
-    const double* WJ = a.val_heap + a.woff[J];
     if (tid == 0) {
       s.misc[8] = 0;
       s.misc[9] = 0;
@@ -1754,8 +1749,8 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
             for (int k = 0; k < 2; ++k) {
               // clamped in range; the products past p are not taken
               const int t = min(t0 + k, max(pp[u] - 1, 0));
-              x[u][k] = a.val_heap[lo[u] + t];
-              y[u][k] = a.val_heap[wo[u] + t];
+              x[u][k] = static_cast<const double*>(a.val_heap)[lo[u] + t];
+              y[u][k] = static_cast<const double*>(a.val_heap)[wo[u] + t];
             }
 #pragma unroll
           for (int u = 0; u < kU; ++u)
@@ -2352,7 +2347,8 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
   // a heap or overflow pool that proves too small grows, and the sweep runs
   // again from the start
   for (int attempt = 0; attempt < 16; ++attempt) {
-    if ((int64_t)h->d_val_heap.n < val_cap) CK(h->d_val_heap.alloc(val_cap));
+    if ((int64_t)h->d_val_heap.n < val_cap * value_bytes(h->opt.update_precision))
+      CK(h->d_val_heap.alloc(val_cap * value_bytes(h->opt.update_precision)));
     CK(h->d_ovf_j.alloc(ovf_cap));
     CK(h->d_ovf_next.alloc(ovf_cap));
     if ((int64_t)h->d_idx_heap.n < idx_cap) CK(h->d_idx_heap.alloc(idx_cap));
@@ -2422,22 +2418,13 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     a.loff = h->d_loff.p; a.woff = h->d_woff.p; a.doff = h->d_doff.p;
     a.dval = h->d_dval.p; a.sval = h->d_sval.p;
     a.idx_heap = h->d_idx_heap.p; a.idx_cap = (int64_t)h->d_idx_heap.n; a.idx_top = h->d_counters.p + 0;
-    a.val_heap = h->d_val_heap.p; a.val_cap = (int64_t)h->d_val_heap.n; a.val_top = h->d_counters.p + 1;
+    a.elem_bytes = value_bytes(h->opt.update_precision);
+    a.val_heap = h->d_val_heap.p;
+    a.val_cap = (int64_t)(h->d_val_heap.n / a.elem_bytes);
+    a.val_top = h->d_counters.p + 1;
     // per-worker chunks: at most an eighth of either heap sits unused in them
     a.val_chunk = std::min<int64_t>(8192, a.val_cap / (8 * workers));
     a.idx_chunk = std::min<int64_t>(4096, a.idx_cap / (8 * workers));
-    a.lo32 = nullptr;
-    a.lo16 = nullptr;
-    a.elem_bytes = 8;
-    if (a.update_prec == 1) {
-      CK(h->d_lo32.alloc(h->d_val_heap.n));
-      a.lo32 = h->d_lo32.p;
-      a.elem_bytes = 4;
-    } else if (a.update_prec == 2) {
-      CK(h->d_lo16.alloc(h->d_val_heap.n));
-      a.lo16 = h->d_lo16.p;
-      a.elem_bytes = 2;
-    }
     a.col_cnt = h->d_col_cnt.p; a.col_list = h->d_col_list.p; a.col_ovf = h->d_col_ovf.p;
     a.row_cnt = h->d_row_cnt.p; a.row_list = h->d_row_list.p; a.row_ovf = h->d_row_ovf.p;
     a.ovf_j = h->d_ovf_j.p; a.ovf_next = h->d_ovf_next.p; a.ovf_top = h->d_status.p + 3;

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/bilu.h"
+#include "values.h"
 
 namespace bilu {
 
@@ -122,11 +123,9 @@ struct FactorArgs {
   double* dval;
   double* sval;
   int32_t* idx_heap; int64_t idx_cap; unsigned long long* idx_top;
-  double* val_heap;  int64_t val_cap; unsigned long long* val_top;
+  void* val_heap;  int64_t val_cap; unsigned long long* val_top;  // L, W in update_prec
   int64_t idx_chunk, val_chunk;    // entries a worker takes from a heap top at once
-  float* lo32;                     // FP32 copy of L/W (same offsets) or null
-  uint16_t* lo16;                  // BF16 copy of L/W (same offsets) or null
-  int elem_bytes;                  // bytes of one update input (8, 4 or 2)
+  int elem_bytes;                  // bytes of one stored L / W value (8, 4 or 2)
   // predecessor lists: inline + overflow linked list
   int32_t* col_cnt; int32_t* col_list; int32_t* col_ovf;
   int32_t* row_cnt; int32_t* row_list; int32_t* row_ovf;
@@ -180,7 +179,8 @@ constexpr double kWaitSeconds = 10.0;
 // Device view of a block factor (initial or aggregated), used by the apply
 // and by export.  Per block K: rows R_K (nr, at idx+roff), columns C_K
 // (nc, at idx+coff), L_K (nr x q row-major at val+loff), W_K (q x nc
-// column-major at val+woff), D_K (q x q row-major at dval+doff).
+// column-major at val+woff), both in precision vprec (values.h), D_K (q x q
+// row-major at dval+doff, FP64).
 struct FactorView {
   int nb = 0;
   const int32_t* bstart = nullptr;
@@ -193,7 +193,8 @@ struct FactorView {
   const int64_t* woff = nullptr;
   const int64_t* doff = nullptr;
   const int32_t* idx = nullptr;
-  const double* val = nullptr;
+  const void* val = nullptr;
+  int vprec = 0;
   const double* dval = nullptr;
 };
 
@@ -242,9 +243,7 @@ struct bilu_handle {
   bilu::DevArray<int32_t> d_nr, d_nc;
   bilu::DevArray<double> d_dval, d_sval;
   bilu::DevArray<int32_t> d_idx_heap;
-  bilu::DevArray<double> d_val_heap;
-  bilu::DevArray<float> d_lo32;
-  bilu::DevArray<uint16_t> d_lo16;
+  bilu::DevArray<unsigned char> d_val_heap;  // L, W values in the update precision (bytes)
   bilu::DevArray<int32_t> d_col_cnt, d_col_list, d_col_ovf, d_row_cnt, d_row_list, d_row_ovf;
   bilu::DevArray<int32_t> d_ovf_j, d_ovf_next;
   bilu::DevArray<double> d_scratch;
@@ -259,8 +258,10 @@ struct bilu_handle {
   bilu::DevArray<int32_t> f_bstart, f_blockof, f_nr, f_nc;
   bilu::DevArray<int64_t> f_roff, f_coff, f_loff, f_woff, f_doff;
   bilu::DevArray<int32_t> f_idx;     // idx heap of the final factor
-  bilu::DevArray<double> f_val, f_dval;
+  bilu::DevArray<unsigned char> f_val;  // merged L, W values (bytes, update precision)
+  bilu::DevArray<double> f_dval;
   bool final_is_initial = true;      // no merge happened: f_* alias the factor storage
+  int64_t f_val_len = 0;             // values of the final factor's value array in use
   bool ilu_static = false;
   // Sec. 3.1 (use_mwm): the factored matrix is D_l A D_r Pi.  Vectors cross
   // the boundary by row (perm, sl / sl_inv) or by column (perm_col = sigma o
@@ -286,7 +287,9 @@ struct bilu_handle {
   bilu::DevArray<int32_t> fw_ptr, fw_j, fw_r0, fw_cnt, bw_ptr, bw_b;
   bilu::DevArray<int64_t> lr_ptr;
   bilu::DevArray<int32_t> lr_col;
-  bilu::DevArray<double> lr_val;
+  bilu::DevArray<unsigned char> lr_val;          // row-major L in the apply precision (bytes)
+  int apply_prec = 0;                            // precision of the values the apply reads
+  bilu::DevArray<unsigned char> d_apply_val;     // FP32 copy of L, W when apply_prec differs
   bilu::DevArray<int32_t> lev_f, lev_b;          // blocks by forward / backward level
   bilu::DevArray<int2> lev_f_fq;                 // first row and width of lev_f's blocks
   bilu::DevArray<int> d_apply_err;              // dataflow apply: wait words, ticket, fault count

@@ -185,11 +185,11 @@ __global__ void iota_k(int n, int32_t* v) {
 // a time, then their rows in K 64 at a time; lane r (and r + 64) then takes
 // row r of K through them in that order.  kFill = false counts the entries
 // of each row into lr_cnt; kFill = true writes them from lr_ptr on.
-template <bool kFill>
+template <bool kFill, class T>
 __global__ void __launch_bounds__(256) lr_build(FactorView f, const int32_t* fw_ptr,
                                                 const int32_t* fw_j, const int32_t* fw_r0,
                                                 const int32_t* fw_cnt, const int64_t* lr_ptr,
-                                                int64_t* lr_cnt, int32_t* lr_col, double* lr_val) {
+                                                int64_t* lr_cnt, int32_t* lr_col, T* lr_val) {
   __shared__ int sOff[4][65];             // prefix of the dependencies' row counts
   __shared__ int sR0[4][64], sF[4][64], sP[4][64];
   __shared__ long long sRoff[4][64], sLoff[4][64];
@@ -261,10 +261,10 @@ __global__ void __launch_bounds__(256) lr_build(FactorView f, const int32_t* fw_
             if (sRow[wv][u] == myr) pos += sP[wv][sLe[wv][u]];
           const int le = sLe[wv][lane];
           const int pJ = sP[wv][le], fJ = sF[wv][le];
-          const double* L = f.val + sLoff[wv][le] + (int64_t)sI[wv][lane] * pJ;
+          const int64_t L = sLoff[wv][le] + (int64_t)sI[wv][lane] * pJ;
           for (int c = 0; c < pJ; ++c) {
             lr_col[pos + c] = fJ + c;
-            lr_val[pos + c] = L[c];
+            lr_val[pos + c] = from_double<T>(value_load(f.val, f.vprec, L + c));
           }
         }
       }
@@ -290,11 +290,13 @@ __global__ void __launch_bounds__(256) lr_build(FactorView f, const int32_t* fw_
 // in K; backward: blocks holding the columns of U_K); one launch per level,
 // one wave per block, no waiting inside a kernel.
 // ---------------------------------------------------------------------------
+template <class T>
 struct SweepArgs {
   FactorView f;
   const int64_t* lr_ptr;
   const int32_t* lr_col;
-  const double* lr_val;
+  const T* lr_val;     // row-major L in the apply precision
+  const T* wval;       // W values in the apply precision, at f.woff
   const int32_t* sched;
   const int2* fq;  // forward: first row and width of each scheduled block
   int begin, end;
@@ -302,7 +304,8 @@ struct SweepArgs {
 
 // forward: t_K = x_K - sum over stored L(i, j) t_j, rows of K from the
 // row-major copy (groups of lanes per row, fixed reduction tree)
-__global__ void __launch_bounds__(256) forward_level(SweepArgs a, const double* x, double* t) {
+template <class T>
+__global__ void __launch_bounds__(256) forward_level(SweepArgs<T> a, const double* x, double* t) {
   const int w = a.begin + blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= a.end) return;
   const int lane = threadIdx.x & 63;
@@ -316,7 +319,7 @@ __global__ void __launch_bounds__(256) forward_level(SweepArgs a, const double* 
     double acc = 0.0;
     if (r < q) {
       const int64_t b = a.lr_ptr[f + r], e = a.lr_ptr[f + r + 1];
-      for (int64_t k = b + sub; k < e; k += g) acc = fma(a.lr_val[k], t[a.lr_col[k]], acc);
+      for (int64_t k = b + sub; k < e; k += g) acc = fma(as_double(a.lr_val[k]), t[a.lr_col[k]], acc);
     }
     for (int o = g >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if (r < q && sub == 0) t[f + r] = x[f + r] - acc;
@@ -327,7 +330,8 @@ __global__ void __launch_bounds__(256) forward_level(SweepArgs a, const double* 
 // of lanes per row: lane (jj, r) takes row r of W_K over the columns
 // jj, jj + g, ... (W_K is column-major, so a wave reads it contiguously),
 // then a fixed reduction tree over jj; v staged in LDS per wave
-__global__ void __launch_bounds__(256) backward_level(SweepArgs a, const double* t, double* z) {
+template <class T>
+__global__ void __launch_bounds__(256) backward_level(SweepArgs<T> a, const double* t, double* z) {
   __shared__ double sv[4][kMaxWidth];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int w = a.begin + blockIdx.x * 4 + wv;
@@ -339,7 +343,7 @@ __global__ void __launch_bounds__(256) backward_level(SweepArgs a, const double*
     q = a.f.bstart[K + 1] - f;
     const int m = a.f.nc[K];
     const int32_t* Cc = a.f.idx + a.f.coff[K];
-    const double* W = a.f.val + a.f.woff[K];
+    const T* W = a.wval + a.f.woff[K];
     int qp = 1;
     while (qp < q && qp < 64) qp <<= 1;
     const int g = 64 / qp;  // column groups
@@ -347,7 +351,7 @@ __global__ void __launch_bounds__(256) backward_level(SweepArgs a, const double*
       const int r = r0 + (lane & (qp - 1)), jj = lane / qp;
       double acc = 0.0;
       if (r < q)
-        for (int j = jj; j < m; j += g) acc = fma(W[(int64_t)j * q + r], z[Cc[j]], acc);
+        for (int j = jj; j < m; j += g) acc = fma(as_double(W[(int64_t)j * q + r]), z[Cc[j]], acc);
       for (int o = 32; o >= qp; o >>= 1) acc += __shfl_xor(acc, o, 64);
       if (jj == 0 && r < q) sv[wv][r] = t[f + r] - acc;
     }
@@ -385,11 +389,13 @@ __global__ void __launch_bounds__(256) backward_level(SweepArgs a, const double*
 constexpr unsigned kPendingHalf = 0x7ff4b11eu;
 constexpr unsigned long long kPending = ((unsigned long long)kPendingHalf << 32) | kPendingHalf;
 
+template <class T>
 struct FlowApplyArgs {
   FactorView f;
   const int64_t* lr_ptr;
   const int32_t* lr_col;
-  const double* lr_val;
+  const T* lr_val;       // row-major L in the apply precision
+  const T* wval;         // W values in the apply precision, at f.woff
   const int2* fq;        // forward slots: first row and width
   const int32_t* lev_b;  // backward slots: block
   int nb;
@@ -405,13 +411,15 @@ struct FlowApplyArgs {
 // Values of t (side 0) or z (side 1) at idx for the lanes with has set, once
 // every one of them is published; the whole wave waits together (no lane
 // spins on its own).  On a timeout the first one records where it waited.
-__device__ __forceinline__ unsigned long long peek_value(const FlowApplyArgs& a, int side, bool has,
+template <class A>
+__device__ __forceinline__ unsigned long long peek_value(const A& a, int side, bool has,
                                                          int64_t idx) {
   return has ? __hip_atomic_load((side ? a.z : a.t) + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
              : 0ull;
 }
 // As await_values, from a value v read before (peek_value).
-__device__ __forceinline__ double await_from(const FlowApplyArgs& a, int side, bool has, int64_t idx,
+template <class A>
+__device__ __forceinline__ double await_from(const A& a, int side, bool has, int64_t idx,
                                              unsigned long long v, unsigned long long t0, bool& bad,
                                              int slot) {
   unsigned long long* p = (side ? a.z : a.t) + (has ? idx : 0);
@@ -438,7 +446,8 @@ __device__ __forceinline__ double await_from(const FlowApplyArgs& a, int side, b
   }
   return __longlong_as_double((long long)v);
 }
-__device__ __forceinline__ double await_values(const FlowApplyArgs& a, int side, bool has, int64_t idx,
+template <class A>
+__device__ __forceinline__ double await_values(const A& a, int side, bool has, int64_t idx,
                                                unsigned long long t0, bool& bad, int slot) {
   return await_from(a, side, has, idx, peek_value(a, side, has, idx), t0, bad, slot);
 }
@@ -454,7 +463,8 @@ __device__ __forceinline__ int wave_max_int(int v) {
 
 constexpr int kPre = 4;  // dependency steps of the dataflow apply loaded together
 
-__global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs a) {
+template <class T>
+__global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs<T> a) {
   __shared__ double sv[4][kMaxWidth];
   __shared__ int s_id;
   int id = blockIdx.x;
@@ -497,7 +507,7 @@ __global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs a) {
             const int64_t k = b + (int64_t)(i0 + u) * g;
             has[u] = i0 + u < steps && k < e;
             col[u] = has[u] ? a.lr_col[k] : 0;
-            lv[u] = has[u] ? a.lr_val[k] : 0.0;
+            lv[u] = has[u] ? as_double(a.lr_val[k]) : 0.0;
           }
 #pragma unroll
           for (int u = 0; u < kPre; ++u) tv0[u] = peek_value(a, 0, has[u], col[u]);
@@ -515,7 +525,7 @@ __global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs a) {
       const int f = a.f.bstart[K], q = a.f.bstart[K + 1] - f;
       const int m = a.f.nc[K];
       const int32_t* Cc = a.f.idx + a.f.coff[K];
-      const double* W = a.f.val + a.f.woff[K];
+      const T* W = a.wval + a.f.woff[K];
       int qp = 1;
       while (qp < q && qp < 64) qp <<= 1;
       const int g = 64 / qp;  // column groups
@@ -535,7 +545,7 @@ __global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs a) {
             const int j = jj + (i0 + u) * g;
             has[u] = i0 + u < steps && r < q && j < m;
             col[u] = has[u] ? Cc[j] : 0;
-            wv[u] = has[u] ? W[(int64_t)j * q + r] : 0.0;
+            wv[u] = has[u] ? as_double(W[(int64_t)j * q + r]) : 0.0;
           }
 #pragma unroll
           for (int u = 0; u < kPre; ++u) zv0[u] = peek_value(a, 1, has[u], col[u]);
@@ -647,6 +657,24 @@ __global__ void __launch_bounds__(256) dot_final(int nparts, const double* parti
   if (threadIdx.x == 0) *out = (sw[0] + sw[1]) + (sw[2] + sw[3]);
 }
 
+// FP32 copies of FP64 factor values (apply_precision F32).
+__global__ void convert_values(int64_t n, const double* x, float* y) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
+// Calls f with a value of the type that holds values of precision prec.
+template <class F>
+void with_value_type(int prec, F&& f) {
+  if (prec == kValF32)
+    f(float{});
+  else if (prec == kValBF16)
+    f(uint16_t{});
+  else
+    f(double{});
+}
+
 inline unsigned grid_for(int64_t n) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
 }
@@ -755,18 +783,33 @@ bilu_status build_apply_plan(bilu_handle* h) {
   CK(device_scan<int32_t>(h, cnt.p, h->bw_ptr.p, nb, &nbw));
   CK(h->bw_b.alloc(std::max<int32_t>(1, nbw)));
   bw_fill<<<(unsigned)nb, 64, 0, st>>>(f, h->bw_ptr.p, h->bw_b.p);
+  // the precision the apply reads L and W in: the stored one, or FP32
+  // copies of FP64 values (apply_precision)
+  h->apply_prec = f.vprec != kValF64 ? f.vprec
+                  : h->opt.apply_precision == BILU_PREC_F32 ? kValF32
+                                                             : kValF64;
+  if (h->apply_prec != f.vprec) {
+    CK(h->d_apply_val.alloc(std::max<int64_t>(1, h->f_val_len) * value_bytes(h->apply_prec)));
+    convert_values<<<grid_for(h->f_val_len), 256, 0, st>>>(
+        h->f_val_len, static_cast<const double*>(f.val),
+        reinterpret_cast<float*>(h->d_apply_val.p));
+  }
   // row-major L
   CK(h->lr_ptr.alloc(n + 1));
   DevArray<int64_t> lc;
   CK(lc.alloc(n));
-  lr_build<false><<<gw, 256, 0, st>>>(f, h->fw_ptr.p, h->fw_j.p, h->fw_r0.p, h->fw_cnt.p, nullptr,
-                                       lc.p, nullptr, nullptr);
+  lr_build<false, double><<<gw, 256, 0, st>>>(f, h->fw_ptr.p, h->fw_j.p, h->fw_r0.p, h->fw_cnt.p,
+                                               nullptr, lc.p, nullptr, nullptr);
   int64_t nlr = 0;
   CK(device_scan<int64_t>(h, lc.p, h->lr_ptr.p, n, &nlr));
   CK(h->lr_col.alloc(std::max<int64_t>(1, nlr)));
-  CK(h->lr_val.alloc(std::max<int64_t>(1, nlr)));
-  lr_build<true><<<gw, 256, 0, st>>>(f, h->fw_ptr.p, h->fw_j.p, h->fw_r0.p, h->fw_cnt.p,
-                                      h->lr_ptr.p, nullptr, h->lr_col.p, h->lr_val.p);
+  CK(h->lr_val.alloc(std::max<int64_t>(1, nlr) * value_bytes(h->apply_prec)));
+  with_value_type(h->apply_prec, [&](auto tag) {
+    using T = decltype(tag);
+    lr_build<true, T><<<gw, 256, 0, st>>>(f, h->fw_ptr.p, h->fw_j.p, h->fw_r0.p, h->fw_cnt.p,
+                                          h->lr_ptr.p, nullptr, h->lr_col.p,
+                                          reinterpret_cast<T*>(h->lr_val.p));
+  });
   CK(hipGetLastError());
   // dependency levels (actual graph of the factor) on the device, then the
   // blocks of each direction ordered by (level, index)
@@ -847,14 +890,23 @@ bilu_status build_apply_plan(bilu_handle* h) {
 #undef CK
 }
 
+// W values the apply reads: the stored ones, or their FP32 copy.
+template <class T>
+static const T* apply_w(const bilu_handle* h) {
+  return reinterpret_cast<const T*>(h->apply_prec == h->fv.vprec ? h->fv.val
+                                                                  : (const void*)h->d_apply_val.p);
+}
+
 // One launch per dependency level (forward_level, backward_level).
+template <class T>
 static void apply_levels_launch(bilu_handle* h, const double* x, double* y, double* t) {
   hipStream_t st = h->stream;
-  SweepArgs a{};
+  SweepArgs<T> a{};
   a.f = h->fv;
   a.lr_ptr = h->lr_ptr.p;
   a.lr_col = h->lr_col.p;
-  a.lr_val = h->lr_val.p;
+  a.lr_val = reinterpret_cast<const T*>(h->lr_val.p);
+  a.wval = apply_w<T>(h);
   a.sched = h->lev_f.p;
   a.fq = h->lev_f_fq.p;
   const int nf = (int)h->lev_f_ptr.size() - 1;
@@ -881,14 +933,17 @@ bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t
     e1 = h->ev_get();
     if (e0) (void)hipEventRecord(e0, st);
   }
+  with_value_type(h->apply_prec, [&](auto tag) {
+  using T = decltype(tag);
   if (h->opt.apply_path == 1) {
-    apply_levels_launch(h, x, y, t);
+    apply_levels_launch<T>(h, x, y, t);
   } else {
-    FlowApplyArgs a{};
+    FlowApplyArgs<T> a{};
     a.f = h->fv;
     a.lr_ptr = h->lr_ptr.p;
     a.lr_col = h->lr_col.p;
-    a.lr_val = h->lr_val.p;
+    a.lr_val = reinterpret_cast<const T*>(h->lr_val.p);
+    a.wval = apply_w<T>(h);
     a.fq = h->lev_f_fq.p;
     a.lev_b = h->lev_b.p;
     a.nb = (int)h->fv.nb;
@@ -900,8 +955,9 @@ bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t
     a.wait_ticks = (h->wait_ticks ? h->wait_ticks : (unsigned long long)1e9) / 5;
     a.ticketed = h->opt.apply_path == 2 ? 1 : 0;
     apply_reset<<<grid_for(n), 256, 0, st>>>(n, a.t, a.z, a.err);
-    apply_flow<<<(unsigned)((2 * h->fv.nb + 3) / 4), 256, 0, st>>>(a);
+    apply_flow<T><<<(unsigned)((2 * h->fv.nb + 3) / 4), 256, 0, st>>>(a);
   }
+  });
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_check(h, e, "apply launch");
   if (h->opt.collect_timing) {
