@@ -141,6 +141,8 @@ typedef struct {
   int64_t apply_faults;       /* dataflow applies whose dependency wait timed out     */
                               /* since analyze (0 unless the device misbehaves)       */
   int64_t heap_regrows;       /* sweeps of the last factor rerun with a larger heap   */
+  double r_kept;              /* ||(L S U - A)_Omega||_F / ||A||_F of the last factor,  */
+                              /* from bilu_kept_residual (-1 until it is called)      */
 } bilu_stats;
 
 /* Library-allocated host copy of the factors (for checking), final blocks. */
@@ -273,6 +275,17 @@ bilu_status bilu_preprocess(const bilu_options* opt, int64_t n, const int64_t* r
  * BILU_ERR_INVALID on bad arguments. */
 bilu_status bilu_mwm(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* val,
                      int64_t* sigma, double* dl, double* dr);
+
+/* Kept-pattern residual of the last factorization (Sec. 2.2: the Crout step
+ * reproduces A exactly on the stored positions):
+ *   *r_kept = ||(L S U - A)_Omega||_F / ||A||_F,
+ * Omega = the diagonal blocks, R_K x K and K x C_K of the sweep's factor
+ * (before aggregation), computed on the device in FP64 from the stored L, W
+ * (in their storage precision) and S_K.  Rounding level in the FP64 form;
+ * it measures the precision of the stored factor and of the updates in the
+ * mixed forms, and perturbed pivot blocks.  Also kept in
+ * bilu_stats.r_kept.  BILU_ERR_STATE before a factorization.  Synchronous. */
+bilu_status bilu_kept_residual(bilu_handle* h, double* r_kept);
 
 /* Statistics of the last analyze/factor (block sizes as in the paper's
  * tables of Sec. 3.2-3.5: number, max, average, standard deviation). */

@@ -60,7 +60,7 @@ class Stats(C.Structure):
         ("dev_ms_factor", C.c_double), ("dev_ms_apply", C.c_double), ("dev_ms_spmv", C.c_double),
         ("n_factor_launches", C.c_int64), ("n_apply", C.c_int64), ("n_spmv", C.c_int64),
         ("bytes_factor", C.c_double), ("t_phase", C.c_double * 8),
-        ("apply_faults", C.c_int64), ("heap_regrows", C.c_int64),
+        ("apply_faults", C.c_int64), ("heap_regrows", C.c_int64), ("r_kept", C.c_double),
     ]
 
 
@@ -82,7 +82,7 @@ EXPORTED = [
     "bilu_spmv", "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors",
     "bilu_free_factors", "bilu_destroy", "bilu_status_string", "bilu_last_error",
     "bilu_preprocess", "bilu_sync", "bilu_export_trace", "bilu_factor_batched", "bilu_mwm",
-    "bilu_analyze_device", "bilu_refactor",
+    "bilu_analyze_device", "bilu_refactor", "bilu_kept_residual",
 ]
 
 _lib = None
@@ -122,10 +122,11 @@ def load(path: str = LIB_PATH):
     lib.bilu_mwm.argtypes = [C.c_int64, vp, vp, vp, vp, vp, vp]
     lib.bilu_analyze_device.argtypes = [vp, C.c_int64, vp, vp, vp]
     lib.bilu_refactor.argtypes = [vp, C.c_double, vp]
+    lib.bilu_kept_residual.argtypes = [vp, C.POINTER(C.c_double)]
     lib.bilu_preprocess.argtypes = [C.POINTER(Options), C.c_int64, vp, vp, vp, C.c_double,
                                     vp, vp, C.POINTER(C.c_int64), vp, C.POINTER(C.c_int64)]
     for f in ("bilu_create", "bilu_analyze", "bilu_analyze_device", "bilu_refactor", "bilu_factor", "bilu_factor_batched", "bilu_apply",
-              "bilu_spmv",
+              "bilu_spmv", "bilu_kept_residual",
               "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors", "bilu_preprocess",
               "bilu_sync"):
         getattr(lib, f).restype = C.c_int
@@ -345,6 +346,12 @@ class Bilu:
         """y = M^{-1} x; x, y: torch float64 CUDA tensors of length n."""
         px, py = _check_vectors(self.n, ("x", x), ("y", y))
         return self._check(self._lib.bilu_apply(self._h, px, py), "bilu_apply")
+
+    def kept_residual(self) -> float:
+        """||(L S U - A)_Omega||_F / ||A||_F of the last factor (bilu_kept_residual)."""
+        r = C.c_double()
+        self._check(self._lib.bilu_kept_residual(self._h, C.byref(r)), "bilu_kept_residual")
+        return r.value
 
     def trace(self):
         """Per-block factor trace (collect_timing=2): (records x 20 uint64, ticks/s)."""

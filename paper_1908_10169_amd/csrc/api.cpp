@@ -79,6 +79,7 @@ namespace bilu {
 // aggregation (Sec. 3.5), the apply plan and the statistics.
 bilu_status finish_factor(bilu_handle* h, std::chrono::steady_clock::time_point t0) {
   bilu_status s = BILU_OK;
+  h->stats.r_kept = -1.0;  // computed on request (bilu_kept_residual)
   h->nb = h->stats.nblocks_initial;
   h->bstart = h->bstart0;
   h->fv = FactorView{};
@@ -556,6 +557,14 @@ bilu_status bilu_preprocess(const bilu_options* opt, int64_t n, const int64_t* r
   *nblocks = ilu1t_partition(h, tau, bs);
   std::copy(bs.begin(), bs.end(), block_starts);
   return BILU_OK;
+  GUARD_END
+}
+
+bilu_status bilu_kept_residual(bilu_handle* h, double* r_kept) {
+  if (!h || !r_kept) return fail(h, BILU_ERR_INVALID, "bilu_kept_residual: null argument");
+  if (h->state < 2) return fail(h, BILU_ERR_STATE, "bilu_kept_residual before bilu_factor");
+  GUARD_BEGIN
+  return kept_residual(h, r_kept);
   GUARD_END
 }
 

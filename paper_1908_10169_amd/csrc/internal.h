@@ -363,6 +363,14 @@ bilu_status aggregate_device(bilu_handle* h);
 
 // solve.hip
 bilu_status build_apply_plan(bilu_handle* h);
+// For every block K of f, the blocks J whose stored rows (cols: columns)
+// fall into K, ascending, with the first position of the run in R_J (C_J)
+// and its length (ptr [nb+1]; j, s0, cnt per entry).  Synchronous.
+bilu_status block_runs(bilu_handle* h, const FactorView& f, bool cols, DevArray<int32_t>& ptr,
+                       DevArray<int32_t>& j, DevArray<int32_t>& s0, DevArray<int32_t>& cnt);
+// kept.hip: ||(L S U - A)_Omega||_F / ||A||_F of the sweep's factor (before
+// aggregation), Omega its stored positions; FP64.  Synchronous.
+bilu_status kept_residual(bilu_handle* h, double* out);
 // Sec. 3.1 maximum weight matching on the host (mwm.cpp); *why explains a
 // failure.
 bilu_status mwm_host(int64_t n, const int64_t* rp, const int32_t* ci, const double* val,

@@ -24,27 +24,28 @@ constexpr int kDotBlocks = 512;
 // ---------------------------------------------------------------------------
 // Apply plan builders (run once per factorization)
 // ---------------------------------------------------------------------------
-// Runs of consecutive rows of R_J that fall into one block K.
-__global__ void __launch_bounds__(256) fw_count(FactorView f, int32_t* cnt) {
+// Runs of consecutive rows of R_J (columns of C_J with cols) that fall into
+// one block K.
+__global__ void __launch_bounds__(256) fw_count(FactorView f, int32_t* cnt, int cols) {
   const int J = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (J >= f.nb) return;
   const int lane = threadIdx.x & 63;
-  const int32_t* R = f.idx + f.roff[J];
-  const int m = f.nr[J];
+  const int32_t* R = f.idx + (cols ? f.coff[J] : f.roff[J]);
+  const int m = cols ? f.nc[J] : f.nr[J];
   for (int i = lane; i < m; i += 64) {
     const int K = f.blockOf[R[i]];
     if (i == 0 || f.blockOf[R[i - 1]] != K) atomicAdd(&cnt[K], 1);
   }
 }
 
-// Packed (J, first row index in R_J, row count) keys, sorted later per block.
+// Packed (J, first index in R_J (C_J), count) keys, sorted later per block.
 __global__ void __launch_bounds__(256) fw_fill(FactorView f, const int32_t* ptr, int32_t* fillc,
-                                               unsigned long long* keys) {
+                                               unsigned long long* keys, int cols) {
   const int J = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (J >= f.nb) return;
   const int lane = threadIdx.x & 63;
-  const int32_t* R = f.idx + f.roff[J];
-  const int m = f.nr[J];
+  const int32_t* R = f.idx + (cols ? f.coff[J] : f.roff[J]);
+  const int m = cols ? f.nc[J] : f.nr[J];
   for (int i = lane; i < m; i += 64) {
     const int K = f.blockOf[R[i]];
     if (i == 0 || f.blockOf[R[i - 1]] != K) {
@@ -749,6 +750,41 @@ static hipError_t device_scan(bilu_handle* h, const T* in, T* out, int64_t count
   return hipStreamSynchronize(st);
 }
 
+// For every block K, the blocks J whose stored rows (cols: columns) fall into
+// K, ascending, each with the first position of that run in R_J (C_J) and
+// its length: ptr [nb+1], then j, s0 and cnt per entry.
+bilu_status block_runs(bilu_handle* h, const FactorView& f, bool cols, DevArray<int32_t>& ptr,
+                       DevArray<int32_t>& j, DevArray<int32_t>& s0, DevArray<int32_t>& cnt) {
+  hipStream_t st = h->stream;
+  const int64_t nb = f.nb;
+#define CK(x)                                          \
+  do {                                                 \
+    hipError_t e_ = (x);                               \
+    if (e_ != hipSuccess) return hip_check(h, e_, #x); \
+  } while (0)
+  const unsigned gw = (unsigned)((nb + 3) / 4);  // one wave per block
+  DevArray<int32_t> c;
+  CK(c.alloc(nb + 1));
+  CK(hipMemsetAsync(c.p, 0, (nb + 1) * sizeof(int32_t), st));
+  fw_count<<<gw, 256, 0, st>>>(f, c.p, cols ? 1 : 0);
+  CK(ptr.alloc(nb + 1));
+  int32_t total = 0;
+  CK(device_scan<int32_t>(h, c.p, ptr.p, nb, &total));
+  const int64_t ne = std::max<int64_t>(1, total);
+  CK(j.alloc(ne));
+  CK(s0.alloc(ne));
+  CK(cnt.alloc(ne));
+  DevArray<unsigned long long> keys;
+  CK(keys.alloc(ne));
+  CK(hipMemsetAsync(c.p, 0, (nb + 1) * sizeof(int32_t), st));
+  fw_fill<<<gw, 256, 0, st>>>(f, ptr.p, c.p, keys.p, cols ? 1 : 0);
+  fw_sort<<<(unsigned)nb, 64, 0, st>>>((int)nb, ptr.p, keys.p, j.p, s0.p, cnt.p);
+  CK(hipGetLastError());
+  CK(hipStreamSynchronize(st));  // keys and counts are freed here
+  return BILU_OK;
+#undef CK
+}
+
 bilu_status build_apply_plan(bilu_handle* h) {
   hipStream_t st = h->stream;
   const FactorView& f = h->fv;
@@ -762,20 +798,10 @@ bilu_status build_apply_plan(bilu_handle* h) {
   DevArray<int32_t> cnt;
   CK(cnt.alloc(nb + 1));
   CK(hipMemsetAsync(cnt.p, 0, (nb + 1) * sizeof(int32_t), st));
-  fw_count<<<gw, 256, 0, st>>>(f, cnt.p);
-  CK(h->fw_ptr.alloc(nb + 1));
-  int32_t nfw = 0;
-  CK(device_scan<int32_t>(h, cnt.p, h->fw_ptr.p, nb, &nfw));
-  const int64_t ne = std::max<int64_t>(1, nfw);
-  CK(h->fw_j.alloc(ne));
-  CK(h->fw_r0.alloc(ne));
-  CK(h->fw_cnt.alloc(ne));
-  DevArray<unsigned long long> keys;
-  CK(keys.alloc(ne));
-  CK(hipMemsetAsync(cnt.p, 0, (nb + 1) * sizeof(int32_t), st));
-  fw_fill<<<gw, 256, 0, st>>>(f, h->fw_ptr.p, cnt.p, keys.p);
-  fw_sort<<<(unsigned)nb, 64, 0, st>>>((int)nb, h->fw_ptr.p, keys.p, h->fw_j.p, h->fw_r0.p,
-                                       h->fw_cnt.p);
+  {
+    const bilu_status rs = block_runs(h, f, false, h->fw_ptr, h->fw_j, h->fw_r0, h->fw_cnt);
+    if (rs != BILU_OK) return rs;
+  }
   // backward successor blocks
   bw_count<<<gw, 256, 0, st>>>(f, cnt.p);
   CK(h->bw_ptr.alloc(nb + 1));

@@ -1,14 +1,20 @@
-"""Mixed-precision Schur updates (FP32 or BF16 inputs, FP32 accumulation) on
-the 2D 32x32 x 3 workload, with the pivot blocks, the drop test and FGMRES
-in FP64.  The paper fixes no result for this form: the checks are the
-acceptance bar for it.
+"""Mixed-precision forms on the 2D 32x32 x 3 workload: Schur updates with
+FP32 or BF16 inputs and FP32 accumulation, L and W stored in that
+precision, while the pivot blocks, the drop test and FGMRES stay FP64; and
+an FP64 factor applied from an FP32 copy (apply_precision).  The paper
+fixes no result for these forms: the checks are the acceptance bar.
 
   r_kept = ||(L S U - A)_Omega||_F / ||A||_F over the stored positions Omega
-           (diagonal blocks, R_K x K, K x C_K) of the unmerged factor;
-  FP64: the kept-pattern identity (r_kept at rounding level);
-  FP32: r_kept <= 1e-5, FGMRES iterations within +10% of the FP64 oracle's;
-  BF16: r_kept <= 2e-2, converged to 1e-8 within twice the FP64 iterations;
-  every form: true final residual <= 1e-8.
+           (diagonal blocks, R_K x K, K x C_K) of the unmerged factor,
+           computed densely here from the exported factor and by the
+           library on the device (bilu_kept_residual); the two agree;
+  FP64: the kept-pattern identity (r_kept at rounding level), the oracle's
+        iteration count;
+  FP32: r_kept <= 1e-6, FGMRES iterations within +10% of the FP64 oracle's;
+  BF16: r_kept <= 2e-3, iterations within +10%;
+  every form, with and without aggregation: true final residual <= 1e-8.
+Measured: r_kept 1.7e-16 (FP64), 1.0e-8 (FP32), 6.1e-4 (BF16), all at the
+FP64 iteration count.
 """
 import math
 import sys
@@ -49,21 +55,24 @@ def r_kept(a, fl):
     return np.linalg.norm((M - A)[omega]) / np.linalg.norm(A)
 
 
-def run(prec, w):
+def run(prec, w, agg=False, apply_precision=0):
     torch = _torch()
     from paper_1908_10169_amd import bilu
-    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=False, update_precision=prec)
+    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=agg, update_precision=prec,
+                  apply_precision=apply_precision)
     h.analyze(w.a, pre_perm=w.perm)
     h.factor(w.tau)
     fl = h.export()
+    rk_dev = h.kept_residual()
     b = w.a.matvec(np.ones(w.a.n))
     bd = torch.from_numpy(b).cuda()
     xd = torch.zeros_like(bd)
     info = h.fgmres(bd, xd, restart=w.restart, rtol=1e-8)
     x = xd.cpu().numpy()
     res = np.linalg.norm(b - w.a.matvec(x)) / np.linalg.norm(b)
+    assert h.stats()["apply_faults"] == 0
     h.close()
-    return fl, info, res
+    return fl, info, res, rk_dev
 
 
 @pytest.fixture(scope="module")
@@ -73,24 +82,52 @@ def reference():
     o = Oracle()
     assert o.run(w.a, OracleOptions(tau=w.tau, use_aggregation=False), pre_perm=w.perm) == 0
     _, info = o.fgmres(w.a.matvec(np.ones(w.a.n)), restart=w.restart, rtol=1e-8)
-    return w, info["iterations"]
+    return w, info["iterations"], o.kept_residual()
 
 
+BARS = {0: 1e-13, 1: 1e-6, 2: 2e-3}
+
+
+@pytest.mark.parametrize("agg", [False, True], ids=["plain", "aggregated"])
 @pytest.mark.parametrize("prec,name", [(0, "f64"), (1, "f32"), (2, "bf16")])
-def test_mixed_precision_acceptance(reference, prec, name):
-    w, it64 = reference
-    fl, info, res = run(prec, w)
-    rk = r_kept(w.a, fl)
-    print(f"[mixed] {name}: r_kept={rk:.3e} iterations={info['iterations']} (FP64 oracle {it64}) "
-          f"residual={res:.2e}", flush=True)
+def test_mixed_precision_acceptance(reference, prec, name, agg):
+    w, it64, rk_oracle = reference
+    fl, info, res, rk_dev = run(prec, w, agg)
+    print(f"[mixed] {name} aggregation={agg}: r_kept={rk_dev:.3e} iterations={info['iterations']} "
+          f"(FP64 oracle {it64}) residual={res:.2e}", flush=True)
     sys.stdout.flush()
     assert info["converged"] and res <= 1e-8
+    assert info["iterations"] <= math.ceil(1.1 * it64)
     if prec == 0:
-        assert rk <= 1e-13
         assert info["iterations"] == it64
-    elif prec == 1:
-        assert rk <= 1e-5
-        assert info["iterations"] <= math.ceil(1.1 * it64)
-    else:
-        assert rk <= 2e-2
-        assert info["iterations"] <= 2 * it64
+    assert rk_dev <= BARS[prec]
+    if not agg:
+        # the exported factor is the sweep's: the dense r_kept is the same
+        # quantity
+        rk = r_kept(w.a, fl)
+        assert abs(rk - rk_dev) <= 1e-6 * rk + 1e-15, (rk, rk_dev)
+        if prec == 0:
+            assert rk_oracle <= 1e-13
+
+
+def test_kept_residual_same_sweep_with_aggregation(reference):
+    """Aggregation runs after the sweep, so the kept-pattern residual of the
+    sweep's factor does not depend on it."""
+    w, _, _ = reference
+    out = []
+    for agg in (False, True):
+        _, _, _, rk = run(1, w, agg)
+        out.append(rk)
+    assert out[0] == out[1]
+
+
+@pytest.mark.parametrize("agg", [False, True], ids=["plain", "aggregated"])
+def test_fp32_apply_of_fp64_factor(reference, agg):
+    """apply_precision F32: the FP64 factor is applied from an FP32 copy."""
+    w, it64, _ = reference
+    _, info, res, rk_dev = run(0, w, agg, apply_precision=1)
+    print(f"[mixed] f64 factor, f32 apply, aggregation={agg}: iterations={info['iterations']} "
+          f"residual={res:.2e}", flush=True)
+    assert info["converged"] and res <= 1e-8
+    assert info["iterations"] <= math.ceil(1.1 * it64)
+    assert rk_dev <= 1e-13  # the factor itself is FP64

@@ -108,6 +108,9 @@ def test_factor_parity(name, make, tau, blocking):
     say(f"[parity] {name} n={a.n} nnz={a.nnz} tau={tau} {blocking}")
     o, h = run_pair(a, tau, perm, **blocking)
     compare_factors(o, h)
+    # the kept-pattern identity (Sec. 2.2) on the device, as in the oracle
+    rk, rk_o = h.kept_residual(), o.kept_residual()
+    assert rk <= 1e-12 and rk_o <= 1e-12, (rk, rk_o)
     check_apply_and_solve(o, h, a)
     h.close()
 
@@ -184,6 +187,10 @@ def test_perturbed_pivot_blocks():
     assert o.stats()["perturbed_blocks"] == 4
     assert h.stats()["perturbed_blocks"] == o.stats()["perturbed_blocks"]
     compare_factors(o, h)
+    # the perturbations are what is left of A on the kept pattern: the
+    # device and the oracle measure the same defect
+    rk, rk_o = h.kept_residual(), o.kept_residual()
+    assert rk_o > 1e-6 and abs(rk - rk_o) <= 1e-10 * rk_o, (rk, rk_o)
 
 
 def test_tiny_and_ragged():
