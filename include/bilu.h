@@ -102,6 +102,12 @@ typedef struct {
                          /* With FP32 or BF16 updates, L and W are stored in that   */
                          /* precision and the apply reads them as stored; D and the */
                          /* vectors are FP64 in every form                           */
+  int update_mfma;       /* 1: the Schur-update terms of blocks up to 16 wide are  */
+                         /* computed as 16x16 matrix-core tiles (FP64 16x16x4, FP32 */
+                         /* 16x16x4 or BF16 16x16x16 with FP32 accumulation); 0     */
+                         /* (default): scalar fused multiply-adds, which measure    */
+                         /* faster on narrow blocks.  Both give the same patterns   */
+                         /* up to rounding of the products                           */
 } bilu_options;
 
 typedef struct bilu_handle bilu_handle;
@@ -218,7 +224,7 @@ bilu_status bilu_refactor(bilu_handle* h, double tau, const double* val);
  * taus[i]; every handle ends as bilu_factor(hs[i], taus[i]) would leave it,
  * with the same factor bit for bit.  The handles must be distinct, on the
  * same device, and agree in drop_norm, beta_one, perturb_tau, perturb_rho,
- * pivot_eps, update_precision and factor_path (BILU_ERR_INVALID
+ * pivot_eps, update_precision, update_mfma and factor_path (BILU_ERR_INVALID
  * otherwise); blocking and aggregation options may differ.  The launch runs
  * on hs[0]'s stream.  The device counters of the launch (flops_update, the
  * update part of bytes_factor, dev_ms_factor, factor_levels) describe the

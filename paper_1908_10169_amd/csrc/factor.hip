@@ -1257,6 +1257,191 @@ __device__ __forceinline__ AEntry a_entry(const FactorArgs& a, const Lds& s, con
   return {a.rv + m, tgt};
 }
 
+// ---------------------------------------------------------------------------
+// Schur-update terms on the matrix cores.  The terms of one predecessor J
+// form a dense product T = L_J(rows, :) W_J(:, cols) of size M x N with
+// contraction p_J (Sec. 2.2, Fig. 2): for a column predecessor the rows of
+// R_J at or below first(K) times the columns of C_J inside K; for a row
+// predecessor the rows of R_J inside K times the columns of C_J beyond K.
+// A wave computes one 16 x 16 tile of T with v_mfma 16x16 instructions,
+// each lane loading its operand fragments straight from the factor heap
+// (one value of L and one of W per lane and k-step, instead of a whole row
+// and column per term), and writes each term with its panel position to
+// Tm / Ti exactly as the scalar loop does, so the ordered accumulation that
+// follows is unchanged.  FP64 inputs use the FP64 instruction (16x16x4),
+// FP32 inputs 16x16x4 with FP32 accumulation, BF16 inputs 16x16x16 with
+// FP32 accumulation.  Lane layout (checked on the device): operand lane l
+// holds row (column) l % 16 of k-group l / 16; the result element i of lane
+// l is row 4 (l / 16) + i (FP64: l / 16 + 4 i) of column l % 16.
+// kG: the staged lists and panels live in the worker's global slot.
+// ---------------------------------------------------------------------------
+// 16-byte loads of stored factor values at their natural alignment (the
+// hardware accepts loads aligned to their element size)
+typedef double wide_f64 __attribute__((ext_vector_type(2), aligned(8)));
+typedef float wide_f32 __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint16_t wide_bf16 __attribute__((ext_vector_type(8), aligned(2)));
+// Slack in values after the end of the value heap: the last 16-byte load of
+// a row may reach past the last stored value.
+constexpr int64_t kHeapSlack = 16;
+
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+typedef short mfma_s4 __attribute__((ext_vector_type(4)));
+
+template <int kPrec>
+struct TileAcc;
+template <>
+struct TileAcc<0> {
+  using T = mfma_d4;
+};
+template <>
+struct TileAcc<1> {
+  using T = mfma_f4;
+};
+template <>
+struct TileAcc<2> {
+  using T = mfma_f4;
+};
+
+// Operand fragment of one lane for k-step k0: FP64 / FP32 one value, BF16
+// four (k = k0 + 4 kg + j); off = -1 or k >= p pads with zero.
+template <int kPrec>
+struct Frag;
+template <>
+struct Frag<0> {
+  using T = double;
+  static constexpr int kStep = 4;
+  __device__ static T load(const void* v, int64_t off, int k0, int kg, int p) {
+    const int k = k0 + kg;
+    return (off >= 0 && k < p) ? static_cast<const double*>(v)[off + k] : 0.0;
+  }
+};
+template <>
+struct Frag<1> {
+  using T = float;
+  static constexpr int kStep = 4;
+  __device__ static T load(const void* v, int64_t off, int k0, int kg, int p) {
+    const int k = k0 + kg;
+    return (off >= 0 && k < p) ? static_cast<const float*>(v)[off + k] : 0.0f;
+  }
+};
+template <>
+struct Frag<2> {
+  using T = mfma_s4;
+  static constexpr int kStep = 16;
+  __device__ static T load(const void* v, int64_t off, int k0, int kg, int p) {
+    T x;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int k = k0 + 4 * kg + j;
+      x[j] = (short)((off >= 0 && k < p) ? static_cast<const uint16_t*>(v)[off + k] : 0);
+    }
+    return x;
+  }
+};
+template <int kPrec>
+__device__ __forceinline__ typename TileAcc<kPrec>::T mfma_step(typename Frag<kPrec>::T x,
+                                                                typename Frag<kPrec>::T y,
+                                                                typename TileAcc<kPrec>::T c) {
+  if constexpr (kPrec == 0)
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+  else if constexpr (kPrec == 1)
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, c, 0, 0, 0);
+}
+
+// Geometry of one tile: its predecessor, the tile's rows a0.. and columns
+// b0.. of the product, and this lane's operand offsets.
+struct TileGeo {
+  int t, M, N, a0, b0;
+  int64_t la, wb;
+  int p;
+  bool live;
+};
+
+// Values of the terms e in [i0, i1) of all predecessors into Tm (their
+// panel positions are already in Ti).  Each wave takes kTiles tiles at a
+// time: their operand fragments for one k-step are loaded together, then
+// their matrix-core steps issued, so the loads of several tiles are in
+// flight at once.  fmeta[t].pad holds the first tile of predecessor t,
+// ntiles their total.
+template <int kPrec>
+__device__ __forceinline__ void mfma_terms(const FactorArgs& a, const PredMeta* fmeta, int npt,
+                                           int np, int i0, int i1, double* Tm, int ntiles) {
+  constexpr int kTiles = 4;
+  const int lane = threadIdx.x & 63, kg = lane >> 4;
+  const int nw = blockDim.x >> 6;
+  for (int base = (int)(threadIdx.x >> 6); base < ntiles; base += nw * kTiles) {
+    TileGeo g[kTiles];
+    int pmax = 0;
+#pragma unroll
+    for (int u = 0; u < kTiles; ++u) {
+      const int task = base + u * nw;
+      g[u].live = false;
+      g[u].la = g[u].wb = -1;
+      g[u].p = 0;
+      g[u].t = g[u].M = g[u].N = g[u].a0 = g[u].b0 = 0;
+      if (task >= ntiles) continue;
+      int lo_t = 0, hi_t = npt;  // the predecessor: last t with first tile <= task
+      while (hi_t - lo_t > 1) {
+        const int mid = (lo_t + hi_t) >> 1;
+        if (fmeta[mid].pad <= task)
+          lo_t = mid;
+        else
+          hi_t = mid;
+      }
+      const int t = lo_t;
+      const PredMeta& m = fmeta[t];
+      const bool colp = t < np;
+      const int M = colp ? m.nr - m.lo2 : m.hi - m.lo;
+      const int N = colp ? m.hi - m.lo : m.nc - m.lo2;
+      const int tn = (N + 15) >> 4;
+      const int a0 = (task - m.pad) / tn * 16, b0 = (task - m.pad) % tn * 16;
+      const int a1 = min(M, a0 + 16), b1 = min(N, b0 + 16);
+      // the tile's first and last term (column predecessors number their
+      // terms row by row, row predecessors column by column)
+      const int emin = colp ? m.ioff + a0 * N + b0 : m.ioff + b0 * M + a0;
+      const int emax = colp ? m.ioff + (a1 - 1) * N + (b1 - 1) : m.ioff + (b1 - 1) * M + (a1 - 1);
+      if (emax < i0 || emin >= i1) continue;
+      const int ra = a0 + (lane & 15), cb = b0 + (lane & 15);
+      g[u] = TileGeo{t, M, N, a0, b0,
+                     ra < M ? m.loff + (int64_t)((colp ? m.lo2 : m.lo) + ra) * m.p : -1,
+                     cb < N ? m.woff + (int64_t)((colp ? m.lo : m.lo2) + cb) * m.p : -1, m.p,
+                     true};
+      pmax = max(pmax, m.p);
+    }
+    typename TileAcc<kPrec>::T acc[kTiles];
+#pragma unroll
+    for (int u = 0; u < kTiles; ++u) acc[u] = typename TileAcc<kPrec>::T{0, 0, 0, 0};
+    for (int k0 = 0; k0 < pmax; k0 += Frag<kPrec>::kStep) {
+      typename Frag<kPrec>::T x[kTiles], y[kTiles];
+#pragma unroll
+      for (int u = 0; u < kTiles; ++u) {
+        x[u] = Frag<kPrec>::load(a.val_heap, g[u].la, k0, kg, g[u].p);
+        y[u] = Frag<kPrec>::load(a.val_heap, g[u].wb, k0, kg, g[u].p);
+      }
+#pragma unroll
+      for (int u = 0; u < kTiles; ++u)
+        if (g[u].live && k0 < g[u].p) acc[u] = mfma_step<kPrec>(x[u], y[u], acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kTiles; ++u) {
+      if (!g[u].live) continue;
+      const bool colp = g[u].t < np;
+      const PredMeta& m = fmeta[g[u].t];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int ar = kPrec == 0 ? g[u].a0 + kg + 4 * i : g[u].a0 + 4 * kg + i;
+        const int bc = g[u].b0 + (lane & 15);
+        if (ar >= g[u].M || bc >= g[u].N) continue;
+        const int e = colp ? m.ioff + ar * g[u].N + bc : m.ioff + bc * g[u].M + ar;
+        if (e >= i0 && e < i1) Tm[e - i0] = (double)acc[u][i];
+      }
+    }
+  }
+}
+
 template <bool kG>
 __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const FlowArgs& d, int K,
                                                  Lds& s, double* s_dyn, double* gslot, int next_pos) {
@@ -1642,6 +1827,36 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     for (int t = tid; t < np + npr; t += nt) fmeta[t].ioff = fpred[t];
     __syncthreads();
   }
+  // matrix-core tiles: the first 16 x 16 tile of every predecessor's term
+  // product (in PredMeta::pad) and their total
+  int ntiles = 0;
+  if (a.mfma) {
+    __syncthreads();
+    if (tid < 64) {  // wave 0 scans 64 predecessors at a time
+      int base = 0;
+      for (int t0 = 0; t0 < np + npr; t0 += 64) {
+        const int t = t0 + tid;
+        int x = 0;
+        if (t < np + npr) {
+          const PredMeta& m = fmeta[t];
+          const int M = t < np ? m.nr - m.lo2 : m.hi - m.lo;
+          const int N = t < np ? m.hi - m.lo : m.nc - m.lo2;
+          x = ((M + 15) >> 4) * ((N + 15) >> 4);
+        }
+        int incl = x;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const int y = __shfl_up(incl, o, 64);
+          if (tid >= o) incl += y;
+        }
+        if (t < np + npr) fmeta[t].pad = base + incl - x;
+        base += __shfl(incl, 63, 64);
+      }
+      if (tid == 0) s.misc[30] = base;
+    }
+    __syncthreads();
+    ntiles = s.misc[30];
+  }
   if (tid == 0) {
     trace_at(d, K, 3, wall_clock64());
     trace_at(d, K, 16, (unsigned long long)np);
@@ -1678,6 +1893,14 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   constexpr int kU = 4;  // terms per thread in flight
   for (int i0 = 0; i0 < nterms; i0 += cap) {
     const int i1 = min(nterms, i0 + cap);
+    if (a.mfma) {
+      if (a.update_prec == 0)
+        mfma_terms<0>(a, fmeta, npt, np, i0, i1, Tm, ntiles);
+      else if (a.update_prec == 1)
+        mfma_terms<1>(a, fmeta, npt, np, i0, i1, Tm, ntiles);
+      else
+        mfma_terms<2>(a, fmeta, npt, np, i0, i1, Tm, ntiles);
+    }
     for (int e0 = i0 + tid; e0 < i1; e0 += kU * nt) {
       // (1) the predecessor and the (row, column) pair of each term
       // each term's row and column index: one from the staged lists (so),
@@ -1735,39 +1958,85 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
         cc[u] = colp[u] ? hv : sv;
       }
       double acc[kU];
-      if (a.update_prec == 0) {
+      if (a.mfma) {
+        // values come from the matrix-core tiles; only positions here
+      } else {
+        // the terms' values: each thread's kU dot products in step, the
+        // rows of L_J and columns of W_J read 16 bytes at a time (2 FP64,
+        // 4 FP32 or 8 BF16 values per load; the value heap has slack past
+        // its end for the last partial load), the products taken in index
+        // order with one fused multiply-add each, as update_term does
         int pmax = 0;
 #pragma unroll
         for (int u = 0; u < kU; ++u) pmax = max(pmax, pp[u]);
+        if (a.update_prec == 0) {
+          const double* v = static_cast<const double*>(a.val_heap);
 #pragma unroll
-        for (int u = 0; u < kU; ++u) acc[u] = 0.0;
-        for (int t0 = 0; t0 < pmax; t0 += 2) {
-          double x[kU][2], y[kU][2];
+          for (int u = 0; u < kU; ++u) acc[u] = 0.0;
+          for (int t0 = 0; t0 < pmax; t0 += 2) {
+            wide_f64 x[kU], y[kU];
 #pragma unroll
-          for (int u = 0; u < kU; ++u)
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-              // clamped in range; the products past p are not taken
-              const int t = min(t0 + k, max(pp[u] - 1, 0));
-              x[u][k] = static_cast<const double*>(a.val_heap)[lo[u] + t];
-              y[u][k] = static_cast<const double*>(a.val_heap)[wo[u] + t];
+            for (int u = 0; u < kU; ++u) {
+              // only while the row lasts: at most 1 values past its end
+              x[u] = t0 < pp[u] ? *reinterpret_cast<const wide_f64*>(v + lo[u] + t0) : wide_f64{};
+              y[u] = t0 < pp[u] ? *reinterpret_cast<const wide_f64*>(v + wo[u] + t0) : wide_f64{};
             }
 #pragma unroll
-          for (int u = 0; u < kU; ++u)
+            for (int u = 0; u < kU; ++u)
 #pragma unroll
-            for (int k = 0; k < 2; ++k)
-              if (t0 + k < pp[u]) acc[u] = fma(x[u][k], y[u][k], acc[u]);
+              for (int k = 0; k < 2; ++k)
+                if (t0 + k < pp[u]) acc[u] = fma(x[u][k], y[u][k], acc[u]);
+          }
+        } else if (a.update_prec == 1) {
+          const float* v = static_cast<const float*>(a.val_heap);
+          float fa[kU];
+#pragma unroll
+          for (int u = 0; u < kU; ++u) fa[u] = 0.0f;
+          for (int t0 = 0; t0 < pmax; t0 += 4) {
+            wide_f32 x[kU], y[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+              // only while the row lasts: at most 3 values past its end
+              x[u] = t0 < pp[u] ? *reinterpret_cast<const wide_f32*>(v + lo[u] + t0) : wide_f32{};
+              y[u] = t0 < pp[u] ? *reinterpret_cast<const wide_f32*>(v + wo[u] + t0) : wide_f32{};
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+              for (int k = 0; k < 4; ++k)
+                if (t0 + k < pp[u]) fa[u] = fmaf(x[u][k], y[u][k], fa[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < kU; ++u) acc[u] = (double)fa[u];
+        } else {
+          const uint16_t* v = static_cast<const uint16_t*>(a.val_heap);
+          float fa[kU];
+#pragma unroll
+          for (int u = 0; u < kU; ++u) fa[u] = 0.0f;
+          for (int t0 = 0; t0 < pmax; t0 += 8) {
+            wide_bf16 x[kU], y[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+              // only while the row lasts: at most 7 values past its end
+              x[u] = t0 < pp[u] ? *reinterpret_cast<const wide_bf16*>(v + lo[u] + t0) : wide_bf16{};
+              y[u] = t0 < pp[u] ? *reinterpret_cast<const wide_bf16*>(v + wo[u] + t0) : wide_bf16{};
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+#pragma unroll
+              for (int k = 0; k < 8; ++k)
+                if (t0 + k < pp[u]) fa[u] = fmaf(bf16_float(x[u][k]), bf16_float(y[u][k]), fa[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < kU; ++u) acc[u] = (double)fa[u];
         }
-      } else {
-#pragma unroll
-        for (int u = 0; u < kU; ++u) acc[u] = pp[u] ? update_term(a, lo[u], wo[u], pp[u]) : 0.0;
       }
       // (3) positions in the panels
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int e = e0 + u * nt;
         if (e < i1) {
-          Tm[e - i0] = acc[u];
+          if (!a.mfma) Tm[e - i0] = acc[u];
           Ti[e - i0] = colp[u] ? lower_bound(s.cand, mc, rr[u]) * q + (cc[u] - f)
                                : mc * q + lower_bound(s.candc, mcc, cc[u]) * q + (rr[u] - f);
         }
@@ -1775,6 +2044,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     }
     if (i0 == 0 && a_tgt >= 0) fbuf[a_tgt] = a_val;
     __syncthreads();
+    if (i0 == 0 && tid == 0) trace_at(d, K, 9, wall_clock64());  // first chunk's terms done
     // (4) in predecessor order (a predecessor's terms hit distinct
     // entries).  Column predecessors update only the column panel and row
     // predecessors only the row panel, so the k-th of each go together.
@@ -1803,7 +2073,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   if (tid == 0) {
     const unsigned long long now = wall_clock64();
     trace_at(d, K, 8, now);
-    trace_at(d, K, 9, now);
+    if (nterms == 0) trace_at(d, K, 9, now);
   }
 
   // ---- pivot block and drop test (shared with the general path)
@@ -2347,8 +2617,8 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
   // a heap or overflow pool that proves too small grows, and the sweep runs
   // again from the start
   for (int attempt = 0; attempt < 16; ++attempt) {
-    if ((int64_t)h->d_val_heap.n < val_cap * value_bytes(h->opt.update_precision))
-      CK(h->d_val_heap.alloc(val_cap * value_bytes(h->opt.update_precision)));
+    if ((int64_t)h->d_val_heap.n < (val_cap + kHeapSlack) * value_bytes(h->opt.update_precision))
+      CK(h->d_val_heap.alloc((val_cap + kHeapSlack) * value_bytes(h->opt.update_precision)));
     CK(h->d_ovf_j.alloc(ovf_cap));
     CK(h->d_ovf_next.alloc(ovf_cap));
     if ((int64_t)h->d_idx_heap.n < idx_cap) CK(h->d_idx_heap.alloc(idx_cap));
@@ -2413,6 +2683,7 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     a.drop_norm = h->opt.drop_norm;
     a.update_prec = h->opt.update_precision;
     a.fast_path = h->opt.factor_path == 0 ? 1 : h->opt.factor_path == 2 ? 2 : 0;
+    a.mfma = h->opt.update_mfma == 1 ? 1 : 0;
     a.lds_pivot = dyn > 0 ? 1 : 0;
     a.roff = h->d_roff.p; a.nr = h->d_nr.p; a.coff = h->d_coff.p; a.nc = h->d_nc.p;
     a.loff = h->d_loff.p; a.woff = h->d_woff.p; a.doff = h->d_doff.p;
@@ -2420,7 +2691,7 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     a.idx_heap = h->d_idx_heap.p; a.idx_cap = (int64_t)h->d_idx_heap.n; a.idx_top = h->d_counters.p + 0;
     a.elem_bytes = value_bytes(h->opt.update_precision);
     a.val_heap = h->d_val_heap.p;
-    a.val_cap = (int64_t)(h->d_val_heap.n / a.elem_bytes);
+    a.val_cap = (int64_t)(h->d_val_heap.n / a.elem_bytes) - kHeapSlack;
     a.val_top = h->d_counters.p + 1;
     // per-worker chunks: at most an eighth of either heap sits unused in them
     a.val_chunk = std::min<int64_t>(8192, a.val_cap / (8 * workers));

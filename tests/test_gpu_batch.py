@@ -3,6 +3,7 @@
 Each handle's factor must equal the one an individual bilu_factor computes
 (bit for bit: the same arithmetic per block) and the oracle's (partition,
 patterns, values within the tolerance, iteration counts)."""
+import math
 import sys
 
 import numpy as np
@@ -107,6 +108,7 @@ def test_batch64_one_launch():
         g.factor(ws[i].tau)
         assert factor_bytes(hs[i].export()) == factor_bytes(g.export()), i
         g.close()
+    it64 = []
     for w, h in zip(ws, hs):
         b = w.a.matvec(np.ones(w.a.n))
         bd = torch.from_numpy(b).cuda()
@@ -114,4 +116,53 @@ def test_batch64_one_launch():
         info = h.fgmres(bd, xd, restart=30, rtol=1e-8)
         res = np.linalg.norm(b - w.a.matvec(xd.cpu().numpy())) / np.linalg.norm(b)
         assert info["converged"] and res <= 1e-8, w.name
+        it64.append(info["iterations"])
+    # a seeded sample of the batch against the oracle: partition, patterns,
+    # values, iterations (the three smallest of eight drawn handles keep the
+    # oracle's time bounded)
+    from oracle import Oracle, OracleOptions
+    rng = np.random.default_rng(64)
+    drawn = sorted(rng.choice(64, size=8, replace=False), key=lambda i: ws[i].a.nnz)[:3]
+    for i in drawn:
+        w = ws[int(i)]
+        o = Oracle()
+        assert o.run(w.a, OracleOptions(tau=w.tau, use_aggregation=True), pre_perm=w.perm) == 0
+        fb, fo = hs[int(i)].export(), o.factors()
+        assert np.array_equal(fb.starts, fo.starts) and np.array_equal(fb.starts_initial,
+                                                                       fo.starts_initial), w.name
+        num = den = 0.0
+        for k in range(len(fo.starts) - 1):
+            assert np.array_equal(fb.R[k], fo.R[k]) and np.array_equal(fb.C[k], fo.C[k]), w.name
+            for x, y in ((fb.L[k], fo.L[k]), (fb.W[k], fo.W[k]), (fb.D[k], fo.D[k])):
+                num += float(np.sum((x - y) ** 2))
+                den += float(np.sum(y ** 2))
+        assert np.sqrt(num / den) <= 1e-10, w.name
+        _, info_o = o.fgmres(w.a.matvec(np.ones(w.a.n)), restart=30, rtol=1e-8)
+        assert it64[int(i)] == info_o["iterations"], w.name
+        say(f"[batch64] {w.name} (n={w.a.n}) equals the oracle")
+    for h in hs:
         h.close()
+    # the configuration's arithmetic: FP32 updates in one launch, FP64 pivot
+    # blocks and FGMRES; every system reaches 1e-8 within +10% of the FP64
+    # iterations
+    hs = []
+    for w in ws:
+        h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, update_precision=bilu.PREC_F32)
+        h.analyze(w.a, pre_perm=w.perm)
+        hs.append(h)
+    bilu.factor_batched(hs, [w.tau for w in ws])
+    say("[batch64] factored with FP32 updates")
+    worst = 0.0
+    for k, (w, h) in enumerate(zip(ws, hs)):
+        b = w.a.matvec(np.ones(w.a.n))
+        bd = torch.from_numpy(b).cuda()
+        xd = torch.zeros_like(bd)
+        info = h.fgmres(bd, xd, restart=30, rtol=1e-8)
+        res = np.linalg.norm(b - w.a.matvec(xd.cpu().numpy())) / np.linalg.norm(b)
+        assert info["converged"] and res <= 1e-8, w.name
+        assert info["iterations"] <= math.ceil(1.1 * it64[k]), (w.name, info["iterations"], it64[k])
+        worst = max(worst, info["iterations"] / it64[k])
+        if k in (0, 31, 63):
+            assert h.kept_residual() <= 1e-6, w.name
+        h.close()
+    say(f"[batch64] FP32: all converged; largest iteration ratio to FP64 {worst:.3f}")

@@ -1,0 +1,120 @@
+"""The 80^3 x 3 elasticity workload (n = 1,536,000, 121M nonzeros,
+tau = 5e-3, FGMRES(30)) at full size, in the benchmark's configuration.
+
+FP64: partition, every pattern, factors within 1e-10 (globally and within
+1e-8 for every single block) and the FGMRES iteration count equal the
+oracle's.  FP32 and BF16 updates (L and W stored in that precision): the
+true final residual reaches 1e-8 within +10% of the FP64 iterations, and
+the kept-pattern residual stays within the acceptance bar.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1908_10169_amd import matgen as mg
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+BLOCK_TOL = 1e-8
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def el80():
+    w = mg.workload("el3d_80_b3")
+    say(f"[el80] generated n={w.a.n} nnz={w.a.nnz}")
+    return w
+
+
+def solve(h, w):
+    torch = _torch()
+    b = w.a.matvec(np.ones(w.a.n))
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd)
+    info = h.fgmres(bd, xd, restart=w.restart, rtol=1e-8)
+    res = np.linalg.norm(b - w.a.matvec(xd.cpu().numpy())) / np.linalg.norm(b)
+    return info, res
+
+
+@pytest.fixture(scope="module")
+def el80_fp64(el80):
+    _torch()
+    from paper_1908_10169_amd import bilu
+    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL)
+    h.analyze(el80.a, pre_perm=el80.perm)
+    h.factor(el80.tau)
+    info, res = solve(h, el80)
+    say(f"[el80] fp64: iterations={info['iterations']} residual={res:.2e}")
+    out = dict(factors=h.export(), stats=h.stats(), info=info, res=res, r_kept=h.kept_residual())
+    h.close()
+    return out
+
+
+def test_full_size_el3d_80_fp64_parity(el80, el80_fp64):
+    from oracle import Oracle, OracleOptions
+    w = el80
+    say("[el80] oracle sweep")
+    o = Oracle()
+    assert o.run(w.a, OracleOptions(tau=w.tau, use_aggregation=True), pre_perm=w.perm) == 0
+    say("[el80] oracle done")
+    fl, fo = el80_fp64["factors"], o.factors()
+    assert el80_fp64["stats"]["merges"] == o.stats()["merges"]
+    assert np.array_equal(fl.perm, fo.perm)
+    assert np.array_equal(fl.starts_initial, fo.starts_initial)
+    assert np.array_equal(fl.starts, fo.starts)
+    for name in ("R", "C"):
+        x, y = getattr(fl, name), getattr(fo, name)
+        assert np.array_equal([len(v) for v in x], [len(v) for v in y]), name
+        assert np.array_equal(np.concatenate(x), np.concatenate(y)), name
+    worst = 0.0
+    for name in ("L", "W", "D"):
+        xs, ys = getattr(fl, name), getattr(fo, name)
+        x = np.concatenate([v.ravel() for v in xs])
+        y = np.concatenate([v.ravel() for v in ys])
+        assert np.linalg.norm(x - y) <= TOL * np.linalg.norm(y), name
+        for a, b in zip(xs, ys):
+            if b.size:
+                worst = max(worst, float(np.linalg.norm(a - b)) / max(float(np.linalg.norm(b)),
+                                                                      1e-300))
+    say(f"[el80] largest per-block relative difference {worst:.2e}")
+    assert worst <= BLOCK_TOL
+    b = w.a.matvec(np.ones(w.a.n))
+    _, info_o = o.fgmres(b, restart=w.restart, rtol=1e-8)
+    assert el80_fp64["info"]["converged"]
+    assert el80_fp64["info"]["iterations"] == info_o["iterations"]
+    assert el80_fp64["res"] <= 1e-8
+    assert el80_fp64["r_kept"] <= 1e-12
+
+
+@pytest.mark.parametrize("prec,name,bar", [(1, "f32", 1e-6), (2, "bf16", 2e-3)])
+def test_full_size_el3d_80_mixed(el80, el80_fp64, prec, name, bar):
+    _torch()
+    from paper_1908_10169_amd import bilu
+    w = el80
+    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, update_precision=prec)
+    h.analyze(w.a, pre_perm=w.perm)
+    h.factor(w.tau)
+    info, res = solve(h, w)
+    rk = h.kept_residual()
+    it64 = el80_fp64["info"]["iterations"]
+    say(f"[el80] {name}: iterations={info['iterations']} (FP64 {it64}) residual={res:.2e} "
+        f"r_kept={rk:.2e}")
+    assert info["converged"] and res <= 1e-8
+    assert info["iterations"] <= math.ceil(1.1 * it64)
+    assert rk <= bar
+    assert h.stats()["apply_faults"] == 0
+    h.close()

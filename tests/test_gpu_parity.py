@@ -58,7 +58,23 @@ def compare_factors(o, h):
     for name in num:
         rel = np.sqrt(num[name] / max(den[name], 1e-300))
         assert rel <= TOL, (name, rel)
+    worst = max_block_error(fl, fo)
+    assert worst <= BLOCK_TOL, worst
     return fl
+
+
+BLOCK_TOL = 1e-8  # per block: one wrong block stands out of the global norm
+
+
+def max_block_error(fl, fo):
+    """Largest relative difference of any single block's L, W or D."""
+    worst = 0.0
+    for name in ("L", "W", "D"):
+        for x, y in zip(getattr(fl, name), getattr(fo, name)):
+            if y.size:
+                worst = max(worst, float(np.linalg.norm(x - y)) / max(float(np.linalg.norm(y)),
+                                                                       1e-300))
+    return worst
 
 
 def check_apply_and_solve(o, h, a, restart=30):
@@ -309,6 +325,9 @@ def test_full_size_cd3d_64(agg):
         x = np.concatenate([v.ravel() for v in getattr(fl, name)])
         y = np.concatenate([v.ravel() for v in getattr(fo, name)])
         assert np.linalg.norm(x - y) <= TOL * np.linalg.norm(y), name
+    worst = max_block_error(fl, fo)
+    say(f"[full] largest per-block relative difference {worst:.2e}")
+    assert worst <= BLOCK_TOL
     b = w.a.matvec(np.ones(w.a.n))
     _, info_o = o.fgmres(b, restart=w.restart, rtol=1e-8)
     bd = torch.from_numpy(b).cuda()
