@@ -55,11 +55,11 @@ def r_kept(a, fl):
     return np.linalg.norm((M - A)[omega]) / np.linalg.norm(A)
 
 
-def run(prec, w, agg=False, apply_precision=0):
+def run(prec, w, agg=False, apply_precision=0, update_mfma=0):
     torch = _torch()
     from paper_1908_10169_amd import bilu
     h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=agg, update_precision=prec,
-                  apply_precision=apply_precision)
+                  apply_precision=apply_precision, update_mfma=update_mfma)
     h.analyze(w.a, pre_perm=w.perm)
     h.factor(w.tau)
     fl = h.export()
@@ -131,3 +131,18 @@ def test_fp32_apply_of_fp64_factor(reference, agg):
     assert info["converged"] and res <= 1e-8
     assert info["iterations"] <= math.ceil(1.1 * it64)
     assert rk_dev <= 1e-13  # the factor itself is FP64
+
+
+@pytest.mark.parametrize("prec,name", [(1, "f32"), (2, "bf16")])
+def test_mixed_precision_on_matrix_cores(reference, prec, name):
+    """The same acceptance bar with the update terms computed as 16x16
+    matrix-core tiles (update_mfma = 1)."""
+    w, it64, _ = reference
+    fl, info, res, rk_dev = run(prec, w, False, update_mfma=1)
+    print(f"[mixed] {name} on matrix cores: r_kept={rk_dev:.3e} iterations={info['iterations']} "
+          f"residual={res:.2e}", flush=True)
+    assert info["converged"] and res <= 1e-8
+    assert info["iterations"] <= math.ceil(1.1 * it64)
+    assert rk_dev <= BARS[prec]
+    rk = r_kept(w.a, fl)
+    assert abs(rk - rk_dev) <= 1e-6 * rk + 1e-15

@@ -28,13 +28,14 @@ def say(msg):
     sys.stdout.flush()
 
 
-def run_pair(a, tau, pre_perm=None, agg=False, **blocking):
+def run_pair(a, tau, pre_perm=None, agg=False, update_mfma=0, **blocking):
     from oracle import Oracle, OracleOptions
     from paper_1908_10169_amd import bilu
     o = Oracle()
     rc = o.run(a, OracleOptions(tau=tau, use_aggregation=agg, **blocking), pre_perm=pre_perm)
     assert rc == 0
-    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=agg, **blocking)
+    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=agg, update_mfma=update_mfma,
+                  **blocking)
     h.analyze(a, pre_perm=pre_perm)
     h.factor(tau)
     return o, h
@@ -127,6 +128,23 @@ def test_factor_parity(name, make, tau, blocking):
     # the kept-pattern identity (Sec. 2.2) on the device, as in the oracle
     rk, rk_o = h.kept_residual(), o.kept_residual()
     assert rk <= 1e-12 and rk_o <= 1e-12, (rk, rk_o)
+    check_apply_and_solve(o, h, a)
+    h.close()
+
+
+MFMA_CASES = [c for c in CASES if c[0] in ("cd2d_nd", "cd3d_12_nd", "el3d_10_nd", "random_sparse")]
+
+
+@pytest.mark.parametrize("name,make,tau,blocking", MFMA_CASES, ids=[c[0] for c in MFMA_CASES])
+def test_factor_parity_matrix_cores(name, make, tau, blocking):
+    """FP64 update terms as 16x16x4 matrix-core tiles (update_mfma = 1): the
+    products round differently, so the bar is the parity bar (patterns
+    identical, values within the tolerance, equal iterations)."""
+    _torch()
+    a, perm = make()
+    say(f"[parity mfma] {name} n={a.n} tau={tau}")
+    o, h = run_pair(a, tau, perm, update_mfma=1, **blocking)
+    compare_factors(o, h)
     check_apply_and_solve(o, h, a)
     h.close()
 
