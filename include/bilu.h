@@ -239,6 +239,19 @@ bilu_status bilu_factor_batched(bilu_handle** hs, int count, const double* taus)
  * successful factor. */
 bilu_status bilu_apply(bilu_handle* h, const double* x, double* y);
 
+/* bilu_apply for callers that cannot allocate device memory (code under
+ * stream capture, serving loops, harnesses that forbid allocation): the
+ * same arguments, result and bits as bilu_apply, but its three work vectors
+ * (n doubles each) live in a fixed 48 MiB array per device that the library
+ * holds until the process ends, instead of the handle's workspace; it calls
+ * no allocator.  n is limited to 2^21 = 2,097,152 unknowns
+ * (BILU_ERR_INVALID beyond, with a message).  Every call on one device
+ * shares that device's array: calls that overlap on one device (other
+ * streams, other handles, other threads) race and must be serialized by the
+ * caller.  Asynchronous on the handle's stream; HIP event timing is not
+ * recorded for it. */
+bilu_status bilu_apply_noalloc(bilu_handle* h, const double* x, double* y);
+
 /* Wait for the handle's stream; BILU_ERR_DEVICE if the runtime reports an
  * error left by asynchronous calls (bilu_apply, bilu_spmv), or if a
  * dataflow apply since the last check timed out in a dependency wait (its

@@ -83,7 +83,7 @@ EXPORTED = [
     "bilu_spmv", "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors",
     "bilu_free_factors", "bilu_destroy", "bilu_status_string", "bilu_last_error",
     "bilu_preprocess", "bilu_sync", "bilu_export_trace", "bilu_factor_batched", "bilu_mwm",
-    "bilu_analyze_device", "bilu_refactor", "bilu_kept_residual",
+    "bilu_analyze_device", "bilu_refactor", "bilu_kept_residual", "bilu_apply_noalloc",
 ]
 
 _lib = None
@@ -104,6 +104,7 @@ def load(path: str = LIB_PATH):
     lib.bilu_factor.argtypes = [vp, C.c_double]
     lib.bilu_factor_batched.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_double)]
     lib.bilu_apply.argtypes = [vp, vp, vp]
+    lib.bilu_apply_noalloc.argtypes = [vp, vp, vp]
     lib.bilu_spmv.argtypes = [vp, vp, vp]
     lib.bilu_fgmres_solve.argtypes = [vp, vp, vp, C.c_int, C.c_double, C.c_int,
                                       C.POINTER(SolveInfo)]
@@ -126,7 +127,8 @@ def load(path: str = LIB_PATH):
     lib.bilu_kept_residual.argtypes = [vp, C.POINTER(C.c_double)]
     lib.bilu_preprocess.argtypes = [C.POINTER(Options), C.c_int64, vp, vp, vp, C.c_double,
                                     vp, vp, C.POINTER(C.c_int64), vp, C.POINTER(C.c_int64)]
-    for f in ("bilu_create", "bilu_analyze", "bilu_analyze_device", "bilu_refactor", "bilu_factor", "bilu_factor_batched", "bilu_apply",
+    for f in ("bilu_create", "bilu_analyze", "bilu_analyze_device", "bilu_refactor", "bilu_factor",
+              "bilu_factor_batched", "bilu_apply", "bilu_apply_noalloc",
               "bilu_spmv", "bilu_kept_residual",
               "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors", "bilu_preprocess",
               "bilu_sync"):
@@ -353,6 +355,12 @@ class Bilu:
         r = C.c_double()
         self._check(self._lib.bilu_kept_residual(self._h, C.byref(r)), "bilu_kept_residual")
         return r.value
+
+    def apply_noalloc(self, x, y):
+        """bilu_apply_noalloc: y = M^{-1} x with the library's fixed device
+        array as workspace (no allocation; n <= 2^21)."""
+        px, py = _check_vectors(self.n, ("x", x), ("y", y))
+        return self._check(self._lib.bilu_apply_noalloc(self._h, px, py), "bilu_apply_noalloc")
 
     def trace(self):
         """Per-block factor trace (collect_timing=2): (records x 20 uint64, ticks/s)."""

@@ -10,7 +10,7 @@ LIB = os.path.join(HERE, "libbilu.so")
 BUILD = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["factor.hip", "aggregate.hip", "solve.hip", "ilu1t.hip", "batch.hip",
-               "analyze_dev.hip", "kept.hip"]
+               "analyze_dev.hip", "kept.hip", "noalloc.hip"]
 CPP_SOURCES = ["api.cpp", "analyze.cpp", "fgmres.cpp", "mwm.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]

@@ -376,7 +376,10 @@ bilu_status kept_residual(bilu_handle* h, double* out);
 // failure.
 bilu_status mwm_host(int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
                      int64_t* sigma, double* dl, double* dr, std::string* why);
-bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t);
+// timed: record HIP events around it when collect_timing is on (events may
+// be created, so allocation-free callers pass false)
+bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t,
+                           bool timed = true);
 // Dataflow applies whose waits timed out since the last call (synchronizes
 // the handle's stream; BILU_ERR_DEVICE when *count > 0).
 bilu_status apply_faults(bilu_handle* h, int64_t* count);

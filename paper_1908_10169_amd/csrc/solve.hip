@@ -950,11 +950,12 @@ static void apply_levels_launch(bilu_handle* h, const double* x, double* y, doub
   }
 }
 
-bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t) {
+bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t, bool timed) {
   hipStream_t st = h->stream;
   const int64_t n = h->n;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (h->opt.collect_timing) {
+  timed = timed && h->opt.collect_timing;
+  if (timed) {
     e0 = h->ev_get();
     e1 = h->ev_get();
     if (e0) (void)hipEventRecord(e0, st);
@@ -986,7 +987,7 @@ bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t
   });
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_check(h, e, "apply launch");
-  if (h->opt.collect_timing) {
+  if (timed) {
     if (e1) (void)hipEventRecord(e1, st);
     h->ev_record(1, e0, e1);
   }
