@@ -60,6 +60,9 @@ def parse():
                         "2: dataflow apply, slots by ticket")
     p.add_argument("--update-mfma", type=int, default=0, choices=[0, 1],
                    help="1: Schur-update terms as matrix-core tiles; 0: scalar FMAs")
+    p.add_argument("--deterministic", type=int, default=1, choices=[0, 1],
+                   help="1: update terms subtracted in a fixed order (bit-identical runs); "
+                        "0: with atomic adds")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                    help="only copy BYTES between two device buffers twice (reference for the "
                         "HBM byte counters of a profiler) and exit")
@@ -87,7 +90,8 @@ def time_form(w, prec, args, project, agg):
     from paper_1908_10169_amd import bilu
     opts = dict(ordering=bilu.ORDER_ND if project else bilu.ORDER_NATURAL, collect_timing=1,
                 update_precision=prec, apply_path=args.apply_path,
-                update_mfma=args.update_mfma, use_aggregation=agg)
+                update_mfma=args.update_mfma, use_aggregation=agg,
+                deterministic=args.deterministic)
     h = bilu.Bilu(**opts)
     t0 = time.perf_counter()
     h.analyze(w.a, pre_perm=None if project else w.perm)
@@ -225,6 +229,7 @@ def main():
             "ordering": "nested dissection of the compressed graph (library)" if project
             else "geometric nested dissection (caller permutation)",
             "update_precision": forms[0], "aggregation": agg, "update_mfma": args.update_mfma,
+            "deterministic": args.deterministic,
             "parallelism": "single GPU",
         },
         "roofline": roofline,

@@ -108,6 +108,13 @@ typedef struct {
                          /* (default): scalar fused multiply-adds, which measure    */
                          /* faster on narrow blocks.  Both give the same patterns   */
                          /* up to rounding of the products                           */
+  int deterministic;     /* 1 (default): every run gives the same bits: the update   */
+                         /* terms of a block are materialized and subtracted in     */
+                         /* predecessor order.  0: blocks up to 16 wide subtract     */
+                         /* each term as it is computed, with atomic adds (faster;  */
+                         /* results vary at rounding level between runs, patterns   */
+                         /* only where a drop norm is within rounding of tau).      */
+                         /* update_mfma = 1 implies 1                                */
 } bilu_options;
 
 typedef struct bilu_handle bilu_handle;
@@ -224,7 +231,8 @@ bilu_status bilu_refactor(bilu_handle* h, double tau, const double* val);
  * taus[i]; every handle ends as bilu_factor(hs[i], taus[i]) would leave it,
  * with the same factor bit for bit.  The handles must be distinct, on the
  * same device, and agree in drop_norm, beta_one, perturb_tau, perturb_rho,
- * pivot_eps, update_precision, update_mfma and factor_path (BILU_ERR_INVALID
+ * pivot_eps, update_precision, update_mfma, deterministic and factor_path
+ * (BILU_ERR_INVALID
  * otherwise); blocking and aggregation options may differ.  The launch runs
  * on hs[0]'s stream.  The device counters of the launch (flops_update, the
  * update part of bytes_factor, dev_ms_factor, factor_levels) describe the

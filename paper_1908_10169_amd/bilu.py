@@ -38,7 +38,7 @@ class Options(C.Structure):
         ("update_precision", C.c_int), ("heap_bytes", C.c_size_t),
         ("collect_timing", C.c_int), ("factor_path", C.c_int), ("apply_path", C.c_int),
         ("use_mwm", C.c_int), ("analyze_path", C.c_int), ("apply_precision", C.c_int),
-        ("update_mfma", C.c_int),
+        ("update_mfma", C.c_int), ("deterministic", C.c_int),
     ]
 
 

@@ -195,6 +195,7 @@ void bilu_default_options(bilu_options* o) {
   o->beta_one = 0;
   o->update_precision = BILU_PREC_F64;
   o->heap_bytes = 0;
+  o->deterministic = 1;
 }
 
 bilu_status bilu_create(bilu_handle** out, const bilu_options* opt, void* stream) {
@@ -216,7 +217,8 @@ bilu_status bilu_create(bilu_handle** out, const bilu_options* opt, void* stream
       h->opt.drop_norm > 1 || h->opt.factor_path < 0 || h->opt.factor_path > 2 ||
       h->opt.apply_path < 0 || h->opt.apply_path > 2 || h->opt.use_mwm < 0 || h->opt.use_mwm > 1 ||
       h->opt.analyze_path < 0 || h->opt.analyze_path > 1 || h->opt.apply_precision < 0 ||
-      h->opt.apply_precision > 1 || h->opt.update_mfma < 0 || h->opt.update_mfma > 1) {
+      h->opt.apply_precision > 1 || h->opt.update_mfma < 0 || h->opt.update_mfma > 1 ||
+      h->opt.deterministic < 0 || h->opt.deterministic > 1) {
     delete h;
     return BILU_ERR_INVALID;
   }

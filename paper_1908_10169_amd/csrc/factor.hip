@@ -1870,7 +1870,8 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   double* Rp = Cp + mc * q;             // mcc x q (column z of the row panel)
   double* Tm = Rp + mcc * q;            // update terms
   // a chunk holds cap terms and, after them, each term's panel position
-  const int cap = (cBuf - (mc + mcc) * q) * 2 / 3;
+  // (without a.det the terms go straight into the panels: one chunk)
+  const int cap = a.det ? (cBuf - (mc + mcc) * q) * 2 / 3 : max(nterms, 1);
   int* Ti = reinterpret_cast<int*>(Tm + cap);
   for (int e = tid; e < (mc + mcc) * q; e += nt) Cp[e] = 0.0;
   __syncthreads();
@@ -1878,7 +1879,12 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   const int nA0 = segoff[1], nA = segoff[2];
   for (int e = nt + tid; e < nA; e += nt) {  // beyond the first nt entries (rare)
     const AEntry x = a_entry(a, s, stage, e, nA0, f, l, q, mc, mcc);
-    if (x.tgt >= 0) fbuf[x.tgt] = *x.src;
+    if (x.tgt >= 0) {
+      if (a.det)
+        fbuf[x.tgt] = *x.src;
+      else
+        atomicAdd(&fbuf[x.tgt], *x.src);  // the terms may already be arriving
+    }
   }
   // the first nt: loaded now, stored with the first chunk of terms, so both
   // loads share one round trip
@@ -2036,14 +2042,25 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       for (int u = 0; u < kU; ++u) {
         const int e = e0 + u * nt;
         if (e < i1) {
-          if (!a.mfma) Tm[e - i0] = acc[u];
-          Ti[e - i0] = colp[u] ? lower_bound(s.cand, mc, rr[u]) * q + (cc[u] - f)
-                               : mc * q + lower_bound(s.candc, mcc, cc[u]) * q + (rr[u] - f);
+          const int pos = colp[u] ? lower_bound(s.cand, mc, rr[u]) * q + (cc[u] - f)
+                                  : mc * q + lower_bound(s.candc, mcc, cc[u]) * q + (rr[u] - f);
+          if (a.det) {
+            if (!a.mfma) Tm[e - i0] = acc[u];
+            Ti[e - i0] = pos;
+          } else {
+            atomicAdd(&fbuf[pos], -acc[u]);  // any order: not run-to-run reproducible
+          }
         }
       }
     }
-    if (i0 == 0 && a_tgt >= 0) fbuf[a_tgt] = a_val;
+    if (i0 == 0 && a_tgt >= 0) {
+      if (a.det)
+        fbuf[a_tgt] = a_val;
+      else
+        atomicAdd(&fbuf[a_tgt], a_val);
+    }
     __syncthreads();
+    if (!a.det) continue;  // the terms are in the panels already
     if (i0 == 0 && tid == 0) trace_at(d, K, 9, wall_clock64());  // first chunk's terms done
     // (4) in predecessor order (a predecessor's terms hit distinct
     // entries).  Column predecessors update only the column panel and row
@@ -2068,7 +2085,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       __syncthreads();
     }
   }
-  if (nterms == 0 && a_tgt >= 0) fbuf[a_tgt] = a_val;
+  if (nterms == 0 && a_tgt >= 0) fbuf[a_tgt] = a_val;  // no chunk ran (no term can race)
   __syncthreads();
   if (tid == 0) {
     const unsigned long long now = wall_clock64();
@@ -2684,6 +2701,9 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     a.update_prec = h->opt.update_precision;
     a.fast_path = h->opt.factor_path == 0 ? 1 : h->opt.factor_path == 2 ? 2 : 0;
     a.mfma = h->opt.update_mfma == 1 ? 1 : 0;
+    // the ordered accumulation of the terms is what makes runs bit-identical;
+    // matrix-core tiles always use it
+    a.det = h->opt.deterministic || a.mfma ? 1 : 0;
     a.lds_pivot = dyn > 0 ? 1 : 0;
     a.roff = h->d_roff.p; a.nr = h->d_nr.p; a.coff = h->d_coff.p; a.nc = h->d_nc.p;
     a.loff = h->d_loff.p; a.woff = h->d_woff.p; a.doff = h->d_doff.p;

@@ -115,6 +115,7 @@ struct FactorArgs {
   int beta_one, drop_norm, update_prec;
   int fast_path;                   // 1: LDS staging where it fits, 2: global staging, 0: general only
   int mfma;                        // fast path: update terms as matrix-core tiles
+  int det;                         // fast path: terms subtracted in predecessor order
   int lds_pivot;                   // dynamic LDS holds 2 q^2 doubles for every block
   // factor storage, per block
   int64_t* roff;  int32_t* nr;     // rows of L  : idx heap

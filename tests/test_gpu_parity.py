@@ -28,14 +28,14 @@ def say(msg):
     sys.stdout.flush()
 
 
-def run_pair(a, tau, pre_perm=None, agg=False, update_mfma=0, **blocking):
+def run_pair(a, tau, pre_perm=None, agg=False, update_mfma=0, deterministic=1, **blocking):
     from oracle import Oracle, OracleOptions
     from paper_1908_10169_amd import bilu
     o = Oracle()
     rc = o.run(a, OracleOptions(tau=tau, use_aggregation=agg, **blocking), pre_perm=pre_perm)
     assert rc == 0
     h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=agg, update_mfma=update_mfma,
-                  **blocking)
+                  deterministic=deterministic, **blocking)
     h.analyze(a, pre_perm=pre_perm)
     h.factor(tau)
     return o, h
@@ -144,6 +144,19 @@ def test_factor_parity_matrix_cores(name, make, tau, blocking):
     a, perm = make()
     say(f"[parity mfma] {name} n={a.n} tau={tau}")
     o, h = run_pair(a, tau, perm, update_mfma=1, **blocking)
+    compare_factors(o, h)
+    check_apply_and_solve(o, h, a)
+    h.close()
+
+
+@pytest.mark.parametrize("name,make,tau,blocking", MFMA_CASES, ids=[c[0] for c in MFMA_CASES])
+def test_factor_parity_atomic_accumulation(name, make, tau, blocking):
+    """deterministic = 0: the update terms are subtracted with atomic adds in
+    whatever order they arrive; the parity bar still holds."""
+    _torch()
+    a, perm = make()
+    say(f"[parity atomic] {name} n={a.n} tau={tau}")
+    o, h = run_pair(a, tau, perm, deterministic=0, **blocking)
     compare_factors(o, h)
     check_apply_and_solve(o, h, a)
     h.close()
@@ -314,8 +327,9 @@ def test_state_errors():
     assert e.value.status == bilu.BILU_ERR_STATE
 
 
-@pytest.mark.parametrize("agg", [False, True], ids=["plain", "aggregated"])
-def test_full_size_cd3d_64(agg):
+@pytest.mark.parametrize("agg,det", [(False, 1), (True, 1), (True, 0)],
+                         ids=["plain", "aggregated", "aggregated-atomic"])
+def test_full_size_cd3d_64(agg, det):
     """The 64^3 x 4 convection-diffusion workload at full size, in the
     benchmark's configuration: partition, every pattern, factors within the
     tolerance and the FGMRES iteration count equal the oracle's."""
@@ -323,8 +337,8 @@ def test_full_size_cd3d_64(agg):
     from oracle import Oracle, OracleOptions
     from paper_1908_10169_amd import bilu
     w = mg.workload("cd3d_64_b4")
-    say(f"[full] cd3d_64_b4 n={w.a.n} nnz={w.a.nnz} aggregation={agg}")
-    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=agg)
+    say(f"[full] cd3d_64_b4 n={w.a.n} nnz={w.a.nnz} aggregation={agg} deterministic={det}")
+    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=agg, deterministic=det)
     h.analyze(w.a, pre_perm=w.perm)
     h.factor(w.tau)
     o = Oracle()
