@@ -115,6 +115,10 @@ typedef struct {
                          /* results vary at rounding level between runs, patterns   */
                          /* only where a drop norm is within rounding of tau).      */
                          /* update_mfma = 1 implies 1                                */
+  double drop_log_margin; /* > 0: log every drop decision whose norm is within      */
+                         /* drop_log_margin * tau of tau (block, row i or column ~j, */
+                         /* norm), for replaying ambiguous decisions; exported by  */
+                         /* bilu_export_factors.  0 (default): no log               */
 } bilu_options;
 
 typedef struct bilu_handle bilu_handle;
@@ -156,6 +160,13 @@ typedef struct {
   int64_t heap_regrows;       /* sweeps of the last factor rerun with a larger heap   */
   double r_kept;              /* ||(L S U - A)_Omega||_F / ||A||_F of the last factor,  */
                               /* from bilu_kept_residual (-1 until it is called)      */
+  /* drop decisions of the last sweep (Alg. 1 in block form: a candidate block
+   * row (column) is dropped when its scaled norm is <= tau) */
+  int64_t drops_rows, drops_cols;
+  double drop_margin_min;     /* smallest |norm - tau| / tau over all decisions      */
+                              /* (-1 when tau = 0 or no candidate was tested)         */
+  int64_t drop_log_count;     /* decisions within drop_log_margin of tau (logged      */
+                              /* up to 2^20, exported with the factors)               */
 } bilu_stats;
 
 /* Library-allocated host copy of the factors (for checking), final blocks. */
@@ -173,6 +184,13 @@ typedef struct {
   double* l_val;           /* per block |R_K| x q row-major, blocks concatenated     */
   double* w_val;           /* per block q x |C_K| column-major                       */
   double* d_val;           /* per block q x q row-major                              */
+  /* the drop-decision log of the sweep (drop_log_margin > 0), in the order
+   * the decisions were taken: initial block, candidate (row i, or ~j for
+   * column j, permuted numbering) and the scaled norm compared with tau */
+  int64_t ndrop_log;
+  int64_t* drop_block;
+  int64_t* drop_index;
+  double* drop_norm;
 } bilu_factors_host;
 
 /* Defaults: the paper's constants (Sec. 3.2, 3.4-3.6). */

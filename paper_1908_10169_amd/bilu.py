@@ -39,6 +39,7 @@ class Options(C.Structure):
         ("collect_timing", C.c_int), ("factor_path", C.c_int), ("apply_path", C.c_int),
         ("use_mwm", C.c_int), ("analyze_path", C.c_int), ("apply_precision", C.c_int),
         ("update_mfma", C.c_int), ("deterministic", C.c_int),
+        ("drop_log_margin", C.c_double),
     ]
 
 
@@ -62,6 +63,8 @@ class Stats(C.Structure):
         ("n_factor_launches", C.c_int64), ("n_apply", C.c_int64), ("n_spmv", C.c_int64),
         ("bytes_factor", C.c_double), ("t_phase", C.c_double * 8),
         ("apply_faults", C.c_int64), ("heap_regrows", C.c_int64), ("r_kept", C.c_double),
+        ("drops_rows", C.c_int64), ("drops_cols", C.c_int64), ("drop_margin_min", C.c_double),
+        ("drop_log_count", C.c_int64),
     ]
 
 
@@ -75,6 +78,8 @@ class FactorsHost(C.Structure):
         ("c_ptr", C.POINTER(C.c_int64)), ("c_idx", C.POINTER(C.c_int32)),
         ("l_val", C.POINTER(C.c_double)), ("w_val", C.POINTER(C.c_double)),
         ("d_val", C.POINTER(C.c_double)),
+        ("ndrop_log", C.c_int64), ("drop_block", C.POINTER(C.c_int64)),
+        ("drop_index", C.POINTER(C.c_int64)), ("drop_norm", C.POINTER(C.c_double)),
     ]
 
 
@@ -164,6 +169,7 @@ class Factors:
     C: list
     W: list
     D: list
+    drop_log: dict | None = None
 
 
 def _check_tensor(t, name, dtype, numel=None):
@@ -415,6 +421,11 @@ class Bilu:
             f = Factors(arr(fh.perm, n, np.int64), starts,
                         arr(fh.starts_initial, fh.nblocks_initial + 1, np.int64),
                         arr(fh.group_starts, fh.ngroups + 1, np.int64), [], [], [], [], [])
+            if fh.ndrop_log > 0:
+                m = fh.ndrop_log
+                f.drop_log = dict(block=arr(fh.drop_block, m, np.int64),
+                                  index=arr(fh.drop_index, m, np.int64),
+                                  norm=arr(fh.drop_norm, m, np.float64))
             lo = wo = do = 0
             for k in range(nb):
                 qk = int(q[k])

@@ -651,6 +651,25 @@ bilu_status bilu_export_factors(const bilu_handle* hc, bilu_factors_host* out) {
     bilu_free_factors(out);
     return fail(h, BILU_ERR_DEVICE, "export copy");
   }
+  // the drop-decision log
+  if (h->drop_log_n > 0) {
+    const int64_t m = h->drop_log_n;
+    std::vector<int32_t> lb(m), li(m);
+    out->drop_norm = new double[m];
+    out->drop_block = new int64_t[m];
+    out->drop_index = new int64_t[m];
+    if (hipMemcpy(lb.data(), h->d_log_blk.p, m * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(li.data(), h->d_log_idx.p, m * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(out->drop_norm, h->d_log_nrm.p, m * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+      bilu_free_factors(out);
+      return fail(h, BILU_ERR_DEVICE, "export copy");
+    }
+    for (int64_t i = 0; i < m; ++i) {
+      out->drop_block[i] = lb[i];
+      out->drop_index[i] = li[i];
+    }
+    out->ndrop_log = m;
+  }
   for (int64_t i = 0; i < val_len; ++i) {
     if (vb == 8) {
       std::memcpy(&vheap[i], raw.data() + 8 * i, 8);
@@ -719,6 +738,9 @@ void bilu_free_factors(bilu_factors_host* f) {
   delete[] f->l_val;
   delete[] f->w_val;
   delete[] f->d_val;
+  delete[] f->drop_block;
+  delete[] f->drop_index;
+  delete[] f->drop_norm;
   std::memset(f, 0, sizeof(*f));
 }
 

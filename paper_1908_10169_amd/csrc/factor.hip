@@ -34,6 +34,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <numeric>
 
 #include <hipcub/hipcub.hpp>
@@ -433,6 +434,7 @@ struct Lds {
   long long hcur[2], hend[2];  // the worker's heap chunks (values, indices); kept across blocks
   // the worker's share of the launch counters, added once when it ends
   unsigned long long acc_flops, acc_bytes;
+  unsigned long long acc_drop[3];  // rows dropped, columns dropped, smallest margin (bits)
   int acc_depth;
 };
 // updater_set counts per hash slot in cand[] followed by candc[]
@@ -787,10 +789,33 @@ __device__ __forceinline__ void store_pivot(const FactorArgs& a, int K, int q, c
 
 // Drop test (Alg. 1 in block form): row z of L is kept iff the norm of
 // C(z, K) D_K exceeds tau, column z of U iff the norm of D_K R(K, z) does.
+// Drop decisions of block K (Alg. 1 in block form): keep_r[z] / keep_c[z]
+// for the candidate rows cand[z] (z >= q) and columns candc[z].  The block's
+// drops and the smallest relative margin |norm - tau| / tau go to the
+// worker's LDS counters acc (rows dropped, columns dropped, margin bits);
+// with a.log_margin > 0 the decisions within that margin of tau are logged.
 __device__ __forceinline__ void drop_flags(const FactorArgs& a, const double* Cp, const double* Rp, int mc, int mcc,
-                           int q, const double* sW, int* keep_r, int* keep_c, double tau) {
+                           int q, const double* sW, int* keep_r, int* keep_c, double tau, int K,
+                           const int* cand, const int* candc, unsigned long long* acc) {
   const int tid = threadIdx.x;
   const bool two = a.drop_norm == 1;
+  unsigned long long dr = 0, dc = 0;
+  double mg = INFINITY;
+  auto decide = [&](double nrm, int side, int idx) {
+    if (tau > 0.0) {
+      const double m = fabs(nrm - tau) / tau;
+      mg = fmin(mg, m);
+      if (m <= a.log_margin) {
+        const int at = (int)atomicAdd(a.drop_ctr + 3, 1ull);
+        if (at < a.log_cap) {
+          a.log_blk[at] = K;
+          a.log_idx[at] = side ? ~idx : idx;
+          a.log_nrm[at] = nrm;
+        }
+      }
+    }
+    return nrm > tau;
+  };
   for (int z = q + tid; z < mc; z += blockDim.x) {
     const double* row = Cp + (int64_t)z * q;
     double nrm = 0.0;
@@ -800,7 +825,9 @@ __device__ __forceinline__ void drop_flags(const FactorArgs& a, const double* Cp
       nrm = two ? fma(v, v, nrm) : fmax(nrm, fabs(v));
     }
     if (two) nrm = sqrt(nrm);
-    keep_r[z] = nrm > tau ? 1 : 0;
+    const bool keep = decide(nrm, 0, cand[z]);
+    keep_r[z] = keep ? 1 : 0;
+    dr += keep ? 0 : 1;
   }
   for (int z = tid; z < mcc; z += blockDim.x) {
     const double* col = Rp + (int64_t)z * q;
@@ -811,7 +838,22 @@ __device__ __forceinline__ void drop_flags(const FactorArgs& a, const double* Cp
       nrm = two ? fma(acc, acc, nrm) : fmax(nrm, fabs(acc));
     }
     if (two) nrm = sqrt(nrm);
-    keep_c[z] = nrm > tau ? 1 : 0;
+    const bool keep = decide(nrm, 1, candc[z]);
+    keep_c[z] = keep ? 1 : 0;
+    dc += keep ? 0 : 1;
+  }
+  // per wave, then one LDS atomic each (non-negative doubles order like
+  // their bit patterns)
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    dr += __shfl_xor(dr, o, 64);
+    dc += __shfl_xor(dc, o, 64);
+    mg = fmin(mg, __shfl_xor(mg, o, 64));
+  }
+  if ((tid & 63) == 0) {
+    if (dr) atomicAdd(&acc[0], dr);
+    if (dc) atomicAdd(&acc[1], dc);
+    if (mg < INFINITY) atomicMin(&acc[2], (unsigned long long)__double_as_longlong(mg));
   }
   __syncthreads();
 }
@@ -1024,7 +1066,8 @@ __device__ __forceinline__ bool factor_block(const FactorArgs& a, const FlowArgs
   // ---------------- drop: rows of L (scaled) and columns of U (D R)
   int* keep_r = s.hash;                 // flags for rows q..mc-1
   int* keep_c = s.hash + kCandCap;      // flags for cols 0..mcc-1
-  drop_flags(a, Cp, Rp, mc, mcc, q, sW, keep_r, keep_c, a.tau_blk ? a.tau_blk[K] : a.tau);
+  drop_flags(a, Cp, Rp, mc, mcc, q, sW, keep_r, keep_c, a.tau_blk ? a.tau_blk[K] : a.tau, K, s.cand,
+             s.candc, s.acc_drop);
   if (tid == 0) trace_at(d, K, 11, wall_clock64());
   constexpr int kPer = kCandCap / kThreads;  // flags per thread
   int fr[kPer], fc[kPer];
@@ -1283,6 +1326,8 @@ typedef uint16_t wide_bf16 __attribute__((ext_vector_type(8), aligned(2)));
 // Slack in values after the end of the value heap: the last 16-byte load of
 // a row may reach past the last stored value.
 constexpr int64_t kHeapSlack = 16;
+// Records of near-tie drop decisions kept at most (drop_log_margin > 0).
+constexpr int kDropLogCap = 1 << 20;
 
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
@@ -2060,8 +2105,8 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
         atomicAdd(&fbuf[a_tgt], a_val);
     }
     __syncthreads();
-    if (!a.det) continue;  // the terms are in the panels already
     if (i0 == 0 && tid == 0) trace_at(d, K, 9, wall_clock64());  // first chunk's terms done
+    if (!a.det) continue;  // the terms are in the panels already
     // (4) in predecessor order (a predecessor's terms hit distinct
     // entries).  Column predecessors update only the column panel and row
     // predecessors only the row panel, so the k-th of each go together.
@@ -2117,7 +2162,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   __syncthreads();
   if (!s.misc[14]) return kFastError;
   if (tid == 0) trace_at(d, K, 10, wall_clock64());
-  drop_flags(a, Cp, Rp, mc, mcc, q, sW, keep_r, keep_c, s.tau_k);
+  drop_flags(a, Cp, Rp, mc, mcc, q, sW, keep_r, keep_c, s.tau_k, K, s.cand, s.candc, s.acc_drop);
   if (tid == 0) trace_at(d, K, 11, wall_clock64());
 
   // ---- positions of kept rows / columns and of their distinct blocks
@@ -2392,6 +2437,8 @@ __global__ void __launch_bounds__(kThreads, 2) factor_worker_kernel(FactorArgs a
   if (threadIdx.x == 0) {
     s.hcur[0] = s.hcur[1] = s.hend[0] = s.hend[1] = 0;
     s.acc_flops = s.acc_bytes = 0;
+    s.acc_drop[0] = s.acc_drop[1] = 0;
+    s.acc_drop[2] = (unsigned long long)__double_as_longlong(INFINITY);
     s.acc_depth = 0;
     // the seeded count, kept in LDS (misc[28]) to spare registers
     s.misc[28] = __hip_atomic_load(d.nleaves, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2466,6 +2513,9 @@ __global__ void __launch_bounds__(kThreads, 2) factor_worker_kernel(FactorArgs a
   }
   if (threadIdx.x == 0) {
     atomicAdd(a.flops, s.acc_flops);
+    atomicAdd(a.drop_ctr + 0, s.acc_drop[0]);
+    atomicAdd(a.drop_ctr + 1, s.acc_drop[1]);
+    atomicMin(a.drop_ctr + 2, s.acc_drop[2]);
     atomicAdd(a.upd_bytes, s.acc_bytes);
     atomicMax(d.max_depth, s.acc_depth);
   }
@@ -2645,6 +2695,14 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     CK(hipMemsetAsync(h->d_row_ovf.p, 0xff, nb * sizeof(int32_t), st));
     CK(hipMemsetAsync(h->d_status.p, 0, 8 * sizeof(int), st));
     CK(hipMemsetAsync(h->d_counters.p, 0, 4 * sizeof(unsigned long long), st));
+    {
+      const double inf = INFINITY;
+      unsigned long long init[4] = {0, 0, 0, 0};
+      std::memcpy(&init[2], &inf, 8);
+      CK(h->d_drop_ctr.alloc(4));
+      CK(hipMemcpyAsync(h->d_drop_ctr.p, init, sizeof(init), hipMemcpyHostToDevice, st));
+      CK(hipStreamSynchronize(st));  // init is on the host stack
+    }
     // pending, started, enqueued, depth = 0; queue = -1; tail, max depth,
     // seeded-block counter, seeded count, claimed positions = 0
     CK(hipMemsetAsync(h->d_flow.p, 0, 4 * nb * sizeof(int), st));
@@ -2729,6 +2787,20 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     a.err_block = h->d_status.p + 1;
     a.n_perturbed = h->d_status.p + 2;
     a.flops = h->d_counters.p + 2;
+    a.drop_ctr = h->d_drop_ctr.p;
+    a.log_margin = h->opt.drop_log_margin > 0.0 ? h->opt.drop_log_margin : -1.0;
+    a.log_cap = 0;
+    a.log_blk = a.log_idx = nullptr;
+    a.log_nrm = nullptr;
+    if (h->opt.drop_log_margin > 0.0) {
+      CK(h->d_log_blk.alloc(kDropLogCap));
+      CK(h->d_log_idx.alloc(kDropLogCap));
+      CK(h->d_log_nrm.alloc(kDropLogCap));
+      a.log_cap = kDropLogCap;
+      a.log_blk = h->d_log_blk.p;
+      a.log_idx = h->d_log_idx.p;
+      a.log_nrm = h->d_log_nrm.p;
+    }
     a.upd_bytes = h->d_counters.p + 3;
     a.troff = h->d_troff.p;
     a.ntr = h->d_ntr.p;
@@ -2805,6 +2877,17 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
                   msg);
     }
     h->stats.perturbed_blocks = status[2];
+    {
+      unsigned long long dc[4];
+      CK(hipMemcpy(dc, h->d_drop_ctr.p, sizeof(dc), hipMemcpyDeviceToHost));
+      double mg;
+      std::memcpy(&mg, &dc[2], 8);
+      h->stats.drops_rows = (int64_t)dc[0];
+      h->stats.drops_cols = (int64_t)dc[1];
+      h->stats.drop_margin_min = std::isfinite(mg) ? mg : -1.0;
+      h->drop_log_n = a.log_cap > 0 ? std::min<int64_t>((int64_t)dc[3], a.log_cap) : 0;
+      h->stats.drop_log_count = (int64_t)dc[3];
+    }
     h->stats.flops_update = (double)ctr[2];
     h->stats.bytes_factor = (double)ctr[3];  // completed with A and output bytes by the caller
     h->stats.factor_levels = max_depth;

@@ -140,6 +140,12 @@ struct FactorArgs {
   int* err; int* err_block; int* n_perturbed;
   unsigned long long* flops;
   unsigned long long* upd_bytes;  // bytes of L_J rows + W_J columns read by updates
+  // drop decisions: [0] rows dropped, [1] columns dropped, [2] smallest
+  // |norm - tau| / tau (double bits), [3] decisions logged (may exceed log_cap)
+  unsigned long long* drop_ctr;
+  double log_margin;               // log decisions with |norm - tau| <= log_margin * tau
+  int log_cap;
+  int32_t* log_blk; int32_t* log_idx; double* log_nrm;  // idx: row i, or ~j for column j
   // block-level patterns: distinct blocks of R_K (tr) and of C_K (tc) in the
   // idx heap, and the static distinct blocks > K of A's pattern of K
   int64_t* troff; int32_t* ntr;
@@ -251,6 +257,10 @@ struct bilu_handle {
   bilu::DevArray<double> d_scratch;
   bilu::DevArray<int> d_status;                  // err, err_block, n_perturbed, ovf_top
   bilu::DevArray<unsigned long long> d_counters; // idx_top, val_top, flops
+  bilu::DevArray<unsigned long long> d_drop_ctr; // drops, margin, log count
+  bilu::DevArray<int32_t> d_log_blk, d_log_idx;  // near-tie drop decisions
+  bilu::DevArray<double> d_log_nrm;
+  int64_t drop_log_n = 0;                        // records in the log
   int64_t scratch_slots = 0, slot_doubles = 0;
   int64_t idx_used = 0, val_used = 0;  // heap entries the last sweep allocated
 

@@ -67,6 +67,19 @@ def compare_factors(o, h):
 BLOCK_TOL = 1e-8  # per block: one wrong block stands out of the global norm
 
 
+def check_drop_counts(o, h, tau):
+    """The sweep's drop statistics equal the oracle's decision log: the
+    number of dropped rows and columns exactly, the smallest margin
+    |norm - tau| / tau to rounding."""
+    log = o.droplog()
+    st = h.stats()
+    assert st["drops_rows"] == int(np.sum((log["kind"] == 0) & ~log["kept"]))
+    assert st["drops_cols"] == int(np.sum((log["kind"] == 1) & ~log["kept"]))
+    if tau > 0 and len(log["norm"]):
+        m = float(np.min(np.abs(log["norm"] - tau) / tau))
+        assert abs(st["drop_margin_min"] - m) <= 1e-9 * max(m, 1e-300) + 1e-15, (st, m)
+
+
 def max_block_error(fl, fo):
     """Largest relative difference of any single block's L, W or D."""
     worst = 0.0
@@ -125,6 +138,7 @@ def test_factor_parity(name, make, tau, blocking):
     say(f"[parity] {name} n={a.n} nnz={a.nnz} tau={tau} {blocking}")
     o, h = run_pair(a, tau, perm, **blocking)
     compare_factors(o, h)
+    check_drop_counts(o, h, tau)
     # the kept-pattern identity (Sec. 2.2) on the device, as in the oracle
     rk, rk_o = h.kept_residual(), o.kept_residual()
     assert rk <= 1e-12 and rk_o <= 1e-12, (rk, rk_o)
@@ -366,4 +380,40 @@ def test_full_size_cd3d_64(agg, det):
     xd = torch.zeros_like(bd)
     info_l = h.fgmres(bd, xd, restart=w.restart, rtol=1e-8)
     assert info_l["converged"] and info_l["iterations"] == info_o["iterations"]
+    h.close()
+
+
+@pytest.mark.parametrize("name", ["cd2d_32x32_b3", "el3d_10_b3"])
+def test_drop_log_equals_oracle(name):
+    """drop_log_margin: the logged near-tie decisions (block, candidate,
+    norm) are the oracle's decisions within that margin of tau."""
+    _torch()
+    from oracle import Oracle, OracleOptions
+    from paper_1908_10169_amd import bilu
+    w = mg.workload(name)
+    margin = 0.05
+    say(f"[drop log] {name} margin={margin}")
+    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=False, drop_log_margin=margin)
+    h.analyze(w.a, pre_perm=w.perm)
+    h.factor(w.tau)
+    fl = h.export()
+    o = Oracle()
+    assert o.run(w.a, OracleOptions(tau=w.tau, use_aggregation=False), pre_perm=w.perm) == 0
+    log = o.droplog()
+    rel = np.abs(log["norm"] - w.tau) / w.tau
+    sel = rel <= margin
+    edge = np.abs(rel - margin) <= 1e-9  # rounding may put these on either side
+    want = {(int(b), int(i) if k == 0 else ~int(i)): nrm
+            for b, i, k, nrm, s_, e in zip(log["block"], log["index"], log["kind"], log["norm"],
+                                           sel, edge) if s_ and not e}
+    got = {}
+    assert fl.drop_log is not None and len(want) > 0
+    for b, i, nrm in zip(fl.drop_log["block"], fl.drop_log["index"], fl.drop_log["norm"]):
+        got[(int(b), int(i))] = float(nrm)
+    edge_keys = {(int(b), int(i) if k == 0 else ~int(i))
+                 for b, i, k, e in zip(log["block"], log["index"], log["kind"], edge) if e}
+    assert set(got) - edge_keys == set(want)
+    for key, nrm in want.items():
+        assert abs(got[key] - nrm) <= 1e-10 * nrm
+    assert h.stats()["drop_log_count"] == len(got)
     h.close()
