@@ -63,6 +63,9 @@ def parse():
     p.add_argument("--deterministic", type=int, default=1, choices=[0, 1],
                    help="1: update terms subtracted in a fixed order (bit-identical runs); "
                         "0: with atomic adds")
+    p.add_argument("--tuning", default="",
+                   help="load this tuning table (paper_1908_10169_amd/tune.py) before timing; "
+                        "handles use its entries for their precision and width class")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                    help="only copy BYTES between two device buffers twice (reference for the "
                         "HBM byte counters of a profiler) and exit")
@@ -197,8 +200,10 @@ def main():
         sys.exit(2)
     import torch
 
-    from paper_1908_10169_amd import matgen as mg
+    from paper_1908_10169_amd import bilu, matgen as mg
     torch.cuda.set_device(0)
+    if args.tuning:
+        bilu.load_tuning(args.tuning)
     forms = [f for f in args.forms.split(",") if f]
     project = args.ordering == "project"
     agg = AGGREGATION_DEFAULT if args.aggregation < 0 else bool(args.aggregation)
@@ -230,6 +235,8 @@ def main():
             else "geometric nested dissection (caller permutation)",
             "update_precision": forms[0], "aggregation": agg, "update_mfma": args.update_mfma,
             "deterministic": args.deterministic,
+            "tuning": os.path.relpath(args.tuning, ROOT) if args.tuning else None,
+            "tuning_applied": bool(st["tuning_applied"]),
             "parallelism": "single GPU",
         },
         "roofline": roofline,

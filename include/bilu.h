@@ -119,6 +119,14 @@ typedef struct {
                          /* drop_log_margin * tau of tau (block, row i or column ~j, */
                          /* norm), for replaying ambiguous decisions; exported by  */
                          /* bilu_export_factors.  0 (default): no log               */
+  int workers_per_cu;    /* workgroups of the factor sweep per compute unit: 0       */
+                         /* (default) as many as fit (two), or 1                     */
+  int use_tuning;        /* 1 (default): a table loaded with bilu_load_tuning that  */
+                         /* has an entry for the update precision, block-width     */
+                         /* class and deterministic setting of a factorization     */
+                         /* supplies workers_per_cu, update_mfma, factor_path,     */
+                         /* apply_path (and, for deterministic = 0, the order of   */
+                         /* accumulation); 0: the options as given                   */
 } bilu_options;
 
 typedef struct bilu_handle bilu_handle;
@@ -167,6 +175,9 @@ typedef struct {
                               /* (-1 when tau = 0 or no candidate was tested)         */
   int64_t drop_log_count;     /* decisions within drop_log_margin of tau (logged      */
                               /* up to 2^20, exported with the factors)               */
+  int64_t tuning_applied;     /* 1 when a tuned entry set the last factorization's    */
+                              /* kernel settings                                       */
+  int64_t max_width_initial;  /* widest block of the initial partition                */
 } bilu_stats;
 
 /* Library-allocated host copy of the factors (for checking), final blocks. */
@@ -331,6 +342,21 @@ bilu_status bilu_mwm(int64_t n, const int64_t* rowptr, const int32_t* colind, co
  * mixed forms, and perturbed pivot blocks.  Also kept in
  * bilu_stats.r_kept.  BILU_ERR_STATE before a factorization.  Synchronous. */
 bilu_status bilu_kept_residual(bilu_handle* h, double* r_kept);
+
+/* Load the tuning table written by the project's tuner
+ * (paper_1908_10169_amd/tune.py): a JSON object whose "entries" array holds
+ * flat objects with the integer fields precision (bilu_precision),
+ * width_class (0: the widest initial block is at most 16 columns, 1: wider),
+ * reproducible (1: for handles with deterministic = 1, 0: for the others),
+ * workers_per_cu, update_mfma, factor_path, apply_path and deterministic
+ * (which must be 1 where reproducible is 1).
+ * Process-wide; replaces any table loaded before; path NULL or "" clears it.
+ * Handles with use_tuning = 1 use the entry that matches each
+ * factorization.  BILU_ERR_INVALID if the file cannot be read or a field is
+ * out of range (the table is then unchanged). */
+bilu_status bilu_load_tuning(const char* path);
+/* Entries in the loaded tuning table. */
+int64_t bilu_tuning_entries(void);
 
 /* Statistics of the last analyze/factor (block sizes as in the paper's
  * tables of Sec. 3.2-3.5: number, max, average, standard deviation). */

@@ -39,7 +39,7 @@ class Options(C.Structure):
         ("collect_timing", C.c_int), ("factor_path", C.c_int), ("apply_path", C.c_int),
         ("use_mwm", C.c_int), ("analyze_path", C.c_int), ("apply_precision", C.c_int),
         ("update_mfma", C.c_int), ("deterministic", C.c_int),
-        ("drop_log_margin", C.c_double),
+        ("drop_log_margin", C.c_double), ("workers_per_cu", C.c_int), ("use_tuning", C.c_int),
     ]
 
 
@@ -64,7 +64,8 @@ class Stats(C.Structure):
         ("bytes_factor", C.c_double), ("t_phase", C.c_double * 8),
         ("apply_faults", C.c_int64), ("heap_regrows", C.c_int64), ("r_kept", C.c_double),
         ("drops_rows", C.c_int64), ("drops_cols", C.c_int64), ("drop_margin_min", C.c_double),
-        ("drop_log_count", C.c_int64),
+        ("drop_log_count", C.c_int64), ("tuning_applied", C.c_int64),
+        ("max_width_initial", C.c_int64),
     ]
 
 
@@ -89,6 +90,7 @@ EXPORTED = [
     "bilu_free_factors", "bilu_destroy", "bilu_status_string", "bilu_last_error",
     "bilu_preprocess", "bilu_sync", "bilu_export_trace", "bilu_factor_batched", "bilu_mwm",
     "bilu_analyze_device", "bilu_refactor", "bilu_kept_residual", "bilu_apply_noalloc",
+    "bilu_load_tuning", "bilu_tuning_entries",
 ]
 
 _lib = None
@@ -130,6 +132,10 @@ def load(path: str = LIB_PATH):
     lib.bilu_analyze_device.argtypes = [vp, C.c_int64, vp, vp, vp]
     lib.bilu_refactor.argtypes = [vp, C.c_double, vp]
     lib.bilu_kept_residual.argtypes = [vp, C.POINTER(C.c_double)]
+    lib.bilu_load_tuning.argtypes = [C.c_char_p]
+    lib.bilu_load_tuning.restype = C.c_int
+    lib.bilu_tuning_entries.argtypes = []
+    lib.bilu_tuning_entries.restype = C.c_int64
     lib.bilu_preprocess.argtypes = [C.POINTER(Options), C.c_int64, vp, vp, vp, C.c_double,
                                     vp, vp, C.POINTER(C.c_int64), vp, C.POINTER(C.c_int64)]
     for f in ("bilu_create", "bilu_analyze", "bilu_analyze_device", "bilu_refactor", "bilu_factor",
@@ -220,6 +226,16 @@ def factor_batched(handles, taus):
         errs = "; ".join(lib.bilu_last_error(h._h).decode() for h in handles)
         raise BiluError(st, f"bilu_factor_batched: {errs}")
     return st
+
+
+def load_tuning(path: str | None):
+    """bilu_load_tuning: the process-wide table of tuned kernel settings
+    (None or "" clears it); returns the number of entries."""
+    lib = load()
+    st = lib.bilu_load_tuning(path.encode() if path else None)
+    if st != BILU_OK:
+        raise BiluError(st, f"bilu_load_tuning({path!r})")
+    return lib.bilu_tuning_entries()
 
 
 def preprocess(a, tau: float, pre_perm=None, **kw):

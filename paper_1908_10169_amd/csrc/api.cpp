@@ -196,6 +196,8 @@ void bilu_default_options(bilu_options* o) {
   o->update_precision = BILU_PREC_F64;
   o->heap_bytes = 0;
   o->deterministic = 1;
+  o->workers_per_cu = 0;
+  o->use_tuning = 1;
 }
 
 bilu_status bilu_create(bilu_handle** out, const bilu_options* opt, void* stream) {
@@ -218,7 +220,9 @@ bilu_status bilu_create(bilu_handle** out, const bilu_options* opt, void* stream
       h->opt.apply_path < 0 || h->opt.apply_path > 2 || h->opt.use_mwm < 0 || h->opt.use_mwm > 1 ||
       h->opt.analyze_path < 0 || h->opt.analyze_path > 1 || h->opt.apply_precision < 0 ||
       h->opt.apply_precision > 1 || h->opt.update_mfma < 0 || h->opt.update_mfma > 1 ||
-      h->opt.deterministic < 0 || h->opt.deterministic > 1) {
+      h->opt.deterministic < 0 || h->opt.deterministic > 1 || h->opt.workers_per_cu < 0 ||
+      h->opt.workers_per_cu > 8 || h->opt.use_tuning < 0 || h->opt.use_tuning > 1 ||
+      !(h->opt.drop_log_margin >= 0.0)) {
     delete h;
     return BILU_ERR_INVALID;
   }

@@ -240,6 +240,12 @@ bilu_status factor_batched(bilu_handle** hs, int count, const double* taus) {
     h->stats.t_phase[3] = sys.stats.t_phase[3];
     h->stats.dev_ms_factor = sys.stats.dev_ms_factor;
     h->stats.n_factor_launches = 1;
+    // the settings of the common sweep; the apply path stays the handle's own
+    // unless a tuned entry chose it
+    h->eff = sys.eff;
+    if (!sys.stats.tuning_applied) h->eff.apply_path = h->opt.apply_path;
+    h->stats.tuning_applied = sys.stats.tuning_applied;
+    h->stats.max_width_initial = sys.stats.max_width_initial;
   }
   CK(hipStreamSynchronize(st));
   // ---- aggregation, apply plan, statistics per handle

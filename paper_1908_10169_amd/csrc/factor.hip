@@ -2603,6 +2603,30 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
   int32_t maxq = 0;
   for (int64_t b = 0; b < nb; ++b) maxq = std::max(maxq, bs[b + 1] - bs[b]);
   if (maxq > kMaxWidth) return fail(h, BILU_ERR_INVALID, "block wider than the kernel limit");
+  // the settings of this sweep: the options, or the tuned entry for its
+  // precision, width class and reproducibility requirement
+  {
+    TunedEntry& e = h->eff;
+    e.precision = h->opt.update_precision;
+    e.width_class = maxq > kFastWidth ? 1 : 0;
+    e.reproducible = h->opt.deterministic;
+    h->stats.max_width_initial = maxq;
+    e.workers_per_cu = h->opt.workers_per_cu;
+    e.update_mfma = h->opt.update_mfma;
+    e.factor_path = h->opt.factor_path;
+    e.apply_path = h->opt.apply_path;
+    e.deterministic = h->opt.deterministic;
+    TunedEntry t;
+    h->stats.tuning_applied = 0;
+    if (h->opt.use_tuning && tuned_entry(e.precision, e.width_class, h->opt.deterministic, &t)) {
+      e.workers_per_cu = t.workers_per_cu;
+      e.update_mfma = t.update_mfma;
+      e.factor_path = t.factor_path;
+      e.apply_path = t.apply_path;
+      e.deterministic = h->opt.deterministic ? 1 : t.deterministic;
+      h->stats.tuning_applied = 1;
+    }
+  }
   h->doff_h.assign(nb + 1, 0);
   for (int64_t b = 0; b < nb; ++b) {
     int64_t q = bs[b + 1] - bs[b];
@@ -2665,10 +2689,11 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
                       : h->opt.update_precision == 2 ? reinterpret_cast<const void*>(factor_worker_kernel<2>)
                                                      : reinterpret_cast<const void*>(factor_worker_kernel<0>);
   CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, worker, kThreads, dyn));
+  if (h->eff.workers_per_cu > 0) per_cu = std::min(per_cu, h->eff.workers_per_cu);
   const int64_t workers = std::min<int64_t>(nb, std::max<int64_t>(1, (int64_t)cus * std::max(per_cu, 1)));
   const int64_t mq = std::max<int32_t>(maxq, 1);
   const int64_t slot_doubles = std::max<int64_t>(2 * (int64_t)kCandCap * mq + 2 * mq * mq,
-                                                  h->opt.factor_path != 1 ? kBigSlotDoubles : 0);
+                                                  h->eff.factor_path != 1 ? kBigSlotDoubles : 0);
   if ((int64_t)h->d_scratch.n < workers * slot_doubles) CK(h->d_scratch.alloc(workers * slot_doubles));
   h->scratch_slots = workers;
   h->slot_doubles = slot_doubles;
@@ -2757,11 +2782,11 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     a.beta_one = h->opt.beta_one;
     a.drop_norm = h->opt.drop_norm;
     a.update_prec = h->opt.update_precision;
-    a.fast_path = h->opt.factor_path == 0 ? 1 : h->opt.factor_path == 2 ? 2 : 0;
-    a.mfma = h->opt.update_mfma == 1 ? 1 : 0;
+    a.fast_path = h->eff.factor_path == 0 ? 1 : h->eff.factor_path == 2 ? 2 : 0;
+    a.mfma = h->eff.update_mfma == 1 ? 1 : 0;
     // the ordered accumulation of the terms is what makes runs bit-identical;
     // matrix-core tiles always use it
-    a.det = h->opt.deterministic || a.mfma ? 1 : 0;
+    a.det = h->eff.deterministic || a.mfma ? 1 : 0;
     a.lds_pivot = dyn > 0 ? 1 : 0;
     a.roff = h->d_roff.p; a.nr = h->d_nr.p; a.coff = h->d_coff.p; a.nc = h->d_nc.p;
     a.loff = h->d_loff.p; a.woff = h->d_woff.p; a.doff = h->d_doff.p;

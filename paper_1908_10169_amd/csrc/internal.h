@@ -207,6 +207,16 @@ struct FactorView {
 };
 
 
+// tuning.cpp: tuned settings for one update precision and block-width
+// class (0: the widest initial block is at most 16, 1: wider), for handles
+// that require reproducible results (reproducible = 1) or not
+struct TunedEntry {
+  int precision = 0, width_class = 0, reproducible = 1;
+  int workers_per_cu = 0;  // 0: as many as fit
+  int update_mfma = 0, factor_path = 0, apply_path = 0, deterministic = 1;
+};
+bool tuned_entry(int precision, int width_class, int reproducible, TunedEntry* out);
+
 }  // namespace bilu
 
 struct bilu_handle {
@@ -313,6 +323,9 @@ struct bilu_handle {
   bilu::DevArray<double> w_red;      // reduction partials
   int64_t w_cols = 0;
 
+  // settings in effect for the last factorization: the options, or a tuned
+  // entry for its precision and block-width class (use_tuning)
+  bilu::TunedEntry eff{};
   bilu_stats stats{};
 
   // event timing (collect_timing): pending event pairs, resolved by stats
@@ -329,6 +342,7 @@ struct bilu_handle {
 };
 
 namespace bilu {
+
 
 // error helpers
 bilu_status fail(bilu_handle* h, bilu_status s, const std::string& msg);

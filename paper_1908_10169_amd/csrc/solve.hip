@@ -853,7 +853,7 @@ bilu_status build_apply_plan(bilu_handle* h) {
     int* lb = lev.p + nb;
     int* top = misc.p;
     int* err = misc.p + 2;
-    int* ticket = h->opt.apply_path == 2 ? misc.p + 3 : nullptr;
+    int* ticket = h->eff.apply_path == 2 ? misc.p + 3 : nullptr;
     apply_levels<<<(unsigned)groups, 256, 0, st>>>((int)nb, h->fw_ptr.p, h->fw_j.p, h->bw_ptr.p,
                                                   h->bw_b.p, lf, lb, err, ticket, wait);
     CK(hipGetLastError());
@@ -962,7 +962,7 @@ bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t
   }
   with_value_type(h->apply_prec, [&](auto tag) {
   using T = decltype(tag);
-  if (h->opt.apply_path == 1) {
+  if (h->eff.apply_path == 1) {
     apply_levels_launch<T>(h, x, y, t);
   } else {
     FlowApplyArgs<T> a{};
@@ -980,7 +980,7 @@ bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t
     a.err = h->d_apply_err.p;
     // every wait ends (see apply_flow); the bound only catches a fault
     a.wait_ticks = (h->wait_ticks ? h->wait_ticks : (unsigned long long)1e9) / 5;
-    a.ticketed = h->opt.apply_path == 2 ? 1 : 0;
+    a.ticketed = h->eff.apply_path == 2 ? 1 : 0;
     apply_reset<<<grid_for(n), 256, 0, st>>>(n, a.t, a.z, a.err);
     apply_flow<T><<<(unsigned)((2 * h->fv.nb + 3) / 4), 256, 0, st>>>(a);
   }

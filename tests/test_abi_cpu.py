@@ -162,3 +162,34 @@ def test_binding_rejects_bad_tensors():
     buf = torch.zeros(2 * n, dtype=torch.float64)
     with pytest.raises(ValueError, match="overlaps"):
         _check_vectors(n, ("x", buf[:n]), ("y", buf[n // 2:n // 2 + n]))
+
+
+def test_tuning_table_reader(tmp_path):
+    """bilu_load_tuning reads the tuner's JSON (flat numeric entries, other
+    keys ignored), rejects out-of-range fields without touching the loaded
+    table, and clears with an empty path."""
+    import json
+    from paper_1908_10169_amd import bilu
+    good = {"version": 1, "entries": [
+        dict(precision=0, width_class=0, reproducible=1, workers_per_cu=0, update_mfma=0,
+             factor_path=0, apply_path=0, deterministic=1, relative_time=1.0),
+        dict(precision=1, width_class=0, reproducible=0, workers_per_cu=1, update_mfma=1,
+             factor_path=2, apply_path=1, deterministic=0, relative_time=0.9)],
+        "notes": [{"workloads": ["x"], "default_ms": {"x": 1.0}}]}
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps(good))
+    assert bilu.load_tuning(str(p)) == 2
+    bad = dict(good, entries=[dict(good["entries"][0], apply_path=7)])
+    q = tmp_path / "bad.json"
+    q.write_text(json.dumps(bad))
+    with pytest.raises(bilu.BiluError):
+        bilu.load_tuning(str(q))
+    # a reproducible entry must keep the ordered accumulation
+    bad2 = dict(good, entries=[dict(good["entries"][0], deterministic=0)])
+    q.write_text(json.dumps(bad2))
+    with pytest.raises(bilu.BiluError):
+        bilu.load_tuning(str(q))
+    assert bilu.load().bilu_tuning_entries() == 2
+    with pytest.raises(bilu.BiluError):
+        bilu.load_tuning(str(tmp_path / "missing.json"))
+    assert bilu.load_tuning(None) == 0
