@@ -124,9 +124,10 @@ typedef struct {
   int use_tuning;        /* 1 (default): a table loaded with bilu_load_tuning that  */
                          /* has an entry for the update precision, block-width     */
                          /* class and deterministic setting of a factorization     */
-                         /* supplies workers_per_cu, update_mfma, factor_path,     */
-                         /* apply_path (and, for deterministic = 0, the order of   */
-                         /* accumulation); 0: the options as given                   */
+                         /* supplies those of workers_per_cu, update_mfma,         */
+                         /* factor_path and apply_path left at 0 (and, for         */
+                         /* deterministic = 0, the order of accumulation); 0: the  */
+                         /* options as given                                         */
 } bilu_options;
 
 typedef struct bilu_handle bilu_handle;
@@ -351,8 +352,10 @@ bilu_status bilu_kept_residual(bilu_handle* h, double* r_kept);
  * workers_per_cu, update_mfma, factor_path, apply_path and deterministic
  * (which must be 1 where reproducible is 1).
  * Process-wide; replaces any table loaded before; path NULL or "" clears it.
- * Handles with use_tuning = 1 use the entry that matches each
- * factorization.  BILU_ERR_INVALID if the file cannot be read or a field is
+ * Without an explicit call, the table shipped beside the library for the
+ * device's architecture (tuning/<gfx...>.json next to libbilu.so) is loaded
+ * at the first factorization, if present.  Handles with use_tuning = 1 use
+ * the entry that matches each factorization.  BILU_ERR_INVALID if the file cannot be read or a field is
  * out of range (the table is then unchanged). */
 bilu_status bilu_load_tuning(const char* path);
 /* Entries in the loaded tuning table. */

@@ -2618,12 +2618,14 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     e.deterministic = h->opt.deterministic;
     TunedEntry t;
     h->stats.tuning_applied = 0;
+    // a tuned entry supplies the settings left at their defaults (0); a
+    // setting the caller chose stays
     if (h->opt.use_tuning && tuned_entry(e.precision, e.width_class, h->opt.deterministic, &t)) {
-      e.workers_per_cu = t.workers_per_cu;
-      e.update_mfma = t.update_mfma;
-      e.factor_path = t.factor_path;
-      e.apply_path = t.apply_path;
-      e.deterministic = h->opt.deterministic ? 1 : t.deterministic;
+      if (e.workers_per_cu == 0) e.workers_per_cu = t.workers_per_cu;
+      if (e.update_mfma == 0) e.update_mfma = t.update_mfma;
+      if (e.factor_path == 0) e.factor_path = t.factor_path;
+      if (e.apply_path == 0) e.apply_path = t.apply_path;
+      if (e.deterministic == 0) e.deterministic = t.deterministic;
       h->stats.tuning_applied = 1;
     }
   }

@@ -7,6 +7,8 @@
 // that require run-to-run reproducible results (reproducible = 1) always
 // keep the ordered accumulation; entries for handles that do not may drop
 // it where that measured faster.
+#include <dlfcn.h>
+
 #include <cctype>
 #include <cstdio>
 #include <mutex>
@@ -37,7 +39,36 @@ double field(const std::string& obj, const char* key, double fallback) {
 
 }  // namespace
 
+// The table shipped beside the library for this device's architecture
+// (tuning/<gfx...>.json next to libbilu.so), loaded once per process on the
+// first lookup unless a table was loaded explicitly.
+bool g_tune_tried = false;
+void load_default_table() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return;
+  std::string arch(prop.gcnArchName);
+  arch = arch.substr(0, arch.find(':'));
+  Dl_info info;
+  if (!dladdr(reinterpret_cast<void*>(&load_default_table), &info) || !info.dli_fname) return;
+  std::string dir(info.dli_fname);
+  const size_t slash = dir.rfind('/');
+  dir = slash == std::string::npos ? std::string(".") : dir.substr(0, slash);
+  const std::string path = dir + "/tuning/" + arch + ".json";
+  FILE* fp = std::fopen(path.c_str(), "rb");
+  if (!fp) return;
+  std::fclose(fp);
+  (void)bilu_load_tuning(path.c_str());
+}
+
 bool tuned_entry(int precision, int width_class, int reproducible, TunedEntry* out) {
+  bool first = false;
+  {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    first = !g_tune_tried;
+    g_tune_tried = true;
+  }
+  if (first) load_default_table();
   std::lock_guard<std::mutex> lock(g_tune_mu);
   for (const TunedEntry& e : g_tune)
     if (e.precision == precision && e.width_class == width_class &&
@@ -96,6 +127,7 @@ extern "C" bilu_status bilu_load_tuning(const char* path) {
     }
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune.swap(table);
+    g_tune_tried = true;  // an explicit table replaces the shipped one
     return BILU_OK;
   } catch (...) {
     return BILU_ERR_INTERNAL;
