@@ -370,7 +370,7 @@ bilu_status bilu_get_stats(const bilu_handle* h, bilu_stats* st);
 bilu_status bilu_export_factors(const bilu_handle* h, bilu_factors_host* out);
 void bilu_free_factors(bilu_factors_host* f);
 
-/* Per-block trace of the last factor kernel (collect_timing = 2): 20 values
+/* Per-block trace of the last factor kernel (collect_timing = 2): 24 values
  * per initial block in block order, device wall-clock ticks: pushed to the
  * ready queue, taken by a worker, its possible-update set built, candidates
  * built, done; then the block whose retraction made it ready (0 for blocks
@@ -378,8 +378,10 @@ void bilu_free_factors(bilu_factors_host* f);
  * fields 8..15 time the end of the column panel, row panel, pivot, drop
  * norms, heap allocation, factor writes, list pushes and successor counts;
  * fields 16..19 are the numbers of column and row predecessors and of
- * candidate rows and columns (20 values per block).  out may be NULL to query
- * *nrecords; capacity counts uint64 values.  BILU_ERR_STATE without a
+ * candidate rows and columns; fields 20..23 (narrow blocks only) time the
+ * end of the list offsets, of the list staging, of the position searches
+ * and candidate compaction, and of the candidate sort.  out may be NULL to
+ * query *nrecords; capacity counts uint64 values.  BILU_ERR_STATE without a
  * trace. */
 bilu_status bilu_export_trace(const bilu_handle* h, uint64_t* out, int64_t capacity,
                               int64_t* nrecords, double* ticks_per_second);

@@ -385,14 +385,14 @@ class Bilu:
         return self._check(self._lib.bilu_apply_noalloc(self._h, px, py), "bilu_apply_noalloc")
 
     def trace(self):
-        """Per-block factor trace (collect_timing=2): (records x 20 uint64, ticks/s)."""
+        """Per-block factor trace (collect_timing=2): (records x 24 uint64, ticks/s)."""
         m, tps = C.c_int64(), C.c_double()
         self._check(self._lib.bilu_export_trace(self._h, None, 0, C.byref(m), C.byref(tps)),
                     "bilu_export_trace")
-        out = np.zeros(m.value * 20, dtype=np.uint64)
+        out = np.zeros(m.value * 24, dtype=np.uint64)
         self._check(self._lib.bilu_export_trace(self._h, out.ctypes.data, out.size, C.byref(m),
                                                 C.byref(tps)), "bilu_export_trace")
-        return out.reshape(m.value, 20), tps.value
+        return out.reshape(m.value, 24), tps.value
 
     def sync(self):
         """Wait for the stream; raise if an asynchronous call reported an error."""

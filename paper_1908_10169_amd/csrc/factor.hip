@@ -120,7 +120,9 @@ __device__ __forceinline__ bool hash_insert_list(int* table, int n, int key, int
                                                  int cap) {
   unsigned h = (unsigned(key) * 2654435761u) & (unsigned)(n - 1);
   for (int probe = 0; probe < n; ++probe) {
-    int old = atomicCAS(&table[h], -1, key);
+    // most keys are repeats: a plain read settles them without an atomic
+    int old = __hip_atomic_load(&table[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (old == -1) old = atomicCAS(&table[h], -1, key);
     if (old == -1) {
       const int o = atomicAdd(count, 1);
       if (o < cap) list[o] = key;
@@ -401,8 +403,9 @@ struct PredMeta {
   int nr, nc, p, ntr, ntc, lo, hi, lo2, ioff, pad;
 };
 
-struct Lds {
-  int hash[kHashSlots];     // candidate dedup; reused as keep flags
+struct alignas(16) Lds {
+  int hash[kHashSlots];     // candidate dedup; reused as keep flags; panels of
+                            // the global variant while the terms accumulate
   int cand[kCandCap];       // sorted candidate rows
   int candc[kCandCap];      // sorted candidate columns
   union {
@@ -440,6 +443,8 @@ struct Lds {
 // updater_set counts per hash slot in cand[] followed by candc[]
 static_assert(2 * kCandCap >= kHashSlots, "count slots");
 static_assert(offsetof(Lds, candc) == offsetof(Lds, cand) + sizeof(int) * kCandCap, "layout");
+static_assert(offsetof(Lds, x.buf) % 16 == 0 && 2 * 4 * (kThreads / 2) <= kHashSlots,
+              "rank sort: 16-byte reads of the candidate lists");
 static_assert(kFastWidth + kFastExtra <= 512 && 2560 + kFastExtra <= kFastStage, "stage layout");
 static_assert(2 + 2 * kFastPreds <= kThreads && kFastPreds <= kThreads, "one thread per segment");
 static_assert(2 * kFastExtra <= kFastBuf * 2, "candidate staging in buf");
@@ -1487,6 +1492,38 @@ __device__ __forceinline__ void mfma_terms(const FactorArgs& a, const PredMeta* 
   }
 }
 
+// Rank sort of distinct keys: dst[#{u : src[u] < src[i]}] = src[i] for
+// every i < m.  The calling thread takes keys lt, lt + ln, ... (at most
+// kRankKeys of them, so m <= kRankKeys * ln) and counts against all of src
+// in one pass, reading four keys per 16-byte LDS load (src 16-byte aligned).
+constexpr int kRankKeys = 4;
+__device__ __forceinline__ void rank_place(const int* src, int m, int* dst, int lt, int ln) {
+  int v[kRankKeys], r[kRankKeys];
+#pragma unroll
+  for (int e = 0; e < kRankKeys; ++e) {
+    const int i = lt + e * ln;
+    v[e] = i < m ? src[i] : INT32_MIN;  // INT32_MIN: counts nothing
+    r[e] = 0;
+  }
+  const int m4 = m & ~3;
+  for (int u = 0; u < m4; u += 4) {
+    const int4 w = *reinterpret_cast<const int4*>(src + u);
+#pragma unroll
+    for (int e = 0; e < kRankKeys; ++e)
+      r[e] += (w.x < v[e]) + (w.y < v[e]) + (w.z < v[e]) + (w.w < v[e]);
+  }
+  for (int u = m4; u < m; ++u) {
+    const int w = src[u];
+#pragma unroll
+    for (int e = 0; e < kRankKeys; ++e) r[e] += w < v[e];
+  }
+#pragma unroll
+  for (int e = 0; e < kRankKeys; ++e) {
+    const int i = lt + e * ln;
+    if (i < m) dst[r[e]] = v[e];
+  }
+}
+
 template <bool kG>
 __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const FlowArgs& d, int K,
                                                  Lds& s, double* s_dyn, double* gslot, int next_pos) {
@@ -1523,10 +1560,15 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     fpred = s.x.pred;
     frpred = s.x.rpred;
   }
-  // ---- round 1: predecessor counts and inline lists, block range
+  // ---- round 1: predecessor counts and inline lists, block range.  The
+  // global variant resumes from the LDS variant's rounds 1 and 2 when that
+  // variant gave the block up after them (misc[31]): the counts, range,
+  // sorted predecessors, their data and A's pointers of K are in LDS.
+  const bool resume = kG && s.misc[31] != 0;
   int* rawc = stage;
   int* rawr = stage + cPreds;
-  if (tid < kListCap) {
+  if (resume) {
+  } else if (tid < kListCap) {
     rawc[tid] = a.col_list[(int64_t)K * kListCap + tid];
   } else if (tid >= 64 && tid < 64 + kListCap) {
     rawr[tid - 64] = a.row_list[(int64_t)K * kListCap + tid - 64];
@@ -1555,7 +1597,10 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   const int f = s.misc[2], l = s.misc[3] - 1, q = l - f + 1;
   if (q > kFastWidth || !a.lds_pivot) return kFastFallback;
   if (np + npr > cPreds) return fallback;
-  if (np > kListCap || npr > kListCap) {
+  if (resume) {
+    for (int t = tid; t < np; t += nt) fpred[t] = s.x.pred[t];
+    for (int t = tid; t < npr; t += nt) frpred[t] = s.x.rpred[t];
+  } else if (np > kListCap || npr > kListCap) {
     // overflow chains: one serial walk per list
     if ((tid == 0 && np > kListCap) || (tid == 64 && npr > kListCap)) {
       const bool col = tid == 0;
@@ -1573,7 +1618,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     if (s.misc[8]) return kFastFallback;  // the general path reports it
   }
   // ascending predecessor order (entries are distinct): rank sort
-  for (int t = tid; t < np + npr; t += nt) {
+  for (int t = resume ? np + npr : tid; t < np + npr; t += nt) {
     const bool col = t < np;
     const int* raw = col ? rawc : rawr;
     const int m = col ? np : npr, i = col ? t : t - np;
@@ -1585,7 +1630,10 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   __syncthreads();
 
   // ---- round 2: predecessor data, A's pointers of K; clear the hash
-  for (int t = tid; t < np + npr; t += nt) {
+  if (resume)  // the LDS variant's data (s.x.meta lies above the first
+               // cPreds entries of the global variant's fmeta, s.x.buf)
+    for (int t = tid; t < np + npr; t += nt) fmeta[t] = s.x.meta[t];
+  for (int t = resume ? np + npr : tid; t < np + npr; t += nt) {
     const int J = t < np ? fpred[t] : frpred[t - np];
     PredMeta& m = fmeta[t];
     m.roff = a.roff[J];
@@ -1600,8 +1648,8 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     m.ntc = a.ntc[J];
     m.p = a.bstart[J + 1] - a.bstart[J];
   }
-  if (tid >= 128 && tid <= 128 + q) s.x.cpk[tid - 128] = a.cp[f + tid - 128];
-  if (tid >= 160 && tid <= 160 + q) s.x.rpk[tid - 160] = a.rp[f + tid - 160];
+  if (!resume && tid >= 128 && tid <= 128 + q) s.x.cpk[tid - 128] = a.cp[f + tid - 128];
+  if (!resume && tid >= 160 && tid <= 160 + q) s.x.rpk[tid - 160] = a.rp[f + tid - 160];
   for (int t = tid; t < kHashSlots; t += nt) s.hash[t] = (!kG && t >= kFastOwnCnt) ? 0 : -1;
   if (tid == 0) {
     s.misc[4] = 0;
@@ -1610,6 +1658,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     s.misc[7] = 0;
     s.misc[9] = 0;
     s.misc[10] = 0;
+    s.misc[31] = kG ? 0 : 1;  // rounds 1 and 2 done (read after the barrier)
   }
   __syncthreads();
   if (tid == 0) trace_at(d, K, 2, wall_clock64());
@@ -1665,6 +1714,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   }
   const int* segoff = fseg;
   const int total = segoff[nseg];
+  if (tid == 0) trace_at(d, K, 20, wall_clock64());
 
   // ---- round 3: stage every list; candidate rows (keys r) and columns
   // (keys ~c) beyond the block go to one hash, and each new key to keys[]
@@ -1682,16 +1732,24 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   const int gA = segoff[2 + np], gap = kG ? segoff[2 + 2 * np + npr] - gA : 0;
   const int tv = tall - gap;
   for (int base = 0; base < tv; base += kBatch * nt) {
-    int v[kBatch];
+    int v[kBatch], sgk[kBatch];
+    // each entry's segment (in segoff, or in useg for K's own counts), kept
+    // for the insertion pass
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k) {
+      const int ev = base + tid + k * nt;
+      const int e = ev < gA ? ev : ev + gap;
+      sgk[k] = e < total ? last_le(segoff, nseg, e) : last_le(s.x.useg, nu, e - total);
+    }
     for (int k = 0; k < kBatch; ++k) {
       const int ev = base + tid + k * nt;
       const int e = ev < gA ? ev : ev + gap;
       if (ev >= tv) {
       } else if (e < total) {
-        const int sg = last_le(segoff, nseg, e);
+        const int sg = sgk[k];
         v[k] = fast_list(a, s, fmeta, sg, np, npr)[e - segoff[sg]];
       } else if (!kG && e < tall) {
-        const int sg = last_le(s.x.useg, nu, e - total);
+        const int sg = sgk[k];
         const int i = e - total - s.x.useg[sg];
         if (sg == 0)
           v[k] = a.bri[s.x.cpk[0] + i];
@@ -1709,7 +1767,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       const int e = ev < gA ? ev : ev + gap;
       if (e < total) {
         stage[e] = v[k];
-        const int sg = last_le(segoff, nseg, e);
+        const int sg = sgk[k];
         const bool rowc = sg == 0 || (sg >= 2 && sg < 2 + np);
         const bool colc = sg == 1 || sg >= 2 + 2 * np + npr;
         if ((rowc || colc) && v[k] > l)
@@ -1726,6 +1784,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     }
   }
   __syncthreads();
+  if (tid == 0) trace_at(d, K, 21, wall_clock64());
   if (!kG && s.misc[10]) return kFastBig;
   if (s.misc[5] || s.misc[4] > 2 * cExtra) return fallback;
   // positions inside the predecessors' sorted lists (the three searches of
@@ -1799,13 +1858,16 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     }
   }
   __syncthreads();
+  if (tid == 0) trace_at(d, K, 22, wall_clock64());
   const int nrow = s.misc[6], ncol = s.misc[7];
   const int mc = q + nrow, mcc = ncol;
   if (nrow > cExtra || ncol > cExtra || (mc + mcc) * q > cBuf - kThreads) return fallback;
   int p2r = 1, p2c = 1;
   while (p2r < nrow) p2r <<= 1;
   while (p2c < ncol) p2c <<= 1;
-  const bool rank_sort = nrow <= 256 && ncol <= 256;
+  // rank sort: rows by the first half of the threads, columns by the second
+  constexpr int kRankMax = kRankKeys * (kThreads / 2);
+  const bool rank_sort = nrow <= kRankMax && ncol <= kRankMax;
   if (!rank_sort && (q + p2r > kCandCap || p2c > kCandCap)) return kFastFallback;
   if (rank_sort) {
     const int* srcR = tmpR;
@@ -1814,23 +1876,16 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       // the lists sit in global scratch: rank them from LDS (the candidate
       // hash is no longer needed)
       for (int t = tid; t < nrow; t += nt) s.hash[t] = tmpR[t];
-      for (int t = tid; t < ncol; t += nt) s.hash[256 + t] = tmpC[t];
+      for (int t = tid; t < ncol; t += nt) s.hash[kRankMax + t] = tmpC[t];
       __syncthreads();
       srcR = s.hash;
-      srcC = s.hash + 256;
+      srcC = s.hash + kRankMax;
     }
-    for (int t = tid; t < nrow + ncol; t += nt) {
-      const bool row = t < nrow;
-      const int* src = row ? srcR : srcC;
-      const int m = row ? nrow : ncol, i = row ? t : t - nrow;
-      const int v = src[i];
-      int r = 0;
-      for (int u = 0; u < m; ++u) r += src[u] < v;
-      if (row)
-        s.cand[q + r] = v;
-      else
-        s.candc[r] = v;
-    }
+    const int half = nt >> 1;
+    if (tid < half)
+      rank_place(srcR, nrow, s.cand + q, tid, half);
+    else
+      rank_place(srcC, ncol, s.candc, tid - half, half);
   } else {
     for (int t = tid; t < nrow; t += nt) s.cand[q + t] = tmpR[t];
     for (int t = tid; t < ncol; t += nt) s.candc[t] = tmpC[t];
@@ -1839,6 +1894,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     wg_bitonic_sort(s.candc, ncol);
   }
   for (int t = tid; t < q; t += nt) s.cand[t] = f + t;
+  if (tid == 0) trace_at(d, K, 23, wall_clock64());
   // update terms per predecessor: column panel (rows >= f) x (columns in K),
   // row panel (rows in K) x (columns > l); their offsets by one wave when
   // there are at most 64 predecessors
@@ -1918,7 +1974,13 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   // (without a.det the terms go straight into the panels: one chunk)
   const int cap = a.det ? (cBuf - (mc + mcc) * q) * 2 / 3 : max(nterms, 1);
   int* Ti = reinterpret_cast<int*>(Tm + cap);
-  for (int e = tid; e < (mc + mcc) * q; e += nt) Cp[e] = 0.0;
+  // the panels accumulate in P: the global variant's go to LDS when both
+  // fit the hash area (free from the candidate sort to the drop test) and
+  // are copied to the global slot afterwards
+  const int npanel = (mc + mcc) * q;
+  const bool lpanel = kG && npanel <= kHashSlots / 2;
+  double* P = lpanel ? reinterpret_cast<double*>(s.hash) : fbuf;
+  for (int e = tid; e < npanel; e += nt) P[e] = 0.0;
   __syncthreads();
   // A's entries of K: panel position (-1: outside the panels) and value
   const int nA0 = segoff[1], nA = segoff[2];
@@ -1926,9 +1988,9 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     const AEntry x = a_entry(a, s, stage, e, nA0, f, l, q, mc, mcc);
     if (x.tgt >= 0) {
       if (a.det)
-        fbuf[x.tgt] = *x.src;
+        P[x.tgt] = *x.src;
       else
-        atomicAdd(&fbuf[x.tgt], *x.src);  // the terms may already be arriving
+        atomicAdd(&P[x.tgt], *x.src);  // the terms may already be arriving
     }
   }
   // the first nt: loaded now, stored with the first chunk of terms, so both
@@ -2082,7 +2144,8 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
           for (int u = 0; u < kU; ++u) acc[u] = (double)fa[u];
         }
       }
-      // (3) positions in the panels
+      // (3) positions in the panels: the candidate row (column) of each
+      // term by branch-free lower bounds stepping together
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int e = e0 + u * nt;
@@ -2093,16 +2156,16 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
             if (!a.mfma) Tm[e - i0] = acc[u];
             Ti[e - i0] = pos;
           } else {
-            atomicAdd(&fbuf[pos], -acc[u]);  // any order: not run-to-run reproducible
+            atomicAdd(&P[pos], -acc[u]);  // any order: not run-to-run reproducible
           }
         }
       }
     }
     if (i0 == 0 && a_tgt >= 0) {
       if (a.det)
-        fbuf[a_tgt] = a_val;
+        P[a_tgt] = a_val;
       else
-        atomicAdd(&fbuf[a_tgt], a_val);
+        atomicAdd(&P[a_tgt], a_val);
     }
     __syncthreads();
     if (i0 == 0 && tid == 0) trace_at(d, K, 9, wall_clock64());  // first chunk's terms done
@@ -2110,7 +2173,14 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     // (4) in predecessor order (a predecessor's terms hit distinct
     // entries).  Column predecessors update only the column panel and row
     // predecessors only the row panel, so the k-th of each go together.
-    for (int k = 0; k < max(np, npr); ++k) {
+    // Each thread's first kAhead entries of the next pair are loaded before
+    // the barrier of the current one.
+    constexpr int kAhead = 2;
+    const int kmax = max(np, npr);
+    int ra0 = 0, rna = 0, rb0 = 0, rnab = 0;  // the current pair's term ranges
+    int pi[kAhead];
+    double pv[kAhead];
+    auto fetch = [&](int k) {
       int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
       if (k < np) {
         a0 = max(i0, fmeta[k].ioff);
@@ -2121,17 +2191,42 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
         b0 = max(i0, fmeta[t].ioff);
         b1 = min(i1, t + 1 < npt ? fmeta[t + 1].ioff : nterms);
       }
-      const int na = max(0, a1 - a0), nab = na + max(0, b1 - b0);
-      if (nab == 0) continue;
-      for (int x = tid; x < nab; x += nt) {
-        const int e = x < na ? a0 + x : b0 + (x - na);
-        fbuf[Ti[e - i0]] -= Tm[e - i0];
+      ra0 = a0;
+      rb0 = b0;
+      rna = max(0, a1 - a0);
+      rnab = rna + max(0, b1 - b0);
+#pragma unroll
+      for (int r = 0; r < kAhead; ++r) {
+        const int x = tid + r * nt;
+        pi[r] = -1;
+        if (x < rnab) {
+          const int e = (x < rna ? ra0 + x : rb0 + (x - rna)) - i0;
+          pi[r] = Ti[e];
+          pv[r] = Tm[e];
+        }
       }
-      __syncthreads();
+    };
+    if (kmax > 0) fetch(0);
+    for (int k = 0; k < kmax; ++k) {
+      // a pair's positions are distinct: all reads, then all writes
+#pragma unroll
+      for (int r = 0; r < kAhead; ++r)
+        if (pi[r] >= 0) P[pi[r]] -= pv[r];
+      for (int x = tid + kAhead * nt; x < rnab; x += nt) {  // beyond the loaded ones
+        const int e = (x < rna ? ra0 + x : rb0 + (x - rna)) - i0;
+        P[Ti[e]] -= Tm[e];
+      }
+      const bool any = rnab > 0;  // uniform
+      if (k + 1 < kmax) fetch(k + 1);
+      if (any) __syncthreads();
     }
   }
-  if (nterms == 0 && a_tgt >= 0) fbuf[a_tgt] = a_val;  // no chunk ran (no term can race)
+  if (nterms == 0 && a_tgt >= 0) P[a_tgt] = a_val;  // no chunk ran (no term can race)
   __syncthreads();
+  if (lpanel) {
+    for (int e = tid; e < npanel; e += nt) fbuf[e] = P[e];
+    __syncthreads();
+  }
   if (tid == 0) {
     const unsigned long long now = wall_clock64();
     trace_at(d, K, 8, now);
@@ -2487,6 +2582,7 @@ __global__ void __launch_bounds__(kThreads, 2) factor_worker_kernel(FactorArgs a
     if (threadIdx.x == 0) {
       s.misc[25] = -1;
       s.misc[29] = -1;  // set by the fast path when it claims or reads ahead
+      s.misc[31] = 0;   // set by the LDS variant once its rounds 1 and 2 are done
     }
     int r = kFastFallback;
     if (a.fast_path == 1) r = factor_block_fast<false>(a, d, K, s, s_dyn, nullptr, next_pos);

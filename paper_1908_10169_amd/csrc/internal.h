@@ -178,7 +178,7 @@ struct FlowArgs {
   unsigned long long* trace;
 };
 
-constexpr int kTraceFields = 20;
+constexpr int kTraceFields = 24;
 
 // Bound of one dependency wait in seconds: a wait that exceeds it reports
 // an error instead of hanging.
