@@ -391,6 +391,11 @@ constexpr int kFastOwnCnt = kFastCandSlots + kFastOwnSlots;  // counts
 // slot, for blocks beyond the LDS capacities; the per-predecessor data stays
 // in LDS (in the space the LDS variant uses for lists and panels).
 constexpr int kBigPreds = 300;
+// The global variant's own-count table (keys, then counts) at the end of
+// the LDS variant's panel and metadata space, when the predecessor data
+// leaves room for it; else that variant counts in a pass of its own after
+// the factor writes.
+constexpr int kGOwnSlots = 1024;
 constexpr int kBigStage = 65536;
 constexpr int kBigBuf = 65536;
 
@@ -402,6 +407,8 @@ struct PredMeta {
   long long roff, coff, loff, woff, troff, tcoff;
   int nr, nc, p, ntr, ntc, lo, hi, lo2, ioff, pad;
 };
+// bytes of the LDS variant's panel and metadata space (contiguous in Lds)
+constexpr int kRegionBytes = sizeof(double) * kFastBuf + sizeof(PredMeta) * kFastPreds;
 
 struct alignas(16) Lds {
   int hash[kHashSlots];     // candidate dedup; reused as keep flags; panels of
@@ -454,7 +461,9 @@ static_assert(sizeof(PredMeta) % 8 == 0, "PredMeta alignment");
 constexpr int64_t kBigSlotDoubles = kBigBuf + kBigStage / 2 + 8;
 static_assert(kBigPreds * sizeof(PredMeta) <= sizeof(double) * kFastBuf + sizeof(PredMeta) * kFastPreds,
               "global variant: predecessor data in LDS");
-static_assert(2 * kBigPreds + 4 + 2 * kBigPreds <= kFastStage, "global variant: offsets in LDS");
+static_assert(2 * kBigPreds + 4 + 2 * kBigPreds + kBigPreds + 3 <= kFastStage,
+              "global variant: list offsets and own-count offsets in LDS");
+static_assert(kRegionBytes % 16 == 0 && 8 * kGOwnSlots < kRegionBytes, "global variant: own-count table");
 static_assert(offsetof(Lds, x.meta) == offsetof(Lds, x.buf) + sizeof(double) * kFastBuf,
               "global variant: the predecessor data spans buf and meta");
 static_assert(kThreads >= 192 && kListCap <= 64 && kFastWidth + 1 <= 32, "round-1 thread map");
@@ -1597,6 +1606,14 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   const int f = s.misc[2], l = s.misc[3] - 1, q = l - f + 1;
   if (q > kFastWidth || !a.lds_pivot) return kFastFallback;
   if (np + npr > cPreds) return fallback;
+  // K's own counts come with the staging pass (round 3) in the LDS variant
+  // and, when its predecessor data leaves room for the table, in the global
+  // variant (gown, over the end of the LDS variant's panel and metadata)
+  const bool ownearly =
+      !kG || (np + npr) * (int)sizeof(PredMeta) <= kRegionBytes - 8 * kGOwnSlots;
+  int* const gown = reinterpret_cast<int*>(reinterpret_cast<char*>(s.x.buf) + kRegionBytes) -
+                    2 * kGOwnSlots;
+  int* const fuseg = kG ? fpred + 2 * kBigPreds : s.x.useg;  // offsets of the own-count lists
   if (resume) {
     for (int t = tid; t < np; t += nt) fpred[t] = s.x.pred[t];
     for (int t = tid; t < npr; t += nt) frpred[t] = s.x.rpred[t];
@@ -1685,28 +1702,30 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       }
       fseg[g] = len;
     }
-    if (!kG)
+    if (ownearly)
       for (int g = tid; g < 2 + np + npr; g += nt)
-        s.x.useg[g] = g == 0   ? (int)(s.x.cpk[q] - s.x.cpk[0])
-                      : g == 1 ? (int)(s.x.rpk[q] - s.x.rpk[0])
-                      : g - 2 < np ? fmeta[g - 2].ntr
-                                   : fmeta[g - 2].ntc;
+        fuseg[g] = g == 0   ? (int)(s.x.cpk[q] - s.x.cpk[0])
+                   : g == 1 ? (int)(s.x.rpk[q] - s.x.rpk[0])
+                   : g - 2 < np ? fmeta[g - 2].ntr
+                                : fmeta[g - 2].ntc;
+    if (kG && ownearly)  // after the barrier that ends the resumed copy of s.x.meta
+      for (int t = tid; t < 2 * kGOwnSlots; t += nt) gown[t] = t < kGOwnSlots ? -1 : 0;
     __syncthreads();
     const int nu = 2 + np + npr;
     if (nseg <= 64 && nu <= 64) {
       // both offset arrays at once, by waves 0 and 1
       if (tid < 64)
         wave_scan_array(fseg, nseg, &fseg[nseg]);
-      else if (!kG && tid < 128)
-        wave_scan_array(s.x.useg, nu, &s.x.useg[nu]);
+      else if (ownearly && tid < 128)
+        wave_scan_array(fuseg, nu, &fuseg[nu]);
       __syncthreads();
       if (fseg[nseg] > cStage) return fallback;
     } else {
       const int total = wg_scan_array(fseg, nseg, s.scan);
       if (tid == 0) fseg[nseg] = total;
-      if (!kG) {
-        const int tot = wg_scan_array(s.x.useg, nu, s.scan);
-        if (tid == 0) s.x.useg[nu] = tot;
+      if (ownearly) {
+        const int tot = wg_scan_array(fuseg, nu, s.scan);
+        if (tid == 0) fuseg[nu] = tot;
       }
       if (total > cStage) return fallback;
       __syncthreads();
@@ -1722,7 +1741,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   // K's own counts come with the same pass (LDS variant): A's entries of K
   // in later blocks, TR_J > K of column predecessors, TC_J > K of row
   // predecessors; entries [total, total + totu) of the combined index range
-  const int nu = 2 + np + npr, totu = kG ? 0 : s.x.useg[nu];
+  const int nu = 2 + np + npr, totu = ownearly ? fuseg[nu] : 0;
   const int tall = total + totu;
   // the column lists of column predecessors and the row lists of row
   // predecessors (one contiguous range of segments) are only searched for
@@ -1739,7 +1758,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     for (int k = 0; k < kBatch; ++k) {
       const int ev = base + tid + k * nt;
       const int e = ev < gA ? ev : ev + gap;
-      sgk[k] = e < total ? last_le(segoff, nseg, e) : last_le(s.x.useg, nu, e - total);
+      sgk[k] = e < total ? last_le(segoff, nseg, e) : last_le(fuseg, nu, e - total);
     }
     for (int k = 0; k < kBatch; ++k) {
       const int ev = base + tid + k * nt;
@@ -1748,9 +1767,9 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
       } else if (e < total) {
         const int sg = sgk[k];
         v[k] = fast_list(a, s, fmeta, sg, np, npr)[e - segoff[sg]];
-      } else if (!kG && e < tall) {
+      } else if (e < tall) {
         const int sg = sgk[k];
-        const int i = e - total - s.x.useg[sg];
+        const int i = e - total - fuseg[sg];
         if (sg == 0)
           v[k] = a.bri[s.x.cpk[0] + i];
         else if (sg == 1)
@@ -1774,18 +1793,21 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
           if (!hash_insert_list(s.hash, kG ? kHashSlots : kFastCandSlots, rowc ? v[k] : ~v[k],
                                 &s.misc[4], keys, 2 * cExtra))
             s.misc[5] = 1;
-      } else if (!kG && v[k] > K) {
-        const int h = hash_insert_at_n(s.hash + kFastOwn, kFastOwnSlots, v[k], &s.misc[9]);
+      } else if (v[k] > K) {  // e < tall: only when ownearly
+        int* const tab = kG ? gown : s.hash + kFastOwn;
+        const int h = hash_insert_at_n(tab, kG ? kGOwnSlots : kFastOwnSlots, v[k], &s.misc[9]);
         if (h < 0)
           s.misc[10] = 1;
         else
-          atomicAdd(&s.hash[kFastOwnCnt + h], 1);
+          atomicAdd(&tab[(kG ? kGOwnSlots : kFastOwnSlots) + h], 1);
       }
     }
   }
   __syncthreads();
   if (tid == 0) trace_at(d, K, 21, wall_clock64());
   if (!kG && s.misc[10]) return kFastBig;
+  // the global variant's early table overflowed: it counts after the writes
+  const bool ownlate = kG && (!ownearly || s.misc[10] != 0);
   if (s.misc[5] || s.misc[4] > 2 * cExtra) return fallback;
   // positions inside the predecessors' sorted lists (the three searches of
   // a predecessor step together, so their loads overlap)
@@ -1969,7 +1991,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   // ---- round 4: A's values into the panels, update terms (chunked)
   double* Cp = fbuf;                    // mc x q, row-major
   double* Rp = Cp + mc * q;             // mcc x q (column z of the row panel)
-  double* Tm = Rp + mcc * q;            // update terms
+  double* const Tm = Rp + mcc * q;      // update terms
   // a chunk holds cap terms and, after them, each term's panel position
   // (without a.det the terms go straight into the panels: one chunk)
   const int cap = a.det ? (cBuf - (mc + mcc) * q) * 2 / 3 : max(nterms, 1);
@@ -2223,9 +2245,21 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   }
   if (nterms == 0 && a_tgt >= 0) P[a_tgt] = a_val;  // no chunk ran (no term can race)
   __syncthreads();
-  if (lpanel) {
+  // the LDS panels stay there through the pivot, drop test and factor
+  // writes when the keep flags fit the LDS after the predecessor data (the
+  // global variant keeps that data over the LDS variant's panel, metadata
+  // and nothing else there); else they go to the global slot
+  int* const keep_lds = reinterpret_cast<int*>(fmeta + npt);
+  const bool lkeep =
+      lpanel && (int64_t)(mc + mcc) * (int64_t)sizeof(int) + (int64_t)npt * (int64_t)sizeof(PredMeta) <=
+                    (int64_t)kRegionBytes - (ownlate ? 0 : 8 * kGOwnSlots);
+  if (lpanel && !lkeep) {
     for (int e = tid; e < npanel; e += nt) fbuf[e] = P[e];
     __syncthreads();
+  }
+  if (lkeep) {
+    Cp = P;
+    Rp = P + mc * q;
   }
   if (tid == 0) {
     const unsigned long long now = wall_clock64();
@@ -2238,8 +2272,8 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   double* sW = s_dyn + q * q;
   // wave 0 takes the pivot block; the other waves meanwhile look up the
   // blocks of the candidate rows and columns (the staged lists are done)
-  int* keep_r = s.hash;
-  int* keep_c = s.hash + (kG ? kCandCap : 1024);  // below the own-count table
+  int* keep_r = lkeep ? keep_lds : s.hash;
+  int* keep_c = lkeep ? keep_lds + mc : s.hash + (kG ? kCandCap : 1024);  // below the own-count table
   int* rblk = stage;                // block of candidate row z
   int* cblk = stage + cSpace;       // block of candidate column z
   int* rbp = stage + 2 * cSpace;    // position in TR_K of the first kept row of a block
@@ -2359,16 +2393,25 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     a.ntr[K] = ntr;
     a.tcoff[K] = io + mk + nk + ntr;
     a.ntc[K] = ntc;
+  } else if (tid >= 64 && tid < 128) {
+    // the update flops and bytes of the block, one wave over the predecessors
     double flops = 0.0, ubytes = 0.0;
-    for (int t = 0; t < npt; ++t) {
+    for (int t = tid - 64; t < npt; t += 64) {
       const PredMeta& m = fmeta[t];
       const int nr = t < np ? m.nr - m.lo2 : m.hi - m.lo;
       const int nc = t < np ? m.hi - m.lo : m.nc - m.lo2;
       flops += 2.0 * nr * nc * m.p;
       ubytes += (double)a.elem_bytes * m.p * (nr + nc);
     }
-    s.acc_flops += (unsigned long long)flops;
-    s.acc_bytes += (unsigned long long)ubytes;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      flops += __shfl_xor(flops, o, 64);
+      ubytes += __shfl_xor(ubytes, o, 64);
+    }
+    if (tid == 64) {
+      s.acc_flops += (unsigned long long)flops;
+      s.acc_bytes += (unsigned long long)ubytes;
+    }
   }
   __syncthreads();
   if (tid == 0) trace_at(d, K, 13, wall_clock64());
@@ -2400,15 +2443,15 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     push_pred_at(a, row ? a.row_list : a.col_list, row ? a.row_ovf : a.col_ovf, B, K, pos);
   }
   if (tid == 0) trace_at(d, K, 14, wall_clock64());
-  if (kG) __syncthreads();  // trS / tcS overlay the counts cleared below
+  if (ownlate) __syncthreads();  // trS / tcS overlay the counts cleared below
 
   // ---- K's own counts (as updater_set): A's entries of K in later blocks,
   // TR_J > K of column predecessors, TC_J > K of row predecessors; the LDS
   // variant built them while staging
-  int* own = kG ? s.hash : s.hash + kFastOwn;
-  int* cnt = kG ? s.cand : s.hash + kFastOwnCnt;  // per hash slot
-  const int own_slots = kG ? kHashSlots : kFastOwnSlots;
-  if (kG) {
+  int* own = ownlate ? s.hash : kG ? gown : s.hash + kFastOwn;
+  int* cnt = ownlate ? s.cand : kG ? gown + kGOwnSlots : s.hash + kFastOwnCnt;  // per hash slot
+  const int own_slots = ownlate ? kHashSlots : kG ? kGOwnSlots : kFastOwnSlots;
+  if (ownlate) {
   for (int t = tid; t < kHashSlots; t += nt) {
     s.hash[t] = -1;
     cnt[t] = 0;
