@@ -8,7 +8,9 @@
 // and the row set J~_k of U is the same with the roles of rows and columns
 // exchanged.  One wave computes both sets of one k: it dedups the direct
 // entries and the fill candidates in an LDS hash and writes them to a
-// padded per-k slot.
+// padded per-k slot.  A source j whose largest off-diagonal entry cannot
+// pass the fill test with a_jk is skipped without reading its column (the
+// bound is exact, so the sets do not change).
 //
 // Growth.  A block started at unit s (a cosine group) takes the next unit
 // while the dense count f' = (r'+s'+l') l' stays within 4/3 of the scalar
@@ -45,6 +47,8 @@ struct IluArgs {
   const int64_t* cp; const int32_t* ri; const double* cv;   // CSC
   const int64_t* rp; const int32_t* ci; const double* rv;   // CSR
   const double* dg;                // diagonal entries (0 when absent)
+  const double* cmax;              // largest |a_ij|, i != j, of column j (CSC)
+  const double* rmax;              // largest |a_ji|, i != j, of row j (CSR)
   const int64_t* gs;               // unit starts [nu+1]
   int32_t* iset; int32_t* jset;    // [n * kSetCap]
   int32_t* icnt; int32_t* jcnt;    // [n]
@@ -60,6 +64,17 @@ __global__ void diag_kernel(int n, const int64_t* rp, const int32_t* ci, const d
   for (int64_t m = rp[i]; m < rp[i + 1]; ++m)
     if (ci[m] == i) d = rv[m];
   dg[i] = d;
+}
+
+// Largest off-diagonal magnitude of every row (CSR) or column (CSC).
+__global__ void offdiag_max_kernel(int n, const int64_t* ptr, const int32_t* idx, const double* val,
+                                   double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double m = 0.0;
+  for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e)
+    if (idx[e] != i) m = fmax(m, fabs(val[e]));
+  out[i] = m;
 }
 
 // Wave-local insert; false when the table is full.
@@ -95,7 +110,7 @@ struct SetLds {
 // One side of the sets of k: (ptr, idx, val) is the CSC for I~_k and the
 // CSR for J~_k.  Writes the set to out[0..cnt) and returns cnt, or -1.
 __device__ int one_set(const IluArgs& a, const int64_t* ptr, const int32_t* idx, const double* val,
-                       int k, SetLds& s, int w, int32_t* out) {
+                       const double* smax, int k, SetLds& s, int w, int32_t* out) {
   const int lane = threadIdx.x & 63;
   int* hash = s.hash[w];
   int* misc = s.misc[w];
@@ -107,13 +122,17 @@ __device__ int one_set(const IluArgs& a, const int64_t* ptr, const int32_t* idx,
   }
   wave_sync();
   const double akk = fabs(a.dg[k]);
+  const double dk = a.dg[k];
   const int64_t b = ptr[k], e = ptr[k + 1];
   for (int64_t m = b + lane; m < e; m += 64) {
     const int i = idx[m];
     const double v = val[m];
     if (i > k && fabs(v) >= a.tau * akk)
       if (!wave_insert(hash, kSetHash, i, &misc[0])) misc[1] = 1;
-    if (i < k) {
+    // a source none of whose entries can pass the fill test is left out:
+    // every candidate product is at most |smax_i v| in magnitude (rounding
+    // is monotone), compared with the candidate test's own threshold
+    if (i < k && fabs(smax[i] * v) >= a.tau * fabs(a.dg[i] * dk)) {
       const int o = atomicAdd(&misc[2], 1);
       if (o < kSrcCap) {
         s.src[w][o] = i;
@@ -149,7 +168,6 @@ __device__ int one_set(const IluArgs& a, const int64_t* ptr, const int32_t* idx,
   if (lane == 0) s.off[w][nsrc] = base;
   wave_sync();
   const int total = base;
-  const double dk = a.dg[k];
   for (int x0 = 0; x0 < total; x0 += 64 * kCandBatch) {
     // sources first (LDS), then every candidate's loads, then the tests
     int iv[kCandBatch], sl[kCandBatch];
@@ -199,8 +217,8 @@ __global__ void __launch_bounds__(64 * kWaves) ilu_sets_kernel(IluArgs a) {
   __shared__ SetLds s;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int k = blockIdx.x * kWaves + w; k < a.n; k += gridDim.x * kWaves) {
-    const int ci_ = one_set(a, a.cp, a.ri, a.cv, k, s, w, a.iset + (int64_t)k * kSetCap);
-    const int cj_ = one_set(a, a.rp, a.ci, a.rv, k, s, w, a.jset + (int64_t)k * kSetCap);
+    const int ci_ = one_set(a, a.cp, a.ri, a.cv, a.cmax, k, s, w, a.iset + (int64_t)k * kSetCap);
+    const int cj_ = one_set(a, a.rp, a.ci, a.rv, a.rmax, k, s, w, a.jset + (int64_t)k * kSetCap);
     if (lane == 0) {
       a.icnt[k] = ci_;
       a.jcnt[k] = cj_;
@@ -310,12 +328,16 @@ int64_t ilu1t_partition_device(bilu_handle* h, double tau, std::vector<int32_t>&
   hipStream_t st = h->stream;
   // the unit starts and the diagonal depend on the analyzed matrix only
   if (!h->ilu_static) {
-    if (h->d_ilu_gs.alloc(gs.size()) != hipSuccess || h->d_ilu_dg.alloc(n) != hipSuccess ||
+    if (h->d_ilu_gs.alloc(gs.size()) != hipSuccess || h->d_ilu_dg.alloc(3 * n) != hipSuccess ||
         hipMemcpyAsync(h->d_ilu_gs.p, gs.data(), gs.size() * sizeof(int64_t), hipMemcpyHostToDevice,
                        st) != hipSuccess)
       return -1;
     diag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>((int)n, h->d_rp.p, h->d_ci.p, h->d_rv.p,
                                                              h->d_ilu_dg.p);
+    offdiag_max_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+        (int)n, h->d_cp.p, h->d_ri.p, h->d_cv.p, h->d_ilu_dg.p + n);
+    offdiag_max_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+        (int)n, h->d_rp.p, h->d_ci.p, h->d_rv.p, h->d_ilu_dg.p + 2 * n);
     if (hipGetLastError() != hipSuccess) return -1;
     h->ilu_static = true;
   }
@@ -330,6 +352,8 @@ int64_t ilu1t_partition_device(bilu_handle* h, double tau, std::vector<int32_t>&
   a.cp = h->d_cp.p; a.ri = h->d_ri.p; a.cv = h->d_cv.p;
   a.rp = h->d_rp.p; a.ci = h->d_ci.p; a.rv = h->d_rv.p;
   a.dg = h->d_ilu_dg.p;
+  a.cmax = h->d_ilu_dg.p + n;
+  a.rmax = h->d_ilu_dg.p + 2 * n;
   a.gs = h->d_ilu_gs.p;
   a.iset = h->d_ilu_set.p;
   a.jset = h->d_ilu_set.p + n * kSetCap;
