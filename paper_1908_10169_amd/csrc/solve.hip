@@ -58,15 +58,30 @@ __global__ void __launch_bounds__(256) fw_fill(FactorView f, const int32_t* ptr,
   }
 }
 
-// Sort each block's keys (ascending J) and unpack them.
-__global__ void __launch_bounds__(64) fw_sort(int nb, const int32_t* ptr, unsigned long long* keys,
-                                              int32_t* fw_j, int32_t* fw_r0, int32_t* fw_cnt) {
-  const int K = blockIdx.x;
-  if (K >= nb) return;
+// Sort each block's keys (ascending J; the keys of a block are distinct)
+// and unpack them.  One wave per block: up to 64 keys are ranked in
+// registers, longer lists by an insertion sort of lane 0.
+__global__ void __launch_bounds__(256) fw_sort(int nb, const int32_t* ptr, unsigned long long* keys,
+                                               int32_t* fw_j, int32_t* fw_r0, int32_t* fw_cnt) {
+  const int K = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (K >= nb) return;  // no workgroup barrier below
+  const int lane = threadIdx.x & 63;
   const int b = ptr[K], m = ptr[K + 1] - b;
-  if (threadIdx.x == 0) {
+  auto put = [&](int i, unsigned long long v) {
+    fw_j[b + i] = (int32_t)(v >> 32);
+    fw_r0[b + i] = (int32_t)((v >> 8) & 0xffffff);
+    fw_cnt[b + i] = (int32_t)(v & 0xff);
+  };
+  if (m <= 64) {
+    const unsigned long long v = lane < m ? keys[b + lane] : ~0ull;
+    int r = 0;
+    for (int j = 0; j < m; ++j) r += __shfl(v, j, 64) < v;
+    if (lane < m) put(r, v);
+    return;
+  }
+  if (lane == 0) {
     unsigned long long* k = keys + b;
-    for (int i = 1; i < m; ++i) {  // insertion sort: lists are short
+    for (int i = 1; i < m; ++i) {
       unsigned long long v = k[i];
       int j = i - 1;
       while (j >= 0 && k[j] > v) {
@@ -76,13 +91,9 @@ __global__ void __launch_bounds__(64) fw_sort(int nb, const int32_t* ptr, unsign
       k[j + 1] = v;
     }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < m; i += blockDim.x) {
-    const unsigned long long v = keys[b + i];
-    fw_j[b + i] = (int32_t)(v >> 32);
-    fw_r0[b + i] = (int32_t)((v >> 8) & 0xffffff);
-    fw_cnt[b + i] = (int32_t)(v & 0xff);
-  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int i = lane; i < m; i += 64) put(i, keys[b + i]);
 }
 
 // Distinct blocks of C_K (successors of K in the backward sweep).
@@ -97,23 +108,30 @@ __global__ void __launch_bounds__(256) bw_count(FactorView f, int32_t* cnt) {
   c = wave_sum(c);
   if (lane == 0) cnt[K] = c;
 }
-__global__ void __launch_bounds__(64) bw_fill(FactorView f, const int32_t* ptr, int32_t* bw_b) {
-  const int K = blockIdx.x;
-  if (K >= f.nb || threadIdx.x != 0) return;
+// One wave per block: the first column of every run of one block, in
+// order (ballot compaction 64 columns at a time).
+__global__ void __launch_bounds__(256) bw_fill(FactorView f, const int32_t* ptr, int32_t* bw_b) {
+  const int K = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (K >= f.nb) return;
+  const int lane = threadIdx.x & 63;
   const int32_t* Cc = f.idx + f.coff[K];
   const int m = f.nc[K];
   int at = ptr[K];
-  for (int i = 0; i < m; ++i) {
-    const int B = f.blockOf[Cc[i]];
-    if (i == 0 || f.blockOf[Cc[i - 1]] != B) bw_b[at++] = B;
+  for (int i0 = 0; i0 < m; i0 += 64) {
+    const int i = i0 + lane;
+    const int B = i < m ? f.blockOf[Cc[i]] : -1;
+    const bool head = i < m && (i == 0 || f.blockOf[Cc[i - 1]] != B);
+    const unsigned long long hm = __ballot(head);
+    if (head) bw_b[at + __popcll(hm & ((1ull << lane) - 1ull))] = B;
+    at += __popcll(hm);
   }
 }
 
 // Dependency levels of the apply: level(K) = 1 + the largest level of the
 // blocks K depends on (0 without any); forward over fw lists (J < K),
-// backward over bw lists (B > K).  One wave per block: slots 0..nb-1 are the
-// forward blocks in ascending order, slots nb..2nb-1 the backward blocks in
-// descending order, so every dependency of a slot sits at a lower slot.
+// backward over bw lists (B > K).  One wave per block: even slots 2i are
+// the forward blocks in ascending order, odd slots 2i+1 the backward blocks
+// in descending order, so every dependency of a slot sits at a lower slot.
 // Workgroup g runs slots 4g..4g+3, g its index (the hardware starts a
 // launch's workgroups in index order) or, with ticket, the order in which
 // workgroups took a ticket when they started.  Either way every workgroup
@@ -135,8 +153,10 @@ __global__ void __launch_bounds__(256) apply_levels(int nb, const int32_t* fptr,
   const int lane = threadIdx.x & 63;
   const int s = id * 4 + (int)(threadIdx.x >> 6);
   if (s >= 2 * nb) return;  // no workgroup barrier below
-  const bool fwd = s < nb;
-  const int K = fwd ? s : 2 * nb - 1 - s;
+  // the two directions interleave (they do not depend on each other): even
+  // slots forward in ascending, odd slots backward in descending order
+  const bool fwd = (s & 1) == 0;
+  const int K = fwd ? s >> 1 : nb - 1 - (s >> 1);
   const int32_t* ptr = fwd ? fptr : bptr;
   const int32_t* adj = fwd ? fj : bb;
   int* lev = fwd ? lf : lb;
@@ -778,7 +798,7 @@ bilu_status block_runs(bilu_handle* h, const FactorView& f, bool cols, DevArray<
   CK(keys.alloc(ne));
   CK(hipMemsetAsync(c.p, 0, (nb + 1) * sizeof(int32_t), st));
   fw_fill<<<gw, 256, 0, st>>>(f, ptr.p, c.p, keys.p, cols ? 1 : 0);
-  fw_sort<<<(unsigned)nb, 64, 0, st>>>((int)nb, ptr.p, keys.p, j.p, s0.p, cnt.p);
+  fw_sort<<<gw, 256, 0, st>>>((int)nb, ptr.p, keys.p, j.p, s0.p, cnt.p);
   CK(hipGetLastError());
   CK(hipStreamSynchronize(st));  // keys and counts are freed here
   return BILU_OK;
@@ -808,7 +828,7 @@ bilu_status build_apply_plan(bilu_handle* h) {
   int32_t nbw = 0;
   CK(device_scan<int32_t>(h, cnt.p, h->bw_ptr.p, nb, &nbw));
   CK(h->bw_b.alloc(std::max<int32_t>(1, nbw)));
-  bw_fill<<<(unsigned)nb, 64, 0, st>>>(f, h->bw_ptr.p, h->bw_b.p);
+  bw_fill<<<gw, 256, 0, st>>>(f, h->bw_ptr.p, h->bw_b.p);
   // the precision the apply reads L and W in: the stored one, or FP32
   // copies of FP64 values (apply_precision)
   h->apply_prec = f.vprec != kValF64 ? f.vprec
