@@ -136,6 +136,7 @@ def time_form(w, prec, args, project, agg):
     elapsed = time.perf_counter() - t0
     st = h.stats()
     assert st["apply_faults"] == 0, "a dataflow apply timed out"
+    assert st["ilu1t_host"] == 0, "the ILU(1,tau) partition was computed on the host"
     info = infos[-1]
     res = float(np.linalg.norm(b_host - w.a.matvec(x.cpu().numpy())) / np.linalg.norm(b_host))
     r_kept = h.kept_residual()   # outside the timed region
@@ -186,6 +187,7 @@ def form_summary(rec, steps, prec):
         "schur_update": {"tflops": round(upd_tflops, 6), "peak": upd_peak,
                          "frac": round(upd_tflops / upd_peak, 8)},
         "apply_faults": st["apply_faults"],
+        "ilu1t_host": st["ilu1t_host"],
     }
 
 

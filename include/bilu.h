@@ -179,6 +179,9 @@ typedef struct {
   int64_t tuning_applied;     /* 1 when a tuned entry set the last factorization's    */
                               /* kernel settings                                       */
   int64_t max_width_initial;  /* widest block of the initial partition                */
+  int64_t ilu1t_host;         /* 1 when the ILU(1,tau) partition of the last          */
+                              /* factorization came from the host computation (a      */
+                              /* device kernel capacity was exceeded), else 0         */
 } bilu_stats;
 
 /* Library-allocated host copy of the factors (for checking), final blocks. */

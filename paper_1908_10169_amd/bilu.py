@@ -66,6 +66,7 @@ class Stats(C.Structure):
         ("drops_rows", C.c_int64), ("drops_cols", C.c_int64), ("drop_margin_min", C.c_double),
         ("drop_log_count", C.c_int64), ("tuning_applied", C.c_int64),
         ("max_width_initial", C.c_int64),
+        ("ilu1t_host", C.c_int64),
     ]
 
 

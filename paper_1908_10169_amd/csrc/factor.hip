@@ -2715,6 +2715,7 @@ int64_t factor_partition(bilu_handle* h, double tau) {
   // ILU(1,tau) on the device; the host computation when a kernel capacity
   // was exceeded (or the step is off)
   int64_t nb = h->opt.use_ilu1t ? ilu1t_partition_device(h, tau, bs, &t_sets) : -1;
+  h->stats.ilu1t_host = nb < 0 && h->opt.use_ilu1t ? 1 : 0;
   if (nb < 0) {
     (void)hipGetLastError();
     if (ensure_host_matrix(h) != BILU_OK) return -1;

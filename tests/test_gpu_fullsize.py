@@ -60,6 +60,7 @@ def el80_fp64(el80):
     info, res = solve(h, el80)
     say(f"[el80] fp64: iterations={info['iterations']} residual={res:.2e}")
     out = dict(factors=h.export(), stats=h.stats(), info=info, res=res, r_kept=h.kept_residual())
+    assert out["stats"]["ilu1t_host"] == 0  # the partition came from the device kernels
     h.close()
     return out
 

@@ -357,6 +357,7 @@ def test_full_size_cd3d_64(agg, det):
     h.factor(w.tau)
     o = Oracle()
     assert o.run(w.a, OracleOptions(tau=w.tau, use_aggregation=agg), pre_perm=w.perm) == 0
+    assert h.stats()["ilu1t_host"] == 0  # the partition came from the device kernels
     assert h.stats()["merges"] == o.stats()["merges"]
     say("[full] oracle done")
     fl, fo = h.export(), o.factors()
