@@ -322,6 +322,12 @@ struct bilu_handle {
   bilu::DevArray<double> w_vec;      // scratch vectors
   bilu::DevArray<double> w_red;      // reduction partials
   int64_t w_cols = 0;
+  bilu::DevArray<double> w_gm;       // FGMRES state on the device (GmState)
+  bilu::DevArray<int> w_flags;       // its flags
+  bilu::PinnedBuf w_hflags;          // host copies of the flags, one per step parity
+  // set by the solver while it runs steps ahead: the apply, the product and
+  // the vector kernels do no work once the int it points to is nonzero
+  const int* run_skip = nullptr;
 
   // settings in effect for the last factorization: the options, or a tuned
   // entry for its precision and block-width class (use_tuning)
@@ -416,12 +422,32 @@ void launch_gather(hipStream_t s, int64_t n, const int32_t* perm, const double* 
 void launch_scatter(hipStream_t s, int64_t n, const int32_t* perm, const double* scale,
                     const double* x, double* y);
 void launch_mul(hipStream_t s, int64_t n, const double* w, const double* x, double* y);  // y = w .* x
+// skip: when set and nonzero at run time (a converged solver step), the
+// kernels do no work
 void launch_axpy(hipStream_t s, int64_t n, const double* alpha_dev, double sign, const double* x,
-                 double* y);
+                 double* y, const int* skip = nullptr);
 void launch_axpy_host(hipStream_t s, int64_t n, double alpha, const double* x, double* y);
 void launch_scale(hipStream_t s, int64_t n, double alpha, const double* x, double* y);
+void launch_scale_dev(hipStream_t s, int64_t n, const double* alpha_dev, const double* x, double* y,
+                      const int* skip = nullptr);
 void launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* partial,
-                double* out);
+                double* out, const int* skip = nullptr);
+// FGMRES state on the device (solve.hip): H is (m+1) x m row-major, hcol the
+// dot products of the current step (m + 3 values)
+struct GmState {
+  double* H;
+  double* cs;
+  double* sn;
+  double* g;
+  double* y;
+  const double* hcol;
+  double* inv_hn;
+  int* flags;
+};
+void launch_gm_init(hipStream_t s, const GmState& g, int m, double beta);
+void launch_gm_update(hipStream_t s, const GmState& g, int j, int m, double target_inner,
+                      int64_t it_before, int64_t maxit);
+void launch_gm_solve(hipStream_t s, const GmState& g, int m);
 void launch_sub(hipStream_t s, int64_t n, const double* b, const double* ax, double* r);
 
 // fgmres.cpp

@@ -321,12 +321,14 @@ struct SweepArgs {
   const int32_t* sched;
   const int2* fq;  // forward: first row and width of each scheduled block
   int begin, end;
+  const int* skip;  // when set and nonzero (a converged solver step): no work
 };
 
 // forward: t_K = x_K - sum over stored L(i, j) t_j, rows of K from the
 // row-major copy (groups of lanes per row, fixed reduction tree)
 template <class T>
 __global__ void __launch_bounds__(256) forward_level(SweepArgs<T> a, const double* x, double* t) {
+  if (a.skip && *a.skip) return;
   const int w = a.begin + blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= a.end) return;
   const int lane = threadIdx.x & 63;
@@ -354,6 +356,7 @@ __global__ void __launch_bounds__(256) forward_level(SweepArgs<T> a, const doubl
 template <class T>
 __global__ void __launch_bounds__(256) backward_level(SweepArgs<T> a, const double* t, double* z) {
   __shared__ double sv[4][kMaxWidth];
+  if (a.skip && *a.skip) return;  // uniform: before the barrier
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int w = a.begin + blockIdx.x * 4 + wv;
   const bool active = w < a.end;
@@ -427,6 +430,7 @@ struct FlowApplyArgs {
                         // [4] the ticket counter
   int ticketed;         // 1: slots by ticket; 0: by workgroup index (dispatch order)
   unsigned long long wait_ticks;
+  const int* skip;      // when set and nonzero (a converged solver step): no work
 };
 
 // Values of t (side 0) or z (side 1) at idx for the lanes with has set, once
@@ -488,6 +492,7 @@ template <class T>
 __global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs<T> a) {
   __shared__ double sv[4][kMaxWidth];
   __shared__ int s_id;
+  if (a.skip && *a.skip) return;  // uniform across the launch
   int id = blockIdx.x;
   if (a.ticketed) {
     if (threadIdx.x == 0) s_id = atomicAdd(&a.err[4], 1);
@@ -599,7 +604,9 @@ __global__ void __launch_bounds__(256) apply_flow(FlowApplyArgs<T> a) {
 // words are cleared.  A timeout of the previous apply (err[0]) is added to
 // err[5], which only apply_faults() reads and clears, so no fault is lost.
 // A fill kernel rather than a memset, so a captured graph can hold it.
-__global__ void apply_reset(int64_t n, unsigned long long* t, unsigned long long* z, int* err) {
+__global__ void apply_reset(int64_t n, unsigned long long* t, unsigned long long* z, int* err,
+                            const int* skip) {
+  if (skip && *skip) return;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     t[i] = kPending;
@@ -613,7 +620,9 @@ __global__ void apply_reset(int64_t n, unsigned long long* t, unsigned long long
 
 // y = A x, CSR, 8 lanes per row.
 __global__ void __launch_bounds__(256) spmv_csr(int64_t n, const int64_t* rp, const int32_t* ci,
-                                                const double* v, const double* x, double* y) {
+                                                const double* v, const double* x, double* y,
+                                                const int* skip) {
+  if (skip && *skip) return;
   const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
   const int sub = threadIdx.x & 7;
   double acc = 0.0;
@@ -635,7 +644,9 @@ __global__ void scatter_k(int64_t n, const int32_t* perm, const double* scale, c
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[perm[i]] = scale ? x[i] * scale[i] : x[i];
 }
-__global__ void axpy_dev_k(int64_t n, const double* alpha, double sign, const double* x, double* y) {
+__global__ void axpy_dev_k(int64_t n, const double* alpha, double sign, const double* x, double* y,
+                           const int* skip) {
+  if (skip && *skip) return;
   const double a = sign * *alpha;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = fma(a, x[i], y[i]);
@@ -648,6 +659,13 @@ __global__ void scale_k(int64_t n, double a, const double* x, double* y) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = a * x[i];
 }
+__global__ void scale_dev_k(int64_t n, const double* alpha, const double* x, double* y,
+                            const int* skip) {
+  if (skip && *skip) return;
+  const double a = *alpha;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
 __global__ void sub_k(int64_t n, const double* b, const double* ax, double* r) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     r[i] = b[i] - ax[i];
@@ -656,8 +674,9 @@ __global__ void sub_k(int64_t n, const double* b, const double* ax, double* r) {
 // Deterministic dot product: fixed grid of partial sums, then one block
 // adds the partials in index order.
 __global__ void __launch_bounds__(256) dot_partial(int64_t n, const double* x, const double* y,
-                                                   double* partial) {
+                                                   double* partial, const int* skip) {
   __shared__ double sw[4];
+  if (skip && *skip) return;
   double acc = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     acc = fma(x[i], y[i], acc);
@@ -667,8 +686,10 @@ __global__ void __launch_bounds__(256) dot_partial(int64_t n, const double* x, c
   __syncthreads();
   if (threadIdx.x == 0) partial[blockIdx.x] = (sw[0] + sw[1]) + (sw[2] + sw[3]);
 }
-__global__ void __launch_bounds__(256) dot_final(int nparts, const double* partial, double* out) {
+__global__ void __launch_bounds__(256) dot_final(int nparts, const double* partial, double* out,
+                                                 const int* skip) {
   __shared__ double sw[4];
+  if (skip && *skip) return;
   double acc = 0.0;
   for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += partial[i];
 #pragma unroll
@@ -696,6 +717,68 @@ void with_value_type(int prec, F&& f) {
     f(double{});
 }
 
+// FGMRES on the device: the Hessenberg column of step j, its Givens
+// rotation and the residual estimate, and the triangular solve of a cycle,
+// by one thread, with the operations (no contraction into fused
+// multiply-adds, IEEE square root and division) of the host version.
+// flags: [0] the cycle is done (the solver's kernels skip their work),
+// [1] steps taken (jend), [2] breakdown.
+__global__ void gm_init(GmState g, int m, double beta) {
+  if (threadIdx.x != 0) return;
+  g.g[0] = beta;
+  for (int i = 1; i <= m; ++i) g.g[i] = 0.0;
+  g.flags[0] = g.flags[1] = g.flags[2] = g.flags[3] = 0;
+}
+__global__ void gm_update(GmState g, int j, int m, double target_inner, long long it_before,
+                          long long maxit) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0 || g.flags[0]) return;
+  const double* col = g.hcol;
+  double* H = g.H;
+  const double hn = sqrt(col[j + 1]);
+  const double wn0 = sqrt(col[m + 1]);
+  for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = col[i];
+  H[(size_t)(j + 1) * m + j] = hn;
+  for (int i = 0; i < j; ++i) {
+    const double a0 = H[(size_t)i * m + j], a1 = H[(size_t)(i + 1) * m + j];
+    H[(size_t)i * m + j] = g.cs[i] * a0 + g.sn[i] * a1;
+    H[(size_t)(i + 1) * m + j] = -g.sn[i] * a0 + g.cs[i] * a1;
+  }
+  const double hjj = H[(size_t)j * m + j], hj1 = H[(size_t)(j + 1) * m + j];
+  if (hj1 == 0.0) {
+    g.cs[j] = 1.0;
+    g.sn[j] = 0.0;
+  } else if (fabs(hj1) > fabs(hjj)) {
+    const double t = hjj / hj1;
+    g.sn[j] = 1.0 / sqrt(1.0 + t * t);
+    g.cs[j] = g.sn[j] * t;
+  } else {
+    const double t = hj1 / hjj;
+    g.cs[j] = 1.0 / sqrt(1.0 + t * t);
+    g.sn[j] = g.cs[j] * t;
+  }
+  H[(size_t)j * m + j] = g.cs[j] * hjj + g.sn[j] * hj1;
+  H[(size_t)(j + 1) * m + j] = 0.0;
+  g.g[j + 1] = -g.sn[j] * g.g[j];
+  g.g[j] = g.cs[j] * g.g[j];
+  const double est = fabs(g.g[j + 1]);
+  const bool breakdown = hn <= 1e-14 * wn0;
+  *g.inv_hn = breakdown ? 0.0 : 1.0 / hn;
+  g.flags[1] = j + 1;
+  g.flags[2] = breakdown ? 1 : 0;
+  if (est <= target_inner || breakdown || it_before + j + 1 >= maxit || j + 1 >= m) g.flags[0] = 1;
+}
+__global__ void gm_solve(GmState g, int m) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0) return;
+  const int jend = g.flags[1];
+  for (int i = jend - 1; i >= 0; --i) {
+    double acc = g.g[i];
+    for (int k = i + 1; k < jend; ++k) acc -= g.H[(size_t)i * m + k] * g.y[k];
+    g.y[i] = acc / g.H[(size_t)i * m + i];
+  }
+}
+
 inline unsigned grid_for(int64_t n) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
 }
@@ -714,8 +797,8 @@ void launch_mul(hipStream_t s, int64_t n, const double* w, const double* x, doub
   gather_k<<<grid_for(n), 256, 0, s>>>(n, nullptr, w, x, y);
 }
 void launch_axpy(hipStream_t s, int64_t n, const double* alpha_dev, double sign, const double* x,
-                 double* y) {
-  axpy_dev_k<<<grid_for(n), 256, 0, s>>>(n, alpha_dev, sign, x, y);
+                 double* y, const int* skip) {
+  axpy_dev_k<<<grid_for(n), 256, 0, s>>>(n, alpha_dev, sign, x, y, skip);
 }
 void launch_axpy_host(hipStream_t s, int64_t n, double alpha, const double* x, double* y) {
   axpy_k<<<grid_for(n), 256, 0, s>>>(n, alpha, x, y);
@@ -723,13 +806,25 @@ void launch_axpy_host(hipStream_t s, int64_t n, double alpha, const double* x, d
 void launch_scale(hipStream_t s, int64_t n, double alpha, const double* x, double* y) {
   scale_k<<<grid_for(n), 256, 0, s>>>(n, alpha, x, y);
 }
+void launch_scale_dev(hipStream_t s, int64_t n, const double* alpha_dev, const double* x, double* y,
+                      const int* skip) {
+  scale_dev_k<<<grid_for(n), 256, 0, s>>>(n, alpha_dev, x, y, skip);
+}
 void launch_sub(hipStream_t s, int64_t n, const double* b, const double* ax, double* r) {
   sub_k<<<grid_for(n), 256, 0, s>>>(n, b, ax, r);
 }
+void launch_gm_init(hipStream_t s, const GmState& g, int m, double beta) {
+  gm_init<<<1, 64, 0, s>>>(g, m, beta);
+}
+void launch_gm_update(hipStream_t s, const GmState& g, int j, int m, double target_inner,
+                      int64_t it_before, int64_t maxit) {
+  gm_update<<<1, 64, 0, s>>>(g, j, m, target_inner, (long long)it_before, (long long)maxit);
+}
+void launch_gm_solve(hipStream_t s, const GmState& g, int m) { gm_solve<<<1, 64, 0, s>>>(g, m); }
 void launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, double* partial,
-                double* out) {
-  dot_partial<<<kDotBlocks, 256, 0, s>>>(n, x, y, partial);
-  dot_final<<<1, 256, 0, s>>>(kDotBlocks, partial, out);
+                double* out, const int* skip) {
+  dot_partial<<<kDotBlocks, 256, 0, s>>>(n, x, y, partial, skip);
+  dot_final<<<1, 256, 0, s>>>(kDotBlocks, partial, out, skip);
 }
 
 bilu_status spmv_permuted(bilu_handle* h, const double* x, double* y) {
@@ -741,7 +836,7 @@ bilu_status spmv_permuted(bilu_handle* h, const double* x, double* y) {
     if (e0) (void)hipEventRecord(e0, h->stream);
   }
   spmv_csr<<<(unsigned)((n * 8 + 255) / 256), 256, 0, h->stream>>>(n, h->d_rp.p, h->d_ci.p,
-                                                                   h->d_rv.p, x, y);
+                                                                   h->d_rv.p, x, y, h->run_skip);
   if (h->opt.collect_timing) {
     if (e1) (void)hipEventRecord(e1, h->stream);
     h->ev_record(2, e0, e1);
@@ -955,6 +1050,7 @@ static void apply_levels_launch(bilu_handle* h, const double* x, double* y, doub
   a.wval = apply_w<T>(h);
   a.sched = h->lev_f.p;
   a.fq = h->lev_f_fq.p;
+  a.skip = h->run_skip;
   const int nf = (int)h->lev_f_ptr.size() - 1;
   for (int L = 0; L < nf; ++L) {
     a.begin = h->lev_f_ptr[L];
@@ -1001,7 +1097,8 @@ bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t
     // every wait ends (see apply_flow); the bound only catches a fault
     a.wait_ticks = (h->wait_ticks ? h->wait_ticks : (unsigned long long)1e9) / 5;
     a.ticketed = h->eff.apply_path == 2 ? 1 : 0;
-    apply_reset<<<grid_for(n), 256, 0, st>>>(n, a.t, a.z, a.err);
+    a.skip = h->run_skip;
+    apply_reset<<<grid_for(n), 256, 0, st>>>(n, a.t, a.z, a.err, a.skip);
     apply_flow<T><<<(unsigned)((2 * h->fv.nb + 3) / 4), 256, 0, st>>>(a);
   }
   });
