@@ -49,10 +49,11 @@ def parse():
     p.add_argument("--second-workload", default="cd3d_64_b4",
                    help="a second workload timed in FP64 ('none' to skip)")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--ordering", choices=["caller", "project"], default="caller",
+    p.add_argument("--ordering", choices=["caller", "project", "multilevel"], default="caller",
                    help="caller: the workload's geometric nested dissection as pre_perm, groups "
                         "in that order; project: the library's nested dissection of the "
-                        "compressed graph (no cpu_baseline)")
+                        "compressed graph by level structures; multilevel: its multilevel "
+                        "nested dissection (both without cpu_baseline)")
     p.add_argument("--aggregation", type=int, default=-1,
                    help="1/0 forces progressive aggregation on/off (default: library default)")
     p.add_argument("--apply-path", type=int, default=0, choices=[0, 1, 2],
@@ -91,7 +92,9 @@ def time_form(w, prec, args, project, agg):
     import torch
 
     from paper_1908_10169_amd import bilu
-    opts = dict(ordering=bilu.ORDER_ND if project else bilu.ORDER_NATURAL, collect_timing=1,
+    order = {"caller": bilu.ORDER_NATURAL, "project": bilu.ORDER_ND,
+             "multilevel": bilu.ORDER_ND_MULTILEVEL}[args.ordering]
+    opts = dict(ordering=order, collect_timing=1,
                 update_precision=prec, apply_path=args.apply_path,
                 update_mfma=args.update_mfma, use_aggregation=agg,
                 deterministic=args.deterministic)
@@ -207,7 +210,7 @@ def main():
     if args.tuning:
         bilu.load_tuning(args.tuning)
     forms = [f for f in args.forms.split(",") if f]
-    project = args.ordering == "project"
+    project = args.ordering != "caller"
     agg = AGGREGATION_DEFAULT if args.aggregation < 0 else bool(args.aggregation)
     w = mg.workload(args.workload)
     recs = {f: time_form(w, FORM_PREC[f], args, project, agg) for f in forms}
@@ -233,8 +236,11 @@ def main():
         "config": {
             "workload": w.name, "n": w.a.n, "nnz": w.a.nnz, "tau": w.tau, "restart": w.restart,
             "rtol": 1e-8,
-            "ordering": "nested dissection of the compressed graph (library)" if project
-            else "geometric nested dissection (caller permutation)",
+            "ordering": {"caller": "geometric nested dissection (caller permutation)",
+                         "project": "nested dissection of the compressed graph (library, level "
+                                    "structures)",
+                         "multilevel": "multilevel nested dissection of the compressed graph "
+                                       "(library)"}[args.ordering],
             "update_precision": forms[0], "aggregation": agg, "update_mfma": args.update_mfma,
             "deterministic": args.deterministic,
             "tuning": os.path.relpath(args.tuning, ROOT) if args.tuning else None,

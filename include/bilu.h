@@ -48,7 +48,15 @@ typedef enum {
   BILU_ERR_INTERNAL = -6
 } bilu_status;
 
-typedef enum { BILU_ORDER_ND = 0, BILU_ORDER_NATURAL = 1 } bilu_ordering;
+/* Sec. 3.3 ordering of the compressed graph: nested dissection by recursive
+ * level-structure bisection, none (the caller's order), or multilevel nested
+ * dissection (heavy-edge coarsening, greedy growing, Fiduccia-Mattheyses
+ * refinement, minimum vertex cover separators; slower, smaller separators) */
+typedef enum {
+  BILU_ORDER_ND = 0,
+  BILU_ORDER_NATURAL = 1,
+  BILU_ORDER_ND_MULTILEVEL = 2
+} bilu_ordering;
 typedef enum { BILU_PREC_F64 = 0, BILU_PREC_F32 = 1, BILU_PREC_BF16 = 2 } bilu_precision;
 typedef enum { BILU_NORM_INF = 0, BILU_NORM_TWO = 1 } bilu_drop_norm;
 

@@ -25,7 +25,7 @@ BILU_ERR_SINGULAR = -4
 BILU_ERR_DEVICE = -5
 BILU_ERR_INTERNAL = -6
 
-ORDER_ND, ORDER_NATURAL = 0, 1
+ORDER_ND, ORDER_NATURAL, ORDER_ND_MULTILEVEL = 0, 1, 2
 PREC_F64, PREC_F32, PREC_BF16 = 0, 1, 2
 
 

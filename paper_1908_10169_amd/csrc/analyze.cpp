@@ -404,7 +404,8 @@ bilu_status order_and_expand(bilu_handle* h, const int64_t* rp1, const int32_t* 
   // group order: natural, or nested dissection of the compressed graph
   std::vector<int32_t> gorder(ng);
   std::iota(gorder.begin(), gorder.end(), 0);
-  if (h->opt.ordering == BILU_ORDER_ND && ng > 8) {
+  if ((h->opt.ordering == BILU_ORDER_ND || h->opt.ordering == BILU_ORDER_ND_MULTILEVEL) && ng > 8) {
+    if (!ci1) return fail(h, BILU_ERR_INTERNAL, "ordering: the column indices are missing");
     std::vector<int32_t> gof(n);
     for (int64_t g = 0; g < ng; ++g)
       for (int64_t k = gs[g]; k < gs[g + 1]; ++k) gof[q[k]] = (int32_t)g;
@@ -466,7 +467,13 @@ bilu_status order_and_expand(bilu_handle* h, const int64_t* rp1, const int32_t* 
     parallel_for(ng, [&](int64_t lo, int64_t hi) {
       for (int64_t g = lo; g < hi; ++g) merge(g, gr.adj.data() + gr.xadj[g]);
     });
-    nd_order(gr, gorder);
+    if (h->opt.ordering == BILU_ORDER_ND_MULTILEVEL) {
+      std::vector<int32_t> vw(ng);
+      for (int64_t g = 0; g < ng; ++g) vw[g] = (int32_t)(gs[g + 1] - gs[g]);
+      mlnd_order(gr.xadj, gr.adj, vw, gorder);
+    } else {
+      nd_order(gr, gorder);
+    }
     if ((int64_t)gorder.size() != ng) return fail(h, BILU_ERR_INTERNAL, "ordering lost vertices");
   }
   // expand: groups contiguous, members in their order

@@ -390,7 +390,8 @@ bilu_status analyze_device(bilu_handle* h, int64_t n, const int64_t* d_a_rp,
   const bool ident = h->opt.pre_perm == nullptr;
 
   // 2. A1 = A(pre, pre), when the cosine step or the ordering reads it
-  const bool need_nd = h->opt.ordering == BILU_ORDER_ND;
+  const bool need_nd =
+      h->opt.ordering == BILU_ORDER_ND || h->opt.ordering == BILU_ORDER_ND_MULTILEVEL;
   std::vector<int64_t> rp1(n + 1, 0), cp1(n + 1, 0);
   DevArray<int32_t> d_pre, d_inv, d_ci1, d_ri1;
   DevArray<int64_t> d_rp1, d_cp1;

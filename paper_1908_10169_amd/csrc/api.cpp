@@ -214,7 +214,7 @@ bilu_status bilu_create(bilu_handle** out, const bilu_options* opt, void* stream
   else
     bilu_default_options(&h->opt);
   if (h->opt.max_block < 1 || h->opt.max_block > kMaxWidth || !(h->opt.cos_eps >= 0.0) ||
-      h->opt.cos_eps > 1.0 || h->opt.ordering < 0 || h->opt.ordering > 1 ||
+      h->opt.cos_eps > 1.0 || h->opt.ordering < 0 || h->opt.ordering > 2 ||
       h->opt.update_precision < 0 || h->opt.update_precision > 2 || h->opt.drop_norm < 0 ||
       h->opt.drop_norm > 1 || h->opt.factor_path < 0 || h->opt.factor_path > 2 ||
       h->opt.apply_path < 0 || h->opt.apply_path > 2 || h->opt.use_mwm < 0 || h->opt.use_mwm > 1 ||

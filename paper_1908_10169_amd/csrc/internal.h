@@ -362,6 +362,10 @@ int64_t ilu1t_partition(const bilu_handle* h, double tau, std::vector<int32_t>& 
 void cosine_limits(int64_t n, int64_t nnz, const int64_t* rc, const int64_t* cc, double* lim_r,
                    double* lim_c);
 bool pre_permutation(const bilu_handle* h, int64_t n, std::vector<int64_t>& pre);
+// mlnd.cpp: multilevel nested dissection of a graph (CSR without self loops,
+// symmetric) with vertex weights vw; order[i] is the vertex at position i
+void mlnd_order(const std::vector<int64_t>& xadj, const std::vector<int32_t>& adj,
+                const std::vector<int32_t>& vw, std::vector<int32_t>& order);
 bilu_status order_and_expand(bilu_handle* h, const int64_t* rp1, const int32_t* ci1,
                              const std::vector<int64_t>& pre, const std::vector<int64_t>& q,
                              const std::vector<int64_t>& gs);

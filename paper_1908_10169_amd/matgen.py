@@ -224,6 +224,31 @@ def random_sparse(n: int, density: float, seed: int, diag_shift: float = 0.0,
     return dense_to_csr(np.where(mask, vals, 0.0), mask)
 
 
+def random_geometric(nodes: int, k: int = 8, dim: int = 2, b: int = 2, seed: int = 0,
+                     dom: float = 1.2) -> Csr:
+    """Irregular mesh-like matrix: ``nodes`` points uniform in the unit
+    square (cube), each coupled to its k nearest neighbours (symmetrized
+    pattern); every coupled node pair gets a dense b x b block ~U(-1,1), and
+    each row's diagonal is ``dom`` times the sum of its off-diagonal
+    magnitudes.  Node-major numbering (row = b * node + component)."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    pts = rng.random((nodes, dim))
+    _, nb = cKDTree(pts).query(pts, k + 1)
+    adj = np.zeros((nodes, nodes), dtype=bool)
+    rows = np.repeat(np.arange(nodes), k)
+    cols = nb[:, 1:].ravel()
+    adj[rows, cols] = True
+    adj |= adj.T
+    np.fill_diagonal(adj, True)
+    n = nodes * b
+    mask = np.kron(adj, np.ones((b, b), dtype=bool))
+    vals = np.where(mask, rng.uniform(-1.0, 1.0, size=(n, n)), 0.0)
+    np.fill_diagonal(vals, 0.0)
+    np.fill_diagonal(vals, dom * np.abs(vals).sum(axis=1) + 1.0)
+    return dense_to_csr(vals, mask)
+
+
 def dense_to_csr(a: np.ndarray, mask: np.ndarray | None = None) -> Csr:
     """CSR of a dense array; ``mask`` selects structural entries (default a != 0)."""
     a = np.asarray(a, dtype=np.float64)

@@ -193,3 +193,41 @@ def test_tuning_table_reader(tmp_path):
     with pytest.raises(bilu.BiluError):
         bilu.load_tuning(str(tmp_path / "missing.json"))
     assert bilu.load_tuning(None) == 0
+
+
+def _symbolic_fill(a, p):
+    A = a.to_dense() != 0
+    F = A[np.ix_(p, p)].copy()
+    for k in range(len(p)):
+        rows = np.flatnonzero(F[k + 1:, k]) + k + 1
+        cols = np.flatnonzero(F[k, k + 1:]) + k + 1
+        F[np.ix_(rows, cols)] = True
+    return int(F.sum())
+
+
+def test_multilevel_nd_is_a_block_permutation_and_deterministic():
+    a = mg.random_geometric(700, k=7, dim=2, b=2, seed=4)
+    p1, gs, _ = bilu.preprocess(a, 1e-2, ordering=bilu.ORDER_ND_MULTILEVEL)
+    p2, _, _ = bilu.preprocess(a, 1e-2, ordering=bilu.ORDER_ND_MULTILEVEL)
+    assert np.array_equal(p1, p2)
+    assert np.array_equal(np.sort(p1), np.arange(a.n))
+    # the ordering only moves the cosine groups: the same groups as in the
+    # natural order, each contiguous
+    pn, gsn, _ = bilu.preprocess(a, 1e-2, ordering=bilu.ORDER_NATURAL)
+    groups = lambda p, s: {frozenset(p[s[g]:s[g + 1]].tolist()) for g in range(len(s) - 1)}
+    assert groups(p1, gs) == groups(pn, gsn)
+
+
+def test_multilevel_nd_beats_level_structure_on_an_irregular_mesh():
+    """On a k-nearest-neighbour mesh (no grid structure for breadth-first
+    levels to follow) the multilevel separators give clearly less exact
+    block-LU fill than the level-structure ones, and both far less than the
+    natural order."""
+    a = mg.random_geometric(900, k=7, dim=2, b=1, seed=2)
+    fills = {}
+    for name, o in (("natural", bilu.ORDER_NATURAL), ("level", bilu.ORDER_ND),
+                    ("multilevel", bilu.ORDER_ND_MULTILEVEL)):
+        perm, _, _ = bilu.preprocess(a, 1e-2, ordering=o, use_cosine=False)
+        fills[name] = _symbolic_fill(a, perm)
+    assert fills["multilevel"] < 0.85 * fills["level"], fills
+    assert fills["level"] < 0.3 * fills["natural"], fills

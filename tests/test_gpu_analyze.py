@@ -111,6 +111,10 @@ CASES = [
     ("arrow_overflow", lambda: mg.Workload("arrow", arrow(2000, 5), 1, (2000,), 1e-2, 30, None),
      dict(ordering=1), False),
     ("el3d_10_no_cosine_nd", lambda: mg.workload("el3d_10_b3"), dict(use_cosine=0), True),
+    ("irregular_mesh_multilevel_nd",
+     lambda: mg.Workload("rgg", mg.random_geometric(1200, k=7, dim=3, b=3, seed=6), 3, (1200,),
+                         1e-2, 30, None),
+     dict(ordering=2), False),
 ]
 
 

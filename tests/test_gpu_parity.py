@@ -418,3 +418,24 @@ def test_drop_log_equals_oracle(name):
         assert abs(got[key] - nrm) <= 1e-10 * nrm
     assert h.stats()["drop_log_count"] == len(got)
     h.close()
+
+
+def test_multilevel_nd_ordering_parity():
+    """The multilevel nested dissection option on an irregular mesh: the
+    library's own analysis orders as the host preprocessing does, and the
+    sweep on that order matches the oracle (which takes it as the caller's
+    permutation)."""
+    _torch()
+    from paper_1908_10169_amd import bilu
+    a = mg.random_geometric(1500, k=7, dim=3, b=3, seed=8)
+    tau = 1e-2
+    say(f"[multilevel nd] irregular mesh n={a.n} nnz={a.nnz}")
+    perm, _, _ = bilu.preprocess(a, tau, ordering=bilu.ORDER_ND_MULTILEVEL)
+    h = bilu.Bilu(ordering=bilu.ORDER_ND_MULTILEVEL, use_aggregation=True)
+    h.analyze(a)
+    h.factor(tau)
+    assert np.array_equal(h.export().perm, perm)
+    h.close()
+    o, h2 = run_pair(a, tau, pre_perm=perm, agg=True)
+    compare_factors(o, h2)
+    h2.close()
