@@ -267,6 +267,23 @@ bilu_status bilu_factor(bilu_handle* h, double tau);
  * Synchronous. */
 bilu_status bilu_refactor(bilu_handle* h, double tau, const double* val);
 
+/* Numeric refactorization with frozen patterns, for the same sequences:
+ * val (as for bilu_refactor) replaces A's values and the last factor's
+ * values are recomputed on its own blocks (after aggregation), row lists
+ * R_K, column lists C_K and storage: the Crout panels of Sec. 2.2 restricted
+ * to the stored positions (updates L_J W_J only where both ends are
+ * stored), the pivot blocks inverted with the perturbation of Sec. 3.6,
+ * L_K = C(R_K, K) D_K and W_K = C(K, C_K).  Nothing is dropped or merged,
+ * so the apply plan is kept; (L S U)_Omega = A_Omega holds on the stored
+ * positions Omega for the new values.  Blocks of one dependency level run
+ * in one launch.  bilu_kept_residual afterwards: BILU_ERR_STATE when the
+ * last factor had merged blocks (its sweep's positions are no longer the
+ * factor's).  Errors: BILU_ERR_STATE before bilu_factor, BILU_ERR_INVALID
+ * (non-finite value: nothing changes; use_mwm; nnz >= 2^31),
+ * BILU_ERR_SINGULAR, BILU_ERR_DEVICE; BILU_WARN_PERTURBED when pivot blocks
+ * were perturbed.  Synchronous. */
+bilu_status bilu_refactor_frozen(bilu_handle* h, const double* val);
+
 /* Factor count independent analyzed handles in one launch of the factor
  * sweep (many matrices at once).  hs[i] is factored with drop tolerance
  * taus[i]; every handle ends as bilu_factor(hs[i], taus[i]) would leave it,

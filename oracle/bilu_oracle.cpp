@@ -1276,7 +1276,10 @@ void orc_lsu_matvec(const orc_handle* h, const double* x, double* y) {
 // also store zero-filled positions whose values were dropped).  L S U is
 // taken from the final (merged) factors; entry (i,j) of L W is the sparse
 // dot product of row i of L with column j of W.
-double orc_kept_residual(const orc_handle* h) {
+namespace {
+// ||(L S U - A)_Omega||_F / ||A||_F; Omega: the positions of the blocks the
+// sweep computed (before merges), or of the final blocks (live).
+double omega_residual(const orc_handle* h, bool live) {
   const i64 n = h->n;
   std::vector<std::vector<std::pair<i64, double>>> Lrow(n), Wcol(n);
   for (i64 i = 0; i < n; ++i) Lrow[i].push_back({i, 1.0});
@@ -1314,8 +1317,11 @@ double orc_kept_residual(const orc_handle* h) {
   double num = 0.0, den = 0.0;
   for (double x : h->A.v) den += x * x;
   const Mat& a = h->P;
-  for (const Block& B : h->blocks) {
-    if (!B.computed) continue;
+  std::vector<char> is_live(h->blocks.size(), 0);
+  for (int id : h->live) is_live[id] = 1;
+  for (size_t id = 0; id < h->blocks.size(); ++id) {
+    const Block& B = h->blocks[id];
+    if (live ? !is_live[id] : !B.computed) continue;
     for (int r = 0; r < B.q; ++r)
       for (int c = 0; c < B.q; ++c) {
         double d = lw(B.first + r, B.first + c) - entry(a, B.first + r, B.first + c);
@@ -1333,6 +1339,98 @@ double orc_kept_residual(const orc_handle* h) {
       }
   }
   return std::sqrt(num / den);
+}
+}  // namespace
+
+double orc_kept_residual(const orc_handle* h) { return omega_residual(h, false); }
+double orc_final_residual(const orc_handle* h) { return omega_residual(h, true); }
+
+// Refactorization with frozen patterns (a variant for sequences of matrices
+// with one pattern, not a step of the paper): the final blocks and their
+// lists R_K, C_K stay, the values follow the new A.  For K in order, the
+// Crout panels of Sec. 2.2 on the stored positions only,
+//   C(i, j) = A(i, j) - sum over earlier final blocks J of L_J(i,:) W_J(:,j),
+// the sum over the J whose lists hold both i (R_J) and j (C_J), in order;
+// then S_K = C(K, K) perturbed and inverted as in the sweep (Sec. 3.6),
+// L_K = C(R_K, K) D_K and W_K = C(K, C_K).  Nothing is dropped or merged.
+int orc_refactor_frozen(orc_handle* h, const double* val) {
+  if (h->live.empty()) return -1;
+  for (size_t e = 0; e < h->A.v.size(); ++e) {
+    if (!std::isfinite(val[e])) return -1;
+  }
+  std::copy(val, val + h->A.v.size(), h->A.v.begin());
+  h->P = permute_sym(h->A, h->perm);
+  const Mat& a = h->P;
+  const orc_options& o = h->opt;
+  h->alpha = 0.0;
+  for (double x : a.v) h->alpha = std::max(h->alpha, std::fabs(x));
+  h->n_perturbed = 0;
+  h->singular = 0;
+  std::vector<int> order(h->live.begin(), h->live.end());
+  for (size_t k = 0; k < order.size(); ++k) {
+    Block& K = h->blocks[order[k]];
+    const int q = K.q;
+    const i64 f = K.first, l = K.last();
+    const size_t nR = K.R.size(), nC = K.C.size();
+    // panel rows: K's own, then R_K; row panel columns: C_K
+    auto rowpos = [&](i64 i) -> i64 {
+      if (i >= f && i <= l) return i - f;
+      auto it = std::lower_bound(K.R.begin(), K.R.end(), i);
+      return it != K.R.end() && *it == i ? q + (i64)(it - K.R.begin()) : -1;
+    };
+    auto colpos = [&](i64 j) -> i64 {
+      auto it = std::lower_bound(K.C.begin(), K.C.end(), j);
+      return it != K.C.end() && *it == j ? (i64)(it - K.C.begin()) : -1;
+    };
+    std::vector<double> Cp((q + nR) * (size_t)q), Rp((size_t)q * nC);
+    for (int r = 0; r < q; ++r)
+      for (int c = 0; c < q; ++c) Cp[(size_t)r * q + c] = entry(a, f + r, f + c);
+    for (size_t t = 0; t < nR; ++t)
+      for (int c = 0; c < q; ++c) Cp[(q + t) * q + c] = entry(a, K.R[t], f + c);
+    for (int r = 0; r < q; ++r)
+      for (size_t t = 0; t < nC; ++t) Rp[(size_t)r * nC + t] = entry(a, f + r, K.C[t]);
+    for (size_t jb = 0; jb < k; ++jb) {
+      const Block& J = h->blocks[order[jb]];
+      const int p = J.q;
+      auto term = [&](size_t tr, size_t tc) {
+        double acc = 0.0;
+        for (int u = 0; u < p; ++u) acc += J.L[tr * p + u] * J.W[tc * p + u];
+        return acc;
+      };
+      for (size_t tc = 0; tc < J.C.size(); ++tc) {
+        const i64 j = J.C[tc];
+        if (j < f) continue;
+        const bool in_k = j <= l;
+        const i64 cj = in_k ? -1 : colpos(j);
+        if (!in_k && cj < 0) continue;
+        for (size_t tr = 0; tr < J.R.size(); ++tr) {
+          const i64 i = J.R[tr];
+          if (in_k) {  // column panel: rows of K and R_K
+            const i64 ri = rowpos(i);
+            if (ri >= 0) Cp[(size_t)ri * q + (j - f)] -= term(tr, tc);
+          } else if (i >= f && i <= l) {  // row panel: rows of K
+            Rp[(size_t)(i - f) * nC + cj] -= term(tr, tc);
+          }
+        }
+      }
+    }
+    std::vector<double> S(Cp.begin(), Cp.begin() + (size_t)q * q);
+    const int rounds = perturb_invert(q, S, h->alpha, o, K.S, K.D);
+    if (rounds < 0) {
+      h->singular = 1;
+      return 1;
+    }
+    if (rounds > 0) ++h->n_perturbed;
+    for (size_t t = 0; t < nR; ++t)
+      for (int c = 0; c < q; ++c) {
+        double acc = 0.0;
+        for (int u = 0; u < q; ++u) acc += Cp[(q + t) * q + u] * K.D[(size_t)u * q + c];
+        K.L[t * q + c] = acc;
+      }
+    for (size_t t = 0; t < nC; ++t)
+      for (int r = 0; r < q; ++r) K.W[t * q + r] = Rp[(size_t)r * nC + t];
+  }
+  return 0;
 }
 
 // Test hook of the pins, not part of the method: adds delta to the stored

@@ -138,8 +138,16 @@ void orc_fgmres_plain(int64_t n, const int64_t* rowptr, const int32_t* colind,
                       int restart, double rtol, int maxit,
                       orc_solve_info* info, double* resid_history);
 
-/* ||(L S U - A)_Omega||_F / ||A||_F over the stored positions Omega. */
+/* ||(L S U - A)_Omega||_F / ||A||_F over the stored positions Omega of the
+ * blocks the sweep computed (before merges). */
 double orc_kept_residual(const orc_handle* h);
+/* The same over the stored positions of the final blocks. */
+double orc_final_residual(const orc_handle* h);
+/* Refactorization with frozen patterns: val (A's values in its entry
+ * order, same pattern) replaces A's values; the final blocks, R_K and C_K
+ * stay and L, W, D (and S) are recomputed on them, nothing dropped or
+ * merged.  0 on success, 1 singular, -1 invalid. */
+int orc_refactor_frozen(orc_handle* h, const double* val);
 /* y = (L S U) x in the permuted numbering. */
 void orc_lsu_matvec(const orc_handle* h, const double* x, double* y);
 

@@ -81,6 +81,10 @@ def load():
                                      C.c_double, C.c_int, C.POINTER(_Info), _F64P]
     lib.orc_kept_residual.argtypes = [vp]
     lib.orc_kept_residual.restype = C.c_double
+    lib.orc_final_residual.argtypes = [vp]
+    lib.orc_final_residual.restype = C.c_double
+    lib.orc_refactor_frozen.argtypes = [vp, _F64P]
+    lib.orc_refactor_frozen.restype = C.c_int
     lib.orc_lsu_matvec.argtypes = [vp, _F64P, _F64P]
     lib.orc_get_times.argtypes = [vp, _F64P]
     lib.orc_plant.argtypes = [vp, C.c_int, C.c_int64, C.c_int64, C.c_double]
@@ -257,6 +261,16 @@ class Oracle:
 
     def kept_residual(self) -> float:
         return self._lib.orc_kept_residual(self._h)
+
+    def final_residual(self) -> float:
+        """||(L S U - A)_Omega|| / ||A|| over the final blocks' positions."""
+        return self._lib.orc_final_residual(self._h)
+
+    def refactor_frozen(self, val) -> int:
+        """New values of A (entry order of the matrix last run, same pattern);
+        the final blocks and patterns stay, L, W, D are recomputed."""
+        v = np.ascontiguousarray(val, dtype=np.float64)
+        return self._lib.orc_refactor_frozen(self._h, v)
 
     def plant(self, which: str, block: int, pos: int, delta: float) -> None:
         """Test hook: add delta to one stored value of L_K ("L") or W_K ("W")."""

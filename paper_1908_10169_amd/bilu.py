@@ -91,7 +91,7 @@ EXPORTED = [
     "bilu_free_factors", "bilu_destroy", "bilu_status_string", "bilu_last_error",
     "bilu_preprocess", "bilu_sync", "bilu_export_trace", "bilu_factor_batched", "bilu_mwm",
     "bilu_analyze_device", "bilu_refactor", "bilu_kept_residual", "bilu_apply_noalloc",
-    "bilu_load_tuning", "bilu_tuning_entries",
+    "bilu_load_tuning", "bilu_tuning_entries", "bilu_refactor_frozen",
 ]
 
 _lib = None
@@ -132,6 +132,7 @@ def load(path: str = LIB_PATH):
     lib.bilu_mwm.argtypes = [C.c_int64, vp, vp, vp, vp, vp, vp]
     lib.bilu_analyze_device.argtypes = [vp, C.c_int64, vp, vp, vp]
     lib.bilu_refactor.argtypes = [vp, C.c_double, vp]
+    lib.bilu_refactor_frozen.argtypes = [vp, vp]
     lib.bilu_kept_residual.argtypes = [vp, C.POINTER(C.c_double)]
     lib.bilu_load_tuning.argtypes = [C.c_char_p]
     lib.bilu_load_tuning.restype = C.c_int
@@ -139,7 +140,8 @@ def load(path: str = LIB_PATH):
     lib.bilu_tuning_entries.restype = C.c_int64
     lib.bilu_preprocess.argtypes = [C.POINTER(Options), C.c_int64, vp, vp, vp, C.c_double,
                                     vp, vp, C.POINTER(C.c_int64), vp, C.POINTER(C.c_int64)]
-    for f in ("bilu_create", "bilu_analyze", "bilu_analyze_device", "bilu_refactor", "bilu_factor",
+    for f in ("bilu_create", "bilu_analyze", "bilu_analyze_device", "bilu_refactor",
+              "bilu_refactor_frozen", "bilu_factor",
               "bilu_factor_batched", "bilu_apply", "bilu_apply_noalloc",
               "bilu_spmv", "bilu_kept_residual",
               "bilu_fgmres_solve", "bilu_get_stats", "bilu_export_factors", "bilu_preprocess",
@@ -367,6 +369,14 @@ class Bilu:
         _check_tensor(val, "val", torch.float64, self.stats()["nnz_a"])
         return self._check(self._lib.bilu_refactor(self._h, tau, val.data_ptr()), "bilu_refactor",
                            ok=(BILU_OK, BILU_WARN_PERTURBED))
+
+    def refactor_frozen(self, val):
+        """bilu_refactor_frozen: val as for refactor; the last factor's
+        blocks and patterns stay, its values are recomputed."""
+        import torch
+        _check_tensor(val, "val", torch.float64, self.stats()["nnz_a"])
+        return self._check(self._lib.bilu_refactor_frozen(self._h, val.data_ptr()),
+                           "bilu_refactor_frozen", ok=(BILU_OK, BILU_WARN_PERTURBED))
 
     def apply(self, x, y):
         """y = M^{-1} x; x, y: torch float64 CUDA tensors of length n."""

@@ -79,6 +79,7 @@ namespace bilu {
 // aggregation (Sec. 3.5), the apply plan and the statistics.
 bilu_status finish_factor(bilu_handle* h, std::chrono::steady_clock::time_point t0) {
   bilu_status s = BILU_OK;
+  h->kept_stale = false;
   h->stats.r_kept = -1.0;  // computed on request (bilu_kept_residual)
   h->nb = h->stats.nblocks_initial;
   h->bstart = h->bstart0;
@@ -451,6 +452,32 @@ bilu_status bilu_refactor(bilu_handle* h, double tau, const double* val) {
   GUARD_END
 }
 
+bilu_status bilu_refactor_frozen(bilu_handle* h, const double* val) {
+  if (!h) return BILU_ERR_INVALID;
+  if (h->state < 2) return fail(h, BILU_ERR_STATE, "bilu_refactor_frozen before bilu_factor");
+  if (!val) return fail(h, BILU_ERR_INVALID, "bilu_refactor_frozen: null values");
+  if (h->mwm) return fail(h, BILU_ERR_INVALID, "bilu_refactor_frozen: not with use_mwm");
+  if (h->nnz > 0 && !h->d_vmap_r.p)
+    return fail(h, BILU_ERR_INVALID, "bilu_refactor_frozen: nnz >= 2^31");
+  GUARD_BEGIN
+  auto t0 = std::chrono::steady_clock::now();
+  bilu_status s = refactor_values(h, val);
+  if (s != BILU_OK) return s;  // nothing changed: the previous factor stands
+  h->state = 1;                // until the new values are complete
+  h->ev_resolve();
+  h->stats.perturbed_blocks = 0;
+  s = frozen_refactor(h);
+  if (s != BILU_OK) return s;
+  s = refresh_apply_values(h);
+  if (s != BILU_OK) return s;
+  h->kept_stale = h->fv.dval != h->d_dval.p;
+  h->stats.r_kept = -1.0;
+  h->stats.t_factor = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  h->state = 2;
+  return h->stats.perturbed_blocks > 0 ? BILU_WARN_PERTURBED : BILU_OK;
+  GUARD_END
+}
+
 bilu_status bilu_factor_batched(bilu_handle** hs, int count, const double* taus) {
   if (!hs || !taus || count < 1) return BILU_ERR_INVALID;
   for (int i = 0; i < count; ++i) {
@@ -569,6 +596,9 @@ bilu_status bilu_preprocess(const bilu_options* opt, int64_t n, const int64_t* r
 bilu_status bilu_kept_residual(bilu_handle* h, double* r_kept) {
   if (!h || !r_kept) return fail(h, BILU_ERR_INVALID, "bilu_kept_residual: null argument");
   if (h->state < 2) return fail(h, BILU_ERR_STATE, "bilu_kept_residual before bilu_factor");
+  if (h->kept_stale)
+    return fail(h, BILU_ERR_STATE,
+                "bilu_kept_residual: the frozen refactorization of a factor with merged blocks");
   GUARD_BEGIN
   return kept_residual(h, r_kept);
   GUARD_END

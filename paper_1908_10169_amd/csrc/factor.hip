@@ -2705,6 +2705,251 @@ __global__ void seed_flags(int nb, const int* pending, int* enq, unsigned char* 
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Refactorization with frozen patterns: new values of A on the last
+// factor's final blocks, row and column lists and storage.  Block K's panels
+// are the Crout ones of Sec. 2.2 restricted to the stored positions:
+//   C(i, j) = A(i, j) - sum over J < K of L_J(i,:) W_J(:,j),
+// for i in K or R_K and j in K (column panel), i in K and j in C_K (row
+// panel), the terms taken per predecessor J in ascending order and only
+// where both ends are stored; then D_K = S_K^-1 (the sweep's pivot routine,
+// perturbation included), L_K = C(R_K, K) D_K and W_K = C(K, C_K).  Nothing
+// is dropped and nothing merges.  One workgroup per block; blocks of one
+// dependency level run in one launch.  The FP64 panels sit in the scratch
+// arrays PL (at the L offsets), PW (at the W offsets) and PD (at the pivot
+// offsets).
+// ---------------------------------------------------------------------------
+struct FrozenArgs {
+  FactorView f;            // the factor rewritten in place (val, dval)
+  double* val64;           // = f.val when it is FP64 (else null)
+  void* val;               // the stored values (f.val), written
+  double* dval;            // D_K, written
+  double* sval;            // S_K at the same offsets, or null
+  double *PL, *PW, *PD;    // FP64 panels
+  double* piv;             // 2 q^2 pivot scratch per block at 2 doff, when not in LDS
+  const int64_t *cp, *rp;  // P A P^T: CSC and CSR
+  const int32_t *ri, *ci;
+  const double *cv, *rv;
+  // per block: the blocks J whose C_J (cptr) or R_J (rptr) has a run inside
+  // K, ascending, with the run's first position and length
+  const int32_t *cptr, *cj, *cs0, *ccnt;
+  const int32_t *rptr, *rj, *rs0, *rcnt;
+  const int32_t* sched;    // blocks of this level
+  int begin, end;
+  FactorArgs fa;           // perturbation settings and status words of the sweep
+};
+
+// Position of key in the sorted list x[0..m) or -1.
+__device__ __forceinline__ int find_sorted(const int* x, int m, int key) {
+  int lo = 0, hi = m;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (x[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo < m && x[lo] == key ? lo : -1;
+}
+
+// One update term of the stored values in precision prec (FP64: fused
+// multiply-adds in index order; FP32 / BF16: the same in FP32).
+__device__ __forceinline__ double frozen_term(const void* heap, int prec, int64_t lo, int64_t wo,
+                                              int p) {
+  if (prec == kValF64) {
+    const double* v = static_cast<const double*>(heap);
+    double acc = 0.0;
+    for (int k = 0; k < p; ++k) acc = fma(v[lo + k], v[wo + k], acc);
+    return acc;
+  }
+  float acc = 0.0f;
+  for (int k = 0; k < p; ++k)
+    acc = fmaf((float)value_load(heap, prec, lo + k), (float)value_load(heap, prec, wo + k), acc);
+  return (double)acc;
+}
+
+__global__ void __launch_bounds__(kThreads) frozen_block_kernel(FrozenArgs a) {
+  __shared__ Lds s;
+  extern __shared__ double s_dyn[];
+  const int w = a.begin + blockIdx.x;
+  if (w >= a.end) return;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const FactorView& f = a.f;
+  const int K = a.sched[w];
+  const int f0 = f.bstart[K], q = f.bstart[K + 1] - f0, l0 = f0 + q - 1;
+  const int nr = f.nr[K], nc = f.nc[K];
+  const int32_t* RK = f.idx + f.roff[K];
+  const int32_t* CK = f.idx + f.coff[K];
+  double* PL = a.PL + f.loff[K];   // nr x q, row-major
+  double* PW = a.PW + f.woff[K];   // q x nc, column-major
+  double* PD = a.PD + f.doff[K];   // q x q, row-major
+  // K's lists in LDS when they fit (searched for every term)
+  const bool lr = nr <= kCandCap, lc = nc <= kCandCap;
+  for (int t = tid; t < nr && lr; t += nt) s.cand[t] = RK[t];
+  for (int t = tid; t < nc && lc; t += nt) s.candc[t] = CK[t];
+  const int* Rl = lr ? s.cand : RK;
+  const int* Cl = lc ? s.candc : CK;
+  for (int e = tid; e < nr * q; e += nt) PL[e] = 0.0;
+  for (int e = tid; e < nc * q; e += nt) PW[e] = 0.0;
+  for (int e = tid; e < q * q; e += nt) PD[e] = 0.0;
+  __syncthreads();
+  // A's entries on the stored positions (each position once)
+  for (int c = 0; c < q; ++c) {
+    const int64_t b = a.cp[f0 + c], e = a.cp[f0 + c + 1];
+    for (int64_t m = b + tid; m < e; m += nt) {
+      const int r = a.ri[m];
+      if (r < f0) continue;
+      if (r <= l0) {
+        PD[(r - f0) * q + c] = a.cv[m];
+      } else {
+        const int i = find_sorted(Rl, nr, r);
+        if (i >= 0) PL[(int64_t)i * q + c] = a.cv[m];
+      }
+    }
+  }
+  for (int r = 0; r < q; ++r) {
+    const int64_t b = a.rp[f0 + r], e = a.rp[f0 + r + 1];
+    for (int64_t m = b + tid; m < e; m += nt) {
+      const int j = a.ci[m];
+      if (j <= l0) continue;
+      const int k = find_sorted(Cl, nc, j);
+      if (k >= 0) PW[(int64_t)k * q + r] = a.rv[m];
+    }
+  }
+  __syncthreads();
+  // column panel: predecessors whose columns run inside K, ascending; a
+  // predecessor's terms hit distinct entries
+  for (int x = a.cptr[K]; x < a.cptr[K + 1]; ++x) {
+    const int J = a.cj[x], c0 = a.cs0[x], cn = a.ccnt[x];
+    const int p = f.bstart[J + 1] - f.bstart[J];
+    const int nrJ = f.nr[J];
+    const int32_t* RJ = f.idx + f.roff[J];
+    const int32_t* CJ = f.idx + f.coff[J];
+    // the rows of J from the block's first row on
+    int lo = 0, hi = nrJ;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (RJ[mid] < f0) lo = mid + 1; else hi = mid;
+    }
+    const int rows = nrJ - lo;
+    for (int e = tid; e < rows * cn; e += nt) {
+      const int i = lo + e / cn, t = c0 + e % cn;
+      const int r = RJ[i];
+      double* dst;
+      if (r <= l0) {
+        dst = PD + (r - f0) * q;
+      } else {
+        const int ii = find_sorted(Rl, nr, r);
+        if (ii < 0) continue;  // not stored
+        dst = PL + (int64_t)ii * q;
+      }
+      dst[CJ[t] - f0] -= frozen_term(f.val, f.vprec, f.loff[J] + (int64_t)i * p,
+                                     f.woff[J] + (int64_t)t * p, p);
+    }
+    __syncthreads();
+  }
+  // row panel: predecessors whose rows run inside K, ascending
+  for (int x = a.rptr[K]; x < a.rptr[K + 1]; ++x) {
+    const int J = a.rj[x], r0 = a.rs0[x], rn = a.rcnt[x];
+    const int p = f.bstart[J + 1] - f.bstart[J];
+    const int ncJ = f.nc[J];
+    const int32_t* RJ = f.idx + f.roff[J];
+    const int32_t* CJ = f.idx + f.coff[J];
+    int lo = 0, hi = ncJ;  // the columns of J beyond the block
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (CJ[mid] <= l0) lo = mid + 1; else hi = mid;
+    }
+    const int cols = ncJ - lo;
+    for (int e = tid; e < rn * cols; e += nt) {
+      const int i = r0 + e % rn, t = lo + e / rn;
+      const int k = find_sorted(Cl, nc, CJ[t]);
+      if (k < 0) continue;
+      PW[(int64_t)k * q + (RJ[i] - f0)] -=
+          frozen_term(f.val, f.vprec, f.loff[J] + (int64_t)i * p, f.woff[J] + (int64_t)t * p, p);
+    }
+    __syncthreads();
+  }
+  // pivot block (the sweep's routine and perturbation), then L_K and W_K
+  double* sS = a.piv ? a.piv + 2 * f.doff[K] : s_dyn;
+  double* sW = sS + q * q;
+  if (tid == 0) s.alpha_k = a.fa.alpha;
+  __syncthreads();
+  if (tid < 64) {
+    const bool ok = (q <= 8 && pivot_regs(a.fa, q, PD, sS, sW)) ||
+                    pivot_block<true>(a.fa, K, q, PD, sS, sW, s, s.alpha_k);
+    if (tid == 0) s.misc[14] = ok ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s.misc[14]) return;  // reported through the status words
+  const int64_t dof = f.doff[K];
+  for (int e = tid; e < q * q; e += nt) {
+    a.dval[dof + e] = sW[e];
+    if (a.sval) a.sval[dof + e] = sS[e];
+  }
+  for (int e = tid; e < nr * q; e += nt) {
+    const int i = e / q, c = e % q;
+    double acc = 0.0;
+    for (int t = 0; t < q; ++t) acc = fma(PL[(int64_t)i * q + t], sW[t * q + c], acc);
+    value_store(a.val, f.vprec, f.loff[K] + e, acc);
+  }
+  for (int e = tid; e < nc * q; e += nt) value_store(a.val, f.vprec, f.woff[K] + e, PW[e]);
+}
+
+// Dependency levels of the frozen refactorization: level(K) = 1 + the
+// largest level of the blocks whose columns (cptr) or rows (rptr) run
+// inside K, all of them earlier.  One wave per block in ascending order of
+// workgroups (every dependency at a lower slot, the hardware starts
+// workgroups in index order); bounded waits.
+__global__ void __launch_bounds__(256) frozen_levels(int nb, const int32_t* cptr, const int32_t* cj,
+                                                     const int32_t* rptr, const int32_t* rj,
+                                                     int* lev, int* err, unsigned long long wait) {
+  const int K = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (K >= nb) return;  // no workgroup barrier below
+  const int lane = threadIdx.x & 63;
+  int l = 0;
+  const unsigned long long t0 = wall_clock64();
+  for (int side = 0; side < 2; ++side) {
+    const int32_t* ptr = side ? rptr : cptr;
+    const int32_t* adj = side ? rj : cj;
+    for (int e = ptr[K]; e < ptr[K + 1]; e += 64) {
+      const int J = e + lane < ptr[K + 1] ? adj[e + lane] : -1;
+      int v = J >= 0 ? __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+      while (!__all(v >= 0)) {
+        if (wall_clock64() - t0 > wait ||
+            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          if (lane == 0) atomicExch(err, 1);
+          return;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if (v < 0) v = __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (J >= 0) l = max(l, v + 1);
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) l = max(l, __shfl_xor(l, o, 64));
+  if (lane == 0) __hip_atomic_store(&lev[K], l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Ends of every block's value ranges (L and W) and pivot range, maximum.
+__global__ void frozen_extent(FactorView f, unsigned long long* mx) {
+  const int K = blockIdx.x * blockDim.x + threadIdx.x;
+  if (K >= f.nb) return;
+  const int64_t q = f.bstart[K + 1] - f.bstart[K];
+  const int64_t e = max(f.loff[K] + f.nr[K] * q, f.woff[K] + f.nc[K] * q);
+  atomicMax(mx, (unsigned long long)e);
+  atomicMax(mx + 1, (unsigned long long)(f.doff[K] + q * q));
+  atomicMax(mx + 2, (unsigned long long)q);
+}
+__global__ void frozen_iota(int n, int32_t* v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = i;
+}
+__global__ void frozen_level_starts(int nb, const int* sorted, int* start) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  if (i == 0 || sorted[i - 1] != sorted[i]) start[sorted[i]] = i;
+  if (i == nb - 1) start[sorted[i] + 1] = nb;
+}
+
+// ---------------------------------------------------------------------------
 // Host driver
 // ---------------------------------------------------------------------------
 int64_t factor_partition(bilu_handle* h, double tau) {
@@ -3067,6 +3312,123 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     return BILU_OK;
   }
   return fail(h, BILU_ERR_NO_MEMORY, "factor heap could not be sized");
+#undef CK
+}
+
+
+// Refactorization with frozen patterns (see frozen_block_kernel): the values
+// of A were replaced (refactor_values); the last factor's blocks, lists and
+// storage stay, its values are recomputed.
+bilu_status frozen_refactor(bilu_handle* h) {
+#define CK(x)                                          \
+  do {                                                 \
+    hipError_t e_ = (x);                               \
+    if (e_ != hipSuccess) return hip_check(h, e_, #x); \
+  } while (0)
+  hipStream_t st = h->stream;
+  const FactorView& f = h->fv;
+  const int nb = f.nb;
+  // the blocks whose columns run inside each block (its rows: the apply
+  // plan's forward lists of the same factor)
+  DevArray<int32_t> cptr, cj, cs0, ccnt;
+  {
+    const bilu_status rs = block_runs(h, f, true, cptr, cj, cs0, ccnt);
+    if (rs != BILU_OK) return rs;
+  }
+  // levels, the blocks ordered by (level, index)
+  DevArray<int> lev, misc;
+  DevArray<unsigned long long> ext;
+  CK(lev.alloc(std::max(1, nb)));
+  CK(misc.alloc(4));
+  CK(ext.alloc(3));
+  CK(hipMemsetAsync(lev.p, 0xff, nb * sizeof(int), st));
+  CK(hipMemsetAsync(misc.p, 0, 4 * sizeof(int), st));
+  CK(hipMemsetAsync(ext.p, 0, 3 * sizeof(unsigned long long), st));
+  const unsigned long long wait = h->wait_ticks ? h->wait_ticks : (unsigned long long)1e9;
+  frozen_levels<<<(unsigned)((nb + 3) / 4), 256, 0, st>>>(nb, cptr.p, cj.p, h->fw_ptr.p, h->fw_j.p,
+                                                          lev.p, misc.p + 2, wait);
+  frozen_extent<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(f, ext.p);
+  CK(hipGetLastError());
+  size_t rb = 0;
+  CK(hipcub::DeviceReduce::Max(nullptr, rb, lev.p, misc.p, nb, st));
+  CK(h->d_scan_tmp.alloc(rb + 1));
+  CK(hipcub::DeviceReduce::Max(h->d_scan_tmp.p, rb, lev.p, misc.p, nb, st));
+  int hm[4];
+  unsigned long long he[3];
+  CK(hipMemcpyAsync(hm, misc.p, sizeof(hm), hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(he, ext.p, sizeof(he), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  if (hm[2]) return fail(h, BILU_ERR_DEVICE, "refactor: a dependency wait timed out");
+  const int maxlev = hm[0];
+  DevArray<int32_t> idx, sched, keys_out, starts;
+  CK(idx.alloc(nb));
+  CK(sched.alloc(nb));
+  CK(keys_out.alloc(nb));
+  CK(starts.alloc(maxlev + 3));
+  frozen_iota<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nb, idx.p);
+  int bits = 1;
+  while ((1 << bits) <= maxlev) ++bits;
+  size_t bytes = 0;
+  CK(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, lev.p, keys_out.p, idx.p, sched.p, nb, 0,
+                                        bits, st));
+  CK(h->d_scan_tmp.alloc(bytes + 1));
+  CK(hipcub::DeviceRadixSort::SortPairs(h->d_scan_tmp.p, bytes, lev.p, keys_out.p, idx.p, sched.p,
+                                        nb, 0, bits, st));
+  frozen_level_starts<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nb, keys_out.p, starts.p);
+  std::vector<int> lstart(maxlev + 2);
+  CK(hipMemcpyAsync(lstart.data(), starts.p, (maxlev + 2) * sizeof(int), hipMemcpyDeviceToHost,
+                    st));
+  CK(hipStreamSynchronize(st));
+  // FP64 panels and pivot scratch
+  const int maxq = (int)he[2];
+  DevArray<double> pv, pd, piv;
+  CK(pv.alloc(std::max<unsigned long long>(1, he[0])));
+  CK(pd.alloc(std::max<unsigned long long>(1, he[1])));
+  const bool lds_pivot = maxq <= kLdsPivotWidth;
+  const size_t dyn = lds_pivot ? 2 * sizeof(double) * maxq * maxq : 0;
+  if (!lds_pivot) CK(piv.alloc(2 * std::max<unsigned long long>(1, he[1])));
+  CK(hipMemsetAsync(h->d_status.p, 0, 3 * sizeof(int), st));
+  FrozenArgs a{};
+  a.f = f;
+  a.val = const_cast<void*>(f.val);
+  a.dval = const_cast<double*>(f.dval);
+  // S_K too when the factor is the sweep's own (no merges), so the
+  // kept-pattern residual stays defined
+  a.sval = f.dval == h->d_dval.p ? h->d_sval.p : nullptr;
+  a.PL = pv.p;
+  a.PW = pv.p;
+  a.PD = pd.p;
+  a.piv = lds_pivot ? nullptr : piv.p;
+  a.cp = h->d_cp.p; a.ri = h->d_ri.p; a.cv = h->d_cv.p;
+  a.rp = h->d_rp.p; a.ci = h->d_ci.p; a.rv = h->d_rv.p;
+  a.cptr = cptr.p; a.cj = cj.p; a.cs0 = cs0.p; a.ccnt = ccnt.p;
+  a.rptr = h->fw_ptr.p; a.rj = h->fw_j.p; a.rs0 = h->fw_r0.p; a.rcnt = h->fw_cnt.p;
+  a.sched = sched.p;
+  a.fa.alpha = h->alpha;
+  a.fa.pert_tau = h->opt.perturb_tau;
+  a.fa.pert_rho = h->opt.perturb_rho;
+  a.fa.pivot_eps = h->opt.pivot_eps;
+  a.fa.beta_one = h->opt.beta_one;
+  a.fa.pflag = nullptr;
+  a.fa.err = h->d_status.p + 0;
+  a.fa.err_block = h->d_status.p + 1;
+  a.fa.n_perturbed = h->d_status.p + 2;
+  for (int L = 0; L <= maxlev; ++L) {
+    a.begin = lstart[L];
+    a.end = lstart[L + 1];
+    if (a.end > a.begin)
+      frozen_block_kernel<<<(unsigned)(a.end - a.begin), kThreads, dyn, st>>>(a);
+  }
+  CK(hipGetLastError());
+  int status[3];
+  CK(hipMemcpyAsync(status, h->d_status.p, sizeof(status), hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  h->stats.perturbed_blocks = status[2];
+  if (status[0] == kDevSingular)
+    return fail(h, BILU_ERR_SINGULAR, "refactor: a pivot block stayed singular (block " +
+                                          std::to_string(status[1]) + ")");
+  if (status[0] != 0) return fail(h, BILU_ERR_DEVICE, "refactor: device error " + std::to_string(status[0]));
+  return BILU_OK;
 #undef CK
 }
 

@@ -328,6 +328,9 @@ struct bilu_handle {
   // set by the solver while it runs steps ahead: the apply, the product and
   // the vector kernels do no work once the int it points to is nonzero
   const int* run_skip = nullptr;
+  // the kept-pattern residual no longer describes the factor (a frozen
+  // refactorization of a factor with merged blocks)
+  bool kept_stale = false;
 
   // settings in effect for the last factorization: the options, or a tuned
   // entry for its precision and block-width class (use_tuning)
@@ -402,6 +405,11 @@ bilu_status build_apply_plan(bilu_handle* h);
 // For every block K of f, the blocks J whose stored rows (cols: columns)
 // fall into K, ascending, with the first position of the run in R_J (C_J)
 // and its length (ptr [nb+1]; j, s0, cnt per entry).  Synchronous.
+// factor.hip: the last factor's values recomputed on its frozen patterns
+bilu_status frozen_refactor(bilu_handle* h);
+// solve.hip: the apply's copies of the factor values (row-major L, FP32
+// copy) made again from the factor, its patterns unchanged
+bilu_status refresh_apply_values(bilu_handle* h);
 bilu_status block_runs(bilu_handle* h, const FactorView& f, bool cols, DevArray<int32_t>& ptr,
                        DevArray<int32_t>& j, DevArray<int32_t>& s0, DevArray<int32_t>& cnt);
 // kept.hip: ||(L S U - A)_Omega||_F / ||A||_F of the sweep's factor (before

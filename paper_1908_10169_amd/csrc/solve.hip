@@ -1031,6 +1031,26 @@ bilu_status build_apply_plan(bilu_handle* h) {
 #undef CK
 }
 
+bilu_status refresh_apply_values(bilu_handle* h) {
+  hipStream_t st = h->stream;
+  const FactorView& f = h->fv;
+  const int64_t nb = f.nb;
+  const unsigned gw = (unsigned)((nb + 3) / 4);
+  if (h->apply_prec != f.vprec)
+    convert_values<<<grid_for(h->f_val_len), 256, 0, st>>>(
+        h->f_val_len, static_cast<const double*>(f.val), reinterpret_cast<float*>(h->d_apply_val.p));
+  with_value_type(h->apply_prec, [&](auto tag) {
+    using T = decltype(tag);
+    lr_build<true, T><<<gw, 256, 0, st>>>(f, h->fw_ptr.p, h->fw_j.p, h->fw_r0.p, h->fw_cnt.p,
+                                          h->lr_ptr.p, nullptr, h->lr_col.p,
+                                          reinterpret_cast<T*>(h->lr_val.p));
+  });
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_check(h, e, "refresh apply values");
+  return BILU_OK;
+}
+
 // W values the apply reads: the stored ones, or their FP32 copy.
 template <class T>
 static const T* apply_w(const bilu_handle* h) {

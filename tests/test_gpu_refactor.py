@@ -204,3 +204,93 @@ def test_refactor_full_size():
         assert s0[k] == s1[k], k
     assert y0.cpu().numpy().tobytes() == y1.cpu().numpy().tobytes()
     h.close()
+
+
+# ---------------------------------------------------------------------------
+# bilu_refactor_frozen: the last factor's blocks and patterns stay, the
+# values follow the new matrix.  Reference: the oracle's frozen
+# refactorization of its own factor of the first matrix (the two factors
+# have the same blocks and patterns by the parity tests).
+# ---------------------------------------------------------------------------
+FROZEN_CASES = [
+    ("cd2d_32x32_b3", "cd2d_32x32_b3", False),
+    ("cd2d_32x32_b3_agg", "cd2d_32x32_b3", True),
+    ("cd3d_12_b4_agg", "cd3d_12_b4", True),
+    ("el3d_10_b3", "el3d_10_b3", False),
+    ("el3d_10_b3_agg", "el3d_10_b3", True),
+]
+
+
+@pytest.mark.parametrize("name,wl,agg", FROZEN_CASES, ids=[c[0] for c in FROZEN_CASES])
+def test_refactor_frozen_matches_oracle(name, wl, agg):
+    torch = _torch()
+    from oracle import Oracle, OracleOptions
+    from paper_1908_10169_amd import bilu
+    w = mg.workload(wl)
+    say(f"[frozen] {name} n={w.a.n}")
+    o = Oracle()
+    assert o.run(w.a, OracleOptions(tau=w.tau, use_aggregation=agg), pre_perm=w.perm) == 0
+    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=agg)
+    h.analyze(w.a, pre_perm=w.perm)
+    h.factor(w.tau)
+    a2 = new_values(w.a, 9)
+    assert o.refactor_frozen(a2.val) == 0
+    h.refactor_frozen(torch.from_numpy(a2.val).cuda())
+    fl = h.export()
+    compare_with_oracle(o, fl)
+    # the apply with the new values, and a solve of the new system
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(w.a.n)
+    y = torch.empty(w.a.n, dtype=torch.float64, device="cuda")
+    h.apply(torch.from_numpy(x).cuda(), y)
+    yo = o.apply(x)
+    assert np.linalg.norm(y.cpu().numpy() - yo) <= TOL * np.linalg.norm(yo)
+    b = a2.matvec(np.ones(w.a.n))
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd)
+    info = h.fgmres(bd, xd, restart=w.restart, rtol=1e-8)
+    assert info["converged"]
+    assert np.linalg.norm(b - a2.matvec(xd.cpu().numpy())) <= 1e-8 * np.linalg.norm(b)
+    assert h.stats()["apply_faults"] == 0
+    if not agg:  # the kept-pattern identity on the new values
+        assert h.kept_residual() <= 1e-13
+    h.close()
+
+
+def test_refactor_frozen_same_values_and_errors():
+    """The same values give the factor back (to rounding, no merges); the
+    kept-pattern residual is refused after merges; a non-finite value
+    changes nothing; a call before bilu_factor is a state error."""
+    torch = _torch()
+    from paper_1908_10169_amd import bilu
+    w = mg.workload("cd3d_12_b4")
+    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=False)
+    h.analyze(w.a, pre_perm=w.perm)
+    with pytest.raises(bilu.BiluError) as e:
+        h.refactor_frozen(torch.from_numpy(w.a.val).cuda())
+    assert e.value.status == bilu.BILU_ERR_STATE
+    h.factor(w.tau)
+    f0 = h.export()
+    h.refactor_frozen(torch.from_numpy(w.a.val).cuda())
+    f1 = h.export()
+    for name in ("L", "W", "D"):
+        x = np.concatenate([v.ravel() for v in getattr(f1, name)])
+        y = np.concatenate([v.ravel() for v in getattr(f0, name)])
+        assert np.linalg.norm(x - y) <= 1e-13 * np.linalg.norm(y), name
+    bad = w.a.val.copy()
+    bad[7] = np.nan
+    with pytest.raises(bilu.BiluError) as e:
+        h.refactor_frozen(torch.from_numpy(bad).cuda())
+    assert e.value.status == bilu.BILU_ERR_INVALID
+    f2 = h.export()
+    assert all(np.array_equal(x, y) for x, y in zip(f1.L + f1.W + f1.D, f2.L + f2.W + f2.D))
+    h.close()
+    g = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=True)
+    g.analyze(w.a, pre_perm=w.perm)
+    g.factor(w.tau)
+    if g.stats()["merges"] > 0:
+        g.refactor_frozen(torch.from_numpy(new_values(w.a, 2).val).cuda())
+        with pytest.raises(bilu.BiluError) as e:
+            g.kept_residual()
+        assert e.value.status == bilu.BILU_ERR_STATE
+    g.close()

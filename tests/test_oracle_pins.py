@@ -717,3 +717,73 @@ def test_p8_sets_use_the_pivot_diagonal():
     I, J = ilu1t_sets(mg.dense_to_csr(A), k, 0.03)
     assert set(I.tolist()) == {k + 1, k + nx, k + nx - 1}
     assert set(J.tolist()) == {k + 1, k + nx, k + nx - 1}
+
+
+# ---------------------------------------------------------------------------
+# P15: refactorization with frozen patterns (a variant for matrix sequences)
+# ---------------------------------------------------------------------------
+def _new_values(a, seed):
+    """The same pattern, values scaled entrywise by 1 + 0.3 U(-1, 1)."""
+    rng = np.random.default_rng(seed)
+    return a.val * (1.0 + 0.3 * rng.uniform(-1.0, 1.0, a.val.size))
+
+
+@pytest.mark.parametrize("blocking", [NO_BLOCKING, {}])
+def test_p15_frozen_tau0_is_exact_lu_of_the_new_matrix(blocking):
+    """With tau = 0 the stored pattern is the full LU fill, so the frozen
+    refactorization on new values is the exact LU of the new matrix."""
+    a = mg.random_sparse(200, 0.03, seed=3, diag_shift=8.0)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=0.0, **blocking)) == 0
+    v2 = _new_values(a, 5)
+    assert o.refactor_frozen(v2) == 0
+    a2 = mg.Csr(a.n, a.rowptr, a.colind, v2)
+    A2 = a2.to_dense()
+    b = A2 @ np.ones(a.n)
+    y = o.apply(b)
+    x_ref = np.linalg.solve(A2, b)
+    assert np.linalg.norm(y - x_ref) <= 1e-11 * np.linalg.norm(x_ref)
+    assert o.final_residual() <= 1e-14
+
+
+@pytest.mark.parametrize("tau,agg", [(1e-2, False), (1e-1, False), (1e-2, True), (1e-1, True)])
+def test_p15_frozen_keeps_the_pattern_identity(tau, agg):
+    """For any tau, with or without merged blocks: the new factor reproduces
+    the new matrix on the stored positions, (L S U)_Omega = A_Omega, and
+    the patterns are the old ones."""
+    w = mg.workload("cd2d_32x32_b3")
+    o = Oracle()
+    assert o.run(w.a, OracleOptions(tau=tau, use_aggregation=agg), pre_perm=w.perm) == 0
+    f0 = o.factors()
+    assert o.refactor_frozen(_new_values(w.a, 7)) == 0
+    f1 = o.factors()
+    assert np.array_equal(f0.starts, f1.starts)
+    for k in range(len(f0.starts) - 1):
+        assert np.array_equal(f0.R[k], f1.R[k]) and np.array_equal(f0.C[k], f1.C[k])
+    assert o.final_residual() <= 1e-13
+    # and a plain definition of the identity, entry by entry on a sample
+    L, S, U, f = assemble(o)
+    a2 = mg.Csr(w.a.n, w.a.rowptr, w.a.colind, _new_values(w.a, 7))
+    P = permuted_dense(a2, f.perm)
+    M = L @ S @ U
+    K0 = 5
+    q = f1.starts[K0 + 1] - f1.starts[K0]
+    for r in range(f1.starts[K0], f1.starts[K0] + q):
+        for j in f1.C[K0]:
+            assert abs(M[r, j] - P[r, j]) <= 1e-12 * np.abs(P).max()
+
+
+def test_p15_frozen_with_the_same_values_reproduces_the_factor():
+    """Without merges the sweep's kept values are the Crout values on its
+    own pattern, so the frozen refactorization of the same matrix gives
+    them back (to rounding)."""
+    w = mg.workload("cd2d_32x32_b3")
+    o = Oracle()
+    assert o.run(w.a, OracleOptions(tau=1e-2, use_aggregation=False), pre_perm=w.perm) == 0
+    f0 = o.factors()
+    assert o.refactor_frozen(w.a.val) == 0
+    f1 = o.factors()
+    for name in ("L", "W", "D"):
+        x = np.concatenate([v.ravel() for v in getattr(f1, name)])
+        y = np.concatenate([v.ravel() for v in getattr(f0, name)])
+        assert np.linalg.norm(x - y) <= 1e-13 * np.linalg.norm(y), name
