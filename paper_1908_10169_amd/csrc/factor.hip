@@ -2812,57 +2812,82 @@ __global__ void __launch_bounds__(kThreads) frozen_block_kernel(FrozenArgs a) {
       if (k >= 0) PW[(int64_t)k * q + r] = a.rv[m];
     }
   }
-  __syncthreads();
-  // column panel: predecessors whose columns run inside K, ascending; a
-  // predecessor's terms hit distinct entries
-  for (int x = a.cptr[K]; x < a.cptr[K + 1]; ++x) {
-    const int J = a.cj[x], c0 = a.cs0[x], cn = a.ccnt[x];
-    const int p = f.bstart[J + 1] - f.bstart[J];
-    const int nrJ = f.nr[J];
-    const int32_t* RJ = f.idx + f.roff[J];
-    const int32_t* CJ = f.idx + f.coff[J];
-    // the rows of J from the block's first row on
-    int lo = 0, hi = nrJ;
+  // every predecessor's first row from the block on (column panel) and
+  // first column beyond the block (row panel), searched all at once
+  const int x0c = a.cptr[K], ncp = a.cptr[K + 1] - x0c;
+  const int x0r = a.rptr[K], nrp = a.rptr[K + 1] - x0r;
+  const bool pre = ncp <= kPredCap && nrp <= kPredCap;
+  auto first_from = [&](const int32_t* v, int m, int key, bool beyond) {
+    int lo = 0, hi = m;  // first position with v >= key (beyond: v > key)
     while (lo < hi) {
       const int mid = (lo + hi) >> 1;
-      if (RJ[mid] < f0) lo = mid + 1; else hi = mid;
+      if (beyond ? v[mid] <= key : v[mid] < key) lo = mid + 1; else hi = mid;
     }
-    const int rows = nrJ - lo;
-    for (int e = tid; e < rows * cn; e += nt) {
-      const int i = lo + e / cn, t = c0 + e % cn;
-      const int r = RJ[i];
-      double* dst;
-      if (r <= l0) {
-        dst = PD + (r - f0) * q;
-      } else {
-        const int ii = find_sorted(Rl, nr, r);
-        if (ii < 0) continue;  // not stored
-        dst = PL + (int64_t)ii * q;
-      }
-      dst[CJ[t] - f0] -= frozen_term(f.val, f.vprec, f.loff[J] + (int64_t)i * p,
-                                     f.woff[J] + (int64_t)t * p, p);
+    return lo;
+  };
+  for (int t = tid; pre && t < ncp + nrp; t += nt) {
+    if (t < ncp) {
+      const int J = a.cj[x0c + t];
+      s.g.pred[t] = first_from(f.idx + f.roff[J], f.nr[J], f0, false);
+    } else {
+      const int J = a.rj[x0r + t - ncp];
+      s.g.rpred[t - ncp] = first_from(f.idx + f.coff[J], f.nc[J], l0, true);
     }
-    __syncthreads();
   }
-  // row panel: predecessors whose rows run inside K, ascending
-  for (int x = a.rptr[K]; x < a.rptr[K + 1]; ++x) {
-    const int J = a.rj[x], r0 = a.rs0[x], rn = a.rcnt[x];
-    const int p = f.bstart[J + 1] - f.bstart[J];
-    const int ncJ = f.nc[J];
-    const int32_t* RJ = f.idx + f.roff[J];
-    const int32_t* CJ = f.idx + f.coff[J];
-    int lo = 0, hi = ncJ;  // the columns of J beyond the block
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (CJ[mid] <= l0) lo = mid + 1; else hi = mid;
+  __syncthreads();
+  // the k-th column-panel predecessor (columns running inside K) and the
+  // k-th row-panel predecessor (rows running inside K) together, in
+  // ascending order: they update different panels, and one predecessor's
+  // terms hit distinct entries, so one barrier per pair keeps every entry's
+  // terms in block order
+  for (int k = 0; k < max(ncp, nrp); ++k) {
+    int Jc = -1, c0 = 0, cn = 0, pc = 0, loc = 0, rows = 0;
+    const int32_t *RJc = nullptr, *CJc = nullptr;
+    if (k < ncp) {
+      Jc = a.cj[x0c + k];
+      c0 = a.cs0[x0c + k];
+      cn = a.ccnt[x0c + k];
+      pc = f.bstart[Jc + 1] - f.bstart[Jc];
+      RJc = f.idx + f.roff[Jc];
+      CJc = f.idx + f.coff[Jc];
+      loc = pre ? s.g.pred[k] : first_from(RJc, f.nr[Jc], f0, false);  // rows from the block on
+      rows = f.nr[Jc] - loc;
     }
-    const int cols = ncJ - lo;
-    for (int e = tid; e < rn * cols; e += nt) {
-      const int i = r0 + e % rn, t = lo + e / rn;
-      const int k = find_sorted(Cl, nc, CJ[t]);
-      if (k < 0) continue;
-      PW[(int64_t)k * q + (RJ[i] - f0)] -=
-          frozen_term(f.val, f.vprec, f.loff[J] + (int64_t)i * p, f.woff[J] + (int64_t)t * p, p);
+    int Jr = -1, r0 = 0, rn = 0, pr = 0, lor = 0, cols = 0;
+    const int32_t *RJr = nullptr, *CJr = nullptr;
+    if (k < nrp) {
+      Jr = a.rj[x0r + k];
+      r0 = a.rs0[x0r + k];
+      rn = a.rcnt[x0r + k];
+      pr = f.bstart[Jr + 1] - f.bstart[Jr];
+      RJr = f.idx + f.roff[Jr];
+      CJr = f.idx + f.coff[Jr];
+      lor = pre ? s.g.rpred[k] : first_from(CJr, f.nc[Jr], l0, true);  // columns beyond
+      cols = f.nc[Jr] - lor;
+    }
+    const int na = rows * cn, nab = na + rn * cols;
+    for (int e = tid; e < nab; e += nt) {
+      if (e < na) {
+        const int i = loc + e / cn, t = c0 + e % cn;
+        const int r = RJc[i];
+        double* dst;
+        if (r <= l0) {
+          dst = PD + (r - f0) * q;
+        } else {
+          const int ii = find_sorted(Rl, nr, r);
+          if (ii < 0) continue;  // not stored
+          dst = PL + (int64_t)ii * q;
+        }
+        dst[CJc[t] - f0] -= frozen_term(f.val, f.vprec, f.loff[Jc] + (int64_t)i * pc,
+                                        f.woff[Jc] + (int64_t)t * pc, pc);
+      } else {
+        const int e2 = e - na;
+        const int i = r0 + e2 % rn, t = lor + e2 / rn;
+        const int kk = find_sorted(Cl, nc, CJr[t]);
+        if (kk < 0) continue;
+        PW[(int64_t)kk * q + (RJr[i] - f0)] -= frozen_term(
+            f.val, f.vprec, f.loff[Jr] + (int64_t)i * pr, f.woff[Jr] + (int64_t)t * pr, pr);
+      }
     }
     __syncthreads();
   }
