@@ -6,6 +6,6 @@ with the GPU library (``paper_1908_10169_amd``) and never imports it.
 """
 from .oracle import (  # noqa: F401
     Oracle, OracleOptions, cosine_groups, ilu1t_blocks, ilu1t_sets, perturb_invert,
-    fgmres_plain, load,
+    fgmres_plain, sqmr_plain, load,
 )
 from .mwm import apply_mwm, mwm, mwm_scalings  # noqa: F401

@@ -1221,6 +1221,110 @@ void fgmres(const Mat& a, Prec prec, const double* b, double* x, int m, double r
   info->converged = converged;
 }
 
+
+double norm_inf(const double* v, i64 n) {
+  double m = 0.0;
+  for (i64 i = 0; i < n; ++i) m = std::max(m, std::fabs(v[i]));
+  return m;
+}
+
+// ||A||_inf: the largest row sum of magnitudes.
+double mat_norm_inf(const Mat& a) {
+  double m = 0.0;
+  for (i64 i = 0; i < a.n; ++i) {
+    double s = 0.0;
+    for (i64 k = a.rp[i]; k < a.rp[i + 1]; ++k) s += std::fabs(a.v[k]);
+    m = std::max(m, s);
+  }
+  return m;
+}
+
+// Normwise backward error of x in the infinity norm (Rigal and Gaches,
+// J. ACM 14, 1967): the smallest eta with (A + E) x = b + f,
+// ||E|| <= eta ||A||, ||f|| <= eta ||b||.  0 when the residual is 0.
+double backward_error(double rmax, double anorm, double xmax, double bmax) {
+  if (rmax == 0.0) return 0.0;
+  return rmax / (anorm * xmax + bmax);
+}
+
+// Simplified QMR (Freund and Nachtigal 1995; Freund and Jarre 1997), the
+// Krylov solver of Sec. 5 for symmetric A with a symmetric, possibly
+// indefinite preconditioner M (the preconditioner splits as M1 = I,
+// M2 = M).  One product with A and one application of M^{-1} per step;
+// r is the Lanczos (BiCG) residual, tau the quasi-residual norm, and
+// ||b - A x_k||_2 <= sqrt(k + 1) tau_k.  The QMR residual b - A x is kept
+// by the recurrence rq -= A d, with A d = cd (A d_old) + cq (A q).
+// Stopping test: the backward error eta of x on the updated QMR residual,
+// confirmed with the true residual (Reading: Sec. 5 names the backward
+// error and the tolerance 1e-6, not its norm; it is taken in the infinity
+// norm).  Breakdown (q^T A q = 0 or r^T M^{-1} r = 0) stops the solve.
+// hist (may be NULL): tau_k after step k.
+template <class Prec>
+void sqmr(const Mat& a, Prec prec, const double* b, double* x, double tol, int maxit,
+          orc_solve_info* info, double* eta_out, double* hist) {
+  const i64 n = a.n;
+  std::vector<double> r(n), rq(n), q(n), t(n), u(n), d(n, 0.0), s(n, 0.0), tr(n);
+  const double anorm = mat_norm_inf(a);
+  const double bmax = norm_inf(b, n);
+  spmv(a, x, r.data());
+  for (i64 i = 0; i < n; ++i) r[i] = b[i] - r[i];
+  rq = r;
+  double eta = backward_error(norm_inf(rq.data(), n), anorm, norm_inf(x, n), bmax);
+  i64 it = 0;
+  int converged = eta <= tol ? 1 : 0;
+  if (!converged && maxit > 0) {
+    double tau = std::sqrt(dot(r, r));
+    prec(r.data(), q.data());
+    double theta = 0.0;
+    double rho = dot(r, q);
+    while (true) {
+      spmv(a, q.data(), t.data());
+      const double sigma = dot(q, t);
+      if (sigma == 0.0) break;
+      const double alpha = rho / sigma;
+      for (i64 i = 0; i < n; ++i) r[i] -= alpha * t[i];
+      const double theta_old = theta;
+      theta = std::sqrt(dot(r, r)) / tau;
+      const double c = 1.0 / std::sqrt(1.0 + theta * theta);
+      const double c2 = c * c;
+      tau = tau * theta * c;
+      const double cd = c2 * theta_old * theta_old, cq = c2 * alpha;
+      for (i64 i = 0; i < n; ++i) {
+        d[i] = cd * d[i] + cq * q[i];
+        s[i] = cd * s[i] + cq * t[i];
+        x[i] += d[i];
+        rq[i] -= s[i];
+      }
+      ++it;
+      if (hist) hist[it - 1] = tau;
+      eta = backward_error(norm_inf(rq.data(), n), anorm, norm_inf(x, n), bmax);
+      if (eta <= tol) {
+        spmv(a, x, tr.data());
+        for (i64 i = 0; i < n; ++i) tr[i] = b[i] - tr[i];
+        if (backward_error(norm_inf(tr.data(), n), anorm, norm_inf(x, n), bmax) <= tol) {
+          converged = 1;
+          break;
+        }
+      }
+      if (it >= maxit || rho == 0.0) break;
+      prec(r.data(), u.data());
+      const double rho_new = dot(r, u);
+      const double beta = rho_new / rho;
+      rho = rho_new;
+      for (i64 i = 0; i < n; ++i) q[i] = u[i] + beta * q[i];
+    }
+  }
+  spmv(a, x, tr.data());
+  for (i64 i = 0; i < n; ++i) tr[i] = b[i] - tr[i];
+  std::vector<double> bb(b, b + n);
+  const double bnorm = std::sqrt(dot(bb, bb));
+  info->iterations = it;
+  info->restarts = 0;
+  info->rel_residual = bnorm > 0.0 ? std::sqrt(dot(tr, tr)) / bnorm : 0.0;
+  info->converged = converged;
+  if (eta_out) *eta_out = backward_error(norm_inf(tr.data(), n), anorm, norm_inf(x, n), bmax);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1244,6 +1348,22 @@ void orc_fgmres_plain(int64_t n, const int64_t* rowptr, const int32_t* colind, c
   fgmres(
       a, [n](const double* in, double* out) { std::copy(in, in + n, out); }, b, x, restart, rtol,
       maxit, info, resid_history);
+}
+
+void orc_sqmr(const orc_handle* h, const double* b, double* x, double tol, int maxit,
+              orc_solve_info* info, double* eta, double* tau_history) {
+  sqmr(
+      h->A, [h](const double* in, double* out) { orc_apply(h, in, out); }, b, x, tol, maxit,
+      info, eta, tau_history);
+}
+
+void orc_sqmr_plain(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* val,
+                    const double* b, double* x, double tol, int maxit, orc_solve_info* info,
+                    double* eta, double* tau_history) {
+  Mat a = from_csr(n, rowptr, colind, val);
+  sqmr(
+      a, [n](const double* in, double* out) { std::copy(in, in + n, out); }, b, x, tol, maxit,
+      info, eta, tau_history);
 }
 
 // (L S U) x in the permuted numbering: W = S U is the non-unit upper factor

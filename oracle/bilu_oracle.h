@@ -118,7 +118,7 @@ int64_t orc_get_mergelog(const orc_handle* h, int64_t* rec /* 6 per entry */);
 void orc_apply(const orc_handle* h, const double* x, double* y);
 
 typedef struct {
-  int64_t iterations;  /* Arnoldi steps                                    */
+  int64_t iterations;  /* Arnoldi steps (FGMRES), steps (SQMR)            */
   int64_t restarts;    /* cycles started                                   */
   double rel_residual; /* true ||b-Ax||/||b|| at exit                      */
   int converged;
@@ -137,6 +137,20 @@ void orc_fgmres_plain(int64_t n, const int64_t* rowptr, const int32_t* colind,
                       const double* val, const double* b, double* x,
                       int restart, double rtol, int maxit,
                       orc_solve_info* info, double* resid_history);
+
+/* Simplified QMR (Sec. 5; Freund and Nachtigal 1995) for symmetric A with
+ * M from the run as preconditioner.  Stops when the infinity-norm backward
+ * error ||b - A x|| / (||A|| ||x|| + ||b||) of the updated QMR residual is
+ * <= tol and the true residual confirms it, after maxit steps, or at a
+ * breakdown.  info->rel_residual is the true 2-norm relative residual;
+ * *eta (may be NULL) the true backward error at exit; tau_history (may be
+ * NULL, maxit entries) the quasi-residual norm after every step. */
+void orc_sqmr(const orc_handle* h, const double* b, double* x, double tol, int maxit,
+              orc_solve_info* info, double* eta, double* tau_history);
+/* orc_sqmr with M = I, on any CSR matrix. */
+void orc_sqmr_plain(int64_t n, const int64_t* rowptr, const int32_t* colind,
+                    const double* val, const double* b, double* x, double tol,
+                    int maxit, orc_solve_info* info, double* eta, double* tau_history);
 
 /* ||(L S U - A)_Omega||_F / ||A||_F over the stored positions Omega of the
  * blocks the sweep computed (before merges). */

@@ -79,6 +79,10 @@ def load():
                                     C.POINTER(_Info), _F64P]
     lib.orc_fgmres_plain.argtypes = [C.c_int64, _I64P, _I32P, _F64P, _F64P, _F64P, C.c_int,
                                      C.c_double, C.c_int, C.POINTER(_Info), _F64P]
+    lib.orc_sqmr.argtypes = [vp, _F64P, _F64P, C.c_double, C.c_int, C.POINTER(_Info),
+                             C.POINTER(C.c_double), _F64P]
+    lib.orc_sqmr_plain.argtypes = [C.c_int64, _I64P, _I32P, _F64P, _F64P, _F64P, C.c_double,
+                                   C.c_int, C.POINTER(_Info), C.POINTER(C.c_double), _F64P]
     lib.orc_kept_residual.argtypes = [vp]
     lib.orc_kept_residual.restype = C.c_double
     lib.orc_final_residual.argtypes = [vp]
@@ -259,6 +263,23 @@ class Oracle:
             return x, out, hist[:info.iterations].copy()
         return x, out
 
+    def sqmr(self, b, x0=None, tol=1e-6, maxit=2000, history=False):
+        """Simplified QMR with M from the run (A and M symmetric); stops on
+        the infinity-norm backward error.  Returns x and a dict with
+        iterations, rel_residual (true 2-norm), eta (true backward error),
+        converged; with history also the quasi-residual norms tau_k."""
+        b = np.ascontiguousarray(b, dtype=np.float64)
+        x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+        info = _Info()
+        eta = C.c_double(0.0)
+        hist = np.zeros(max(maxit, 1))
+        self._lib.orc_sqmr(self._h, b, x, tol, maxit, C.byref(info), C.byref(eta), hist)
+        out = dict(iterations=info.iterations, rel_residual=info.rel_residual,
+                   eta=eta.value, converged=bool(info.converged))
+        if history:
+            return x, out, hist[:info.iterations].copy()
+        return x, out
+
     def kept_residual(self) -> float:
         return self._lib.orc_kept_residual(self._h)
 
@@ -331,3 +352,17 @@ def fgmres_plain(a, b, restart=30, rtol=1e-8, maxit=2000):
     return x, dict(iterations=info.iterations, restarts=info.restarts,
                    rel_residual=info.rel_residual, converged=bool(info.converged)), \
         hist[:info.iterations]
+
+
+def sqmr_plain(a, b, tol=1e-6, maxit=2000, x0=None):
+    """Simplified QMR with M = I on a CSR matrix; returns x, info, tau_k."""
+    lib = load()
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    info = _Info()
+    eta = C.c_double(0.0)
+    hist = np.zeros(max(maxit, 1))
+    lib.orc_sqmr_plain(a.n, a.rowptr, a.colind, a.val, b, x, tol, maxit, C.byref(info),
+                       C.byref(eta), hist)
+    return x, dict(iterations=info.iterations, rel_residual=info.rel_residual,
+                   eta=eta.value, converged=bool(info.converged)), hist[:info.iterations].copy()

@@ -170,8 +170,11 @@ def grid3d_convdiff(side: int = 64, b: int = 4, pe: float = 10.0,
 
 
 def grid3d_elasticity(side: int = 80, b: int = 3, seed: int = 2,
-                      pert: float = 0.05, dims=None) -> Csr:
-    """27-point elasticity-like operator, SPD shifted, randomly perturbed."""
+                      pert: float = 0.05, dims=None, shift: float = 0.1) -> Csr:
+    """27-point elasticity-like operator plus shift * (mean diagonal) * I,
+    its entries randomly perturbed by up to ``pert``.  pert = 0 keeps it
+    symmetric: positive definite for shift > 0, indefinite for a negative
+    shift inside the spectrum."""
     if b != 3:
         raise ValueError("elasticity-like operator uses 3 unknowns per node")
     rng = np.random.default_rng(np.random.PCG64(seed))
@@ -195,7 +198,7 @@ def grid3d_elasticity(side: int = 80, b: int = 3, seed: int = 2,
     blocks *= offmask[:, :, None, None]
     blocks[:, centre] = np.einsum("no,oij->nij", offmask.astype(np.float64), mats)
     mean_diag = float(np.mean(np.diagonal(blocks[:, centre], axis1=1, axis2=2)))
-    blocks[:, centre] += 0.1 * mean_diag * np.eye(3)
+    blocks[:, centre] += shift * mean_diag * np.eye(3)
     xi = rng.uniform(-1.0, 1.0, size=(N, O, 3, 3))
     scale = 1.0 + pert * xi
     scale[:, centre, np.arange(3), np.arange(3)] = 1.0   # keep scalar diagonal

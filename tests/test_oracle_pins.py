@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import Oracle, OracleOptions, cosine_groups, ilu1t_blocks, perturb_invert, \
-    fgmres_plain
+    fgmres_plain, sqmr_plain
 from paper_1908_10169_amd import matgen as mg
 
 NO_BLOCKING = dict(use_cosine=False, use_ilu1t=False, use_aggregation=False)
@@ -787,3 +787,130 @@ def test_p15_frozen_with_the_same_values_reproduces_the_factor():
         x = np.concatenate([v.ravel() for v in getattr(f1, name)])
         y = np.concatenate([v.ravel() for v in getattr(f0, name)])
         assert np.linalg.norm(x - y) <= 1e-13 * np.linalg.norm(y), name
+
+
+# ---------------------------------------------------------------------------
+# P16: simplified QMR (Sec. 5), the Krylov solver for symmetric A and M.
+# Pins: (a) for symmetric A and M, QMR with the two-sided Lanczos process
+# and right preconditioner M (SciPy's qmr, an independent implementation
+# with its own recurrences) produces the same iterates in exact
+# arithmetic; (b) finite termination after as many steps as A has distinct
+# eigenvalues; (c) the QMR bound ||b - A x_k||_2 <= sqrt(k + 1) tau_k;
+# (d) an exact preconditioner (tau = 0) solves in one step; (e) the stop is
+# taken at the first step whose backward error meets the tolerance.
+# ---------------------------------------------------------------------------
+def _sym_indefinite(n, eigs, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return Q @ np.diag(eigs) @ Q.T, rng.standard_normal(n)
+
+
+def _sym_elasticity(side, shift):
+    a = mg.grid3d_elasticity(side, 3, seed=2, pert=0.0, shift=shift)
+    perm = mg.node_perm_to_scalar(
+        mg.grid_nd_node_order((side,) * 3, dissect_separators=False), 3)
+    return a, perm
+
+
+def _scipy_qmr(A, b, k, prec=None):
+    import scipy.sparse.linalg as sla
+    kw = {}
+    if prec is not None:
+        n = len(b)
+        eye = sla.LinearOperator((n, n), matvec=lambda v: v, rmatvec=lambda v: v)
+        M2 = sla.LinearOperator((n, n), matvec=prec, rmatvec=prec)
+        kw = dict(M1=eye, M2=M2)
+    x, _ = sla.qmr(A, b, maxiter=k, rtol=1e-300, atol=0.0, **kw)
+    return x
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 8, 12])
+def test_p16_sqmr_plain_matches_qmr(k):
+    rng = np.random.default_rng(11)
+    eigs = np.concatenate([rng.uniform(1.0, 5.0, 32), -rng.uniform(1.0, 3.0, 8)])
+    A, b = _sym_indefinite(40, eigs, 4)
+    x, info, _ = sqmr_plain(mg.dense_to_csr(A), b, tol=0.0, maxit=k)
+    assert info["iterations"] == k and not info["converged"]
+    xs = _scipy_qmr(A, b, k)
+    assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_p16_sqmr_preconditioned_matches_qmr(k):
+    """M from the block ILU of a symmetric indefinite matrix: the sweep on
+    symmetric data is symmetric (L^T and U share their patterns), so M is
+    symmetric up to rounding and QMR with right preconditioner M agrees."""
+    a, perm = _sym_elasticity(6, -0.1)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=1e-2, use_aggregation=True), pre_perm=perm) == 0
+    st = o.stats()
+    assert st["nnz_L"] == st["nnz_W"]
+    b = a.matvec(np.linspace(-1.0, 1.0, a.n))
+    x, info = o.sqmr(b, tol=0.0, maxit=k)
+    assert info["iterations"] == k
+    xs = _scipy_qmr(a.to_dense(), b, k, prec=o.apply)
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+def test_p16_sqmr_finite_termination():
+    """Three distinct eigenvalues, one of them negative: the Krylov space
+    stops growing after three steps, where the QMR iterate is the solution."""
+    A, b = _sym_indefinite(30, np.repeat([2.0, -1.0, 5.0], 10), 6)
+    a = mg.dense_to_csr(A)
+    _, info2, _ = sqmr_plain(a, b, tol=1e-12, maxit=2)
+    assert not info2["converged"] and info2["rel_residual"] > 1e-3
+    x, info, _ = sqmr_plain(a, b, tol=1e-12, maxit=10)
+    assert info["converged"] and info["iterations"] == 3
+    assert np.linalg.norm(x - np.linalg.solve(A, b)) <= 1e-11 * np.linalg.norm(x)
+
+
+def test_p16_sqmr_quasi_residual_bound():
+    a, perm = _sym_elasticity(5, -0.2)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=3e-2), pre_perm=perm) == 0
+    b = a.matvec(np.ones(a.n))
+    A = a.to_dense()
+    _, info, taus = o.sqmr(b, tol=0.0, maxit=12, history=True)
+    assert len(taus) == 12
+    for k in range(1, 13):
+        x, _ = o.sqmr(b, tol=0.0, maxit=k)
+        r = np.linalg.norm(b - A @ x)
+        assert r <= np.sqrt(k + 1) * taus[k - 1] * (1 + 1e-10), k
+
+
+def test_p16_sqmr_exact_preconditioner_one_step():
+    a, perm = _sym_elasticity(4, -0.3)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=0.0), pre_perm=perm) == 0
+    b = a.matvec(np.cos(np.arange(a.n)))
+    x, info = o.sqmr(b, tol=1e-12, maxit=5)
+    assert info["converged"] and info["iterations"] == 1
+
+
+def test_p16_sqmr_stops_at_the_first_step_below_tol():
+    """The returned eta is the infinity-norm backward error of the returned
+    x (checked with the Rigal-Gaches perturbation built from it), it meets
+    the tolerance, and one step fewer does not."""
+    a, perm = _sym_elasticity(6, 0.1)
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=1e-2), pre_perm=perm) == 0
+    b = a.matvec(np.ones(a.n))
+    A = a.to_dense()
+    tol = 1e-6
+    x, info = o.sqmr(b, tol=tol)
+    k = info["iterations"]
+    assert info["converged"] and info["eta"] <= tol and k > 1
+    # (A + E) x = b + f with ||E|| = eta ||A||, ||f|| = eta ||b|| (inf-norms)
+    r = b - A @ x
+    an = np.abs(A).sum(axis=1).max()
+    den = an * np.abs(x).max() + np.abs(b).max()
+    j = int(np.argmax(np.abs(x)))
+    z = np.zeros(a.n)
+    z[j] = np.sign(x[j])
+    E = np.outer(r, z) * (an / den)
+    f = -r * (np.abs(b).max() / den)
+    assert np.abs((A + E) @ x - (b + f)).max() <= 1e-12 * np.abs(b).max()
+    assert np.isclose(np.abs(E).sum(axis=1).max(), info["eta"] * an, rtol=1e-8)
+    assert np.isclose(np.abs(f).max(), info["eta"] * np.abs(b).max(), rtol=1e-8)
+    _, info1 = o.sqmr(b, tol=tol, maxit=k - 1)
+    assert not info1["converged"] and info1["eta"] > tol
