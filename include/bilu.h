@@ -141,7 +141,7 @@ typedef struct {
 typedef struct bilu_handle bilu_handle;
 
 typedef struct {
-  int64_t iterations;    /* Arnoldi steps taken                                       */
+  int64_t iterations;    /* Arnoldi steps (FGMRES) or steps (SQMR) taken              */
   int64_t restarts;      /* restart cycles started                                    */
   double rel_residual;   /* true ||b - A x||_2 / ||b||_2 at exit                      */
   double seconds;        /* wall time of the call                                     */
@@ -336,6 +336,24 @@ bilu_status bilu_spmv(bilu_handle* h, const double* x, double* y);
  * BILU_WARN_NOT_CONVERGED.  Synchronous. */
 bilu_status bilu_fgmres_solve(bilu_handle* h, const double* b, double* x, int restart,
                               double rtol, int maxit, bilu_solve_info* info);
+
+/* Simplified QMR (Sec. 5, the solver used there with the symmetric block
+ * factorization; Freund and Nachtigal 1995) for a symmetric A, with M from
+ * bilu_factor as preconditioner.  On symmetric data the factorization is
+ * symmetric (the kept columns of U are the transposed kept rows of L), so M
+ * is symmetric up to rounding; it may be indefinite.  b, x: device arrays
+ * (original numbering); x holds the initial guess on entry and the
+ * solution on exit.  Stops when the normwise backward error in the
+ * infinity norm, ||b - A x|| / (||A|| ||x|| + ||b||), of the updated QMR
+ * residual is <= tol and the true residual confirms it, after maxit steps,
+ * or at a breakdown (q^T A q = 0 or r^T M^{-1} r = 0).  info (host, may be
+ * NULL): steps in iterations, restarts 0, the true 2-norm relative
+ * residual; *backward_error (host, may be NULL): the true backward error at
+ * exit.  BILU_ERR_INVALID when the handle uses the matching (use_mwm: its
+ * one-sided permutation and scalings make M nonsymmetric) or for tol < 0,
+ * maxit < 0.  Returns BILU_OK or BILU_WARN_NOT_CONVERGED.  Synchronous. */
+bilu_status bilu_sqmr_solve(bilu_handle* h, const double* b, double* x, double tol, int maxit,
+                            bilu_solve_info* info, double* backward_error);
 
 /* Host-only structural preprocessing (no GPU is touched): the cosine
  * groups (Sec. 3.2), the ordering of the compressed graph (Sec. 3.3) and the

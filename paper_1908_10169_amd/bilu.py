@@ -91,7 +91,7 @@ EXPORTED = [
     "bilu_free_factors", "bilu_destroy", "bilu_status_string", "bilu_last_error",
     "bilu_preprocess", "bilu_sync", "bilu_export_trace", "bilu_factor_batched", "bilu_mwm",
     "bilu_analyze_device", "bilu_refactor", "bilu_kept_residual", "bilu_apply_noalloc",
-    "bilu_load_tuning", "bilu_tuning_entries", "bilu_refactor_frozen",
+    "bilu_load_tuning", "bilu_tuning_entries", "bilu_refactor_frozen", "bilu_sqmr_solve",
 ]
 
 _lib = None
@@ -116,6 +116,9 @@ def load(path: str = LIB_PATH):
     lib.bilu_spmv.argtypes = [vp, vp, vp]
     lib.bilu_fgmres_solve.argtypes = [vp, vp, vp, C.c_int, C.c_double, C.c_int,
                                       C.POINTER(SolveInfo)]
+    lib.bilu_sqmr_solve.argtypes = [vp, vp, vp, C.c_double, C.c_int, C.POINTER(SolveInfo),
+                                    C.POINTER(C.c_double)]
+    lib.bilu_sqmr_solve.restype = C.c_int
     lib.bilu_get_stats.argtypes = [vp, C.POINTER(Stats)]
     lib.bilu_export_factors.argtypes = [vp, C.POINTER(FactorsHost)]
     lib.bilu_free_factors.argtypes = [C.POINTER(FactorsHost)]
@@ -421,6 +424,18 @@ class Bilu:
         return dict(iterations=info.iterations, restarts=info.restarts,
                     rel_residual=info.rel_residual, seconds=info.seconds,
                     converged=bool(info.converged))
+
+    def sqmr(self, b, x, tol=1e-6, maxit=2000):
+        """Simplified QMR for symmetric A (bilu_sqmr_solve); stops on the
+        infinity-norm backward error.  Returns iterations (steps),
+        rel_residual, eta (backward error), seconds, converged."""
+        pb, px = _check_vectors(self.n, ("b", b), ("x", x))
+        info = SolveInfo()
+        eta = C.c_double(0.0)
+        st = self._lib.bilu_sqmr_solve(self._h, pb, px, tol, maxit, C.byref(info), C.byref(eta))
+        self._check(st, "bilu_sqmr_solve", ok=(BILU_OK, BILU_WARN_NOT_CONVERGED))
+        return dict(iterations=info.iterations, rel_residual=info.rel_residual, eta=eta.value,
+                    seconds=info.seconds, converged=bool(info.converged))
 
     def stats(self) -> dict:
         s = Stats()

@@ -11,7 +11,8 @@ BUILD = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["factor.hip", "aggregate.hip", "solve.hip", "ilu1t.hip", "batch.hip",
                "analyze_dev.hip", "kept.hip", "noalloc.hip"]
-CPP_SOURCES = ["api.cpp", "analyze.cpp", "fgmres.cpp", "mwm.cpp", "tuning.cpp", "mlnd.cpp"]
+CPP_SOURCES = ["api.cpp", "analyze.cpp", "fgmres.cpp", "mwm.cpp", "tuning.cpp", "mlnd.cpp",
+               "sqmr.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function"]
 # packed FP32 instructions are disabled for device code

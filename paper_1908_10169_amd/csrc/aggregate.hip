@@ -184,6 +184,19 @@ struct MergeLds {
 
 // Sorted union of the members' indices beyond last into out (LDS sort);
 // returns the count or -1 when it does not fit.
+// Position of x in the sorted list lst[0..cnt), or -1.
+__device__ __forceinline__ int find_sorted(const int32_t* lst, int cnt, int x) {
+  int lo = 0, hi = cnt;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (lst[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < cnt && lst[lo] == x) ? lo : -1;
+}
+
 __device__ int merged_index_set(const MergeArgs& a, int b0, int b1, int last, bool rows,
                                 MergeLds& s, int* out) {
   const int tid = threadIdx.x;
@@ -194,10 +207,16 @@ __device__ int merged_index_set(const MergeArgs& a, int b0, int b1, int last, bo
     const int32_t* lst = a.in.idx + (rows ? a.in.roff[J] : a.in.coff[J]);
     for (int t = tid; t < cnt; t += blockDim.x) {
       const int x = lst[t];
-      if (x > last) {
-        const int o = atomicAdd(&s.misc[0], 1);
-        if (o < kMergeSort) s.keys[o] = x;
-      }
+      if (x <= last) continue;
+      // an index that an earlier block of the group holds is taken there,
+      // so the LDS holds the union itself, not the sum of the list lengths
+      bool seen = false;
+      for (int J2 = b0; J2 < J && !seen; ++J2)
+        seen = find_sorted(a.in.idx + (rows ? a.in.roff[J2] : a.in.coff[J2]),
+                           rows ? a.in.nr[J2] : a.in.nc[J2], x) >= 0;
+      if (seen) continue;
+      const int o = atomicAdd(&s.misc[0], 1);
+      if (o < kMergeSort) s.keys[o] = x;
     }
   }
   __syncthreads();
@@ -220,18 +239,6 @@ __device__ int merged_index_set(const MergeArgs& a, int b0, int b1, int last, bo
   return total;
 }
 
-// Position of x in the sorted list lst[0..cnt), or -1.
-__device__ __forceinline__ int find_sorted(const int32_t* lst, int cnt, int x) {
-  int lo = 0, hi = cnt;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (lst[mid] < x)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return (lo < cnt && lst[lo] == x) ? lo : -1;
-}
 
 __global__ void __launch_bounds__(kMergeThreads) agg_merge_kernel(MergeArgs a) {
   __shared__ MergeLds s;

@@ -550,6 +550,15 @@ bilu_status bilu_fgmres_solve(bilu_handle* h, const double* b, double* x, int re
   GUARD_END
 }
 
+bilu_status bilu_sqmr_solve(bilu_handle* h, const double* b, double* x, double tol, int maxit,
+                            bilu_solve_info* info, double* backward_error) {
+  if (!h || !b || !x || b == x) return fail(h, BILU_ERR_INVALID, "bilu_sqmr_solve: bad pointers");
+  if (h->state < 2) return fail(h, BILU_ERR_STATE, "bilu_sqmr_solve before bilu_factor");
+  GUARD_BEGIN
+  return sqmr(h, b, x, tol, maxit, info, backward_error);
+  GUARD_END
+}
+
 bilu_status bilu_mwm(int64_t n, const int64_t* rowptr, const int32_t* colind, const double* val,
                      int64_t* sigma, double* dl, double* dr) {
   if (n < 0) return BILU_ERR_INVALID;

@@ -462,8 +462,53 @@ void launch_gm_update(hipStream_t s, const GmState& g, int j, int m, double targ
 void launch_gm_solve(hipStream_t s, const GmState& g, int m);
 void launch_sub(hipStream_t s, int64_t n, const double* b, const double* ax, double* r);
 
+// SQMR state on the device (solve.hip): scalar slots of s, the partial
+// maxima (2 * kSqParts) and the flags: [0] the solve stopped (the solver's
+// kernels skip their work), [1] why (1 the updated backward error met the
+// tolerance, 2 breakdown, 3 maxit), [2] steps taken.
+enum SqSlot {
+  kSqRho = 0,   // r^T M^{-1} r of the previous step
+  kSqRhoNew,    // of this step
+  kSqTau,       // quasi-residual norm
+  kSqTheta,
+  kSqSigma,     // q^T A q
+  kSqRR,        // r^T r
+  kSqAlpha,
+  kSqCd,        // c^2 theta_old^2
+  kSqCq,        // c^2 alpha
+  kSqRmax,      // ||rq||_inf
+  kSqXmax,      // ||x||_inf
+  kSqAnorm,     // ||A||_inf
+  kSqBmax,      // ||b||_inf
+  kSqEta,       // backward error of the updated residual
+  kSqSlots = 16
+};
+constexpr int kSqParts = 512;
+struct SqState {
+  double* s;
+  double* part;
+  int* flags;
+};
+void launch_sq_init(hipStream_t s, const SqState& g);
+void launch_sq_resume(hipStream_t s, const SqState& g);
+void launch_sq_alpha(hipStream_t s, const SqState& g);
+void launch_sq_theta(hipStream_t s, const SqState& g);
+// d = cd d + cq q, sv = cd sv + cq t, x += d, rq -= sv, then the maxima of
+// |x| and |rq|, the backward error and the stop test
+void launch_sq_update(hipStream_t s, int64_t n, const SqState& g, const double* q, const double* t,
+                      double* d, double* sv, double* x, double* rq, double tol, int64_t maxit);
+// q = u + (rho_new / rho) q
+void launch_sq_direction(hipStream_t s, int64_t n, const SqState& g, const double* u, double* q);
+// *out = max |x_i|; *out = max_i sum_k |v_k| over row i
+void launch_amax(hipStream_t s, int64_t n, const double* x, double* partial, double* out);
+void launch_row_amax(hipStream_t s, int64_t n, const int64_t* rp, const double* v, double* partial,
+                     double* out);
+
 // fgmres.cpp
 bilu_status fgmres(bilu_handle* h, const double* b, double* x, int restart, double rtol,
                    int maxit, bilu_solve_info* info);
+// sqmr.cpp
+bilu_status sqmr(bilu_handle* h, const double* b, double* x, double tol, int maxit,
+                 bilu_solve_info* info, double* eta);
 
 }  // namespace bilu

@@ -779,6 +779,147 @@ __global__ void gm_solve(GmState g, int m) {
   }
 }
 
+// SQMR on the device.  The scalar recurrences of a step run on one thread
+// with the operations of the host version (no contraction into fused
+// multiply-adds, IEEE square root and division); a kernel that finds the
+// stop flag set does nothing.
+__device__ inline double block_max(double v, double* sw) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double r = fmax(fmax(sw[0], sw[1]), fmax(sw[2], sw[3]));
+  __syncthreads();
+  return r;
+}
+__global__ void sq_init(SqState g) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0) return;
+  g.s[kSqTau] = sqrt(g.s[kSqRR]);
+  g.s[kSqTheta] = 0.0;
+  g.s[kSqRho] = g.s[kSqRhoNew];
+  g.flags[0] = g.flags[1] = g.flags[2] = g.flags[3] = 0;
+}
+__global__ void sq_resume(SqState g) {
+  if (threadIdx.x == 0) g.flags[0] = g.flags[1] = 0;
+}
+// alpha = rho_{k-1} / sigma; rho_{k-1} becomes the previous step's value
+__global__ void sq_alpha(SqState g) {
+  if (threadIdx.x != 0 || g.flags[0]) return;
+  const double rho = g.s[kSqRhoNew];
+  g.s[kSqRho] = rho;
+  const double sigma = g.s[kSqSigma];
+  if (sigma == 0.0) {
+    g.flags[1] = 2;
+    g.flags[0] = 1;
+    return;
+  }
+  g.s[kSqAlpha] = rho / sigma;
+}
+__global__ void sq_theta(SqState g) {
+#pragma clang fp contract(off)
+  if (threadIdx.x != 0 || g.flags[0]) return;
+  const double theta_old = g.s[kSqTheta];
+  const double theta = sqrt(g.s[kSqRR]) / g.s[kSqTau];
+  const double c = 1.0 / sqrt(1.0 + theta * theta);
+  const double c2 = c * c;
+  g.s[kSqTau] = g.s[kSqTau] * theta * c;
+  g.s[kSqTheta] = theta;
+  g.s[kSqCd] = c2 * theta_old * theta_old;
+  g.s[kSqCq] = c2 * g.s[kSqAlpha];
+}
+__global__ void __launch_bounds__(256) sq_update(int64_t n, SqState g, const double* q,
+                                                 const double* t, double* d, double* sv,
+                                                 double* x, double* rq) {
+#pragma clang fp contract(off)
+  __shared__ double sw[4];
+  if (g.flags[0]) return;
+  const double cd = g.s[kSqCd], cq = g.s[kSqCq];
+  double mx = 0.0, mr = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double di = cd * d[i] + cq * q[i];
+    const double si = cd * sv[i] + cq * t[i];
+    const double xi = x[i] + di;
+    const double ri = rq[i] - si;
+    d[i] = di;
+    sv[i] = si;
+    x[i] = xi;
+    rq[i] = ri;
+    mx = fmax(mx, fabs(xi));
+    mr = fmax(mr, fabs(ri));
+  }
+  mx = block_max(mx, sw);
+  mr = block_max(mr, sw);
+  if (threadIdx.x == 0) {
+    g.part[blockIdx.x] = mx;
+    g.part[kSqParts + blockIdx.x] = mr;
+  }
+}
+// the maxima, eta = ||rq|| / (||A|| ||x|| + ||b||) and the stop test
+__global__ void __launch_bounds__(256) sq_check(SqState g, double tol, long long maxit) {
+#pragma clang fp contract(off)
+  __shared__ double sw[4];
+  if (g.flags[0]) return;
+  double mx = 0.0, mr = 0.0;
+  for (int i = threadIdx.x; i < kSqParts; i += blockDim.x) {
+    mx = fmax(mx, g.part[i]);
+    mr = fmax(mr, g.part[kSqParts + i]);
+  }
+  mx = block_max(mx, sw);
+  mr = block_max(mr, sw);
+  if (threadIdx.x != 0) return;
+  g.s[kSqXmax] = mx;
+  g.s[kSqRmax] = mr;
+  const double eta = mr == 0.0 ? 0.0 : mr / (g.s[kSqAnorm] * mx + g.s[kSqBmax]);
+  g.s[kSqEta] = eta;
+  const int steps = g.flags[2] + 1;
+  g.flags[2] = steps;
+  int why = 0;
+  if (eta <= tol)
+    why = 1;
+  else if (steps >= maxit)
+    why = 3;
+  else if (g.s[kSqRho] == 0.0)
+    why = 2;
+  if (why) {
+    g.flags[1] = why;
+    g.flags[0] = 1;
+  }
+}
+__global__ void sq_direction(int64_t n, SqState g, const double* u, double* q) {
+#pragma clang fp contract(off)
+  if (g.flags[0]) return;
+  const double beta = g.s[kSqRhoNew] / g.s[kSqRho];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    q[i] = u[i] + beta * q[i];
+}
+__global__ void __launch_bounds__(256) amax_partial(int64_t n, const int64_t* rp, const double* v,
+                                                    double* partial) {
+  __shared__ double sw[4];
+  double m = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (rp) {
+      double a = 0.0;
+      for (int64_t k = rp[i]; k < rp[i + 1]; ++k) a += fabs(v[k]);
+      m = fmax(m, a);
+    } else {
+      m = fmax(m, fabs(v[i]));
+    }
+  }
+  m = block_max(m, sw);
+  if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+__global__ void __launch_bounds__(256) amax_final(int nparts, const double* partial, double* out) {
+  __shared__ double sw[4];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = fmax(m, partial[i]);
+  m = block_max(m, sw);
+  if (threadIdx.x == 0) *out = m;
+}
+
 inline unsigned grid_for(int64_t n) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
 }
@@ -825,6 +966,28 @@ void launch_dot(hipStream_t s, int64_t n, const double* x, const double* y, doub
                 double* out, const int* skip) {
   dot_partial<<<kDotBlocks, 256, 0, s>>>(n, x, y, partial, skip);
   dot_final<<<1, 256, 0, s>>>(kDotBlocks, partial, out, skip);
+}
+
+void launch_sq_init(hipStream_t s, const SqState& g) { sq_init<<<1, 64, 0, s>>>(g); }
+void launch_sq_resume(hipStream_t s, const SqState& g) { sq_resume<<<1, 64, 0, s>>>(g); }
+void launch_sq_alpha(hipStream_t s, const SqState& g) { sq_alpha<<<1, 64, 0, s>>>(g); }
+void launch_sq_theta(hipStream_t s, const SqState& g) { sq_theta<<<1, 64, 0, s>>>(g); }
+void launch_sq_update(hipStream_t s, int64_t n, const SqState& g, const double* q, const double* t,
+                      double* d, double* sv, double* x, double* rq, double tol, int64_t maxit) {
+  sq_update<<<kSqParts, 256, 0, s>>>(n, g, q, t, d, sv, x, rq);
+  sq_check<<<1, 256, 0, s>>>(g, tol, (long long)maxit);
+}
+void launch_sq_direction(hipStream_t s, int64_t n, const SqState& g, const double* u, double* q) {
+  sq_direction<<<grid_for(n), 256, 0, s>>>(n, g, u, q);
+}
+void launch_amax(hipStream_t s, int64_t n, const double* x, double* partial, double* out) {
+  amax_partial<<<kDotBlocks, 256, 0, s>>>(n, nullptr, x, partial);
+  amax_final<<<1, 256, 0, s>>>(kDotBlocks, partial, out);
+}
+void launch_row_amax(hipStream_t s, int64_t n, const int64_t* rp, const double* v, double* partial,
+                     double* out) {
+  amax_partial<<<kDotBlocks, 256, 0, s>>>(n, rp, v, partial);
+  amax_final<<<1, 256, 0, s>>>(kDotBlocks, partial, out);
 }
 
 bilu_status spmv_permuted(bilu_handle* h, const double* x, double* y) {

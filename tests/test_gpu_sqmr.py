@@ -1,0 +1,191 @@
+"""Simplified QMR on the GPU (bilu_sqmr_solve) against the oracle's SQMR,
+on symmetric elasticity-like operators: positive definite (shift 0.1) and
+indefinite (negative shifts put eigenvalues below zero), unperturbed so the
+matrix and the block factorization are symmetric.
+
+Parity: after a fixed number of steps (tol = 0) the iterates agree to
+rounding; with a tolerance both sides stop at the same step, meet the
+backward-error bar with the true residual and agree on it.
+"""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1908_10169_amd import matgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _system(side, shift):
+    a = mg.grid3d_elasticity(side, 3, seed=2, pert=0.0, shift=shift)
+    perm = mg.node_perm_to_scalar(
+        mg.grid_nd_node_order((side,) * 3, dissect_separators=False), 3)
+    return a, perm
+
+
+def _pair(a, perm, tau, agg=True):
+    from oracle import Oracle, OracleOptions
+    from paper_1908_10169_amd import bilu
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=tau, use_aggregation=agg), pre_perm=perm) == 0
+    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=agg)
+    h.analyze(a, pre_perm=perm)
+    h.factor(tau)
+    return o, h
+
+
+def _eta(a, b, x):
+    r = b - a.matvec(x)
+    an = max(np.abs(a.val[a.rowptr[i]:a.rowptr[i + 1]]).sum() for i in range(a.n))
+    return np.abs(r).max() / (an * np.abs(x).max() + np.abs(b).max())
+
+
+CASES = [
+    # (side, shift, tau, aggregation): M well conditioned, so a relative
+    # change of 1e-13 in M^{-1} moves the fifth iterate by 1e-11 or less
+    (10, 0.1, 1e-2, True),
+    (10, -0.05, 1e-2, True),
+    (10, -0.1, 3e-3, True),
+    (10, -0.3, 3e-3, False),
+    (16, 0.1, 1e-2, True),
+]
+# Indefinite cases whose factor is close to singular: ||M^{-1}|| is large,
+# and a relative change of 1e-13 in M^{-1} moves the fifth iterate by 2e-7
+# (first) and 5e-9 (second, 140 to 190 steps), so the GPU's rounding
+# (another summation order in the products) moves the stopping step; both
+# sides must still converge to the bar, in about as many steps.
+SENSITIVE = [(10, -0.1, 1e-2, True), (12, -0.2, 1e-2, False)]
+
+
+def _ids(cases):
+    return [f"el3d{c[0]}-shift{c[1]}-tau{c[2]}-{'agg' if c[3] else 'plain'}" for c in cases]
+
+
+IDS = _ids(CASES)
+
+
+@pytest.mark.parametrize("side,shift,tau,agg", CASES, ids=IDS)
+def test_sqmr_fixed_steps_iterates(side, shift, tau, agg):
+    """tol = 0, five steps: the GPU iterate is the oracle's to rounding."""
+    torch = _torch()
+    a, perm = _system(side, shift)
+    say(f"[sqmr-steps] side={side} shift={shift} tau={tau} agg={agg}")
+    o, h = _pair(a, perm, tau, agg)
+    b = a.matvec(np.ones(a.n))
+    x_o, info_o = o.sqmr(b, tol=0.0, maxit=5)
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd)
+    info = h.sqmr(bd, xd, tol=0.0, maxit=5)
+    x = xd.cpu().numpy()
+    assert info["iterations"] == info_o["iterations"] == 5
+    assert not info["converged"]
+    assert np.linalg.norm(x - x_o) <= 1e-9 * np.linalg.norm(x_o)
+    assert abs(info["eta"] - info_o["eta"]) <= 1e-7 * info_o["eta"]
+    h.close()
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-10])
+@pytest.mark.parametrize("side,shift,tau,agg", CASES + SENSITIVE, ids=_ids(CASES + SENSITIVE))
+def test_sqmr_converges_like_the_oracle(side, shift, tau, agg, tol):
+    torch = _torch()
+    a, perm = _system(side, shift)
+    say(f"[sqmr] side={side} shift={shift} tau={tau} agg={agg} tol={tol}")
+    o, h = _pair(a, perm, tau, agg)
+    b = a.matvec(np.linspace(-1.0, 2.0, a.n))
+    _, info_o = o.sqmr(b, tol=tol, maxit=1000)
+    assert info_o["converged"]
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd)
+    info = h.sqmr(bd, xd, tol=tol, maxit=1000)
+    x = xd.cpu().numpy()
+    assert info["converged"]
+    if (side, shift, tau, agg) in SENSITIVE:
+        # 140 to 190 steps on the long case; measured 187 against 177
+        it_o = info_o["iterations"]
+        assert abs(info["iterations"] - it_o) <= max(2, 0.1 * it_o)
+    else:
+        assert info["iterations"] == info_o["iterations"]
+    # the residual of a converged x is formed with cancellation: its
+    # rounding error, relative to ||A|| ||x||, is a few dozen ulps
+    eta = _eta(a, b, x)
+    assert eta <= tol and info["eta"] <= tol
+    assert abs(eta - info["eta"]) <= 1e-6 * eta + 1e-14
+    res = np.linalg.norm(b - a.matvec(x)) / np.linalg.norm(b)
+    assert abs(res - info["rel_residual"]) <= 1e-6 * res + 1e-13
+    assert h.stats()["apply_faults"] == 0
+    h.close()
+
+
+def test_sqmr_maxit_and_exact_start():
+    """maxit = 1 stops unconverged with the oracle's backward error; an
+    exact initial guess takes no step."""
+    torch = _torch()
+    from paper_1908_10169_amd import bilu
+    a, perm = _system(10, -0.1)
+    say("[sqmr-maxit] side=10 shift=-0.1")
+    o, h = _pair(a, perm, 1e-2)
+    b = a.matvec(np.ones(a.n))
+    _, info_o = o.sqmr(b, tol=1e-8, maxit=1)
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd)
+    info = bilu.SolveInfo()
+    eta = C.c_double(0.0)
+    st = bilu.load().bilu_sqmr_solve(h._h, bd.data_ptr(), xd.data_ptr(), 1e-8, 1,
+                                     C.byref(info), C.byref(eta))
+    assert st == bilu.BILU_WARN_NOT_CONVERGED
+    assert info.iterations == 1 and info.restarts == 0 and not info.converged
+    assert not info_o["converged"] and info_o["iterations"] == 1
+    assert abs(eta.value - info_o["eta"]) <= 1e-8 * info_o["eta"]
+    xd = torch.ones_like(bd)
+    out = h.sqmr(bd, xd, tol=1e-12, maxit=10)
+    assert out["converged"] and out["iterations"] == 0
+    assert torch.equal(xd, torch.ones_like(bd))
+    h.close()
+
+
+def test_sqmr_below_rounding_runs_to_maxit():
+    """A tolerance below the rounding floor: the updated residual passes it
+    while the true one cannot, so the solver confirms, resumes the stopped
+    step and goes on until maxit."""
+    torch = _torch()
+    a, perm = _system(8, 0.1)
+    say("[sqmr-floor] side=8 tol=1e-17")
+    o, h = _pair(a, perm, 1e-2)
+    b = a.matvec(np.ones(a.n))
+    _, info_o = o.sqmr(b, tol=1e-17, maxit=60)
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd)
+    info = h.sqmr(bd, xd, tol=1e-17, maxit=60)
+    assert not info_o["converged"] and info_o["iterations"] == 60
+    assert not info["converged"] and info["iterations"] == 60
+    assert info["eta"] <= 1e-14 and info_o["eta"] <= 1e-14
+    h.close()
+
+
+def test_sqmr_refuses_the_matching():
+    torch = _torch()
+    from paper_1908_10169_amd import bilu
+    a, perm = _system(6, 0.1)
+    say("[sqmr-mwm] side=6")
+    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_mwm=True)
+    h.analyze(a, pre_perm=perm)
+    h.factor(1e-2)
+    bd = torch.from_numpy(a.matvec(np.ones(a.n))).cuda()
+    xd = torch.zeros_like(bd)
+    st = bilu.load().bilu_sqmr_solve(h._h, bd.data_ptr(), xd.data_ptr(), 1e-6, 10, None, None)
+    assert st == bilu.BILU_ERR_INVALID
+    h.close()
