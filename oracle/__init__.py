@@ -8,4 +8,4 @@ from .oracle import (  # noqa: F401
     Oracle, OracleOptions, cosine_groups, ilu1t_blocks, ilu1t_sets, perturb_invert,
     fgmres_plain, sqmr_plain, load,
 )
-from .mwm import apply_mwm, mwm, mwm_scalings  # noqa: F401
+from .mwm import apply_mwm, mwm, mwm_scalings, symmetric_units  # noqa: F401

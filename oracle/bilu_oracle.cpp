@@ -112,9 +112,13 @@ double sgn(double x) { return x < 0.0 ? -1.0 : 1.0; }  // Reading: sign(0) = +1
 // are left out of the grouping.
 // Readings: a left-out index becomes a group of its own; the test compares
 // against the seed row i; groups are listed in seed order, members
-// ascending; a group never exceeds max_block members.
+// ascending; a group never exceeds max_block members.  With width (the
+// rows of a compressed matrix stand for width[i] scalars) a group never
+// exceeds max_block scalars: a close row that would overflow it is passed
+// over.
 i64 cosine_groups(const Mat& a, double eps, int max_block, std::vector<i64>& perm,
-                  std::vector<i64>& gstart, i64* n_ignored) {
+                  std::vector<i64>& gstart, i64* n_ignored,
+                  const std::vector<i64>* width = nullptr) {
   const i64 n = a.n;
   Mat at = transpose(a);
   std::vector<i64> nzr(n), nzc(n);
@@ -158,7 +162,7 @@ i64 cosine_groups(const Mat& a, double eps, int max_block, std::vector<i64>& per
         }
       }
       std::sort(touched.begin(), touched.end());
-      i64 members = 1;
+      i64 members = width ? (*width)[i] : 1;
       for (i64 j : touched) {
         i64 ov = cnt[j];
         bool close;
@@ -166,10 +170,11 @@ i64 cosine_groups(const Mat& a, double eps, int max_block, std::vector<i64>& per
           close = 5 * ov * ov >= 4 * nzr[i] * nzr[j];
         else
           close = double(ov) * double(ov) >= eps * double(nzr[i]) * double(nzr[j]);
-        if (close && members < max_block) {
+        const i64 wj = width ? (*width)[j] : 1;
+        if (close && members + wj <= max_block) {
           assigned[j] = 1;
           perm.push_back(j);
-          ++members;
+          members += wj;
         }
       }
       for (i64 j : touched) cnt[j] = 0;
@@ -177,6 +182,32 @@ i64 cosine_groups(const Mat& a, double eps, int max_block, std::vector<i64>& per
     gstart.push_back((i64)perm.size());
   }
   return (i64)gstart.size() - 1;
+}
+
+// Sec. 5 (symmetric variant): the compressed companion matrix.  Units are
+// contiguous index ranges [us[u], us[u+1]) (a 1x1 or a 2x2 pivot of the
+// symmetric matching); row u of the result is the union of the unit's rows
+// with every column index replaced by its unit (pattern only).
+Mat compress_units(const Mat& a, const std::vector<i64>& us) {
+  const i64 nu = (i64)us.size() - 1;
+  std::vector<i64> unit_of(a.n);
+  for (i64 u = 0; u < nu; ++u)
+    for (i64 i = us[u]; i < us[u + 1]; ++i) unit_of[i] = u;
+  Mat c;
+  c.n = nu;
+  c.rp.assign(1, 0);
+  std::vector<i64> row;
+  for (i64 u = 0; u < nu; ++u) {
+    row.clear();
+    for (i64 i = us[u]; i < us[u + 1]; ++i)
+      for (i64 k = a.rp[i]; k < a.rp[i + 1]; ++k) row.push_back(unit_of[a.ci[k]]);
+    std::sort(row.begin(), row.end());
+    row.erase(std::unique(row.begin(), row.end()), row.end());
+    c.ci.insert(c.ci.end(), row.begin(), row.end());
+    c.rp.push_back((i64)c.ci.size());
+  }
+  c.v.assign(c.ci.size(), 0.0);
+  return c;
 }
 
 // ---------------------------------------------------------------------------
@@ -910,7 +941,18 @@ void orc_destroy(orc_handle* h) { delete h; }
 
 int orc_run(orc_handle* h, int64_t n, const int64_t* rowptr, const int32_t* colind,
             const double* val, const int64_t* pre_perm, const orc_options* opt) {
+  return orc_run_units(h, n, rowptr, colind, val, pre_perm, 0, nullptr, opt);
+}
+
+int orc_run_units(orc_handle* h, int64_t n, const int64_t* rowptr, const int32_t* colind,
+                  const double* val, const int64_t* pre_perm, int64_t nunits,
+                  const int64_t* unit_starts, const orc_options* opt) {
   if (!valid_csr(n, rowptr, colind, val)) return -1;
+  if (unit_starts) {
+    if (nunits < 1 || unit_starts[0] != 0 || unit_starts[nunits] != n) return -1;
+    for (i64 u = 0; u < nunits; ++u)
+      if (unit_starts[u + 1] <= unit_starts[u]) return -1;
+  }
   auto t0 = Clock::now();
   h->opt = *opt;
   h->n = n;
@@ -919,7 +961,28 @@ int orc_run(orc_handle* h, int64_t n, const int64_t* rowptr, const int32_t* coli
   for (i64 i = 0; i < n; ++i) pre[i] = pre_perm ? pre_perm[i] : i;
   Mat A1 = permute_sym(h->A, pre);
   std::vector<i64> q, gs;
-  if (opt->use_cosine) {
+  if (unit_starts) {
+    // Sec. 5: the groups are formed on the compressed companion matrix and
+    // expanded; without the cosine step every unit is a group
+    std::vector<i64> us(unit_starts, unit_starts + nunits + 1), width(nunits), qu, gu;
+    for (i64 u = 0; u < nunits; ++u) width[u] = us[u + 1] - us[u];
+    if (opt->use_cosine) {
+      cosine_groups(compress_units(A1, us), opt->cos_eps, opt->max_block, qu, gu,
+                    &h->n_ignored, &width);
+    } else {
+      qu.resize(nunits);
+      gu.resize(nunits + 1);
+      for (i64 u = 0; u < nunits; ++u) qu[u] = u;
+      for (i64 u = 0; u <= nunits; ++u) gu[u] = u;
+      h->n_ignored = 0;
+    }
+    gs.assign(1, 0);
+    for (size_t g = 0; g + 1 < gu.size(); ++g) {
+      for (i64 k = gu[g]; k < gu[g + 1]; ++k)
+        for (i64 i = us[qu[k]]; i < us[qu[k] + 1]; ++i) q.push_back(i);
+      gs.push_back((i64)q.size());
+    }
+  } else if (opt->use_cosine) {
     cosine_groups(A1, opt->cos_eps, opt->max_block, q, gs, &h->n_ignored);
   } else {
     q.resize(n);

@@ -65,6 +65,15 @@ void orc_destroy(orc_handle* h);
 int orc_run(orc_handle* h, int64_t n, const int64_t* rowptr,
             const int32_t* colind, const double* val, const int64_t* pre_perm,
             const orc_options* opt);
+/* orc_run with units (Sec. 5, the symmetric variant): the pre-permuted
+ * index range splits into nunits contiguous units [unit_starts[u],
+ * unit_starts[u+1]) (1x1 and 2x2 pivots of the symmetric matching) that no
+ * group splits; the cosine test runs on the compressed companion matrix
+ * (a unit's row is the union of its rows, columns replaced by their units)
+ * and a group holds at most max_block scalars.  unit_starts NULL: orc_run. */
+int orc_run_units(orc_handle* h, int64_t n, const int64_t* rowptr,
+                  const int32_t* colind, const double* val, const int64_t* pre_perm,
+                  int64_t nunits, const int64_t* unit_starts, const orc_options* opt);
 
 /* Same, but with a caller-given block partition of the permuted matrix
  * (starts[0]=0 < ... < starts[nblocks]=n); cosine and ILU(1,tau) skipped. */

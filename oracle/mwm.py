@@ -135,3 +135,64 @@ def apply_mwm(a, sigma, dl, dr):
     """Dense D_l A D_r Pi (column i of the result is column sigma(i))."""
     A = a.to_dense()
     return (dl[:, None] * A * dr[None, :])[:, sigma]
+
+
+def symmetric_units(a, sigma, dl, dr, pre=None):
+    """Sec. 5, eq. (smwm): the symmetric matching of the BILDL variant
+    (Duff and Pralet, SIAM J. Matrix Anal. Appl. 27, 2005).
+
+    For symmetric A and a maximum product matching (sigma, D_l, D_r) the
+    symmetric scaling d_i = sqrt(dl_i dr_i) keeps |(D A D)_ij| <= 1 with
+    the matched entries of magnitude one.  The matching's cycles give the
+    pivots: a fixed point a 1x1 pivot, a 2-cycle a 2x2 pivot; a longer
+    cycle c_0 -> c_1 -> ... (c_0 its smallest index, c_{k+1} = sigma(c_k))
+    is cut into consecutive pairs (c_0, c_1), (c_2, c_3), ...; an odd one
+    first leaves out as a 1x1 pivot the member with the largest |(D A D)_ii|
+    (the first in cycle order on ties) and pairs the rest from the member
+    after it on.  Readings: the two pairings of an even cycle are both made
+    of matched entries, the one starting at c_0 is taken; a pair lists its
+    smaller index first.
+
+    Returns (d, order, unit_starts): order (new -> old) lists the units in
+    the order their first index is met along pre (identity when None),
+    unit_starts their boundaries in that numbering."""
+    n = a.n
+    sigma = np.asarray(sigma, dtype=np.int64)
+    d = np.sqrt(np.asarray(dl) * np.asarray(dr))
+    diag = np.zeros(n)
+    for i in range(n):
+        diag[i] = _entry(a, i, i) * d[i] * d[i]
+    unit = np.full(n, -1, dtype=np.int64)
+    units = []
+    for s in range(n):
+        if unit[s] >= 0:
+            continue
+        cyc = [s]
+        j = int(sigma[s])
+        while j != s:
+            cyc.append(j)
+            j = int(sigma[j])
+        L = len(cyc)
+        first = len(units)
+        if L % 2 == 1:
+            best = max(range(L), key=lambda k: (diag[cyc[k]], -k))
+            units.append([cyc[best]])
+            rest = [cyc[(best + 1 + t) % L] for t in range(L - 1)]
+        else:
+            rest = cyc
+        for t in range(0, len(rest), 2):
+            units.append(sorted(rest[t:t + 2]))
+        for k in range(first, len(units)):
+            for i in units[k]:
+                unit[i] = k
+    pre = np.arange(n) if pre is None else np.asarray(pre, dtype=np.int64)
+    done = np.zeros(len(units), dtype=bool)
+    order, starts = [], [0]
+    for i in pre:
+        u = unit[i]
+        if done[u]:
+            continue
+        done[u] = True
+        order.extend(units[u])
+        starts.append(len(order))
+    return d, np.array(order, dtype=np.int64), np.array(starts, dtype=np.int64)

@@ -206,6 +206,42 @@ def grid3d_elasticity(side: int = 80, b: int = 3, seed: int = 2,
     return _assemble(dims, b, offs, blocks, valid)
 
 
+def kkt_elasticity(side: int = 8, ncon: int | None = None, seed: int = 7,
+                   shift: float = 0.1, constraints_first: bool = True):
+    """Symmetric indefinite saddle-point matrix [[K, B^T], [B, 0]]: K the
+    unperturbed elasticity-like operator (positive definite), B holds ncon
+    constraints (default: one per two nodes), each coupling the 3 unknowns
+    of a random node and of its neighbour along the first axis with
+    U(-1, 1) weights; the constraint rows store no diagonal.  Returned with
+    a node-major ordering in which each constraint sits just before (or,
+    constraints_first=False, just after) the unknowns of its node: (Csr,
+    order new->old, number of constraints)."""
+    import scipy.sparse as sp
+    K = grid3d_elasticity(side, 3, seed=2, pert=0.0, shift=shift)
+    nodes = side ** 3
+    m = nodes // 2 if ncon is None else ncon
+    rng = np.random.default_rng(np.random.PCG64(seed))
+    node = rng.integers(0, nodes, size=m)
+    x = node % side
+    nb = np.where(x + 1 < side, node + 1, node - 1)
+    cols = np.concatenate([3 * node[:, None] + np.arange(3), 3 * nb[:, None] + np.arange(3)], axis=1)
+    vals = rng.uniform(-1.0, 1.0, size=cols.shape)
+    B = sp.csr_matrix((vals.ravel(), (np.repeat(np.arange(m), 6), cols.ravel())),
+                      shape=(m, K.n))
+    Ks = sp.csr_matrix((K.val, K.colind, K.rowptr), shape=(K.n, K.n))
+    S = sp.bmat([[Ks, B.T], [B, None]], format="csr")
+    S.sort_indices()
+    a = Csr(S.shape[0], S.indptr.astype(np.int64), S.indices.astype(np.int32), S.data.copy())
+    by_node = [[] for _ in range(nodes)]
+    for r in range(m):
+        by_node[node[r]].append(K.n + r)
+    order = []
+    for v in range(nodes):
+        dofs = [3 * v, 3 * v + 1, 3 * v + 2]
+        order.extend(by_node[v] + dofs if constraints_first else dofs + by_node[v])
+    return a, np.array(order, dtype=np.int64), m
+
+
 def _set_dominant_diagonal(a: Csr, dom: float) -> None:
     rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
     diag = a.colind == rows

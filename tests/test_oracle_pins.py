@@ -914,3 +914,118 @@ def test_p16_sqmr_stops_at_the_first_step_below_tol():
     assert np.isclose(np.abs(f).max(), info["eta"] * np.abs(b).max(), rtol=1e-8)
     _, info1 = o.sqmr(b, tol=tol, maxit=k - 1)
     assert not info1["converged"] and info1["eta"] > tol
+
+
+# ---------------------------------------------------------------------------
+# P17: the symmetric matching of Sec. 5 (eq. (smwm)) and groups built on the
+# compressed companion matrix.  Pins: (a) the Duff-Pralet property: the
+# symmetrized scaling of a maximum product matching keeps every |a^_ij| <= 1
+# and the matched entries, hence the 2x2 pivots' off-diagonal entries and
+# the fixed points' diagonal entries, at magnitude one; (b) the cycle rule on
+# hand-solved 3x3 cases; (c) all-1x1 units reduce the unit pipeline to the
+# plain one; (d) no group or block splits a unit.
+# ---------------------------------------------------------------------------
+def _scaled_dense(a, d):
+    return d[:, None] * a.to_dense() * d[None, :]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_p17_symmetric_scaling_duff_pralet(seed):
+    from oracle import mwm_scalings, symmetric_units
+    rng = np.random.default_rng(seed)
+    n = 40
+    A = rng.standard_normal((n, n)) * (rng.uniform(size=(n, n)) < 0.15)
+    A = A + A.T + np.diag(np.where(rng.uniform(size=n) < 0.6, 0.0, rng.standard_normal(n)))
+    A[np.arange(n), np.arange(n)] = np.where(np.abs(np.diag(A)) > 0, np.diag(A), 0.0)
+    a = mg.dense_to_csr(A, mask=(A != 0))
+    sigma, dl, dr = mwm_scalings(a)
+    d, order, us = symmetric_units(a, sigma, dl, dr)
+    Ah = _scaled_dense(a, d)
+    assert np.abs(Ah).max() <= 1.0 + 1e-12
+    assert np.allclose(np.abs(Ah[np.arange(n), sigma]), 1.0, atol=1e-12)
+    assert np.array_equal(np.sort(order), np.arange(n))
+    w = np.diff(us)
+    assert set(w.tolist()) <= {1, 2}
+    for u in range(len(w)):
+        idx = order[us[u]:us[u + 1]]
+        if len(idx) == 2:
+            assert abs(abs(Ah[idx[0], idx[1]]) - 1.0) <= 1e-12
+            assert idx[0] < idx[1]
+        elif sigma[idx[0]] == idx[0]:
+            assert abs(abs(Ah[idx[0], idx[0]]) - 1.0) <= 1e-12
+
+
+def test_p17_odd_cycle_rule():
+    """[[0,1,1],[1,0,1],[1,1,c]]: for c = 0.5 the best transversal is a
+    3-cycle (product 1 against 0.5 for (0 1)(2)); its member with the
+    largest scaled diagonal (index 2) is the 1x1 pivot, {0, 1} the 2x2 one.
+    For c = 0 all diagonals tie and the first in cycle order (0) stays."""
+    from oracle import mwm_scalings, symmetric_units
+    for c, want_order, want_starts in ((0.5, [0, 1, 2], [0, 2, 3]), (0.0, [0, 1, 2], [0, 1, 3])):
+        A = np.array([[0.0, 1.0, 1.0], [1.0, 0.0, 1.0], [1.0, 1.0, c]])
+        a = mg.dense_to_csr(A, mask=(A != 0))
+        sigma, dl, dr = mwm_scalings(a)
+        assert sorted(sigma.tolist()) == [0, 1, 2] and all(sigma[i] != i for i in range(3))
+        _, order, us = symmetric_units(a, sigma, dl, dr)
+        assert order.tolist() == want_order and us.tolist() == want_starts, c
+
+
+def test_p17_singleton_units_reduce_to_the_plain_run():
+    w = mg.workload("cd2d_32x32_b3")
+    o1, o2 = Oracle(), Oracle()
+    opts = OracleOptions(tau=1e-2, use_aggregation=True)
+    assert o1.run(w.a, opts, pre_perm=w.perm) == 0
+    assert o2.run(w.a, opts, pre_perm=w.perm, unit_starts=np.arange(w.a.n + 1)) == 0
+    f1, f2 = o1.factors(), o2.factors()
+    assert np.array_equal(f1.perm, f2.perm) and np.array_equal(f1.starts, f2.starts)
+    assert np.array_equal(o1.group_starts(), o2.group_starts())
+    for x, y in zip(f1.L + f1.W + f1.D, f2.L + f2.W + f2.D):
+        assert np.array_equal(x, y)
+
+
+def _kkt_symmetric(side, tau, agg=True):
+    import scipy.sparse as sp
+    from oracle import mwm_scalings, symmetric_units
+    a, order, m = mg.kkt_elasticity(side)
+    sigma, dl, dr = mwm_scalings(a)
+    d, uorder, us = symmetric_units(a, sigma, dl, dr, pre=order)
+    S = sp.csr_matrix((a.val, a.colind, a.rowptr), shape=(a.n, a.n))
+    Ah = (sp.diags(d) @ S @ sp.diags(d)).tocsr()
+    Ah.sort_indices()
+    ah = mg.Csr(a.n, Ah.indptr.astype(np.int64), Ah.indices.astype(np.int32), Ah.data.copy())
+    o = Oracle()
+    assert o.run(ah, OracleOptions(tau=tau, use_aggregation=agg), pre_perm=uorder,
+                 unit_starts=us) == 0
+    return a, order, o, d, uorder, us
+
+
+def test_p17_units_stay_whole():
+    a, _, o, d, uorder, us = _kkt_symmetric(5, 1e-2)
+    perm = o.factors().perm
+    pos = np.empty(a.n, dtype=np.int64)
+    pos[perm] = np.arange(a.n)
+    for bounds in (o.group_starts(), o.factors().starts_initial, o.factors().starts):
+        block_of = np.searchsorted(bounds, np.arange(a.n), side="right") - 1
+        for u in range(len(us) - 1):
+            idx = uorder[us[u]:us[u + 1]]
+            assert len(set(block_of[pos[idx]].tolist())) == 1
+            assert np.all(np.diff(pos[idx]) == 1)   # contiguous, in unit order
+
+
+def test_p17_matching_removes_the_perturbations():
+    """Constraints ordered before their unknowns: the plain factorization
+    meets zero pivots (perturbed blocks) and SQMR needs hundreds of steps;
+    with the symmetric matching the 2x2 pivots keep every block regular."""
+    a, order, m = mg.kkt_elasticity(6)
+    b = a.matvec(np.ones(a.n))
+    o = Oracle()
+    assert o.run(a, OracleOptions(tau=1e-2), pre_perm=order) == 0
+    _, plain = o.sqmr(b, tol=1e-8, maxit=1000)
+    assert o.stats()["perturbed_blocks"] > 0
+    a, _, o2, d, _, _ = _kkt_symmetric(6, 1e-2)
+    assert o2.stats()["perturbed_blocks"] == 0
+    xh, sym = o2.sqmr(d * b, tol=1e-8, maxit=1000)
+    assert sym["converged"] and plain["converged"]
+    assert sym["iterations"] * 10 < plain["iterations"]
+    x = d * xh
+    assert np.linalg.norm(b - a.matvec(x)) <= 1e-6 * np.linalg.norm(b)
