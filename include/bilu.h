@@ -98,7 +98,15 @@ typedef struct {
                          /* slower).  All compute identical bits                     */
   int use_mwm;           /* 1: Sec. 3.1 first: the handle factors D_l A D_r Pi     */
                          /* (bilu_mwm) instead of A; apply, spmv and fgmres still   */
-                         /* act on A in its own numbering (default 0)               */
+                         /* act on A in its own numbering (default 0).              */
+                         /* 2: Sec. 5, eq. (smwm), for symmetric A: the symmetric  */
+                         /* matching; the handle factors D A D (d_i = sqrt(dl_i    */
+                         /* dr_i) from bilu_mwm) with the matching's 1x1 and 2x2   */
+                         /* pivots kept whole by the cosine groups, which form on  */
+                         /* the compressed companion matrix (a pivot's row is the  */
+                         /* union of its rows, columns replaced by their pivots),  */
+                         /* listed along pre_perm; M stays symmetric.  Both route  */
+                         /* the analysis through the host                           */
   int analyze_path;      /* 0 (default): bilu_analyze checks the entries, searches  */
                          /* the cosine candidates and builds P A P^T on the device  */
                          /* (the host keeps the limits, the greedy replay and the   */
@@ -239,7 +247,7 @@ bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr,
  * bilu_analyze): rowptr (n+1), colind and val (rowptr[n] entries each) are
  * device arrays owned by the caller, read during the call only.  rowptr is
  * copied to the host and checked there before any entry is read; the entries
- * are checked on the device.  With use_mwm = 1, analyze_path = 1 or
+ * are checked on the device.  With use_mwm = 1 or 2, analyze_path = 1 or
  * nnz >= 2^31 the matrix is copied to the host and analyzed as by
  * bilu_analyze.  The handle ends as bilu_analyze would leave it, bit for bit.
  * Same errors as bilu_analyze, plus BILU_ERR_DEVICE.  Synchronous. */
@@ -349,8 +357,10 @@ bilu_status bilu_fgmres_solve(bilu_handle* h, const double* b, double* x, int re
  * or at a breakdown (q^T A q = 0 or r^T M^{-1} r = 0).  info (host, may be
  * NULL): steps in iterations, restarts 0, the true 2-norm relative
  * residual; *backward_error (host, may be NULL): the true backward error at
- * exit.  BILU_ERR_INVALID when the handle uses the matching (use_mwm: its
- * one-sided permutation and scalings make M nonsymmetric) or for tol < 0,
+ * exit.  With use_mwm = 2 the iteration runs on D A D x^ = D b, x = D x^,
+ * and the stopping test stays on A x = b.  BILU_ERR_INVALID when the
+ * handle uses the nonsymmetric matching (use_mwm = 1: its one-sided
+ * permutation and scalings make M nonsymmetric) or for tol < 0,
  * maxit < 0.  Returns BILU_OK or BILU_WARN_NOT_CONVERGED.  Synchronous. */
 bilu_status bilu_sqmr_solve(bilu_handle* h, const double* b, double* x, double tol, int maxit,
                             bilu_solve_info* info, double* backward_error);
@@ -358,9 +368,11 @@ bilu_status bilu_sqmr_solve(bilu_handle* h, const double* b, double* x, double t
 /* Host-only structural preprocessing (no GPU is touched): the cosine
  * groups (Sec. 3.2), the ordering of the compressed graph (Sec. 3.3) and the
  * ILU(1,tau) initial partition (Sec. 3.4) that bilu_analyze + bilu_factor
- * would use.  perm (n entries, new -> old), group_starts (n+1 entries) and
- * block_starts (n+1 entries) are caller-allocated host arrays; *ngroups and
- * *nblocks receive the counts.  Same errors as bilu_analyze. */
+ * would use (with use_mwm = 2 also the symmetric matching, on D A D; the
+ * nonsymmetric matching, use_mwm = 1, is not applied here).  perm (n
+ * entries, new -> old), group_starts (n+1 entries) and block_starts (n+1
+ * entries) are caller-allocated host arrays; *ngroups and *nblocks receive
+ * the counts.  Same errors as bilu_analyze. */
 bilu_status bilu_preprocess(const bilu_options* opt, int64_t n, const int64_t* rowptr,
                             const int32_t* colind, const double* val, double tau,
                             int64_t* perm, int64_t* group_starts, int64_t* ngroups,

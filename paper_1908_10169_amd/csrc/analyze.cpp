@@ -113,10 +113,12 @@ Csr permute(const Csr& a, const std::vector<int64_t>& perm) {
 // of j (or i) has more than mu + 2 sigma entries.  The test involves only
 // the pair, so candidates are found for every seed in parallel and the
 // greedy seed order (ascending i, members ascending j, at most max_block
-// members) is replayed afterwards.
+// members) is replayed afterwards.  With width (rows of a compressed matrix
+// standing for width[i] scalars) a group holds at most max_block scalars
+// and a close row that would overflow it is passed over.
 // ---------------------------------------------------------------------------
 void cosine(const Csr& a, const Csr& at, double eps, int max_block, std::vector<int64_t>& q,
-            std::vector<int64_t>& gstart) {
+            std::vector<int64_t>& gstart, const std::vector<int64_t>* width = nullptr) {
   const int64_t n = a.n;
   std::vector<int64_t> rc(n), cc(n);
   for (int64_t i = 0; i < n; ++i) {
@@ -178,13 +180,14 @@ void cosine(const Csr& a, const Csr& at, double eps, int max_block, std::vector<
       if (taken[i]) continue;
       taken[i] = 1;
       q.push_back(i);
-      int members = 1;
+      int64_t members = width ? (*width)[i] : 1;
       for (int64_t k = cptr[t][i - lo]; k < cptr[t][i - lo + 1] && members < max_block; ++k) {
         int64_t j = clist[t][k];
-        if (taken[j]) continue;
+        const int64_t wj = width ? (*width)[j] : 1;
+        if (taken[j] || members + wj > max_block) continue;
         taken[j] = 1;
         q.push_back(j);
-        ++members;
+        members += wj;
       }
       gstart.push_back((int64_t)q.size());
     }
@@ -538,14 +541,58 @@ bilu_status analyze_host(bilu_handle* h, int64_t n, const int64_t* rowptr,
   h->alpha = 0.0;
   for (double x : a.v) h->alpha = std::max(h->alpha, std::fabs(x));
 
-  // optional caller pre-permutation
+  // optional caller pre-permutation (with the symmetric matching: the
+  // units listed along it)
   std::vector<int64_t> pre;
-  if (!pre_permutation(h, n, pre)) return fail(h, BILU_ERR_INVALID, "pre_perm is not a permutation");
-  Csr a1 = h->opt.pre_perm ? permute(a, pre) : a;
+  const bool units = !h->sym_ustart.empty();
+  if (units)
+    pre = h->sym_order;
+  else if (!pre_permutation(h, n, pre))
+    return fail(h, BILU_ERR_INVALID, "pre_perm is not a permutation");
+  Csr a1 = h->opt.pre_perm || units ? permute(a, pre) : a;
 
   // cosine groups
   std::vector<int64_t> q, gs;
-  if (h->opt.use_cosine) {
+  if (units) {
+    // Sec. 5: groups of the compressed companion matrix (a unit's row is
+    // the union of its rows, every column replaced by its unit), expanded;
+    // without the cosine step every unit is a group
+    const std::vector<int64_t>& us = h->sym_ustart;
+    const int64_t nu = (int64_t)us.size() - 1;
+    std::vector<int64_t> unit_of(n), width(nu), qu, gu;
+    for (int64_t u = 0; u < nu; ++u) {
+      width[u] = us[u + 1] - us[u];
+      for (int64_t i = us[u]; i < us[u + 1]; ++i) unit_of[i] = u;
+    }
+    if (h->opt.use_cosine) {
+      Csr c;
+      c.n = nu;
+      c.rp.assign(1, 0);
+      std::vector<int32_t> row;
+      for (int64_t u = 0; u < nu; ++u) {
+        row.clear();
+        for (int64_t i = us[u]; i < us[u + 1]; ++i)
+          for (int64_t k = a1.rp[i]; k < a1.rp[i + 1]; ++k) row.push_back((int32_t)unit_of[a1.ci[k]]);
+        std::sort(row.begin(), row.end());
+        row.erase(std::unique(row.begin(), row.end()), row.end());
+        c.ci.insert(c.ci.end(), row.begin(), row.end());
+        c.rp.push_back((int64_t)c.ci.size());
+      }
+      c.v.assign(c.ci.size(), 0.0);
+      cosine(c, transpose(c), h->opt.cos_eps, h->opt.max_block, qu, gu, &width);
+    } else {
+      qu.resize(nu);
+      std::iota(qu.begin(), qu.end(), 0);
+      gu.resize(nu + 1);
+      std::iota(gu.begin(), gu.end(), 0);
+    }
+    gs.assign(1, 0);
+    for (size_t g = 0; g + 1 < gu.size(); ++g) {
+      for (int64_t k = gu[g]; k < gu[g + 1]; ++k)
+        for (int64_t i = us[qu[k]]; i < us[qu[k] + 1]; ++i) q.push_back(i);
+      gs.push_back((int64_t)q.size());
+    }
+  } else if (h->opt.use_cosine) {
     Csr a1t = transpose(a1);
     cosine(a1, a1t, h->opt.cos_eps, h->opt.max_block, q, gs);
   } else {

@@ -218,7 +218,7 @@ bilu_status bilu_create(bilu_handle** out, const bilu_options* opt, void* stream
       h->opt.cos_eps > 1.0 || h->opt.ordering < 0 || h->opt.ordering > 2 ||
       h->opt.update_precision < 0 || h->opt.update_precision > 2 || h->opt.drop_norm < 0 ||
       h->opt.drop_norm > 1 || h->opt.factor_path < 0 || h->opt.factor_path > 2 ||
-      h->opt.apply_path < 0 || h->opt.apply_path > 2 || h->opt.use_mwm < 0 || h->opt.use_mwm > 1 ||
+      h->opt.apply_path < 0 || h->opt.apply_path > 2 || h->opt.use_mwm < 0 || h->opt.use_mwm > 2 ||
       h->opt.analyze_path < 0 || h->opt.analyze_path > 1 || h->opt.apply_precision < 0 ||
       h->opt.apply_precision > 1 || h->opt.update_mfma < 0 || h->opt.update_mfma > 1 ||
       h->opt.deterministic < 0 || h->opt.deterministic > 1 || h->opt.workers_per_cu < 0 ||
@@ -238,6 +238,35 @@ void bilu_destroy(bilu_handle* h) {
   delete h;
 }
 
+namespace {
+// use_mwm = 2 (Sec. 5): the symmetric matching.  The analyzed matrix is
+// D A D (A's pattern, values in sv); its 1x1 and 2x2 pivot units, listed
+// along the caller's pre_perm, go to h->sym_order / h->sym_ustart.
+bilu_status sym_prepare(bilu_handle* h, int64_t n, const int64_t* rowptr, const int32_t* colind,
+                        const double* val, std::vector<double>& d, std::vector<double>& sv) {
+  if (n <= 0 || !rowptr || !colind || !val || rowptr[0] != 0)
+    return fail(h, BILU_ERR_INVALID, "null CSR or n<=0");
+  for (int64_t i = 0; i < n; ++i)
+    if (rowptr[i + 1] < rowptr[i]) return fail(h, BILU_ERR_INVALID, "rowptr not monotone");
+  if (h->opt.pre_perm) {
+    std::vector<char> seen(n, 0);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t p = h->opt.pre_perm[i];
+      if (p < 0 || p >= n || seen[p]) return fail(h, BILU_ERR_INVALID, "pre_perm is not a permutation");
+      seen[p] = 1;
+    }
+  }
+  std::string why;
+  const bilu_status ms = sym_matching_host(n, rowptr, colind, val, h->opt.pre_perm, d,
+                                           h->sym_order, h->sym_ustart, &why);
+  if (ms != BILU_OK) return fail(h, ms, "symmetric matching: " + why);
+  sv.resize(rowptr[n]);
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) sv[k] = (d[i] * val[k]) * d[colind[k]];
+  return BILU_OK;
+}
+}  // namespace
+
 bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr, const int32_t* colind,
                          const double* val) {
   if (!h) return BILU_ERR_INVALID;
@@ -246,13 +275,22 @@ bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr, const
   h->state = 0;
   h->ilu_static = false;
   h->mwm = false;
-  // Sec. 3.1 (use_mwm): analyze D_l A D_r Pi instead of A
+  h->mwm_sym = false;
+  h->sym_order.clear();
+  h->sym_ustart.clear();
+  // Sec. 3.1 (use_mwm = 1): analyze D_l A D_r Pi instead of A; Sec. 5
+  // (use_mwm = 2): D A D with the symmetric matching's pivot units
   std::vector<int64_t> sigma;
   std::vector<double> dl, dr;
   std::vector<int64_t> m_rp;
   std::vector<int32_t> m_ci;
   std::vector<double> m_v;
-  if (h->opt.use_mwm) {
+  std::vector<double> sym_d;
+  if (h->opt.use_mwm == 2) {
+    const bilu_status ss = sym_prepare(h, n, rowptr, colind, val, sym_d, m_v);
+    if (ss != BILU_OK) return ss;
+    val = m_v.data();
+  } else if (h->opt.use_mwm) {
     if (n <= 0 || !rowptr || !colind || !val || rowptr[0] != 0)
       return fail(h, BILU_ERR_INVALID, "null CSR or n<=0");
     for (int64_t i = 0; i < n; ++i)
@@ -294,7 +332,8 @@ bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr, const
     hipError_t e_ = (x);                               \
     if (e_ != hipSuccess) return hip_check(h, e_, #x); \
   } while (0)
-  if (h->opt.analyze_path == 0 && n > 0 && n <= INT32_MAX - 1 && rowptr && colind && val &&
+  if (h->opt.analyze_path == 0 && h->opt.use_mwm != 2 && n > 0 && n <= INT32_MAX - 1 && rowptr &&
+      colind && val &&
       rowptr[0] == 0 && rowptr_monotone(n, rowptr) && rowptr[n] <= INT32_MAX) {
     // the matrix goes to HBM as it is; checks, cosine search and P A P^T there
     const int64_t nnz = rowptr[n];
@@ -343,16 +382,17 @@ bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr, const
   }
   if (h->opt.use_mwm) {
     // boundary of the scaled system: rows by perm with D_l, columns by
-    // sigma o perm with D_r
+    // sigma o perm with D_r (symmetric matching: both by perm with D)
+    const bool sym = h->opt.use_mwm == 2;
     std::vector<int32_t> pc(n);
     std::vector<double> sl(n), sli(n), sr(n), sri(n);
     for (int64_t i = 0; i < n; ++i) {
-      const int64_t p = h->perm[i], c = sigma[p];
+      const int64_t p = h->perm[i], c = sym ? p : sigma[p];
       pc[i] = (int32_t)c;
-      sl[i] = dl[p];
-      sli[i] = 1.0 / dl[p];
-      sr[i] = dr[c];
-      sri[i] = 1.0 / dr[c];
+      sl[i] = sym ? sym_d[p] : dl[p];
+      sli[i] = 1.0 / sl[i];
+      sr[i] = sym ? sym_d[c] : dr[c];
+      sri[i] = 1.0 / sr[i];
     }
     CK(h->d_perm_col.alloc(n));
     CK(h->d_sl.alloc(n));
@@ -365,6 +405,7 @@ bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr, const
     CK(hipMemcpyAsync(h->d_sr.p, sr.data(), n * 8, hipMemcpyHostToDevice, st));
     CK(hipMemcpyAsync(h->d_sr_inv.p, sri.data(), n * 8, hipMemcpyHostToDevice, st));
     h->mwm = true;
+    h->mwm_sym = sym;
   }
   CK(hipStreamSynchronize(st));
 #undef CK
@@ -589,7 +630,15 @@ bilu_status bilu_preprocess(const bilu_options* opt, int64_t n, const int64_t* r
   else
     bilu_default_options(&h->opt);
   if (h->opt.max_block < 1 || h->opt.max_block > kMaxWidth) return BILU_ERR_INVALID;
+  if (h->opt.use_mwm < 0 || h->opt.use_mwm > 2) return BILU_ERR_INVALID;
   GUARD_BEGIN
+  std::vector<double> sym_d, sym_v;
+  if (h->opt.use_mwm == 2) {
+    // the symmetric matching's units and scaled values, as bilu_analyze
+    const bilu_status ss = sym_prepare(h, n, rowptr, colind, val, sym_d, sym_v);
+    if (ss != BILU_OK) return ss;
+    val = sym_v.data();
+  }
   bilu_status s = analyze_host(h, n, rowptr, colind, val);
   if (s != BILU_OK) return s;
   std::copy(h->perm.begin(), h->perm.end(), perm);

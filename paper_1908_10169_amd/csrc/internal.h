@@ -289,6 +289,11 @@ struct bilu_handle {
   // the boundary by row (perm, sl / sl_inv) or by column (perm_col = sigma o
   // perm, sr / sr_inv); without it perm_col = perm and no scaling.
   bool mwm = false;
+  // use_mwm = 2 (Sec. 5): symmetric scaling D on both sides, no column
+  // permutation; sym_order (new -> old) lists the 1x1 and 2x2 pivot units
+  // that the cosine groups keep whole, sym_ustart their boundaries
+  bool mwm_sym = false;
+  std::vector<int64_t> sym_order, sym_ustart;
   bilu::DevArray<int32_t> d_perm_col;
   bilu::DevArray<double> d_sl, d_sl_inv, d_sr, d_sr_inv;
   const int32_t* perm_col() const { return mwm ? d_perm_col.p : d_perm.p; }
@@ -419,6 +424,13 @@ bilu_status kept_residual(bilu_handle* h, double* out);
 // failure.
 bilu_status mwm_host(int64_t n, const int64_t* rp, const int32_t* ci, const double* val,
                      int64_t* sigma, double* dl, double* dr, std::string* why);
+// Sec. 5 symmetric matching (mwm.cpp): the symmetrized scaling d, the 1x1
+// and 2x2 pivot units in the order their first index is met along pre
+// (NULL: identity), order new -> old, unit boundaries ustart.
+bilu_status sym_matching_host(int64_t n, const int64_t* rp, const int32_t* ci,
+                              const double* val, const int64_t* pre, std::vector<double>& d,
+                              std::vector<int64_t>& order, std::vector<int64_t>& ustart,
+                              std::string* why);
 // timed: record HIP events around it when collect_timing is on (events may
 // be created, so allocation-free callers pass false)
 bilu_status apply_permuted(bilu_handle* h, const double* x, double* y, double* t,
@@ -494,14 +506,19 @@ void launch_sq_resume(hipStream_t s, const SqState& g);
 void launch_sq_alpha(hipStream_t s, const SqState& g);
 void launch_sq_theta(hipStream_t s, const SqState& g);
 // d = cd d + cq q, sv = cd sv + cq t, x += d, rq -= sv, then the maxima of
-// |x| and |rq|, the backward error and the stop test
+// |x .* xs| and |rq .* rs| (scales NULL: 1), the backward error and the
+// stop test
 void launch_sq_update(hipStream_t s, int64_t n, const SqState& g, const double* q, const double* t,
-                      double* d, double* sv, double* x, double* rq, double tol, int64_t maxit);
+                      double* d, double* sv, double* x, double* rq, const double* xs,
+                      const double* rs, double tol, int64_t maxit);
 // q = u + (rho_new / rho) q
 void launch_sq_direction(hipStream_t s, int64_t n, const SqState& g, const double* u, double* q);
-// *out = max |x_i|; *out = max_i sum_k |v_k| over row i
-void launch_amax(hipStream_t s, int64_t n, const double* x, double* partial, double* out);
-void launch_row_amax(hipStream_t s, int64_t n, const int64_t* rp, const double* v, double* partial,
+// *out = max_i |x_i w_i| (w NULL: 1); *out = max_i rs_i sum_k |v_k| cs_{ci_k}
+// over the rows of a CSR matrix (scales NULL: 1)
+void launch_amax(hipStream_t s, int64_t n, const double* x, const double* w, double* partial,
+                 double* out);
+void launch_row_amax(hipStream_t s, int64_t n, const int64_t* rp, const int32_t* ci,
+                     const double* v, const double* rs, const double* cs, double* partial,
                      double* out);
 
 // fgmres.cpp

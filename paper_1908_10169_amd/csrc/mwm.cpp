@@ -150,4 +150,74 @@ bilu_status mwm_host(int64_t n, const int64_t* rp, const int32_t* ci, const doub
   return BILU_OK;
 }
 
+// Sec. 5, eq. (smwm): the symmetric matching of the symmetric variant
+// (Duff and Pralet, SIAM J. Matrix Anal. Appl. 27, 2005).  For symmetric A
+// the symmetrized scaling d_i = sqrt(dl_i dr_i) of a maximum product
+// matching keeps |d_i a_ij d_j| <= 1 with the matched entries at magnitude
+// one.  The matching's cycles give the pivots: a fixed point a 1x1 pivot, a
+// 2-cycle a 2x2 pivot; a longer cycle c_0 -> c_1 -> ... (c_0 its smallest
+// index) is cut into consecutive pairs (c_0, c_1), (c_2, c_3), ...; an odd
+// cycle first leaves out as a 1x1 pivot its member with the largest scaled
+// diagonal |a_ii| d_i d_i (the first in cycle order on ties) and pairs the
+// rest from the member after it on.  A pair lists its smaller index first.
+// The units are listed in the order their first index is met along pre
+// (identity when NULL): order (new -> old) and their boundaries ustart.
+bilu_status sym_matching_host(int64_t n, const int64_t* rp, const int32_t* ci,
+                              const double* val, const int64_t* pre, std::vector<double>& d,
+                              std::vector<int64_t>& order, std::vector<int64_t>& ustart,
+                              std::string* why) {
+  std::vector<int64_t> sigma(n);
+  std::vector<double> dl(n), dr(n);
+  const bilu_status ms = mwm_host(n, rp, ci, val, sigma.data(), dl.data(), dr.data(), why);
+  if (ms != BILU_OK) return ms;
+  d.resize(n);
+  std::vector<double> diag(n, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    d[i] = std::sqrt(dl[i] * dr[i]);
+    for (int64_t m = rp[i]; m < rp[i + 1]; ++m)
+      if (ci[m] == i) diag[i] = std::fabs(val[m]);
+  }
+  for (int64_t i = 0; i < n; ++i) diag[i] = diag[i] * d[i] * d[i];
+  // units: unit_first[u], unit_second[u] (-1 for a 1x1 pivot)
+  std::vector<int64_t> unit(n, -1), ufirst, usecond, cyc, rest;
+  for (int64_t s0 = 0; s0 < n; ++s0) {
+    if (unit[s0] >= 0) continue;
+    cyc.assign(1, s0);
+    for (int64_t j = sigma[s0]; j != s0; j = sigma[j]) cyc.push_back(j);
+    const int64_t L = (int64_t)cyc.size();
+    rest.clear();
+    if (L % 2 == 1) {
+      int64_t best = 0;
+      for (int64_t k = 1; k < L; ++k)
+        if (diag[cyc[k]] > diag[cyc[best]]) best = k;
+      unit[cyc[best]] = (int64_t)ufirst.size();
+      ufirst.push_back(cyc[best]);
+      usecond.push_back(-1);
+      for (int64_t t = 1; t < L; ++t) rest.push_back(cyc[(best + t) % L]);
+    } else {
+      rest = cyc;
+    }
+    for (size_t t = 0; t + 1 < rest.size(); t += 2) {
+      const int64_t a = std::min(rest[t], rest[t + 1]), b = std::max(rest[t], rest[t + 1]);
+      unit[a] = unit[b] = (int64_t)ufirst.size();
+      ufirst.push_back(a);
+      usecond.push_back(b);
+    }
+  }
+  std::vector<char> done(ufirst.size(), 0);
+  order.clear();
+  order.reserve(n);
+  ustart.assign(1, 0);
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t i = pre ? pre[k] : k;
+    const int64_t u = unit[i];
+    if (done[u]) continue;
+    done[u] = 1;
+    order.push_back(ufirst[u]);
+    if (usecond[u] >= 0) order.push_back(usecond[u]);
+    ustart.push_back((int64_t)order.size());
+  }
+  return BILU_OK;
+}
+
 }  // namespace bilu

@@ -830,7 +830,8 @@ __global__ void sq_theta(SqState g) {
 }
 __global__ void __launch_bounds__(256) sq_update(int64_t n, SqState g, const double* q,
                                                  const double* t, double* d, double* sv,
-                                                 double* x, double* rq) {
+                                                 double* x, double* rq, const double* xs,
+                                                 const double* rs) {
 #pragma clang fp contract(off)
   __shared__ double sw[4];
   if (g.flags[0]) return;
@@ -846,8 +847,8 @@ __global__ void __launch_bounds__(256) sq_update(int64_t n, SqState g, const dou
     sv[i] = si;
     x[i] = xi;
     rq[i] = ri;
-    mx = fmax(mx, fabs(xi));
-    mr = fmax(mr, fabs(ri));
+    mx = fmax(mx, fabs(xs ? xi * xs[i] : xi));
+    mr = fmax(mr, fabs(rs ? ri * rs[i] : ri));
   }
   mx = block_max(mx, sw);
   mr = block_max(mr, sw);
@@ -895,7 +896,11 @@ __global__ void sq_direction(int64_t n, SqState g, const double* u, double* q) {
        i += (int64_t)gridDim.x * blockDim.x)
     q[i] = u[i] + beta * q[i];
 }
-__global__ void __launch_bounds__(256) amax_partial(int64_t n, const int64_t* rp, const double* v,
+// max_i |v_i w_i| (rp NULL), or the largest row sum max_i rs_i sum_k
+// |v_k| cs_{ci_k} of a CSR matrix (scales NULL: 1)
+__global__ void __launch_bounds__(256) amax_partial(int64_t n, const int64_t* rp,
+                                                    const int32_t* ci, const double* v,
+                                                    const double* rs, const double* cs,
                                                     double* partial) {
   __shared__ double sw[4];
   double m = 0.0;
@@ -903,10 +908,10 @@ __global__ void __launch_bounds__(256) amax_partial(int64_t n, const int64_t* rp
        i += (int64_t)gridDim.x * blockDim.x) {
     if (rp) {
       double a = 0.0;
-      for (int64_t k = rp[i]; k < rp[i + 1]; ++k) a += fabs(v[k]);
-      m = fmax(m, a);
+      for (int64_t k = rp[i]; k < rp[i + 1]; ++k) a += fabs(cs ? v[k] * cs[ci[k]] : v[k]);
+      m = fmax(m, rs ? a * rs[i] : a);
     } else {
-      m = fmax(m, fabs(v[i]));
+      m = fmax(m, fabs(rs ? v[i] * rs[i] : v[i]));
     }
   }
   m = block_max(m, sw);
@@ -973,20 +978,23 @@ void launch_sq_resume(hipStream_t s, const SqState& g) { sq_resume<<<1, 64, 0, s
 void launch_sq_alpha(hipStream_t s, const SqState& g) { sq_alpha<<<1, 64, 0, s>>>(g); }
 void launch_sq_theta(hipStream_t s, const SqState& g) { sq_theta<<<1, 64, 0, s>>>(g); }
 void launch_sq_update(hipStream_t s, int64_t n, const SqState& g, const double* q, const double* t,
-                      double* d, double* sv, double* x, double* rq, double tol, int64_t maxit) {
-  sq_update<<<kSqParts, 256, 0, s>>>(n, g, q, t, d, sv, x, rq);
+                      double* d, double* sv, double* x, double* rq, const double* xs,
+                      const double* rs, double tol, int64_t maxit) {
+  sq_update<<<kSqParts, 256, 0, s>>>(n, g, q, t, d, sv, x, rq, xs, rs);
   sq_check<<<1, 256, 0, s>>>(g, tol, (long long)maxit);
 }
 void launch_sq_direction(hipStream_t s, int64_t n, const SqState& g, const double* u, double* q) {
   sq_direction<<<grid_for(n), 256, 0, s>>>(n, g, u, q);
 }
-void launch_amax(hipStream_t s, int64_t n, const double* x, double* partial, double* out) {
-  amax_partial<<<kDotBlocks, 256, 0, s>>>(n, nullptr, x, partial);
+void launch_amax(hipStream_t s, int64_t n, const double* x, const double* w, double* partial,
+                 double* out) {
+  amax_partial<<<kDotBlocks, 256, 0, s>>>(n, nullptr, nullptr, x, w, nullptr, partial);
   amax_final<<<1, 256, 0, s>>>(kDotBlocks, partial, out);
 }
-void launch_row_amax(hipStream_t s, int64_t n, const int64_t* rp, const double* v, double* partial,
+void launch_row_amax(hipStream_t s, int64_t n, const int64_t* rp, const int32_t* ci,
+                     const double* v, const double* rs, const double* cs, double* partial,
                      double* out) {
-  amax_partial<<<kDotBlocks, 256, 0, s>>>(n, rp, v, partial);
+  amax_partial<<<kDotBlocks, 256, 0, s>>>(n, rp, ci, v, rs, cs, partial);
   amax_final<<<1, 256, 0, s>>>(kDotBlocks, partial, out);
 }
 

@@ -8,11 +8,15 @@
 // permuted numbering (permutations preserve inner products and maximum
 // norms).
 //
-// Stopping test: the normwise backward error in the infinity norm,
-// eta = ||b - A x|| / (||A|| ||x|| + ||b||), evaluated on the QMR residual
-// that the iteration updates (rq -= A d, with A d kept by its own
+// With the symmetric matching (use_mwm = 2) the iteration runs on
+// D A D x^ = D b (x = D x^); M stays symmetric.
+//
+// Stopping test: the normwise backward error of A x = b in the infinity
+// norm, eta = ||b - A x|| / (||A|| ||x|| + ||b||), evaluated on the QMR
+// residual that the iteration updates (rq -= A d, with A d kept by its own
 // recurrence) and confirmed with the true residual; a step whose update
-// met the tolerance but whose true residual does not is resumed.
+// met the tolerance but whose true residual does not is resumed.  Under
+// the scaling, x = D x^ and b - A x = D^{-1} (D b - D A D x^).
 //
 // As in the FGMRES driver the host queues step k + 1 before it reads
 // whether step k - 1 stopped (flags copied to pinned memory); the kernels of
@@ -45,10 +49,10 @@ bilu_status sqmr(bilu_handle* h, const double* b_orig, double* x_orig, double to
   using clk = std::chrono::steady_clock;
   const auto t_start = clk::now();
   if (maxit < 0 || !(tol >= 0)) return fail(h, BILU_ERR_INVALID, "bad solver parameters");
-  if (h->mwm)
+  if (h->mwm && !h->mwm_sym)
     return fail(h, BILU_ERR_INVALID,
                 "SQMR needs a symmetric preconditioner; the matching's one-sided permutation "
-                "and scalings make M nonsymmetric");
+                "and scalings make M nonsymmetric (use_mwm = 2 keeps it symmetric)");
   const int64_t n = h->n;
   hipStream_t st = h->stream;
   // workspace: b, x, r, rq, q, t, u, d, sv, apply temporary
@@ -84,21 +88,31 @@ bilu_status sqmr(bilu_handle* h, const double* b_orig, double* x_orig, double to
     return hipMemcpyAsync(hs, g.s, sizeof(hs), hipMemcpyDeviceToHost, st) == hipSuccess &&
            hipStreamSynchronize(st) == hipSuccess;
   };
-  // true residual b - A x into t, its maximum and 2-norm, and ||x||
+  // the scales between the iterated and A's own vectors (NULL: none)
+  const double* rscale = h->sl_inv();  // b - A x = rscale .* (b^ - A^ x^)
+  const double* xscale = h->sr();      // x = xscale .* x^
+  // true residual b^ - A^ x^ into t; the maxima of A's residual and of x,
+  // and the 2-norm of A's residual (formed in tmp, free outside applies)
   auto true_residual = [&]() {
     h->run_skip = nullptr;
     spmv_permuted(h, x, t);
     launch_sub(st, n, b, t, t);
-    launch_amax(st, n, t, red, g.s + kSqRmax);
-    launch_amax(st, n, x, red, g.s + kSqXmax);
-    launch_dot(st, n, t, t, red, g.s + kSqRR);
+    const double* ro = t;
+    if (rscale) {
+      launch_mul(st, n, rscale, t, tmp);
+      ro = tmp;
+    }
+    launch_amax(st, n, ro, nullptr, red, g.s + kSqRmax);
+    launch_amax(st, n, x, xscale, red, g.s + kSqXmax);
+    launch_dot(st, n, ro, ro, red, g.s + kSqRR);
   };
 
-  launch_gather(st, n, h->d_perm.p, nullptr, b_orig, b);
-  launch_gather(st, n, h->d_perm.p, nullptr, x_orig, x);
-  launch_row_amax(st, n, h->d_rp.p, h->d_rv.p, red, g.s + kSqAnorm);
-  launch_amax(st, n, b, red, g.s + kSqBmax);
-  launch_dot(st, n, b, b, red, g.s + kSqEta);  // ||b||^2, read once below
+  launch_gather(st, n, h->d_perm.p, h->sl(), b_orig, b);
+  launch_gather(st, n, h->perm_col(), h->sr_inv(), x_orig, x);
+  launch_row_amax(st, n, h->d_rp.p, h->d_ci.p, h->d_rv.p, h->sl_inv(), h->sr_inv(), red,
+                  g.s + kSqAnorm);
+  launch_amax(st, n, b_orig, nullptr, red, g.s + kSqBmax);
+  launch_dot(st, n, b_orig, b_orig, red, g.s + kSqEta);  // ||b||^2, read once below
   true_residual();
   if (!read_scalars()) return device_error();
   const double anorm = hs[kSqAnorm], bmax = hs[kSqBmax], bnorm = std::sqrt(hs[kSqEta]);
@@ -107,7 +121,7 @@ bilu_status sqmr(bilu_handle* h, const double* b_orig, double* x_orig, double to
   int64_t steps = 0;
   int converged = eta <= tol ? 1 : 0;
   if (!converged && maxit > 0) {
-    // r = rq = b - A x (in t), q = M^{-1} r, rho = r^T q, tau = ||r||
+    // r = rq = b^ - A^ x^ (in t), q = M^{-1} r, rho = r^T q, tau = ||r||
     if (hipMemcpyAsync(r, t, n * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess ||
         hipMemcpyAsync(rq, t, n * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess ||
         hipMemsetAsync(d, 0, n * sizeof(double), st) != hipSuccess ||
@@ -116,6 +130,7 @@ bilu_status sqmr(bilu_handle* h, const double* b_orig, double* x_orig, double to
     bilu_status s0 = apply_permuted(h, r, q, tmp);
     if (s0 != BILU_OK) return s0;
     launch_dot(st, n, r, q, red, g.s + kSqRhoNew);
+    launch_dot(st, n, r, r, red, g.s + kSqRR);  // the iterated residual's norm
     launch_sq_init(st, g);
     // the second half of a step: u = M^{-1} r, rho_new = r^T u, q = u + beta q
     auto tail = [&]() -> bilu_status {
@@ -140,7 +155,7 @@ bilu_status sqmr(bilu_handle* h, const double* b_orig, double* x_orig, double to
         launch_axpy(st, n, g.s + kSqAlpha, -1.0, t, r, flags);
         launch_dot(st, n, r, r, red, g.s + kSqRR, flags);
         launch_sq_theta(st, g);
-        launch_sq_update(st, n, g, q, t, d, sv, x, rq, tol, maxit);
+        launch_sq_update(st, n, g, q, t, d, sv, x, rq, xscale, rscale, tol, maxit);
         bilu_status s = tail();
         if (s != BILU_OK) return s;
         int* hf = hflags + 4 * (j & 1);
@@ -174,7 +189,7 @@ bilu_status sqmr(bilu_handle* h, const double* b_orig, double* x_orig, double to
     resid2 = hs[kSqRR];
     eta = backward_error(hs[kSqRmax], anorm, hs[kSqXmax], bmax);
   }
-  launch_scatter(st, n, h->d_perm.p, nullptr, x, x_orig);
+  launch_scatter(st, n, h->perm_col(), h->sr(), x, x_orig);
   if (hipStreamSynchronize(st) != hipSuccess) return device_error();
   int64_t faults = 0;
   if (apply_faults(h, &faults) != BILU_OK) return BILU_ERR_DEVICE;

@@ -231,3 +231,46 @@ def test_multilevel_nd_beats_level_structure_on_an_irregular_mesh():
         fills[name] = _symbolic_fill(a, perm)
     assert fills["multilevel"] < 0.85 * fills["level"], fills
     assert fills["level"] < 0.3 * fills["natural"], fills
+
+
+def _sym_cases():
+    rng = np.random.default_rng(12)
+    n = 41   # odd, zero diagonal: the matching must hold an odd cycle
+    A = rng.standard_normal((n, n)) * (rng.uniform(size=(n, n)) < 0.12)
+    A = np.triu(A, 1)
+    A = A + A.T
+    A[np.arange(n - 1), np.arange(1, n)] = A[np.arange(1, n), np.arange(n - 1)] = 0.7
+    zd = mg.dense_to_csr(A)
+    kkt5 = mg.kkt_elasticity(5)
+    kkt6 = mg.kkt_elasticity(6, constraints_first=False)
+    return {"zero_diagonal_41": (zd, None), "kkt5": (kkt5[0], kkt5[1]),
+            "kkt6_after": (kkt6[0], kkt6[1])}
+
+
+@pytest.mark.parametrize("name", ["zero_diagonal_41", "kkt5", "kkt6_after"])
+@pytest.mark.parametrize("max_block,use_cosine", [(128, True), (5, True), (128, False)])
+def test_symmetric_matching_preprocess_matches_oracle(name, max_block, use_cosine):
+    """use_mwm = 2: the library's symmetric matching, unit-aware cosine
+    groups and ILU(1,tau) partition equal the oracle's on D A D, with the
+    library's matching (sigma, D_l, D_r from bilu_mwm; the duals are not
+    unique) handed to the oracle's pivot rule."""
+    from oracle import Oracle, OracleOptions, symmetric_units
+    a, order = _sym_cases()[name]
+    tau = 1e-2
+    sigma, dl, dr = bilu.mwm(a)
+    d, uorder, us = symmetric_units(a, sigma, dl, dr, pre=order)
+    # D A D on A's own pattern (stored zeros stay)
+    rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
+    ah = mg.Csr(a.n, a.rowptr, a.colind, (d[rows] * a.val) * d[a.colind])
+    o = Oracle()
+    assert o.run(ah, OracleOptions(tau=tau, use_aggregation=False, max_block=max_block,
+                                   use_cosine=use_cosine),
+                 pre_perm=uorder, unit_starts=us) == 0
+    perm, gs, bs = bilu.preprocess(a, tau, pre_perm=order, ordering=bilu.ORDER_NATURAL,
+                                   use_mwm=2, max_block=max_block, use_cosine=use_cosine)
+    assert np.array_equal(perm, o.perm())
+    assert np.array_equal(gs, o.group_starts())
+    assert np.array_equal(bs, o.starts_initial())
+    if name == "zero_diagonal_41":
+        assert (np.diff(us) == 1).sum() >= 1   # an odd cycle left a 1x1 pivot
+    assert np.diff(gs).max() <= max_block
