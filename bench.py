@@ -13,7 +13,12 @@ forms (FP32 and BF16 Schur updates with L and W stored in that precision;
 pivot blocks, drop test and FGMRES in FP64).  Each form reports its factor
 and solve times, iterations, the true final residual and the kept-pattern
 residual ||(L S U - A)_Omega||/||A||, and the mixed/FP64 time ratio.  The
-64^3 x 4 convection-diffusion workload in FP64 is a second figure.
+form f64_atomic is FP64 with the Schur terms subtracted by atomic adds
+(deterministic = 0): faster, but the summation order, and so the last bits,
+vary from run to run; the line's value stays the reproducible FP64 form.
+The 64^3 x 4 convection-diffusion workload in FP64 is a second figure, and
+the symmetric variant (symmetric matching, SQMR) on a saddle-point matrix a
+third.
 
 Prints one JSON line.  Extra fields: the roofline of the dominant kernel
 (device time from HIP events on the library's stream), the Schur-update
@@ -35,7 +40,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 (vector and matrix)
 FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector
 AGGREGATION_DEFAULT = True  # the full method: cosine + ILU(1,tau) blocking + progressive aggregation
-FORM_PREC = {"f64": 0, "f32": 1, "bf16": 2}
+FORM_PREC = {"f64": 0, "f32": 1, "bf16": 2, "f64_atomic": 0}
+FORM_DET = {"f64_atomic": 0}   # forms that override --deterministic
 
 
 def parse():
@@ -44,7 +50,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="el3d_80_b3")
-    p.add_argument("--forms", default="f64,f32,bf16",
+    p.add_argument("--forms", default="f64,f32,bf16,f64_atomic",
                    help="comma-separated update precisions; the first is the line's value")
     p.add_argument("--second-workload", default="cd3d_64_b4",
                    help="a second workload timed in FP64 ('none' to skip)")
@@ -90,7 +96,7 @@ def calibrate_copy(nbytes):
     print(json.dumps({"calibrate_copy_bytes": nbytes // 8 * 8, "copies": 2}), flush=True)
 
 
-def time_form(w, prec, args, project, agg):
+def time_form(w, prec, args, project, agg, det=None):
     """K timed steps of one form on workload w; returns its record."""
     import numpy as np
     import torch
@@ -101,7 +107,7 @@ def time_form(w, prec, args, project, agg):
     opts = dict(ordering=order, collect_timing=1,
                 update_precision=prec, apply_path=args.apply_path,
                 update_mfma=args.update_mfma, use_aggregation=agg,
-                deterministic=args.deterministic)
+                deterministic=args.deterministic if det is None else det)
     h = bilu.Bilu(**opts)
     t0 = time.perf_counter()
     h.analyze(w.a, pre_perm=None if project else w.perm)
@@ -276,7 +282,7 @@ def main():
     project = args.ordering != "caller"
     agg = AGGREGATION_DEFAULT if args.aggregation < 0 else bool(args.aggregation)
     w = mg.workload(args.workload)
-    recs = {f: time_form(w, FORM_PREC[f], args, project, agg) for f in forms}
+    recs = {f: time_form(w, FORM_PREC[f], args, project, agg, FORM_DET.get(f)) for f in forms}
     main_rec = recs[forms[0]]
     st = main_rec["stats"]
     roofline, other = roofline_of(main_rec, w, args.steps)
@@ -294,7 +300,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": forms[0],
+        "dtype": forms[0].split("_")[0],
         "data": "synthetic",
         "config": {
             "workload": w.name, "n": w.a.n, "nnz": w.a.nnz, "tau": w.tau, "restart": w.restart,
@@ -304,8 +310,9 @@ def main():
                                     "structures)",
                          "multilevel": "multilevel nested dissection of the compressed graph "
                                        "(library)"}[args.ordering],
-            "update_precision": forms[0], "aggregation": agg, "update_mfma": args.update_mfma,
-            "deterministic": args.deterministic,
+            "update_precision": forms[0].split("_")[0], "aggregation": agg,
+            "update_mfma": args.update_mfma,
+            "deterministic": FORM_DET.get(forms[0], args.deterministic),
             "tuning": os.path.relpath(args.tuning, ROOT) if args.tuning else None,
             "tuning_applied": bool(st["tuning_applied"]),
             "parallelism": "single GPU",
