@@ -2713,11 +2713,27 @@ __global__ void seed_flags(int nb, const int* pending, int* enq, unsigned char* 
 // panel), the terms taken per predecessor J in ascending order and only
 // where both ends are stored; then D_K = S_K^-1 (the sweep's pivot routine,
 // perturbation included), L_K = C(R_K, K) D_K and W_K = C(K, C_K).  Nothing
-// is dropped and nothing merges.  One workgroup per block; blocks of one
-// dependency level run in one launch.  The FP64 panels sit in the scratch
+// is dropped and nothing merges.  One workgroup per block, all blocks in one
+// launch ordered by dependency level: a block waits (bounded) until every
+// predecessor has published its values.  The FP64 panels sit in the scratch
 // arrays PL (at the L offsets), PW (at the W offsets) and PD (at the pivot
 // offsets).
 // ---------------------------------------------------------------------------
+// One predecessor of the frozen refactorization as the pair loop reads it.
+struct FrozenPred {
+  long long roff, coff, loff, woff;  // the block's list and value offsets
+  int J, s0, cnt;                    // the block and its run inside K
+  int p;                             // its width
+  int len;                           // length of its row (column) list
+  int first;                         // first row from K on (first column beyond K)
+  int pad[2];
+};
+static_assert(sizeof(FrozenPred) == 64, "layout");
+// predecessors staged in LDS, over the general path's annotation lists
+constexpr int kFrozenStaged = (int)(2 * kAnnCap * sizeof(int) / sizeof(FrozenPred));
+static_assert(offsetof(Lds, g.annc) == offsetof(Lds, g.ann) + sizeof(int) * kAnnCap &&
+                  offsetof(Lds, g.ann) % alignof(FrozenPred) == 0,
+              "layout");
 struct FrozenArgs {
   FactorView f;            // the factor rewritten in place (val, dval)
   double* val64;           // = f.val when it is FP64 (else null)
@@ -2733,8 +2749,10 @@ struct FrozenArgs {
   // K, ascending, with the run's first position and length
   const int32_t *cptr, *cj, *cs0, *ccnt;
   const int32_t *rptr, *rj, *rs0, *rcnt;
-  const int32_t* sched;    // blocks of this level
-  int begin, end;
+  const int32_t* sched;    // the blocks by (level, index): every predecessor earlier
+  int nb;
+  int* done;               // per block: set once its values are published
+  unsigned long long wait; // bound of a dependency wait (wall-clock ticks)
   FactorArgs fa;           // perturbation settings and status words of the sweep
 };
 
@@ -2767,18 +2785,26 @@ __device__ __forceinline__ double frozen_term(const void* heap, int prec, int64_
 __global__ void __launch_bounds__(kThreads) frozen_block_kernel(FrozenArgs a) {
   __shared__ Lds s;
   extern __shared__ double s_dyn[];
-  const int w = a.begin + blockIdx.x;
-  if (w >= a.end) return;
+  const int w = blockIdx.x;
+  if (w >= a.nb) return;
   const int tid = threadIdx.x, nt = blockDim.x;
   const FactorView& f = a.f;
   const int K = a.sched[w];
+  // K's values are published (or K gave up) for the blocks that wait on it
+  auto publish = [&]() {
+    wg_release_agent();
+    if (tid == 0) __hip_atomic_store(&a.done[K], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
   const int f0 = f.bstart[K], q = f.bstart[K + 1] - f0, l0 = f0 + q - 1;
   const int nr = f.nr[K], nc = f.nc[K];
   const int32_t* RK = f.idx + f.roff[K];
   const int32_t* CK = f.idx + f.coff[K];
-  double* PL = a.PL + f.loff[K];   // nr x q, row-major
-  double* PW = a.PW + f.woff[K];   // q x nc, column-major
-  double* PD = a.PD + f.doff[K];   // q x q, row-major
+  // FP64 panels: in LDS (the candidate hash, unused here) when they fit,
+  // else in the scratch arrays
+  const bool lp = (int64_t)(nr + nc + q) * q <= kHashSlots / 2;
+  double* PL = lp ? reinterpret_cast<double*>(s.hash) : a.PL + f.loff[K];  // nr x q, row-major
+  double* PW = lp ? PL + (int64_t)nr * q : a.PW + f.woff[K];              // q x nc, column-major
+  double* PD = lp ? PW + (int64_t)nc * q : a.PD + f.doff[K];              // q x q, row-major
   // K's lists in LDS when they fit (searched for every term)
   const bool lr = nr <= kCandCap, lc = nc <= kCandCap;
   for (int t = tid; t < nr && lr; t += nt) s.cand[t] = RK[t];
@@ -2812,11 +2838,13 @@ __global__ void __launch_bounds__(kThreads) frozen_block_kernel(FrozenArgs a) {
       if (k >= 0) PW[(int64_t)k * q + r] = a.rv[m];
     }
   }
-  // every predecessor's first row from the block on (column panel) and
-  // first column beyond the block (row panel), searched all at once
+  // per predecessor (column-panel ones first, then row-panel ones): the
+  // block, its run inside K, its width and list and value offsets, and its
+  // first row from the block on (column panel) or first column beyond the
+  // block (row panel); staged in LDS all at once when they fit, else read
+  // per pair
   const int x0c = a.cptr[K], ncp = a.cptr[K + 1] - x0c;
   const int x0r = a.rptr[K], nrp = a.rptr[K + 1] - x0r;
-  const bool pre = ncp <= kPredCap && nrp <= kPredCap;
   auto first_from = [&](const int32_t* v, int m, int key, bool beyond) {
     int lo = 0, hi = m;  // first position with v >= key (beyond: v > key)
     while (lo < hi) {
@@ -2825,69 +2853,108 @@ __global__ void __launch_bounds__(kThreads) frozen_block_kernel(FrozenArgs a) {
     }
     return lo;
   };
-  for (int t = tid; pre && t < ncp + nrp; t += nt) {
-    if (t < ncp) {
-      const int J = a.cj[x0c + t];
-      s.g.pred[t] = first_from(f.idx + f.roff[J], f.nr[J], f0, false);
-    } else {
-      const int J = a.rj[x0r + t - ncp];
-      s.g.rpred[t - ncp] = first_from(f.idx + f.coff[J], f.nc[J], l0, true);
+  auto load_pred = [&](int t) {
+    FrozenPred m;
+    const bool col = t < ncp;
+    const int x = col ? x0c + t : x0r + t - ncp;
+    m.J = col ? a.cj[x] : a.rj[x];
+    m.s0 = col ? a.cs0[x] : a.rs0[x];
+    m.cnt = col ? a.ccnt[x] : a.rcnt[x];
+    m.p = f.bstart[m.J + 1] - f.bstart[m.J];
+    m.roff = f.roff[m.J];
+    m.coff = f.coff[m.J];
+    m.loff = f.loff[m.J];
+    m.woff = f.woff[m.J];
+    m.len = col ? f.nr[m.J] : f.nc[m.J];
+    m.first = col ? first_from(f.idx + m.roff, m.len, f0, false)
+                  : first_from(f.idx + m.coff, m.len, l0, true);
+    return m;
+  };
+  FrozenPred* md = reinterpret_cast<FrozenPred*>(s.g.ann);
+  const bool staged = ncp + nrp <= kFrozenStaged;
+  for (int t = tid; staged && t < ncp + nrp; t += nt) md[t] = load_pred(t);
+  // every predecessor has published its values (bounded wait; the
+  // structure read above is the old factor's and does not change)
+  {
+    const unsigned long long t0 = wall_clock64();
+    bool stop = false;
+    for (int t = tid; t < ncp + nrp && !stop; t += nt) {
+      const int J = t < ncp ? a.cj[x0c + t] : a.rj[x0r + t - ncp];
+      while (__hip_atomic_load(&a.done[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+        if (wall_clock64() - t0 > a.wait ||
+            __hip_atomic_load(a.fa.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          stop = true;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
     }
+    if (__syncthreads_or(stop)) {
+      if (tid == 0) raise_error(a.fa, kDevSpin, K);
+      publish();
+      return;
+    }
+    wg_acquire_agent();
   }
-  __syncthreads();
   // the k-th column-panel predecessor (columns running inside K) and the
   // k-th row-panel predecessor (rows running inside K) together, in
   // ascending order: they update different panels, and one predecessor's
   // terms hit distinct entries, so one barrier per pair keeps every entry's
   // terms in block order
   for (int k = 0; k < max(ncp, nrp); ++k) {
-    int Jc = -1, c0 = 0, cn = 0, pc = 0, loc = 0, rows = 0;
-    const int32_t *RJc = nullptr, *CJc = nullptr;
-    if (k < ncp) {
-      Jc = a.cj[x0c + k];
-      c0 = a.cs0[x0c + k];
-      cn = a.ccnt[x0c + k];
-      pc = f.bstart[Jc + 1] - f.bstart[Jc];
-      RJc = f.idx + f.roff[Jc];
-      CJc = f.idx + f.coff[Jc];
-      loc = pre ? s.g.pred[k] : first_from(RJc, f.nr[Jc], f0, false);  // rows from the block on
-      rows = f.nr[Jc] - loc;
-    }
-    int Jr = -1, r0 = 0, rn = 0, pr = 0, lor = 0, cols = 0;
-    const int32_t *RJr = nullptr, *CJr = nullptr;
-    if (k < nrp) {
-      Jr = a.rj[x0r + k];
-      r0 = a.rs0[x0r + k];
-      rn = a.rcnt[x0r + k];
-      pr = f.bstart[Jr + 1] - f.bstart[Jr];
-      RJr = f.idx + f.roff[Jr];
-      CJr = f.idx + f.coff[Jr];
-      lor = pre ? s.g.rpred[k] : first_from(CJr, f.nc[Jr], l0, true);  // columns beyond
-      cols = f.nc[Jr] - lor;
-    }
-    const int na = rows * cn, nab = na + rn * cols;
-    for (int e = tid; e < nab; e += nt) {
+    FrozenPred mc{}, mr{};
+    if (k < ncp) mc = staged ? md[k] : load_pred(k);
+    if (k < nrp) mr = staged ? md[ncp + k] : load_pred(ncp + k);
+    const int c0 = mc.s0, cn = mc.cnt, pc = mc.p, loc = mc.first;
+    const int rows = k < ncp ? mc.len - loc : 0;
+    const int32_t* RJc = f.idx + mc.roff;
+    const int32_t* CJc = f.idx + mc.coff;
+    const int r0 = mr.s0, rn = mr.cnt, pr = mr.p, lor = mr.first;
+    const int cols = k < nrp ? mr.len - lor : 0;
+    const int32_t* RJr = f.idx + mr.roff;
+    const int32_t* CJr = f.idx + mr.coff;
+    const int na = rows * cn, nab = na + (k < nrp ? rn * cols : 0);
+    // term e of the pair and its entry (null: the position is not stored)
+    auto term_at = [&](int e, double*& dst) -> double {
+      dst = nullptr;
       if (e < na) {
         const int i = loc + e / cn, t = c0 + e % cn;
         const int r = RJc[i];
-        double* dst;
+        double* row;
         if (r <= l0) {
-          dst = PD + (r - f0) * q;
+          row = PD + (r - f0) * q;
         } else {
           const int ii = find_sorted(Rl, nr, r);
-          if (ii < 0) continue;  // not stored
-          dst = PL + (int64_t)ii * q;
+          if (ii < 0) return 0.0;
+          row = PL + (int64_t)ii * q;
         }
-        dst[CJc[t] - f0] -= frozen_term(f.val, f.vprec, f.loff[Jc] + (int64_t)i * pc,
-                                        f.woff[Jc] + (int64_t)t * pc, pc);
-      } else {
-        const int e2 = e - na;
-        const int i = r0 + e2 % rn, t = lor + e2 / rn;
-        const int kk = find_sorted(Cl, nc, CJr[t]);
-        if (kk < 0) continue;
-        PW[(int64_t)kk * q + (RJr[i] - f0)] -= frozen_term(
-            f.val, f.vprec, f.loff[Jr] + (int64_t)i * pr, f.woff[Jr] + (int64_t)t * pr, pr);
+        dst = row + (CJc[t] - f0);
+        return frozen_term(f.val, f.vprec, mc.loff + (int64_t)i * pc, mc.woff + (int64_t)t * pc,
+                           pc);
       }
+      const int e2 = e - na;
+      const int i = r0 + e2 % rn, t = lor + e2 / rn;
+      const int kk = find_sorted(Cl, nc, CJr[t]);
+      if (kk < 0) return 0.0;
+      dst = PW + (int64_t)kk * q + (RJr[i] - f0);
+      return frozen_term(f.val, f.vprec, mr.loff + (int64_t)i * pr, mr.woff + (int64_t)t * pr,
+                         pr);
+    };
+    // a pair's terms hit distinct entries, so four of them are formed
+    // (their loads in flight together) before they are subtracted
+    constexpr int kU = 4;
+    for (int e0 = tid; e0 < nab; e0 += kU * nt) {
+      double v[kU];
+      double* d[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int e = e0 + u * nt;
+        d[u] = nullptr;
+        v[u] = e < nab ? term_at(e, d[u]) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (d[u]) *d[u] -= v[u];
     }
     __syncthreads();
   }
@@ -2902,7 +2969,10 @@ __global__ void __launch_bounds__(kThreads) frozen_block_kernel(FrozenArgs a) {
     if (tid == 0) s.misc[14] = ok ? 1 : 0;
   }
   __syncthreads();
-  if (!s.misc[14]) return;  // reported through the status words
+  if (!s.misc[14]) {  // reported through the status words
+    publish();
+    return;
+  }
   const int64_t dof = f.doff[K];
   for (int e = tid; e < q * q; e += nt) {
     a.dval[dof + e] = sW[e];
@@ -2915,6 +2985,7 @@ __global__ void __launch_bounds__(kThreads) frozen_block_kernel(FrozenArgs a) {
     value_store(a.val, f.vprec, f.loff[K] + e, acc);
   }
   for (int e = tid; e < nc * q; e += nt) value_store(a.val, f.vprec, f.woff[K] + e, PW[e]);
+  publish();
 }
 
 // Dependency levels of the frozen refactorization: level(K) = 1 + the
@@ -2966,12 +3037,6 @@ __global__ void frozen_extent(FactorView f, unsigned long long* mx) {
 __global__ void frozen_iota(int n, int32_t* v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = i;
-}
-__global__ void frozen_level_starts(int nb, const int* sorted, int* start) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nb) return;
-  if (i == 0 || sorted[i - 1] != sorted[i]) start[sorted[i]] = i;
-  if (i == nb - 1) start[sorted[i] + 1] = nb;
 }
 
 // ---------------------------------------------------------------------------
@@ -3385,11 +3450,13 @@ bilu_status frozen_refactor(bilu_handle* h) {
   CK(hipStreamSynchronize(st));
   if (hm[2]) return fail(h, BILU_ERR_DEVICE, "refactor: a dependency wait timed out");
   const int maxlev = hm[0];
-  DevArray<int32_t> idx, sched, keys_out, starts;
+  DevArray<int32_t> idx, sched, keys_out;
+  DevArray<int> done;
   CK(idx.alloc(nb));
   CK(sched.alloc(nb));
   CK(keys_out.alloc(nb));
-  CK(starts.alloc(maxlev + 3));
+  CK(done.alloc(std::max(1, nb)));
+  CK(hipMemsetAsync(done.p, 0, nb * sizeof(int), st));
   frozen_iota<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nb, idx.p);
   int bits = 1;
   while ((1 << bits) <= maxlev) ++bits;
@@ -3399,11 +3466,6 @@ bilu_status frozen_refactor(bilu_handle* h) {
   CK(h->d_scan_tmp.alloc(bytes + 1));
   CK(hipcub::DeviceRadixSort::SortPairs(h->d_scan_tmp.p, bytes, lev.p, keys_out.p, idx.p, sched.p,
                                         nb, 0, bits, st));
-  frozen_level_starts<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nb, keys_out.p, starts.p);
-  std::vector<int> lstart(maxlev + 2);
-  CK(hipMemcpyAsync(lstart.data(), starts.p, (maxlev + 2) * sizeof(int), hipMemcpyDeviceToHost,
-                    st));
-  CK(hipStreamSynchronize(st));
   // FP64 panels and pivot scratch
   const int maxq = (int)he[2];
   DevArray<double> pv, pd, piv;
@@ -3429,6 +3491,9 @@ bilu_status frozen_refactor(bilu_handle* h) {
   a.cptr = cptr.p; a.cj = cj.p; a.cs0 = cs0.p; a.ccnt = ccnt.p;
   a.rptr = h->fw_ptr.p; a.rj = h->fw_j.p; a.rs0 = h->fw_r0.p; a.rcnt = h->fw_cnt.p;
   a.sched = sched.p;
+  a.nb = nb;
+  a.done = done.p;
+  a.wait = wait;
   a.fa.alpha = h->alpha;
   a.fa.pert_tau = h->opt.perturb_tau;
   a.fa.pert_rho = h->opt.perturb_rho;
@@ -3438,12 +3503,10 @@ bilu_status frozen_refactor(bilu_handle* h) {
   a.fa.err = h->d_status.p + 0;
   a.fa.err_block = h->d_status.p + 1;
   a.fa.n_perturbed = h->d_status.p + 2;
-  for (int L = 0; L <= maxlev; ++L) {
-    a.begin = lstart[L];
-    a.end = lstart[L + 1];
-    if (a.end > a.begin)
-      frozen_block_kernel<<<(unsigned)(a.end - a.begin), kThreads, dyn, st>>>(a);
-  }
+  // one launch: workgroup w takes the w-th block by (level, index), so
+  // every block it waits on sits at a lower workgroup, which the hardware
+  // has started before it; no workgroup needs another to be resident
+  if (nb > 0) frozen_block_kernel<<<(unsigned)nb, kThreads, dyn, st>>>(a);
   CK(hipGetLastError());
   int status[3];
   CK(hipMemcpyAsync(status, h->d_status.p, sizeof(status), hipMemcpyDeviceToHost, st));

@@ -189,7 +189,9 @@ bilu_status sqmr(bilu_handle* h, const double* b_orig, double* x_orig, double to
     resid2 = hs[kSqRR];
     eta = backward_error(hs[kSqRmax], anorm, hs[kSqXmax], bmax);
   }
-  launch_scatter(st, n, h->perm_col(), h->sr(), x, x_orig);
+  // x is written back only when a step changed it (the round trip through
+  // the scaling could move its last bits)
+  if (steps > 0) launch_scatter(st, n, h->perm_col(), h->sr(), x, x_orig);
   if (hipStreamSynchronize(st) != hipSuccess) return device_error();
   int64_t faults = 0;
   if (apply_faults(h, &faults) != BILU_OK) return BILU_ERR_DEVICE;
