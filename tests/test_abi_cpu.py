@@ -274,3 +274,19 @@ def test_symmetric_matching_preprocess_matches_oracle(name, max_block, use_cosin
     if name == "zero_diagonal_41":
         assert (np.diff(us) == 1).sum() >= 1   # an odd cycle left a 1x1 pivot
     assert np.diff(gs).max() <= max_block
+
+
+def test_symmetric_matching_errors():
+    """use_mwm = 2 on a structurally singular matrix (an empty row and
+    column): BILU_ERR_SINGULAR from the matching; a bad use_mwm value:
+    BILU_ERR_INVALID."""
+    A = np.array([[2.0, 1.0, 0.0], [1.0, 3.0, 0.0], [0.0, 0.0, 0.0]])
+    mask = A != 0
+    a = mg.dense_to_csr(A, mask=mask)
+    with pytest.raises(bilu.BiluError) as e:
+        bilu.preprocess(a, 1e-2, use_mwm=2)
+    assert e.value.status == bilu.BILU_ERR_SINGULAR
+    good = mg.dense_to_csr(np.array([[2.0, 1.0], [1.0, 3.0]]))
+    with pytest.raises(bilu.BiluError) as e:
+        bilu.preprocess(good, 1e-2, use_mwm=3)
+    assert e.value.status == bilu.BILU_ERR_INVALID
