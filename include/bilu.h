@@ -283,8 +283,10 @@ bilu_status bilu_refactor(bilu_handle* h, double tau, const double* val);
  * stored), the pivot blocks inverted with the perturbation of Sec. 3.6,
  * L_K = C(R_K, K) D_K and W_K = C(K, C_K).  Nothing is dropped or merged,
  * so the apply plan is kept; (L S U)_Omega = A_Omega holds on the stored
- * positions Omega for the new values.  Blocks of one dependency level run
- * in one launch.  bilu_kept_residual afterwards: BILU_ERR_STATE when the
+ * positions Omega for the new values.  All blocks run in one launch,
+ * ordered by dependency level, each after its predecessors (a bounded wait;
+ * BILU_ERR_DEVICE when it times out).  bilu_kept_residual afterwards:
+ * BILU_ERR_STATE when the
  * last factor had merged blocks (its sweep's positions are no longer the
  * factor's).  Errors: BILU_ERR_STATE before bilu_factor, BILU_ERR_INVALID
  * (non-finite value: nothing changes; use_mwm; nnz >= 2^31),
