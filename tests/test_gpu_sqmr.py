@@ -271,3 +271,45 @@ def test_symmetric_matching_sqmr_and_fgmres():
         f"FGMRES {fg['iterations']}")
     h.close()
     g.close()
+
+
+def test_symmetric_matching_with_the_library_ordering():
+    """The symmetric workload's configuration (use_mwm = 2 with the
+    library's nested dissection of the compressed graph): the analysis
+    equals the host preprocessing, and the factor equals the oracle's
+    sweep of D A D on that numbering with the library's groups as units."""
+    torch = _torch()
+    from oracle import Oracle, OracleOptions
+    from paper_1908_10169_amd import bilu
+    a, order, m = mg.kkt_elasticity(8)
+    tau = 1e-2
+    say(f"[symmwm-nd] kkt side=8 n={a.n}")
+    perm, gs, bs = bilu.preprocess(a, tau, pre_perm=order, ordering=bilu.ORDER_ND, use_mwm=2)
+    h = bilu.Bilu(ordering=bilu.ORDER_ND, use_aggregation=True, use_mwm=2)
+    h.analyze(a, pre_perm=order)
+    h.factor(tau)
+    fl = h.export()
+    assert np.array_equal(fl.perm, perm) and np.array_equal(fl.starts_initial, bs)
+    sigma, dl, dr = bilu.mwm(a)
+    d = np.sqrt(dl * dr)
+    rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
+    ah = mg.Csr(a.n, a.rowptr, a.colind, (d[rows] * a.val) * d[a.colind])
+    o = Oracle()
+    assert o.run(ah, OracleOptions(tau=tau, use_aggregation=True, use_cosine=False),
+                 pre_perm=perm, unit_starts=gs) == 0
+    fo = o.factors()
+    assert np.array_equal(fo.perm, fl.perm)
+    assert np.array_equal(fo.starts_initial, fl.starts_initial)
+    assert np.array_equal(fo.starts, fl.starts)
+    for k in range(len(fo.starts) - 1):
+        assert np.array_equal(fl.R[k], fo.R[k]) and np.array_equal(fl.C[k], fo.C[k]), k
+    for name in ("L", "W", "D"):
+        num = sum(float(np.sum((x - y) ** 2)) for x, y in zip(getattr(fl, name), getattr(fo, name)))
+        den = sum(float(np.sum(y ** 2)) for y in getattr(fo, name))
+        assert np.sqrt(num / max(den, 1e-300)) <= 1e-10, name
+    b = a.matvec(np.ones(a.n))
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd)
+    info = h.sqmr(bd, xd, tol=1e-6, maxit=500)
+    assert info["converged"] and _eta(a, b, xd.cpu().numpy()) <= 1e-6
+    h.close()
