@@ -80,6 +80,7 @@ namespace bilu {
 bilu_status finish_factor(bilu_handle* h, std::chrono::steady_clock::time_point t0) {
   bilu_status s = BILU_OK;
   h->kept_stale = false;
+  h->frozen.ready = false;  // a new factor: the frozen schedule is rebuilt on demand
   h->stats.r_kept = -1.0;  // computed on request (bilu_kept_residual)
   h->nb = h->stats.nblocks_initial;
   h->bstart = h->bstart0;

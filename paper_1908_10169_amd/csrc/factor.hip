@@ -2880,13 +2880,17 @@ __global__ void __launch_bounds__(kThreads) frozen_block_kernel(FrozenArgs a) {
     bool stop = false;
     for (int t = tid; t < ncp + nrp && !stop; t += nt) {
       const int J = t < ncp ? a.cj[x0c + t] : a.rj[x0r + t - ncp];
-      while (__hip_atomic_load(&a.done[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        if (wall_clock64() - t0 > a.wait ||
-            __hip_atomic_load(a.fa.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      int ready = __hip_atomic_load(&a.done[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      while (!ready) {
+        __builtin_amdgcn_s_sleep(1);
+        // the flag's reload, the error word and the clock go out together
+        ready = __hip_atomic_load(&a.done[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int err = __hip_atomic_load(a.fa.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long now = wall_clock64();
+        if (!ready && (err != 0 || now - t0 > a.wait)) {
           stop = true;
           break;
         }
-        __builtin_amdgcn_s_sleep(1);
       }
     }
     if (__syncthreads_or(stop)) {
@@ -3008,13 +3012,17 @@ __global__ void __launch_bounds__(256) frozen_levels(int nb, const int32_t* cptr
       const int J = e + lane < ptr[K + 1] ? adj[e + lane] : -1;
       int v = J >= 0 ? __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
       while (!__all(v >= 0)) {
-        if (wall_clock64() - t0 > wait ||
-            __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        __builtin_amdgcn_s_sleep(1);
+        // the level's reload, the error word and the clock go out together
+        const int nv = v < 0 ? __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : v;
+        const int e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long now = wall_clock64();
+        v = nv;
+        if (e != 0) return;
+        if (now - t0 > wait && !__all(v >= 0)) {
           if (lane == 0) atomicExch(err, 1);
           return;
         }
-        __builtin_amdgcn_s_sleep(1);
-        if (v < 0) v = __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       if (J >= 0) l = max(l, v + 1);
     }
@@ -3418,62 +3426,63 @@ bilu_status frozen_refactor(bilu_handle* h) {
   hipStream_t st = h->stream;
   const FactorView& f = h->fv;
   const int nb = f.nb;
-  // the blocks whose columns run inside each block (its rows: the apply
-  // plan's forward lists of the same factor)
-  DevArray<int32_t> cptr, cj, cs0, ccnt;
-  {
-    const bilu_status rs = block_runs(h, f, true, cptr, cj, cs0, ccnt);
-    if (rs != BILU_OK) return rs;
-  }
-  // levels, the blocks ordered by (level, index)
-  DevArray<int> lev, misc;
-  DevArray<unsigned long long> ext;
-  CK(lev.alloc(std::max(1, nb)));
-  CK(misc.alloc(4));
-  CK(ext.alloc(3));
-  CK(hipMemsetAsync(lev.p, 0xff, nb * sizeof(int), st));
-  CK(hipMemsetAsync(misc.p, 0, 4 * sizeof(int), st));
-  CK(hipMemsetAsync(ext.p, 0, 3 * sizeof(unsigned long long), st));
   const unsigned long long wait = h->wait_ticks ? h->wait_ticks : (unsigned long long)1e9;
-  frozen_levels<<<(unsigned)((nb + 3) / 4), 256, 0, st>>>(nb, cptr.p, cj.p, h->fw_ptr.p, h->fw_j.p,
-                                                          lev.p, misc.p + 2, wait);
-  frozen_extent<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(f, ext.p);
-  CK(hipGetLastError());
-  size_t rb = 0;
-  CK(hipcub::DeviceReduce::Max(nullptr, rb, lev.p, misc.p, nb, st));
-  CK(h->d_scan_tmp.alloc(rb + 1));
-  CK(hipcub::DeviceReduce::Max(h->d_scan_tmp.p, rb, lev.p, misc.p, nb, st));
-  int hm[4];
-  unsigned long long he[3];
-  CK(hipMemcpyAsync(hm, misc.p, sizeof(hm), hipMemcpyDeviceToHost, st));
-  CK(hipMemcpyAsync(he, ext.p, sizeof(he), hipMemcpyDeviceToHost, st));
-  CK(hipStreamSynchronize(st));
-  if (hm[2]) return fail(h, BILU_ERR_DEVICE, "refactor: a dependency wait timed out");
-  const int maxlev = hm[0];
-  DevArray<int32_t> idx, sched, keys_out;
-  DevArray<int> done;
-  CK(idx.alloc(nb));
-  CK(sched.alloc(nb));
-  CK(keys_out.alloc(nb));
-  CK(done.alloc(std::max(1, nb)));
-  CK(hipMemsetAsync(done.p, 0, nb * sizeof(int), st));
-  frozen_iota<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nb, idx.p);
-  int bits = 1;
-  while ((1 << bits) <= maxlev) ++bits;
-  size_t bytes = 0;
-  CK(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, lev.p, keys_out.p, idx.p, sched.p, nb, 0,
-                                        bits, st));
-  CK(h->d_scan_tmp.alloc(bytes + 1));
-  CK(hipcub::DeviceRadixSort::SortPairs(h->d_scan_tmp.p, bytes, lev.p, keys_out.p, idx.p, sched.p,
-                                        nb, 0, bits, st));
-  // FP64 panels and pivot scratch
-  const int maxq = (int)he[2];
-  DevArray<double> pv, pd, piv;
-  CK(pv.alloc(std::max<unsigned long long>(1, he[0])));
-  CK(pd.alloc(std::max<unsigned long long>(1, he[1])));
+  FrozenPlan& fp = h->frozen;
+  if (!fp.ready) {
+    // the schedule depends on the factor's structure only: built once per
+    // factorization.  The blocks whose columns run inside each block (its
+    // rows: the apply plan's forward lists of the same factor)
+    const bilu_status rs = block_runs(h, f, true, fp.cptr, fp.cj, fp.cs0, fp.ccnt);
+    if (rs != BILU_OK) return rs;
+    // levels, the blocks ordered by (level, index)
+    DevArray<int> lev, misc;
+    DevArray<unsigned long long> ext;
+    CK(lev.alloc(std::max(1, nb)));
+    CK(misc.alloc(4));
+    CK(ext.alloc(3));
+    CK(hipMemsetAsync(lev.p, 0xff, nb * sizeof(int), st));
+    CK(hipMemsetAsync(misc.p, 0, 4 * sizeof(int), st));
+    CK(hipMemsetAsync(ext.p, 0, 3 * sizeof(unsigned long long), st));
+    frozen_levels<<<(unsigned)((nb + 3) / 4), 256, 0, st>>>(nb, fp.cptr.p, fp.cj.p, h->fw_ptr.p,
+                                                            h->fw_j.p, lev.p, misc.p + 2, wait);
+    frozen_extent<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(f, ext.p);
+    CK(hipGetLastError());
+    size_t rb = 0;
+    CK(hipcub::DeviceReduce::Max(nullptr, rb, lev.p, misc.p, nb, st));
+    CK(h->d_scan_tmp.alloc(rb + 1));
+    CK(hipcub::DeviceReduce::Max(h->d_scan_tmp.p, rb, lev.p, misc.p, nb, st));
+    int hm[4];
+    CK(hipMemcpyAsync(hm, misc.p, sizeof(hm), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(fp.ext, ext.p, sizeof(fp.ext), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (hm[2]) return fail(h, BILU_ERR_DEVICE, "refactor: a dependency wait timed out");
+    const int maxlev = hm[0];
+    DevArray<int32_t> idx, keys_out;
+    CK(idx.alloc(nb));
+    CK(fp.sched.alloc(nb));
+    CK(keys_out.alloc(nb));
+    frozen_iota<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nb, idx.p);
+    int bits = 1;
+    while ((1 << bits) <= maxlev) ++bits;
+    size_t bytes = 0;
+    CK(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, lev.p, keys_out.p, idx.p, fp.sched.p, nb,
+                                          0, bits, st));
+    CK(h->d_scan_tmp.alloc(bytes + 1));
+    CK(hipcub::DeviceRadixSort::SortPairs(h->d_scan_tmp.p, bytes, lev.p, keys_out.p, idx.p,
+                                          fp.sched.p, nb, 0, bits, st));
+    // FP64 panels (for blocks whose panels do not fit the LDS) and pivot
+    // scratch, kept with the schedule
+    CK(fp.pv.alloc(std::max<unsigned long long>(1, fp.ext[0])));
+    CK(fp.pd.alloc(std::max<unsigned long long>(1, fp.ext[1])));
+    if ((int)fp.ext[2] > kLdsPivotWidth) CK(fp.piv.alloc(2 * std::max<unsigned long long>(1, fp.ext[1])));
+    CK(fp.done.alloc(std::max(1, nb)));
+    CK(hipStreamSynchronize(st));
+    fp.ready = true;
+  }
+  CK(hipMemsetAsync(fp.done.p, 0, nb * sizeof(int), st));
+  const int maxq = (int)fp.ext[2];
   const bool lds_pivot = maxq <= kLdsPivotWidth;
   const size_t dyn = lds_pivot ? 2 * sizeof(double) * maxq * maxq : 0;
-  if (!lds_pivot) CK(piv.alloc(2 * std::max<unsigned long long>(1, he[1])));
   CK(hipMemsetAsync(h->d_status.p, 0, 3 * sizeof(int), st));
   FrozenArgs a{};
   a.f = f;
@@ -3482,17 +3491,17 @@ bilu_status frozen_refactor(bilu_handle* h) {
   // S_K too when the factor is the sweep's own (no merges), so the
   // kept-pattern residual stays defined
   a.sval = f.dval == h->d_dval.p ? h->d_sval.p : nullptr;
-  a.PL = pv.p;
-  a.PW = pv.p;
-  a.PD = pd.p;
-  a.piv = lds_pivot ? nullptr : piv.p;
+  a.PL = fp.pv.p;
+  a.PW = fp.pv.p;
+  a.PD = fp.pd.p;
+  a.piv = lds_pivot ? nullptr : fp.piv.p;
   a.cp = h->d_cp.p; a.ri = h->d_ri.p; a.cv = h->d_cv.p;
   a.rp = h->d_rp.p; a.ci = h->d_ci.p; a.rv = h->d_rv.p;
-  a.cptr = cptr.p; a.cj = cj.p; a.cs0 = cs0.p; a.ccnt = ccnt.p;
+  a.cptr = fp.cptr.p; a.cj = fp.cj.p; a.cs0 = fp.cs0.p; a.ccnt = fp.ccnt.p;
   a.rptr = h->fw_ptr.p; a.rj = h->fw_j.p; a.rs0 = h->fw_r0.p; a.rcnt = h->fw_cnt.p;
-  a.sched = sched.p;
+  a.sched = fp.sched.p;
   a.nb = nb;
-  a.done = done.p;
+  a.done = fp.done.p;
   a.wait = wait;
   a.fa.alpha = h->alpha;
   a.fa.pert_tau = h->opt.perturb_tau;

@@ -207,6 +207,18 @@ struct FactorView {
 };
 
 
+// The frozen refactorization's schedule: per block the runs of the blocks
+// whose columns fall inside it, the blocks by dependency level, the largest
+// value and pivot offsets and width (ext), FP64 scratch and done flags.  It
+// depends on the factor's structure only.
+struct FrozenPlan {
+  bool ready = false;
+  DevArray<int32_t> cptr, cj, cs0, ccnt, sched;
+  DevArray<int> done;
+  DevArray<double> pv, pd, piv;
+  unsigned long long ext[3] = {0, 0, 0};
+};
+
 // tuning.cpp: tuned settings for one update precision and block-width
 // class (0: the widest initial block is at most 16, 1: wider), for handles
 // that require reproducible results (reproducible = 1) or not
@@ -336,6 +348,9 @@ struct bilu_handle {
   // the kept-pattern residual no longer describes the factor (a frozen
   // refactorization of a factor with merged blocks)
   bool kept_stale = false;
+  // the frozen refactorization's schedule and scratch (factor.hip), kept
+  // from one call to the next until the factor changes
+  bilu::FrozenPlan frozen;
 
   // settings in effect for the last factorization: the options, or a tuned
   // entry for its precision and block-width class (use_tuning)

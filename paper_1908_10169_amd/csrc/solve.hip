@@ -167,13 +167,17 @@ __global__ void __launch_bounds__(256) apply_levels(int nb, const int32_t* fptr,
     const int J = e + lane < e1 ? adj[e + lane] : -1;
     int v = J >= 0 ? __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
     while (!__all(v >= 0)) {
-      if (wall_clock64() - t0 > wait_ticks ||
-          __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      __builtin_amdgcn_s_sleep(1);
+      // the level's reload, the error word and the clock go out together
+      const int nv = v < 0 ? __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : v;
+      const int e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned long long now = wall_clock64();
+      v = nv;
+      if (e != 0) return;
+      if (now - t0 > wait_ticks && !__all(v >= 0)) {
         if (lane == 0) atomicExch(err, 1);
         return;
       }
-      __builtin_amdgcn_s_sleep(1);
-      if (v < 0) v = __hip_atomic_load(&lev[J], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     if (J >= 0) l = max(l, v + 1);
   }
@@ -453,7 +457,19 @@ __device__ __forceinline__ double await_from(const A& a, int side, bool has, int
       bad = true;
       return 0.0;
     }
-    if (wall_clock64() - t0 > a.wait_ticks) {
+    __builtin_amdgcn_s_sleep(1);
+    // the value's reload, the error word and the clock go out together
+    // (one round trip per poll)
+    const unsigned long long nv =
+        has && v == kPending ? __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : v;
+    const int err = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long now = wall_clock64();
+    v = nv;
+    if (err != 0) {
+      bad = true;
+      return 0.0;
+    }
+    if (now - t0 > a.wait_ticks && !__all(!has || v != kPending)) {
       if (has && v == kPending && atomicCAS(&a.err[0], 0, 1) == 0) {
         a.err[1] = slot;
         a.err[2] = side;
@@ -462,12 +478,6 @@ __device__ __forceinline__ double await_from(const A& a, int side, bool has, int
       bad = true;
       return 0.0;
     }
-    if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-      bad = true;
-      return 0.0;
-    }
-    __builtin_amdgcn_s_sleep(1);
-    if (has && v == kPending) v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   return __longlong_as_double((long long)v);
 }
