@@ -273,19 +273,22 @@ def test_symmetric_matching_sqmr_and_fgmres():
     g.close()
 
 
-def test_symmetric_matching_with_the_library_ordering():
+@pytest.mark.parametrize("ordering", ["nd", "multilevel"])
+def test_symmetric_matching_with_the_library_ordering(ordering):
     """The symmetric workload's configuration (use_mwm = 2 with the
-    library's nested dissection of the compressed graph): the analysis
-    equals the host preprocessing, and the factor equals the oracle's
-    sweep of D A D on that numbering with the library's groups as units."""
+    library's nested dissection of the compressed graph, multilevel as the
+    benchmark runs it): the analysis equals the host preprocessing, and the
+    factor equals the oracle's sweep of D A D on that numbering with the
+    library's groups as units."""
     torch = _torch()
     from oracle import Oracle, OracleOptions
     from paper_1908_10169_amd import bilu
+    order_id = {"nd": bilu.ORDER_ND, "multilevel": bilu.ORDER_ND_MULTILEVEL}[ordering]
     a, order, m = mg.kkt_elasticity(8)
     tau = 1e-2
-    say(f"[symmwm-nd] kkt side=8 n={a.n}")
-    perm, gs, bs = bilu.preprocess(a, tau, pre_perm=order, ordering=bilu.ORDER_ND, use_mwm=2)
-    h = bilu.Bilu(ordering=bilu.ORDER_ND, use_aggregation=True, use_mwm=2)
+    say(f"[symmwm-{ordering}] kkt side=8 n={a.n}")
+    perm, gs, bs = bilu.preprocess(a, tau, pre_perm=order, ordering=order_id, use_mwm=2)
+    h = bilu.Bilu(ordering=order_id, use_aggregation=True, use_mwm=2)
     h.analyze(a, pre_perm=order)
     h.factor(tau)
     fl = h.export()
