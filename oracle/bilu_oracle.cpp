@@ -294,11 +294,27 @@ std::vector<i64> union_above(const std::vector<i64>& x, const std::vector<i64>& 
 // Readings: the unit of growth is a cosine group (a scalar without the
 // cosine step); |I|, |J| in c' are the estimated sets; the diagonal is the
 // "+1"; widths never exceed max_block.
+// Sec. 5 (symmetric variant, 1x1 and 2x2 pivots): with partner (the other
+// index of a scalar's 2x2 pivot, -1 for a 1x1 pivot) both scalars of a 2x2
+// pivot take the pivot block's largest magnitude in place of |a_kk| in the
+// thresholds.  Reading: the paper says only that ILU(1,tau) is modified to
+// deal with 1x1 and 2x2 pivots; a zero diagonal inside a 2x2 pivot would
+// otherwise pass every candidate.
 i64 ilu1t_blocks(const Mat& a, const std::vector<i64>& ustart, double tau, int max_block,
-                 bool grow, std::vector<i64>& bstart) {
+                 bool grow, std::vector<i64>& bstart, const std::vector<i64>* partner = nullptr) {
   Mat at = transpose(a);
   std::vector<double> dg(a.n, 0.0);
   for (i64 i = 0; i < a.n; ++i) dg[i] = entry(a, i, i);
+  if (partner && !partner->empty()) {
+    std::vector<double> d2(dg);
+    for (i64 i = 0; i < a.n; ++i) {
+      const i64 p = (*partner)[i];
+      if (p < 0) continue;
+      d2[i] = std::max(std::max(std::fabs(entry(a, i, i)), std::fabs(entry(a, p, p))),
+                       std::max(std::fabs(entry(a, i, p)), std::fabs(entry(a, p, i))));
+    }
+    dg.swap(d2);
+  }
   const i64 nu = (i64)ustart.size() - 1;
   bstart.assign(1, 0);
   i64 u = 0;
@@ -515,6 +531,7 @@ struct orc_handle {
   Mat P;                       // permuted  (P(i,j) = A(perm[i], perm[j]))
   std::vector<i64> perm;       // new -> old
   std::vector<i64> gstart;     // cosine groups in permuted numbering
+  std::vector<i64> partner;    // the other scalar of a 2x2 pivot (-1: 1x1), permuted numbering
   std::vector<i64> start0;     // initial partition
   std::vector<Block> blocks;   // all blocks ever created (dead ones merged)
   std::vector<int> live;       // ids of final blocks in order
@@ -893,7 +910,8 @@ int run_common(orc_handle* h, const orc_options* opt) {
   h->start0.clear();
   i64 nu = (i64)h->gstart.size() - 1;
   (void)nu;
-  ilu1t_blocks(h->P, h->gstart, h->opt.tau, h->opt.max_block, h->opt.use_ilu1t != 0, h->start0);
+  ilu1t_blocks(h->P, h->gstart, h->opt.tau, h->opt.max_block, h->opt.use_ilu1t != 0, h->start0,
+               &h->partner);
   auto t2 = Clock::now();
   h->t_ilu1t = std::chrono::duration<double>(t2 - t1).count();
   (void)opt;
@@ -941,18 +959,19 @@ void orc_destroy(orc_handle* h) { delete h; }
 
 int orc_run(orc_handle* h, int64_t n, const int64_t* rowptr, const int32_t* colind,
             const double* val, const int64_t* pre_perm, const orc_options* opt) {
-  return orc_run_units(h, n, rowptr, colind, val, pre_perm, 0, nullptr, opt);
+  return orc_run_units(h, n, rowptr, colind, val, pre_perm, 0, nullptr, nullptr, opt);
 }
 
 int orc_run_units(orc_handle* h, int64_t n, const int64_t* rowptr, const int32_t* colind,
                   const double* val, const int64_t* pre_perm, int64_t nunits,
-                  const int64_t* unit_starts, const orc_options* opt) {
+                  const int64_t* unit_starts, const int64_t* partner, const orc_options* opt) {
   if (!valid_csr(n, rowptr, colind, val)) return -1;
   if (unit_starts) {
     if (nunits < 1 || unit_starts[0] != 0 || unit_starts[nunits] != n) return -1;
     for (i64 u = 0; u < nunits; ++u)
       if (unit_starts[u + 1] <= unit_starts[u]) return -1;
   }
+  h->partner.clear();
   auto t0 = Clock::now();
   h->opt = *opt;
   h->n = n;
@@ -982,6 +1001,22 @@ int orc_run_units(orc_handle* h, int64_t n, const int64_t* rowptr, const int32_t
         for (i64 i = us[qu[k]]; i < us[qu[k] + 1]; ++i) q.push_back(i);
       gs.push_back((i64)q.size());
     }
+    // the 2x2 pivots in the final numbering (the groups keep the group
+    // order, so q is that numbering): the units of two scalars, unless the
+    // caller gives them
+    if (partner) {
+      h->partner.assign(partner, partner + n);
+    } else {
+      std::vector<i64> qinv(n);
+      for (i64 i = 0; i < n; ++i) qinv[q[i]] = i;
+      h->partner.assign(n, -1);
+      for (i64 u = 0; u < nunits; ++u)
+        if (us[u + 1] - us[u] == 2) {
+          const i64 p0 = qinv[us[u]], p1 = qinv[us[u] + 1];
+          h->partner[p0] = p1;
+          h->partner[p1] = p0;
+        }
+    }
   } else if (opt->use_cosine) {
     cosine_groups(A1, opt->cos_eps, opt->max_block, q, gs, &h->n_ignored);
   } else {
@@ -1010,6 +1045,7 @@ int orc_run_partition(orc_handle* h, int64_t n, const int64_t* rowptr, const int
     if (starts[b + 1] <= starts[b]) return -1;
   h->opt = *opt;
   h->n = n;
+  h->partner.clear();
   h->A = from_csr(n, rowptr, colind, val);
   h->perm.resize(n);
   for (i64 i = 0; i < n; ++i) h->perm[i] = perm ? perm[i] : i;

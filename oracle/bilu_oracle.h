@@ -70,10 +70,16 @@ int orc_run(orc_handle* h, int64_t n, const int64_t* rowptr,
  * unit_starts[u+1]) (1x1 and 2x2 pivots of the symmetric matching) that no
  * group splits; the cosine test runs on the compressed companion matrix
  * (a unit's row is the union of its rows, columns replaced by their units)
- * and a group holds at most max_block scalars.  unit_starts NULL: orc_run. */
+ * and a group holds at most max_block scalars.  Both scalars of a 2x2
+ * pivot take the pivot block's largest magnitude in place of |a_kk| in
+ * the ILU(1,tau) thresholds.  partner (n entries in the final numbering,
+ * the other scalar of each 2x2 pivot or -1; may be NULL) names the 2x2
+ * pivots when the units are coarser (groups given by the caller); NULL:
+ * the units of two scalars.  unit_starts NULL: orc_run. */
 int orc_run_units(orc_handle* h, int64_t n, const int64_t* rowptr,
                   const int32_t* colind, const double* val, const int64_t* pre_perm,
-                  int64_t nunits, const int64_t* unit_starts, const orc_options* opt);
+                  int64_t nunits, const int64_t* unit_starts, const int64_t* partner,
+                  const orc_options* opt);
 
 /* Same, but with a caller-given block partition of the permuted matrix
  * (starts[0]=0 < ... < starts[nblocks]=n); cosine and ILU(1,tau) skipped. */

@@ -44,7 +44,7 @@ def load():
     lib.orc_default_options.argtypes = [C.POINTER(_Opts)]
     lib.orc_run.argtypes = [vp, C.c_int64, _I64P, _I32P, _F64P, vp, C.POINTER(_Opts)]
     lib.orc_run.restype = C.c_int
-    lib.orc_run_units.argtypes = [vp, C.c_int64, _I64P, _I32P, _F64P, vp, C.c_int64, vp,
+    lib.orc_run_units.argtypes = [vp, C.c_int64, _I64P, _I32P, _F64P, vp, C.c_int64, vp, vp,
                                   C.POINTER(_Opts)]
     lib.orc_run_units.restype = C.c_int
     lib.orc_run_partition.argtypes = [vp, C.c_int64, _I64P, _I32P, _F64P, vp, C.c_int64,
@@ -147,19 +147,24 @@ class Oracle:
         except Exception:
             pass
 
-    def run(self, a, opts: OracleOptions | None = None, pre_perm=None, unit_starts=None) -> int:
+    def run(self, a, opts: OracleOptions | None = None, pre_perm=None, unit_starts=None,
+            partner=None) -> int:
         """The full pipeline; unit_starts (in the pre-permuted numbering)
-        gives the units of the symmetric variant that groups never split."""
+        gives the units of the symmetric variant that groups never split;
+        partner (final numbering) the 2x2 pivots when the units are
+        coarser than them."""
         opts = opts or OracleOptions()
         self.n = a.n
         self.a = a
         pp = None if pre_perm is None else np.ascontiguousarray(pre_perm, dtype=np.int64)
         self._pp = pp
         us = None if unit_starts is None else np.ascontiguousarray(unit_starts, dtype=np.int64)
+        pt = None if partner is None else np.ascontiguousarray(partner, dtype=np.int64)
         rc = self._lib.orc_run_units(self._h, a.n, a.rowptr, a.colind, a.val,
                                      pp.ctypes.data if pp is not None else None,
                                      0 if us is None else len(us) - 1,
                                      us.ctypes.data if us is not None else None,
+                                     pt.ctypes.data if pt is not None else None,
                                      C.byref(opts.c()))
         return rc
 

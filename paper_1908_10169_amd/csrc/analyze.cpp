@@ -603,6 +603,20 @@ bilu_status analyze_host(bilu_handle* h, int64_t n, const int64_t* rowptr,
   }
   const bilu_status os = order_and_expand(h, a1.rp.data(), a1.ci.data(), pre, q, gs);
   if (os != BILU_OK) return os;
+  h->sym_partner.clear();
+  if (units) {
+    // the 2x2 pivots in the final numbering
+    std::vector<int64_t> pos(n);
+    for (int64_t i = 0; i < n; ++i) pos[h->perm[i]] = i;
+    h->sym_partner.assign(n, -1);
+    const std::vector<int64_t>& us = h->sym_ustart;
+    for (size_t u = 0; u + 1 < us.size(); ++u)
+      if (us[u + 1] - us[u] == 2) {
+        const int64_t p0 = pos[h->sym_order[us[u]]], p1 = pos[h->sym_order[us[u] + 1]];
+        h->sym_partner[p0] = (int32_t)p1;
+        h->sym_partner[p1] = (int32_t)p0;
+      }
+  }
   Csr p = permute(a, h->perm);
   Csr pt = transpose(p);
   h->prp = std::move(p.rp);
@@ -643,6 +657,22 @@ int64_t ilu1t_partition(const bilu_handle* h, double tau, std::vector<int32_t>& 
   for (int64_t i = 0; i < n; ++i)
     for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
       if (ci[k] == i) dg[i] = rv[k];
+  // Sec. 5: both scalars of a 2x2 pivot take the pivot block's largest
+  // magnitude in place of |a_kk| (a zero diagonal inside a 2x2 pivot would
+  // pass every candidate)
+  if (!h->sym_partner.empty()) {
+    auto at = [&](int64_t r, int64_t c) {
+      const auto b = ci.begin() + rp[r], e = ci.begin() + rp[r + 1];
+      const auto it = std::lower_bound(b, e, (int32_t)c);
+      return it != e && *it == c ? std::fabs(rv[it - ci.begin()]) : 0.0;
+    };
+    std::vector<double> d2(dg);
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t p = h->sym_partner[i];
+      if (p >= 0) d2[i] = std::max(std::max(at(i, i), at(p, p)), std::max(at(i, p), at(p, i)));
+    }
+    dg.swap(d2);
+  }
   // per-k sets, computed in parallel into per-range buffers
   unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   int64_t chunk = (n + nt - 1) / nt;

@@ -279,6 +279,7 @@ bilu_status bilu_analyze(bilu_handle* h, int64_t n, const int64_t* rowptr, const
   h->mwm_sym = false;
   h->sym_order.clear();
   h->sym_ustart.clear();
+  h->sym_partner.clear();
   // Sec. 3.1 (use_mwm = 1): analyze D_l A D_r Pi instead of A; Sec. 5
   // (use_mwm = 2): D A D with the symmetric matching's pivot units
   std::vector<int64_t> sigma;

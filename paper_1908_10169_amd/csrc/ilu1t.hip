@@ -66,6 +66,25 @@ __global__ void diag_kernel(int n, const int64_t* rp, const int32_t* ci, const d
   dg[i] = d;
 }
 
+// Sec. 5: both scalars of a 2x2 pivot (partner >= 0) take the pivot
+// block's largest magnitude in place of their diagonal.
+__global__ void pair_dg_kernel(int n, const int32_t* partner, const int64_t* rp, const int32_t* ci,
+                               const double* rv, double* dg) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int p = partner[i];
+  if (p < 0) return;
+  auto at = [&](int r, int c) {
+    int64_t lo = rp[r], hi = rp[r + 1];
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (ci[mid] < c) lo = mid + 1; else hi = mid;
+    }
+    return lo < rp[r + 1] && ci[lo] == c ? fabs(rv[lo]) : 0.0;
+  };
+  dg[i] = fmax(fmax(at(i, i), at(p, p)), fmax(at(i, p), at(p, i)));
+}
+
 // Largest off-diagonal magnitude of every row (CSR) or column (CSC).
 __global__ void offdiag_max_kernel(int n, const int64_t* ptr, const int32_t* idx, const double* val,
                                    double* out) {
@@ -334,6 +353,14 @@ int64_t ilu1t_partition_device(bilu_handle* h, double tau, std::vector<int32_t>&
       return -1;
     diag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>((int)n, h->d_rp.p, h->d_ci.p, h->d_rv.p,
                                                              h->d_ilu_dg.p);
+    if (!h->sym_partner.empty()) {
+      if (h->d_partner.alloc(n) != hipSuccess ||
+          hipMemcpyAsync(h->d_partner.p, h->sym_partner.data(), n * sizeof(int32_t),
+                         hipMemcpyHostToDevice, st) != hipSuccess)
+        return -1;
+      pair_dg_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
+          (int)n, h->d_partner.p, h->d_rp.p, h->d_ci.p, h->d_rv.p, h->d_ilu_dg.p);
+    }
     offdiag_max_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(
         (int)n, h->d_cp.p, h->d_ri.p, h->d_cv.p, h->d_ilu_dg.p + n);
     offdiag_max_kernel<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(

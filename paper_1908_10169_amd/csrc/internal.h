@@ -306,6 +306,10 @@ struct bilu_handle {
   // that the cosine groups keep whole, sym_ustart their boundaries
   bool mwm_sym = false;
   std::vector<int64_t> sym_order, sym_ustart;
+  // the other scalar of each 2x2 pivot in the final numbering (-1: a 1x1
+  // pivot; empty without the symmetric matching), for ILU(1,tau)
+  std::vector<int32_t> sym_partner;
+  bilu::DevArray<int32_t> d_partner;
   bilu::DevArray<int32_t> d_perm_col;
   bilu::DevArray<double> d_sl, d_sl_inv, d_sr, d_sr_inv;
   const int32_t* perm_col() const { return mwm ? d_perm_col.p : d_perm.p; }

@@ -230,6 +230,8 @@ def test_symmetric_matching_factor_parity(side, tau, agg):
         den = sum(float(np.sum(y ** 2)) for y in getattr(fo, name))
         assert np.sqrt(num / max(den, 1e-300)) <= 1e-10, name
     assert h.stats()["perturbed_blocks"] == o.stats()["perturbed_blocks"] == 0
+    # the 2x2 pivots' thresholds keep the sets within the device kernels
+    assert h.stats()["ilu1t_host"] == 0
     h.close()
 
 
@@ -293,13 +295,23 @@ def test_symmetric_matching_with_the_library_ordering(ordering):
     h.factor(tau)
     fl = h.export()
     assert np.array_equal(fl.perm, perm) and np.array_equal(fl.starts_initial, bs)
+    from oracle import symmetric_units
     sigma, dl, dr = bilu.mwm(a)
-    d = np.sqrt(dl * dr)
+    d, uorder, us = symmetric_units(a, sigma, dl, dr, pre=order)
+    # the 2x2 pivots in the library's numbering (its groups are the units
+    # here, coarser than the pivots)
+    pos = np.empty(a.n, dtype=np.int64)
+    pos[perm] = np.arange(a.n)
+    partner = np.full(a.n, -1, dtype=np.int64)
+    for u in range(len(us) - 1):
+        if us[u + 1] - us[u] == 2:
+            p0, p1 = pos[uorder[us[u]]], pos[uorder[us[u] + 1]]
+            partner[p0], partner[p1] = p1, p0
     rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
     ah = mg.Csr(a.n, a.rowptr, a.colind, (d[rows] * a.val) * d[a.colind])
     o = Oracle()
     assert o.run(ah, OracleOptions(tau=tau, use_aggregation=True, use_cosine=False),
-                 pre_perm=perm, unit_starts=gs) == 0
+                 pre_perm=perm, unit_starts=gs, partner=partner) == 0
     fo = o.factors()
     assert np.array_equal(fo.perm, fl.perm)
     assert np.array_equal(fo.starts_initial, fl.starts_initial)
