@@ -1027,3 +1027,99 @@ def test_p17_matching_removes_the_perturbations():
     assert sym["iterations"] * 10 < plain["iterations"]
     x = d * xh
     assert np.linalg.norm(b - a.matvec(x)) <= 1e-6 * np.linalg.norm(b)
+
+
+def _ilu1t_partition_dense(P, mask, dvec, ustart, tau, max_block=128):
+    """The ILU(1,tau) block guess of Sec. 3.4 written from its definition
+    on dense arrays (independent of the oracle's sparse loops): the
+    estimated rows I_k of column k of L and columns J_k of row k of U,
+    then units added while the dense count stays within the scalar one."""
+    n = P.shape[0]
+
+    def sets(k):
+        I, J = set(), set()
+        for i in range(k + 1, n):
+            if mask[i, k] and abs(P[i, k]) >= tau * abs(dvec[k]):
+                I.add(i)
+            if mask[k, i] and abs(P[k, i]) >= tau * abs(dvec[k]):
+                J.add(i)
+        for j in range(k):
+            if mask[j, k]:
+                for i in range(k + 1, n):
+                    if mask[i, j] and abs(P[i, j] * P[j, k]) >= tau * abs(dvec[j] * dvec[k]):
+                        I.add(i)
+            if mask[k, j]:
+                for i in range(k + 1, n):
+                    if mask[j, i] and abs(P[k, j] * P[j, i]) >= tau * abs(dvec[j] * dvec[k]):
+                        J.add(i)
+        return I, J
+
+    nu = len(ustart) - 1
+    starts = [0]
+    u = 0
+    while u < nu:
+        s0, e0 = ustart[u], ustart[u + 1]
+        rows, cols, c = set(), set(), 0
+        for k in range(s0, e0):
+            I, J = sets(k)
+            rows |= {i for i in I if i >= e0}
+            cols |= {j for j in J if j >= e0}
+            c += len(I) + len(J) + 1
+        width = e0 - s0
+        u += 1
+        while u < nu:
+            s1, e1 = ustart[u], ustart[u + 1]
+            w2 = width + (e1 - s1)
+            if w2 > max_block:
+                break
+            rows2 = {i for i in rows if i >= e1}
+            cols2 = {j for j in cols if j >= e1}
+            c2 = c
+            for k in range(s1, e1):
+                I, J = sets(k)
+                rows2 |= {i for i in I if i >= e1}
+                cols2 |= {j for j in J if j >= e1}
+                c2 += len(I) + len(J) + 1
+            f2 = (len(rows2) + len(cols2) + w2) * w2
+            if 3 * f2 <= 4 * c2 or f2 <= c2 + 4 * w2:
+                rows, cols, c, width = rows2, cols2, c2, w2
+                u += 1
+            else:
+                break
+        starts.append(starts[-1] + width)
+    return np.array(starts)
+
+
+@pytest.mark.parametrize("tau", [1e-2, 1e-1])
+def test_p17_ilu1t_thresholds_of_2x2_pivots(tau):
+    """The reading for 2x2 pivots (Sec. 5): both scalars of a 2x2 pivot take
+    the pivot block's largest magnitude in place of |a_kk|.  The oracle's
+    partition of a saddle point (units = the symmetric matching's pivots,
+    no cosine step) equals the dense definition with that reading, and
+    differs from the one with the scalar diagonals (constraint rows have
+    none)."""
+    from oracle import mwm_scalings, symmetric_units
+    a, order, m = mg.kkt_elasticity(4)
+    sigma, dl, dr = mwm_scalings(a)
+    d, uorder, us = symmetric_units(a, sigma, dl, dr, pre=order)
+    rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
+    ah = mg.Csr(a.n, a.rowptr, a.colind, (d[rows] * a.val) * d[a.colind])
+    o = Oracle()
+    assert o.run(ah, OracleOptions(tau=tau, use_cosine=False, use_aggregation=False),
+                 pre_perm=uorder, unit_starts=us) == 0
+    assert np.array_equal(o.perm(), uorder)
+    mask_full = np.zeros((a.n, a.n), dtype=bool)
+    mask_full[rows, a.colind] = True
+    Pd = ah.to_dense()[np.ix_(uorder, uorder)]
+    mask = mask_full[np.ix_(uorder, uorder)]
+    scalar = np.diag(Pd).copy()
+    paired = scalar.copy()
+    for u in range(len(us) - 1):
+        if us[u + 1] - us[u] == 2:
+            i, p = us[u], us[u] + 1
+            blk = np.abs(Pd[np.ix_([i, p], [i, p])])
+            paired[i] = paired[p] = blk.max()
+    want = _ilu1t_partition_dense(Pd, mask, paired, us, tau)
+    assert np.array_equal(o.starts_initial(), want)
+    other = _ilu1t_partition_dense(Pd, mask, scalar, us, tau)
+    assert not np.array_equal(other, want)
