@@ -328,3 +328,27 @@ def test_symmetric_matching_with_the_library_ordering(ordering):
     info = h.sqmr(bd, xd, tol=1e-6, maxit=500)
     assert info["converged"] and _eta(a, b, xd.cpu().numpy()) <= 1e-6
     h.close()
+
+
+def test_symmetric_matching_analyze_device_equals_host():
+    """bilu_analyze_device with use_mwm = 2 takes the host route and leaves
+    the handle as bilu_analyze does: the factors agree bit for bit."""
+    torch = _torch()
+    from paper_1908_10169_amd import bilu
+    a, order, m = mg.kkt_elasticity(6)
+    say(f"[symmwm-device] kkt side=6 n={a.n}")
+    h = bilu.Bilu(ordering=bilu.ORDER_ND, use_mwm=2)
+    h.analyze(a, pre_perm=order)
+    h.factor(1e-2)
+    g = bilu.Bilu(ordering=bilu.ORDER_ND, use_mwm=2)
+    g.analyze_device(a.n, torch.from_numpy(np.asarray(a.rowptr, dtype=np.int64)).cuda(),
+                     torch.from_numpy(np.asarray(a.colind, dtype=np.int32)).cuda(),
+                     torch.from_numpy(np.asarray(a.val, dtype=np.float64)).cuda(), pre_perm=order)
+    g.factor(1e-2)
+    fh, fg = h.export(), g.export()
+    assert np.array_equal(fh.perm, fg.perm) and np.array_equal(fh.starts, fg.starts)
+    for name in ("L", "W", "D"):
+        assert b"".join(x.tobytes() for x in getattr(fh, name)) == \
+            b"".join(x.tobytes() for x in getattr(fg, name)), name
+    h.close()
+    g.close()
