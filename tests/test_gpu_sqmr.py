@@ -352,3 +352,59 @@ def test_symmetric_matching_analyze_device_equals_host():
             b"".join(x.tobytes() for x in getattr(fg, name)), name
     h.close()
     g.close()
+
+
+def test_symmetric_workload_full_size_parity():
+    """The benchmark's symmetric line at its own size (kkt_32, n = 114,688,
+    the symmetric matching, multilevel ND, aggregation): partition, every
+    pattern and every value against the oracle's sweep of D A D on the
+    library's numbering, no perturbed block, and SQMR to the benchmark's
+    backward error of 1e-6."""
+    torch = _torch()
+    from oracle import Oracle, OracleOptions, symmetric_units
+    from paper_1908_10169_amd import bilu
+    a, order, m = mg.kkt_elasticity(32)
+    tau = 1e-2
+    say(f"[symmwm-full] kkt side=32 n={a.n} nnz={a.nnz}")
+    h = bilu.Bilu(ordering=bilu.ORDER_ND_MULTILEVEL, use_aggregation=True, use_mwm=2)
+    h.analyze(a, pre_perm=order)
+    h.factor(tau)
+    fl = h.export()
+    assert h.stats()["ilu1t_host"] == 0
+    perm, gs, bs = bilu.preprocess(a, tau, pre_perm=order, ordering=bilu.ORDER_ND_MULTILEVEL,
+                                   use_mwm=2)
+    assert np.array_equal(fl.perm, perm) and np.array_equal(fl.starts_initial, bs)
+    sigma, dl, dr = bilu.mwm(a)
+    d, uorder, us = symmetric_units(a, sigma, dl, dr, pre=order)
+    pos = np.empty(a.n, dtype=np.int64)
+    pos[perm] = np.arange(a.n)
+    partner = np.full(a.n, -1, dtype=np.int64)
+    for u in range(len(us) - 1):
+        if us[u + 1] - us[u] == 2:
+            p0, p1 = pos[uorder[us[u]]], pos[uorder[us[u] + 1]]
+            partner[p0], partner[p1] = p1, p0
+    rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
+    ah = mg.Csr(a.n, a.rowptr, a.colind, (d[rows] * a.val) * d[a.colind])
+    say("[symmwm-full] oracle sweep")
+    o = Oracle()
+    assert o.run(ah, OracleOptions(tau=tau, use_aggregation=True, use_cosine=False),
+                 pre_perm=perm, unit_starts=gs, partner=partner) == 0
+    fo = o.factors()
+    assert np.array_equal(fo.starts_initial, fl.starts_initial)
+    assert np.array_equal(fo.starts, fl.starts)
+    for k in range(len(fo.starts) - 1):
+        assert np.array_equal(fl.R[k], fo.R[k]) and np.array_equal(fl.C[k], fo.C[k]), k
+    for name in ("L", "W", "D"):
+        num = sum(float(np.sum((x - y) ** 2)) for x, y in zip(getattr(fl, name), getattr(fo, name)))
+        den = sum(float(np.sum(y ** 2)) for y in getattr(fo, name))
+        assert np.sqrt(num / max(den, 1e-300)) <= 1e-10, name
+    assert h.stats()["perturbed_blocks"] == o.stats()["perturbed_blocks"] == 0
+    b = a.matvec(np.ones(a.n))
+    bd = torch.from_numpy(b).cuda()
+    xd = torch.zeros_like(bd)
+    info = h.sqmr(bd, xd, tol=1e-6, maxit=2000)
+    eta = _eta(a, b, xd.cpu().numpy())
+    say(f"[symmwm-full] SQMR {info['iterations']} steps, eta {eta:.2e}")
+    assert info["converged"] and eta <= 1e-6
+    assert abs(eta - info["eta"]) <= 1e-6 * eta + 1e-14
+    h.close()
