@@ -1123,3 +1123,18 @@ def test_p17_ilu1t_thresholds_of_2x2_pivots(tau):
     assert np.array_equal(o.starts_initial(), want)
     other = _ilu1t_partition_dense(Pd, mask, scalar, us, tau)
     assert not np.array_equal(other, want)
+
+
+@pytest.mark.parametrize("k", [2, 5])
+def test_p16_sqmr_with_the_symmetric_matching_matches_qmr(k):
+    """M from the symmetric variant's pipeline (D A D of a saddle point,
+    2x2 pivots as units): still symmetric up to rounding, so SQMR equals
+    QMR with right preconditioner M on the scaled system."""
+    a, order, o, d, uorder, us = _kkt_symmetric(4, 1e-2)
+    rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
+    ah = mg.Csr(a.n, a.rowptr, a.colind, (d[rows] * a.val) * d[a.colind])
+    b = d * a.matvec(np.ones(a.n))
+    x, info = o.sqmr(b, tol=0.0, maxit=k)
+    assert info["iterations"] == k
+    xs = _scipy_qmr(ah.to_dense(), b, k, prec=o.apply)
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
