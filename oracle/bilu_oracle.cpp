@@ -399,6 +399,25 @@ void perturb_row(std::vector<double>& m, int q, int i, double alpha, const orc_o
   m[i * q + k] = d * (1.0 + o.pert_rho * beta) + sgn(d) * o.pert_tau * alpha;
 }
 
+// Sec. 5, the symmetrized perturbation (reading: the paper names it only):
+// column j's entry is chosen as in perturb_col and the same new value is
+// written at (k, j) and at its mirror (j, k), one column after the other.
+void perturb_sym(std::vector<double>& m, int q, int j, double alpha, const orc_options& o) {
+  int k = 0;
+  double dmax = -1.0;
+  for (int i = 0; i < q; ++i)
+    if (std::fabs(m[i * q + j]) > dmax) {
+      dmax = std::fabs(m[i * q + j]);
+      k = i;
+    }
+  if (2.0 * std::fabs(m[j * q + j]) >= std::fabs(m[k * q + j])) k = j;
+  double beta = o.beta_one ? 1.0 : dmax;
+  double d = m[k * q + j];
+  const double nv = d * (1.0 + o.pert_rho * beta) + sgn(d) * o.pert_tau * alpha;
+  m[k * q + j] = nv;
+  m[j * q + k] = nv;
+}
+
 // LU with partial pivoting (lowest index wins ties).  Returns false when a
 // pivot is not above pivot_eps * max|m|.
 bool getrf(std::vector<double> lu, int q, double pivot_eps, std::vector<double>& out,
@@ -477,8 +496,12 @@ int perturb_invert(int q, std::vector<double> m, double alpha, const orc_options
   for (int attempt = 0;; ++attempt) {
     if (getrf(m, q, o.pivot_eps, lu, piv)) break;
     if (attempt == 3) return -1;
-    for (int j = 0; j < q; ++j) perturb_col(m, q, j, alpha, o);
-    for (int i = 0; i < q; ++i) perturb_row(m, q, i, alpha, o);
+    if (o.sym_perturb) {
+      for (int j = 0; j < q; ++j) perturb_sym(m, q, j, alpha, o);
+    } else {
+      for (int j = 0; j < q; ++j) perturb_col(m, q, j, alpha, o);
+      for (int i = 0; i < q; ++i) perturb_row(m, q, i, alpha, o);
+    }
     ++rounds;
   }
   lu_inverse(lu, piv, q, dinv);
@@ -952,6 +975,7 @@ void orc_default_options(orc_options* o) {
   o->pivot_eps = 1e-12;
   o->beta_one = 0;
   o->drop_norm = 0;
+  o->sym_perturb = 0;
 }
 
 orc_handle* orc_create(void) { return new orc_handle(); }

@@ -49,6 +49,9 @@ typedef struct {
   double pivot_eps;     /* relative pivot size that triggers perturbation   */
   int beta_one;         /* reading of the undefined beta_j: 0 -> delta_j, 1 -> 1 */
   int drop_norm;        /* 0 = max-abs (inf) norm, 1 = Euclidean norm       */
+  int sym_perturb;      /* Sec. 5: a failed inversion perturbs each column's */
+                        /* selected entry and its mirror together (symmetric */
+                        /* pivot blocks stay symmetric)                      */
 } orc_options;
 
 void orc_default_options(orc_options* o);

@@ -21,7 +21,7 @@ class _Opts(C.Structure):
         ("use_cosine", C.c_int), ("use_ilu1t", C.c_int), ("use_aggregation", C.c_int),
         ("max_block", C.c_int), ("tau", C.c_double), ("cos_eps", C.c_double),
         ("pert_tau", C.c_double), ("pert_rho", C.c_double), ("pivot_eps", C.c_double),
-        ("beta_one", C.c_int), ("drop_norm", C.c_int),
+        ("beta_one", C.c_int), ("drop_norm", C.c_int), ("sym_perturb", C.c_int),
     ]
 
 
@@ -113,6 +113,7 @@ class OracleOptions:
     pivot_eps: float = 1e-12
     beta_one: bool = False
     drop_norm: int = 0
+    sym_perturb: bool = False
 
     def c(self) -> _Opts:
         o = _Opts()

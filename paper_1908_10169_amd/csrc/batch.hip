@@ -84,10 +84,12 @@ bilu_status factor_batched(bilu_handle** hs, int count, const double* taus) {
     if (a.drop_norm != b.drop_norm || a.beta_one != b.beta_one || a.perturb_tau != b.perturb_tau ||
         a.perturb_rho != b.perturb_rho || a.pivot_eps != b.pivot_eps ||
         a.update_precision != b.update_precision || a.factor_path != b.factor_path ||
-        a.update_mfma != b.update_mfma || a.deterministic != b.deterministic)
+        a.update_mfma != b.update_mfma || a.deterministic != b.deterministic ||
+        h0->mwm_sym != hs[i]->mwm_sym)
       return fail(hs[i], BILU_ERR_INVALID,
-                  "batched factorization: drop norm, perturbation, pivot threshold, update "
-                  "precision, matrix-core use, determinism and kernel path must agree across the batch");
+                  "batched factorization: drop norm, perturbation (and its symmetric form), "
+                  "pivot threshold, update precision, matrix-core use, determinism and kernel "
+                  "path must agree across the batch");
   }
   // ---- per-handle partitions (a3)
   for (int i = 0; i < count; ++i) {

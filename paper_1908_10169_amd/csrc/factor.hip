@@ -283,6 +283,29 @@ __device__ __forceinline__ void perturb_row(double* m, int q, int i, const Facto
   m[i * q + k] = d * (1.0 + a.pert_rho * beta) + (d < 0.0 ? -1.0 : 1.0) * a.pert_tau * alpha;
 }
 
+// Sec. 5, the symmetrized perturbation: column j's entry is chosen as in
+// perturb_column and the same new value is written at (k, j) and at its
+// mirror (j, k).  Columns are taken one after the other (a mirror lands in
+// another column).
+__device__ __forceinline__ void perturb_symmetric(double* m, int q, int j, const FactorArgs& a,
+                                                  double alpha) {
+  int k = 0;
+  double dmax = -1.0;
+  for (int i = 0; i < q; ++i) {
+    double v = fabs(m[i * q + j]);
+    if (v > dmax) {
+      dmax = v;
+      k = i;
+    }
+  }
+  if (2.0 * fabs(m[j * q + j]) >= fabs(m[k * q + j])) k = j;
+  const double beta = a.beta_one ? 1.0 : dmax;
+  const double d = m[k * q + j];
+  const double nv = d * (1.0 + a.pert_rho * beta) + (d < 0.0 ? -1.0 : 1.0) * a.pert_tau * alpha;
+  m[k * q + j] = nv;
+  m[j * q + k] = nv;
+}
+
 // Thread group of a cooperative step: the whole workgroup, or wave 0 alone
 // (wave-synchronous: LDS accesses of one wave complete in order, so a fence
 // that stops compiler reordering is the only synchronisation needed).
@@ -719,10 +742,16 @@ __device__ __forceinline__ bool pivot_block(const FactorArgs& a, int K, int q, c
       if (tid == 0) raise_error(a, kDevSingular, K);
       return false;
     }
-    for (int j = tid; j < q; j += nth) perturb_column(sS, q, j, a, alpha);
-    G::sync();
-    for (int i = tid; i < q; i += nth) perturb_row(sS, q, i, a, alpha);
-    G::sync();
+    if (a.sym_pert) {
+      if (tid == 0)
+        for (int j = 0; j < q; ++j) perturb_symmetric(sS, q, j, a, alpha);
+      G::sync();
+    } else {
+      for (int j = tid; j < q; j += nth) perturb_column(sS, q, j, a, alpha);
+      G::sync();
+      for (int i = tid; i < q; i += nth) perturb_row(sS, q, i, a, alpha);
+      G::sync();
+    }
     ++rounds;
   }
   if (tid == 0 && rounds > 0) {
@@ -3263,6 +3292,7 @@ bilu_status factor_sweep(bilu_handle* h, double tau, const std::vector<double>* 
     }
     a.pert_tau = h->opt.perturb_tau;
     a.pert_rho = h->opt.perturb_rho;
+    a.sym_pert = h->mwm_sym ? 1 : 0;
     a.pivot_eps = h->opt.pivot_eps;
     a.beta_one = h->opt.beta_one;
     a.drop_norm = h->opt.drop_norm;
@@ -3506,6 +3536,7 @@ bilu_status frozen_refactor(bilu_handle* h) {
   a.fa.alpha = h->alpha;
   a.fa.pert_tau = h->opt.perturb_tau;
   a.fa.pert_rho = h->opt.perturb_rho;
+  a.fa.sym_pert = h->mwm_sym ? 1 : 0;
   a.fa.pivot_eps = h->opt.pivot_eps;
   a.fa.beta_one = h->opt.beta_one;
   a.fa.pflag = nullptr;

@@ -113,6 +113,7 @@ struct FactorArgs {
   const double* alpha_blk;
   int* pflag;                      // per-block perturbed flag or null
   int beta_one, drop_norm, update_prec;
+  int sym_pert;                    // Sec. 5: symmetrized perturbation (symmetric matching)
   int fast_path;                   // 1: LDS staging where it fits, 2: global staging, 0: general only
   int mfma;                        // fast path: update terms as matrix-core tiles
   int det;                         // fast path: terms subtracted in predecessor order

@@ -204,7 +204,8 @@ def _kkt_pair(side, tau, agg):
     rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
     ah = mg.Csr(a.n, a.rowptr, a.colind, (d[rows] * a.val) * d[a.colind])
     o = Oracle()
-    assert o.run(ah, OracleOptions(tau=tau, use_aggregation=agg), pre_perm=uorder,
+    assert o.run(ah, OracleOptions(tau=tau, use_aggregation=agg, sym_perturb=True),
+                 pre_perm=uorder,
                  unit_starts=us) == 0
     h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_aggregation=agg, use_mwm=2)
     h.analyze(a, pre_perm=order)
@@ -310,7 +311,8 @@ def test_symmetric_matching_with_the_library_ordering(ordering):
     rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
     ah = mg.Csr(a.n, a.rowptr, a.colind, (d[rows] * a.val) * d[a.colind])
     o = Oracle()
-    assert o.run(ah, OracleOptions(tau=tau, use_aggregation=True, use_cosine=False),
+    assert o.run(ah, OracleOptions(tau=tau, use_aggregation=True, use_cosine=False,
+                                   sym_perturb=True),
                  pre_perm=perm, unit_starts=gs, partner=partner) == 0
     fo = o.factors()
     assert np.array_equal(fo.perm, fl.perm)
@@ -387,7 +389,8 @@ def test_symmetric_workload_full_size_parity():
     ah = mg.Csr(a.n, a.rowptr, a.colind, (d[rows] * a.val) * d[a.colind])
     say("[symmwm-full] oracle sweep")
     o = Oracle()
-    assert o.run(ah, OracleOptions(tau=tau, use_aggregation=True, use_cosine=False),
+    assert o.run(ah, OracleOptions(tau=tau, use_aggregation=True, use_cosine=False,
+                                   sym_perturb=True),
                  pre_perm=perm, unit_starts=gs, partner=partner) == 0
     fo = o.factors()
     assert np.array_equal(fo.starts_initial, fl.starts_initial)
@@ -407,4 +410,57 @@ def test_symmetric_workload_full_size_parity():
     say(f"[symmwm-full] SQMR {info['iterations']} steps, eta {eta:.2e}")
     assert info["converged"] and eta <= 1e-6
     assert abs(eta - info["eta"]) <= 1e-6 * eta + 1e-14
+    h.close()
+
+
+def _singular_pair_elasticity(side):
+    """The unperturbed elasticity operator with unknown 1 a copy of unknown
+    0 (row and column): node 0's pivot block is singular."""
+    a = mg.grid3d_elasticity(side, 3, seed=2, pert=0.0, shift=0.1)
+    A = a.to_dense()
+    mask = np.zeros_like(A, dtype=bool)
+    mask[np.repeat(np.arange(a.n), np.diff(a.rowptr)), a.colind] = True
+    A[1, :] = A[0, :]
+    A[:, 1] = A[:, 0]
+    A[1, 1] = A[0, 0]
+    return mg.dense_to_csr(A, mask=mask)
+
+
+def test_symmetric_matching_perturbs_symmetrically():
+    """A singular pivot block under the symmetric matching: the library
+    perturbs it with the symmetric rule, as the oracle does with
+    sym_perturb (same patterns, values to 1e-10), and not as the
+    column-then-row rule would."""
+    _torch()
+    from oracle import Oracle, OracleOptions, symmetric_units
+    from paper_1908_10169_amd import bilu
+    a = _singular_pair_elasticity(4)
+    order = mg.node_perm_to_scalar(mg.grid_nd_node_order((4,) * 3, dissect_separators=False), 3)
+    say(f"[symmwm-perturb] n={a.n}")
+    h = bilu.Bilu(ordering=bilu.ORDER_NATURAL, use_mwm=2)
+    h.analyze(a, pre_perm=order)
+    h.factor(1e-2)
+    fl = h.export()
+    sigma, dl, dr = bilu.mwm(a)
+    d, uorder, us = symmetric_units(a, sigma, dl, dr, pre=order)
+    rows = np.repeat(np.arange(a.n), np.diff(a.rowptr))
+    ah = mg.Csr(a.n, a.rowptr, a.colind, (d[rows] * a.val) * d[a.colind])
+    fo = {}
+    for sp in (True, False):
+        o = Oracle()
+        assert o.run(ah, OracleOptions(tau=1e-2, sym_perturb=sp), pre_perm=uorder,
+                     unit_starts=us) == 0
+        assert o.stats()["perturbed_blocks"] == 1
+        fo[sp] = o.factors()
+    assert h.stats()["perturbed_blocks"] == 1
+    f = fo[True]
+    assert np.array_equal(fl.perm, f.perm) and np.array_equal(fl.starts, f.starts)
+    for k in range(len(f.starts) - 1):
+        assert np.array_equal(fl.R[k], f.R[k]) and np.array_equal(fl.C[k], f.C[k]), k
+    for name in ("L", "W", "D"):
+        num = sum(float(np.sum((x - y) ** 2)) for x, y in zip(getattr(fl, name), getattr(f, name)))
+        den = sum(float(np.sum(y ** 2)) for y in getattr(f, name))
+        assert np.sqrt(num / max(den, 1e-300)) <= 1e-10, name
+    other = max(float(np.abs(x - y).max()) for x, y in zip(fl.D, fo[False].D))
+    assert other > 1e-6
     h.close()

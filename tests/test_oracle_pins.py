@@ -1138,3 +1138,38 @@ def test_p16_sqmr_with_the_symmetric_matching_matches_qmr(k):
     assert info["iterations"] == k
     xs = _scipy_qmr(ah.to_dense(), b, k, prec=o.apply)
     assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+
+
+# P11b: the symmetrized perturbation (Sec. 5, sym_perturb): each column's
+# selected entry and its mirror take the same value, so a symmetric pivot
+# block stays symmetric.
+def test_p11_symmetric_all_ones_2x2():
+    """[[1,1],[1,1]] is singular; column 0 selects its diagonal (2|1| >= |1|),
+    column 1 too, each becomes 1 (1 + rho beta) + tau alpha with beta = 1."""
+    s = np.ones((2, 2))
+    alpha, rho, tau = 3.0, 1e-1, 1e-2
+    r, su, di = perturb_invert(s, alpha=alpha, opts=OracleOptions(sym_perturb=True))
+    d = 1.0 * (1.0 + rho * 1.0) + tau * alpha
+    assert r == 1
+    assert np.array_equal(su, np.array([[d, 1.0], [1.0, d]]))
+    assert np.allclose(di @ su, np.eye(2), atol=1e-14)
+
+
+def test_p11_symmetric_keeps_symmetry():
+    """A symmetric singular 3x3 block whose row 2 is twice row 1: the
+    symmetric rule perturbs each column's diagonal once (2|m_jj| >= the
+    column's largest entry), so S stays symmetric bit for bit and matches
+    the closed form; the column-then-row rule perturbs the diagonals a
+    second time in its row pass."""
+    s = np.array([[4.0, 1.0, 2.0], [1.0, 10.0, 20.0], [2.0, 20.0, 40.0]])
+    alpha, rho, tau = 1.0, 1e-1, 1e-2
+    r, su, di = perturb_invert(s, alpha=alpha, opts=OracleOptions(sym_perturb=True))
+    assert r == 1 and np.array_equal(su, su.T)
+    want = s.copy()
+    for j in range(3):
+        beta = np.abs(s[:, j]).max()
+        want[j, j] = s[j, j] * (1.0 + rho * beta) + tau * alpha
+    assert np.array_equal(su, want)
+    assert np.allclose(su @ di, np.eye(3), atol=1e-12)
+    r2, su2, _ = perturb_invert(s, alpha=alpha)
+    assert r2 == 1 and not np.array_equal(su2, su)
