@@ -19,7 +19,8 @@
 //   W^ = L_GG W_{G,C},
 // with R (C) the union of the members' rows (columns) beyond the group: the
 // closed form of merging the members pairwise in order.  One workgroup
-// builds each group in a scratch slot.
+// builds each group in a slot of its LDS (of global scratch when the widest
+// block's four w x w matrices do not fit kMergeLdsSlot).
 #include <algorithm>
 #include <chrono>
 #include <numeric>
@@ -34,6 +35,7 @@ constexpr int kAggHash = 1024;   // LDS hash slots per wave and side (decisions)
 constexpr int kAggWaves = 4;
 constexpr int kMergeThreads = 256;
 constexpr int kMergeSort = 4096; // rows (columns) of a merged block sorted in LDS
+constexpr int64_t kMergeLdsSlot = 24576;  // bytes: the work matrices stay in LDS up to this
 
 struct DecideArgs {
   int nb, maxb;
@@ -173,6 +175,7 @@ struct MergeArgs {
   const int32_t* fnr; const int32_t* fnc;
   int32_t* fidx; void* fval; double* fdval;   // fval in the precision in.vprec
   double* scratch; int64_t slot_doubles;   // per workgroup: 4 w^2 doubles
+  int lds_slot;   // 1: the slot is the launch's dynamic LDS, not scratch
   int* err;
   int copy_all;   // 0: blocks that merged with nothing stay in place (only D_K is copied)
 };
@@ -182,8 +185,6 @@ struct MergeLds {
   int misc[8];
 };
 
-// Sorted union of the members' indices beyond last into out (LDS sort);
-// returns the count or -1 when it does not fit.
 // Position of x in the sorted list lst[0..cnt), or -1.
 __device__ __forceinline__ int find_sorted(const int32_t* lst, int cnt, int x) {
   int lo = 0, hi = cnt;
@@ -197,6 +198,8 @@ __device__ __forceinline__ int find_sorted(const int32_t* lst, int cnt, int x) {
   return (lo < cnt && lst[lo] == x) ? lo : -1;
 }
 
+// Sorted union of the members' indices beyond last into out (LDS sort);
+// returns the count or -1 when it does not fit.
 __device__ int merged_index_set(const MergeArgs& a, int b0, int b1, int last, bool rows,
                                 MergeLds& s, int* out) {
   const int tid = threadIdx.x;
@@ -242,8 +245,12 @@ __device__ int merged_index_set(const MergeArgs& a, int b0, int b1, int last, bo
 
 __global__ void __launch_bounds__(kMergeThreads) agg_merge_kernel(MergeArgs a) {
   __shared__ MergeLds s;
+  extern __shared__ double s_slot[];
   const int tid = threadIdx.x, nt = blockDim.x;
-  double* Lg = a.scratch + (int64_t)blockIdx.x * a.slot_doubles;  // L_GG   (w x w)
+  // L_GG (w x w), then L_GG^{-1}, U_GG and the product below; every step
+  // of the two triangular solves reads the rows before it, so the slot sits
+  // in LDS whenever it fits
+  double* Lg = a.lds_slot ? s_slot : a.scratch + (int64_t)blockIdx.x * a.slot_doubles;
   for (int g = blockIdx.x; g < a.ngroups; g += gridDim.x) {
     const int b0 = a.gfirst[g], b1 = a.gfirst[g + 1];
     const int f0 = a.in.bstart[b0], last = a.in.bstart[b1] - 1, w = last - f0 + 1;
@@ -328,15 +335,17 @@ __global__ void __launch_bounds__(kMergeThreads) agg_merge_kernel(MergeArgs a) {
       Tm[e] = acc;
     }
     __syncthreads();
-    // D^ = U_GG^{-1} Tm (back substitution per column)
+    // D^ = U_GG^{-1} Tm (back substitution per column, in place: row x
+    // reads the finished rows below it), then out
     for (int y = tid; y < w; y += nt) {
       for (int x = w - 1; x >= 0; --x) {
         double acc = Tm[x * w + y];
-        for (int z = x + 1; z < w; ++z) acc = fma(-Ug[x * w + z], Dout[z * w + y], acc);
-        Dout[x * w + y] = acc;
+        for (int z = x + 1; z < w; ++z) acc = fma(-Ug[x * w + z], Tm[z * w + y], acc);
+        Tm[x * w + y] = acc;
       }
     }
     __syncthreads();
+    for (int e = tid; e < w * w; e += nt) Dout[e] = Tm[e];
     // rows of the merged block: L^ = L_{R,G} L_GG^{-1}
     {
       const int m = merged_index_set(a, b0, b1, last, true, s, Rout);
@@ -584,10 +593,28 @@ bilu_status aggregate_device(bilu_handle* h) {
                                                                 h->f_blockof.p);
   }
   // ---- merged blocks
-  const int64_t slots = std::min<int64_t>(ng, 1024);
+  // A merged group's steps are short and separated by workgroup barriers,
+  // so the merge is bound by latency: launch as many workgroups as can be
+  // resident.  Each owns a slot of 4 w_max^2 doubles: dynamic LDS when that
+  // fits kMergeLdsSlot, else global scratch, kept within 256 MiB when the
+  // blocks are wide.
   const int64_t slot_doubles = 4 * wmax * wmax;
+  const bool lds_slot = 8 * slot_doubles <= kMergeLdsSlot;
+  const size_t dyn = lds_slot ? (size_t)(8 * slot_doubles) : 0;
+  int64_t slots = 1024;
+  {
+    int dev = 0, cus = 0, per_cu = 0;
+    CK(hipGetDevice(&dev));
+    CK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    CK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(agg_merge_kernel), kMergeThreads, dyn));
+    const int64_t resident = (int64_t)std::max(cus, 1) * std::max(per_cu, 1);
+    const int64_t cap =
+        lds_slot ? resident : std::max<int64_t>(1024, (int64_t(256) << 20) / (8 * slot_doubles));
+    slots = std::max<int64_t>(1, std::min({ng, resident, cap}));
+  }
   DevArray<int> err;
-  CK(h->d_agg_scratch.alloc(slots * slot_doubles));
+  if (!lds_slot) CK(h->d_agg_scratch.alloc(slots * slot_doubles));
   CK(err.alloc(1));
   CK(hipMemsetAsync(err.p, 0, sizeof(int), st));
   MergeArgs ma{};
@@ -605,10 +632,11 @@ bilu_status aggregate_device(bilu_handle* h) {
   ma.fval = in_place ? h->d_val_heap.p : h->f_val.p;
   ma.copy_all = in_place ? 0 : 1;
   ma.fdval = h->f_dval.p;
-  ma.scratch = h->d_agg_scratch.p;
+  ma.scratch = lds_slot ? nullptr : h->d_agg_scratch.p;
   ma.slot_doubles = slot_doubles;
+  ma.lds_slot = lds_slot ? 1 : 0;
   ma.err = err.p;
-  agg_merge_kernel<<<(unsigned)slots, kMergeThreads, 0, st>>>(ma);
+  agg_merge_kernel<<<(unsigned)slots, kMergeThreads, dyn, st>>>(ma);
   CK(hipGetLastError());
   int herr = 0;
   CK(hipMemcpyAsync(&herr, err.p, sizeof(int), hipMemcpyDeviceToHost, st));
