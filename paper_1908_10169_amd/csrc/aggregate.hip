@@ -354,14 +354,26 @@ __global__ void __launch_bounds__(kMergeThreads) agg_merge_kernel(MergeArgs a) {
         return;
       }
     }
+    // the position of every merged row in every member's row list, found
+    // once per (member, row) into the LDS key array when it fits, else per
+    // entry below
+    const int nmem = b1 - b0;
+    const bool rtab = nmem * nrg <= kMergeSort;
+    if (rtab) {
+      for (int e = tid; e < nmem * nrg; e += nt) {
+        const int J = b0 + e / nrg;
+        s.keys[e] = find_sorted(a.in.idx + a.in.roff[J], a.in.nr[J], Rout[e % nrg]);
+      }
+      __syncthreads();
+    }
     for (int e = tid; e < nrg * w; e += nt) {
       const int z = e / w, y = e % w;
-      const int i = Rout[z];
       double acc = 0.0;
       for (int J = b0; J < b1; ++J) {
         const int oJ = a.in.bstart[J] - f0, qJ = a.in.bstart[J + 1] - a.in.bstart[J];
         if (oJ + qJ <= y) continue;  // L_GG^{-1} is lower triangular
-        const int pz = find_sorted(a.in.idx + a.in.roff[J], a.in.nr[J], i);
+        const int pz = rtab ? s.keys[(J - b0) * nrg + z]
+                            : find_sorted(a.in.idx + a.in.roff[J], a.in.nr[J], Rout[z]);
         if (pz < 0) continue;
         const int64_t row = a.in.loff[J] + (int64_t)pz * qJ;
         for (int c = 0; c < qJ; ++c)
@@ -378,14 +390,22 @@ __global__ void __launch_bounds__(kMergeThreads) agg_merge_kernel(MergeArgs a) {
         return;
       }
     }
+    const bool ctab = nmem * ncg <= kMergeSort;  // as for the rows
+    if (ctab) {
+      for (int e = tid; e < nmem * ncg; e += nt) {
+        const int J = b0 + e / ncg;
+        s.keys[e] = find_sorted(a.in.idx + a.in.coff[J], a.in.nc[J], Cout[e % ncg]);
+      }
+      __syncthreads();
+    }
     for (int e = tid; e < ncg * w; e += nt) {
       const int z = e / w, x = e % w;
-      const int j = Cout[z];
       double acc = 0.0;
       for (int J = b0; J < b1; ++J) {
         const int oJ = a.in.bstart[J] - f0, qJ = a.in.bstart[J + 1] - a.in.bstart[J];
         if (oJ > x) break;  // L_GG is lower triangular
-        const int pz = find_sorted(a.in.idx + a.in.coff[J], a.in.nc[J], j);
+        const int pz = ctab ? s.keys[(J - b0) * ncg + z]
+                            : find_sorted(a.in.idx + a.in.coff[J], a.in.nc[J], Cout[z]);
         if (pz < 0) continue;
         const int64_t col = a.in.woff[J] + (int64_t)pz * qJ;
         for (int c = 0; c < qJ; ++c)
