@@ -127,11 +127,58 @@ __global__ void __launch_bounds__(256) bw_fill(FactorView f, const int32_t* ptr,
   }
 }
 
+// Order of the level computation below.  A block's key starts as the
+// largest sweep depth among the initial blocks it holds (depth0 over the
+// initial partition, blockOf0 its row map; both read within bounds whatever
+// they hold).  Keys only grow, and only to values already present.
+__global__ void plan_keys(int nb, const int32_t* bstart, const int32_t* blockOf0, int nb0,
+                          const int* depth0, int* key) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nb) return;
+  const int i0 = bstart[g], i1 = bstart[g + 1] - 1;
+  const int b0 = min(max(blockOf0[i0], 0), nb0 - 1);
+  const int b1 = min(max(blockOf0[i1], 0), nb0 - 1);
+  int k = 0;
+  for (int b = b0; b <= b1 && b - b0 <= i1 - i0; ++b) k = max(k, depth0[b]);
+  key[g] = k;
+}
+// One relaxation pass, one wave per block K: key(K) rises to the keys of
+// the blocks it depends on forward (fw lists), and the blocks it depends on
+// backward (bw lists) rise to key(K).  *changed is set when a key rose.  A
+// pass that changes nothing read constant keys throughout, so afterwards
+// key(J) <= key(K) for every forward dependency J of K and key(B) >= key(K)
+// for every backward one B.
+__global__ void __launch_bounds__(256) plan_relax(int nb, const int32_t* fptr, const int32_t* fj,
+                                                  const int32_t* bptr, const int32_t* bb, int* key,
+                                                  int* changed) {
+  const int K = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (K >= nb) return;
+  const int lane = threadIdx.x & 63;
+  int m = 0;
+  for (int e = fptr[K] + lane; e < fptr[K + 1]; e += 64)
+    m = max(m, __hip_atomic_load(&key[fj[e]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+  int kk = __hip_atomic_load(&key[K], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (m > kk) {
+    if (lane == 0 && atomicMax(&key[K], m) < m) atomicExch(changed, 1);
+    kk = m;
+  }
+  for (int e = bptr[K] + lane; e < bptr[K + 1]; e += 64) {
+    const int B = bb[e];
+    if (__hip_atomic_load(&key[B], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < kk &&
+        atomicMax(&key[B], kk) < kk)
+      atomicExch(changed, 1);
+  }
+}
+
 // Dependency levels of the apply: level(K) = 1 + the largest level of the
 // blocks K depends on (0 without any); forward over fw lists (J < K),
-// backward over bw lists (B > K).  One wave per block: even slots 2i are
-// the forward blocks in ascending order, odd slots 2i+1 the backward blocks
-// in descending order, so every dependency of a slot sits at a lower slot.
+// backward over bw lists (B > K).  One wave per block: even slots 2i hold
+// the forward blocks in the order ord (ascending index when ord is null),
+// odd slots 2i+1 the backward blocks in the reverse order.  ord lists every
+// forward dependency of a block before it, and so every backward one after
+// it: every dependency of a slot sits at a lower slot.
 // Workgroup g runs slots 4g..4g+3, g its index (the hardware starts a
 // launch's workgroups in index order) or, with ticket, the order in which
 // workgroups took a ticket when they started.  Either way every workgroup
@@ -140,9 +187,9 @@ __global__ void __launch_bounds__(256) bw_fill(FactorView f, const int32_t* ptr,
 // done: the launch needs no workgroup to be resident for another to make
 // progress.  Waits are bounded; a timeout sets *err.  Levels start at -1.
 __global__ void __launch_bounds__(256) apply_levels(int nb, const int32_t* fptr, const int32_t* fj,
-                                                    const int32_t* bptr, const int32_t* bb, int* lf,
-                                                    int* lb, int* err, int* ticket,
-                                                    unsigned long long wait_ticks) {
+                                                    const int32_t* bptr, const int32_t* bb,
+                                                    const int32_t* ord, int* lf, int* lb, int* err,
+                                                    int* ticket, unsigned long long wait_ticks) {
   __shared__ int s_id;
   int id = blockIdx.x;
   if (ticket) {
@@ -154,9 +201,10 @@ __global__ void __launch_bounds__(256) apply_levels(int nb, const int32_t* fptr,
   const int s = id * 4 + (int)(threadIdx.x >> 6);
   if (s >= 2 * nb) return;  // no workgroup barrier below
   // the two directions interleave (they do not depend on each other): even
-  // slots forward in ascending, odd slots backward in descending order
+  // slots forward along ord, odd slots backward along its reverse
   const bool fwd = (s & 1) == 0;
-  const int K = fwd ? s >> 1 : nb - 1 - (s >> 1);
+  const int p = fwd ? s >> 1 : nb - 1 - (s >> 1);
+  const int K = ord ? ord[p] : p;
   const int32_t* ptr = fwd ? fptr : bptr;
   const int32_t* adj = fwd ? fj : bb;
   int* lev = fwd ? lf : lb;
@@ -1150,10 +1198,56 @@ bilu_status build_apply_plan(bilu_handle* h) {
     int* top = misc.p;
     int* err = misc.p + 2;
     int* ticket = h->eff.apply_path == 2 ? misc.p + 3 : nullptr;
-    apply_levels<<<(unsigned)groups, 256, 0, st>>>((int)nb, h->fw_ptr.p, h->fw_j.p, h->bw_ptr.p,
-                                                  h->bw_b.p, lf, lb, err, ticket, wait);
-    CK(hipGetLastError());
     int nbi = (int)nb;
+    // the slots in the order of the sweep's dependency depths, made
+    // consistent with the apply's own dependencies by relaxation passes (a
+    // merged block can hold a deeper member than a block that depends on
+    // it); block order when the depths are not there or the passes do not
+    // settle
+    DevArray<int32_t> key, ord, sorted_keys, seq;
+    const int32_t* slot_order = nullptr;
+    const int64_t nb0 = h->stats.nblocks_initial;
+    if (nb0 > 0 && h->d_flow.p && h->d_flow.n >= (size_t)(5 * nb0 + 8) && h->d_blockof.p &&
+        h->d_blockof.n >= (size_t)n) {
+      constexpr int kRounds = 4, kPasses = 4;
+      DevArray<int> changed;
+      CK(key.alloc(nb));
+      CK(changed.alloc(kRounds * kPasses));
+      CK(hipMemsetAsync(changed.p, 0, kRounds * kPasses * sizeof(int), st));
+      plan_keys<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nbi, f.bstart, h->d_blockof.p,
+                                                             (int)nb0, h->d_flow.p + 3 * nb0, key.p);
+      CK(hipGetLastError());
+      bool settled = false;
+      for (int r = 0; r < kRounds && !settled; ++r) {
+        for (int q = 0; q < kPasses; ++q)
+          plan_relax<<<gw, 256, 0, st>>>(nbi, h->fw_ptr.p, h->fw_j.p, h->bw_ptr.p, h->bw_b.p, key.p,
+                                         changed.p + r * kPasses + q);
+        CK(hipGetLastError());
+        int last = 1;
+        CK(hipMemcpyAsync(&last, changed.p + r * kPasses + kPasses - 1, sizeof(int),
+                          hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        settled = last == 0;
+      }
+      if (settled) {
+        // (key, index) ascending: a stable sort of the indices by key
+        CK(ord.alloc(nb));
+        CK(sorted_keys.alloc(nb));
+        CK(seq.alloc(nb));
+        iota_k<<<(unsigned)((nb + 255) / 256), 256, 0, st>>>(nbi, seq.p);
+        CK(hipGetLastError());
+        size_t bytes = 0;
+        CK(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, key.p, sorted_keys.p, seq.p, ord.p,
+                                              nbi, 0, 32, st));
+        CK(h->d_scan_tmp.alloc(bytes + 1));
+        CK(hipcub::DeviceRadixSort::SortPairs(h->d_scan_tmp.p, bytes, key.p, sorted_keys.p, seq.p,
+                                              ord.p, nbi, 0, 32, st));
+        slot_order = ord.p;
+      }
+    }
+    apply_levels<<<(unsigned)groups, 256, 0, st>>>((int)nb, h->fw_ptr.p, h->fw_j.p, h->bw_ptr.p,
+                                                  h->bw_b.p, slot_order, lf, lb, err, ticket, wait);
+    CK(hipGetLastError());
     {
       // the largest level of each direction
       size_t rb = 0;
