@@ -1209,7 +1209,7 @@ bilu_status build_apply_plan(bilu_handle* h) {
     const int64_t nb0 = h->stats.nblocks_initial;
     if (nb0 > 0 && h->d_flow.p && h->d_flow.n >= (size_t)(5 * nb0 + 8) && h->d_blockof.p &&
         h->d_blockof.n >= (size_t)n) {
-      constexpr int kRounds = 4, kPasses = 4;
+      constexpr int kRounds = 8, kPasses = 2;
       DevArray<int> changed;
       CK(key.alloc(nb));
       CK(changed.alloc(kRounds * kPasses));
