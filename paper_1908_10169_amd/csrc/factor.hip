@@ -489,7 +489,7 @@ static_assert(2 * kBigPreds + 4 + 2 * kBigPreds + kBigPreds + 3 <= kFastStage,
 static_assert(kRegionBytes % 16 == 0 && 8 * kGOwnSlots < kRegionBytes, "global variant: own-count table");
 static_assert(offsetof(Lds, x.meta) == offsetof(Lds, x.buf) + sizeof(double) * kFastBuf,
               "global variant: the predecessor data spans buf and meta");
-static_assert(kThreads >= 192 && kListCap <= 64 && kFastWidth + 1 <= 32, "round-1 thread map");
+static_assert(kThreads >= 192 && kListCap <= 64 && kFastWidth + 1 <= 32, "phase-1 thread map");
 static_assert(kFastOwnCnt + kFastOwnSlots <= kHashSlots && 2 * kFastExtra <= kFastCandSlots / 2 &&
                   1024 + kFastExtra <= kFastCandSlots,
               "LDS variant hash layout");
@@ -1598,7 +1598,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     fpred = s.x.pred;
     frpred = s.x.rpred;
   }
-  // ---- round 1: predecessor counts and inline lists, block range.  The
+  // ---- phase 1: predecessor counts and inline lists, block range.  The
   // global variant resumes from the LDS variant's rounds 1 and 2 when that
   // variant gave the block up after them (misc[31]): the counts, range,
   // sorted predecessors, their data and A's pointers of K are in LDS.
@@ -1635,7 +1635,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   const int f = s.misc[2], l = s.misc[3] - 1, q = l - f + 1;
   if (q > kFastWidth || !a.lds_pivot) return kFastFallback;
   if (np + npr > cPreds) return fallback;
-  // K's own counts come with the staging pass (round 3) in the LDS variant
+  // K's own counts come with the staging pass (phase 3) in the LDS variant
   // and, when its predecessor data leaves room for the table, in the global
   // variant (gown, over the end of the LDS variant's panel and metadata)
   const bool ownearly =
@@ -1675,7 +1675,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   }
   __syncthreads();
 
-  // ---- round 2: predecessor data, A's pointers of K; clear the hash
+  // ---- phase 2: predecessor data, A's pointers of K; clear the hash
   if (resume)  // the LDS variant's data (s.x.meta lies above the first
                // cPreds entries of the global variant's fmeta, s.x.buf)
     for (int t = tid; t < np + npr; t += nt) fmeta[t] = s.x.meta[t];
@@ -1764,7 +1764,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
   const int total = segoff[nseg];
   if (tid == 0) trace_at(d, K, 20, wall_clock64());
 
-  // ---- round 3: stage every list; candidate rows (keys r) and columns
+  // ---- phase 3: stage every list; candidate rows (keys r) and columns
   // (keys ~c) beyond the block go to one hash, and each new key to keys[]
   int* keys = reinterpret_cast<int*>(fbuf) + 2 * cExtra;
   // K's own counts come with the same pass (LDS variant): A's entries of K
@@ -2017,7 +2017,7 @@ __device__ __forceinline__ int factor_block_fast(const FactorArgs& a, const Flow
     trace_at(d, K, 19, (unsigned long long)mcc);
   }
 
-  // ---- round 4: A's values into the panels, update terms (chunked)
+  // ---- phase 4: A's values into the panels, update terms (chunked)
   double* Cp = fbuf;                    // mc x q, row-major
   double* Rp = Cp + mc * q;             // mcc x q (column z of the row panel)
   double* const Tm = Rp + mcc * q;      // update terms
